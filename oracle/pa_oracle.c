@@ -1,0 +1,579 @@
+/*
+ * Oracle for population annealing (PA) of the 2D Ising model.
+ *
+ * TEST INFRASTRUCTURE ONLY: a plain, slow, single-threaded CPU implementation
+ * of the method.  Only the test suite, the smoke entry point and the
+ * CPU-baseline leg of the benchmark load it.  It shares no code, header,
+ * table or constant with the HIP path.
+ *
+ * The method (paper Sec. 2, "Population annealing algorithm"):
+ *   1. start with R replicas drawn uniformly at beta_0 = 0 (Eq. part-F, the
+ *      second one: at infinite temperature every state is equally likely);
+ *   2. for each step beta_{i-1} -> beta_i compute the normalised partition
+ *      function ratio Q (Eq. part-Q) and the weights tau_j (Eq. tau);
+ *   3. resample: replica j gets a random number of exact copies whose mean is
+ *      proportional to tau_j, keeping the population near its target;
+ *   4. equilibrate every replica with theta MCMC sweeps at beta_i;
+ *   5. measure observables over the population;
+ *   6. accumulate ln Z(beta_i) = ln Omega + sum_l ln Q_l (Eq. Free-En).
+ * The model is the 2D Ising ferromagnet on an L x L periodic square lattice
+ * (Sec. 3, Eq. Ham); the +-J Edwards-Anderson glass (a system named in the
+ * Introduction and the Discussion) only replaces the coupling of each bond.
+ *
+ * Readings of the paper fixed here (the paper is silent or garbled on them):
+ *   - Eq. Free-En lacks the logarithm and the sign; it is read as
+ *     ln Z(beta_i) = ln Omega + sum_{l<=i} ln Q(beta_{l-1}, beta_l) with
+ *     ln Omega = N ln 2 for cooling from beta_0 = 0.
+ *   - Resampling law: nearest-integer (floor of the mean plus one Bernoulli
+ *     draw on its fractional part) instead of Poisson; the mean number of
+ *     copies is rho_j = R_target * tau_j / R_{i-1}, i.e. population control
+ *     to the fixed target R_target.
+ *   - MCMC: checkerboard Metropolis, colour 0 ((x+y) even) first; integer
+ *     acceptance threshold T = floor(exp(-beta dE) 2^32), accept iff
+ *     dE <= 0 or r < T for a 32-bit random word r.
+ *   - Weights are shifted by the minimum energy (largest weight 1) and summed
+ *     over energy levels in ascending order, in double precision.
+ *   - Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) with
+ *     key (seed low word, seed high word) and counter
+ *       c0 = (domain << 28) | group, c1 = (step << 16) | half_sweep,
+ *       c2 = replica slot, c3 = population id.
+ *
+ * ORC_MUTANT (unset in every normal build) plants one plausible mistake so
+ * that the test suite can show its pins catch it; see the tests of the
+ * oracle's mutants.
+ */
+#ifndef ORC_MUTANT
+#define ORC_MUTANT 0
+#endif
+#include "pa_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define DOMAIN_INIT 1u
+#define DOMAIN_MCMC 2u
+#define DOMAIN_RESAMPLE 3u
+
+struct orc_pa {
+  int L, N;
+  int8_t* J;        /* NULL (ferromagnet) or [2][L][L] */
+  int64_t R_t, cap, R;
+  uint64_t seed;
+  uint32_t pop;
+  int8_t* spins;    /* [cap][N] */
+  int32_t* E;       /* [cap] */
+  int32_t* M;       /* [cap] */
+  uint32_t* n;      /* copy counts of the last resampling, [cap] */
+  int64_t n_len;
+  double beta, lnZ, lnQ_last;
+  int step;
+  int sweeps_at_step;
+  uint64_t shuffle_seed;
+};
+
+/* ---------------------------------------------------------------- Philox */
+
+/* Philox4x32 with 10 rounds, as defined by Salmon et al. (SC'11): each round
+   multiplies counter words 0 and 2 by the two round constants, swaps the
+   halves and mixes in the key; the key is advanced by the two Weyl
+   constants between rounds. */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2],
+                       uint32_t out[4]) {
+  uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+    uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+    uint32_t y1 = (uint32_t)p1;
+    uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+    uint32_t y3 = (uint32_t)p0;
+    x0 = y0;
+    x1 = y1;
+    x2 = y2;
+    x3 = y3;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  out[0] = x0;
+  out[1] = x1;
+  out[2] = x2;
+  out[3] = x3;
+}
+
+/* One random word of the stream layout described at the top of the file. */
+static uint32_t draw_word(uint64_t seed, uint32_t domain, uint32_t group,
+                          uint32_t step, uint32_t half_sweep, uint32_t slot,
+                          uint32_t pop, int word) {
+  uint32_t ctr[4], key[2], out[4];
+  ctr[0] = (domain << 28) | group;
+  ctr[1] = (step << 16) | half_sweep;
+  ctr[2] = slot;
+  ctr[3] = pop;
+  key[0] = (uint32_t)(seed & 0xFFFFFFFFu);
+  key[1] = (uint32_t)(seed >> 32);
+  orc_philox4x32_10(ctr, key, out);
+  return out[word];
+}
+
+/* ---------------------------------------------------------------- model */
+
+/* Coupling of the bond from site (x,y) to its right (dir 0) or lower
+   (dir 1) neighbour; the ferromagnet has J = 1 on every bond. */
+static int bond(const int8_t* J, int L, int dir, int x, int y) {
+  if (!J) return 1;
+  return J[(size_t)dir * L * L + (size_t)y * L + x];
+}
+
+/* Eq. Ham: H = -(J/2) sum over every spin of sigma times each of its four
+   neighbours, i.e. minus the coupling-weighted product summed once over the
+   2N bonds of the periodic lattice. */
+void orc_energy(int L, const int8_t* J, const int8_t* s, int32_t* E,
+                int32_t* M) {
+  int64_t e = 0, m = 0;
+  for (int y = 0; y < L; ++y) {
+    for (int x = 0; x < L; ++x) {
+      int sv = s[y * L + x];
+      int right = (ORC_MUTANT == 5) ? s[((x + 1) % L) * L + y]
+                                    : s[y * L + (x + 1) % L];
+      int down = s[((y + 1) % L) * L + x];
+      e -= bond(J, L, 0, x, y) * sv * right;
+      e -= bond(J, L, 1, x, y) * sv * down;
+      m += sv;
+    }
+  }
+  *E = (int32_t)e;
+  *M = (int32_t)m;
+}
+
+/* ------------------------------------------------------------- lifetime */
+
+int orc_create(int L, const int8_t* J, int64_t R_t, int64_t cap,
+               uint64_t seed, uint32_t pop, orc_pa** out) {
+  if (!out) return ORC_EINVAL;
+  *out = NULL;
+  if (L < 4 || L > 128 || (L % 2) != 0) return ORC_EINVAL;
+  if (R_t < 1 || R_t > ((int64_t)1 << 31)) return ORC_EINVAL;
+  if (cap == 0) cap = R_t + 16 * (int64_t)ceil(sqrt((double)R_t)) + 1024;
+  if (cap < R_t) return ORC_EINVAL;
+  orc_pa* p = (orc_pa*)calloc(1, sizeof(orc_pa));
+  if (!p) return ORC_ENOMEM;
+  p->L = L;
+  p->N = L * L;
+  p->R_t = R_t;
+  p->cap = cap;
+  p->seed = seed;
+  p->pop = pop;
+  size_t N = (size_t)p->N;
+  p->spins = (int8_t*)malloc((size_t)cap * N);
+  p->E = (int32_t*)malloc((size_t)cap * sizeof(int32_t));
+  p->M = (int32_t*)malloc((size_t)cap * sizeof(int32_t));
+  p->n = (uint32_t*)calloc((size_t)cap, sizeof(uint32_t));
+  if (J) {
+    p->J = (int8_t*)malloc(2 * N);
+    if (p->J) memcpy(p->J, J, 2 * N);
+  }
+  if (!p->spins || !p->E || !p->M || !p->n || (J && !p->J)) {
+    orc_destroy(p);
+    return ORC_ENOMEM;
+  }
+  /* Initial population at beta_0 = 0 (Eq. part-F, second form): every
+     state has the same probability, so each spin is an independent fair
+     coin.  Site (x,y) takes word x mod 4 of group y*ceil(L/4) + x/4 of the
+     INIT stream of its replica; the top bit of the word set means +1. */
+  int G4 = (L + 3) / 4;
+  for (int64_t j = 0; j < R_t; ++j) {
+    int8_t* s = p->spins + (size_t)j * N;
+    for (int y = 0; y < L; ++y)
+      for (int x = 0; x < L; ++x) {
+        uint32_t w = draw_word(seed, DOMAIN_INIT, (uint32_t)(y * G4 + x / 4), 0,
+                               0, (uint32_t)j, pop, x % 4);
+        s[y * L + x] = (w >> 31) ? 1 : -1;
+      }
+    orc_energy(L, p->J, s, &p->E[j], &p->M[j]);
+  }
+  p->R = R_t;
+  p->beta = 0.0;
+  /* ln Omega: 2^N states, all with weight 1 at beta_0 = 0. */
+  p->lnZ = (ORC_MUTANT == 7) ? 0.0 : (double)p->N * log(2.0);
+  p->lnQ_last = 0.0;
+  p->step = 0;
+  p->sweeps_at_step = 0;
+  p->n_len = 0;
+  *out = p;
+  return ORC_OK;
+}
+
+void orc_destroy(orc_pa* p) {
+  if (!p) return;
+  free(p->spins);
+  free(p->E);
+  free(p->M);
+  free(p->n);
+  free(p->J);
+  free(p);
+}
+
+/* ------------------------------------------------------------ resampling */
+
+/* Steps 2-3 of the method (Eqs. part-Q, tau) for a population given by its
+   energies E[0..R): computes ln Q for the step dbeta and the copy count of
+   every replica.  The resampling draws of slot j come from the RESAMPLE
+   stream at step `step_next` (the index of the temperature being entered). */
+int orc_counts(int N, const int32_t* E, int64_t R, int64_t R_t, double dbeta,
+               uint64_t seed, uint32_t pop, int step_next, uint32_t* n_out,
+               int64_t* R_new, double* lnQ_out) {
+  if (N < 16 || !E || R < 1 || R_t < 1 || !n_out || !isfinite(dbeta) ||
+      dbeta < 0.0)
+    return ORC_EINVAL;
+  int nlev = 4 * N + 1; /* energies -2N..2N, index E + 2N */
+  uint32_t* h = (uint32_t*)calloc((size_t)nlev, sizeof(uint32_t));
+  double* w = (double*)calloc((size_t)nlev, sizeof(double));
+  uint32_t* f = (uint32_t*)calloc((size_t)nlev, sizeof(uint32_t));
+  uint64_t* T = (uint64_t*)calloc((size_t)nlev, sizeof(uint64_t));
+  if (!h || !w || !f || !T) {
+    free(h); free(w); free(f); free(T);
+    return ORC_ENOMEM;
+  }
+  /* (a) histogram of the energies and the smallest energy */
+  int32_t Emin = 2 * N + 1;
+  for (int64_t j = 0; j < R; ++j) {
+    h[E[j] + 2 * N] += 1;
+    if (E[j] < Emin) Emin = E[j];
+  }
+  /* (b) Boltzmann factors exp(-dbeta E) shifted by Emin, summed per energy
+     level in ascending energy order (Eq. part-Q numerator) */
+  double S = 0.0;
+  for (int e = -2 * N; e <= 2 * N; ++e) {
+    uint32_t c = h[e + 2 * N];
+    if (c == 0) continue;
+    double we = exp(-(dbeta * (double)(e - Emin)));
+    w[e + 2 * N] = we;
+    double term = (ORC_MUTANT == 6) ? we : (double)c * we;
+    S = S + term;
+  }
+  /* (c) ln Q = ln[(1/R) sum_j exp(-dbeta E_j)] with the shift restored */
+  double lnQ = ((ORC_MUTANT == 2) ? (dbeta * (double)Emin)
+                                  : (-(dbeta * (double)Emin))) +
+               log(S / (double)R);
+  /* (d) mean copy number rho = R_target tau / R (Eq. tau); its integer part
+     and its fractional part as a 32-bit threshold */
+  for (int e = -2 * N; e <= 2 * N; ++e) {
+    if (h[e + 2 * N] == 0) continue;
+    double rho = ((double)R_t * w[e + 2 * N]) / S;
+    double fl = floor(rho);
+    f[e + 2 * N] = (uint32_t)fl;
+    T[e + 2 * N] = (uint64_t)floor(ldexp(rho - fl, 32));
+  }
+  /* (e) copy counts: floor plus a Bernoulli draw on the fraction */
+  int64_t total = 0;
+  for (int64_t j = 0; j < R; ++j) {
+    int idx = E[j] + 2 * N;
+    uint32_t r = draw_word(seed, DOMAIN_RESAMPLE, 0, (uint32_t)step_next, 0,
+                           (uint32_t)j, pop, 0);
+    uint32_t nj = f[idx] + ((uint64_t)r < T[idx] ? 1u : 0u);
+    n_out[j] = nj;
+    total += nj;
+  }
+  free(h); free(w); free(f); free(T);
+  if (R_new) *R_new = total;
+  if (lnQ_out) *lnQ_out = lnQ;
+  return ORC_OK;
+}
+
+int orc_resample(orc_pa* p, double beta_next, int64_t* R_new) {
+  if (!p || !isfinite(beta_next) || !(beta_next >= p->beta))
+    return ORC_EINVAL;
+  if (p->step + 1 > 65535) return ORC_EINVAL;
+  uint32_t* n = (uint32_t*)malloc((size_t)p->R * sizeof(uint32_t));
+  if (!n) return ORC_ENOMEM;
+  int64_t total = 0;
+  double lnQ = 0.0;
+  int rc = orc_counts(p->N, p->E, p->R, p->R_t, beta_next - p->beta, p->seed,
+                      p->pop, p->step + 1, n, &total, &lnQ);
+  if (rc != ORC_OK) { free(n); return rc; }
+  if (R_new) *R_new = total;
+  if (total > p->cap) { free(n); return ORC_ECAPACITY; }
+  if (total == 0) { free(n); return ORC_EEMPTY; }
+  /* (f) the new population: parents in ascending slot order, each repeated
+     n_j times contiguously, exact copies (spins, E and M) */
+  size_t N = (size_t)p->N;
+  int8_t* ns = (int8_t*)malloc((size_t)p->cap * N);
+  int32_t* nE = (int32_t*)malloc((size_t)p->cap * sizeof(int32_t));
+  int32_t* nM = (int32_t*)malloc((size_t)p->cap * sizeof(int32_t));
+  if (!ns || !nE || !nM) {
+    free(ns); free(nE); free(nM); free(n);
+    return ORC_ENOMEM;
+  }
+  int64_t k = 0;
+  for (int64_t j = 0; j < p->R; ++j) {
+    for (uint32_t c = 0; c < n[j]; ++c) {
+      memcpy(ns + (size_t)k * N, p->spins + (size_t)j * N, N);
+      nE[k] = p->E[j];
+      nM[k] = p->M[j];
+      ++k;
+    }
+  }
+  memcpy(p->n, n, (size_t)p->R * sizeof(uint32_t));
+  p->n_len = p->R;
+  free(n);
+  free(p->spins); free(p->E); free(p->M);
+  p->spins = ns; p->E = nE; p->M = nM;
+  p->R = total;
+  p->beta = beta_next;
+  p->step += 1;
+  p->sweeps_at_step = 0;
+  p->lnQ_last = lnQ;
+  /* Eq. Free-En (read with the logarithm): ln Z accumulates ln Q */
+  p->lnZ = p->lnZ + lnQ;
+  return ORC_OK;
+}
+
+/* ---------------------------------------------------------------- sweeps */
+
+static uint64_t splitmix(uint64_t* s) {
+  uint64_t z = (*s += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+/* Step 4 of the method: theta checkerboard Metropolis sweeps of one replica
+   (spins s, energy *E, magnetisation *M) at the inverse temperature whose
+   thresholds are T4, T8.  Sites of colour c have (x+y) mod 2 = c; a colour-c
+   site with k = x/2 uses word k mod 4 of group y*ceil(L/8) + k/4 of the MCMC
+   stream (step, half sweep 2t+c, slot, population), where t counts the
+   sweeps made at this step before this one (t0 of them precede the call). */
+static void sweep_one(int L, const int8_t* J, int8_t* s, int32_t* E,
+                      int32_t* M, uint64_t seed, uint32_t pop, int step,
+                      int t0, int theta, uint32_t slot, uint64_t T4,
+                      uint64_t T8, uint64_t shuffle_seed) {
+  int G8 = (L + 7) / 8;
+  int half = L * L / 2;
+  int* order = (int*)malloc((size_t)half * sizeof(int));
+  for (int t = 0; t < theta; ++t) {
+    int tt = t0 + t;
+    for (int c = 0; c < 2; ++c) {
+      int cnt = 0;
+      for (int y = 0; y < L; ++y)
+        for (int x = 0; x < L; ++x)
+          if (((x + y) & 1) == c) order[cnt++] = y * L + x;
+      if (shuffle_seed) {
+        uint64_t st = shuffle_seed ^ ((uint64_t)slot << 20) ^
+                      ((uint64_t)tt << 4) ^ (uint64_t)c;
+        for (int i = cnt - 1; i > 0; --i) {
+          int r = (int)(splitmix(&st) % (uint64_t)(i + 1));
+          int tmp = order[i]; order[i] = order[r]; order[r] = tmp;
+        }
+      }
+      for (int i = 0; i < cnt; ++i) {
+        int x = order[i] % L, y = order[i] / L;
+        int xl = (x + L - 1) % L, xr = (x + 1) % L;
+        int yu = (y + L - 1) % L, yd = (y + 1) % L;
+        int sv = s[y * L + x];
+        /* unsatisfied bonds: coupling * sigma * neighbour < 0 */
+        int a = 0;
+        a += (bond(J, L, 0, x, y) * sv * s[y * L + xr] < 0);
+        a += (bond(J, L, 0, xl, y) * sv * s[y * L + xl] < 0);
+        a += (bond(J, L, 1, x, y) * sv * s[yd * L + x] < 0);
+        if (ORC_MUTANT != 1)
+          a += (bond(J, L, 1, x, (ORC_MUTANT == 3) ? y : yu) * sv *
+                    s[yu * L + x] < 0);
+        int dE = 8 - 4 * a;
+        int k = x / 2;
+        uint32_t r = draw_word(seed, DOMAIN_MCMC, (uint32_t)(y * G8 + k / 4),
+                               (uint32_t)step, (uint32_t)(2 * tt + c), slot,
+                               pop, k % 4);
+        int accept;
+        if (dE <= 0) accept = 1;
+        else if (ORC_MUTANT == 4) accept = (uint64_t)r < (dE == 4 ? T8 : T4);
+        else accept = (uint64_t)r < (dE == 4 ? T4 : T8);
+        if (accept) {
+          s[y * L + x] = (int8_t)(-sv);
+          *E += dE;
+          *M += 2 * (-sv);
+        }
+      }
+    }
+  }
+  free(order);
+}
+
+/* Metropolis acceptance probabilities exp(-beta dE) for dE = 4, 8 as
+   32-bit integer thresholds: accept iff r < floor(p 2^32). */
+static void thresholds(double beta, uint64_t* T4, uint64_t* T8) {
+  *T4 = (uint64_t)floor(ldexp(exp(-(beta * 4.0)), 32));
+  *T8 = (uint64_t)floor(ldexp(exp(-(beta * 8.0)), 32));
+}
+
+int orc_sweep_replica(int L, const int8_t* J, int8_t* spins, int32_t* E,
+                      int32_t* M, double beta, uint64_t seed, uint32_t pop,
+                      int step, int t0, int theta, uint32_t slot) {
+  if (L < 4 || L > 128 || (L % 2) || !spins || !E || !M || theta < 0 ||
+      t0 < 0 || t0 + theta > 32767 || !isfinite(beta))
+    return ORC_EINVAL;
+  uint64_t T4, T8;
+  thresholds(beta, &T4, &T8);
+  sweep_one(L, J, spins, E, M, seed, pop, step, t0, theta, slot, T4, T8, 0);
+  return ORC_OK;
+}
+
+int orc_sweep(orc_pa* p, int theta) {
+  if (!p || theta < 0) return ORC_EINVAL;
+  if (p->sweeps_at_step + theta > 32767) return ORC_EINVAL;
+  uint64_t T4, T8;
+  thresholds(p->beta, &T4, &T8);
+  for (int64_t j = 0; j < p->R; ++j)
+    sweep_one(p->L, p->J, p->spins + (size_t)j * p->N, &p->E[j], &p->M[j],
+              p->seed, p->pop, p->step, p->sweeps_at_step, theta, (uint32_t)j,
+              T4, T8, p->shuffle_seed);
+  p->sweeps_at_step += theta;
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------ observables */
+
+int orc_observables(const orc_pa* p, orc_obs* o) {
+  if (!p || !o) return ORC_EINVAL;
+  int64_t sE = 0, sE2 = 0, sAM = 0, sM2 = 0;
+  int32_t mn = 2 * p->N + 1, mx = -2 * p->N - 1;
+  for (int64_t j = 0; j < p->R; ++j) {
+    int64_t e = p->E[j], m = p->M[j];
+    sE += e;
+    sE2 += e * e;
+    sAM += m < 0 ? -m : m;
+    sM2 += m * m;
+    if (p->E[j] < mn) mn = p->E[j];
+    if (p->E[j] > mx) mx = p->E[j];
+  }
+  double R = (double)p->R, N = (double)p->N;
+  __int128 var = (__int128)p->R * sE2 - (__int128)sE * sE;
+  o->R = p->R;
+  o->beta = p->beta;
+  o->e = (double)sE / (R * N);
+  o->abs_m = (double)sAM / (R * N);
+  o->m2 = (double)sM2 / (R * N * N);
+  o->C = ((p->beta * p->beta) * (double)var) / ((R * R) * N);
+  o->sumE = sE;
+  o->sumE2 = sE2;
+  o->sumAbsM = sAM;
+  o->sumM2 = sM2;
+  o->Emin = mn;
+  o->Emax = mx;
+  return ORC_OK;
+}
+
+int orc_free_energy(const orc_pa* p, double* lnZ, double* lnQ_last) {
+  if (!p) return ORC_EINVAL;
+  if (lnZ) *lnZ = p->lnZ;
+  if (lnQ_last) *lnQ_last = p->lnQ_last;
+  return ORC_OK;
+}
+
+/* -------------------------------------------------------------- accessors */
+
+int64_t orc_R(const orc_pa* p) { return p->R; }
+double orc_beta(const orc_pa* p) { return p->beta; }
+int orc_step(const orc_pa* p) { return p->step; }
+
+int orc_get_population(const orc_pa* p, int8_t* spins, int32_t* E,
+                       int32_t* M, int64_t cap) {
+  if (!p || cap < p->R) return ORC_EINVAL;
+  if (spins) memcpy(spins, p->spins, (size_t)p->R * p->N);
+  if (E) memcpy(E, p->E, (size_t)p->R * sizeof(int32_t));
+  if (M) memcpy(M, p->M, (size_t)p->R * sizeof(int32_t));
+  return ORC_OK;
+}
+
+int orc_get_counts(const orc_pa* p, uint32_t* n, int64_t cap) {
+  if (!p || !n || cap < p->n_len) return ORC_EINVAL;
+  memcpy(n, p->n, (size_t)p->n_len * sizeof(uint32_t));
+  return (int)0;
+}
+
+int orc_set_population(orc_pa* p, const int8_t* spins, int64_t R) {
+  if (!p || !spins || R < 1 || R > p->cap) return ORC_EINVAL;
+  for (int64_t i = 0; i < R * p->N; ++i)
+    if (spins[i] != 1 && spins[i] != -1) return ORC_EINVAL;
+  memcpy(p->spins, spins, (size_t)R * p->N);
+  for (int64_t j = 0; j < R; ++j)
+    orc_energy(p->L, p->J, p->spins + (size_t)j * p->N, &p->E[j], &p->M[j]);
+  p->R = R;
+  p->n_len = 0;
+  return ORC_OK;
+}
+
+int orc_histogram(const orc_pa* p, uint32_t* out) {
+  if (!p || !out) return ORC_EINVAL;
+  memset(out, 0, (size_t)(4 * p->N + 1) * sizeof(uint32_t));
+  for (int64_t j = 0; j < p->R; ++j) out[p->E[j] + 2 * p->N] += 1;
+  return ORC_OK;
+}
+
+void orc_set_visit_shuffle(orc_pa* p, uint64_t shuffle_seed) {
+  if (p) p->shuffle_seed = shuffle_seed;
+}
+
+/* ------------------------------------------------------ adaptive schedule */
+
+/* Overlap of the energy distribution at beta with the reweighted one at
+   beta + dbeta: alpha = sum_E min(P(E), P'(E)) with P = h/R and
+   P' = h w / sum h w, w = exp(-dbeta (E - Emin)).  1 - alpha is the
+   fraction of the population the resampling culls on average, the quantity
+   an adaptive step (Sec. 3, last paragraph on fluctuations) keeps fixed. */
+int orc_overlap(const orc_pa* p, double dbeta, double* alpha) {
+  if (!p || !alpha || !isfinite(dbeta) || dbeta < 0.0) return ORC_EINVAL;
+  int N = p->N;
+  int nlev = 4 * N + 1;
+  uint32_t* h = (uint32_t*)calloc((size_t)nlev, sizeof(uint32_t));
+  if (!h) return ORC_ENOMEM;
+  int32_t Emin = 2 * N + 1;
+  for (int64_t j = 0; j < p->R; ++j) {
+    h[p->E[j] + 2 * N] += 1;
+    if (p->E[j] < Emin) Emin = p->E[j];
+  }
+  double S = 0.0;
+  for (int e = -2 * N; e <= 2 * N; ++e) {
+    uint32_t c = h[e + 2 * N];
+    if (c == 0) continue;
+    double term = (double)c * exp(-(dbeta * (double)(e - Emin)));
+    S = S + term;
+  }
+  double a = 0.0;
+  for (int e = -2 * N; e <= 2 * N; ++e) {
+    uint32_t c = h[e + 2 * N];
+    if (c == 0) continue;
+    double pe = (double)c / (double)p->R;
+    double qe = ((double)c * exp(-(dbeta * (double)(e - Emin)))) / S;
+    a = a + (pe < qe ? pe : qe);
+  }
+  free(h);
+  *alpha = a;
+  return ORC_OK;
+}
+
+/* Largest step dbeta <= beta_f - beta whose overlap is at least target:
+   the whole remaining interval if it qualifies, otherwise 64 halvings of
+   [0, beta_f - beta] keeping the lower end qualified. */
+int orc_bisect_dbeta(const orc_pa* p, double target, double beta_f,
+                     double* dbeta) {
+  if (!p || !dbeta || !(target > 0.0 && target <= 1.0) || !isfinite(beta_f))
+    return ORC_EINVAL;
+  double span = beta_f - p->beta;
+  if (!(span > 0.0)) { *dbeta = 0.0; return ORC_OK; }
+  double a;
+  int rc = orc_overlap(p, span, &a);
+  if (rc) return rc;
+  if (a >= target) { *dbeta = span; return ORC_OK; }
+  double lo = 0.0, hi = span;
+  for (int it = 0; it < 64; ++it) {
+    double mid = 0.5 * (lo + hi);
+    rc = orc_overlap(p, mid, &a);
+    if (rc) return rc;
+    if (a >= target) lo = mid;
+    else hi = mid;
+  }
+  *dbeta = lo;
+  return ORC_OK;
+}

@@ -1,0 +1,46 @@
+"""The oracle's pins must catch plausible mistakes.  Each case builds the
+oracle with one planted mistake (a dropped term, a wrong sign, a wrong or
+transposed index, swapped operands) and reruns the pins that should see it,
+in a subprocess, expecting them to fail."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+import oracle
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+
+CASES = {
+    1: ("dropped up-neighbour term in the local field",
+        ["test_oracle_model.py::test_metropolis_samples_boltzmann_L4",
+         "test_oracle_model.py::test_tracked_energy_equals_recomputed_after_annealing"]),
+    2: ("wrong sign of the energy shift in ln Q",
+        ["test_oracle_resample.py::test_counts_are_floor_or_ceil_of_mean"]),
+    3: ("wrong row index of the upper bond coupling",
+        ["test_oracle_physics.py::test_gauge_symmetry_of_pmJ_model"]),
+    4: ("acceptance thresholds of dE=4 and dE=8 swapped",
+        ["test_oracle_model.py::test_metropolis_samples_boltzmann_L4"]),
+    5: ("transposed index of the right neighbour in the energy",
+        ["test_oracle_model.py::test_energy_matches_bond_sum"]),
+    6: ("level multiplicity dropped from the weight sum",
+        ["test_oracle_resample.py::test_counts_are_floor_or_ceil_of_mean"]),
+    7: ("ln Omega dropped from the free energy",
+        ["test_oracle_physics.py::test_lnZ_and_Zhat_unbiased_L4"]),
+}
+
+
+@pytest.mark.parametrize("mutant", sorted(CASES))
+def test_planted_mistake_is_caught(mutant, tmp_path):
+    what, pins = CASES[mutant]
+    so = str(tmp_path / ("liboracle_m%d.so" % mutant))
+    oracle.build(mutant=mutant, out=so)
+    env = dict(os.environ, PA_ORACLE_SO=so)
+    for pin in pins:
+        r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q",
+                            os.path.join(HERE, pin)], cwd=ROOT, env=env,
+                           capture_output=True, text=True, timeout=300)
+        assert r.returncode != 0, "mutant %d (%s) passed %s" % (mutant, what,
+                                                               pin)
