@@ -1,0 +1,208 @@
+#!/usr/bin/env python3
+"""Benchmark of the population-annealing hot path on one MI355X.
+
+One benchmark step is one full anneal of a synthetic population, every step
+of the method on the device: init at beta_0 = 0, then for each of the K
+temperatures the energy histogram, the host reweighting tables, copy counts,
+scan, gather-copy, theta Metropolis sweeps and the observables, with the
+free energy accumulated on the way.
+
+Default workload: the 2D Ising ferromagnet, L = 64 periodic, R = 65536
+replicas, int8 spins, beta 0 -> 1 in 200 linear steps, theta = 10.
+
+Prints one JSON line (rank 0):
+  value           spin-flip attempts per ns over the whole timed anneals
+  roofline        the sweep kernel (dominant) against the VALU issue peak,
+                  from HIP events on the library's stream
+  resample        achieved HBM bandwidth of histogram+counts+scatter+gather
+  cpu_baseline    the single-threaded oracle timed on a bounded sample of the
+                  same workload on this host
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import pa_workloads as W  # noqa: E402
+
+METRIC = ("spin-flip attempts/ns + resample GB/s (% HBM peak); wall time to "
+          "β_f plain vs batched+MLP Δβ")
+HBM_PEAK_GBPS = 8000.0
+# VALU issue peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+VALU_LANE_CYCLES_PER_S = 256 * 4 * 16 * 2.4e9
+# Issue cost of one spin-flip attempt in VALU lane-cycles: a quarter of a
+# Philox4x32-10 block (20 v_mad_u64_u32 at a quarter of the full rate and 40
+# v_xor_b32, i.e. 120 lane-cycles per 4 words) plus the two threshold
+# compares and accumulates of the site (4 lane-cycles).
+LANE_CYCLES_PER_ATTEMPT = 120 / 4 + 4
+
+
+def run_anneal(binding, cfg, stream, timing=False, rows_per_lane=0):
+    layout = binding.PA_BITS if cfg["layout"] == "bits" else binding.PA_INT8
+    L, R, theta = cfg["L"], cfg["R"], cfg["theta"]
+    g = binding.Population(L, R, seed=cfg["seed"], layout=layout,
+                           rows_per_lane=rows_per_lane, stream=stream)
+    if timing:
+        g.set_timing(True)
+    attempts = 0
+    for b in W.linear_schedule(cfg["beta_f"], cfg["K"]):
+        g.resample(b)
+        attempts += g.R * L * L * theta
+        g.sweep(b, theta)
+        g.observables()
+    lnZ, _ = g.free_energy()
+    t = g.timing() if timing else None
+    g.close()
+    return attempts, lnZ, t
+
+
+def cpu_baseline(cfg, budget_s=15.0):
+    """The oracle (single thread) on the first temperature steps of the same
+    workload with a reduced population, scaled to attempts/ns."""
+    import oracle
+    oracle.build(force=False)
+    L, theta = cfg["L"], cfg["theta"]
+    R = 2048
+    sched = W.linear_schedule(cfg["beta_f"], cfg["K"])
+    p = oracle.OraclePA(L, R, seed=cfg["seed"])
+    t0 = time.perf_counter()
+    attempts, steps = 0, 0
+    for b in sched:
+        p.resample(b)
+        attempts += p.R * L * L * theta
+        p.sweep(theta)
+        p.observables()
+        steps += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": attempts / (dt * 1e9), "unit": "spin-flip attempts/ns",
+            "cores": 1, "kind": "oracle",
+            "sample": "%s shape with R=%d replicas, first %d of %d temperature "
+                      "steps (resample + %d sweeps + observables), %.1f s, "
+                      "single thread" % (cfg.get("name", "?"), R, steps,
+                                         cfg["K"], theta, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="C2", choices=sorted(W.CONFIGS))
+    ap.add_argument("--rows-per-lane", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU "
+              "path (the population would shard by replica slots; see the "
+              "design notes).  Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2006_00561_amd import binding
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream().cuda_stream
+    cfg = dict(W.CONFIGS[args.workload])
+    cfg["name"] = args.workload
+
+    for _ in range(args.warmup):
+        run_anneal(binding, cfg, stream, rows_per_lane=args.rows_per_lane)
+    torch.cuda.synchronize()
+
+    total_attempts = 0
+    tsum = None
+    lnZs = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        a, lnZ, t = run_anneal(binding, cfg, stream, timing=True,
+                               rows_per_lane=args.rows_per_lane)
+        total_attempts += a
+        lnZs.append(lnZ)
+        if tsum is None:
+            tsum = t
+        else:
+            for k in binding.KERNEL_CLASSES:
+                for f in ("ms", "launches", "bytes"):
+                    tsum[k][f] += t[k][f]
+            tsum["attempts"] += t["attempts"]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+
+    sw = tsum["sweep"]
+    sweep_avg_ms = sw["ms"] / max(1, sw["launches"])
+    sweep_rate = tsum["attempts"] / (sw["ms"] * 1e6)       # attempts/ns
+    achieved = tsum["attempts"] / sw["launches"] * LANE_CYCLES_PER_ATTEMPT / (
+        sweep_avg_ms * 1e-3) / 1e12
+    peak = VALU_LANE_CYCLES_PER_S / 1e12
+    res_ms = sum(tsum[k]["ms"] for k in ("hist", "counts", "scatter",
+                                         "gather"))
+    res_bytes = sum(tsum[k]["bytes"] for k in ("hist", "counts", "scatter",
+                                               "gather"))
+    res_gbps = res_bytes / (res_ms * 1e6) if res_ms > 0 else 0.0
+    g_ms = tsum["gather"]["ms"]
+    gather_gbps = tsum["gather"]["bytes"] / (g_ms * 1e6) if g_ms > 0 else 0.0
+
+    out = {
+        "metric": METRIC,
+        "value": total_attempts / (dt * 1e9),
+        "unit": "spin-flip attempts/ns",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": "%s: 2D Ising ferromagnet L=%d periodic, R=%d, %s "
+                        "spins, beta 0->%g in %d linear steps, theta=%d, "
+                        "seed %d; one step = one full anneal"
+                        % (args.workload, cfg["L"], cfg["R"], cfg["layout"],
+                           cfg["beta_f"], cfg["K"], cfg["theta"],
+                           cfg["seed"]),
+            "L": cfg["L"], "R": cfg["R"], "K": cfg["K"],
+            "theta": cfg["theta"], "layout": cfg["layout"],
+        },
+        "roofline": {
+            "kernel": "k_lattice (theta fused Metropolis sweeps)",
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": peak,
+            "unit": "T VALU lane-cycles/s",
+            "frac": achieved / peak,
+            "traffic": None,
+            "sweep_attempts_per_ns": sweep_rate,
+            "sweep_avg_ms": sweep_avg_ms,
+            "lane_cycles_per_attempt": LANE_CYCLES_PER_ATTEMPT,
+        },
+        "resample": {
+            "GBps": res_gbps,
+            "frac_hbm": res_gbps / HBM_PEAK_GBPS,
+            "gather_GBps": gather_gbps,
+            "ms_per_anneal": res_ms / args.steps,
+            "kernel_ms": {k: tsum[k]["ms"] / args.steps for k in
+                          binding.KERNEL_CLASSES},
+        },
+        "wall_time_to_beta_f_s": dt / args.steps,
+        "lnZ_final": lnZs[-1],
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,718 @@
+// C ABI of libpa.so: host orchestration of the population-annealing hot path
+// on one gfx950 device.  All per-replica work runs in the kernels of
+// pa_kernels.hip; the host only turns the exact integer energy histogram
+// into double-precision per-level tables (Eqs. part-Q, tau, Free-En) and
+// keeps beta, the step index and ln Z.
+//
+// The double-precision host arithmetic is written as plain IEEE operations
+// in a fixed order (per energy level, ascending energy) and compiled with
+// -ffp-contract=off, so every table entry is reproducible bit for bit.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "pa.h"
+#include "pa_internal.h"
+
+using namespace pa;
+
+namespace {
+
+struct TimedLaunch {
+  int cls;
+  hipEvent_t ev0, ev1;
+  int64_t bytes, attempts;
+};
+
+int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+}  // namespace
+
+struct pa_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int L = 0, N = 0, model = 0, layout = 0, W = 0, rpl = 1, lpr = 0, rpw = 0;
+  int64_t R_t = 0, cap = 0, R = 0, stride = 0, ntiles_cap = 0;
+  uint64_t seed = 0;
+  uint32_t pop = 0;
+  double beta = 0.0, lnZ = 0.0, lnQ_last = 0.0;
+  int step = 0, sweeps_at_step = 0, cur = 0;
+  uint8_t* spins[2] = {nullptr, nullptr};
+  int32_t* E[2] = {nullptr, nullptr};
+  int32_t* M[2] = {nullptr, nullptr};
+  uint32_t* n = nullptr;
+  uint32_t* parent = nullptr;
+  uint32_t* tile_sum = nullptr;
+  uint32_t* tile_off = nullptr;
+  uint32_t* hist = nullptr;
+  uint32_t* tab = nullptr;              // [2][nbins]: f then T
+  unsigned long long* scal = nullptr;   // sum|M|, sum M^2, total, survivors
+  uint32_t* jbits = nullptr;
+  uint32_t* h_hist = nullptr;           // pinned host mirrors
+  unsigned long long* h_scal = nullptr;
+  uint32_t* h_tab = nullptr;
+  int nbins = 0, hshift = 0;
+  bool hist_valid = false;
+  int64_t n_len = 0;
+  bool timing = false;
+  std::vector<TimedLaunch> pending;
+  std::vector<hipEvent_t> pool;
+  pa_timing acc{};
+};
+
+#define CK(x)                                  \
+  do {                                         \
+    if ((x) != hipSuccess) return PA_EDEVICE;  \
+  } while (0)
+
+namespace {
+
+// ------------------------------------------------------------------ timing
+
+hipEvent_t take_event(pa_ctx* c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+hipEvent_t t_begin(pa_ctx* c) {
+  if (!c->timing) return nullptr;
+  hipEvent_t e = take_event(c);
+  if (e) hipEventRecord(e, c->stream);
+  return e;
+}
+
+void t_end(pa_ctx* c, int cls, hipEvent_t e0, int64_t bytes,
+           int64_t attempts) {
+  if (!c->timing || !e0) return;
+  hipEvent_t e1 = take_event(c);
+  if (!e1) return;
+  hipEventRecord(e1, c->stream);
+  c->pending.push_back({cls, e0, e1, bytes, attempts});
+}
+
+// After a stream synchronisation: fold finished launches into the totals.
+void t_harvest(pa_ctx* c) {
+  for (auto& t : c->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, t.ev0, t.ev1) == hipSuccess) {
+      c->acc.ms[t.cls] += ms;
+      c->acc.launches[t.cls] += 1;
+      c->acc.bytes[t.cls] += t.bytes;
+      c->acc.attempts += t.attempts;
+    }
+    c->pool.push_back(t.ev0);
+    c->pool.push_back(t.ev1);
+  }
+  c->pending.clear();
+}
+
+int sync(pa_ctx* c) {
+  CK(hipStreamSynchronize(c->stream));
+  t_harvest(c);
+  return PA_OK;
+}
+
+// --------------------------------------------------------- double tables
+
+// Metropolis acceptance probabilities exp(-beta dE) for dE = 4, 8 as 32-bit
+// integer thresholds floor(p 2^32); a threshold of 2^32 means "always".
+void thresholds(double beta, LatticeArgs& a) {
+  const uint64_t T4 = (uint64_t)std::floor(std::ldexp(std::exp(-(beta * 4.0)), 32));
+  const uint64_t T8 = (uint64_t)std::floor(std::ldexp(std::exp(-(beta * 8.0)), 32));
+  a.all4 = T4 >= (1ull << 32);
+  a.all8 = T8 >= (1ull << 32);
+  a.T4 = a.all4 ? 0xFFFFFFFFu : (uint32_t)T4;
+  a.T8 = a.all8 ? 0xFFFFFFFFu : (uint32_t)T8;
+}
+
+LatticeArgs lattice_args(pa_ctx* c) {
+  LatticeArgs a{};
+  a.spins = c->spins[c->cur];
+  a.E = c->E[c->cur];
+  a.M = c->M[c->cur];
+  a.jbits = c->jbits;
+  a.R = c->R;
+  a.stride = c->stride;
+  a.L = c->L;
+  a.lpr = c->lpr;
+  a.rpw = c->rpw;
+  a.k0 = (uint32_t)(c->seed & 0xFFFFFFFFu);
+  a.k1 = (uint32_t)(c->seed >> 32);
+  a.pop = c->pop;
+  a.step = (uint32_t)c->step;
+  a.t0 = c->sweeps_at_step;
+  return a;
+}
+
+int run_lattice(pa_ctx* c, LatticeArgs& a, int cls) {
+  hipEvent_t e0 = t_begin(c);
+  CK(launch_lattice(a, c->W, c->rpl, c->layout == PA_INT8, c->model == PA_PMJ,
+                    c->stream));
+  t_end(c, cls, e0, (a.init ? 1 : 2) * c->R * c->stride + 8 * c->R,
+        (int64_t)c->R * c->N * a.theta);
+  return PA_OK;
+}
+
+// Exact energy histogram and |M|, M^2 sums of the current population,
+// mirrored into pinned host memory.
+int compute_hist(pa_ctx* c) {
+  if (c->hist_valid) return PA_OK;
+  CK(launch_fill_u32(c->hist, c->nbins, 0u, c->stream));
+  CK(launch_fill_u32(reinterpret_cast<uint32_t*>(c->scal), 8, 0u, c->stream));
+  HistArgs h{};
+  h.E = c->E[c->cur];
+  h.M = c->M[c->cur];
+  h.hist = c->hist;
+  h.moments = c->scal;
+  h.R = c->R;
+  h.twoN = 2 * c->N;
+  h.shift = c->hshift;
+  h.nbins = c->nbins;
+  h.use_lds = (int64_t)c->nbins * 4 <= 64 * 1024;
+  hipEvent_t e0 = t_begin(c);
+  CK(launch_hist(h, c->stream));
+  t_end(c, PA_K_HIST, e0, 8 * c->R, 0);
+  CK(hipMemcpyAsync(c->h_hist, c->hist, (size_t)c->nbins * 4,
+                    hipMemcpyDeviceToHost, c->stream));
+  CK(hipMemcpyAsync(c->h_scal, c->scal, 4 * sizeof(unsigned long long),
+                    hipMemcpyDeviceToHost, c->stream));
+  int rc = sync(c);
+  if (rc) return rc;
+  if (c->h_scal[3] != 0) return PA_EDEVICE;  // an energy outside [-2N, 2N]
+  c->hist_valid = true;
+  return PA_OK;
+}
+
+int level_energy(const pa_ctx* c, int i) { return -2 * c->N + (i << c->hshift); }
+
+void occupied(const pa_ctx* c, int* lo, int* hi) {
+  int a = 0, b = c->nbins - 1;
+  while (a < c->nbins && c->h_hist[a] == 0) ++a;
+  while (b >= 0 && c->h_hist[b] == 0) --b;
+  *lo = a;
+  *hi = b;
+}
+
+// Overlap alpha(dbeta) = sum_E min(h/R, h w / S) from the host histogram.
+double overlap_of(const pa_ctx* c, double dbeta) {
+  int lo, hi;
+  occupied(c, &lo, &hi);
+  const int Emin = level_energy(c, lo);
+  double S = 0.0;
+  for (int i = lo; i <= hi; ++i) {
+    const uint32_t h = c->h_hist[i];
+    if (h == 0) continue;
+    const double term =
+        (double)h * std::exp(-(dbeta * (double)(level_energy(c, i) - Emin)));
+    S = S + term;
+  }
+  double a = 0.0;
+  for (int i = lo; i <= hi; ++i) {
+    const uint32_t h = c->h_hist[i];
+    if (h == 0) continue;
+    const double pe = (double)h / (double)c->R;
+    const double qe =
+        ((double)h * std::exp(-(dbeta * (double)(level_energy(c, i) - Emin)))) / S;
+    a = a + (pe < qe ? pe : qe);
+  }
+  return a;
+}
+
+void free_all(pa_ctx* c) {
+  for (int b = 0; b < 2; ++b) {
+    if (c->spins[b]) (void)hipFree(c->spins[b]);
+    if (c->E[b]) (void)hipFree(c->E[b]);
+    if (c->M[b]) (void)hipFree(c->M[b]);
+  }
+  void* dev[] = {c->n, c->parent, c->tile_sum, c->tile_off, c->hist, c->tab,
+                 c->scal, c->jbits};
+  for (void* p : dev)
+    if (p) (void)hipFree(p);
+  if (c->h_hist) (void)hipHostFree(c->h_hist);
+  if (c->h_scal) (void)hipHostFree(c->h_scal);
+  if (c->h_tab) (void)hipHostFree(c->h_tab);
+  for (auto& t : c->pending) {
+    (void)hipEventDestroy(t.ev0);
+    (void)hipEventDestroy(t.ev1);
+  }
+  for (auto e : c->pool) (void)hipEventDestroy(e);
+}
+
+template <typename T>
+bool dmalloc(T** p, size_t bytes) {
+  return hipMalloc(reinterpret_cast<void**>(p), bytes ? bytes : 16) == hipSuccess;
+}
+
+// canonical int8 [L][L] -> device layout of one replica (stride bytes)
+void pack_replica(const pa_ctx* c, const int8_t* s, uint8_t* out) {
+  std::memset(out, 0, (size_t)c->stride);
+  if (c->layout == PA_INT8) {
+    std::memcpy(out, s, (size_t)c->N);
+    return;
+  }
+  uint32_t* w = reinterpret_cast<uint32_t*>(out);
+  for (int y = 0; y < c->L; ++y)
+    for (int x = 0; x < c->L; ++x)
+      if (s[y * c->L + x] == 1) w[y * c->W + x / 32] |= 1u << (x % 32);
+}
+
+void unpack_replica(const pa_ctx* c, const uint8_t* in, int8_t* s) {
+  if (c->layout == PA_INT8) {
+    std::memcpy(s, in, (size_t)c->N);
+    return;
+  }
+  const uint32_t* w = reinterpret_cast<const uint32_t*>(in);
+  for (int y = 0; y < c->L; ++y)
+    for (int x = 0; x < c->L; ++x)
+      s[y * c->L + x] = ((w[y * c->W + x / 32] >> (x % 32)) & 1u) ? 1 : -1;
+}
+
+}  // namespace
+
+// =================================================================== ABI
+
+extern "C" {
+
+const char* pa_strerror(int code) {
+  switch (code) {
+    case PA_OK: return "ok";
+    case PA_EINVAL: return "invalid argument";
+    case PA_ENOMEM: return "out of memory";
+    case PA_ECAPACITY: return "population would exceed the capacity";
+    case PA_EDEVICE: return "HIP runtime error";
+    case PA_ESTATE: return "call out of order";
+    case PA_EEMPTY: return "resampling drew no replica";
+    default: return "unknown error";
+  }
+}
+
+int pa_init(const pa_config* cfg, pa_ctx** out) {
+  if (!out) return PA_EINVAL;
+  *out = nullptr;
+  if (!cfg) return PA_EINVAL;
+  const int L = cfg->L;
+  if (L < 4 || L > 128 || (L & 1)) return PA_EINVAL;
+  if (cfg->model != PA_FERRO && cfg->model != PA_PMJ) return PA_EINVAL;
+  if (cfg->model == PA_PMJ && !cfg->J) return PA_EINVAL;
+  if (cfg->layout != PA_INT8 && cfg->layout != PA_BITS) return PA_EINVAL;
+  if (cfg->R_target < 1 || cfg->R_target >= (1ll << 31)) return PA_EINVAL;
+  int64_t cap = cfg->capacity;
+  if (cap == 0)
+    cap = cfg->R_target +
+          16 * (int64_t)std::ceil(std::sqrt((double)cfg->R_target)) + 1024;
+  if (cap < cfg->R_target || cap >= (1ll << 32)) return PA_EINVAL;
+  const int W = (L + 31) / 32;
+  int rpl = cfg->rows_per_lane;
+  if (rpl == 0) rpl = (L > 64) ? 2 : 1;
+  if (rpl != 1 && rpl != 2 && rpl != 4) return PA_EINVAL;
+  if (L % rpl != 0 || L / rpl > 64) return PA_EINVAL;
+  if (W >= 3 && rpl < 2) return PA_EINVAL;
+  if (cfg->model == PA_PMJ) {
+    for (int64_t i = 0; i < 2ll * L * L; ++i)
+      if (cfg->J[i] != 1 && cfg->J[i] != -1) return PA_EINVAL;
+  }
+
+  pa_ctx* c = new (std::nothrow) pa_ctx();
+  if (!c) return PA_ENOMEM;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return PA_EDEVICE;
+  }
+  c->stream = reinterpret_cast<hipStream_t>(cfg->stream);
+  c->L = L;
+  c->N = L * L;
+  c->model = cfg->model;
+  c->layout = cfg->layout;
+  c->W = W;
+  c->rpl = rpl;
+  c->lpr = L / rpl;
+  c->rpw = 64 / c->lpr;
+  c->R_t = cfg->R_target;
+  c->cap = cap;
+  c->seed = cfg->seed;
+  c->pop = cfg->population_id;
+  c->stride = (c->layout == PA_INT8) ? round_up(c->N, 16)
+                                     : round_up((int64_t)L * W * 4, 16);
+  c->hshift = (c->model == PA_FERRO) ? 2 : 1;
+  c->nbins = (4 * c->N >> c->hshift) + 1;
+  c->ntiles_cap = (cap + 255) / 256;
+
+  bool ok = true;
+  for (int b = 0; b < 2 && ok; ++b) {
+    ok = ok && dmalloc(&c->spins[b], (size_t)(cap * c->stride));
+    ok = ok && dmalloc(&c->E[b], (size_t)cap * 4);
+    ok = ok && dmalloc(&c->M[b], (size_t)cap * 4);
+  }
+  ok = ok && dmalloc(&c->n, (size_t)cap * 4);
+  ok = ok && dmalloc(&c->parent, (size_t)cap * 4);
+  ok = ok && dmalloc(&c->tile_sum, (size_t)c->ntiles_cap * 4);
+  ok = ok && dmalloc(&c->tile_off, (size_t)c->ntiles_cap * 4);
+  ok = ok && dmalloc(&c->hist, (size_t)c->nbins * 4);
+  ok = ok && dmalloc(&c->tab, (size_t)c->nbins * 8);
+  ok = ok && dmalloc(&c->scal, 4 * sizeof(unsigned long long));
+  ok = ok && dmalloc(&c->jbits, (size_t)2 * L * W * 4);
+  ok = ok && hipHostMalloc(reinterpret_cast<void**>(&c->h_hist),
+                           (size_t)c->nbins * 4) == hipSuccess;
+  ok = ok && hipHostMalloc(reinterpret_cast<void**>(&c->h_scal),
+                           4 * sizeof(unsigned long long)) == hipSuccess;
+  ok = ok && hipHostMalloc(reinterpret_cast<void**>(&c->h_tab),
+                           (size_t)c->nbins * 8) == hipSuccess;
+  if (!ok) {
+    free_all(c);
+    delete c;
+    return PA_ENOMEM;
+  }
+  // +-J couplings as row bit masks, bit set where J < 0
+  std::vector<uint32_t> jb((size_t)2 * L * W, 0u);
+  if (c->model == PA_PMJ)
+    for (int d = 0; d < 2; ++d)
+      for (int y = 0; y < L; ++y)
+        for (int x = 0; x < L; ++x)
+          if (cfg->J[(size_t)d * L * L + (size_t)y * L + x] < 0)
+            jb[((size_t)d * L + y) * W + x / 32] |= 1u << (x % 32);
+  int rc = PA_OK;
+  if (hipMemcpyAsync(c->jbits, jb.data(), jb.size() * 4, hipMemcpyHostToDevice,
+                     c->stream) != hipSuccess)
+    rc = PA_EDEVICE;
+  if (rc == PA_OK) {
+    c->R = c->R_t;
+    LatticeArgs a = lattice_args(c);
+    a.init = 1;
+    a.theta = 0;
+    rc = run_lattice(c, a, PA_K_INIT);
+  }
+  if (rc == PA_OK) rc = sync(c);
+  if (rc != PA_OK) {
+    free_all(c);
+    delete c;
+    return rc;
+  }
+  c->beta = 0.0;
+  c->lnZ = (double)c->N * std::log(2.0);
+  c->lnQ_last = 0.0;
+  *out = c;
+  return PA_OK;
+}
+
+void pa_destroy(pa_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  free_all(c);
+  delete c;
+}
+
+int pa_sweep(pa_ctx* c, double beta, int32_t theta) {
+  if (!c || theta < 0 || !std::isfinite(beta)) return PA_EINVAL;
+  if (beta != c->beta) return PA_ESTATE;
+  if (c->sweeps_at_step + theta > 32767) return PA_EINVAL;
+  if (theta == 0) return PA_OK;
+  LatticeArgs a = lattice_args(c);
+  thresholds(c->beta, a);
+  a.theta = theta;
+  int rc = run_lattice(c, a, PA_K_SWEEP);
+  if (rc) return rc;
+  c->sweeps_at_step += theta;
+  c->hist_valid = false;
+  return PA_OK;
+}
+
+int pa_resample(pa_ctx* c, double beta_next, int64_t* R_new) {
+  if (!c || !std::isfinite(beta_next) || !(beta_next >= c->beta))
+    return PA_EINVAL;
+  if (c->step + 1 > 65535) return PA_EINVAL;
+  int rc = compute_hist(c);
+  if (rc) return rc;
+  const double dbeta = beta_next - c->beta;
+  int lo, hi;
+  occupied(c, &lo, &hi);
+  if (lo > hi) return PA_ESTATE;
+  const int Emin = level_energy(c, lo);
+  const int nl = hi - lo + 1;
+  // (b) Boltzmann factors shifted by Emin, summed in ascending energy
+  std::vector<double> w((size_t)nl, 0.0);
+  double S = 0.0;
+  for (int i = lo; i <= hi; ++i) {
+    const uint32_t h = c->h_hist[i];
+    if (h == 0) continue;
+    const double we = std::exp(-(dbeta * (double)(level_energy(c, i) - Emin)));
+    w[i - lo] = we;
+    const double term = (double)h * we;
+    S = S + term;
+  }
+  // (c) ln Q with the shift restored (Eq. part-Q)
+  const double lnQ = (-(dbeta * (double)Emin)) + std::log(S / (double)c->R);
+  // (d) rho = R_target tau / R (Eq. tau): integer part and 32-bit threshold
+  uint32_t* tf = c->h_tab;
+  uint32_t* tT = c->h_tab + nl;
+  for (int i = lo; i <= hi; ++i) {
+    tf[i - lo] = 0u;
+    tT[i - lo] = 0u;
+    if (c->h_hist[i] == 0) continue;
+    const double rho = ((double)c->R_t * w[i - lo]) / S;
+    const double fl = std::floor(rho);
+    tf[i - lo] = (uint32_t)fl;
+    tT[i - lo] = (uint32_t)(uint64_t)std::floor(std::ldexp(rho - fl, 32));
+  }
+  CK(hipMemcpyAsync(c->tab, c->h_tab, (size_t)nl * 8, hipMemcpyHostToDevice,
+                    c->stream));
+  // (e) copy counts and their exclusive scan
+  CountsArgs ca{};
+  ca.E = c->E[c->cur];
+  ca.f = c->tab;
+  ca.T = c->tab + nl;
+  ca.n = c->n;
+  ca.tile_sum = c->tile_sum;
+  ca.R = c->R;
+  ca.twoN = 2 * c->N;
+  ca.shift = c->hshift;
+  ca.lvl0 = lo;
+  ca.nlvl = nl;
+  ca.k0 = (uint32_t)(c->seed & 0xFFFFFFFFu);
+  ca.k1 = (uint32_t)(c->seed >> 32);
+  ca.pop = c->pop;
+  ca.step_next = (uint32_t)(c->step + 1);
+  const int64_t ntiles = (c->R + 255) / 256;
+  hipEvent_t e0 = t_begin(c);
+  CK(launch_counts(ca, c->stream));
+  CK(launch_scan(c->tile_sum, c->tile_off, ntiles, c->scal + 2, c->stream));
+  t_end(c, PA_K_COUNTS, e0, 8 * c->R + 8 * ntiles, 0);
+  CK(hipMemcpyAsync(c->h_scal + 2, c->scal + 2, sizeof(unsigned long long),
+                    hipMemcpyDeviceToHost, c->stream));
+  rc = sync(c);
+  if (rc) return rc;
+  const int64_t total = (int64_t)c->h_scal[2];
+  if (R_new) *R_new = total;
+  if (total > c->cap) {
+    c->n_len = 0;
+    return PA_ECAPACITY;
+  }
+  if (total == 0) {
+    c->n_len = 0;
+    return PA_EEMPTY;
+  }
+  // (f) parent of every new slot, then the copies into the other buffer
+  e0 = t_begin(c);
+  CK(launch_scatter(c->n, c->tile_off, c->R, c->cap, c->parent, c->stream));
+  t_end(c, PA_K_SCATTER, e0, 4 * c->R + 4 * total, 0);
+  GatherArgs g{};
+  g.src = c->spins[c->cur];
+  g.dst = c->spins[c->cur ^ 1];
+  g.E_src = c->E[c->cur];
+  g.M_src = c->M[c->cur];
+  g.E_dst = c->E[c->cur ^ 1];
+  g.M_dst = c->M[c->cur ^ 1];
+  g.parent = c->parent;
+  g.R_new = total;
+  g.stride = c->stride;
+  g.chunks = (int32_t)(c->stride / 16);
+  int lg = 0;
+  while ((1 << lg) < g.chunks && lg < 6) ++lg;
+  g.lpr_log2 = lg;
+  e0 = t_begin(c);
+  CK(launch_gather(g, c->stream));
+  t_end(c, PA_K_GATHER, e0, 2 * total * c->stride + 20 * total, 0);
+  c->n_len = c->R;
+  c->cur ^= 1;
+  c->R = total;
+  c->beta = beta_next;
+  c->step += 1;
+  c->sweeps_at_step = 0;
+  c->lnQ_last = lnQ;
+  c->lnZ = c->lnZ + lnQ;  // Eq. Free-En, read with the logarithm
+  c->hist_valid = false;
+  return PA_OK;
+}
+
+int pa_observables(pa_ctx* c, pa_obs* o) {
+  if (!c || !o) return PA_EINVAL;
+  int rc = compute_hist(c);
+  if (rc) return rc;
+  int64_t sE = 0, sE2 = 0;
+  int lo, hi;
+  occupied(c, &lo, &hi);
+  for (int i = lo; i <= hi; ++i) {
+    const int64_t h = c->h_hist[i], e = level_energy(c, i);
+    sE += h * e;
+    sE2 += h * e * e;
+  }
+  const int64_t sAM = (int64_t)c->h_scal[0], sM2 = (int64_t)c->h_scal[1];
+  const double R = (double)c->R, N = (double)c->N;
+  const __int128 var = (__int128)c->R * sE2 - (__int128)sE * sE;
+  o->R = c->R;
+  o->beta = c->beta;
+  o->e = (double)sE / (R * N);
+  o->abs_m = (double)sAM / (R * N);
+  o->m2 = (double)sM2 / (R * N * N);
+  o->C = ((c->beta * c->beta) * (double)var) / ((R * R) * N);
+  o->sumE = sE;
+  o->sumE2 = sE2;
+  o->sumAbsM = sAM;
+  o->sumM2 = sM2;
+  o->Emin = level_energy(c, lo);
+  o->Emax = level_energy(c, hi);
+  return PA_OK;
+}
+
+int pa_free_energy(pa_ctx* c, double* lnZ, double* lnQ_last) {
+  if (!c) return PA_EINVAL;
+  if (lnZ) *lnZ = c->lnZ;
+  if (lnQ_last) *lnQ_last = c->lnQ_last;
+  return PA_OK;
+}
+
+int pa_state(pa_ctx* c, int64_t* R, double* beta, int32_t* step) {
+  if (!c) return PA_EINVAL;
+  if (R) *R = c->R;
+  if (beta) *beta = c->beta;
+  if (step) *step = c->step;
+  return PA_OK;
+}
+
+int pa_get_population(pa_ctx* c, int8_t* spins, int32_t* E, int32_t* M,
+                      int64_t cap) {
+  if (!c || cap < c->R) return PA_EINVAL;
+  int rc = sync(c);
+  if (rc) return rc;
+  if (spins) {
+    if (c->layout == PA_INT8) {
+      CK(hipMemcpy2D(spins, (size_t)c->N, c->spins[c->cur], (size_t)c->stride,
+                     (size_t)c->N, (size_t)c->R, hipMemcpyDeviceToHost));
+    } else {
+      std::vector<uint8_t> tmp((size_t)(c->R * c->stride));
+      CK(hipMemcpy(tmp.data(), c->spins[c->cur], tmp.size(),
+                   hipMemcpyDeviceToHost));
+      for (int64_t j = 0; j < c->R; ++j)
+        unpack_replica(c, tmp.data() + j * c->stride, spins + j * c->N);
+    }
+  }
+  if (E) CK(hipMemcpy(E, c->E[c->cur], (size_t)c->R * 4, hipMemcpyDeviceToHost));
+  if (M) CK(hipMemcpy(M, c->M[c->cur], (size_t)c->R * 4, hipMemcpyDeviceToHost));
+  return PA_OK;
+}
+
+int pa_get_replicas(pa_ctx* c, const int64_t* slots, int64_t k, int8_t* spins,
+                    int32_t* E, int32_t* M) {
+  if (!c || (k > 0 && !slots) || k < 0) return PA_EINVAL;
+  for (int64_t i = 0; i < k; ++i)
+    if (slots[i] < 0 || slots[i] >= c->R) return PA_EINVAL;
+  int rc = sync(c);
+  if (rc) return rc;
+  std::vector<uint8_t> tmp((size_t)c->stride);
+  for (int64_t i = 0; i < k; ++i) {
+    const int64_t j = slots[i];
+    if (spins) {
+      CK(hipMemcpy(tmp.data(), c->spins[c->cur] + j * c->stride, tmp.size(),
+                   hipMemcpyDeviceToHost));
+      unpack_replica(c, tmp.data(), spins + i * c->N);
+    }
+    if (E) CK(hipMemcpy(E + i, c->E[c->cur] + j, 4, hipMemcpyDeviceToHost));
+    if (M) CK(hipMemcpy(M + i, c->M[c->cur] + j, 4, hipMemcpyDeviceToHost));
+  }
+  return PA_OK;
+}
+
+int pa_get_counts(pa_ctx* c, uint32_t* n, int64_t cap, int64_t* len) {
+  if (!c || (c->n_len > 0 && !n) || cap < c->n_len) return PA_EINVAL;
+  int rc = sync(c);
+  if (rc) return rc;
+  if (c->n_len > 0)
+    CK(hipMemcpy(n, c->n, (size_t)c->n_len * 4, hipMemcpyDeviceToHost));
+  if (len) *len = c->n_len;
+  return PA_OK;
+}
+
+int pa_set_population(pa_ctx* c, const int8_t* spins, int64_t R) {
+  if (!c || !spins || R < 1 || R > c->cap) return PA_EINVAL;
+  for (int64_t i = 0; i < R * c->N; ++i)
+    if (spins[i] != 1 && spins[i] != -1) return PA_EINVAL;
+  int rc = sync(c);
+  if (rc) return rc;
+  std::vector<uint8_t> tmp((size_t)(R * c->stride));
+  for (int64_t j = 0; j < R; ++j)
+    pack_replica(c, spins + j * c->N, tmp.data() + j * c->stride);
+  CK(hipMemcpy(c->spins[c->cur], tmp.data(), tmp.size(), hipMemcpyHostToDevice));
+  c->R = R;
+  LatticeArgs a = lattice_args(c);
+  a.theta = 0;
+  rc = run_lattice(c, a, PA_K_SWEEP);
+  if (rc) return rc;
+  rc = sync(c);
+  if (rc) return rc;
+  c->hist_valid = false;
+  c->n_len = 0;
+  return PA_OK;
+}
+
+int pa_histogram(pa_ctx* c, uint32_t* h, int64_t cap, int32_t* nbins,
+                 int32_t* step) {
+  if (!c || (h && cap < c->nbins)) return PA_EINVAL;
+  int rc = compute_hist(c);
+  if (rc) return rc;
+  if (h) std::memcpy(h, c->h_hist, (size_t)c->nbins * 4);
+  if (nbins) *nbins = c->nbins;
+  if (step) *step = 1 << c->hshift;
+  return PA_OK;
+}
+
+int pa_overlap(pa_ctx* c, double dbeta, double* alpha) {
+  if (!c || !alpha || !std::isfinite(dbeta) || dbeta < 0.0) return PA_EINVAL;
+  int rc = compute_hist(c);
+  if (rc) return rc;
+  *alpha = overlap_of(c, dbeta);
+  return PA_OK;
+}
+
+int pa_bisect_dbeta(pa_ctx* c, double target, double beta_f, double* dbeta) {
+  if (!c || !dbeta || !(target > 0.0 && target <= 1.0) ||
+      !std::isfinite(beta_f))
+    return PA_EINVAL;
+  int rc = compute_hist(c);
+  if (rc) return rc;
+  const double span = beta_f - c->beta;
+  if (!(span > 0.0)) {
+    *dbeta = 0.0;
+    return PA_OK;
+  }
+  if (overlap_of(c, span) >= target) {
+    *dbeta = span;
+    return PA_OK;
+  }
+  double lo = 0.0, hi = span;
+  for (int it = 0; it < 64; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (overlap_of(c, mid) >= target) lo = mid;
+    else hi = mid;
+  }
+  *dbeta = lo;
+  return PA_OK;
+}
+
+int pa_set_timing(pa_ctx* c, int32_t enable) {
+  if (!c) return PA_EINVAL;
+  int rc = sync(c);
+  if (rc) return rc;
+  c->timing = enable != 0;
+  if (c->timing) c->acc = pa_timing{};
+  return PA_OK;
+}
+
+int pa_get_timing(pa_ctx* c, pa_timing* out) {
+  if (!c || !out) return PA_EINVAL;
+  int rc = sync(c);
+  if (rc) return rc;
+  *out = c->acc;
+  return PA_OK;
+}
+
+}  // extern "C"

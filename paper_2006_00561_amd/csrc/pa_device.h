@@ -1,0 +1,87 @@
+// Device helpers for the gfx950 population-annealing kernels: the Philox
+// counter generator and bit-sliced operations on lattice rows.
+//
+// A lattice row of L sites is held as W32 = ceil(L/32) 32-bit words, site x
+// in bit x%32 of word x/32, bit set = spin +1; bits at x >= L are zero.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pa {
+
+constexpr uint32_t kDomainInit = 1u;
+constexpr uint32_t kDomainMcmc = 2u;
+constexpr uint32_t kDomainResample = 3u;
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 32x32->64 multiplies by the round constants, a swap of the halves and a
+// xor with the key, the key stepping by the Weyl constants between rounds.
+// The key arrives in kernel arguments, so its schedule stays in scalar
+// registers and each round costs two v_mad_u64_u32 and two v_xor3_b32.
+__device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int i = 0; i < 10; ++i) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c.x;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c.z;
+    c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1,
+                   (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
+// Mask of the valid bits of word `w` of a row of L sites.
+__device__ __forceinline__ uint32_t valid_mask(int L, int w) {
+  const int rem = L - 32 * w;
+  return rem >= 32 ? 0xFFFFFFFFu : (rem <= 0 ? 0u : ((1u << rem) - 1u));
+}
+
+// out[x] = in[x-1 mod L]  (the left neighbour of every site)
+template <int W>
+__device__ __forceinline__ void row_from_left(const uint32_t* in, uint32_t* out,
+                                              int L) {
+  const uint32_t top = (in[W - 1] >> ((L - 1) & 31)) & 1u;
+#pragma unroll
+  for (int w = W - 1; w >= 1; --w) out[w] = (in[w] << 1) | (in[w - 1] >> 31);
+  out[0] = (in[0] << 1) | top;
+  out[W - 1] &= valid_mask(L, W - 1);
+}
+
+// out[x] = in[x+1 mod L]  (the right neighbour of every site)
+template <int W>
+__device__ __forceinline__ void row_from_right(const uint32_t* in,
+                                               uint32_t* out, int L) {
+#pragma unroll
+  for (int w = 0; w < W - 1; ++w) out[w] = (in[w] >> 1) | (in[w + 1] << 31);
+  out[W - 1] = (in[W - 1] >> 1) | ((in[0] & 1u) << ((L - 1) & 31));
+}
+
+// Spread the 16 low bits of v to the even bit positions of a word.
+__device__ __forceinline__ uint32_t spread_even(uint32_t v) {
+  v &= 0xFFFFu;
+  v = (v | (v << 8)) & 0x00FF00FFu;
+  v = (v | (v << 4)) & 0x0F0F0F0Fu;
+  v = (v | (v << 2)) & 0x33333333u;
+  v = (v | (v << 1)) & 0x55555555u;
+  return v;
+}
+
+// 4 int8 spins (+1 = 0x01, -1 = 0xFF) -> 4 bits, bit i = byte i is +1.
+__device__ __forceinline__ uint32_t pack4(uint32_t w) {
+  const uint32_t m = (~w >> 7) & 0x01010101u;
+  return ((m * 0x01020408u) >> 24) & 0xFu;
+}
+
+// 4 bits -> 4 int8 spins.
+__device__ __forceinline__ uint32_t unpack4(uint32_t nib) {
+  const uint32_t b = (nib * 0x00204081u) & 0x01010101u;
+  return 0xFFFFFFFFu - b * 0xFEu;
+}
+
+// Lane shuffle over the whole wave (ds_bpermute).
+__device__ __forceinline__ uint32_t shfl(uint32_t v, int src_lane) {
+  return (uint32_t)__builtin_amdgcn_ds_bpermute(src_lane << 2, (int)v);
+}
+
+}  // namespace pa

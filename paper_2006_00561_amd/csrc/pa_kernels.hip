@@ -1,0 +1,535 @@
+// HIP kernels (gfx950) of the population-annealing hot path.
+//
+//  k_lattice   init at beta_0 = 0 / theta checkerboard Metropolis sweeps /
+//              energy and magnetisation of every replica (paper Sec. 2,
+//              first and equilibration steps; Eq. Ham).  One replica's
+//              lattice lives in the VGPRs of L/RPL lanes of one wave, bit
+//              packed (lane = RPL consecutive rows, 32 sites per register);
+//              vertical neighbours come from the adjacent lanes through
+//              ds_bpermute, horizontal ones from in-register shifts.  The
+//              lattice is read from HBM once and written once per call,
+//              whatever theta is.
+//  k_hist      exact energy histogram + |M| and M^2 sums (Eqs. part-Q/tau
+//              need only the energy distribution).
+//  k_counts    copy counts floor(rho) + Bernoulli(frac rho) per replica from
+//              the host's per-level tables, plus one partial sum per tile.
+//  k_scan      exclusive scan of the tile sums (single workgroup).
+//  k_scatter   per-tile scan of the counts -> parent index of every new slot.
+//  k_gather    copy of every parent's lattice, E and M into its new slots of
+//              the second buffer (16-byte chunks, one wave per row group).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pa_device.h"
+#include "pa_internal.h"
+
+namespace pa {
+
+// ------------------------------------------------------------- lattice pass
+
+template <int W, int RPL, bool INT8>
+__device__ __forceinline__ void load_row(const uint8_t* rp, int L, int y,
+                                         uint32_t* row) {
+#pragma unroll
+  for (int w = 0; w < W; ++w) row[w] = 0u;
+  if (!INT8) {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(rp) + (size_t)y * W;
+#pragma unroll
+    for (int w = 0; w < W; ++w) row[w] = src[w];
+    return;
+  }
+  const uint8_t* src = rp + (size_t)y * L;
+  if ((L & 15) == 0) {
+#pragma unroll
+    for (int w = 0; w < W; ++w)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int xo = 32 * w + 16 * q;
+        if (xo < L) {
+          const uint4 v = *reinterpret_cast<const uint4*>(src + xo);
+          const uint32_t b = pack4(v.x) | (pack4(v.y) << 4) |
+                             (pack4(v.z) << 8) | (pack4(v.w) << 12);
+          row[w] |= b << (16 * q);
+        }
+      }
+  } else if ((L & 3) == 0) {
+#pragma unroll
+    for (int w = 0; w < W; ++w)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int xo = 32 * w + 4 * q;
+        if (xo < L)
+          row[w] |= pack4(*reinterpret_cast<const uint32_t*>(src + xo))
+                    << (4 * q);
+      }
+  } else {
+#pragma unroll
+    for (int w = 0; w < W; ++w)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int xo = 32 * w + 2 * q;
+        if (xo < L) {
+          const uint32_t v = *reinterpret_cast<const uint16_t*>(src + xo);
+          row[w] |= (pack4(v | 0x01010000u) & 3u) << (2 * q);
+        }
+      }
+  }
+}
+
+template <int W, int RPL, bool INT8>
+__device__ __forceinline__ void store_row(uint8_t* rp, int L, int y,
+                                          const uint32_t* row) {
+  if (!INT8) {
+    uint32_t* dst = reinterpret_cast<uint32_t*>(rp) + (size_t)y * W;
+#pragma unroll
+    for (int w = 0; w < W; ++w) dst[w] = row[w];
+    return;
+  }
+  uint8_t* dst = rp + (size_t)y * L;
+  if ((L & 15) == 0) {
+#pragma unroll
+    for (int w = 0; w < W; ++w)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int xo = 32 * w + 16 * q;
+        if (xo < L) {
+          const uint32_t b = row[w] >> (16 * q);
+          uint4 v;
+          v.x = unpack4(b & 0xFu);
+          v.y = unpack4((b >> 4) & 0xFu);
+          v.z = unpack4((b >> 8) & 0xFu);
+          v.w = unpack4((b >> 12) & 0xFu);
+          *reinterpret_cast<uint4*>(dst + xo) = v;
+        }
+      }
+  } else if ((L & 3) == 0) {
+#pragma unroll
+    for (int w = 0; w < W; ++w)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int xo = 32 * w + 4 * q;
+        if (xo < L)
+          *reinterpret_cast<uint32_t*>(dst + xo) =
+              unpack4((row[w] >> (4 * q)) & 0xFu);
+      }
+  } else {
+#pragma unroll
+    for (int w = 0; w < W; ++w)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int xo = 32 * w + 2 * q;
+        if (xo < L)
+          *reinterpret_cast<uint16_t*>(dst + xo) =
+              (uint16_t)(unpack4((row[w] >> (2 * q)) & 3u) & 0xFFFFu);
+      }
+  }
+}
+
+template <int W, int RPL, bool INT8, bool GLASS>
+__global__ __launch_bounds__(256) void k_lattice(const LatticeArgs a) {
+  __shared__ int2 red[256];
+  const int lane = threadIdx.x & 63;
+  const int64_t wave =
+      ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int L = a.L;
+  const int g = lane / a.lpr;
+  const int lr = lane - g * a.lpr;
+  const int64_t rep = wave * a.rpw + g;
+  const bool active = (g < a.rpw) && (rep < a.R);
+  const int base = g * a.lpr;
+  const int up_lane = active ? base + (lr == 0 ? a.lpr - 1 : lr - 1) : lane;
+  const int dn_lane = active ? base + (lr == a.lpr - 1 ? 0 : lr + 1) : lane;
+  const uint32_t slot = (uint32_t)(active ? rep : 0);
+  uint8_t* rp = a.spins + (size_t)slot * (size_t)a.stride;
+
+  uint32_t s[RPL][W];
+  // couplings: jr = bond to the right, jl = bond to the left (jr of x-1),
+  // jd = bond below, ju = bond above (jd of row y-1); bit set = J < 0
+  uint32_t jr[RPL][W], jl[RPL][W], jd[RPL][W], ju[RPL][W];
+
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    const int y = lr * RPL + r;
+    if (GLASS) {
+      const int yu = (y == 0) ? L - 1 : y - 1;
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        jr[r][w] = a.jbits[(size_t)y * W + w];
+        jd[r][w] = a.jbits[(size_t)(L + y) * W + w];
+        ju[r][w] = a.jbits[(size_t)(L + yu) * W + w];
+      }
+      row_from_left<W>(jr[r], jl[r], L);
+    } else {
+#pragma unroll
+      for (int w = 0; w < W; ++w) jr[r][w] = jl[r][w] = jd[r][w] = ju[r][w] = 0u;
+    }
+    if (a.init) {
+      // INIT stream: site x of row y <- word x%4 of group y*ceil(L/4) + x/4
+      const int G4 = (L + 3) >> 2;
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        uint32_t v = 0u;
+#pragma unroll
+        for (int gq = 0; gq < 8; ++gq) {
+          if (32 * w + 4 * gq < L) {
+            const uint4 b = philox10(
+                make_uint4((kDomainInit << 28) | (uint32_t)(y * G4 + 8 * w + gq),
+                           0u, slot, a.pop),
+                a.k0, a.k1);
+            const uint32_t bits = (b.x >> 31) | ((b.y >> 31) << 1) |
+                                  ((b.z >> 31) << 2) | ((b.w >> 31) << 3);
+            v |= bits << (4 * gq);
+          }
+        }
+        s[r][w] = v & valid_mask(L, w);
+      }
+    } else if (active) {
+      load_row<W, RPL, INT8>(rp, L, y, s[r]);
+    } else {
+#pragma unroll
+      for (int w = 0; w < W; ++w) s[r][w] = 0u;
+    }
+  }
+
+  const int G8 = (L + 7) >> 3;
+  const int half = L >> 1;
+  for (int t = 0; t < a.theta; ++t) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      uint32_t up0[W], dnl[W];
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        up0[w] = shfl(s[RPL - 1][w], up_lane);
+        dnl[w] = shfl(s[0][w], dn_lane);
+      }
+      const uint32_t ctr1 = (a.step << 16) | (uint32_t)(2 * (a.t0 + t) + c);
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) {
+        const int y = lr * RPL + r;
+        const uint32_t p = (uint32_t)((c + y) & 1);
+        const uint32_t* up = (r == 0) ? up0 : s[r > 0 ? r - 1 : 0];
+        const uint32_t* dn = (r == RPL - 1) ? dnl : s[r < RPL - 1 ? r + 1 : 0];
+        uint32_t lf[W], rt[W];
+        row_from_left<W>(s[r], lf, L);
+        row_from_right<W>(s[r], rt, L);
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          const uint32_t sv = s[r][w];
+          const uint32_t d1 = sv ^ lf[w] ^ jl[r][w];
+          const uint32_t d2 = sv ^ rt[w] ^ jr[r][w];
+          const uint32_t d3 = sv ^ up[w] ^ ju[r][w];
+          const uint32_t d4 = sv ^ dn[w] ^ jd[r][w];
+          const uint32_t x1 = d1 ^ d2, a1 = d1 & d2;
+          const uint32_t x2 = d3 ^ d4, a2 = d3 & d4;
+          const uint32_t eq0 = ~(d1 | d2 | d3 | d4);  // dE = +8
+          const uint32_t eq1 = (x1 ^ x2) & ~(a1 | a2); // dE = +4
+          uint32_t ge2 = ~(eq0 | eq1);                 // dE <= 0
+          if (a.all8) ge2 |= eq0;
+          if (a.all4) ge2 |= eq1;
+          // 16 colour sites of this word: k = 16w .. 16w+15, x = 2k + p
+          uint32_t c4 = 0u, c8 = 0u;
+#pragma unroll
+          for (int gq = 0; gq < 4; ++gq) {
+            if (16 * w + 4 * gq < half) {
+              const uint4 b = philox10(
+                  make_uint4((kDomainMcmc << 28) |
+                                 (uint32_t)(y * G8 + 4 * w + gq),
+                             ctr1, slot, a.pop),
+                  a.k0, a.k1);
+              const uint32_t m4 = (uint32_t)(b.x < a.T4) |
+                                  ((uint32_t)(b.y < a.T4) << 1) |
+                                  ((uint32_t)(b.z < a.T4) << 2) |
+                                  ((uint32_t)(b.w < a.T4) << 3);
+              const uint32_t m8 = (uint32_t)(b.x < a.T8) |
+                                  ((uint32_t)(b.y < a.T8) << 1) |
+                                  ((uint32_t)(b.z < a.T8) << 2) |
+                                  ((uint32_t)(b.w < a.T8) << 3);
+              c4 |= m4 << (4 * gq);
+              c8 |= m8 << (4 * gq);
+            }
+          }
+          const uint32_t M4 = spread_even(c4) << p;
+          const uint32_t M8 = spread_even(c8) << p;
+          const uint32_t col = (p ? 0xAAAAAAAAu : 0x55555555u) & valid_mask(L, w);
+          const uint32_t flip = col & (ge2 | (eq1 & M4) | (eq0 & M8));
+          s[r][w] = sv ^ flip;
+        }
+      }
+    }
+  }
+
+  // energy and magnetisation of the final state (Eq. Ham)
+  uint32_t dnl[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) dnl[w] = shfl(s[0][w], dn_lane);
+  int unsat = 0, ups = 0;
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    const uint32_t* dn = (r == RPL - 1) ? dnl : s[r < RPL - 1 ? r + 1 : 0];
+    uint32_t rt[W];
+    row_from_right<W>(s[r], rt, L);
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const uint32_t vm = valid_mask(L, w);
+      unsat += __popc((s[r][w] ^ rt[w] ^ jr[r][w]) & vm);
+      unsat += __popc((s[r][w] ^ dn[w] ^ jd[r][w]) & vm);
+      ups += __popc(s[r][w]);
+    }
+  }
+  red[threadIdx.x] = make_int2(unsat, ups);
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) store_row<W, RPL, INT8>(rp, L, lr * RPL + r, s[r]);
+    if (lr == 0) {
+      int us = 0, up = 0;
+      const int w0 = threadIdx.x & ~63;
+      for (int i = 0; i < a.lpr; ++i) {
+        const int2 v = red[w0 + base + i];
+        us += v.x;
+        up += v.y;
+      }
+      const int N = L * L;
+      a.E[rep] = 2 * us - 2 * N;
+      a.M[rep] = 2 * up - N;
+    }
+  }
+}
+
+// -------------------------------------------------------------- histogram
+
+__global__ __launch_bounds__(256) void k_hist(HistArgs a) {
+  extern __shared__ uint32_t sh[];
+  if (a.use_lds) {
+    for (int i = threadIdx.x; i < a.nbins; i += blockDim.x) sh[i] = 0u;
+    __syncthreads();
+  }
+  unsigned long long sam = 0ull, sm2 = 0ull;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < a.R;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const int idx = (a.E[j] + a.twoN) >> a.shift;
+    if (idx < 0 || idx >= a.nbins) {  // corrupt energy: report, never index
+      atomicAdd(&a.moments[3], 1ull);
+      continue;
+    }
+    if (a.use_lds)
+      atomicAdd(&sh[idx], 1u);
+    else
+      atomicAdd(&a.hist[idx], 1u);
+    const int m = a.M[j];
+    sam += (unsigned long long)(m < 0 ? -m : m);
+    sm2 += (unsigned long long)((long long)m * m);
+  }
+  if (a.use_lds) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < a.nbins; i += blockDim.x)
+      if (sh[i]) atomicAdd(&a.hist[i], sh[i]);
+  }
+  // wave reduction of the |M| and M^2 sums
+  for (int off = 32; off > 0; off >>= 1) {
+    sam += __shfl_down(sam, off, 64);
+    sm2 += __shfl_down(sm2, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(&a.moments[0], sam);
+    atomicAdd(&a.moments[1], sm2);
+  }
+}
+
+// ------------------------------------------------------------ copy counts
+
+// Workgroup-wide exclusive scan of one value per thread (256 threads);
+// returns the exclusive prefix and writes the total to *total.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* lds,
+                                                    uint32_t* total) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint32_t incl = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t o = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += o;
+  }
+  if (lane == 63) lds[wid] = incl;
+  __syncthreads();
+  uint32_t wbase = 0u, tot = 0u;
+  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+    const uint32_t x = lds[i];
+    if (i < wid) wbase += x;
+    tot += x;
+  }
+  *total = tot;
+  return wbase + incl - v;
+}
+
+__global__ __launch_bounds__(256) void k_counts(CountsArgs a) {
+  __shared__ uint32_t lds[8];
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t nj = 0u;
+  if (j < a.R) {
+    const int l = ((a.E[j] + a.twoN) >> a.shift) - a.lvl0;
+    const uint4 b = philox10(make_uint4(kDomainResample << 28,
+                                        a.step_next << 16, (uint32_t)j, a.pop),
+                             a.k0, a.k1);
+    if (l >= 0 && l < a.nlvl) nj = a.f[l] + (b.x < a.T[l] ? 1u : 0u);
+    a.n[j] = nj;
+  }
+  uint32_t total;
+  (void)block_excl_scan(nj, lds, &total);
+  if (threadIdx.x == 0) a.tile_sum[blockIdx.x] = total;
+}
+
+// Single workgroup of 1024 threads: exclusive scan of ntiles tile sums.
+__global__ __launch_bounds__(1024) void k_scan(const uint32_t* tile_sum,
+                                               uint32_t* tile_off,
+                                               int64_t ntiles,
+                                               unsigned long long* total) {
+  __shared__ unsigned long long part[1024];
+  const int tid = threadIdx.x;
+  const int64_t per = (ntiles + 1023) / 1024;
+  const int64_t b = tid * per;
+  const int64_t e = (b + per < ntiles) ? b + per : ntiles;
+  unsigned long long s = 0ull;
+  for (int64_t i = b; i < e; ++i) s += tile_sum[i];
+  part[tid] = s;
+  __syncthreads();
+  // Hillis-Steele inclusive scan over the 1024 partial sums
+  for (int off = 1; off < 1024; off <<= 1) {
+    unsigned long long v = (tid >= off) ? part[tid - off] : 0ull;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  unsigned long long run = part[tid] - s;
+  for (int64_t i = b; i < e; ++i) {
+    tile_off[i] = (uint32_t)run;
+    run += tile_sum[i];
+  }
+  if (tid == 1023) *total = part[1023];
+}
+
+__global__ __launch_bounds__(256) void k_scatter(const uint32_t* n,
+                                                 const uint32_t* tile_off,
+                                                 int64_t R, int64_t cap,
+                                                 uint32_t* parent) {
+  __shared__ uint32_t lds[8];
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t nj = (j < R) ? n[j] : 0u;
+  uint32_t total;
+  const uint32_t ex = block_excl_scan(nj, lds, &total);
+  const int64_t o = (int64_t)tile_off[blockIdx.x] + ex;
+  for (uint32_t t = 0; t < nj; ++t)
+    if (o + t < cap) parent[o + t] = (uint32_t)j;
+}
+
+// ---------------------------------------------------------------- gather
+
+__global__ __launch_bounds__(256) void k_gather(GatherArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave =
+      ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int sub = lane >> a.lpr_log2;                 // row within the wave
+  const int c0 = lane & ((1 << a.lpr_log2) - 1);       // first chunk
+  const int64_t k = wave * (64 >> a.lpr_log2) + sub;  // new slot
+  if (k >= a.R_new) return;
+  const uint32_t p = a.parent[k];
+  const uint4* src = reinterpret_cast<const uint4*>(a.src + (size_t)p * a.stride);
+  uint4* dst = reinterpret_cast<uint4*>(a.dst + (size_t)k * a.stride);
+  for (int c = c0; c < a.chunks; c += (1 << a.lpr_log2)) dst[c] = src[c];
+  if (c0 == 0) {
+    a.E_dst[k] = a.E_src[p];
+    a.M_dst[k] = a.M_src[p];
+  }
+}
+
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// --------------------------------------------------------------- launchers
+
+template <int W, int RPL>
+static hipError_t launch_lattice_w(const LatticeArgs& a, bool int8, bool glass,
+                                   dim3 grid, hipStream_t st) {
+  if (int8) {
+    if (glass) hipLaunchKernelGGL((k_lattice<W, RPL, true, true>), grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_lattice<W, RPL, true, false>), grid, dim3(256), 0, st, a);
+  } else {
+    if (glass) hipLaunchKernelGGL((k_lattice<W, RPL, false, true>), grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_lattice<W, RPL, false, false>), grid, dim3(256), 0, st, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_lattice(const LatticeArgs& a, int W, int RPL, bool int8,
+                          bool glass, hipStream_t st) {
+  const int64_t waves = (a.R + a.rpw - 1) / a.rpw;
+  const int64_t blocks = (waves + 3) / 4;
+  if (blocks <= 0) return hipSuccess;
+  if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)blocks);
+  switch (W * 8 + RPL) {
+    case 1 * 8 + 1: return launch_lattice_w<1, 1>(a, int8, glass, grid, st);
+    case 1 * 8 + 2: return launch_lattice_w<1, 2>(a, int8, glass, grid, st);
+    case 1 * 8 + 4: return launch_lattice_w<1, 4>(a, int8, glass, grid, st);
+    case 2 * 8 + 1: return launch_lattice_w<2, 1>(a, int8, glass, grid, st);
+    case 2 * 8 + 2: return launch_lattice_w<2, 2>(a, int8, glass, grid, st);
+    case 2 * 8 + 4: return launch_lattice_w<2, 4>(a, int8, glass, grid, st);
+    case 3 * 8 + 2: return launch_lattice_w<3, 2>(a, int8, glass, grid, st);
+    case 3 * 8 + 4: return launch_lattice_w<3, 4>(a, int8, glass, grid, st);
+    case 4 * 8 + 2: return launch_lattice_w<4, 2>(a, int8, glass, grid, st);
+    case 4 * 8 + 4: return launch_lattice_w<4, 4>(a, int8, glass, grid, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_hist(const HistArgs& a, hipStream_t st) {
+  int64_t blocks = (a.R + 256 * 8 - 1) / (256 * 8);
+  if (blocks < 1) blocks = 1;
+  if (blocks > 2048) blocks = 2048;
+  const size_t shm = a.use_lds ? (size_t)a.nbins * sizeof(uint32_t) : 0;
+  hipLaunchKernelGGL(k_hist, dim3((unsigned)blocks), dim3(256), shm, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_counts(const CountsArgs& a, hipStream_t st) {
+  const int64_t blocks = (a.R + 255) / 256;
+  hipLaunchKernelGGL(k_counts, dim3((unsigned)blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan(const uint32_t* tile_sum, uint32_t* tile_off,
+                       int64_t ntiles, unsigned long long* total,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, tile_sum, tile_off,
+                     ntiles, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(const uint32_t* n, const uint32_t* tile_off,
+                          int64_t R, int64_t cap, uint32_t* parent,
+                          hipStream_t st) {
+  const int64_t blocks = (R + 255) / 256;
+  hipLaunchKernelGGL(k_scatter, dim3((unsigned)blocks), dim3(256), 0, st, n,
+                     tile_off, R, cap, parent);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const GatherArgs& a, hipStream_t st) {
+  const int64_t rows_per_wave = 64 >> a.lpr_log2;
+  const int64_t waves = (a.R_new + rows_per_wave - 1) / rows_per_wave;
+  const int64_t blocks = (waves + 3) / 4;
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather, dim3((unsigned)blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st) {
+  int64_t blocks = (n + 255) / 256;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace pa

@@ -1,0 +1,274 @@
+"""Parity of the HIP path (through the C ABI) with the oracle.
+
+Spins, energies, magnetisations, copy counts and population sizes must be
+bit-exact; ln Z, ln Q and observables within 1e-12 relative (both sides
+compute them in the same double-precision operation order, so they are in
+fact expected to be identical).  At the full benchmark sizes the oracle
+checks every copy count and ln Q exactly and a sample of replicas through
+their sweeps."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import pa_workloads as W
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def pa():
+    if not os.path.exists("/dev/kfd"):
+        pytest.skip("no GPU")
+    from paper_2006_00561_amd import binding
+    binding.lib()
+    return binding
+
+
+def _close(a, b):
+    return abs(a - b) <= REL * max(1.0, abs(a), abs(b))
+
+
+def _cmp_obs(og, oo):
+    for k in ("R", "sumE", "sumE2", "sumAbsM", "sumM2", "Emin", "Emax"):
+        assert og[k] == oo[k], k
+    for k in ("beta", "e", "abs_m", "m2", "C"):
+        assert _close(og[k], oo[k]), (k, og[k], oo[k])
+
+
+def _cmp_state(g, o, tag):
+    sg, Eg, Mg = g.population()
+    so, Eo, Mo = o.population()
+    assert len(Eg) == len(Eo), tag
+    assert np.array_equal(Eg, Eo), tag
+    assert np.array_equal(Mg, Mo), tag
+    assert np.array_equal(sg, so), tag
+    zg, qg = g.free_energy()
+    zo, qo = o.free_energy()
+    assert _close(zg, zo) and _close(qg, qo), (tag, zg, zo, qg, qo)
+
+
+def _parity_run(pa, L, R, steps, theta, beta_f, seed=1, pop=0, J=None,
+                layout=0, rpl=0, check_every=1):
+    print("parity L=%d R=%d steps=%d theta=%d layout=%d rpl=%d J=%s"
+          % (L, R, steps, theta, layout, rpl, J is not None), flush=True)
+    g = pa.Population(L, R, seed=seed, population_id=pop, J=J, layout=layout,
+                      rows_per_lane=rpl)
+    o = oracle.OraclePA(L, R, seed=seed, pop=pop, J=J)
+    _cmp_state(g, o, "init")
+    for i, b in enumerate(W.linear_schedule(beta_f, steps), start=1):
+        R_old = g.R
+        rg = g.resample(b)
+        ro = o.resample(b)
+        assert rg == ro, (i, rg, ro)
+        assert np.array_equal(g.counts(), o.counts(R_old)), i
+        g.sweep(b, theta)
+        o.sweep(theta)
+        if i % check_every == 0 or i == steps:
+            _cmp_state(g, o, "step %d" % i)
+            _cmp_obs(g.observables(), o.observables())
+    g.close()
+    o.close()
+
+
+def test_C1_full_trajectory(pa):
+    """L=16, R=1000, beta 0 -> 1 in 100 steps, theta=5, seed 1: every step."""
+    c = W.CONFIGS["C1"]
+    _parity_run(pa, c["L"], c["R"], c["K"], c["theta"], c["beta_f"],
+                seed=c["seed"])
+
+
+SHAPES = [
+    # L, R, layout, rows per lane, glass
+    (4, 37, 0, 0, False), (4, 37, 1, 4, True), (6, 300, 0, 0, False),
+    (6, 300, 1, 2, True), (8, 257, 0, 0, True), (10, 129, 1, 0, False),
+    (12, 513, 0, 0, True), (12, 100, 0, 4, False), (16, 700, 1, 2, False),
+    (24, 333, 0, 0, True), (24, 200, 1, 4, True), (32, 300, 0, 1, False),
+    (32, 300, 1, 4, True), (40, 65, 0, 2, False), (48, 90, 1, 0, True),
+    (64, 129, 0, 0, False), (64, 70, 1, 2, True), (64, 70, 0, 4, False),
+    (66, 20, 0, 0, False), (96, 30, 1, 0, True), (100, 12, 0, 4, False),
+    (128, 24, 1, 0, False), (128, 20, 0, 4, True),
+]
+
+
+@pytest.mark.parametrize("L,R,layout,rpl,glass", SHAPES)
+def test_shapes_and_layouts(pa, L, R, layout, rpl, glass):
+    J = W.pmj_couplings(L, 100 + L) if glass else None
+    _parity_run(pa, L, R, 5, 2, 0.8, seed=3 + L, pop=L, J=J, layout=layout,
+                rpl=rpl)
+
+
+def test_launch_shape_and_layout_do_not_change_results(pa):
+    for L in (32, 64):
+        runs = []
+        for layout in (0, 1):
+            for rpl in (1, 2, 4):
+                g = pa.Population(L, 500, seed=9, layout=layout,
+                                  rows_per_lane=rpl)
+                for b in W.linear_schedule(0.7, 6):
+                    g.resample(b)
+                    g.sweep(b, 3)
+                runs.append(g.population())
+                g.close()
+        for r in runs[1:]:
+            for a, b in zip(runs[0], r):
+                assert np.array_equal(a, b)
+
+
+def test_zero_step_is_identity(pa):
+    g = pa.Population(16, 400, seed=5)
+    s0, E0, M0 = g.population()
+    z0, _ = g.free_energy()
+    assert g.resample(0.0) == 400
+    assert np.all(g.counts() == 1)
+    s1, E1, M1 = g.population()
+    assert np.array_equal(s0, s1) and np.array_equal(E0, E1)
+    z1, q1 = g.free_energy()
+    assert q1 == 0.0 and z1 == z0
+
+
+def test_capacity_overflow_leaves_population_untouched(pa):
+    for seed in range(1, 40):
+        g = pa.Population(6, 1000, seed=seed, capacity=1000)
+        s0, E0, M0 = g.population()
+        rc, Rn = g.resample_rc(0.3)
+        if rc == pa.PA_OK:
+            continue
+        assert rc == pa.PA_ECAPACITY and Rn > 1000
+        assert g.state() == (1000, 0.0, 0)
+        s, E, M = g.population()
+        assert np.array_equal(s, s0) and np.array_equal(E, E0)
+        # the context still works afterwards
+        o = oracle.OraclePA(6, 1000, seed=seed, capacity=1000)
+        assert o.resample_rc(0.3) == (oracle.ECAPACITY, Rn)
+        return
+    raise AssertionError("no seed overflowed")
+
+
+def test_state_errors(pa):
+    g = pa.Population(8, 50, seed=1)
+    with pytest.raises(pa.PAError) as e:
+        g.sweep(0.5, 1)            # not the current beta
+    assert e.value.code == pa.PA_ESTATE
+    g.resample(0.2)
+    with pytest.raises(pa.PAError) as e:
+        g.resample(0.1)            # heating is not supported
+    assert e.value.code == pa.PA_EINVAL
+    with pytest.raises(pa.PAError):
+        g.set_population(np.zeros((3, 8, 8), np.int8))
+
+
+def test_set_population_and_global_flip(pa):
+    L, R = 16, 300
+    g = pa.Population(L, R, seed=5)
+    o = oracle.OraclePA(L, R, seed=5)
+    s, _, _ = o.population()
+    g.set_population(-s)
+    o.set_population(-s)
+    _cmp_state(g, o, "flipped")
+    for b in W.linear_schedule(0.8, 5):
+        assert g.resample(b) == o.resample(b)
+        g.sweep(b, 3)
+        o.sweep(3)
+    _cmp_state(g, o, "after")
+
+
+def test_gauge_transformed_glass_matches_ferromagnet(pa):
+    L, R = 24, 400
+    J, eps = W.gauge_couplings(L, 31)
+    f = pa.Population(L, R, seed=6)
+    g = pa.Population(L, R, seed=6, J=J)
+    s, _, _ = f.population()
+    g.set_population(s * eps[None])
+    for b in W.linear_schedule(1.0, 8):
+        assert f.resample(b) == g.resample(b)
+        f.sweep(b, 2)
+        g.sweep(b, 2)
+    sf, Ef, _ = f.population()
+    sg, Eg, _ = g.population()
+    assert np.array_equal(sf * eps[None], sg) and np.array_equal(Ef, Eg)
+    assert f.free_energy() == g.free_energy()
+
+
+def test_overlap_and_bisection_match_oracle(pa):
+    L, R = 16, 2000
+    g = pa.Population(L, R, seed=8)
+    o = oracle.OraclePA(L, R, seed=8)
+    for b in W.linear_schedule(0.4, 4):
+        g.resample(b)
+        o.resample(b)
+        g.sweep(b, 2)
+        o.sweep(2)
+    for d in (0.0, 0.01, 0.1, 0.5):
+        assert g.overlap(d) == o.overlap(d)
+    assert g.bisect_dbeta(0.85, 3.0) == o.bisect_dbeta(0.85, 3.0)
+    hg, st = g.histogram()
+    ho = o.histogram()
+    assert np.array_equal(hg, ho[::st])
+
+
+def test_timing_counters(pa):
+    g = pa.Population(32, 1000, seed=2)
+    g.set_timing(True)
+    for b in W.linear_schedule(0.5, 3):
+        g.resample(b)
+        g.sweep(b, 4)
+    t = g.timing()
+    assert t["sweep"]["launches"] == 3 and t["sweep"]["ms"] > 0
+    assert t["gather"]["launches"] == 3 and t["hist"]["launches"] == 3
+    assert t["attempts"] > 3 * 4 * 32 * 32 * 900
+
+
+@pytest.mark.parametrize("name,steps,sample", [("C2", 3, 48), ("C3a", 2, 24),
+                                               ("C3b", 2, 16)])
+def test_full_size_sampled(pa, name, steps, sample):
+    """At the benchmark sizes: every copy count, R_new and ln Q exactly from
+    the oracle's count step on the device energies; a sample of replicas
+    through theta sweeps with the oracle's single-replica sweep; observables
+    from the full E and M arrays."""
+    c = W.CONFIGS[name]
+    L, R, theta = c["L"], c["R"], c["theta"]
+    layout = 1 if c["layout"] == "bits" else 0
+    print("full-size parity %s L=%d R=%d layout=%d" % (name, L, R, layout),
+          flush=True)
+    g = pa.Population(L, R, seed=c["seed"], layout=layout)
+    rng = np.random.default_rng(0)
+    sched = W.linear_schedule(c["beta_f"], c["K"])
+    # initial state: sampled replicas against the oracle's init
+    o = oracle.OraclePA(L, 8, seed=c["seed"])
+    so, Eo, Mo = o.population()
+    sg, Eg, Mg = g.replicas(np.arange(8))
+    assert np.array_equal(sg, so) and np.array_equal(Eg, Eo)
+    zlast = g.free_energy()[0]
+    for i in range(1, steps + 1):
+        b = sched[i - 1]
+        E, M = g.energies()
+        n_o, Rn_o, lnQ_o = oracle.counts(L * L, E, R, b - g.beta, c["seed"],
+                                         0, i)
+        Rn = g.resample(b)
+        assert Rn == Rn_o
+        assert np.array_equal(g.counts(), n_o)
+        z, q = g.free_energy()
+        assert _close(q, lnQ_o) and _close(z, zlast + lnQ_o)
+        zlast = z
+        parent = np.repeat(np.arange(len(E)), n_o)
+        slots = np.sort(rng.choice(Rn, size=sample, replace=False))
+        s_pre, E_pre, M_pre = g.replicas(slots)
+        assert np.array_equal(E_pre, E[parent[slots]])
+        g.sweep(b, theta)
+        s_post, E_post, M_post = g.replicas(slots)
+        for k, j in enumerate(slots):
+            so, eo, mo = oracle.sweep_replica(s_pre[k], E_pre[k], M_pre[k],
+                                              b, c["seed"], 0, i, 0, theta,
+                                              int(j))
+            assert np.array_equal(s_post[k], so), (name, i, j)
+            assert (E_post[k], M_post[k]) == (eo, mo)
+        E2, M2 = g.energies()
+        ob = g.observables()
+        assert ob["sumE"] == int(E2.astype(np.int64).sum())
+        assert ob["sumAbsM"] == int(np.abs(M2.astype(np.int64)).sum())
+        assert ob["sumM2"] == int((M2.astype(np.int64) ** 2).sum())
+    g.close()
