@@ -12,7 +12,7 @@ replicas, int8 spins, beta 0 -> 1 in 200 linear steps, theta = 10.
 
 Prints one JSON line (rank 0):
   value           spin-flip attempts per ns over the whole timed anneals
-  roofline        the sweep kernel (dominant) against the VALU issue peak,
+  roofline        the sweep kernel (dominant) against the integer VALU peak,
                   from HIP events on the library's stream
   resample        achieved HBM bandwidth of histogram+counts+scatter+gather
   cpu_baseline    the single-threaded oracle timed on a bounded sample of the
@@ -35,13 +35,14 @@ import pa_workloads as W  # noqa: E402
 METRIC = ("spin-flip attempts/ns + resample GB/s (% HBM peak); wall time to "
           "β_f plain vs batched+MLP Δβ")
 HBM_PEAK_GBPS = 8000.0
-# VALU issue peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
-VALU_LANE_CYCLES_PER_S = 256 * 4 * 16 * 2.4e9
-# Issue cost of one spin-flip attempt in VALU lane-cycles: a quarter of a
-# Philox4x32-10 block (20 v_mad_u64_u32 at a quarter of the full rate and 40
-# v_xor_b32, i.e. 120 lane-cycles per 4 words) plus the two threshold
-# compares and accumulates of the site (4 lane-cycles).
-LANE_CYCLES_PER_ATTEMPT = 120 / 4 + 4
+# Integer VALU peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one
+# 32-bit operation per lane per cycle (gfx950 issues v_mad_u64_u32 and
+# v_bitop3_b32 at that rate; packed FP32 does not apply to integer work).
+VALU_OPS_PER_S = 256 * 4 * 16 * 2.4e9
+# Algorithmic integer work of one spin-flip attempt: a quarter of a
+# Philox4x32-10 block (10 rounds of 2 32x32->64 multiplies and 2 three-input
+# xors = 40 ops per 4 words) plus one threshold test and one accumulate.
+ALGO_OPS_PER_ATTEMPT = 40 / 4 + 2
 
 
 def run_anneal(binding, cfg, stream, timing=False, rows_per_lane=0):
@@ -100,6 +101,9 @@ def main():
     ap.add_argument("--rows-per-lane", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy, the reference "
+                         "for scaling FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU "
@@ -115,6 +119,14 @@ def main():
     stream = torch.cuda.current_stream().cuda_stream
     cfg = dict(W.CONFIGS[args.workload])
     cfg["name"] = args.workload
+    if args.calibrate_copy:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        src.fill_(1)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     for _ in range(args.warmup):
         run_anneal(binding, cfg, stream, rows_per_lane=args.rows_per_lane)
@@ -142,9 +154,9 @@ def main():
     sw = tsum["sweep"]
     sweep_avg_ms = sw["ms"] / max(1, sw["launches"])
     sweep_rate = tsum["attempts"] / (sw["ms"] * 1e6)       # attempts/ns
-    achieved = tsum["attempts"] / sw["launches"] * LANE_CYCLES_PER_ATTEMPT / (
+    achieved = tsum["attempts"] / sw["launches"] * ALGO_OPS_PER_ATTEMPT / (
         sweep_avg_ms * 1e-3) / 1e12
-    peak = VALU_LANE_CYCLES_PER_S / 1e12
+    peak = VALU_OPS_PER_S / 1e12
     res_ms = sum(tsum[k]["ms"] for k in ("hist", "counts", "scatter",
                                          "gather"))
     res_bytes = sum(tsum[k]["bytes"] for k in ("hist", "counts", "scatter",
@@ -181,12 +193,12 @@ def main():
             "bound": "alu",
             "achieved": achieved,
             "peak": peak,
-            "unit": "T VALU lane-cycles/s",
+            "unit": "TOP/s (32-bit integer VALU)",
             "frac": achieved / peak,
             "traffic": None,
             "sweep_attempts_per_ns": sweep_rate,
             "sweep_avg_ms": sweep_avg_ms,
-            "lane_cycles_per_attempt": LANE_CYCLES_PER_ATTEMPT,
+            "ops_per_attempt": ALGO_OPS_PER_ATTEMPT,
         },
         "resample": {
             "GBps": res_gbps,

@@ -126,14 +126,13 @@ int sync(pa_ctx* c) {
 // --------------------------------------------------------- double tables
 
 // Metropolis acceptance probabilities exp(-beta dE) for dE = 4, 8 as 32-bit
-// integer thresholds floor(p 2^32); a threshold of 2^32 means "always".
+// integer thresholds T = floor(p 2^32) (T = 2^32 accepts always); the kernel
+// receives K = 2^32 - T and rejects a random word r iff r + K >= 2^32.
 void thresholds(double beta, LatticeArgs& a) {
   const uint64_t T4 = (uint64_t)std::floor(std::ldexp(std::exp(-(beta * 4.0)), 32));
   const uint64_t T8 = (uint64_t)std::floor(std::ldexp(std::exp(-(beta * 8.0)), 32));
-  a.all4 = T4 >= (1ull << 32);
-  a.all8 = T8 >= (1ull << 32);
-  a.T4 = a.all4 ? 0xFFFFFFFFu : (uint32_t)T4;
-  a.T8 = a.all8 ? 0xFFFFFFFFu : (uint32_t)T8;
+  a.K4 = (1ull << 32) - T4;
+  a.K8 = (1ull << 32) - T8;
 }
 
 LatticeArgs lattice_args(pa_ctx* c) {
@@ -152,6 +151,7 @@ LatticeArgs lattice_args(pa_ctx* c) {
   a.pop = c->pop;
   a.step = (uint32_t)c->step;
   a.t0 = c->sweeps_at_step;
+  a.one = 1u;
   return a;
 }
 

@@ -13,22 +13,54 @@ constexpr uint32_t kDomainInit = 1u;
 constexpr uint32_t kDomainMcmc = 2u;
 constexpr uint32_t kDomainResample = 3u;
 
+// Three-input XOR in one VALU instruction (gfx950 v_bitop3_b32, truth
+// table 0x96).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
 // 32x32->64 multiplies by the round constants, a swap of the halves and a
 // xor with the key, the key stepping by the Weyl constants between rounds.
 // The key arrives in kernel arguments, so its schedule stays in scalar
-// registers and each round costs two v_mad_u64_u32 and two v_xor3_b32.
+// registers.  Counter words 1 and 3 are uniform in every caller, so the
+// first round folds them into the key on the scalar unit; each later round
+// is two v_mad_u64_u32 and two v_bitop3_b32.
 __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
-#pragma unroll
-  for (int i = 0; i < 10; ++i) {
+  {
     const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c.x;
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c.z;
-    c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1,
-                   (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
+    c = make_uint4((uint32_t)(p1 >> 32) ^ (c.y ^ k0), (uint32_t)p1,
+                   (uint32_t)(p0 >> 32) ^ (c.w ^ k1), (uint32_t)p0);
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+#pragma unroll
+  for (int i = 1; i < 10; ++i) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c.x;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c.z;
+    c = make_uint4(xor3((uint32_t)(p1 >> 32), c.y, k0), (uint32_t)p1,
+                   xor3((uint32_t)(p0 >> 32), c.w, k1), (uint32_t)p0);
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }
   return c;
+}
+
+// acc * 4 + bit as one v_lshl_add_u32.  Written as an instruction so that the
+// compiler keeps one shift-add per decision instead of re-associating the
+// chain into wider trees.
+__device__ __forceinline__ uint32_t shl2_add(uint32_t acc, uint32_t bit) {
+  uint32_t out;
+  asm("v_lshl_add_u32 %0, %1, 2, %2" : "=v"(out) : "v"(acc), "v"(bit));
+  return out;
+}
+
+// 1 iff r >= T, given K = 2^32 - T: the high word of r * one + K, a single
+// v_mad_u64_u32 (`one` is 1 at run time).
+__device__ __forceinline__ uint32_t reject_bit(uint32_t r, uint32_t one,
+                                               uint64_t K) {
+  return (uint32_t)(((uint64_t)r * one + K) >> 32);
 }
 
 // Mask of the valid bits of word `w` of a row of L sites.

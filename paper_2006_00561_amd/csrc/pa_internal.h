@@ -16,8 +16,9 @@ struct LatticeArgs {
   int32_t L;
   int32_t lpr;            // lanes per replica = L / rows per lane
   int32_t rpw;            // replicas per wave = 64 / lpr
-  uint32_t T4, T8;        // Metropolis thresholds for dE = 4, 8
-  int32_t all4, all8;     // threshold is 2^32: always accept
+  uint64_t K4, K8;        // 2^32 - T for the Metropolis thresholds
+                          // T = floor(exp(-beta dE) 2^32), dE = 4, 8
+  uint32_t one;           // the constant 1, opaque to the compiler
   uint32_t k0, k1;        // Philox key
   uint32_t pop, step;
   int32_t t0, theta;      // first sweep index at this step, sweep count

@@ -192,7 +192,6 @@ __global__ __launch_bounds__(256) void k_lattice(const LatticeArgs a) {
   }
 
   const int G8 = (L + 7) >> 3;
-  const int half = L >> 1;
   for (int t = 0; t < a.theta; ++t) {
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
@@ -207,6 +206,7 @@ __global__ __launch_bounds__(256) void k_lattice(const LatticeArgs a) {
       for (int r = 0; r < RPL; ++r) {
         const int y = lr * RPL + r;
         const uint32_t p = (uint32_t)((c + y) & 1);
+        const uint32_t rowbase = (kDomainMcmc << 28) | (uint32_t)(y * G8);
         const uint32_t* up = (r == 0) ? up0 : s[r > 0 ? r - 1 : 0];
         const uint32_t* dn = (r == RPL - 1) ? dnl : s[r < RPL - 1 ? r + 1 : 0];
         uint32_t lf[W], rt[W];
@@ -223,33 +223,30 @@ __global__ __launch_bounds__(256) void k_lattice(const LatticeArgs a) {
           const uint32_t x2 = d3 ^ d4, a2 = d3 & d4;
           const uint32_t eq0 = ~(d1 | d2 | d3 | d4);  // dE = +8
           const uint32_t eq1 = (x1 ^ x2) & ~(a1 | a2); // dE = +4
-          uint32_t ge2 = ~(eq0 | eq1);                 // dE <= 0
-          if (a.all8) ge2 |= eq0;
-          if (a.all4) ge2 |= eq1;
-          // 16 colour sites of this word: k = 16w .. 16w+15, x = 2k + p
-          uint32_t c4 = 0u, c8 = 0u;
-#pragma unroll
-          for (int gq = 0; gq < 4; ++gq) {
-            if (16 * w + 4 * gq < half) {
-              const uint4 b = philox10(
-                  make_uint4((kDomainMcmc << 28) |
-                                 (uint32_t)(y * G8 + 4 * w + gq),
-                             ctr1, slot, a.pop),
-                  a.k0, a.k1);
-              const uint32_t m4 = (uint32_t)(b.x < a.T4) |
-                                  ((uint32_t)(b.y < a.T4) << 1) |
-                                  ((uint32_t)(b.z < a.T4) << 2) |
-                                  ((uint32_t)(b.w < a.T4) << 3);
-              const uint32_t m8 = (uint32_t)(b.x < a.T8) |
-                                  ((uint32_t)(b.y < a.T8) << 1) |
-                                  ((uint32_t)(b.z < a.T8) << 2) |
-                                  ((uint32_t)(b.w < a.T8) << 3);
-              c4 |= m4 << (4 * gq);
-              c8 |= m8 << (4 * gq);
-            }
+          const uint32_t ge2 = ~(eq0 | eq1);           // dE <= 0
+          // The 16 colour sites of this word (k = 16w + j, x = 2k + p) draw
+          // word j%4 of group 4w + j/4.  The rejection bit of a site is the
+          // carry of r + (2^32 - T): hi(r * 1 + K) is 1 iff r >= T, one
+          // v_mad_u64_u32 (the 1 comes from the arguments, so it is not
+          // folded away); v_lshl_add then moves it to bit 2j, highest site
+          // first.  T = 2^32 (K = 0) never rejects, T = 0 (K = 2^32) always.
+          uint32_t rj4 = 0u, rj8 = 0u;
+          const int ng = min(4, max(0, G8 - 4 * w));
+          for (int gq = ng - 1; gq >= 0; --gq) {
+            const uint4 b = philox10(
+                make_uint4(rowbase + (uint32_t)(4 * w + gq), ctr1, slot, a.pop),
+                a.k0, a.k1);
+            rj4 = shl2_add(rj4, reject_bit(b.w, a.one, a.K4));
+            rj8 = shl2_add(rj8, reject_bit(b.w, a.one, a.K8));
+            rj4 = shl2_add(rj4, reject_bit(b.z, a.one, a.K4));
+            rj8 = shl2_add(rj8, reject_bit(b.z, a.one, a.K8));
+            rj4 = shl2_add(rj4, reject_bit(b.y, a.one, a.K4));
+            rj8 = shl2_add(rj8, reject_bit(b.y, a.one, a.K8));
+            rj4 = shl2_add(rj4, reject_bit(b.x, a.one, a.K4));
+            rj8 = shl2_add(rj8, reject_bit(b.x, a.one, a.K8));
           }
-          const uint32_t M4 = spread_even(c4) << p;
-          const uint32_t M8 = spread_even(c8) << p;
+          const uint32_t M4 = (~rj4 & 0x55555555u) << p;
+          const uint32_t M8 = (~rj8 & 0x55555555u) << p;
           const uint32_t col = (p ? 0xAAAAAAAAu : 0x55555555u) & valid_mask(L, w);
           const uint32_t flip = col & (ge2 | (eq1 & M4) | (eq0 & M8));
           s[r][w] = sv ^ flip;
