@@ -92,6 +92,99 @@ def cpu_baseline(cfg, budget_s=15.0):
                                          cfg["K"], theta, dt)}
 
 
+def bench_batched(binding, stream, use_graph=True):
+    """C4: 64 +-J populations (L in {8..32}, R in [2^10, 2^16]), beta 0 -> 3
+    in 300 linear steps, theta = 10; each population alone through the
+    single-population path, then all of them in one batch.  Both runs give
+    bit-identical ln Z, so accuracy is equal by construction."""
+    import torch
+    inst = W.batched_glass_instances()
+    betas = W.linear_schedule(3.0, 300)
+    theta = 10
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lnz_plain, attempts = [], 0
+    for c in inst:
+        g = binding.Population(c["L"], c["R"], seed=c["seed"],
+                               population_id=c["population_id"], J=c["J"],
+                               stream=stream)
+        for b in betas:
+            g.resample(b)
+            attempts += g.R * c["L"] ** 2 * theta
+            g.sweep(b, theta)
+            g.observables()
+        lnz_plain.append(g.free_energy()[0])
+        g.close()
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    bt = binding.Batch(inst, autotune=True)        # tuning outside the timing
+    bt.close()
+    t0 = time.perf_counter()
+    bt = binding.Batch(inst, autotune=True)
+    bt.run(betas, theta, use_graph=use_graph)
+    lnz_batch = [bt.state(p)[3] for p in range(len(inst))]
+    t_batch = time.perf_counter() - t0
+    bt.close()
+    return {
+        "workload": "C4: 64 +-J EA instances, L in {8,12,16,24,32}, R "
+                    "log-uniform in [2^10,2^16], beta 0->3 in 300 linear "
+                    "steps, theta=10",
+        "plain_s": t_plain, "batched_s": t_batch,
+        "speedup": t_plain / t_batch,
+        "batched_attempts_per_ns": attempts / (t_batch * 1e9),
+        "graph": bool(use_graph),
+        "lnZ_bitwise_equal": lnz_plain == lnz_batch,
+    }
+
+
+def bench_learned(binding, use_graph=True, target=0.85, tol=0.02):
+    """Adaptive schedules on the C4 populations to beta_f = 3, theta = 10:
+    the exact bisection on the overlap, and the network (trained on the
+    exact schedules of 32 other instances) with the bisection as judge and
+    fallback.  Wall time to beta_f, host time of the decisions, exact
+    overlap evaluations, and the ln Z agreement of the two."""
+    from paper_2006_00561_amd import learned
+    import numpy as np
+    inst = W.batched_glass_instances()
+    train_inst = W.batched_glass_instances(n=32, seed=4242,
+                                           coupling_seed0=10001)
+    for k, c in enumerate(train_inst):
+        c["population_id"] = 1000 + k
+    theta, beta_f = 10, 3.0
+    t0 = time.perf_counter()
+    X, T = learned.generate(train_inst, [0.8, 0.85, 0.9], beta_f, theta)
+    mlp, loss = learned.train(X, T, iters=3000, lr=2e-3, seed=5)
+    t_train = time.perf_counter() - t0
+    out = {"training_pairs": int(len(X)), "training_s": t_train,
+           "final_loss": loss, "target": target, "tol": tol}
+    res = {}
+    for mode in ("bisection", "learned"):
+        b = binding.Batch(inst, autotune=True)
+        t0 = time.perf_counter()
+        if mode == "bisection":
+            steps = b.run_adaptive(target, beta_f, 20000, theta,
+                                   use_graph=use_graph)
+        else:
+            steps, _ = b.run_learned(mlp, target, tol, beta_f, 20000, theta,
+                                     use_graph=use_graph)
+        dt = time.perf_counter() - t0
+        st = b.host_stats()
+        lnz = np.array([b.state(p)[3] for p in range(len(inst))])
+        res[mode] = (dt, steps, st, lnz)
+        b.close()
+    for mode, (dt, steps, st, lnz) in res.items():
+        out[mode] = {"wall_s": dt, "max_steps": steps,
+                     "host_ms": st["host_ms"],
+                     "overlap_evals": st["overlap_evals"],
+                     "sources": st["sources"]}
+    Ns = np.array([c["L"] ** 2 for c in inst], np.float64)
+    d = (res["learned"][3] - res["bisection"][3]) / Ns
+    out["lnZ_per_spin_rms_diff"] = float(np.sqrt(np.mean(d * d)))
+    out["speedup"] = res["bisection"][0] / res["learned"][0]
+    mlp.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +194,10 @@ def main():
     ap.add_argument("--rows-per-lane", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--eager", action="store_true",
+                    help="batched runs without HIP graphs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy, the reference "
                          "for scaling FETCH_SIZE / WRITE_SIZE counters")
@@ -211,6 +308,11 @@ def main():
         "wall_time_to_beta_f_s": dt / args.steps,
         "lnZ_final": lnZs[-1],
     }
+    if not args.no_batched:
+        out["batched"] = bench_batched(binding, stream,
+                                       use_graph=not args.eager)
+    if not args.no_learned:
+        out["learned"] = bench_learned(binding, use_graph=not args.eager)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -183,6 +183,142 @@ int pa_get_timing(pa_ctx* c, pa_timing* out);
 
 void pa_destroy(pa_ctx* c);
 const char* pa_strerror(int code);
+/* Text of the last failing HIP call on the calling thread (the call, the
+   source line and HIP's message) behind a PA_EDEVICE; "" if none.  The
+   string stays valid until the next failure on the thread. */
+const char* pa_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Batched populations: n independent populations (each its own pa_config:
+ * L, model, couplings, R_target, capacity, layout, rows_per_lane, seed,
+ * population_id; cfg.stream is ignored) advanced together.  Each population
+ * follows exactly the steps of Sec. 2 described above for pa_resample and
+ * pa_sweep, so its spins, energies, copy counts and ln Z are bit for bit those
+ * of a single-population context with the same configuration and schedule.
+ * Per temperature step all populations share one launch of each segmented
+ * kernel, one persistent sweep kernel per row-width class pulling
+ * (population, wave) items from a device queue, one device->host copy of all
+ * histograms, one host function for all double-precision tables and one
+ * host->device copy; with use_graph the kernels before and after the host
+ * function are captured once as two HIP graphs (kernel nodes only) and
+ * replayed every step, the copies and the host function running between
+ * the two launches.
+ *
+ * Errors: as above, except that after PA_ECAPACITY, PA_EEMPTY or PA_EDEVICE
+ * from pa_batch_run* the batch must only be destroyed.
+ * ---------------------------------------------------------------------- */
+typedef struct pa_batch pa_batch;
+enum { PA_BATCH_AUTOTUNE = 1 };   /* flags of pa_batch_init */
+
+/* Launch-shape autotuner: times theta sweeps of a synthetic population of R
+   replicas of side L for 1, 2 and 4 rows per lane (those valid for L) with
+   HIP events; *best receives the fastest, ms[3] (may be NULL) the times
+   (-1 for invalid shapes).  Results never depend on the shape. */
+int pa_tune_rows_per_lane(int32_t L, int32_t layout, int32_t model,
+                          int64_t R, int32_t theta, void* stream,
+                          int32_t* best, float* ms);
+
+/* Creates n populations at beta_0 = 0 (Eq. part-F, as pa_init).  stream NULL
+   = a private non-blocking stream (graph capture needs one).  flags:
+   PA_BATCH_AUTOTUNE picks rows_per_lane per distinct (L, layout, model) with
+   pa_tune_rows_per_lane where a config leaves it 0 (cached per process). */
+int pa_batch_init(const pa_config* cfgs, int32_t n, void* stream,
+                  int32_t flags, pa_batch** out);
+
+/* Advances every population through `steps` temperatures: betas[i*n + p] is
+   population p's i-th next beta (non-decreasing per population); theta
+   sweeps after each resampling.  Records the observables after each step's
+   sweeps (pa_batch_trajectory).  Synchronises at the end. */
+int pa_batch_run(pa_batch* b, int32_t steps, const double* betas,
+                 int32_t theta, int32_t use_graph);
+
+/* Adaptive schedule (Sec. 3 notes that an adaptive temperature step reduces
+   the population fluctuations): each population picks its own next beta as
+   the largest step to beta_f whose energy-distribution overlap is at least
+   `target` (the bisection of pa_bisect_dbeta, in the host function), and
+   stops at beta_f.  At most max_steps steps; *steps_taken receives the most
+   any population made. */
+int pa_batch_run_adaptive(pa_batch* b, double target, double beta_f,
+                          int32_t max_steps, int32_t theta, int32_t use_graph,
+                          int32_t* steps_taken);
+
+/* ------------------------------------------------------------------------
+ * Temperature-step network: an FP32 multilayer perceptron (n_in inputs,
+ * `depth` tanh layers of `width` units, one linear output) that proposes
+ * log(dbeta) from histogram summaries of a population.  Inputs are
+ * standardised with (mu, sigma), the output de-standardised with
+ * (mu_y, sigma_y).  Forward, backward (mean squared error on standardised
+ * targets) and Adam run in the library's HIP kernels.  The exact bisection
+ * remains the judge and the fallback, and the reweighting stays exact, so the
+ * network only changes which temperatures are visited, never the weights.
+ * Parameters: one flat FP32 vector, per layer W (out x in, row-major), b.
+ * ---------------------------------------------------------------------- */
+typedef struct pa_mlp pa_mlp;
+/* Glorot-uniform weights from `seed`, zero biases, identity scaling.
+   1 <= n_in <= 64, 1 <= width <= 1024, 1 <= depth <= 8. */
+int pa_mlp_create(int32_t n_in, int32_t width, int32_t depth, uint64_t seed,
+                  void* stream, pa_mlp** out);
+int pa_mlp_n_params(pa_mlp* m, int64_t* n);
+int pa_mlp_set_params(pa_mlp* m, const float* p, int64_t n);
+int pa_mlp_get_params(pa_mlp* m, float* p, int64_t n);
+int pa_mlp_set_norm(pa_mlp* m, const float* mu, const float* sigma,
+                    float mu_y, float sigma_y);
+/* y[s] = mu_y + sigma_y z(x_s) for B host rows X [B][n_in]. */
+int pa_mlp_forward(pa_mlp* m, const float* X, int32_t B, float* y);
+/* Mean squared error of the standardised outputs against standardised
+   targets T [B], and its gradient w.r.t. the parameters (host, may be
+   NULL). */
+int pa_mlp_loss_grad(pa_mlp* m, const float* X, const float* T, int32_t B,
+                     float* loss, float* grad);
+/* `iters` Adam steps (lr, beta1 0.9, beta2 0.999, eps 1e-8) on minibatches
+   of `batch` rows drawn in shuffled passes over the n rows (seeded);
+   *loss receives the last minibatch's loss. */
+int pa_mlp_train(pa_mlp* m, const float* X, const float* T, int64_t n,
+                 int32_t batch, int32_t iters, float lr, uint64_t seed,
+                 float* loss);
+void pa_mlp_destroy(pa_mlp* m);
+
+/* Adaptive schedule with the network: each population's next step is the
+   network's proposal when its exact overlap is within `tol` of `target`,
+   the whole remaining interval when that qualifies, else the bisection of
+   pa_batch_run_adaptive.  The summaries (8 per population: mean/N, ln sd(E),
+   skewness, (Emin - mean)/sd, beta, ln N, ln R, target) and the inference
+   run on the device in the step graph.  src_counts[5] (may be NULL) receives
+   how many steps came from each source (see pa_batch_decisions). */
+int pa_batch_run_learned(pa_batch* b, pa_mlp* m, double target, double tol,
+                         double beta_f, int32_t max_steps, int32_t theta,
+                         int32_t use_graph, int32_t* steps_taken,
+                         int64_t* src_counts);
+
+/* Per step of the last run in which population p moved: its 8 summaries,
+   the dbeta taken and its source (0 schedule, 1 bisection, 2 network,
+   3 bisection after a rejected proposal, 4 the whole remaining interval);
+   host arrays of `cap` rows.  The training data of the network. */
+int pa_batch_decisions(pa_batch* b, int32_t p, float* feat, double* dbeta,
+                       int32_t* src, int32_t cap, int32_t* len);
+
+/* Cost of the schedule decisions of the last run: milliseconds spent in the
+   host function, exact overlap evaluations made, steps per source [5]. */
+int pa_batch_host_stats(pa_batch* b, double* host_ms, int64_t* overlap_evals,
+                        int64_t* src_counts);
+
+/* Population p's size, beta, step index and ln Z (Eq. Free-En). */
+int pa_batch_state(pa_batch* b, int32_t p, int64_t* R, double* beta,
+                   int32_t* step, double* lnZ);
+
+/* Observables and ln Z of population p after each step of the last run in
+   which it moved (host arrays of `cap` entries; *len receives the count). */
+int pa_batch_trajectory(pa_batch* b, int32_t p, pa_obs* obs, double* lnZ,
+                        int32_t cap, int32_t* len);
+
+/* Canonical export of population p (as pa_get_population). */
+int pa_batch_get_population(pa_batch* b, int32_t p, int8_t* spins, int32_t* E,
+                            int32_t* M, int64_t cap);
+
+/* Workgroups of the persistent sweep kernel (default 2048). */
+int pa_batch_set_sweep_blocks(pa_batch* b, int32_t blocks);
+
+void pa_batch_destroy(pa_batch* b);
 
 #ifdef __cplusplus
 }

@@ -64,16 +64,18 @@ def gauge_couplings(L: int, seed: int):
     return J, eps
 
 
-def batched_glass_instances(n: int = 64, seed: int = 2006):
+def batched_glass_instances(n: int = 64, seed: int = 2006,
+                            coupling_seed0: int = 1):
     """The batched workload: n independent +-J populations with L drawn
     uniformly from {8, 12, 16, 24, 32} and R log-uniform in [2^10, 2^16];
-    instance k uses coupling seed k + 1 and population id k."""
+    instance k uses coupling seed coupling_seed0 + k and population id k."""
     rng = np.random.Generator(np.random.PCG64(seed))
     Ls = rng.choice([8, 12, 16, 24, 32], size=n)
     Rs = np.round(2.0 ** (10.0 + 6.0 * rng.random(n))).astype(np.int64)
     out = []
     for k in range(n):
         L = int(Ls[k])
-        out.append(dict(L=L, R=int(Rs[k]), J=pmj_couplings(L, k + 1),
+        out.append(dict(L=L, R=int(Rs[k]),
+                        J=pmj_couplings(L, coupling_seed0 + k),
                         population_id=k, seed=1))
     return out

@@ -17,8 +17,11 @@ from .binding import (  # noqa: F401
     PA_INT8,
     PA_OK,
     PA_PMJ,
+    MLP,
+    Batch,
     PAError,
     Population,
     lib,
     strerror,
+    tune_rows_per_lane,
 )

@@ -48,7 +48,10 @@ class pa_timing(C.Structure):
 
 class PAError(RuntimeError):
     def __init__(self, code, what):
-        super().__init__("%s failed: %s (%d)" % (what, strerror(code), code))
+        msg = "%s failed: %s (%d)" % (what, strerror(code), code)
+        if code == PA_EDEVICE:
+            msg += ": " + lib().pa_last_error().decode()
+        super().__init__(msg)
         self.code = code
 
 
@@ -85,6 +88,38 @@ def lib():
             "pa_get_timing": ([P, C.POINTER(pa_timing)], C.c_int),
             "pa_destroy": ([P], None),
             "pa_strerror": ([C.c_int], C.c_char_p),
+            "pa_last_error": ([], C.c_char_p),
+            "pa_tune_rows_per_lane": ([i32, i32, i32, i64, i32, P,
+                                       C.POINTER(i32), P], C.c_int),
+            "pa_batch_init": ([P, i32, P, i32, C.POINTER(P)], C.c_int),
+            "pa_batch_run": ([P, i32, P, i32, i32], C.c_int),
+            "pa_batch_run_adaptive": ([P, d, d, i32, i32, i32,
+                                       C.POINTER(i32)], C.c_int),
+            "pa_batch_state": ([P, i32, C.POINTER(i64), C.POINTER(d),
+                                C.POINTER(i32), C.POINTER(d)], C.c_int),
+            "pa_batch_trajectory": ([P, i32, P, P, i32, C.POINTER(i32)],
+                                    C.c_int),
+            "pa_batch_get_population": ([P, i32, P, P, P, i64], C.c_int),
+            "pa_batch_set_sweep_blocks": ([P, i32], C.c_int),
+            "pa_batch_destroy": ([P], None),
+            "pa_batch_run_learned": ([P, P, d, d, d, i32, i32, i32,
+                                      C.POINTER(i32), P], C.c_int),
+            "pa_batch_decisions": ([P, i32, P, P, P, i32, C.POINTER(i32)],
+                                   C.c_int),
+            "pa_batch_host_stats": ([P, C.POINTER(d), C.POINTER(i64), P],
+                                    C.c_int),
+            "pa_mlp_create": ([i32, i32, i32, C.c_uint64, P, C.POINTER(P)],
+                              C.c_int),
+            "pa_mlp_n_params": ([P, C.POINTER(i64)], C.c_int),
+            "pa_mlp_set_params": ([P, P, i64], C.c_int),
+            "pa_mlp_get_params": ([P, P, i64], C.c_int),
+            "pa_mlp_set_norm": ([P, P, P, C.c_float, C.c_float], C.c_int),
+            "pa_mlp_forward": ([P, P, i32, P], C.c_int),
+            "pa_mlp_loss_grad": ([P, P, P, i32, C.POINTER(C.c_float), P],
+                                 C.c_int),
+            "pa_mlp_train": ([P, P, P, i64, i32, i32, C.c_float, C.c_uint64,
+                              C.POINTER(C.c_float)], C.c_int),
+            "pa_mlp_destroy": ([P], None),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -256,3 +291,202 @@ class Population:
                       "bytes": t.bytes[i]}
         out["attempts"] = t.attempts
         return out
+
+
+def tune_rows_per_lane(L, layout=PA_INT8, model=PA_FERRO, R=4096, theta=4,
+                       stream=None):
+    """Fastest rows-per-lane sweep shape for side L (and the three times)."""
+    best = C.c_int32()
+    ms = (C.c_float * 3)()
+    _ck(lib().pa_tune_rows_per_lane(L, layout, model, R, theta, stream,
+                                    C.byref(best), ms),
+        "pa_tune_rows_per_lane")
+    return best.value, list(ms)
+
+
+class Batch:
+    """Many independent populations advanced together (pa_batch_*)."""
+
+    def __init__(self, pops, stream=None, autotune=False):
+        """pops: list of dicts with keys L, R (target), and optionally J,
+        seed, population_id, layout, capacity, rows_per_lane."""
+        self.n = len(pops)
+        self._keep = []
+        cfgs = (pa_config * self.n)()
+        self.L = []
+        for i, p in enumerate(pops):
+            c = cfgs[i]
+            J = p.get("J")
+            if J is not None:
+                J = np.ascontiguousarray(J, np.int8)
+                self._keep.append(J)
+            c.L = p["L"]
+            c.model = PA_FERRO if J is None else PA_PMJ
+            c.J = _ptr(J)
+            c.R_target = p["R"]
+            c.capacity = p.get("capacity", 0)
+            c.layout = p.get("layout", PA_INT8)
+            c.rows_per_lane = p.get("rows_per_lane", 0)
+            c.seed = p.get("seed", 1)
+            c.population_id = p.get("population_id", i)
+            self.L.append(p["L"])
+        h = C.c_void_p()
+        _ck(lib().pa_batch_init(cfgs, self.n, stream, 1 if autotune else 0,
+                                C.byref(h)), "pa_batch_init")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pa_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, betas, theta, use_graph=True):
+        """betas: array [steps][n] of next temperatures."""
+        b = np.ascontiguousarray(betas, np.float64)
+        if b.ndim == 1:
+            b = np.repeat(b[:, None], self.n, axis=1).copy()
+        assert b.shape[1] == self.n
+        _ck(lib().pa_batch_run(self._h, b.shape[0], _ptr(b), theta,
+                               1 if use_graph else 0), "pa_batch_run")
+
+    def run_adaptive(self, target, beta_f, max_steps, theta, use_graph=True):
+        st = C.c_int32()
+        _ck(lib().pa_batch_run_adaptive(self._h, target, beta_f, max_steps,
+                                        theta, 1 if use_graph else 0,
+                                        C.byref(st)), "pa_batch_run_adaptive")
+        return st.value
+
+    def state(self, p):
+        R, b, s, z = C.c_int64(), C.c_double(), C.c_int32(), C.c_double()
+        _ck(lib().pa_batch_state(self._h, p, C.byref(R), C.byref(b),
+                                 C.byref(s), C.byref(z)), "pa_batch_state")
+        return R.value, b.value, s.value, z.value
+
+    def trajectory(self, p, cap=100000):
+        obs = (pa_obs * cap)()
+        z = np.zeros(cap, np.float64)
+        ln = C.c_int32()
+        _ck(lib().pa_batch_trajectory(self._h, p, obs, _ptr(z), cap,
+                                      C.byref(ln)), "pa_batch_trajectory")
+        return [obs[i].as_dict() for i in range(ln.value)], z[:ln.value]
+
+    def population(self, p):
+        R = self.state(p)[0]
+        L = self.L[p]
+        s = np.empty((R, L, L), np.int8)
+        E = np.empty(R, np.int32)
+        M = np.empty(R, np.int32)
+        _ck(lib().pa_batch_get_population(self._h, p, _ptr(s), _ptr(E),
+                                          _ptr(M), R),
+            "pa_batch_get_population")
+        return s, E, M
+
+    def set_sweep_blocks(self, blocks):
+        _ck(lib().pa_batch_set_sweep_blocks(self._h, blocks),
+            "pa_batch_set_sweep_blocks")
+
+    def run_learned(self, mlp, target, tol, beta_f, max_steps, theta,
+                    use_graph=True):
+        st = C.c_int32()
+        src = np.zeros(5, np.int64)
+        _ck(lib().pa_batch_run_learned(self._h, mlp._h, target, tol, beta_f,
+                                       max_steps, theta, 1 if use_graph else 0,
+                                       C.byref(st), _ptr(src)),
+            "pa_batch_run_learned")
+        return st.value, src
+
+    def decisions(self, p, cap=100000):
+        """(features [k][8] float32, dbeta [k], source [k]) of population p
+        over the last run."""
+        f = np.zeros((cap, 8), np.float32)
+        db = np.zeros(cap, np.float64)
+        src = np.zeros(cap, np.int32)
+        ln = C.c_int32()
+        _ck(lib().pa_batch_decisions(self._h, p, _ptr(f), _ptr(db), _ptr(src),
+                                     cap, C.byref(ln)), "pa_batch_decisions")
+        k = ln.value
+        return f[:k], db[:k], src[:k]
+
+    def host_stats(self):
+        ms = C.c_double()
+        ev = C.c_int64()
+        src = np.zeros(5, np.int64)
+        _ck(lib().pa_batch_host_stats(self._h, C.byref(ms), C.byref(ev),
+                                      _ptr(src)), "pa_batch_host_stats")
+        return {"host_ms": ms.value, "overlap_evals": ev.value,
+                "sources": src.tolist()}
+
+
+class MLP:
+    """The temperature-step network (pa_mlp_*): FP32, trained and evaluated
+    by the library's HIP kernels."""
+
+    def __init__(self, n_in=8, width=64, depth=3, seed=1, stream=None):
+        h = C.c_void_p()
+        _ck(lib().pa_mlp_create(n_in, width, depth, seed, stream, C.byref(h)),
+            "pa_mlp_create")
+        self._h = h
+        self.n_in, self.width, self.depth = n_in, width, depth
+        n = C.c_int64()
+        _ck(lib().pa_mlp_n_params(h, C.byref(n)), "pa_mlp_n_params")
+        self.n_params = n.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pa_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self):
+        p = np.zeros(self.n_params, np.float32)
+        _ck(lib().pa_mlp_get_params(self._h, _ptr(p), self.n_params),
+            "pa_mlp_get_params")
+        return p
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, np.float32)
+        _ck(lib().pa_mlp_set_params(self._h, _ptr(p), len(p)),
+            "pa_mlp_set_params")
+
+    def set_norm(self, mu, sigma, mu_y, sigma_y):
+        mu = np.ascontiguousarray(mu, np.float32)
+        sigma = np.ascontiguousarray(sigma, np.float32)
+        _ck(lib().pa_mlp_set_norm(self._h, _ptr(mu), _ptr(sigma),
+                                  float(mu_y), float(sigma_y)),
+            "pa_mlp_set_norm")
+
+    def forward(self, X):
+        X = np.ascontiguousarray(X, np.float32)
+        y = np.zeros(len(X), np.float32)
+        _ck(lib().pa_mlp_forward(self._h, _ptr(X), len(X), _ptr(y)),
+            "pa_mlp_forward")
+        return y
+
+    def loss_grad(self, X, T):
+        X = np.ascontiguousarray(X, np.float32)
+        T = np.ascontiguousarray(T, np.float32)
+        g = np.zeros(self.n_params, np.float32)
+        loss = C.c_float()
+        _ck(lib().pa_mlp_loss_grad(self._h, _ptr(X), _ptr(T), len(X),
+                                   C.byref(loss), _ptr(g)), "pa_mlp_loss_grad")
+        return loss.value, g
+
+    def train(self, X, T, batch=256, iters=2000, lr=1e-3, seed=7):
+        X = np.ascontiguousarray(X, np.float32)
+        T = np.ascontiguousarray(T, np.float32)
+        loss = C.c_float()
+        _ck(lib().pa_mlp_train(self._h, _ptr(X), _ptr(T), len(X), batch,
+                               iters, lr, seed, C.byref(loss)),
+            "pa_mlp_train")
+        return loss.value

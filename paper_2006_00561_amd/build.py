@@ -17,7 +17,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 SO = os.path.join(HERE, "libpa.so")
-SOURCES = ["pa_kernels.hip", "pa_api.hip"]
+SOURCES = ["pa_kernels.hip", "pa_tables.hip", "pa_api.hip", "pa_batch.hip",
+           "pa_mlp.hip"]
 ARCH = os.environ.get("PA_OFFLOAD_ARCH", "gfx950")
 
 

@@ -65,10 +65,7 @@ struct pa_ctx {
   pa_timing acc{};
 };
 
-#define CK(x)                                  \
-  do {                                         \
-    if ((x) != hipSuccess) return PA_EDEVICE;  \
-  } while (0)
+#define CK(x) PA_HIP(x)
 
 namespace {
 
@@ -88,7 +85,7 @@ hipEvent_t take_event(pa_ctx* c) {
 hipEvent_t t_begin(pa_ctx* c) {
   if (!c->timing) return nullptr;
   hipEvent_t e = take_event(c);
-  if (e) hipEventRecord(e, c->stream);
+  if (e) (void)hipEventRecord(e, c->stream);
   return e;
 }
 
@@ -97,7 +94,7 @@ void t_end(pa_ctx* c, int cls, hipEvent_t e0, int64_t bytes,
   if (!c->timing || !e0) return;
   hipEvent_t e1 = take_event(c);
   if (!e1) return;
-  hipEventRecord(e1, c->stream);
+  (void)hipEventRecord(e1, c->stream);
   c->pending.push_back({cls, e0, e1, bytes, attempts});
 }
 
@@ -124,16 +121,6 @@ int sync(pa_ctx* c) {
 }
 
 // --------------------------------------------------------- double tables
-
-// Metropolis acceptance probabilities exp(-beta dE) for dE = 4, 8 as 32-bit
-// integer thresholds T = floor(p 2^32) (T = 2^32 accepts always); the kernel
-// receives K = 2^32 - T and rejects a random word r iff r + K >= 2^32.
-void thresholds(double beta, LatticeArgs& a) {
-  const uint64_t T4 = (uint64_t)std::floor(std::ldexp(std::exp(-(beta * 4.0)), 32));
-  const uint64_t T8 = (uint64_t)std::floor(std::ldexp(std::exp(-(beta * 8.0)), 32));
-  a.K4 = (1ull << 32) - T4;
-  a.K8 = (1ull << 32) - T8;
-}
 
 LatticeArgs lattice_args(pa_ctx* c) {
   LatticeArgs a{};
@@ -192,41 +179,6 @@ int compute_hist(pa_ctx* c) {
   if (c->h_scal[3] != 0) return PA_EDEVICE;  // an energy outside [-2N, 2N]
   c->hist_valid = true;
   return PA_OK;
-}
-
-int level_energy(const pa_ctx* c, int i) { return -2 * c->N + (i << c->hshift); }
-
-void occupied(const pa_ctx* c, int* lo, int* hi) {
-  int a = 0, b = c->nbins - 1;
-  while (a < c->nbins && c->h_hist[a] == 0) ++a;
-  while (b >= 0 && c->h_hist[b] == 0) --b;
-  *lo = a;
-  *hi = b;
-}
-
-// Overlap alpha(dbeta) = sum_E min(h/R, h w / S) from the host histogram.
-double overlap_of(const pa_ctx* c, double dbeta) {
-  int lo, hi;
-  occupied(c, &lo, &hi);
-  const int Emin = level_energy(c, lo);
-  double S = 0.0;
-  for (int i = lo; i <= hi; ++i) {
-    const uint32_t h = c->h_hist[i];
-    if (h == 0) continue;
-    const double term =
-        (double)h * std::exp(-(dbeta * (double)(level_energy(c, i) - Emin)));
-    S = S + term;
-  }
-  double a = 0.0;
-  for (int i = lo; i <= hi; ++i) {
-    const uint32_t h = c->h_hist[i];
-    if (h == 0) continue;
-    const double pe = (double)h / (double)c->R;
-    const double qe =
-        ((double)h * std::exp(-(dbeta * (double)(level_energy(c, i) - Emin)))) / S;
-    a = a + (pe < qe ? pe : qe);
-  }
-  return a;
 }
 
 void free_all(pa_ctx* c) {
@@ -418,7 +370,7 @@ int pa_sweep(pa_ctx* c, double beta, int32_t theta) {
   if (c->sweeps_at_step + theta > 32767) return PA_EINVAL;
   if (theta == 0) return PA_OK;
   LatticeArgs a = lattice_args(c);
-  thresholds(c->beta, a);
+  metropolis_K(c->beta, &a.K4, &a.K8);
   a.theta = theta;
   int rc = run_lattice(c, a, PA_K_SWEEP);
   if (rc) return rc;
@@ -434,43 +386,20 @@ int pa_resample(pa_ctx* c, double beta_next, int64_t* R_new) {
   int rc = compute_hist(c);
   if (rc) return rc;
   const double dbeta = beta_next - c->beta;
-  int lo, hi;
-  occupied(c, &lo, &hi);
-  if (lo > hi) return PA_ESTATE;
-  const int Emin = level_energy(c, lo);
-  const int nl = hi - lo + 1;
-  // (b) Boltzmann factors shifted by Emin, summed in ascending energy
-  std::vector<double> w((size_t)nl, 0.0);
-  double S = 0.0;
-  for (int i = lo; i <= hi; ++i) {
-    const uint32_t h = c->h_hist[i];
-    if (h == 0) continue;
-    const double we = std::exp(-(dbeta * (double)(level_energy(c, i) - Emin)));
-    w[i - lo] = we;
-    const double term = (double)h * we;
-    S = S + term;
-  }
-  // (c) ln Q with the shift restored (Eq. part-Q)
-  const double lnQ = (-(dbeta * (double)Emin)) + std::log(S / (double)c->R);
-  // (d) rho = R_target tau / R (Eq. tau): integer part and 32-bit threshold
-  uint32_t* tf = c->h_tab;
-  uint32_t* tT = c->h_tab + nl;
-  for (int i = lo; i <= hi; ++i) {
-    tf[i - lo] = 0u;
-    tT[i - lo] = 0u;
-    if (c->h_hist[i] == 0) continue;
-    const double rho = ((double)c->R_t * w[i - lo]) / S;
-    const double fl = std::floor(rho);
-    tf[i - lo] = (uint32_t)fl;
-    tT[i - lo] = (uint32_t)(uint64_t)std::floor(std::ldexp(rho - fl, 32));
-  }
-  CK(hipMemcpyAsync(c->tab, c->h_tab, (size_t)nl * 8, hipMemcpyHostToDevice,
-                    c->stream));
+  TableRange tr;
+  const int nbins = c->nbins;
+  rc = build_tables(c->h_hist, nbins, c->hshift, c->N, c->R, c->R_t, dbeta,
+                    c->h_tab, c->h_tab + nbins, &tr);
+  if (rc) return rc;
+  const int lo = tr.lo, nl = tr.hi - tr.lo + 1;
+  const double lnQ = tr.lnQ;
+  CK(hipMemcpyAsync(c->tab, c->h_tab, (size_t)nbins * 8,
+                    hipMemcpyHostToDevice, c->stream));
   // (e) copy counts and their exclusive scan
   CountsArgs ca{};
   ca.E = c->E[c->cur];
   ca.f = c->tab;
-  ca.T = c->tab + nl;
+  ca.T = c->tab + nbins;
   ca.n = c->n;
   ca.tile_sum = c->tile_sum;
   ca.R = c->R;
@@ -538,29 +467,8 @@ int pa_observables(pa_ctx* c, pa_obs* o) {
   if (!c || !o) return PA_EINVAL;
   int rc = compute_hist(c);
   if (rc) return rc;
-  int64_t sE = 0, sE2 = 0;
-  int lo, hi;
-  occupied(c, &lo, &hi);
-  for (int i = lo; i <= hi; ++i) {
-    const int64_t h = c->h_hist[i], e = level_energy(c, i);
-    sE += h * e;
-    sE2 += h * e * e;
-  }
-  const int64_t sAM = (int64_t)c->h_scal[0], sM2 = (int64_t)c->h_scal[1];
-  const double R = (double)c->R, N = (double)c->N;
-  const __int128 var = (__int128)c->R * sE2 - (__int128)sE * sE;
-  o->R = c->R;
-  o->beta = c->beta;
-  o->e = (double)sE / (R * N);
-  o->abs_m = (double)sAM / (R * N);
-  o->m2 = (double)sM2 / (R * N * N);
-  o->C = ((c->beta * c->beta) * (double)var) / ((R * R) * N);
-  o->sumE = sE;
-  o->sumE2 = sE2;
-  o->sumAbsM = sAM;
-  o->sumM2 = sM2;
-  o->Emin = level_energy(c, lo);
-  o->Emax = level_energy(c, hi);
+  observables_from_hist(c->h_hist, c->nbins, c->hshift, c->N, c->R, c->beta,
+                        (int64_t)c->h_scal[0], (int64_t)c->h_scal[1], o);
   return PA_OK;
 }
 
@@ -669,7 +577,8 @@ int pa_overlap(pa_ctx* c, double dbeta, double* alpha) {
   if (!c || !alpha || !std::isfinite(dbeta) || dbeta < 0.0) return PA_EINVAL;
   int rc = compute_hist(c);
   if (rc) return rc;
-  *alpha = overlap_of(c, dbeta);
+  *alpha = overlap_from_hist(c->h_hist, c->nbins, c->hshift, c->N, c->R,
+                             dbeta);
   return PA_OK;
 }
 
@@ -679,22 +588,8 @@ int pa_bisect_dbeta(pa_ctx* c, double target, double beta_f, double* dbeta) {
     return PA_EINVAL;
   int rc = compute_hist(c);
   if (rc) return rc;
-  const double span = beta_f - c->beta;
-  if (!(span > 0.0)) {
-    *dbeta = 0.0;
-    return PA_OK;
-  }
-  if (overlap_of(c, span) >= target) {
-    *dbeta = span;
-    return PA_OK;
-  }
-  double lo = 0.0, hi = span;
-  for (int it = 0; it < 64; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    if (overlap_of(c, mid) >= target) lo = mid;
-    else hi = mid;
-  }
-  *dbeta = lo;
+  *dbeta = bisect_from_hist(c->h_hist, c->nbins, c->hshift, c->N, c->R,
+                            target, beta_f - c->beta);
   return PA_OK;
 }
 

@@ -1,0 +1,1292 @@
+// Batched population annealing: many independent populations (uneven L and
+// R, ferromagnets and +-J glasses) advanced together, one set of launches
+// per temperature step for all of them.
+//
+// Each population is the method of the paper's Sec. 2 on its own (its own
+// Philox key and population id, its own schedule, its own ln Z), so every
+// population's trajectory is bit for bit the one the single-population path
+// (pa_init / pa_resample / pa_sweep) produces.  What changes is the launch
+// structure:
+//   - segmented kernels (grid y = population) for the histogram, copy
+//     counts, scan, parent scatter and gather, reading every population's
+//     size from device memory;
+//   - one persistent sweep kernel per row-width class that pulls (population,
+//     wave) work items from a device queue, largest lattices first;
+//   - one device->host copy of all histograms, one host function building
+//     every population's double-precision tables (and next beta), one
+//     host->device copy of all tables per step;
+//   - the kernels before and after the host function have no host-side size
+//     dependence, so each sequence is captured once as a HIP graph of kernel
+//     nodes and replayed every step; the two copies and the host function
+//     run between the two graph launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <numeric>
+#include <tuple>
+#include <vector>
+
+#include "pa.h"
+#include "pa_device.h"
+#include "pa_internal.h"
+#include "pa_lattice.h"
+
+namespace pa {
+
+// -------------------------------------------------------------- kernels
+
+// One-dimensional grid: gx workgroups of 2048 replicas per population.
+__global__ __launch_bounds__(256) void k_bhist(const BatchPop* P,
+                                               const int64_t* R,
+                                               const int32_t* cur,
+                                               unsigned long long* mom,
+                                               unsigned long long* flags,
+                                               int lds_bins, int gx) {
+  extern __shared__ uint32_t sh[];
+  const int p = blockIdx.x / gx;
+  const int bx = blockIdx.x - p * gx;
+  const int64_t Rp = R[p];
+  if ((int64_t)bx * 256 * 8 >= Rp) return;  // whole block
+  const BatchPop& q = P[p];
+  const int c = cur[p];
+  const int32_t* E = q.E[c];
+  const int32_t* M = q.M[c];
+  const int twoN = 2 * q.L * q.L;
+  const bool lds = q.nbins <= lds_bins;
+  if (lds) {
+    for (int i = threadIdx.x; i < q.nbins; i += blockDim.x) sh[i] = 0u;
+    __syncthreads();
+  }
+  unsigned long long sam = 0ull, sm2 = 0ull;
+  const int64_t j0 = (int64_t)bx * 256 * 8;
+  const int64_t j1 = min(j0 + 256 * 8, Rp);
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += 256) {
+    const int idx = (E[j] + twoN) >> q.shift;
+    if (idx < 0 || idx >= q.nbins) {
+      atomicAdd(&flags[0], 1ull);
+      continue;
+    }
+    if (lds) atomicAdd(&sh[idx], 1u);
+    else atomicAdd(&q.hist[idx], 1u);
+    const int m = M[j];
+    sam += (unsigned long long)(m < 0 ? -m : m);
+    sm2 += (unsigned long long)((long long)m * m);
+  }
+  if (lds) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < q.nbins; i += blockDim.x)
+      if (sh[i]) atomicAdd(&q.hist[i], sh[i]);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    sam += __shfl_down(sam, off, 64);
+    sm2 += __shfl_down(sm2, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(&mom[2 * p], sam);
+    atomicAdd(&mom[2 * p + 1], sm2);
+  }
+}
+
+__device__ __forceinline__ uint32_t block_excl_scan256(uint32_t v,
+                                                       uint32_t* lds,
+                                                       uint32_t* total) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint32_t incl = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t o = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += o;
+  }
+  if (lane == 63) lds[wid] = incl;
+  __syncthreads();
+  uint32_t wbase = 0u, tot = 0u;
+  for (int i = 0; i < 4; ++i) {
+    const uint32_t x = lds[i];
+    if (i < wid) wbase += x;
+    tot += x;
+  }
+  *total = tot;
+  return wbase + incl - v;
+}
+
+__global__ __launch_bounds__(256) void k_bcounts(const BatchPop* P,
+                                                 const BatchStep* S,
+                                                 const int64_t* R,
+                                                 const int32_t* cur) {
+  __shared__ uint32_t lds[4];
+  const int p = blockIdx.y;
+  const int64_t Rp = R[p];
+  if (!S[p].active || (int64_t)blockIdx.x * 256 >= Rp) return;  // whole block
+  const BatchPop& q = P[p];
+  const BatchStep& st = S[p];
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  uint32_t nj = 0u;
+  if (j < Rp) {
+    const int32_t* E = q.E[cur[p]];
+    const int l = ((E[j] + 2 * q.L * q.L) >> q.shift) - st.lvl0;
+    const uint4 b = philox10(make_uint4(kDomainResample << 28, st.step << 16,
+                                        (uint32_t)j, q.pop),
+                             q.k0, q.k1);
+    if (l >= 0 && l < st.nlvl)
+      nj = q.tab[l] + (b.x < q.tab[q.nbins + l] ? 1u : 0u);
+    q.n[j] = nj;
+  }
+  uint32_t total;
+  (void)block_excl_scan256(nj, lds, &total);
+  if (threadIdx.x == 0) q.tile_sum[blockIdx.x] = total;
+}
+
+// One workgroup per population: scan of its tile sums, its new size.
+__global__ __launch_bounds__(1024) void k_bscan(const BatchPop* P,
+                                                const BatchStep* S,
+                                                const int64_t* R,
+                                                int64_t* Rnew,
+                                                unsigned long long* flags) {
+  __shared__ unsigned long long part[1024];
+  const int p = blockIdx.x;
+  if (!S[p].active) {
+    if (threadIdx.x == 0) Rnew[p] = R[p];
+    return;
+  }
+  const BatchPop& q = P[p];
+  const int tid = threadIdx.x;
+  const int64_t ntiles = (R[p] + 255) / 256;
+  const int64_t per = (ntiles + 1023) / 1024;
+  const int64_t b = tid * per;
+  const int64_t e = (b + per < ntiles) ? b + per : ntiles;
+  unsigned long long s = 0ull;
+  for (int64_t i = b; i < e; ++i) s += q.tile_sum[i];
+  part[tid] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const unsigned long long v = (tid >= off) ? part[tid - off] : 0ull;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  unsigned long long run = part[tid] - s;
+  for (int64_t i = b; i < e; ++i) {
+    q.tile_off[i] = (uint32_t)run;
+    run += q.tile_sum[i];
+  }
+  if (tid == 1023) {
+    const int64_t tot = (int64_t)part[1023];
+    Rnew[p] = tot;
+    if (tot > q.cap) atomicOr(&flags[1], 1ull);
+    if (tot == 0) atomicOr(&flags[1], 2ull);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_bscatter(const BatchPop* P,
+                                                  const BatchStep* S,
+                                                  const int64_t* R) {
+  __shared__ uint32_t lds[4];
+  const int p = blockIdx.y;
+  const int64_t Rp = R[p];
+  if (!S[p].active || (int64_t)blockIdx.x * 256 >= Rp) return;  // whole block
+  const BatchPop& q = P[p];
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const uint32_t nj = (j < Rp) ? q.n[j] : 0u;
+  uint32_t total;
+  const uint32_t ex = block_excl_scan256(nj, lds, &total);
+  const int64_t o = (int64_t)q.tile_off[blockIdx.x] + ex;
+  for (uint32_t t = 0; t < nj; ++t)
+    if (o + t < q.cap) q.parent[o + t] = (uint32_t)j;
+}
+
+// Grid-stride over row groups of every population (grid y = population).
+__global__ __launch_bounds__(256) void k_bgather(const BatchPop* P,
+                                                 const BatchStep* S,
+                                                 const int64_t* Rnew,
+                                                 const int32_t* cur) {
+  const int p = blockIdx.y;
+  if (!S[p].active) return;
+  const BatchPop& q = P[p];
+  const int64_t Rn = min(Rnew[p], q.cap);
+  const int c = cur[p];
+  const int lane = threadIdx.x & 63;
+  const int sub = lane >> q.lpr_log2;
+  const int c0 = lane & ((1 << q.lpr_log2) - 1);
+  const int64_t rows_per_wave = 64 >> q.lpr_log2;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+       w * rows_per_wave < Rn; w += waves) {
+    const int64_t k = w * rows_per_wave + sub;
+    if (k >= Rn) continue;
+    const uint32_t par = q.parent[k];
+    const uint4* src =
+        reinterpret_cast<const uint4*>(q.spins[c] + (size_t)par * q.stride);
+    uint4* dst = reinterpret_cast<uint4*>(q.spins[c ^ 1] + (size_t)k * q.stride);
+    for (int ch = c0; ch < q.chunks; ch += (1 << q.lpr_log2)) dst[ch] = src[ch];
+    if (c0 == 0) {
+      q.E[c ^ 1][k] = q.E[c][par];
+      q.M[c ^ 1][k] = q.M[c][par];
+    }
+  }
+}
+
+// Single workgroup: adopt the new populations, then lay out the sweep work
+// queue (items = waves of rpw replicas) for every row-width class, in the
+// sorted population order.
+__global__ __launch_bounds__(256) void k_bcommit(
+    const BatchPop* P, const BatchStep* S, int64_t* R, const int64_t* Rnew,
+    int32_t* cur, const int32_t* order, int n, const int32_t* cls_first,
+    const int32_t* cls_count, int64_t* prefix, unsigned long long* queue,
+    int commit) {
+  if (commit) {
+    for (int p = threadIdx.x; p < n; p += blockDim.x) {
+      if (!S[p].active) continue;
+      const int64_t rn = Rnew[p];
+      if (rn >= 1 && rn <= P[p].cap) {
+        R[p] = rn;
+        cur[p] ^= 1;
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 5 && cls_count[threadIdx.x] > 0) {
+    const int w = threadIdx.x;
+    int64_t acc = 0;
+    const int f = cls_first[w];
+    for (int i = 0; i < cls_count[w]; ++i) {
+      const int p = order[f + i];
+      prefix[f + w + i] = acc;
+      if (S[p].active && S[p].theta > 0) acc += (R[p] + P[p].rpw - 1) / P[p].rpw;
+    }
+    prefix[f + w + cls_count[w]] = acc;
+    queue[w] = 0ull;
+  }
+}
+
+// Histogram summaries of every population (one workgroup each), from its
+// exact energy histogram: mean/N, log of the energy standard deviation,
+// skewness, (Emin - mean)/sd, beta, log N, log R and the overlap target.
+// Double precision, rounded to FP32 for the network.
+__global__ __launch_bounds__(256) void k_bfeatures(const BatchPop* P,
+                                                   const BatchStep* S,
+                                                   const int64_t* R,
+                                                   float* feat) {
+  __shared__ double red[256];
+  __shared__ int mn[256];
+  const int p = blockIdx.x;
+  const BatchPop& q = P[p];
+  const int N = q.L * q.L;
+  const double Rd = (double)R[p];
+  auto level = [&](int i) { return (double)(-2 * N + (i << q.shift)); };
+  auto block_sum = [&](double v) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+      if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+      __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+  };
+  double s1 = 0.0;
+  int imin = q.nbins;
+  for (int i = threadIdx.x; i < q.nbins; i += 256) {
+    const uint32_t h = q.hist[i];
+    if (h) {
+      s1 += (double)h * level(i);
+      imin = min(imin, i);
+    }
+  }
+  mn[threadIdx.x] = imin;
+  const double mean = block_sum(s1) / Rd;
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off)
+      mn[threadIdx.x] = min(mn[threadIdx.x], mn[threadIdx.x + off]);
+    __syncthreads();
+  }
+  const int i0 = mn[0];
+  double s2 = 0.0, s3 = 0.0;
+  for (int i = threadIdx.x; i < q.nbins; i += 256) {
+    const uint32_t h = q.hist[i];
+    if (h) {
+      const double d = level(i) - mean;
+      s2 += (double)h * d * d;
+      s3 += (double)h * d * d * d;
+    }
+  }
+  const double var = block_sum(s2) / Rd;
+  const double m3 = block_sum(s3) / Rd;
+  if (threadIdx.x == 0) {
+    const double sd = sqrt(var > 1e-3 ? var : 1e-3);
+    float* f = feat + (size_t)p * kFeatures;
+    f[0] = (float)(mean / N);
+    f[1] = (float)log(sd);
+    f[2] = (float)(var > 0.0 ? m3 / (var * sqrt(var)) : 0.0);
+    f[3] = (float)((level(i0) - mean) / sd);
+    f[4] = (float)S[p].beta;
+    f[5] = (float)log((double)N);
+    f[6] = (float)log(Rd);
+    f[7] = (float)S[p].target;
+  }
+}
+
+// log dbeta proposals of the network (de-standardised) next to the features.
+__global__ void k_bpred(const float* z, float* pred, int n, float mu_y,
+                        float sigma_y) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) pred[p] = mu_y + sigma_y * z[p];
+}
+
+template <int W>
+__device__ __forceinline__ void dispatch_pass(const LatticeArgs& a,
+                                              const BatchPop& q,
+                                              int64_t wave) {
+  const int key = (q.rpl == 1 ? 0 : q.rpl == 2 ? 1 : 2) * 4 + q.int8 * 2 +
+                  q.glass;
+  switch (key) {
+    case 0: if constexpr (W <= 2) lattice_pass<W, 1, false, false>(a, wave); break;
+    case 1: if constexpr (W <= 2) lattice_pass<W, 1, false, true>(a, wave); break;
+    case 2: if constexpr (W <= 2) lattice_pass<W, 1, true, false>(a, wave); break;
+    case 3: if constexpr (W <= 2) lattice_pass<W, 1, true, true>(a, wave); break;
+    case 4: lattice_pass<W, 2, false, false>(a, wave); break;
+    case 5: lattice_pass<W, 2, false, true>(a, wave); break;
+    case 6: lattice_pass<W, 2, true, false>(a, wave); break;
+    case 7: lattice_pass<W, 2, true, true>(a, wave); break;
+    case 8: lattice_pass<W, 4, false, false>(a, wave); break;
+    case 9: lattice_pass<W, 4, false, true>(a, wave); break;
+    case 10: lattice_pass<W, 4, true, false>(a, wave); break;
+    case 11: lattice_pass<W, 4, true, true>(a, wave); break;
+    default: break;
+  }
+}
+
+// Persistent sweep kernel of one row-width class W: every wave pulls work
+// items (population, wave of replicas) from the class queue until the queue
+// is exhausted; every wave reaches the exit once the counter passes the
+// total, which k_bcommit fixed before the launch.
+template <int W>
+__global__ __launch_bounds__(256) void k_bsweep(
+    const BatchPop* P, const BatchStep* S, const int64_t* R,
+    const int32_t* cur, const int32_t* order, const int64_t* prefix,
+    unsigned long long* queue, int first, int count, uint32_t one) {
+  const int lane = threadIdx.x & 63;
+  const int64_t* pre = prefix + first + W;
+  const int64_t total = pre[count];
+  while (true) {
+    int it = 0;
+    if (lane == 0) it = (int)atomicAdd(&queue[W], 1ull);
+    const int64_t item = (int64_t)__shfl(it, 0, 64);
+    if (item >= total) break;
+    int lo = 0, hi = count - 1;  // last i with pre[i] <= item
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (pre[mid] <= item) lo = mid;
+      else hi = mid - 1;
+    }
+    const int p = order[first + lo];
+    const BatchPop& q = P[p];
+    const BatchStep& st = S[p];
+    const int c = cur[p];
+    LatticeArgs a;
+    a.spins = q.spins[c];
+    a.E = q.E[c];
+    a.M = q.M[c];
+    a.jbits = q.jbits;
+    a.R = R[p];
+    a.stride = q.stride;
+    a.L = q.L;
+    a.lpr = q.lpr;
+    a.rpw = q.rpw;
+    a.K4 = st.K4;
+    a.K8 = st.K8;
+    a.one = one;
+    a.k0 = q.k0;
+    a.k1 = q.k1;
+    a.pop = q.pop;
+    a.step = st.step;
+    a.t0 = 0;
+    a.theta = st.theta;
+    a.init = 0;
+    dispatch_pass<W>(a, q, item - pre[lo]);
+  }
+}
+
+}  // namespace pa
+
+using namespace pa;
+
+// ================================================================= host
+
+namespace {
+
+struct PopHost {
+  BatchPop d;        // the device description (pointers into the arenas)
+  int64_t R_t = 0;
+  int N = 0, model = 0;
+  double beta = 0.0, lnZ = 0.0, lnQ_last = 0.0;
+  int step = 0;
+  size_t rb_hist = 0;  // offset of the histogram in the readback block
+  int moved = 0;       // the population moved in the previous step
+  size_t up_tab = 0;   // offset of the tables in the upload block
+};
+
+struct TuneKey {
+  int L, layout, model;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(L, layout, model) < std::tie(o.L, o.layout, o.model);
+  }
+};
+std::map<TuneKey, int>& tune_cache() {
+  static std::map<TuneKey, int> m;
+  return m;
+}
+
+}  // namespace
+
+struct pa_batch {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int n = 0;
+  std::vector<PopHost> pops;
+  BatchPop* d_pops = nullptr;
+  // readback block: R[n] | flags[4] (sticky) | mom[2n] | features[n][8]
+  // | predictions[n] | histograms
+  uint8_t* d_rb = nullptr;
+  uint8_t* h_rb = nullptr;
+  size_t rb_bytes = 0, rb_clear_off = 0;
+  size_t off_flags = 0, off_mom = 0, off_feat = 0, off_pred = 0;
+  // upload block: BatchStep[n] | tables
+  uint8_t* d_up = nullptr;
+  uint8_t* h_up = nullptr;
+  size_t up_bytes = 0;
+  // device control
+  int64_t* d_Rnew = nullptr;
+  int32_t* d_cur = nullptr;
+  int32_t* d_order = nullptr;
+  int32_t* d_cls_first = nullptr;
+  int32_t* d_cls_count = nullptr;
+  int64_t* d_prefix = nullptr;
+  unsigned long long* d_queue = nullptr;
+  std::vector<void*> allocs;
+  int cls_first[5] = {0}, cls_count[5] = {0};
+  int64_t max_cap = 0;
+  int lds_bins = 0;
+  int sweep_blocks = 2048;
+  // temperature-step network (learned mode) and its acceptance tolerance
+  pa_mlp* mlp = nullptr;
+  pa_mlp* graph_mlp = nullptr;  // the network the graph was built with
+  double tol = 0.02;
+  // schedule
+  int mode = 0;                 // 0 explicit schedule, 1 bisection, 2 learned
+  std::vector<double> sched;    // [steps][n]
+  int sched_steps = 0, pos = 0;
+  double beta_f = 0.0, target = 0.0;
+  int theta = 0;
+  int adaptive_max_steps = 0;
+  // trajectory of observables after each step's sweeps
+  std::vector<pa_obs> traj;
+  std::vector<double> traj_lnZ;
+  // per step and population: the features, the step taken and its source
+  std::vector<float> dec_feat;
+  std::vector<double> dec_dbeta;
+  std::vector<int32_t> dec_src;
+  int64_t src_count[5] = {0, 0, 0, 0, 0};
+  int64_t overlap_evals = 0;  // exact overlap evaluations by the host
+  double host_ms = 0.0;       // time spent in the host function
+  int record = 0;
+  // graphs of the kernels before and after the host function
+  hipGraph_t graph = nullptr, graph2 = nullptr;
+  hipGraphExec_t exec = nullptr, exec2 = nullptr;
+  int host_err = 0;
+  int64_t attempts = 0;
+};
+
+namespace {
+
+int64_t* rb_R(pa_batch* b) { return reinterpret_cast<int64_t*>(b->h_rb); }
+unsigned long long* rb_flags(pa_batch* b) {
+  return reinterpret_cast<unsigned long long*>(b->h_rb + b->off_flags);
+}
+unsigned long long* rb_mom(pa_batch* b) {
+  return reinterpret_cast<unsigned long long*>(b->h_rb + b->off_mom);
+}
+const float* rb_feat(pa_batch* b) {
+  return reinterpret_cast<const float*>(b->h_rb + b->off_feat);
+}
+const float* rb_pred(pa_batch* b) {
+  return reinterpret_cast<const float*>(b->h_rb + b->off_pred);
+}
+BatchStep* up_steps(pa_batch* b) {
+  return reinterpret_cast<BatchStep*>(b->h_up);
+}
+
+// The host part of one step, between the two kernel sequences:
+// observables of every population after the previous sweeps, the next beta
+// of every population, its tables and Metropolis thresholds.
+void host_step(void* ud) {
+  pa_batch* b = static_cast<pa_batch*>(ud);
+  const auto t0 = std::chrono::steady_clock::now();
+  const int64_t* R = rb_R(b);
+  const unsigned long long* mom = rb_mom(b);
+  BatchStep* st = up_steps(b);
+  const bool last = (b->mode == 0) ? (b->pos >= b->sched_steps)
+                                   : (b->pos >= b->adaptive_max_steps);
+  for (int p = 0; p < b->n; ++p) {
+    PopHost& q = b->pops[p];
+    const uint32_t* h = reinterpret_cast<const uint32_t*>(b->h_rb + q.rb_hist);
+    if (b->record && q.moved) {
+      pa_obs o;
+      observables_from_hist(h, q.d.nbins, q.d.shift, q.N, R[p], q.beta,
+                            (int64_t)mom[2 * p], (int64_t)mom[2 * p + 1], &o);
+      const size_t at = (size_t)(b->pos - 1) * b->n + p;
+      if (at < b->traj.size()) {
+        b->traj[at] = o;
+        b->traj_lnZ[at] = q.lnZ;
+      }
+    }
+    BatchStep& s = st[p];
+    s.active = 0;
+    s.beta = q.beta;
+    s.target = b->target;
+    q.moved = 0;
+    if (last) continue;
+    double beta_next;
+    int src = 0;
+    if (b->mode == 0) {
+      beta_next = b->sched[(size_t)b->pos * b->n + p];
+    } else {
+      if (!(q.beta < b->beta_f)) continue;
+      const double span = b->beta_f - q.beta;
+      double d = -1.0;
+      int ev = 1;
+      // the remaining interval whenever it qualifies
+      if (overlap_from_hist(h, q.d.nbins, q.d.shift, q.N, R[p], span) >=
+          b->target) {
+        d = span;
+        src = 4;
+      } else if (b->mode == 2) {
+        // the network's proposal, kept if its exact overlap is within tol
+        const double prop = std::exp((double)rb_pred(b)[p]);
+        if (prop > 0.0 && prop < span) {
+          ++ev;
+          const double a =
+              overlap_from_hist(h, q.d.nbins, q.d.shift, q.N, R[p], prop);
+          if (std::fabs(a - b->target) <= b->tol) {
+            d = prop;
+            src = 2;
+          }
+        }
+        if (d < 0.0) src = 3;  // fallback
+      } else {
+        src = 1;
+      }
+      if (d < 0.0)
+        d = bisect_from_hist(h, q.d.nbins, q.d.shift, q.N, R[p], b->target,
+                             span, &ev);
+      b->overlap_evals += ev;
+      beta_next = (d == span) ? b->beta_f : q.beta + d;
+      if (!(beta_next > q.beta)) beta_next = b->beta_f;  // no progress
+    }
+    if (!(beta_next >= q.beta) || q.step + 1 > 65535) {
+      b->host_err = PA_EINVAL;
+      continue;
+    }
+    uint32_t* f = reinterpret_cast<uint32_t*>(b->h_up + q.up_tab);
+    TableRange tr;
+    if (build_tables(h, q.d.nbins, q.d.shift, q.N, R[p], q.R_t,
+                     beta_next - q.beta, f, f + q.d.nbins, &tr) != PA_OK) {
+      b->host_err = PA_ESTATE;
+      continue;
+    }
+    {
+      const size_t at = (size_t)b->pos * b->n + p;
+      if (at < b->dec_src.size()) {
+        std::memcpy(&b->dec_feat[at * kFeatures], rb_feat(b) + (size_t)p * kFeatures,
+                    sizeof(float) * kFeatures);
+        b->dec_dbeta[at] = beta_next - q.beta;
+        b->dec_src[at] = src;
+      }
+      b->src_count[src] += 1;
+    }
+    metropolis_K(beta_next, &s.K4, &s.K8);
+    s.lvl0 = tr.lo;
+    s.nlvl = tr.hi - tr.lo + 1;
+    s.step = (uint32_t)(q.step + 1);
+    s.theta = b->theta;
+    s.active = 1;
+    q.lnQ_last = tr.lnQ;
+    q.lnZ = q.lnZ + tr.lnQ;  // Eq. Free-En, read with the logarithm
+    q.beta = beta_next;
+    q.step += 1;
+    q.moved = 1;
+    s.beta = beta_next;
+  }
+  b->pos += 1;
+  b->host_ms += std::chrono::duration<double, std::milli>(
+                    std::chrono::steady_clock::now() - t0).count();
+}
+
+#define BK(x) PA_HIP(x)
+
+// Kernels of one step before the host function.
+int enqueue_front(pa_batch* b) {
+  hipStream_t st = b->stream;
+  const size_t clear = b->rb_bytes - b->rb_clear_off;
+  BK(launch_fill_u32(reinterpret_cast<uint32_t*>(b->d_rb + b->rb_clear_off),
+                     (int64_t)(clear / 4), 0u, st));
+  const int64_t* dR = reinterpret_cast<const int64_t*>(b->d_rb);
+  unsigned long long* dflags =
+      reinterpret_cast<unsigned long long*>(b->d_rb + b->off_flags);
+  unsigned long long* dmom =
+      reinterpret_cast<unsigned long long*>(b->d_rb + b->off_mom);
+  float* dfeat = reinterpret_cast<float*>(b->d_rb + b->off_feat);
+  const unsigned gx = (unsigned)((b->max_cap + 2047) / 2048);
+  hipLaunchKernelGGL(k_bhist, dim3(gx * (unsigned)b->n), dim3(256),
+                     (size_t)b->lds_bins * 4, st, b->d_pops, dR, b->d_cur,
+                     dmom, dflags, b->lds_bins, (int)gx);
+  BK(hipGetLastError());
+  hipLaunchKernelGGL(k_bfeatures, dim3(b->n), dim3(256), 0, st, b->d_pops,
+                     reinterpret_cast<const BatchStep*>(b->d_up), dR, dfeat);
+  BK(hipGetLastError());
+  if (b->mlp) {
+    const int rc = mlp_infer_on(b->mlp, dfeat, b->n, st);
+    if (rc) return rc;
+    float mu_y, sig_y;
+    mlp_out_scale(b->mlp, &mu_y, &sig_y);
+    hipLaunchKernelGGL(k_bpred, dim3((b->n + 255) / 256), dim3(256), 0, st,
+                       mlp_output_dev(b->mlp),
+                       reinterpret_cast<float*>(b->d_rb + b->off_pred), b->n,
+                       mu_y, sig_y);
+    BK(hipGetLastError());
+  }
+  return PA_OK;
+}
+
+// Kernels of one step after the host function.
+int enqueue_back(pa_batch* b) {
+  hipStream_t st = b->stream;
+  int64_t* dR = reinterpret_cast<int64_t*>(b->d_rb);
+  unsigned long long* dflags =
+      reinterpret_cast<unsigned long long*>(b->d_rb + b->off_flags);
+  const BatchStep* dS = reinterpret_cast<const BatchStep*>(b->d_up);
+  const unsigned tiles = (unsigned)((b->max_cap + 255) / 256);
+  hipLaunchKernelGGL(k_bcounts, dim3(tiles, b->n), dim3(256), 0, st, b->d_pops,
+                     dS, dR, b->d_cur);
+  BK(hipGetLastError());
+  hipLaunchKernelGGL(k_bscan, dim3(b->n), dim3(1024), 0, st, b->d_pops, dS, dR,
+                     b->d_Rnew, dflags);
+  BK(hipGetLastError());
+  hipLaunchKernelGGL(k_bscatter, dim3(tiles, b->n), dim3(256), 0, st,
+                     b->d_pops, dS, dR);
+  BK(hipGetLastError());
+  hipLaunchKernelGGL(k_bgather, dim3(256, b->n), dim3(256), 0, st, b->d_pops,
+                     dS, b->d_Rnew, b->d_cur);
+  BK(hipGetLastError());
+  hipLaunchKernelGGL(k_bcommit, dim3(1), dim3(256), 0, st, b->d_pops, dS, dR,
+                     b->d_Rnew, b->d_cur, b->d_order, b->n, b->d_cls_first,
+                     b->d_cls_count, b->d_prefix, b->d_queue, 1);
+  BK(hipGetLastError());
+  for (int w = 1; w <= 4; ++w) {
+    if (b->cls_count[w] == 0) continue;
+    const int first = b->cls_first[w], count = b->cls_count[w];
+    switch (w) {
+      case 1: hipLaunchKernelGGL(k_bsweep<1>, dim3(b->sweep_blocks), dim3(256), 0, st, b->d_pops, dS, dR, b->d_cur, b->d_order, b->d_prefix, b->d_queue, first, count, 1u); break;
+      case 2: hipLaunchKernelGGL(k_bsweep<2>, dim3(b->sweep_blocks), dim3(256), 0, st, b->d_pops, dS, dR, b->d_cur, b->d_order, b->d_prefix, b->d_queue, first, count, 1u); break;
+      case 3: hipLaunchKernelGGL(k_bsweep<3>, dim3(b->sweep_blocks), dim3(256), 0, st, b->d_pops, dS, dR, b->d_cur, b->d_order, b->d_prefix, b->d_queue, first, count, 1u); break;
+      case 4: hipLaunchKernelGGL(k_bsweep<4>, dim3(b->sweep_blocks), dim3(256), 0, st, b->d_pops, dS, dR, b->d_cur, b->d_order, b->d_prefix, b->d_queue, first, count, 1u); break;
+    }
+    BK(hipGetLastError());
+  }
+  return PA_OK;
+}
+
+int check_flags(pa_batch* b) {
+  const unsigned long long* fl = rb_flags(b);
+  if (b->host_err) return b->host_err;
+  if (fl[0]) return PA_EDEVICE;
+  if (fl[1] & 1ull) return PA_ECAPACITY;
+  if (fl[1] & 2ull) return PA_EEMPTY;
+  return PA_OK;
+}
+
+// The host part of a step between the two kernel sequences: all
+// histograms down, synchronise, the host function, all tables up.  The
+// copies and the host function stay outside the graphs.
+int host_between(pa_batch* b) {
+  BK(hipMemcpyAsync(b->h_rb, b->d_rb, b->rb_bytes, hipMemcpyDeviceToHost,
+                    b->stream));
+  BK(hipStreamSynchronize(b->stream));
+  const int rc = check_flags(b);
+  if (rc) return rc;
+  host_step(b);
+  if (b->host_err) return b->host_err;
+  BK(hipMemcpyAsync(b->d_up, b->h_up, b->up_bytes, hipMemcpyHostToDevice,
+                    b->stream));
+  return PA_OK;
+}
+
+// One step with individual launches.
+int step_eager(pa_batch* b) {
+  int rc = enqueue_front(b);
+  if (!rc) rc = host_between(b);
+  if (!rc) rc = enqueue_back(b);
+  return rc;
+}
+
+// Captures a kernel sequence as a graph (kernel nodes only: clearing uses a
+// fill kernel, and no copy or host callback is recorded).
+int capture(pa_batch* b, int (*enqueue)(pa_batch*), hipGraphExec_t* out,
+            hipGraph_t* g_out) {
+  BK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed));
+  const int rc = enqueue(b);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(b->stream, &g);
+  if (rc != PA_OK || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    if (e != hipSuccess) set_last_error("hipStreamEndCapture", e, __LINE__);
+    return rc ? rc : PA_EDEVICE;
+  }
+  hipGraphExec_t x = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (ei != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    set_last_error("hipGraphInstantiate", ei, __LINE__);
+    return PA_EDEVICE;
+  }
+  *out = x;
+  *g_out = g;
+  return PA_OK;
+}
+
+void drop_graph(pa_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->exec2) (void)hipGraphExecDestroy(b->exec2);
+  if (b->graph2) (void)hipGraphDestroy(b->graph2);
+  b->exec = b->exec2 = nullptr;
+  b->graph = b->graph2 = nullptr;
+}
+
+int build_graph(pa_batch* b) {
+  if (b->exec && b->exec2 && b->graph_mlp == b->mlp) return PA_OK;
+  drop_graph(b);
+  b->graph_mlp = b->mlp;
+  int rc = capture(b, enqueue_front, &b->exec, &b->graph);
+  if (rc == PA_OK) rc = capture(b, enqueue_back, &b->exec2, &b->graph2);
+  if (rc != PA_OK) drop_graph(b);
+  return rc;
+}
+
+// One step with the two captured kernel sequences.
+int step_graph(pa_batch* b) {
+  BK(hipGraphLaunch(b->exec, b->stream));
+  const int rc = host_between(b);
+  if (rc) return rc;
+  BK(hipGraphLaunch(b->exec2, b->stream));
+  return PA_OK;
+}
+
+void free_batch(pa_batch* b) {
+  drop_graph(b);
+  for (void* p : b->allocs) (void)hipFree(p);
+  if (b->h_rb) (void)hipHostFree(b->h_rb);
+  if (b->h_up) (void)hipHostFree(b->h_up);
+  if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+}
+
+template <typename T>
+bool balloc(pa_batch* b, T** p, size_t bytes) {
+  void* q = nullptr;
+  if (hipMalloc(&q, bytes ? bytes : 16) != hipSuccess) return false;
+  b->allocs.push_back(q);
+  *p = static_cast<T*>(q);
+  return true;
+}
+
+int64_t round_up16(int64_t v) { return (v + 15) / 16 * 16; }
+
+}  // namespace
+
+// =================================================================== ABI
+
+extern "C" {
+
+int pa_tune_rows_per_lane(int32_t L, int32_t layout, int32_t model,
+                          int64_t R, int32_t theta, void* stream,
+                          int32_t* best, float* ms) {
+  if (!best || L < 4 || L > 128 || (L & 1) || R < 1 || theta < 1)
+    return PA_EINVAL;
+  const int cand[3] = {1, 2, 4};
+  float t[3] = {-1.f, -1.f, -1.f};
+  std::vector<int8_t> J;
+  if (model == PA_PMJ) {
+    J.assign((size_t)2 * L * L, 1);
+    for (size_t i = 0; i < J.size(); i += 3) J[i] = -1;
+  }
+  int bi = -1;
+  for (int k = 0; k < 3; ++k) {
+    const int rpl = cand[k];
+    if (L % rpl || L / rpl > 64 || ((L + 31) / 32 >= 3 && rpl < 2)) continue;
+    pa_config cfg{};
+    cfg.L = L;
+    cfg.model = model;
+    cfg.J = J.empty() ? nullptr : J.data();
+    cfg.R_target = R;
+    cfg.layout = layout;
+    cfg.rows_per_lane = rpl;
+    cfg.seed = 12345;
+    cfg.stream = stream;
+    pa_ctx* c = nullptr;
+    int rc = pa_init(&cfg, &c);
+    if (rc) return rc;
+    rc = pa_resample(c, 0.4, nullptr);
+    if (!rc) rc = pa_sweep(c, 0.4, 1);  // warm-up
+    if (!rc) rc = pa_set_timing(c, 1);
+    if (!rc) rc = pa_sweep(c, 0.4, theta);
+    if (!rc) rc = pa_sweep(c, 0.4, theta);
+    pa_timing tm{};
+    if (!rc) rc = pa_get_timing(c, &tm);
+    pa_destroy(c);
+    if (rc) return rc;
+    t[k] = (float)(tm.ms[PA_K_SWEEP] / 2.0);
+    if (bi < 0 || t[k] < t[bi]) bi = k;
+  }
+  if (bi < 0) return PA_EINVAL;
+  *best = cand[bi];
+  if (ms)
+    for (int k = 0; k < 3; ++k) ms[k] = t[k];
+  return PA_OK;
+}
+
+int pa_batch_init(const pa_config* cfgs, int32_t n, void* stream,
+                  int32_t flags, pa_batch** out) {
+  if (!out) return PA_EINVAL;
+  *out = nullptr;
+  if (!cfgs || n < 1 || n > 4096) return PA_EINVAL;
+  for (int p = 0; p < n; ++p) {
+    const pa_config& c = cfgs[p];
+    if (c.L < 4 || c.L > 128 || (c.L & 1)) return PA_EINVAL;
+    if (c.model != PA_FERRO && c.model != PA_PMJ) return PA_EINVAL;
+    if (c.model == PA_PMJ && !c.J) return PA_EINVAL;
+    if (c.layout != PA_INT8 && c.layout != PA_BITS) return PA_EINVAL;
+    if (c.R_target < 1 || c.R_target >= (1ll << 31)) return PA_EINVAL;
+    const int rpl = c.rows_per_lane;
+    if (rpl != 0 && rpl != 1 && rpl != 2 && rpl != 4) return PA_EINVAL;
+    if (rpl && (c.L % rpl || c.L / rpl > 64 || ((c.L + 31) / 32 >= 3 && rpl < 2)))
+      return PA_EINVAL;
+    if (c.model == PA_PMJ)
+      for (int64_t i = 0; i < 2ll * c.L * c.L; ++i)
+        if (c.J[i] != 1 && c.J[i] != -1) return PA_EINVAL;
+  }
+  pa_batch* b = new (std::nothrow) pa_batch();
+  if (!b) return PA_ENOMEM;
+  if (hipGetDevice(&b->device) != hipSuccess) {
+    delete b;
+    return PA_EDEVICE;
+  }
+  b->stream = reinterpret_cast<hipStream_t>(stream);
+  if (!b->stream) {  // graph capture needs a stream other than the null one
+    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete b;
+      return PA_EDEVICE;
+    }
+    b->own_stream = true;
+  }
+  b->n = n;
+  b->pops.resize(n);
+  // layout of the readback and upload blocks
+  b->off_flags = (size_t)8 * n;
+  b->off_mom = b->off_flags + 32;
+  b->off_feat = b->off_mom + (size_t)16 * n;
+  b->off_pred = b->off_feat + (size_t)4 * kFeatures * n;
+  size_t rb = (size_t)round_up16((int64_t)(b->off_pred + (size_t)4 * n));
+  b->rb_clear_off = b->off_mom;  // moments, features and histograms
+  size_t up = round_up16((int64_t)sizeof(BatchStep) * n);
+  int max_bins = 0;
+  for (int p = 0; p < n; ++p) {
+    const pa_config& c = cfgs[p];
+    PopHost& q = b->pops[p];
+    BatchPop& d = q.d;
+    int rpl = c.rows_per_lane;
+    if (rpl == 0 && (flags & 1)) {
+      const TuneKey key{c.L, c.layout, c.model};
+      auto it = tune_cache().find(key);
+      if (it != tune_cache().end()) {
+        rpl = it->second;
+      } else {
+        int32_t best = 0;
+        const int rc = pa_tune_rows_per_lane(c.L, c.layout, c.model, 4096, 4,
+                                             b->stream, &best, nullptr);
+        if (rc) {
+          free_batch(b);
+          delete b;
+          return rc;
+        }
+        tune_cache()[key] = best;
+        rpl = best;
+      }
+    }
+    if (rpl == 0) rpl = (c.L > 64) ? 2 : 1;
+    d.L = c.L;
+    d.W = (c.L + 31) / 32;
+    d.rpl = rpl;
+    d.lpr = c.L / rpl;
+    d.rpw = 64 / d.lpr;
+    d.shift = (c.model == PA_FERRO) ? 2 : 1;
+    d.nbins = ((4 * c.L * c.L) >> d.shift) + 1;
+    d.glass = c.model == PA_PMJ;
+    d.int8 = c.layout == PA_INT8;
+    d.stride = d.int8 ? round_up16((int64_t)c.L * c.L)
+                      : round_up16((int64_t)c.L * d.W * 4);
+    d.chunks = (int32_t)(d.stride / 16);
+    int lg = 0;
+    while ((1 << lg) < d.chunks && lg < 6) ++lg;
+    d.lpr_log2 = lg;
+    d.cap = c.capacity ? c.capacity
+                       : c.R_target +
+                             16 * (int64_t)std::ceil(std::sqrt((double)c.R_target)) +
+                             1024;
+    d.k0 = (uint32_t)(c.seed & 0xFFFFFFFFu);
+    d.k1 = (uint32_t)(c.seed >> 32);
+    d.pop = c.population_id;
+    q.R_t = c.R_target;
+    q.N = c.L * c.L;
+    q.model = c.model;
+    q.lnZ = (double)q.N * std::log(2.0);
+    q.rb_hist = rb;
+    rb += (size_t)d.nbins * 4;
+    q.up_tab = up;
+    up += (size_t)d.nbins * 8;
+    max_bins = std::max(max_bins, d.nbins);
+    b->max_cap = std::max(b->max_cap, d.cap);
+    if (d.cap < c.R_target || d.cap >= (1ll << 32)) {
+      free_batch(b);
+      delete b;
+      return PA_EINVAL;
+    }
+  }
+  b->rb_bytes = (size_t)round_up16((int64_t)rb);
+  b->up_bytes = (size_t)round_up16((int64_t)up);
+  b->lds_bins = std::min(max_bins, 16384);
+  bool ok = true;
+  ok = ok && balloc(b, &b->d_rb, b->rb_bytes);
+  ok = ok && balloc(b, &b->d_up, b->up_bytes);
+  ok = ok && hipHostMalloc(reinterpret_cast<void**>(&b->h_rb), b->rb_bytes) == hipSuccess;
+  ok = ok && hipHostMalloc(reinterpret_cast<void**>(&b->h_up), b->up_bytes) == hipSuccess;
+  ok = ok && balloc(b, &b->d_Rnew, (size_t)8 * n);
+  ok = ok && balloc(b, &b->d_cur, (size_t)4 * n);
+  ok = ok && balloc(b, &b->d_order, (size_t)4 * n);
+  ok = ok && balloc(b, &b->d_cls_first, 4 * 5);
+  ok = ok && balloc(b, &b->d_cls_count, 4 * 5);
+  ok = ok && balloc(b, &b->d_prefix, (size_t)8 * (n + 5));
+  ok = ok && balloc(b, &b->d_queue, 8 * 5);
+  ok = ok && balloc(b, &b->d_pops, sizeof(BatchPop) * n);
+  for (int p = 0; p < n && ok; ++p) {
+    BatchPop& d = b->pops[p].d;
+    const size_t cap = (size_t)d.cap;
+    for (int k = 0; k < 2 && ok; ++k) {
+      ok = ok && balloc(b, &d.spins[k], cap * (size_t)d.stride);
+      ok = ok && balloc(b, &d.E[k], cap * 4);
+      ok = ok && balloc(b, &d.M[k], cap * 4);
+    }
+    ok = ok && balloc(b, &d.n, cap * 4);
+    ok = ok && balloc(b, &d.parent, cap * 4);
+    ok = ok && balloc(b, &d.tile_sum, (cap / 256 + 2) * 4);
+    ok = ok && balloc(b, &d.tile_off, (cap / 256 + 2) * 4);
+    d.hist = reinterpret_cast<uint32_t*>(b->d_rb + b->pops[p].rb_hist);
+    d.tab = reinterpret_cast<uint32_t*>(b->d_up + b->pops[p].up_tab);
+    if (cfgs[p].model == PA_PMJ) {
+      uint32_t* jb = nullptr;
+      ok = ok && balloc(b, &jb, (size_t)2 * d.L * d.W * 4);
+      d.jbits = jb;
+    }
+  }
+  if (!ok) {
+    free_batch(b);
+    delete b;
+    return PA_ENOMEM;
+  }
+  // population order: by row-width class, then by L descending
+  std::vector<int32_t> order(n);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+    const BatchPop &x = b->pops[a].d, &y = b->pops[c].d;
+    if (x.W != y.W) return x.W < y.W;
+    return x.L > y.L;
+  });
+  int cf[5] = {0}, cc[5] = {0};
+  for (int i = n - 1; i >= 0; --i) cf[b->pops[order[i]].d.W] = i;
+  for (int i = 0; i < n; ++i) cc[b->pops[order[i]].d.W] += 1;
+  for (int w = 0; w < 5; ++w) {
+    b->cls_first[w] = cc[w] ? cf[w] : 0;
+    b->cls_count[w] = cc[w];
+  }
+  int rc = PA_OK;
+  std::vector<BatchPop> dp(n);
+  for (int p = 0; p < n; ++p) dp[p] = b->pops[p].d;
+  std::vector<int32_t> cur0(n, 0);
+  if (hipMemcpy(b->d_pops, dp.data(), sizeof(BatchPop) * n, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->d_order, order.data(), 4 * n, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->d_cls_first, b->cls_first, 4 * 5, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->d_cls_count, b->cls_count, 4 * 5, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->d_cur, cur0.data(), 4 * n, hipMemcpyHostToDevice) != hipSuccess)
+    rc = PA_EDEVICE;
+  // couplings and the initial populations (the INIT stream of each)
+  std::memset(b->h_rb, 0, b->rb_bytes);
+  std::memset(b->h_up, 0, b->up_bytes);
+  if (rc == PA_OK && hipMemcpy(b->d_up, b->h_up, b->up_bytes,
+                               hipMemcpyHostToDevice) != hipSuccess)
+    rc = PA_EDEVICE;
+  for (int p = 0; p < n && rc == PA_OK; ++p) {
+    const pa_config& c = cfgs[p];
+    BatchPop& d = b->pops[p].d;
+    rb_R(b)[p] = c.R_target;
+    if (c.model == PA_PMJ) {
+      std::vector<uint32_t> jb((size_t)2 * d.L * d.W, 0u);
+      for (int k = 0; k < 2; ++k)
+        for (int y = 0; y < d.L; ++y)
+          for (int x = 0; x < d.L; ++x)
+            if (c.J[(size_t)k * d.L * d.L + (size_t)y * d.L + x] < 0)
+              jb[((size_t)k * d.L + y) * d.W + x / 32] |= 1u << (x % 32);
+      if (hipMemcpy(const_cast<uint32_t*>(d.jbits), jb.data(), jb.size() * 4,
+                    hipMemcpyHostToDevice) != hipSuccess)
+        rc = PA_EDEVICE;
+    }
+    LatticeArgs a{};
+    a.spins = d.spins[0];
+    a.E = d.E[0];
+    a.M = d.M[0];
+    a.jbits = d.jbits;
+    a.R = c.R_target;
+    a.stride = d.stride;
+    a.L = d.L;
+    a.lpr = d.lpr;
+    a.rpw = d.rpw;
+    a.k0 = d.k0;
+    a.k1 = d.k1;
+    a.pop = d.pop;
+    a.one = 1u;
+    a.init = 1;
+    if (rc == PA_OK && launch_lattice(a, d.W, d.rpl, d.int8, d.glass,
+                                      b->stream) != hipSuccess)
+      rc = PA_EDEVICE;
+  }
+  // the whole readback block: sizes, zeroed sticky error flags, moments
+  if (rc == PA_OK &&
+      hipMemcpyAsync(b->d_rb, b->h_rb, b->rb_bytes, hipMemcpyHostToDevice,
+                     b->stream) != hipSuccess)
+    rc = PA_EDEVICE;
+  if (rc == PA_OK && hipStreamSynchronize(b->stream) != hipSuccess)
+    rc = PA_EDEVICE;
+  if (rc != PA_OK) {
+    free_batch(b);
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return PA_OK;
+}
+
+void pa_batch_destroy(pa_batch* b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->stream);
+  free_batch(b);
+  delete b;
+}
+
+static int batch_run(pa_batch* b, int steps, int use_graph) {
+  b->host_err = 0;
+  b->pos = 0;
+  const int total = steps + 1;  // the extra pass only measures
+  b->record = 1;
+  b->traj.assign((size_t)steps * b->n, pa_obs{});
+  b->traj_lnZ.assign((size_t)steps * b->n, 0.0);
+  b->dec_feat.assign((size_t)steps * b->n * kFeatures, 0.0f);
+  b->dec_dbeta.assign((size_t)steps * b->n, 0.0);
+  b->dec_src.assign((size_t)steps * b->n, -1);
+  for (auto& c : b->src_count) c = 0;
+  b->overlap_evals = 0;
+  b->host_ms = 0.0;
+  if (b->mlp) {
+    const int rc = mlp_prepare(b->mlp, b->n);
+    if (rc) return rc;
+  }
+  // current beta and target of every population for the first summaries
+  BK(hipStreamSynchronize(b->stream));
+  BatchStep* st = up_steps(b);
+  for (int p = 0; p < b->n; ++p) {
+    st[p].beta = b->pops[p].beta;
+    st[p].target = b->target;
+    st[p].active = 0;
+  }
+  BK(hipMemcpyAsync(b->d_up, b->h_up, sizeof(BatchStep) * b->n,
+                    hipMemcpyHostToDevice, b->stream));
+  if (use_graph) {
+    const int rc = build_graph(b);
+    if (rc) return rc;
+  }
+  for (int i = 0; i < total; ++i) {
+    const int rc = use_graph ? step_graph(b) : step_eager(b);
+    if (rc) return rc;
+  }
+  BK(hipStreamSynchronize(b->stream));
+  return check_flags(b);
+}
+
+int pa_batch_run(pa_batch* b, int32_t steps, const double* betas,
+                 int32_t theta, int32_t use_graph) {
+  if (!b || steps < 1 || !betas || theta < 0) return PA_EINVAL;
+  for (int64_t i = 0; i < (int64_t)steps * b->n; ++i)
+    if (!std::isfinite(betas[i])) return PA_EINVAL;
+  b->mode = 0;
+  b->mlp = nullptr;
+  b->sched.assign(betas, betas + (size_t)steps * b->n);
+  b->sched_steps = steps;
+  b->theta = theta;
+  return batch_run(b, steps, use_graph);
+}
+
+int pa_batch_run_adaptive(pa_batch* b, double target, double beta_f,
+                          int32_t max_steps, int32_t theta, int32_t use_graph,
+                          int32_t* steps_taken) {
+  if (!b || !(target > 0.0 && target <= 1.0) || !std::isfinite(beta_f) ||
+      max_steps < 1 || theta < 0)
+    return PA_EINVAL;
+  b->mode = 1;
+  b->mlp = nullptr;
+  b->target = target;
+  b->beta_f = beta_f;
+  b->adaptive_max_steps = max_steps;
+  b->theta = theta;
+  int rc = batch_run(b, max_steps, use_graph);
+  if (steps_taken) {
+    int mx = 0;
+    for (auto& q : b->pops) mx = std::max(mx, q.step);
+    *steps_taken = mx;
+  }
+  return rc;
+}
+
+int pa_batch_run_learned(pa_batch* b, pa_mlp* m, double target, double tol,
+                         double beta_f, int32_t max_steps, int32_t theta,
+                         int32_t use_graph, int32_t* steps_taken,
+                         int64_t* src_counts) {
+  if (!b || !m || !(target > 0.0 && target <= 1.0) || !(tol >= 0.0) ||
+      !std::isfinite(beta_f) || max_steps < 1 || theta < 0)
+    return PA_EINVAL;
+  if (mlp_n_in(m) != kFeatures) return PA_EINVAL;
+  b->mode = 2;
+  b->mlp = m;
+  b->target = target;
+  b->tol = tol;
+  b->beta_f = beta_f;
+  b->adaptive_max_steps = max_steps;
+  b->theta = theta;
+  int rc = batch_run(b, max_steps, use_graph);
+  if (steps_taken) {
+    int mx = 0;
+    for (auto& q : b->pops) mx = std::max(mx, q.step);
+    *steps_taken = mx;
+  }
+  if (src_counts)
+    for (int k = 0; k < 5; ++k) src_counts[k] = b->src_count[k];
+  return rc;
+}
+
+int pa_batch_host_stats(pa_batch* b, double* host_ms, int64_t* overlap_evals,
+                        int64_t* src_counts) {
+  if (!b) return PA_EINVAL;
+  if (host_ms) *host_ms = b->host_ms;
+  if (overlap_evals) *overlap_evals = b->overlap_evals;
+  if (src_counts)
+    for (int k = 0; k < 5; ++k) src_counts[k] = b->src_count[k];
+  return PA_OK;
+}
+
+int pa_batch_decisions(pa_batch* b, int32_t p, float* feat, double* dbeta,
+                       int32_t* src, int32_t cap, int32_t* len) {
+  if (!b || p < 0 || p >= b->n || cap < 0) return PA_EINVAL;
+  const int steps = (int)(b->dec_src.size() / b->n);
+  int k = 0;
+  for (int i = 0; i < steps && k < cap; ++i) {
+    const size_t at = (size_t)i * b->n + p;
+    if (b->dec_src[at] < 0) continue;  // the population did not move
+    if (feat)
+      std::memcpy(feat + (size_t)k * kFeatures, &b->dec_feat[at * kFeatures],
+                  sizeof(float) * kFeatures);
+    if (dbeta) dbeta[k] = b->dec_dbeta[at];
+    if (src) src[k] = b->dec_src[at];
+    ++k;
+  }
+  if (len) *len = k;
+  return PA_OK;
+}
+
+int pa_batch_state(pa_batch* b, int32_t p, int64_t* R, double* beta,
+                   int32_t* step, double* lnZ) {
+  if (!b || p < 0 || p >= b->n) return PA_EINVAL;
+  BK(hipStreamSynchronize(b->stream));
+  if (R) *R = rb_R(b)[p];
+  if (beta) *beta = b->pops[p].beta;
+  if (step) *step = b->pops[p].step;
+  if (lnZ) *lnZ = b->pops[p].lnZ;
+  return PA_OK;
+}
+
+int pa_batch_trajectory(pa_batch* b, int32_t p, pa_obs* obs, double* lnZ,
+                        int32_t cap, int32_t* len) {
+  if (!b || p < 0 || p >= b->n) return PA_EINVAL;
+  const int steps = b->n ? (int)(b->traj.size() / b->n) : 0;
+  int k = 0;
+  for (int i = 0; i < steps && k < cap; ++i) {
+    const pa_obs& o = b->traj[(size_t)i * b->n + p];
+    if (o.R == 0) continue;  // the population had stopped
+    if (obs) obs[k] = o;
+    if (lnZ) lnZ[k] = b->traj_lnZ[(size_t)i * b->n + p];
+    ++k;
+  }
+  if (len) *len = k;
+  return PA_OK;
+}
+
+int pa_batch_get_population(pa_batch* b, int32_t p, int8_t* spins, int32_t* E,
+                            int32_t* M, int64_t cap) {
+  if (!b || p < 0 || p >= b->n) return PA_EINVAL;
+  BK(hipStreamSynchronize(b->stream));
+  const BatchPop& d = b->pops[p].d;
+  int32_t cur = 0;
+  BK(hipMemcpy(&cur, b->d_cur + p, 4, hipMemcpyDeviceToHost));
+  int64_t R = 0;
+  BK(hipMemcpy(&R, b->d_rb + 8 * (size_t)p, 8, hipMemcpyDeviceToHost));
+  if (cap < R) return PA_EINVAL;
+  const int N = d.L * d.L;
+  if (spins) {
+    std::vector<uint8_t> tmp((size_t)(R * d.stride));
+    BK(hipMemcpy(tmp.data(), d.spins[cur], tmp.size(), hipMemcpyDeviceToHost));
+    for (int64_t j = 0; j < R; ++j) {
+      const uint8_t* in = tmp.data() + j * d.stride;
+      int8_t* s = spins + j * N;
+      if (d.int8) {
+        std::memcpy(s, in, (size_t)N);
+      } else {
+        const uint32_t* w = reinterpret_cast<const uint32_t*>(in);
+        for (int y = 0; y < d.L; ++y)
+          for (int x = 0; x < d.L; ++x)
+            s[y * d.L + x] = ((w[y * d.W + x / 32] >> (x % 32)) & 1u) ? 1 : -1;
+      }
+    }
+  }
+  if (E) BK(hipMemcpy(E, d.E[cur], (size_t)R * 4, hipMemcpyDeviceToHost));
+  if (M) BK(hipMemcpy(M, d.M[cur], (size_t)R * 4, hipMemcpyDeviceToHost));
+  return PA_OK;
+}
+
+int pa_batch_set_sweep_blocks(pa_batch* b, int32_t blocks) {
+  if (!b || blocks < 1 || blocks > 65535) return PA_EINVAL;
+  drop_graph(b);
+  b->sweep_blocks = blocks;
+  return PA_OK;
+}
+
+}  // extern "C"

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "pa.h"
+
 namespace pa {
 
 struct LatticeArgs {
@@ -59,6 +61,80 @@ struct GatherArgs {
   int32_t lpr_log2; // log2 of the lanes that copy one row
 };
 
+// ---- batched populations (pa_batch.hip)
+struct BatchPop {          // static description of one population
+  uint8_t* spins[2];
+  int32_t* E[2];
+  int32_t* M[2];
+  uint32_t* n;             // copy counts            [cap]
+  uint32_t* parent;        // parent of each new slot [cap]
+  uint32_t* tile_sum;      // per 256-replica tile   [cap/256 + 1]
+  uint32_t* tile_off;
+  uint32_t* hist;          // energy histogram       [nbins]
+  uint32_t* tab;           // f[nbins] then T[nbins]
+  const uint32_t* jbits;   // +-J couplings or null
+  int64_t cap, stride;
+  int32_t L, W, rpl, lpr, rpw, nbins, shift, glass, int8, chunks, lpr_log2;
+  uint32_t k0, k1, pop;
+};
+
+struct BatchStep {         // per population, rewritten by the host each step
+  uint64_t K4, K8;         // Metropolis thresholds at the new beta
+  double beta;             // the population's beta after this step
+  double target;           // overlap target of the adaptive schedule
+  int32_t lvl0, nlvl;      // table range (histogram levels)
+  uint32_t step;           // index of the temperature being entered
+  int32_t theta;           // sweeps at the new beta
+  int32_t active;          // 0: the population does not move this step
+  int32_t pad;
+};
+
+// Histogram summaries fed to the temperature-step network (kFeatures per
+// population, computed on the device from the exact histogram).
+constexpr int kFeatures = 8;
+
+
+
+// ---- temperature-step network (pa_mlp.hip), used by the batch
+int mlp_prepare(pa_mlp* m, int B);
+int mlp_infer_on(pa_mlp* m, const float* X, int B, hipStream_t st);
+const float* mlp_output_dev(pa_mlp* m);
+void mlp_out_scale(const pa_mlp* m, float* mu_y, float* sigma_y);
+int mlp_n_in(const pa_mlp* m);
+
+// ---- diagnostics: text of the last failing HIP call on this thread
+void set_last_error(const char* what, hipError_t e, int line);
+
+// Evaluate a HIP call; on failure record it and return PA_EDEVICE.
+#define PA_HIP(x)                                   \
+  do {                                              \
+    const hipError_t pa_e_ = (x);                   \
+    if (pa_e_ != hipSuccess) {                      \
+      ::pa::set_last_error(#x, pa_e_, __LINE__);    \
+      return PA_EDEVICE;                            \
+    }                                               \
+  } while (0)
+
+// ---- host double-precision helpers (pa_tables.hip)
+struct TableRange {
+  int lo, hi;    // occupied histogram levels; tables hold levels lo..hi
+  double lnQ;    // ln Q of the step (Eq. part-Q)
+};
+void occupied_range(const uint32_t* h, int nbins, int* lo, int* hi);
+void metropolis_K(double beta, uint64_t* K4, uint64_t* K8);
+int build_tables(const uint32_t* h, int nbins, int shift, int N, int64_t R,
+                 int64_t R_t, double dbeta, uint32_t* f, uint32_t* T,
+                 TableRange* out);
+double overlap_from_hist(const uint32_t* h, int nbins, int shift, int N,
+                         int64_t R, double dbeta);
+void observables_from_hist(const uint32_t* h, int nbins, int shift, int N,
+                           int64_t R, double beta, int64_t sumAbsM,
+                           int64_t sumM2, pa_obs* o);
+double bisect_from_hist(const uint32_t* h, int nbins, int shift, int N,
+                        int64_t R, double target, double span,
+                        int* evals = nullptr);
+
+// ---- kernel launchers (pa_kernels.hip)
 hipError_t launch_lattice(const LatticeArgs& a, int W, int RPL, bool int8,
                           bool glass, hipStream_t st);
 hipError_t launch_hist(const HistArgs& a, hipStream_t st);

@@ -22,275 +22,16 @@
 
 #include "pa_device.h"
 #include "pa_internal.h"
+#include "pa_lattice.h"
 
 namespace pa {
 
 // ------------------------------------------------------------- lattice pass
 
-template <int W, int RPL, bool INT8>
-__device__ __forceinline__ void load_row(const uint8_t* rp, int L, int y,
-                                         uint32_t* row) {
-#pragma unroll
-  for (int w = 0; w < W; ++w) row[w] = 0u;
-  if (!INT8) {
-    const uint32_t* src = reinterpret_cast<const uint32_t*>(rp) + (size_t)y * W;
-#pragma unroll
-    for (int w = 0; w < W; ++w) row[w] = src[w];
-    return;
-  }
-  const uint8_t* src = rp + (size_t)y * L;
-  if ((L & 15) == 0) {
-#pragma unroll
-    for (int w = 0; w < W; ++w)
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const int xo = 32 * w + 16 * q;
-        if (xo < L) {
-          const uint4 v = *reinterpret_cast<const uint4*>(src + xo);
-          const uint32_t b = pack4(v.x) | (pack4(v.y) << 4) |
-                             (pack4(v.z) << 8) | (pack4(v.w) << 12);
-          row[w] |= b << (16 * q);
-        }
-      }
-  } else if ((L & 3) == 0) {
-#pragma unroll
-    for (int w = 0; w < W; ++w)
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int xo = 32 * w + 4 * q;
-        if (xo < L)
-          row[w] |= pack4(*reinterpret_cast<const uint32_t*>(src + xo))
-                    << (4 * q);
-      }
-  } else {
-#pragma unroll
-    for (int w = 0; w < W; ++w)
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int xo = 32 * w + 2 * q;
-        if (xo < L) {
-          const uint32_t v = *reinterpret_cast<const uint16_t*>(src + xo);
-          row[w] |= (pack4(v | 0x01010000u) & 3u) << (2 * q);
-        }
-      }
-  }
-}
-
-template <int W, int RPL, bool INT8>
-__device__ __forceinline__ void store_row(uint8_t* rp, int L, int y,
-                                          const uint32_t* row) {
-  if (!INT8) {
-    uint32_t* dst = reinterpret_cast<uint32_t*>(rp) + (size_t)y * W;
-#pragma unroll
-    for (int w = 0; w < W; ++w) dst[w] = row[w];
-    return;
-  }
-  uint8_t* dst = rp + (size_t)y * L;
-  if ((L & 15) == 0) {
-#pragma unroll
-    for (int w = 0; w < W; ++w)
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const int xo = 32 * w + 16 * q;
-        if (xo < L) {
-          const uint32_t b = row[w] >> (16 * q);
-          uint4 v;
-          v.x = unpack4(b & 0xFu);
-          v.y = unpack4((b >> 4) & 0xFu);
-          v.z = unpack4((b >> 8) & 0xFu);
-          v.w = unpack4((b >> 12) & 0xFu);
-          *reinterpret_cast<uint4*>(dst + xo) = v;
-        }
-      }
-  } else if ((L & 3) == 0) {
-#pragma unroll
-    for (int w = 0; w < W; ++w)
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int xo = 32 * w + 4 * q;
-        if (xo < L)
-          *reinterpret_cast<uint32_t*>(dst + xo) =
-              unpack4((row[w] >> (4 * q)) & 0xFu);
-      }
-  } else {
-#pragma unroll
-    for (int w = 0; w < W; ++w)
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int xo = 32 * w + 2 * q;
-        if (xo < L)
-          *reinterpret_cast<uint16_t*>(dst + xo) =
-              (uint16_t)(unpack4((row[w] >> (2 * q)) & 3u) & 0xFFFFu);
-      }
-  }
-}
-
 template <int W, int RPL, bool INT8, bool GLASS>
 __global__ __launch_bounds__(256) void k_lattice(const LatticeArgs a) {
-  __shared__ int2 red[256];
-  const int lane = threadIdx.x & 63;
-  const int64_t wave =
-      ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int L = a.L;
-  const int g = lane / a.lpr;
-  const int lr = lane - g * a.lpr;
-  const int64_t rep = wave * a.rpw + g;
-  const bool active = (g < a.rpw) && (rep < a.R);
-  const int base = g * a.lpr;
-  const int up_lane = active ? base + (lr == 0 ? a.lpr - 1 : lr - 1) : lane;
-  const int dn_lane = active ? base + (lr == a.lpr - 1 ? 0 : lr + 1) : lane;
-  const uint32_t slot = (uint32_t)(active ? rep : 0);
-  uint8_t* rp = a.spins + (size_t)slot * (size_t)a.stride;
-
-  uint32_t s[RPL][W];
-  // couplings: jr = bond to the right, jl = bond to the left (jr of x-1),
-  // jd = bond below, ju = bond above (jd of row y-1); bit set = J < 0
-  uint32_t jr[RPL][W], jl[RPL][W], jd[RPL][W], ju[RPL][W];
-
-#pragma unroll
-  for (int r = 0; r < RPL; ++r) {
-    const int y = lr * RPL + r;
-    if (GLASS) {
-      const int yu = (y == 0) ? L - 1 : y - 1;
-#pragma unroll
-      for (int w = 0; w < W; ++w) {
-        jr[r][w] = a.jbits[(size_t)y * W + w];
-        jd[r][w] = a.jbits[(size_t)(L + y) * W + w];
-        ju[r][w] = a.jbits[(size_t)(L + yu) * W + w];
-      }
-      row_from_left<W>(jr[r], jl[r], L);
-    } else {
-#pragma unroll
-      for (int w = 0; w < W; ++w) jr[r][w] = jl[r][w] = jd[r][w] = ju[r][w] = 0u;
-    }
-    if (a.init) {
-      // INIT stream: site x of row y <- word x%4 of group y*ceil(L/4) + x/4
-      const int G4 = (L + 3) >> 2;
-#pragma unroll
-      for (int w = 0; w < W; ++w) {
-        uint32_t v = 0u;
-#pragma unroll
-        for (int gq = 0; gq < 8; ++gq) {
-          if (32 * w + 4 * gq < L) {
-            const uint4 b = philox10(
-                make_uint4((kDomainInit << 28) | (uint32_t)(y * G4 + 8 * w + gq),
-                           0u, slot, a.pop),
-                a.k0, a.k1);
-            const uint32_t bits = (b.x >> 31) | ((b.y >> 31) << 1) |
-                                  ((b.z >> 31) << 2) | ((b.w >> 31) << 3);
-            v |= bits << (4 * gq);
-          }
-        }
-        s[r][w] = v & valid_mask(L, w);
-      }
-    } else if (active) {
-      load_row<W, RPL, INT8>(rp, L, y, s[r]);
-    } else {
-#pragma unroll
-      for (int w = 0; w < W; ++w) s[r][w] = 0u;
-    }
-  }
-
-  const int G8 = (L + 7) >> 3;
-  for (int t = 0; t < a.theta; ++t) {
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      uint32_t up0[W], dnl[W];
-#pragma unroll
-      for (int w = 0; w < W; ++w) {
-        up0[w] = shfl(s[RPL - 1][w], up_lane);
-        dnl[w] = shfl(s[0][w], dn_lane);
-      }
-      const uint32_t ctr1 = (a.step << 16) | (uint32_t)(2 * (a.t0 + t) + c);
-#pragma unroll
-      for (int r = 0; r < RPL; ++r) {
-        const int y = lr * RPL + r;
-        const uint32_t p = (uint32_t)((c + y) & 1);
-        const uint32_t rowbase = (kDomainMcmc << 28) | (uint32_t)(y * G8);
-        const uint32_t* up = (r == 0) ? up0 : s[r > 0 ? r - 1 : 0];
-        const uint32_t* dn = (r == RPL - 1) ? dnl : s[r < RPL - 1 ? r + 1 : 0];
-        uint32_t lf[W], rt[W];
-        row_from_left<W>(s[r], lf, L);
-        row_from_right<W>(s[r], rt, L);
-#pragma unroll
-        for (int w = 0; w < W; ++w) {
-          const uint32_t sv = s[r][w];
-          const uint32_t d1 = sv ^ lf[w] ^ jl[r][w];
-          const uint32_t d2 = sv ^ rt[w] ^ jr[r][w];
-          const uint32_t d3 = sv ^ up[w] ^ ju[r][w];
-          const uint32_t d4 = sv ^ dn[w] ^ jd[r][w];
-          const uint32_t x1 = d1 ^ d2, a1 = d1 & d2;
-          const uint32_t x2 = d3 ^ d4, a2 = d3 & d4;
-          const uint32_t eq0 = ~(d1 | d2 | d3 | d4);  // dE = +8
-          const uint32_t eq1 = (x1 ^ x2) & ~(a1 | a2); // dE = +4
-          const uint32_t ge2 = ~(eq0 | eq1);           // dE <= 0
-          // The 16 colour sites of this word (k = 16w + j, x = 2k + p) draw
-          // word j%4 of group 4w + j/4.  The rejection bit of a site is the
-          // carry of r + (2^32 - T): hi(r * 1 + K) is 1 iff r >= T, one
-          // v_mad_u64_u32 (the 1 comes from the arguments, so it is not
-          // folded away); v_lshl_add then moves it to bit 2j, highest site
-          // first.  T = 2^32 (K = 0) never rejects, T = 0 (K = 2^32) always.
-          uint32_t rj4 = 0u, rj8 = 0u;
-          const int ng = min(4, max(0, G8 - 4 * w));
-          for (int gq = ng - 1; gq >= 0; --gq) {
-            const uint4 b = philox10(
-                make_uint4(rowbase + (uint32_t)(4 * w + gq), ctr1, slot, a.pop),
-                a.k0, a.k1);
-            rj4 = shl2_add(rj4, reject_bit(b.w, a.one, a.K4));
-            rj8 = shl2_add(rj8, reject_bit(b.w, a.one, a.K8));
-            rj4 = shl2_add(rj4, reject_bit(b.z, a.one, a.K4));
-            rj8 = shl2_add(rj8, reject_bit(b.z, a.one, a.K8));
-            rj4 = shl2_add(rj4, reject_bit(b.y, a.one, a.K4));
-            rj8 = shl2_add(rj8, reject_bit(b.y, a.one, a.K8));
-            rj4 = shl2_add(rj4, reject_bit(b.x, a.one, a.K4));
-            rj8 = shl2_add(rj8, reject_bit(b.x, a.one, a.K8));
-          }
-          const uint32_t M4 = (~rj4 & 0x55555555u) << p;
-          const uint32_t M8 = (~rj8 & 0x55555555u) << p;
-          const uint32_t col = (p ? 0xAAAAAAAAu : 0x55555555u) & valid_mask(L, w);
-          const uint32_t flip = col & (ge2 | (eq1 & M4) | (eq0 & M8));
-          s[r][w] = sv ^ flip;
-        }
-      }
-    }
-  }
-
-  // energy and magnetisation of the final state (Eq. Ham)
-  uint32_t dnl[W];
-#pragma unroll
-  for (int w = 0; w < W; ++w) dnl[w] = shfl(s[0][w], dn_lane);
-  int unsat = 0, ups = 0;
-#pragma unroll
-  for (int r = 0; r < RPL; ++r) {
-    const uint32_t* dn = (r == RPL - 1) ? dnl : s[r < RPL - 1 ? r + 1 : 0];
-    uint32_t rt[W];
-    row_from_right<W>(s[r], rt, L);
-#pragma unroll
-    for (int w = 0; w < W; ++w) {
-      const uint32_t vm = valid_mask(L, w);
-      unsat += __popc((s[r][w] ^ rt[w] ^ jr[r][w]) & vm);
-      unsat += __popc((s[r][w] ^ dn[w] ^ jd[r][w]) & vm);
-      ups += __popc(s[r][w]);
-    }
-  }
-  red[threadIdx.x] = make_int2(unsat, ups);
-  __syncthreads();
-  if (active) {
-#pragma unroll
-    for (int r = 0; r < RPL; ++r) store_row<W, RPL, INT8>(rp, L, lr * RPL + r, s[r]);
-    if (lr == 0) {
-      int us = 0, up = 0;
-      const int w0 = threadIdx.x & ~63;
-      for (int i = 0; i < a.lpr; ++i) {
-        const int2 v = red[w0 + base + i];
-        us += v.x;
-        up += v.y;
-      }
-      const int N = L * L;
-      a.E[rep] = 2 * us - 2 * N;
-      a.M[rep] = 2 * up - N;
-    }
-  }
+  lattice_pass<W, RPL, INT8, GLASS>(
+      a, ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
 }
 
 // -------------------------------------------------------------- histogram

@@ -1,0 +1,160 @@
+// Host double-precision arithmetic of the population-annealing step, shared
+// by the single-population and the batched paths: reweighting tables from an
+// exact energy histogram (Eqs. part-Q, tau), the free-energy increment
+// (Eq. Free-En), Metropolis thresholds, observables from exact sums, and the
+// overlap / bisection of the adaptive temperature step.
+//
+// Every quantity is a plain IEEE operation in a fixed order (per energy
+// level, ascending energy); the library is compiled with -ffp-contract=off.
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <vector>
+
+#include "pa.h"
+#include "pa_internal.h"
+
+namespace pa {
+
+static thread_local char g_last_error[512] = "";
+
+void set_last_error(const char* what, hipError_t e, int line) {
+  std::snprintf(g_last_error, sizeof g_last_error, "%s failed at line %d: %s",
+                what, line, hipGetErrorString(e));
+}
+
+const char* last_error() { return g_last_error; }
+
+static inline int level_energy(int N, int shift, int i) {
+  return -2 * N + (i << shift);
+}
+
+void occupied_range(const uint32_t* h, int nbins, int* lo, int* hi) {
+  int a = 0, b = nbins - 1;
+  while (a < nbins && h[a] == 0) ++a;
+  while (b >= 0 && h[b] == 0) --b;
+  *lo = a;
+  *hi = b;
+}
+
+// Metropolis acceptance probabilities exp(-beta dE) for dE = 4, 8 as 32-bit
+// integer thresholds T = floor(p 2^32) (T = 2^32 accepts always); the kernel
+// receives K = 2^32 - T and rejects a random word r iff r + K >= 2^32.
+void metropolis_K(double beta, uint64_t* K4, uint64_t* K8) {
+  const uint64_t T4 = (uint64_t)std::floor(std::ldexp(std::exp(-(beta * 4.0)), 32));
+  const uint64_t T8 = (uint64_t)std::floor(std::ldexp(std::exp(-(beta * 8.0)), 32));
+  *K4 = (1ull << 32) - T4;
+  *K8 = (1ull << 32) - T8;
+}
+
+int build_tables(const uint32_t* h, int nbins, int shift, int N, int64_t R,
+                 int64_t R_t, double dbeta, uint32_t* f, uint32_t* T,
+                 TableRange* out) {
+  int lo, hi;
+  occupied_range(h, nbins, &lo, &hi);
+  if (lo > hi || R < 1) return PA_ESTATE;
+  const int Emin = level_energy(N, shift, lo);
+  const int nl = hi - lo + 1;
+  // (b) Boltzmann factors shifted by Emin, summed in ascending energy
+  std::vector<double> w((size_t)nl, 0.0);
+  double S = 0.0;
+  for (int i = lo; i <= hi; ++i) {
+    if (h[i] == 0) continue;
+    const double we =
+        std::exp(-(dbeta * (double)(level_energy(N, shift, i) - Emin)));
+    w[i - lo] = we;
+    const double term = (double)h[i] * we;
+    S = S + term;
+  }
+  // (c) ln Q with the shift restored (Eq. part-Q)
+  out->lnQ = (-(dbeta * (double)Emin)) + std::log(S / (double)R);
+  // (d) rho = R_target tau / R (Eq. tau): integer part and 32-bit threshold
+  for (int i = lo; i <= hi; ++i) {
+    f[i - lo] = 0u;
+    T[i - lo] = 0u;
+    if (h[i] == 0) continue;
+    const double rho = ((double)R_t * w[i - lo]) / S;
+    const double fl = std::floor(rho);
+    f[i - lo] = (uint32_t)fl;
+    T[i - lo] = (uint32_t)(uint64_t)std::floor(std::ldexp(rho - fl, 32));
+  }
+  out->lo = lo;
+  out->hi = hi;
+  return PA_OK;
+}
+
+void observables_from_hist(const uint32_t* h, int nbins, int shift, int N,
+                           int64_t R, double beta, int64_t sumAbsM,
+                           int64_t sumM2, pa_obs* o) {
+  int64_t sE = 0, sE2 = 0;
+  int lo, hi;
+  occupied_range(h, nbins, &lo, &hi);
+  for (int i = lo; i <= hi; ++i) {
+    const int64_t c = h[i], e = level_energy(N, shift, i);
+    sE += c * e;
+    sE2 += c * e * e;
+  }
+  const double Rd = (double)R, Nd = (double)N;
+  const __int128 var = (__int128)R * sE2 - (__int128)sE * sE;
+  o->R = R;
+  o->beta = beta;
+  o->e = (double)sE / (Rd * Nd);
+  o->abs_m = (double)sumAbsM / (Rd * Nd);
+  o->m2 = (double)sumM2 / (Rd * Nd * Nd);
+  o->C = ((beta * beta) * (double)var) / ((Rd * Rd) * Nd);
+  o->sumE = sE;
+  o->sumE2 = sE2;
+  o->sumAbsM = sumAbsM;
+  o->sumM2 = sumM2;
+  o->Emin = level_energy(N, shift, lo);
+  o->Emax = level_energy(N, shift, hi);
+}
+
+// alpha(dbeta) = sum_E min(h/R, h w / S), w = exp(-dbeta (E - Emin))
+double overlap_from_hist(const uint32_t* h, int nbins, int shift, int N,
+                         int64_t R, double dbeta) {
+  int lo, hi;
+  occupied_range(h, nbins, &lo, &hi);
+  const int Emin = level_energy(N, shift, lo);
+  double S = 0.0;
+  for (int i = lo; i <= hi; ++i) {
+    if (h[i] == 0) continue;
+    const double term = (double)h[i] *
+        std::exp(-(dbeta * (double)(level_energy(N, shift, i) - Emin)));
+    S = S + term;
+  }
+  double a = 0.0;
+  for (int i = lo; i <= hi; ++i) {
+    if (h[i] == 0) continue;
+    const double pe = (double)h[i] / (double)R;
+    const double qe = ((double)h[i] *
+        std::exp(-(dbeta * (double)(level_energy(N, shift, i) - Emin)))) / S;
+    a = a + (pe < qe ? pe : qe);
+  }
+  return a;
+}
+
+// Largest dbeta <= span with alpha(dbeta) >= target: the whole span if it
+// qualifies, else 64 halvings of [0, span] keeping the lower end qualified.
+double bisect_from_hist(const uint32_t* h, int nbins, int shift, int N,
+                        int64_t R, double target, double span, int* evals) {
+  if (!(span > 0.0)) return 0.0;
+  int k = 1;
+  double d = span;
+  if (overlap_from_hist(h, nbins, shift, N, R, span) < target) {
+    double lo = 0.0, hi = span;
+    for (int it = 0; it < 64; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      ++k;
+      if (overlap_from_hist(h, nbins, shift, N, R, mid) >= target) lo = mid;
+      else hi = mid;
+    }
+    d = lo;
+  }
+  if (evals) *evals += k;
+  return d;
+}
+
+}  // namespace pa
+
+extern "C" const char* pa_last_error(void) { return pa::last_error(); }

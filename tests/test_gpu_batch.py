@@ -1,0 +1,165 @@
+"""Batched populations: every population of a batch must be bit for bit the
+oracle's run of the same configuration (spins, energies, ln Z, observables
+after every step); the graph-captured step must reproduce the eager one on
+every replay; the batch must equal the single-population path; the
+adaptive schedule must make the oracle's bisection choices."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import pa_workloads as W
+
+pytestmark = pytest.mark.gpu
+REL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def pa():
+    if not os.path.exists("/dev/kfd"):
+        pytest.skip("no GPU")
+    from paper_2006_00561_amd import binding
+    binding.lib()
+    return binding
+
+
+def _close(a, b):
+    return abs(a - b) <= REL * max(1.0, abs(a), abs(b))
+
+
+MIXED = [  # L, R, glass, layout
+    (4, 50, False, 0), (6, 300, True, 0), (8, 257, True, 0),
+    (12, 513, True, 0), (16, 700, False, 1), (24, 333, True, 0),
+    (32, 300, False, 0), (64, 70, True, 0), (128, 20, False, 1),
+]
+
+
+def _mixed_pops():
+    pops = []
+    for k, (L, R, glass, layout) in enumerate(MIXED):
+        pops.append(dict(L=L, R=R, J=W.pmj_couplings(L, 50 + k) if glass
+                         else None, seed=7, population_id=k, layout=layout))
+    return pops
+
+
+def _oracle_run(pop, betas, theta):
+    o = oracle.OraclePA(pop["L"], pop["R"], seed=pop["seed"],
+                        pop=pop["population_id"], J=pop["J"])
+    traj = []
+    for b in betas:
+        o.resample(b)
+        o.sweep(theta)
+        traj.append((o.observables(), o.free_energy()[0]))
+    return o, traj
+
+
+def _check_pop(batch, p, o, traj_o):
+    s, E, M = batch.population(p)
+    so, Eo, Mo = o.population()
+    assert np.array_equal(E, Eo) and np.array_equal(M, Mo), p
+    assert np.array_equal(s, so), p
+    R, beta, step, lnZ = batch.state(p)
+    assert R == o.R and beta == o.beta and step == o.step
+    assert _close(lnZ, o.free_energy()[0])
+    obs, lnZs = batch.trajectory(p)
+    assert len(obs) == len(traj_o)
+    for (og, zg), (oo, zo) in zip(zip(obs, lnZs), traj_o):
+        for k in ("R", "sumE", "sumE2", "sumAbsM", "sumM2", "Emin", "Emax"):
+            assert og[k] == oo[k], (p, k)
+        for k in ("beta", "e", "abs_m", "m2", "C"):
+            assert _close(og[k], oo[k]), (p, k)
+        assert _close(zg, zo)
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_mixed_batch_matches_oracle(pa, use_graph):
+    pops = _mixed_pops()
+    betas = W.linear_schedule(1.2, 6)
+    theta = 3
+    print("batch parity graph=%s" % use_graph, flush=True)
+    b = pa.Batch(pops)
+    b.run(np.array(betas), theta, use_graph=use_graph)
+    for p, pop in enumerate(pops):
+        o, traj = _oracle_run(pop, betas, theta)
+        _check_pop(b, p, o, traj)
+    b.close()
+
+
+def test_graph_replays_match_eager_across_runs(pa):
+    """Two graph runs of 4 steps each, with host reads in between, against
+    one eager run of 8 steps: identical populations and ln Z."""
+    pops = _mixed_pops()
+    betas = np.array(W.linear_schedule(1.6, 8))
+    g = pa.Batch(pops)
+    e = pa.Batch(pops)
+    g.run(betas[:4], 2, use_graph=True)
+    mid = [g.state(p) for p in range(len(pops))]
+    g.run(betas[4:], 2, use_graph=True)
+    e.run(betas[:4], 2, use_graph=False)
+    assert [e.state(p) for p in range(len(pops))] == mid
+    e.run(betas[4:], 2, use_graph=False)
+    for p in range(len(pops)):
+        assert g.state(p) == e.state(p)
+        for a, c in zip(g.population(p), e.population(p)):
+            assert np.array_equal(a, c)
+
+
+def test_batch_equals_single_population_path(pa):
+    """The batched glass workload (64 instances, L in {8..32}, R up to 2^16),
+    first 12 steps of its schedule, against each instance run alone through
+    pa_init / pa_resample / pa_sweep."""
+    inst = W.batched_glass_instances()
+    betas = np.array(W.linear_schedule(3.0, 300)[:12])
+    theta = 10
+    b = pa.Batch(inst, autotune=True)
+    b.run(betas, theta, use_graph=True)
+    for p, c in enumerate(inst):
+        g = pa.Population(c["L"], c["R"], seed=c["seed"],
+                          population_id=c["population_id"], J=c["J"])
+        for beta in betas:
+            g.resample(beta)
+            g.sweep(beta, theta)
+        sg, Eg, Mg = g.population()
+        sb, Eb, Mb = b.population(p)
+        assert np.array_equal(Eg, Eb) and np.array_equal(sg, sb), p
+        assert g.free_energy()[0] == b.state(p)[3]
+        g.close()
+    b.close()
+
+
+def test_adaptive_schedule_matches_oracle_bisection(pa):
+    pops = [dict(L=L, R=R, J=W.pmj_couplings(L, 90 + k) if k % 2 else None,
+                 seed=3, population_id=k)
+            for k, (L, R) in enumerate([(8, 400), (12, 300), (16, 500),
+                                        (24, 200)])]
+    target, beta_f, theta = 0.85, 2.0, 2
+    b = pa.Batch(pops)
+    steps = b.run_adaptive(target, beta_f, 200, theta, use_graph=True)
+    assert steps < 200
+    for p, pop in enumerate(pops):
+        o = oracle.OraclePA(pop["L"], pop["R"], seed=3, pop=p, J=pop["J"])
+        traj = []
+        while o.beta < beta_f:
+            span = beta_f - o.beta
+            d = o.bisect_dbeta(target, beta_f)
+            nb = beta_f if d == span else o.beta + d
+            if not nb > o.beta:
+                nb = beta_f
+            if d < span:
+                # the bisection step honours the overlap target
+                assert o.overlap(d) >= target
+            o.resample(nb)
+            o.sweep(theta)
+            traj.append((o.observables(), o.free_energy()[0]))
+        _check_pop(b, p, o, traj)
+    b.close()
+
+
+def test_autotuner_reports_valid_shapes(pa):
+    for L, valid in ((16, (1, 2, 4)), (24, (1, 2, 4)), (64, (1, 2, 4)),
+                     (128, (2, 4))):
+        best, ms = pa.tune_rows_per_lane(L, R=2048, theta=2)
+        assert best in valid
+        for rpl, t in zip((1, 2, 4), ms):
+            assert (t > 0) == (rpl in valid)
