@@ -45,6 +45,34 @@ VALU_OPS_PER_S = 256 * 4 * 16 * 2.4e9
 ALGO_OPS_PER_ATTEMPT = 40 / 4 + 2
 
 
+KERNEL_SOURCES = ("paper_2006_00561_amd/csrc/pa_lattice.h",
+                  "paper_2006_00561_amd/csrc/pa_device.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_lattice_C2_traffic.json")
+
+
+def kernel_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload):
+    """HBM bytes per k_lattice launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known
+    size), or None if it was taken on another workload or an older kernel."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("workload") != workload or t.get("kernel_sha256") != kernel_hash():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
 def run_anneal(binding, cfg, stream, timing=False, rows_per_lane=0):
     layout = binding.PA_BITS if cfg["layout"] == "bits" else binding.PA_INT8
     L, R, theta = cfg["L"], cfg["R"], cfg["theta"]
@@ -185,6 +213,71 @@ def bench_learned(binding, use_graph=True, target=0.85, tol=0.02):
     return out
 
 
+def summarize_profiles(trace_dir, fetch_dir, write_dir, workload, command):
+    """Write profiles/ summaries from rocprofv3 CSV output: per-kernel
+    durations (--kernel-trace --stats) and HBM traffic (--pmc FETCH_SIZE and
+    --pmc WRITE_SIZE runs that also ran a 1 GiB device copy, whose counters
+    calibrate the scale)."""
+    import csv
+    import glob
+
+    def one(pattern):
+        f = glob.glob(os.path.join(pattern))
+        if not f:
+            raise SystemExit("no file matches " + pattern)
+        return f[0]
+
+    stats = list(csv.DictReader(open(one(os.path.join(trace_dir,
+                                                       "*kernel_stats.csv")))))
+    per = {}
+    for cnt, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = list(csv.DictReader(open(one(os.path.join(
+            d, "*counter_collection.csv")))))
+        agg = {}
+        for r in rows:
+            agg.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        copy = [v for k, v in agg.items() if "copyBuffer" in k
+                or "copy" in k.lower()]
+        copy_kib = max((sum(v) / len(v) for v in copy), default=0.0)
+        scale = (1 << 20) / copy_kib if copy_kib > 0 else float("nan")
+        per[cnt] = (agg, scale, copy_kib)
+    lat_f = per["FETCH_SIZE"][0].get("k_lattice", [])
+    lat_w = per["WRITE_SIZE"][0].get("k_lattice", [])
+    fetch_b = (sum(lat_f) / len(lat_f)) * 1024 * per["FETCH_SIZE"][1]
+    write_b = (sum(lat_w) / len(lat_w)) * 1024 * per["WRITE_SIZE"][1]
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump({
+            "workload": workload, "kernel": "k_lattice",
+            "kernel_sha256": kernel_hash(),
+            "fetch_scale": per["FETCH_SIZE"][1],
+            "write_scale": per["WRITE_SIZE"][1],
+            "copy_calibration_KiB": {"FETCH_SIZE": per["FETCH_SIZE"][2],
+                                     "WRITE_SIZE": per["WRITE_SIZE"][2],
+                                     "expected": 1 << 20},
+            "launches": len(lat_f),
+            "fetch_bytes_per_launch": fetch_b,
+            "write_bytes_per_launch": write_b,
+            "hbm_bytes_per_launch": fetch_b + write_b,
+            "commands": command}, fh, indent=1)
+    lines = ["# rocprofv3 kernel statistics, workload %s" % workload, "",
+             "Commands:", ""] + ["    " + c for c in command] + [
+             "", "| kernel | calls | average ns | total ns | % |",
+             "|---|---|---|---|---|"]
+    for r in stats:
+        lines.append("| %s | %s | %.0f | %s | %s |" % (
+            r["Name"], r["Calls"], float(r["AverageNs"]),
+            r["TotalDurationNs"], r["Percentage"]))
+    lines += ["", "HBM traffic of k_lattice per launch (counters scaled by "
+              "a 1 GiB copy: FETCH_SIZE x%.3f, WRITE_SIZE x%.3f): fetch "
+              "%.1f MB, write %.1f MB, total %.1f MB over %d launches." % (
+                  per["FETCH_SIZE"][1], per["WRITE_SIZE"][1], fetch_b / 1e6,
+                  write_b / 1e6, (fetch_b + write_b) / 1e6, len(lat_f))]
+    with open(os.path.join(ROOT, "profiles", "kernels_%s.md" % workload),
+              "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -198,10 +291,27 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--eager", action="store_true",
                     help="batched runs without HIP graphs")
+    ap.add_argument("--summarize-profiles", nargs=3,
+                    metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/ summaries from rocprofv3 output")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy, the reference "
                          "for scaling FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        cmd = ["rocprofv3 --kernel-trace --stats -T -d <TRACE_DIR> -o c2 "
+               "--output-format csv -- python3 bench.py --workload %s "
+               "--steps 2 --warmup 1 --no-cpu-baseline --no-batched "
+               "--no-learned" % args.workload,
+               "rocprofv3 --pmc FETCH_SIZE -T -d <FETCH_DIR> -o c2 "
+               "--output-format csv -- python3 bench.py --workload %s "
+               "--steps 1 --warmup 0 --no-cpu-baseline --no-batched "
+               "--no-learned --calibrate-copy" % args.workload,
+               "rocprofv3 --pmc WRITE_SIZE (same as the previous line)",
+               "python3 bench.py --workload %s --summarize-profiles "
+               "<TRACE_DIR> <FETCH_DIR> <WRITE_DIR>" % args.workload]
+        summarize_profiles(*args.summarize_profiles, args.workload, cmd)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU "
               "path (the population would shard by replica slots; see the "
@@ -292,7 +402,7 @@ def main():
             "peak": peak,
             "unit": "TOP/s (32-bit integer VALU)",
             "frac": achieved / peak,
-            "traffic": None,
+            "traffic": measured_traffic(args.workload),
             "sweep_attempts_per_ns": sweep_rate,
             "sweep_avg_ms": sweep_avg_ms,
             "ops_per_attempt": ALGO_OPS_PER_ATTEMPT,

@@ -291,11 +291,14 @@ int pa_batch_run_learned(pa_batch* b, pa_mlp* m, double target, double tol,
                          int64_t* src_counts);
 
 /* Per step of the last run in which population p moved: its 8 summaries,
-   the dbeta taken and its source (0 schedule, 1 bisection, 2 network,
-   3 bisection after a rejected proposal, 4 the whole remaining interval);
-   host arrays of `cap` rows.  The training data of the network. */
+   the dbeta taken, its source (0 schedule, 1 bisection, 2 network,
+   3 bisection after a rejected proposal, 4 the whole remaining interval)
+   and the network's proposed log dbeta (NaN without a network); host arrays
+   of `cap` rows, any pointer may be NULL.  The training data of the
+   network. */
 int pa_batch_decisions(pa_batch* b, int32_t p, float* feat, double* dbeta,
-                       int32_t* src, int32_t cap, int32_t* len);
+                       int32_t* src, float* proposal, int32_t cap,
+                       int32_t* len);
 
 /* Cost of the schedule decisions of the last run: milliseconds spent in the
    host function, exact overlap evaluations made, steps per source [5]. */

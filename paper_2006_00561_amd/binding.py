@@ -104,8 +104,8 @@ def lib():
             "pa_batch_destroy": ([P], None),
             "pa_batch_run_learned": ([P, P, d, d, d, i32, i32, i32,
                                       C.POINTER(i32), P], C.c_int),
-            "pa_batch_decisions": ([P, i32, P, P, P, i32, C.POINTER(i32)],
-                                   C.c_int),
+            "pa_batch_decisions": ([P, i32, P, P, P, P, i32,
+                                    C.POINTER(i32)], C.c_int),
             "pa_batch_host_stats": ([P, C.POINTER(d), C.POINTER(i64), P],
                                     C.c_int),
             "pa_mlp_create": ([i32, i32, i32, C.c_uint64, P, C.POINTER(P)],
@@ -401,16 +401,20 @@ class Batch:
             "pa_batch_run_learned")
         return st.value, src
 
-    def decisions(self, p, cap=100000):
+    def decisions(self, p, cap=100000, with_proposals=False):
         """(features [k][8] float32, dbeta [k], source [k]) of population p
-        over the last run."""
+        over the last run, and the network's log dbeta proposals if asked."""
         f = np.zeros((cap, 8), np.float32)
         db = np.zeros(cap, np.float64)
         src = np.zeros(cap, np.int32)
+        prop = np.zeros(cap, np.float32)
         ln = C.c_int32()
         _ck(lib().pa_batch_decisions(self._h, p, _ptr(f), _ptr(db), _ptr(src),
-                                     cap, C.byref(ln)), "pa_batch_decisions")
+                                     _ptr(prop), cap, C.byref(ln)),
+            "pa_batch_decisions")
         k = ln.value
+        if with_proposals:
+            return f[:k], db[:k], src[:k], prop[:k]
         return f[:k], db[:k], src[:k]
 
     def host_stats(self):

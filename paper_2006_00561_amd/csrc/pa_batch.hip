@@ -476,6 +476,7 @@ struct pa_batch {
   // temperature-step network (learned mode) and its acceptance tolerance
   pa_mlp* mlp = nullptr;
   pa_mlp* graph_mlp = nullptr;  // the network the graph was built with
+  uint64_t graph_mlp_gen = 0;   // and its scratch/scale generation
   double tol = 0.02;
   // schedule
   int mode = 0;                 // 0 explicit schedule, 1 bisection, 2 learned
@@ -489,6 +490,7 @@ struct pa_batch {
   std::vector<double> traj_lnZ;
   // per step and population: the features, the step taken and its source
   std::vector<float> dec_feat;
+  std::vector<float> dec_prop;   // the network's log dbeta (NaN without one)
   std::vector<double> dec_dbeta;
   std::vector<int32_t> dec_src;
   int64_t src_count[5] = {0, 0, 0, 0, 0};
@@ -605,6 +607,7 @@ void host_step(void* ud) {
         std::memcpy(&b->dec_feat[at * kFeatures], rb_feat(b) + (size_t)p * kFeatures,
                     sizeof(float) * kFeatures);
         b->dec_dbeta[at] = beta_next - q.beta;
+        b->dec_prop[at] = b->mlp ? rb_pred(b)[p] : std::nanf("");
         b->dec_src[at] = src;
       }
       b->src_count[src] += 1;
@@ -769,9 +772,12 @@ void drop_graph(pa_batch* b) {
 }
 
 int build_graph(pa_batch* b) {
-  if (b->exec && b->exec2 && b->graph_mlp == b->mlp) return PA_OK;
+  const uint64_t gen = mlp_generation(b->mlp);
+  if (b->exec && b->exec2 && b->graph_mlp == b->mlp && b->graph_mlp_gen == gen)
+    return PA_OK;
   drop_graph(b);
   b->graph_mlp = b->mlp;
+  b->graph_mlp_gen = gen;
   int rc = capture(b, enqueue_front, &b->exec, &b->graph);
   if (rc == PA_OK) rc = capture(b, enqueue_back, &b->exec2, &b->graph2);
   if (rc != PA_OK) drop_graph(b);
@@ -1104,6 +1110,7 @@ static int batch_run(pa_batch* b, int steps, int use_graph) {
   b->traj_lnZ.assign((size_t)steps * b->n, 0.0);
   b->dec_feat.assign((size_t)steps * b->n * kFeatures, 0.0f);
   b->dec_dbeta.assign((size_t)steps * b->n, 0.0);
+  b->dec_prop.assign((size_t)steps * b->n, 0.0f);
   b->dec_src.assign((size_t)steps * b->n, -1);
   for (auto& c : b->src_count) c = 0;
   b->overlap_evals = 0;
@@ -1205,7 +1212,8 @@ int pa_batch_host_stats(pa_batch* b, double* host_ms, int64_t* overlap_evals,
 }
 
 int pa_batch_decisions(pa_batch* b, int32_t p, float* feat, double* dbeta,
-                       int32_t* src, int32_t cap, int32_t* len) {
+                       int32_t* src, float* proposal, int32_t cap,
+                       int32_t* len) {
   if (!b || p < 0 || p >= b->n || cap < 0) return PA_EINVAL;
   const int steps = (int)(b->dec_src.size() / b->n);
   int k = 0;
@@ -1217,6 +1225,7 @@ int pa_batch_decisions(pa_batch* b, int32_t p, float* feat, double* dbeta,
                   sizeof(float) * kFeatures);
     if (dbeta) dbeta[k] = b->dec_dbeta[at];
     if (src) src[k] = b->dec_src[at];
+    if (proposal) proposal[k] = b->dec_prop[at];
     ++k;
   }
   if (len) *len = k;

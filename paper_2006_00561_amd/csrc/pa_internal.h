@@ -101,6 +101,7 @@ int mlp_infer_on(pa_mlp* m, const float* X, int B, hipStream_t st);
 const float* mlp_output_dev(pa_mlp* m);
 void mlp_out_scale(const pa_mlp* m, float* mu_y, float* sigma_y);
 int mlp_n_in(const pa_mlp* m);
+uint64_t mlp_generation(const pa_mlp* m);
 
 // ---- diagnostics: text of the last failing HIP call on this thread
 void set_last_error(const char* what, hipError_t e, int line);

@@ -16,6 +16,7 @@
 // (a loop over the samples in order, so gradients are deterministic).
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -131,11 +132,17 @@ struct pa_mlp {
         *d_delta = nullptr, *d_r2 = nullptr;
   int32_t* d_idx = nullptr;
   int64_t act_stride = 0;  // floats per activation slot (B * max width)
+  // changes whenever a captured inference would go stale: new scratch
+  // addresses or new output scale
+  uint64_t gen = 0;
 };
 
 namespace {
 
 #define MK(x) PA_HIP(x)
+
+std::atomic<uint64_t> g_generation{0};
+void bump(pa_mlp* m) { m->gen = ++g_generation; }
 
 void mlp_free_scratch(pa_mlp* m) {
   void* p[] = {m->d_X, m->d_T, m->d_Tb, m->d_act, m->d_delta, m->d_r2,
@@ -165,6 +172,7 @@ int ensure_batch(pa_mlp* m, int B) {
     return PA_ENOMEM;
   }
   m->cap_B = B;
+  bump(m);
   return PA_OK;
 }
 
@@ -218,6 +226,7 @@ void mlp_out_scale(const pa_mlp* m, float* mu_y, float* sigma_y) {
   *sigma_y = m->h_norm[2 * m->n_in + 1];
 }
 int mlp_n_in(const pa_mlp* m) { return m->n_in; }
+uint64_t mlp_generation(const pa_mlp* m) { return m ? m->gen : 0; }
 
 // Backward pass for B samples whose forward activations are in the slots and
 // whose standardised targets are in d_Tb: gradient into d_grad.
@@ -378,6 +387,7 @@ int pa_mlp_set_norm(pa_mlp* m, const float* mu, const float* sigma,
   MK(hipMemcpyAsync(m->d_norm, m->h_norm, (size_t)(2 * m->n_in + 2) * 4,
                     hipMemcpyHostToDevice, m->stream));
   MK(hipStreamSynchronize(m->stream));
+  bump(m);
   return PA_OK;
 }
 
