@@ -236,13 +236,21 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, workload, command):
         agg = {}
         for r in rows:
             agg.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
-        copy = [v for k, v in agg.items() if "copyBuffer" in k
-                or "copy" in k.lower()]
-        copy_kib = max((sum(v) / len(v) for v in copy), default=0.0)
+        # the 1 GiB copies are the largest copy dispatches of the run (the
+        # library's own small copies share the kernel name)
+        copy = sorted(v for k, vs in agg.items() if "copy" in k.lower()
+                      for v in vs)[-3:]
+        copy_kib = sum(copy) / len(copy) if copy else 0.0
         scale = (1 << 20) / copy_kib if copy_kib > 0 else float("nan")
         per[cnt] = (agg, scale, copy_kib)
-    lat_f = per["FETCH_SIZE"][0].get("k_lattice", [])
-    lat_w = per["WRITE_SIZE"][0].get("k_lattice", [])
+    def lattice(agg):
+        return [v for k, vs in agg.items() if k.startswith("k_lattice")
+                for v in vs]
+
+    lat_f = lattice(per["FETCH_SIZE"][0])
+    lat_w = lattice(per["WRITE_SIZE"][0])
+    if not lat_f or not lat_w:
+        raise SystemExit("no k_lattice dispatch in the counter output")
     fetch_b = (sum(lat_f) / len(lat_f)) * 1024 * per["FETCH_SIZE"][1]
     write_b = (sum(lat_w) / len(lat_w)) * 1024 * per["WRITE_SIZE"][1]
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
@@ -299,15 +307,17 @@ def main():
                          "for scaling FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.summarize_profiles:
-        cmd = ["rocprofv3 --kernel-trace --stats -T -d <TRACE_DIR> -o c2 "
-               "--output-format csv -- python3 bench.py --workload %s "
-               "--steps 2 --warmup 1 --no-cpu-baseline --no-batched "
-               "--no-learned" % args.workload,
-               "rocprofv3 --pmc FETCH_SIZE -T -d <FETCH_DIR> -o c2 "
-               "--output-format csv -- python3 bench.py --workload %s "
-               "--steps 1 --warmup 0 --no-cpu-baseline --no-batched "
-               "--no-learned --calibrate-copy" % args.workload,
-               "rocprofv3 --pmc WRITE_SIZE (same as the previous line)",
+        base = ("python3 <repo>/bench.py --workload %s --no-cpu-baseline "
+                "--no-batched --no-learned" % args.workload)
+        cmd = ["cd /tmp && export TMPDIR=/tmp",
+               "rocprofv3 --kernel-trace --stats -T -d <TRACE_DIR> -o run "
+               "--output-format csv -- %s --steps 2 --warmup 1" % base,
+               "rocprofv3 --pmc FETCH_SIZE -T -d <FETCH_DIR> -o run "
+               "--output-format csv -- %s --steps 1 --warmup 0 "
+               "--calibrate-copy" % base,
+               "rocprofv3 --pmc WRITE_SIZE -T -d <WRITE_DIR> -o run "
+               "--output-format csv -- %s --steps 1 --warmup 0 "
+               "--calibrate-copy" % base,
                "python3 bench.py --workload %s --summarize-profiles "
                "<TRACE_DIR> <FETCH_DIR> <WRITE_DIR>" % args.workload]
         summarize_profiles(*args.summarize_profiles, args.workload, cmd)
