@@ -119,9 +119,13 @@ int pa_sweep(pa_ctx* c, double beta, int32_t theta);
    host, per energy level in ascending order, w = exp(-dbeta (E - Emin)),
    S = sum h w, ln Q = -dbeta Emin + ln(S / R), rho = R_target w / S; copy
    counts n_j = floor(rho) + [r_j < floor(frac(rho) 2^32)] (RESAMPLE word 0
-   of slot j at the new step); exclusive scan; gather of the copies (parents
-   in slot order, copies contiguous) into the second buffer.  Advances beta
-   and the step, adds ln Q to ln Z (Eq. Free-En).  *R_new (may be NULL)
+   of slot j at the new step); exclusive scan; parent of every new slot
+   (parents in slot order, copies contiguous).  The copies into the second
+   buffer are made by the next pa_sweep with theta > 0 as it loads each new
+   slot from its parent, or by a plain gather before any other call that
+   reads the population; either way every later call sees the resampled
+   population.  Advances beta and the step, adds ln Q to ln Z (Eq.
+   Free-En).  *R_new (may be NULL)
    receives the new population size, also when it exceeds the capacity
    (then PA_ECAPACITY and nothing changes). */
 int pa_resample(pa_ctx* c, double beta_next, int64_t* R_new);

@@ -58,6 +58,10 @@ struct pa_ctx {
   uint32_t* h_tab = nullptr;
   int nbins = 0, hshift = 0;
   bool hist_valid = false;
+  // pa_resample left the copies to the next sweep: parent[] holds the
+  // parent of each of the R new slots, the buffer `cur` still the old
+  // population
+  bool gather_pending = false;
   int64_t n_len = 0;
   bool timing = false;
   std::vector<TimedLaunch> pending;
@@ -151,10 +155,38 @@ int run_lattice(pa_ctx* c, LatticeArgs& a, int cls) {
   return PA_OK;
 }
 
+// The resampling copies of the last pa_resample when no sweep took them
+// over: every new slot receives its parent's lattice, E and M.
+int finish_gather(pa_ctx* c) {
+  if (!c->gather_pending) return PA_OK;
+  GatherArgs g{};
+  g.src = c->spins[c->cur];
+  g.dst = c->spins[c->cur ^ 1];
+  g.E_src = c->E[c->cur];
+  g.M_src = c->M[c->cur];
+  g.E_dst = c->E[c->cur ^ 1];
+  g.M_dst = c->M[c->cur ^ 1];
+  g.parent = c->parent;
+  g.R_new = c->R;
+  g.stride = c->stride;
+  g.chunks = (int32_t)(c->stride / 16);
+  int lg = 0;
+  while ((1 << lg) < g.chunks && lg < 6) ++lg;
+  g.lpr_log2 = lg;
+  hipEvent_t e0 = t_begin(c);
+  CK(launch_gather(g, c->stream));
+  t_end(c, PA_K_GATHER, e0, 2 * c->R * c->stride + 20 * c->R, 0);
+  c->cur ^= 1;
+  c->gather_pending = false;
+  return PA_OK;
+}
+
 // Exact energy histogram and |M|, M^2 sums of the current population,
 // mirrored into pinned host memory.
 int compute_hist(pa_ctx* c) {
   if (c->hist_valid) return PA_OK;
+  const int rg = finish_gather(c);
+  if (rg) return rg;
   CK(launch_fill_u32(c->hist, c->nbins, 0u, c->stream));
   CK(launch_fill_u32(reinterpret_cast<uint32_t*>(c->scal), 8, 0u, c->stream));
   HistArgs h{};
@@ -372,8 +404,22 @@ int pa_sweep(pa_ctx* c, double beta, int32_t theta) {
   LatticeArgs a = lattice_args(c);
   metropolis_K(c->beta, &a.K4, &a.K8);
   a.theta = theta;
+  const bool fused = c->gather_pending;
+  if (fused) {
+    // the resampling copies happen on the way in: each new slot loads its
+    // parent's lattice from the old buffer and the pass writes the new one
+    a.src = c->spins[c->cur];
+    a.parent = c->parent;
+    a.spins = c->spins[c->cur ^ 1];
+    a.E = c->E[c->cur ^ 1];
+    a.M = c->M[c->cur ^ 1];
+  }
   int rc = run_lattice(c, a, PA_K_SWEEP);
   if (rc) return rc;
+  if (fused) {
+    c->cur ^= 1;
+    c->gather_pending = false;
+  }
   c->sweeps_at_step += theta;
   c->hist_valid = false;
   return PA_OK;
@@ -430,29 +476,13 @@ int pa_resample(pa_ctx* c, double beta_next, int64_t* R_new) {
     c->n_len = 0;
     return PA_EEMPTY;
   }
-  // (f) parent of every new slot, then the copies into the other buffer
+  // (f) parent of every new slot; the copies into the other buffer are left
+  // to the next sweep, which reads every new slot from its parent
   e0 = t_begin(c);
   CK(launch_scatter(c->n, c->tile_off, c->R, c->cap, c->parent, c->stream));
   t_end(c, PA_K_SCATTER, e0, 4 * c->R + 4 * total, 0);
-  GatherArgs g{};
-  g.src = c->spins[c->cur];
-  g.dst = c->spins[c->cur ^ 1];
-  g.E_src = c->E[c->cur];
-  g.M_src = c->M[c->cur];
-  g.E_dst = c->E[c->cur ^ 1];
-  g.M_dst = c->M[c->cur ^ 1];
-  g.parent = c->parent;
-  g.R_new = total;
-  g.stride = c->stride;
-  g.chunks = (int32_t)(c->stride / 16);
-  int lg = 0;
-  while ((1 << lg) < g.chunks && lg < 6) ++lg;
-  g.lpr_log2 = lg;
-  e0 = t_begin(c);
-  CK(launch_gather(g, c->stream));
-  t_end(c, PA_K_GATHER, e0, 2 * total * c->stride + 20 * total, 0);
   c->n_len = c->R;
-  c->cur ^= 1;
+  c->gather_pending = true;
   c->R = total;
   c->beta = beta_next;
   c->step += 1;
@@ -490,7 +520,9 @@ int pa_state(pa_ctx* c, int64_t* R, double* beta, int32_t* step) {
 int pa_get_population(pa_ctx* c, int8_t* spins, int32_t* E, int32_t* M,
                       int64_t cap) {
   if (!c || cap < c->R) return PA_EINVAL;
-  int rc = sync(c);
+  int rc = finish_gather(c);
+  if (rc) return rc;
+  rc = sync(c);
   if (rc) return rc;
   if (spins) {
     if (c->layout == PA_INT8) {
@@ -514,7 +546,9 @@ int pa_get_replicas(pa_ctx* c, const int64_t* slots, int64_t k, int8_t* spins,
   if (!c || (k > 0 && !slots) || k < 0) return PA_EINVAL;
   for (int64_t i = 0; i < k; ++i)
     if (slots[i] < 0 || slots[i] >= c->R) return PA_EINVAL;
-  int rc = sync(c);
+  int rc = finish_gather(c);
+  if (rc) return rc;
+  rc = sync(c);
   if (rc) return rc;
   std::vector<uint8_t> tmp((size_t)c->stride);
   for (int64_t i = 0; i < k; ++i) {
@@ -546,6 +580,7 @@ int pa_set_population(pa_ctx* c, const int8_t* spins, int64_t R) {
     if (spins[i] != 1 && spins[i] != -1) return PA_EINVAL;
   int rc = sync(c);
   if (rc) return rc;
+  c->gather_pending = false;  // the new population replaces the pending one
   std::vector<uint8_t> tmp((size_t)(R * c->stride));
   for (int64_t j = 0; j < R; ++j)
     pack_replica(c, spins + j * c->N, tmp.data() + j * c->stride);

@@ -8,10 +8,13 @@
 // (pa_init / pa_resample / pa_sweep) produces.  What changes is the launch
 // structure:
 //   - segmented kernels (grid y = population) for the histogram, copy
-//     counts, scan, parent scatter and gather, reading every population's
-//     size from device memory;
+//     counts, scan and parent scatter, reading every population's size from
+//     device memory;
 //   - one persistent sweep kernel per row-width class that pulls (population,
-//     wave) work items from a device queue, largest lattices first;
+//     wave) work items from a device queue, largest lattices first, and
+//     loads every new slot straight from its parent (the resampling copy
+//     costs no pass of its own; a separate gather runs only for populations
+//     without sweeps at the new temperature);
 //   - one device->host copy of all histograms, one host function building
 //     every population's double-precision tables (and next beta), one
 //     host->device copy of all tables per step;
@@ -199,12 +202,14 @@ __global__ __launch_bounds__(256) void k_bscatter(const BatchPop* P,
 }
 
 // Grid-stride over row groups of every population (grid y = population).
+// Only populations without sweeps at the new temperature: the sweep kernel
+// reads every other population's new slots from their parents directly.
 __global__ __launch_bounds__(256) void k_bgather(const BatchPop* P,
                                                  const BatchStep* S,
                                                  const int64_t* Rnew,
                                                  const int32_t* cur) {
   const int p = blockIdx.y;
-  if (!S[p].active) return;
+  if (!S[p].active || S[p].theta > 0) return;
   const BatchPop& q = P[p];
   const int64_t Rn = min(Rnew[p], q.cap);
   const int c = cur[p];
@@ -388,7 +393,11 @@ __global__ __launch_bounds__(256) void k_bsweep(
     const BatchStep& st = S[p];
     const int c = cur[p];
     LatticeArgs a;
+    // the population was resampled at this step (k_bcommit made buffer c
+    // current): each new slot is read from its parent in buffer c ^ 1
     a.spins = q.spins[c];
+    a.src = q.spins[c ^ 1];
+    a.parent = q.parent;
     a.E = q.E[c];
     a.M = q.M[c];
     a.jbits = q.jbits;
@@ -497,6 +506,9 @@ struct pa_batch {
   int64_t overlap_evals = 0;  // exact overlap evaluations by the host
   double host_ms = 0.0;       // time spent in the host function
   int record = 0;
+  int rec_rows = 0;      // rows of the per-step records allocated so far
+  int rec_rows_max = 0;  // rows the run can need
+  int n_active = 0;      // populations that moved in the last host step
   // graphs of the kernels before and after the host function
   hipGraph_t graph = nullptr, graph2 = nullptr;
   hipGraphExec_t exec = nullptr, exec2 = nullptr;
@@ -523,6 +535,20 @@ BatchStep* up_steps(pa_batch* b) {
   return reinterpret_cast<BatchStep*>(b->h_up);
 }
 
+// Per-step records grow with the run (an adaptive run's length is unknown).
+void grow_records(pa_batch* b, int rows) {
+  if (rows <= b->rec_rows) return;
+  rows = std::min(std::max(rows, 2 * b->rec_rows), b->rec_rows_max);
+  const size_t n = (size_t)rows * b->n;
+  b->traj.resize(n, pa_obs{});
+  b->traj_lnZ.resize(n, 0.0);
+  b->dec_feat.resize(n * kFeatures, 0.0f);
+  b->dec_dbeta.resize(n, 0.0);
+  b->dec_prop.resize(n, 0.0f);
+  b->dec_src.resize(n, -1);
+  b->rec_rows = rows;
+}
+
 // The host part of one step, between the two kernel sequences:
 // observables of every population after the previous sweeps, the next beta
 // of every population, its tables and Metropolis thresholds.
@@ -534,6 +560,8 @@ void host_step(void* ud) {
   BatchStep* st = up_steps(b);
   const bool last = (b->mode == 0) ? (b->pos >= b->sched_steps)
                                    : (b->pos >= b->adaptive_max_steps);
+  grow_records(b, b->pos + 1);
+  int active = 0;
   for (int p = 0; p < b->n; ++p) {
     PopHost& q = b->pops[p];
     const uint32_t* h = reinterpret_cast<const uint32_t*>(b->h_rb + q.rb_hist);
@@ -618,6 +646,7 @@ void host_step(void* ud) {
     s.step = (uint32_t)(q.step + 1);
     s.theta = b->theta;
     s.active = 1;
+    ++active;
     q.lnQ_last = tr.lnQ;
     q.lnZ = q.lnZ + tr.lnQ;  // Eq. Free-En, read with the logarithm
     q.beta = beta_next;
@@ -625,6 +654,7 @@ void host_step(void* ud) {
     q.moved = 1;
     s.beta = beta_next;
   }
+  b->n_active = active;
   b->pos += 1;
   b->host_ms += std::chrono::duration<double, std::milli>(
                     std::chrono::steady_clock::now() - t0).count();
@@ -1106,12 +1136,15 @@ static int batch_run(pa_batch* b, int steps, int use_graph) {
   b->pos = 0;
   const int total = steps + 1;  // the extra pass only measures
   b->record = 1;
-  b->traj.assign((size_t)steps * b->n, pa_obs{});
-  b->traj_lnZ.assign((size_t)steps * b->n, 0.0);
-  b->dec_feat.assign((size_t)steps * b->n * kFeatures, 0.0f);
-  b->dec_dbeta.assign((size_t)steps * b->n, 0.0);
-  b->dec_prop.assign((size_t)steps * b->n, 0.0f);
-  b->dec_src.assign((size_t)steps * b->n, -1);
+  b->traj.clear();
+  b->traj_lnZ.clear();
+  b->dec_feat.clear();
+  b->dec_dbeta.clear();
+  b->dec_prop.clear();
+  b->dec_src.clear();
+  b->rec_rows = 0;
+  b->rec_rows_max = steps;
+  grow_records(b, std::min(steps, 256));
   for (auto& c : b->src_count) c = 0;
   b->overlap_evals = 0;
   b->host_ms = 0.0;
@@ -1136,6 +1169,9 @@ static int batch_run(pa_batch* b, int steps, int use_graph) {
   for (int i = 0; i < total; ++i) {
     const int rc = use_graph ? step_graph(b) : step_eager(b);
     if (rc) return rc;
+    // an adaptive run ends once every population has reached beta_f (this
+    // pass recorded the observables of their last step)
+    if (b->mode != 0 && b->n_active == 0) break;
   }
   BK(hipStreamSynchronize(b->stream));
   return check_flags(b);

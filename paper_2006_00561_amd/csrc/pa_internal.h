@@ -12,6 +12,11 @@ struct LatticeArgs {
   uint8_t* spins;         // buffer base; replica j at spins + j * stride
   int32_t* E;
   int32_t* M;
+  // resampling copies fused into the pass: when parent is set, replica j is
+  // read from src + parent[j] * stride (the other buffer) instead of its own
+  // slot, and written to its own slot of `spins`
+  const uint8_t* src;
+  const uint32_t* parent;
   const uint32_t* jbits;  // +-J couplings, [2][L][W] bits, set where J < 0
   int64_t R;              // replicas to process
   int64_t stride;         // bytes per replica (multiple of 16)

@@ -8,7 +8,9 @@
 //              vertical neighbours come from the adjacent lanes through
 //              ds_bpermute, horizontal ones from in-register shifts.  The
 //              lattice is read from HBM once and written once per call,
-//              whatever theta is.
+//              whatever theta is.  After a resampling the call reads every
+//              new slot from its parent in the other buffer, so the
+//              resampling copy needs no pass of its own.
 //  k_hist      exact energy histogram + |M| and M^2 sums (Eqs. part-Q/tau
 //              need only the energy distribution).
 //  k_counts    copy counts floor(rho) + Bernoulli(frac rho) per replica from
@@ -16,7 +18,8 @@
 //  k_scan      exclusive scan of the tile sums (single workgroup).
 //  k_scatter   per-tile scan of the counts -> parent index of every new slot.
 //  k_gather    copy of every parent's lattice, E and M into its new slots of
-//              the second buffer (16-byte chunks, one wave per row group).
+//              the second buffer (16-byte chunks, one wave per row group),
+//              when no sweep follows the resampling.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 

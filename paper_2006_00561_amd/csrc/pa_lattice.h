@@ -129,6 +129,10 @@ __device__ __forceinline__ void lattice_pass(const LatticeArgs& a,
   const int dn_lane = active ? base + (lr == a.lpr - 1 ? 0 : lr + 1) : lane;
   const uint32_t slot = (uint32_t)(active ? rep : 0);
   uint8_t* rp = a.spins + (size_t)slot * (size_t)a.stride;
+  // where the replica's spins come from: its own slot, or its parent's slot
+  // of the other buffer when the resampling copy is fused into this pass
+  const uint8_t* lp =
+      a.parent ? a.src + (size_t)a.parent[slot] * (size_t)a.stride : rp;
 
   uint32_t s[RPL][W];
   // couplings: jr = bond to the right, jl = bond to the left (jr of x-1),
@@ -172,7 +176,7 @@ __device__ __forceinline__ void lattice_pass(const LatticeArgs& a,
         s[r][w] = v & valid_mask(L, w);
       }
     } else if (active) {
-      load_row<W, RPL, INT8>(rp, L, y, s[r]);
+      load_row<W, RPL, INT8>(lp, L, y, s[r]);
     } else {
 #pragma unroll
       for (int w = 0; w < W; ++w) s[r][w] = 0u;

@@ -218,8 +218,15 @@ def test_timing_counters(pa):
         g.sweep(b, 4)
     t = g.timing()
     assert t["sweep"]["launches"] == 3 and t["sweep"]["ms"] > 0
-    assert t["gather"]["launches"] == 3 and t["hist"]["launches"] == 3
+    # the sweeps made the resampling copies: no gather of its own
+    assert t["gather"]["launches"] == 0 and t["hist"]["launches"] == 3
     assert t["attempts"] > 3 * 4 * 32 * 32 * 900
+    # a read of the population before the sweep needs the gather
+    g.resample(0.6)
+    g.energies()
+    g.sweep(0.6, 1)
+    t = g.timing()
+    assert t["gather"]["launches"] == 1 and t["sweep"]["launches"] == 4
 
 
 @pytest.mark.parametrize("name,steps,sample", [("C2", 3, 48), ("C3a", 2, 24),
@@ -272,3 +279,73 @@ def test_full_size_sampled(pa, name, steps, sample):
         assert ob["sumAbsM"] == int(np.abs(M2.astype(np.int64)).sum())
         assert ob["sumM2"] == int((M2.astype(np.int64) ** 2).sum())
     g.close()
+
+
+@pytest.mark.parametrize("layout,glass", [(0, False), (1, True)])
+def test_resampling_copies_in_every_call_order(pa, layout, glass):
+    """The copies of a resampling are made by the next sweep or, before any
+    other read of the population, by a plain gather: every order of calls
+    after a resampling must give the oracle's population."""
+    L, R = 12, 600
+    J = W.pmj_couplings(L, 77) if glass else None
+    g = pa.Population(L, R, seed=4, population_id=3, J=J, layout=layout)
+    o = oracle.OraclePA(L, R, seed=4, pop=3, J=J)
+    betas = iter(W.linear_schedule(1.4, 14))
+
+    def step():
+        b = next(betas)
+        assert g.resample(b) == o.resample(b)
+        return b
+
+    # resample, then sweep (copies fused into the sweep)
+    b = step()
+    g.sweep(b, 3)
+    o.sweep(3)
+    _cmp_state(g, o, "fused")
+    # resample, energies only, then sweep
+    b = step()
+    Eg, Mg = g.energies()
+    Eo, Mo = o.energies()
+    assert np.array_equal(Eg, Eo) and np.array_equal(Mg, Mo)
+    g.sweep(b, 2)
+    o.sweep(2)
+    _cmp_state(g, o, "energies first")
+    # two resamplings in a row, then a sweep
+    step()
+    b = step()
+    g.sweep(b, 2)
+    o.sweep(2)
+    _cmp_state(g, o, "back to back")
+    # resample, zero sweeps, observables, then sweeps
+    b = step()
+    g.sweep(b, 0)
+    o.sweep(0)
+    _cmp_obs(g.observables(), o.observables())
+    g.sweep(b, 2)
+    o.sweep(2)
+    _cmp_state(g, o, "zero sweeps")
+    # resample, single replicas, overlap and histogram, then sweep
+    b = step()
+    slots = [0, g.R // 2, g.R - 1]
+    s1, E1, M1 = g.replicas(slots)
+    so, Eo, Mo = o.population()
+    assert np.array_equal(s1, so[slots]) and np.array_equal(E1, Eo[slots])
+    hg, st = g.histogram()
+    assert np.array_equal(hg, o.histogram()[::st])
+    assert g.overlap(0.05) == o.overlap(0.05)
+    g.sweep(b, 1)
+    o.sweep(1)
+    _cmp_state(g, o, "replicas first")
+    # resample, then a new population replaces the resampled one
+    step()
+    spins = o.population()[0][:300].copy()
+    spins[:, 0, 0] *= -1
+    g.set_population(spins)
+    o.set_population(spins)
+    _cmp_state(g, o, "replaced")
+    b = step()
+    g.sweep(b, 2)
+    o.sweep(2)
+    _cmp_state(g, o, "after replacement")
+    g.close()
+    o.close()
