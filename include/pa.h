@@ -125,9 +125,13 @@ int pa_sweep(pa_ctx* c, double beta, int32_t theta);
    slot from its parent, or by a plain gather before any other call that
    reads the population; either way every later call sees the resampled
    population.  Advances beta and the step, adds ln Q to ln Z (Eq.
-   Free-En).  *R_new (may be NULL)
-   receives the new population size, also when it exceeds the capacity
-   (then PA_ECAPACITY and nothing changes). */
+   Free-En).  *R_new receives the new population size, also when it exceeds
+   the capacity (then PA_ECAPACITY and nothing changes); the call then waits
+   for the counts.  With R_new NULL the call does not wait when the tables
+   bound the new size within [1, capacity] (every replica gets floor(rho) or
+   floor(rho) + 1 copies): the kernels that follow read the size on the
+   device, and the host learns it at the next synchronising call.
+   Otherwise it waits and checks as above. */
 int pa_resample(pa_ctx* c, double beta_next, int64_t* R_new);
 
 /* Sec. 2, measurement after equilibration: population averages from exact
@@ -139,7 +143,8 @@ int pa_observables(pa_ctx* c, pa_obs* out);
    NULL.  No device work. */
 int pa_free_energy(pa_ctx* c, double* lnZ, double* lnQ_last);
 
-/* Current population size, beta and step index. */
+/* Current population size, beta and step index (synchronises when the
+   size of a resampled population has not reached the host yet). */
 int pa_state(pa_ctx* c, int64_t* R, double* beta, int32_t* step);
 
 /* Canonical export of the whole population into caller-owned host arrays of
@@ -180,9 +185,13 @@ int pa_overlap(pa_ctx* c, double dbeta, double* alpha);
 int pa_bisect_dbeta(pa_ctx* c, double target, double beta_f, double* dbeta);
 
 /* Per-kernel-class device timing with HIP events on the context's stream.
-   enable = 1 starts (and zeroes) the counters, 0 stops.  pa_get_timing
-   synchronises and reports the totals since the last enable. */
-int pa_set_timing(pa_ctx* c, int32_t enable);
+   classes: PA_TIMING_ALL times every class, otherwise a bit mask of the
+   classes to time (bit PA_K_SWEEP = 1 << PA_K_SWEEP, ...); a nonzero value
+   starts (and zeroes) the counters, 0 stops.  Each timed launch records two
+   events on the stream.  pa_get_timing synchronises and reports the totals
+   since timing was started. */
+#define PA_TIMING_ALL (-1)
+int pa_set_timing(pa_ctx* c, int32_t classes);
 int pa_get_timing(pa_ctx* c, pa_timing* out);
 
 void pa_destroy(pa_ctx* c);

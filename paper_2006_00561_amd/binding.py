@@ -20,6 +20,7 @@ PA_OK, PA_EINVAL, PA_ENOMEM, PA_ECAPACITY, PA_EDEVICE, PA_ESTATE, PA_EEMPTY = (
 PA_FERRO, PA_PMJ = 0, 1
 PA_INT8, PA_BITS = 0, 1
 KERNEL_CLASSES = ("init", "sweep", "hist", "counts", "scatter", "gather")
+PA_TIMING_ALL = -1
 
 
 class pa_config(C.Structure):
@@ -179,7 +180,13 @@ class Population:
     def sweep(self, beta, theta):
         _ck(lib().pa_sweep(self._h, beta, theta), "pa_sweep")
 
-    def resample(self, beta_next):
+    def resample(self, beta_next, wait=True):
+        """Resample to beta_next and return the new size; with wait=False
+        the call may return before the size is known (returns None) and the
+        next synchronising call brings it to the host."""
+        if not wait:
+            _ck(lib().pa_resample(self._h, beta_next, None), "pa_resample")
+            return None
         Rn = C.c_int64()
         _ck(lib().pa_resample(self._h, beta_next, C.byref(Rn)), "pa_resample")
         return Rn.value
@@ -279,8 +286,18 @@ class Population:
             "pa_bisect_dbeta")
         return d.value
 
-    def set_timing(self, enable=True):
-        _ck(lib().pa_set_timing(self._h, 1 if enable else 0), "pa_set_timing")
+    def set_timing(self, enable=True, classes=None):
+        """Start (zeroed) or stop the per-class kernel timing; classes is an
+        iterable of KERNEL_CLASSES names to time (default: all)."""
+        if not enable:
+            mask = 0
+        elif classes is None:
+            mask = PA_TIMING_ALL
+        else:
+            mask = 0
+            for k in classes:
+                mask |= 1 << KERNEL_CLASSES.index(k)
+        _ck(lib().pa_set_timing(self._h, mask), "pa_set_timing")
 
     def timing(self):
         t = pa_timing()

@@ -27,6 +27,9 @@ struct TimedLaunch {
   int cls;
   hipEvent_t ev0, ev1;
   int64_t bytes, attempts;
+  // parts proportional to a population size that was not yet known on the
+  // host at launch time; multiplied by it when the launch is harvested
+  int64_t bytes_rep, attempts_rep;
 };
 
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
@@ -49,21 +52,33 @@ struct pa_ctx {
   uint32_t* parent = nullptr;
   uint32_t* tile_sum = nullptr;
   uint32_t* tile_off = nullptr;
-  uint32_t* hist = nullptr;
-  uint32_t* tab = nullptr;              // [2][nbins]: f then T
-  unsigned long long* scal = nullptr;   // sum|M|, sum M^2, total, survivors
+  // Read-back block, one device->host copy per histogram: the histogram
+  // (nbins words, padded to an even count nb2), then scal = [0] sum|M|,
+  // [1] sum M^2, [2] unused, [3] energies outside the histogram, all
+  // cleared before every histogram, and [4] the size of the last resampled
+  // population.
+  uint32_t* rb = nullptr;
+  uint32_t* hist = nullptr;             // rb
+  unsigned long long* scal = nullptr;   // rb + nb2
+  uint32_t* tab = nullptr;              // f[nl] then T[nl] of the last step
   uint32_t* jbits = nullptr;
-  uint32_t* h_hist = nullptr;           // pinned host mirrors
+  uint32_t* h_rb = nullptr;             // pinned host mirror of rb
+  uint32_t* h_hist = nullptr;
   unsigned long long* h_scal = nullptr;
-  uint32_t* h_tab = nullptr;
-  int nbins = 0, hshift = 0;
+  uint32_t* h_tab = nullptr;            // pinned, 2 * nbins words
+  int nbins = 0, nb2 = 0, hshift = 0;
   bool hist_valid = false;
+  bool rb_zero = false;  // the cleared part of rb is known to be zero
   // pa_resample left the copies to the next sweep: parent[] holds the
   // parent of each of the R new slots, the buffer `cur` still the old
   // population
   bool gather_pending = false;
+  // pa_resample did not wait for the new population size: R holds an exact
+  // upper bound (grid sizes), the size itself is in scal[4] on the device
+  // and reaches the host at the next synchronisation
+  bool R_pending = false;
   int64_t n_len = 0;
-  bool timing = false;
+  uint32_t timing = 0;  // bit k set: launches of class k are timed
   std::vector<TimedLaunch> pending;
   std::vector<hipEvent_t> pool;
   pa_timing acc{};
@@ -86,20 +101,27 @@ hipEvent_t take_event(pa_ctx* c) {
   return e;
 }
 
-hipEvent_t t_begin(pa_ctx* c) {
-  if (!c->timing) return nullptr;
+hipEvent_t t_begin(pa_ctx* c, int cls) {
+  if (!(c->timing >> cls & 1u)) return nullptr;
   hipEvent_t e = take_event(c);
   if (e) (void)hipEventRecord(e, c->stream);
   return e;
 }
 
+// bytes and attempts of the launch: fixed parts plus parts per replica of
+// the current population
 void t_end(pa_ctx* c, int cls, hipEvent_t e0, int64_t bytes,
-           int64_t attempts) {
-  if (!c->timing || !e0) return;
+           int64_t attempts, int64_t bytes_rep = 0, int64_t attempts_rep = 0) {
+  if (!e0) return;
   hipEvent_t e1 = take_event(c);
   if (!e1) return;
   (void)hipEventRecord(e1, c->stream);
-  c->pending.push_back({cls, e0, e1, bytes, attempts});
+  if (!c->R_pending) {
+    bytes += bytes_rep * c->R;
+    attempts += attempts_rep * c->R;
+    bytes_rep = attempts_rep = 0;
+  }
+  c->pending.push_back({cls, e0, e1, bytes, attempts, bytes_rep, attempts_rep});
 }
 
 // After a stream synchronisation: fold finished launches into the totals.
@@ -109,8 +131,8 @@ void t_harvest(pa_ctx* c) {
     if (hipEventElapsedTime(&ms, t.ev0, t.ev1) == hipSuccess) {
       c->acc.ms[t.cls] += ms;
       c->acc.launches[t.cls] += 1;
-      c->acc.bytes[t.cls] += t.bytes;
-      c->acc.attempts += t.attempts;
+      c->acc.bytes[t.cls] += t.bytes + t.bytes_rep * c->R;
+      c->acc.attempts += t.attempts + t.attempts_rep * c->R;
     }
     c->pool.push_back(t.ev0);
     c->pool.push_back(t.ev1);
@@ -118,8 +140,16 @@ void t_harvest(pa_ctx* c) {
   c->pending.clear();
 }
 
-int sync(pa_ctx* c) {
+// size_copied: the caller already queued the copy of scal[4] to the host.
+int sync(pa_ctx* c, bool size_copied = false) {
+  if (c->R_pending && !size_copied)
+    CK(hipMemcpyAsync(c->h_scal + 4, c->scal + 4, sizeof(unsigned long long),
+                      hipMemcpyDeviceToHost, c->stream));
   CK(hipStreamSynchronize(c->stream));
+  if (c->R_pending) {
+    c->R = (int64_t)c->h_scal[4];
+    c->R_pending = false;
+  }
   t_harvest(c);
   return PA_OK;
 }
@@ -133,6 +163,7 @@ LatticeArgs lattice_args(pa_ctx* c) {
   a.M = c->M[c->cur];
   a.jbits = c->jbits;
   a.R = c->R;
+  a.Rdev = c->R_pending ? c->scal + 4 : nullptr;
   a.stride = c->stride;
   a.L = c->L;
   a.lpr = c->lpr;
@@ -147,11 +178,11 @@ LatticeArgs lattice_args(pa_ctx* c) {
 }
 
 int run_lattice(pa_ctx* c, LatticeArgs& a, int cls) {
-  hipEvent_t e0 = t_begin(c);
+  hipEvent_t e0 = t_begin(c, cls);
   CK(launch_lattice(a, c->W, c->rpl, c->layout == PA_INT8, c->model == PA_PMJ,
                     c->stream));
-  t_end(c, cls, e0, (a.init ? 1 : 2) * c->R * c->stride + 8 * c->R,
-        (int64_t)c->R * c->N * a.theta);
+  t_end(c, cls, e0, 0, 0, (a.init ? 1 : 2) * c->stride + 8,
+        (int64_t)c->N * a.theta);
   return PA_OK;
 }
 
@@ -159,6 +190,10 @@ int run_lattice(pa_ctx* c, LatticeArgs& a, int cls) {
 // over: every new slot receives its parent's lattice, E and M.
 int finish_gather(pa_ctx* c) {
   if (!c->gather_pending) return PA_OK;
+  if (c->R_pending) {
+    const int rs = sync(c);
+    if (rs) return rs;
+  }
   GatherArgs g{};
   g.src = c->spins[c->cur];
   g.dst = c->spins[c->cur ^ 1];
@@ -173,7 +208,7 @@ int finish_gather(pa_ctx* c) {
   int lg = 0;
   while ((1 << lg) < g.chunks && lg < 6) ++lg;
   g.lpr_log2 = lg;
-  hipEvent_t e0 = t_begin(c);
+  hipEvent_t e0 = t_begin(c, PA_K_GATHER);
   CK(launch_gather(g, c->stream));
   t_end(c, PA_K_GATHER, e0, 2 * c->R * c->stride + 20 * c->R, 0);
   c->cur ^= 1;
@@ -187,26 +222,29 @@ int compute_hist(pa_ctx* c) {
   if (c->hist_valid) return PA_OK;
   const int rg = finish_gather(c);
   if (rg) return rg;
-  CK(launch_fill_u32(c->hist, c->nbins, 0u, c->stream));
-  CK(launch_fill_u32(reinterpret_cast<uint32_t*>(c->scal), 8, 0u, c->stream));
+  // the histogram and moments start from zero (k_counts of the last
+  // resampling cleared them unless something else ran since)
+  if (!c->rb_zero)
+    CK(launch_fill_u32(c->rb, c->nb2 + 8, 0u, c->stream));
   HistArgs h{};
   h.E = c->E[c->cur];
   h.M = c->M[c->cur];
   h.hist = c->hist;
   h.moments = c->scal;
   h.R = c->R;
+  h.Rdev = c->R_pending ? c->scal + 4 : nullptr;
   h.twoN = 2 * c->N;
   h.shift = c->hshift;
   h.nbins = c->nbins;
   h.use_lds = (int64_t)c->nbins * 4 <= 64 * 1024;
-  hipEvent_t e0 = t_begin(c);
+  hipEvent_t e0 = t_begin(c, PA_K_HIST);
   CK(launch_hist(h, c->stream));
-  t_end(c, PA_K_HIST, e0, 8 * c->R, 0);
-  CK(hipMemcpyAsync(c->h_hist, c->hist, (size_t)c->nbins * 4,
+  t_end(c, PA_K_HIST, e0, 0, 0, 8, 0);
+  c->rb_zero = false;
+  // histogram, moments and population size in one copy
+  CK(hipMemcpyAsync(c->h_rb, c->rb, ((size_t)c->nb2 + 10) * 4,
                     hipMemcpyDeviceToHost, c->stream));
-  CK(hipMemcpyAsync(c->h_scal, c->scal, 4 * sizeof(unsigned long long),
-                    hipMemcpyDeviceToHost, c->stream));
-  int rc = sync(c);
+  int rc = sync(c, true);
   if (rc) return rc;
   if (c->h_scal[3] != 0) return PA_EDEVICE;  // an energy outside [-2N, 2N]
   c->hist_valid = true;
@@ -219,12 +257,11 @@ void free_all(pa_ctx* c) {
     if (c->E[b]) (void)hipFree(c->E[b]);
     if (c->M[b]) (void)hipFree(c->M[b]);
   }
-  void* dev[] = {c->n, c->parent, c->tile_sum, c->tile_off, c->hist, c->tab,
-                 c->scal, c->jbits};
+  void* dev[] = {c->n, c->parent, c->tile_sum, c->tile_off, c->rb, c->tab,
+                 c->jbits};
   for (void* p : dev)
     if (p) (void)hipFree(p);
-  if (c->h_hist) (void)hipHostFree(c->h_hist);
-  if (c->h_scal) (void)hipHostFree(c->h_scal);
+  if (c->h_rb) (void)hipHostFree(c->h_rb);
   if (c->h_tab) (void)hipHostFree(c->h_tab);
   for (auto& t : c->pending) {
     (void)hipEventDestroy(t.ev0);
@@ -342,14 +379,12 @@ int pa_init(const pa_config* cfg, pa_ctx** out) {
   ok = ok && dmalloc(&c->parent, (size_t)cap * 4);
   ok = ok && dmalloc(&c->tile_sum, (size_t)c->ntiles_cap * 4);
   ok = ok && dmalloc(&c->tile_off, (size_t)c->ntiles_cap * 4);
-  ok = ok && dmalloc(&c->hist, (size_t)c->nbins * 4);
+  c->nb2 = (c->nbins + 1) & ~1;
+  ok = ok && dmalloc(&c->rb, ((size_t)c->nb2 + 16) * 4);
   ok = ok && dmalloc(&c->tab, (size_t)c->nbins * 8);
-  ok = ok && dmalloc(&c->scal, 4 * sizeof(unsigned long long));
   ok = ok && dmalloc(&c->jbits, (size_t)2 * L * W * 4);
-  ok = ok && hipHostMalloc(reinterpret_cast<void**>(&c->h_hist),
-                           (size_t)c->nbins * 4) == hipSuccess;
-  ok = ok && hipHostMalloc(reinterpret_cast<void**>(&c->h_scal),
-                           4 * sizeof(unsigned long long)) == hipSuccess;
+  ok = ok && hipHostMalloc(reinterpret_cast<void**>(&c->h_rb),
+                           ((size_t)c->nb2 + 16) * 4) == hipSuccess;
   ok = ok && hipHostMalloc(reinterpret_cast<void**>(&c->h_tab),
                            (size_t)c->nbins * 8) == hipSuccess;
   if (!ok) {
@@ -357,6 +392,10 @@ int pa_init(const pa_config* cfg, pa_ctx** out) {
     delete c;
     return PA_ENOMEM;
   }
+  c->hist = c->rb;
+  c->scal = reinterpret_cast<unsigned long long*>(c->rb + c->nb2);
+  c->h_hist = c->h_rb;
+  c->h_scal = reinterpret_cast<unsigned long long*>(c->h_rb + c->nb2);
   // +-J couplings as row bit masks, bit set where J < 0
   std::vector<uint32_t> jb((size_t)2 * L * W, 0u);
   if (c->model == PA_PMJ)
@@ -439,13 +478,21 @@ int pa_resample(pa_ctx* c, double beta_next, int64_t* R_new) {
   if (rc) return rc;
   const int lo = tr.lo, nl = tr.hi - tr.lo + 1;
   const double lnQ = tr.lnQ;
-  CK(hipMemcpyAsync(c->tab, c->h_tab, (size_t)nbins * 8,
-                    hipMemcpyHostToDevice, c->stream));
-  // (e) copy counts and their exclusive scan
+  // only the occupied levels go to the device: f[nl] then T[nl]
+  uint32_t* hf = c->h_tab;
+  uint32_t* hT = c->h_tab + nl;
+  std::memmove(hT, c->h_tab + nbins, (size_t)nl * 4);
+  CK(hipMemcpyAsync(c->tab, c->h_tab, (size_t)nl * 8, hipMemcpyHostToDevice,
+                    c->stream));
+  // (e) copy counts and their exclusive scan; the counts kernel also clears
+  // the histogram and moments for the next step (their copy to the host
+  // precedes it on the stream)
   CountsArgs ca{};
   ca.E = c->E[c->cur];
   ca.f = c->tab;
-  ca.T = c->tab + nbins;
+  ca.T = c->tab + nl;
+  ca.clear = c->rb;
+  ca.nclear = c->nb2 + 8;
   ca.n = c->n;
   ca.tile_sum = c->tile_sum;
   ca.R = c->R;
@@ -458,32 +505,50 @@ int pa_resample(pa_ctx* c, double beta_next, int64_t* R_new) {
   ca.pop = c->pop;
   ca.step_next = (uint32_t)(c->step + 1);
   const int64_t ntiles = (c->R + 255) / 256;
-  hipEvent_t e0 = t_begin(c);
-  CK(launch_counts(ca, c->stream));
-  CK(launch_scan(c->tile_sum, c->tile_off, ntiles, c->scal + 2, c->stream));
-  t_end(c, PA_K_COUNTS, e0, 8 * c->R + 8 * ntiles, 0);
-  CK(hipMemcpyAsync(c->h_scal + 2, c->scal + 2, sizeof(unsigned long long),
-                    hipMemcpyDeviceToHost, c->stream));
-  rc = sync(c);
-  if (rc) return rc;
-  const int64_t total = (int64_t)c->h_scal[2];
-  if (R_new) *R_new = total;
-  if (total > c->cap) {
-    c->n_len = 0;
-    return PA_ECAPACITY;
+  // exact bounds of the new size: every replica at level l gets f or f + 1
+  // copies, f + 1 only where its threshold is nonzero
+  int64_t r_min = 0, r_max = 0;
+  for (int i = lo; i <= tr.hi; ++i) {
+    const int64_t h = c->h_hist[i];
+    r_min += h * (int64_t)hf[i - lo];
+    r_max += h * ((int64_t)hf[i - lo] + (hT[i - lo] ? 1 : 0));
   }
-  if (total == 0) {
-    c->n_len = 0;
-    return PA_EEMPTY;
+  // the size need not reach the host now when it cannot be out of range and
+  // the caller did not ask for it: the next synchronisation brings it
+  const bool deferred = !R_new && r_min >= 1 && r_max <= c->cap;
+  hipEvent_t e0 = t_begin(c, PA_K_COUNTS);
+  CK(launch_counts(ca, c->stream));
+  CK(launch_scan(c->tile_sum, c->tile_off, ntiles, c->scal + 4, c->stream));
+  t_end(c, PA_K_COUNTS, e0, 8 * c->R + 8 * ntiles, 0);
+  c->rb_zero = true;
+  const int64_t R_old = c->R;
+  if (!deferred) {
+    CK(hipMemcpyAsync(c->h_scal + 4, c->scal + 4, sizeof(unsigned long long),
+                      hipMemcpyDeviceToHost, c->stream));
+    rc = sync(c);
+    if (rc) return rc;
+    const int64_t total = (int64_t)c->h_scal[4];
+    if (R_new) *R_new = total;
+    if (total > c->cap) {
+      c->n_len = 0;
+      return PA_ECAPACITY;
+    }
+    if (total == 0) {
+      c->n_len = 0;
+      return PA_EEMPTY;
+    }
+    c->R = total;
+  } else {
+    c->R = r_max;
+    c->R_pending = true;
   }
   // (f) parent of every new slot; the copies into the other buffer are left
   // to the next sweep, which reads every new slot from its parent
-  e0 = t_begin(c);
-  CK(launch_scatter(c->n, c->tile_off, c->R, c->cap, c->parent, c->stream));
-  t_end(c, PA_K_SCATTER, e0, 4 * c->R + 4 * total, 0);
-  c->n_len = c->R;
+  e0 = t_begin(c, PA_K_SCATTER);
+  CK(launch_scatter(c->n, c->tile_off, R_old, c->cap, c->parent, c->stream));
+  t_end(c, PA_K_SCATTER, e0, 4 * R_old, 0, 4, 0);
+  c->n_len = R_old;
   c->gather_pending = true;
-  c->R = total;
   c->beta = beta_next;
   c->step += 1;
   c->sweeps_at_step = 0;
@@ -511,6 +576,10 @@ int pa_free_energy(pa_ctx* c, double* lnZ, double* lnQ_last) {
 
 int pa_state(pa_ctx* c, int64_t* R, double* beta, int32_t* step) {
   if (!c) return PA_EINVAL;
+  if (R && c->R_pending) {
+    const int rc = sync(c);
+    if (rc) return rc;
+  }
   if (R) *R = c->R;
   if (beta) *beta = c->beta;
   if (step) *step = c->step;
@@ -519,8 +588,11 @@ int pa_state(pa_ctx* c, int64_t* R, double* beta, int32_t* step) {
 
 int pa_get_population(pa_ctx* c, int8_t* spins, int32_t* E, int32_t* M,
                       int64_t cap) {
-  if (!c || cap < c->R) return PA_EINVAL;
-  int rc = finish_gather(c);
+  if (!c) return PA_EINVAL;
+  int rc = sync(c);  // the population size, if still on the device
+  if (rc) return rc;
+  if (cap < c->R) return PA_EINVAL;
+  rc = finish_gather(c);
   if (rc) return rc;
   rc = sync(c);
   if (rc) return rc;
@@ -544,9 +616,11 @@ int pa_get_population(pa_ctx* c, int8_t* spins, int32_t* E, int32_t* M,
 int pa_get_replicas(pa_ctx* c, const int64_t* slots, int64_t k, int8_t* spins,
                     int32_t* E, int32_t* M) {
   if (!c || (k > 0 && !slots) || k < 0) return PA_EINVAL;
+  int rc = sync(c);  // the population size, if still on the device
+  if (rc) return rc;
   for (int64_t i = 0; i < k; ++i)
     if (slots[i] < 0 || slots[i] >= c->R) return PA_EINVAL;
-  int rc = finish_gather(c);
+  rc = finish_gather(c);
   if (rc) return rc;
   rc = sync(c);
   if (rc) return rc;
@@ -628,11 +702,11 @@ int pa_bisect_dbeta(pa_ctx* c, double target, double beta_f, double* dbeta) {
   return PA_OK;
 }
 
-int pa_set_timing(pa_ctx* c, int32_t enable) {
+int pa_set_timing(pa_ctx* c, int32_t classes) {
   if (!c) return PA_EINVAL;
   int rc = sync(c);
   if (rc) return rc;
-  c->timing = enable != 0;
+  c->timing = (classes == PA_TIMING_ALL) ? 0x3Fu : ((uint32_t)classes & 0x3Fu);
   if (c->timing) c->acc = pa_timing{};
   return PA_OK;
 }

@@ -398,6 +398,7 @@ __global__ __launch_bounds__(256) void k_bsweep(
     a.spins = q.spins[c];
     a.src = q.spins[c ^ 1];
     a.parent = q.parent;
+    a.Rdev = nullptr;
     a.E = q.E[c];
     a.M = q.M[c];
     a.jbits = q.jbits;
@@ -878,7 +879,7 @@ int pa_tune_rows_per_lane(int32_t L, int32_t layout, int32_t model,
     if (rc) return rc;
     rc = pa_resample(c, 0.4, nullptr);
     if (!rc) rc = pa_sweep(c, 0.4, 1);  // warm-up
-    if (!rc) rc = pa_set_timing(c, 1);
+    if (!rc) rc = pa_set_timing(c, 1 << PA_K_SWEEP);
     if (!rc) rc = pa_sweep(c, 0.4, theta);
     if (!rc) rc = pa_sweep(c, 0.4, theta);
     pa_timing tm{};

@@ -17,6 +17,9 @@ struct LatticeArgs {
   // slot, and written to its own slot of `spins`
   const uint8_t* src;
   const uint32_t* parent;
+  // when set, the replica count is min(*Rdev, R): R is then only a bound
+  // (the grid size) and the exact count is still on the device
+  const unsigned long long* Rdev;
   const uint32_t* jbits;  // +-J couplings, [2][L][W] bits, set where J < 0
   int64_t R;              // replicas to process
   int64_t stride;         // bytes per replica (multiple of 16)
@@ -38,6 +41,7 @@ struct HistArgs {
   uint32_t* hist;
   unsigned long long* moments;  // [0] sum |M|, [1] sum M^2, [3] bad energies
   int64_t R;
+  const unsigned long long* Rdev;  // as in LatticeArgs
   int32_t twoN, shift, nbins, use_lds;
 };
 
@@ -47,6 +51,8 @@ struct CountsArgs {
   const uint32_t* T;  // 32-bit threshold of the fractional part per level
   uint32_t* n;
   uint32_t* tile_sum;
+  uint32_t* clear;    // words [0, nclear) set to zero on the way (may be null)
+  int64_t nclear;
   int64_t R;
   int32_t twoN, shift, lvl0, nlvl;
   uint32_t k0, k1, pop, step_next;

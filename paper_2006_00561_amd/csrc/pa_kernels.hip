@@ -14,7 +14,8 @@
 //  k_hist      exact energy histogram + |M| and M^2 sums (Eqs. part-Q/tau
 //              need only the energy distribution).
 //  k_counts    copy counts floor(rho) + Bernoulli(frac rho) per replica from
-//              the host's per-level tables, plus one partial sum per tile.
+//              the host's per-level tables, plus one partial sum per tile;
+//              clears the histogram of the next step on the way.
 //  k_scan      exclusive scan of the tile sums (single workgroup).
 //  k_scatter   per-tile scan of the counts -> parent index of every new slot.
 //  k_gather    copy of every parent's lattice, E and M into its new slots of
@@ -46,7 +47,8 @@ __global__ __launch_bounds__(256) void k_hist(HistArgs a) {
     __syncthreads();
   }
   unsigned long long sam = 0ull, sm2 = 0ull;
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < a.R;
+  const int64_t R = a.Rdev ? min((int64_t)*a.Rdev, a.R) : a.R;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < R;
        j += (int64_t)gridDim.x * blockDim.x) {
     const int idx = (a.E[j] + a.twoN) >> a.shift;
     if (idx < 0 || idx >= a.nbins) {  // corrupt energy: report, never index
@@ -104,6 +106,8 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* lds,
 __global__ __launch_bounds__(256) void k_counts(CountsArgs a) {
   __shared__ uint32_t lds[8];
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t i = j; i < a.nclear; i += (int64_t)gridDim.x * blockDim.x)
+    a.clear[i] = 0u;
   uint32_t nj = 0u;
   if (j < a.R) {
     const int l = ((a.E[j] + a.twoN) >> a.shift) - a.lvl0;

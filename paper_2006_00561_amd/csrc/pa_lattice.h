@@ -122,8 +122,12 @@ __device__ __forceinline__ void lattice_pass(const LatticeArgs& a,
   const int L = a.L;
   const int g = lane / a.lpr;
   const int lr = lane - g * a.lpr;
+  const int64_t R = a.Rdev ? min((int64_t)*a.Rdev, a.R) : a.R;
+  // a wave past the population has nothing to do (the grid may be sized
+  // for a bound of R); the pass has no workgroup barrier, so it may leave
+  if (wave * a.rpw >= R) return;
   const int64_t rep = wave * a.rpw + g;
-  const bool active = (g < a.rpw) && (rep < a.R);
+  const bool active = (g < a.rpw) && (rep < R);
   const int base = g * a.lpr;
   const int up_lane = active ? base + (lr == 0 ? a.lpr - 1 : lr - 1) : lane;
   const int dn_lane = active ? base + (lr == a.lpr - 1 ? 0 : lr + 1) : lane;

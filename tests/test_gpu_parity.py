@@ -227,6 +227,16 @@ def test_timing_counters(pa):
     g.sweep(0.6, 1)
     t = g.timing()
     assert t["gather"]["launches"] == 1 and t["sweep"]["launches"] == 4
+    # timing of the sweeps alone
+    g.set_timing(True, classes=("sweep",))
+    g.resample(0.7, wait=False)
+    g.sweep(0.7, 2)
+    g.observables()
+    t = g.timing()
+    assert t["sweep"]["launches"] == 1 and t["sweep"]["ms"] > 0
+    assert t["attempts"] == g.R * 32 * 32 * 2
+    for k in ("hist", "counts", "scatter", "gather"):
+        assert t[k]["launches"] == 0 and t[k]["ms"] == 0.0
 
 
 @pytest.mark.parametrize("name,steps,sample", [("C2", 3, 48), ("C3a", 2, 24),
@@ -348,4 +358,55 @@ def test_resampling_copies_in_every_call_order(pa, layout, glass):
     o.sweep(2)
     _cmp_state(g, o, "after replacement")
     g.close()
+    o.close()
+
+
+@pytest.mark.parametrize("layout,glass", [(0, False), (1, True)])
+def test_deferred_population_size_matches_waiting_path(pa, layout, glass):
+    """Resampling without waiting for the new size (the kernels read it on
+    the device) against the waiting path and the oracle: same populations,
+    sizes, ln Z, and the same timing totals."""
+    L, R, theta = 16, 900, 3
+    J = W.pmj_couplings(L, 21) if glass else None
+    fast = pa.Population(L, R, seed=6, population_id=1, J=J, layout=layout)
+    slow = pa.Population(L, R, seed=6, population_id=1, J=J, layout=layout)
+    o = oracle.OraclePA(L, R, seed=6, pop=1, J=J)
+    fast.set_timing(True)
+    slow.set_timing(True)
+    sizes = [R]
+    for i, b in enumerate(W.linear_schedule(1.2, 12), start=1):
+        assert fast.resample(b, wait=False) is None
+        rs = slow.resample(b)
+        ro = o.resample(b)
+        assert rs == ro
+        sizes.append(ro)
+        fast.sweep(b, theta)
+        slow.sweep(b, theta)
+        o.sweep(theta)
+        if i % 4 == 0:
+            assert fast.R == ro               # synchronises
+        oo = o.observables()
+        _cmp_obs(fast.observables(), oo)
+        _cmp_obs(slow.observables(), oo)
+    _cmp_state(fast, o, "deferred")
+    _cmp_state(slow, o, "waiting")
+    tf, ts = fast.timing(), slow.timing()
+    for k in ("sweep", "hist", "counts", "scatter"):
+        print(k, "deferred", tf[k]["launches"], tf[k]["bytes"],
+              "waiting", ts[k]["launches"], ts[k]["bytes"])
+    print("sizes", sizes, "sum", sum(sizes))
+    assert tf["attempts"] == ts["attempts"] == sum(sizes[1:]) * L * L * theta
+    # one histogram per step and one before the first resampling
+    assert tf["hist"]["launches"] == len(sizes)
+    assert tf["hist"]["bytes"] == ts["hist"]["bytes"] == 8 * sum(sizes)
+    for k in ("sweep", "hist", "counts", "scatter"):
+        assert tf[k]["launches"] == ts[k]["launches"], k
+        assert tf[k]["bytes"] == ts[k]["bytes"], k
+    # a deferred resampling followed directly by reads of the population
+    b = 1.3
+    fast.resample(b, wait=False)
+    o.resample(b)
+    _cmp_state(fast, o, "deferred, read before the sweep")
+    fast.close()
+    slow.close()
     o.close()
