@@ -157,15 +157,18 @@ def bench_batched(binding, stream, use_graph=True):
     bt.close()
     t0 = time.perf_counter()
     bt = binding.Batch(inst, autotune=True)
+    t_init = time.perf_counter() - t0
     bt.run(betas, theta, use_graph=use_graph)
     lnz_batch = [bt.state(p)[3] for p in range(len(inst))]
     t_batch = time.perf_counter() - t0
+    host_ms = bt.host_stats()["host_ms"]
     bt.close()
     return {
         "workload": "C4: 64 +-J EA instances, L in {8,12,16,24,32}, R "
                     "log-uniform in [2^10,2^16], beta 0->3 in 300 linear "
                     "steps, theta=10",
         "plain_s": t_plain, "batched_s": t_batch,
+        "batched_init_s": t_init, "batched_host_ms": host_ms,
         "speedup": t_plain / t_batch,
         "batched_attempts_per_ns": attempts / (t_batch * 1e9),
         "graph": bool(use_graph),
@@ -305,6 +308,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the batched comparison (for profiling)")
     ap.add_argument("--eager", action="store_true",
                     help="batched runs without HIP graphs")
     ap.add_argument("--summarize-profiles", nargs=3,
@@ -342,6 +347,10 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream().cuda_stream
+    if args.batched_only:
+        print(json.dumps(bench_batched(binding, stream,
+                                       use_graph=not args.eager)), flush=True)
+        return
     cfg = dict(W.CONFIGS[args.workload])
     cfg["name"] = args.workload
     if args.calibrate_copy:

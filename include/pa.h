@@ -331,8 +331,10 @@ int pa_batch_trajectory(pa_batch* b, int32_t p, pa_obs* obs, double* lnZ,
 int pa_batch_get_population(pa_batch* b, int32_t p, int8_t* spins, int32_t* E,
                             int32_t* M, int64_t cap);
 
-/* Workgroups of the persistent sweep kernel (default 2048). */
-int pa_batch_set_sweep_blocks(pa_batch* b, int32_t blocks);
+/* Launch shape of the persistent sweep kernel: workgroups (default 1024,
+   at most 65535) and work items taken per queue atomic (default 4,
+   1..1024).  Results do not depend on either. */
+int pa_batch_set_sweep_blocks(pa_batch* b, int32_t blocks, int32_t chunk);
 
 void pa_batch_destroy(pa_batch* b);
 

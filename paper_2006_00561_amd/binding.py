@@ -101,7 +101,7 @@ def lib():
             "pa_batch_trajectory": ([P, i32, P, P, i32, C.POINTER(i32)],
                                     C.c_int),
             "pa_batch_get_population": ([P, i32, P, P, P, i64], C.c_int),
-            "pa_batch_set_sweep_blocks": ([P, i32], C.c_int),
+            "pa_batch_set_sweep_blocks": ([P, i32, i32], C.c_int),
             "pa_batch_destroy": ([P], None),
             "pa_batch_run_learned": ([P, P, d, d, d, i32, i32, i32,
                                       C.POINTER(i32), P], C.c_int),
@@ -404,8 +404,8 @@ class Batch:
             "pa_batch_get_population")
         return s, E, M
 
-    def set_sweep_blocks(self, blocks):
-        _ck(lib().pa_batch_set_sweep_blocks(self._h, blocks),
+    def set_sweep_blocks(self, blocks, chunk=1):
+        _ck(lib().pa_batch_set_sweep_blocks(self._h, blocks, chunk),
             "pa_batch_set_sweep_blocks")
 
     def run_learned(self, mlp, target, tol, beta_f, max_steps, theta,

@@ -41,6 +41,15 @@
 
 namespace pa {
 
+// Sweep classes: one per lattice variant (row words W, rows per lane, spin
+// layout, model), so a persistent launch carries the code of one variant.
+constexpr int kClasses = 48;
+__host__ __device__ constexpr int sweep_class(int W, int rpl, int int8,
+                                              int glass) {
+  return (((W - 1) * 3 + (rpl == 1 ? 0 : rpl == 2 ? 1 : 2)) * 2 + int8) * 2 +
+         glass;
+}
+
 // -------------------------------------------------------------- kernels
 
 // One-dimensional grid: gx workgroups of 2048 replicas per population.
@@ -235,8 +244,8 @@ __global__ __launch_bounds__(256) void k_bgather(const BatchPop* P,
 }
 
 // Single workgroup: adopt the new populations, then lay out the sweep work
-// queue (items = waves of rpw replicas) for every row-width class, in the
-// sorted population order.
+// queue (items = waves of rpw replicas) of every sweep class, in the sorted
+// population order (class c's prefix sums sit at first_c + c + i).
 __global__ __launch_bounds__(256) void k_bcommit(
     const BatchPop* P, const BatchStep* S, int64_t* R, const int64_t* Rnew,
     int32_t* cur, const int32_t* order, int n, const int32_t* cls_first,
@@ -253,7 +262,7 @@ __global__ __launch_bounds__(256) void k_bcommit(
     }
   }
   __syncthreads();
-  if (threadIdx.x < 5 && cls_count[threadIdx.x] > 0) {
+  if (threadIdx.x < kClasses && cls_count[threadIdx.x] > 0) {
     const int w = threadIdx.x;
     int64_t acc = 0;
     const int f = cls_first[w];
@@ -342,50 +351,35 @@ __global__ void k_bpred(const float* z, float* pred, int n, float mu_y,
   if (p < n) pred[p] = mu_y + sigma_y * z[p];
 }
 
-template <int W>
-__device__ __forceinline__ void dispatch_pass(const LatticeArgs& a,
-                                              const BatchPop& q,
-                                              int64_t wave) {
-  const int key = (q.rpl == 1 ? 0 : q.rpl == 2 ? 1 : 2) * 4 + q.int8 * 2 +
-                  q.glass;
-  switch (key) {
-    case 0: if constexpr (W <= 2) lattice_pass<W, 1, false, false>(a, wave); break;
-    case 1: if constexpr (W <= 2) lattice_pass<W, 1, false, true>(a, wave); break;
-    case 2: if constexpr (W <= 2) lattice_pass<W, 1, true, false>(a, wave); break;
-    case 3: if constexpr (W <= 2) lattice_pass<W, 1, true, true>(a, wave); break;
-    case 4: lattice_pass<W, 2, false, false>(a, wave); break;
-    case 5: lattice_pass<W, 2, false, true>(a, wave); break;
-    case 6: lattice_pass<W, 2, true, false>(a, wave); break;
-    case 7: lattice_pass<W, 2, true, true>(a, wave); break;
-    case 8: lattice_pass<W, 4, false, false>(a, wave); break;
-    case 9: lattice_pass<W, 4, false, true>(a, wave); break;
-    case 10: lattice_pass<W, 4, true, false>(a, wave); break;
-    case 11: lattice_pass<W, 4, true, true>(a, wave); break;
-    default: break;
-  }
-}
-
-// Persistent sweep kernel of one row-width class W: every wave pulls work
+// Persistent sweep kernel of one lattice variant: every wave pulls work
 // items (population, wave of replicas) from the class queue until the queue
 // is exhausted; every wave reaches the exit once the counter passes the
 // total, which k_bcommit fixed before the launch.
-template <int W>
+template <int W, int RPL, bool INT8, bool GLASS>
 __global__ __launch_bounds__(256) void k_bsweep(
     const BatchPop* P, const BatchStep* S, const int64_t* R,
     const int32_t* cur, const int32_t* order, const int64_t* prefix,
-    unsigned long long* queue, int first, int count, uint32_t one) {
+    unsigned long long* queue, int first, int count, int chunk,
+    uint32_t one) {
+  constexpr int cls = sweep_class(W, RPL, INT8 ? 1 : 0, GLASS ? 1 : 0);
   const int lane = threadIdx.x & 63;
-  const int64_t* pre = prefix + first + W;
+  const int64_t* pre = prefix + first + cls;
   const int64_t total = pre[count];
+  // items are taken `chunk` at a time: one atomic per chunk
+  int64_t item = 0, end = 0;
   while (true) {
-    int it = 0;
-    if (lane == 0) it = (int)atomicAdd(&queue[W], 1ull);
-    const int64_t item = (int64_t)__shfl(it, 0, 64);
+    if (item == end) {
+      int it = 0;
+      if (lane == 0) it = (int)atomicAdd(&queue[cls], (unsigned long long)chunk);
+      item = (int64_t)__shfl(it, 0, 64);
+      end = item + chunk;
+    }
     if (item >= total) break;
-    int lo = 0, hi = count - 1;  // last i with pre[i] <= item
+    const int64_t this_item = item++;
+    int lo = 0, hi = count - 1;  // last i with pre[i] <= this_item
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (pre[mid] <= item) lo = mid;
+      if (pre[mid] <= this_item) lo = mid;
       else hi = mid - 1;
     }
     const int p = order[first + lo];
@@ -417,7 +411,7 @@ __global__ __launch_bounds__(256) void k_bsweep(
     a.t0 = 0;
     a.theta = st.theta;
     a.init = 0;
-    dispatch_pass<W>(a, q, item - pre[lo]);
+    lattice_pass<W, RPL, INT8, GLASS>(a, this_item - pre[lo]);
   }
 }
 
@@ -479,10 +473,14 @@ struct pa_batch {
   int64_t* d_prefix = nullptr;
   unsigned long long* d_queue = nullptr;
   std::vector<void*> allocs;
-  int cls_first[5] = {0}, cls_count[5] = {0};
+  int cls_first[kClasses] = {0}, cls_count[kClasses] = {0};
   int64_t max_cap = 0;
   int lds_bins = 0;
-  int sweep_blocks = 2048;
+  // persistent sweep shape: 4 waves per SIMD, and 4 work items per queue
+  // atomic (one atomic per item serialised the queue counter: 3.9 ms per
+  // step of the 64-instance glass batch against 2.3 ms with 4)
+  int sweep_blocks = 1024;
+  int sweep_chunk = 4;
   // temperature-step network (learned mode) and its acceptance tolerance
   pa_mlp* mlp = nullptr;
   pa_mlp* graph_mlp = nullptr;  // the network the graph was built with
@@ -697,6 +695,53 @@ int enqueue_front(pa_batch* b) {
   return PA_OK;
 }
 
+template <int W, int RPL>
+hipError_t launch_bsweep_wr(int int8, int glass, unsigned blocks,
+                            hipStream_t st, const BatchPop* P,
+                            const BatchStep* S, const int64_t* R,
+                            const int32_t* cur, const int32_t* order,
+                            const int64_t* prefix, unsigned long long* queue,
+                            int first, int count, int chunk) {
+  const dim3 g(blocks), t(256);
+  if (int8 && glass)
+    hipLaunchKernelGGL((k_bsweep<W, RPL, true, true>), g, t, 0, st, P, S, R, cur, order, prefix, queue, first, count, chunk, 1u);
+  else if (int8)
+    hipLaunchKernelGGL((k_bsweep<W, RPL, true, false>), g, t, 0, st, P, S, R, cur, order, prefix, queue, first, count, chunk, 1u);
+  else if (glass)
+    hipLaunchKernelGGL((k_bsweep<W, RPL, false, true>), g, t, 0, st, P, S, R, cur, order, prefix, queue, first, count, chunk, 1u);
+  else
+    hipLaunchKernelGGL((k_bsweep<W, RPL, false, false>), g, t, 0, st, P, S, R, cur, order, prefix, queue, first, count, chunk, 1u);
+  return hipGetLastError();
+}
+
+// The persistent sweep of sweep class k (see sweep_class).
+hipError_t launch_bsweep(int k, int blocks, int chunk, hipStream_t st,
+                         const BatchPop* P, const BatchStep* S,
+                         const int64_t* R, const int32_t* cur,
+                         const int32_t* order, const int64_t* prefix,
+                         unsigned long long* queue, int first, int count) {
+  const int glass = k & 1, int8 = (k >> 1) & 1, ri = (k >> 2) % 3,
+            W = (k >> 2) / 3 + 1;
+  const unsigned bl = (unsigned)blocks;
+#define PA_BS(w, r) \
+  launch_bsweep_wr<w, r>(int8, glass, bl, st, P, S, R, cur, order, prefix, \
+                         queue, first, count, chunk)
+  switch (W * 8 + (ri == 0 ? 1 : ri == 1 ? 2 : 4)) {
+    case 1 * 8 + 1: return PA_BS(1, 1);
+    case 1 * 8 + 2: return PA_BS(1, 2);
+    case 1 * 8 + 4: return PA_BS(1, 4);
+    case 2 * 8 + 1: return PA_BS(2, 1);
+    case 2 * 8 + 2: return PA_BS(2, 2);
+    case 2 * 8 + 4: return PA_BS(2, 4);
+    case 3 * 8 + 2: return PA_BS(3, 2);
+    case 3 * 8 + 4: return PA_BS(3, 4);
+    case 4 * 8 + 2: return PA_BS(4, 2);
+    case 4 * 8 + 4: return PA_BS(4, 4);
+    default: return hipErrorInvalidValue;
+  }
+#undef PA_BS
+}
+
 // Kernels of one step after the host function.
 int enqueue_back(pa_batch* b) {
   hipStream_t st = b->stream;
@@ -721,16 +766,12 @@ int enqueue_back(pa_batch* b) {
                      b->d_Rnew, b->d_cur, b->d_order, b->n, b->d_cls_first,
                      b->d_cls_count, b->d_prefix, b->d_queue, 1);
   BK(hipGetLastError());
-  for (int w = 1; w <= 4; ++w) {
-    if (b->cls_count[w] == 0) continue;
-    const int first = b->cls_first[w], count = b->cls_count[w];
-    switch (w) {
-      case 1: hipLaunchKernelGGL(k_bsweep<1>, dim3(b->sweep_blocks), dim3(256), 0, st, b->d_pops, dS, dR, b->d_cur, b->d_order, b->d_prefix, b->d_queue, first, count, 1u); break;
-      case 2: hipLaunchKernelGGL(k_bsweep<2>, dim3(b->sweep_blocks), dim3(256), 0, st, b->d_pops, dS, dR, b->d_cur, b->d_order, b->d_prefix, b->d_queue, first, count, 1u); break;
-      case 3: hipLaunchKernelGGL(k_bsweep<3>, dim3(b->sweep_blocks), dim3(256), 0, st, b->d_pops, dS, dR, b->d_cur, b->d_order, b->d_prefix, b->d_queue, first, count, 1u); break;
-      case 4: hipLaunchKernelGGL(k_bsweep<4>, dim3(b->sweep_blocks), dim3(256), 0, st, b->d_pops, dS, dR, b->d_cur, b->d_order, b->d_prefix, b->d_queue, first, count, 1u); break;
-    }
-    BK(hipGetLastError());
+  for (int k = 0; k < kClasses; ++k) {
+    if (b->cls_count[k] == 0) continue;
+    BK(launch_bsweep(k, b->sweep_blocks, b->sweep_chunk, st, b->d_pops, dS,
+                     dR, b->d_cur,
+                     b->d_order, b->d_prefix, b->d_queue, b->cls_first[k],
+                     b->cls_count[k]));
   }
   return PA_OK;
 }
@@ -1014,10 +1055,10 @@ int pa_batch_init(const pa_config* cfgs, int32_t n, void* stream,
   ok = ok && balloc(b, &b->d_Rnew, (size_t)8 * n);
   ok = ok && balloc(b, &b->d_cur, (size_t)4 * n);
   ok = ok && balloc(b, &b->d_order, (size_t)4 * n);
-  ok = ok && balloc(b, &b->d_cls_first, 4 * 5);
-  ok = ok && balloc(b, &b->d_cls_count, 4 * 5);
-  ok = ok && balloc(b, &b->d_prefix, (size_t)8 * (n + 5));
-  ok = ok && balloc(b, &b->d_queue, 8 * 5);
+  ok = ok && balloc(b, &b->d_cls_first, 4 * kClasses);
+  ok = ok && balloc(b, &b->d_cls_count, 4 * kClasses);
+  ok = ok && balloc(b, &b->d_prefix, (size_t)8 * (n + kClasses));
+  ok = ok && balloc(b, &b->d_queue, 8 * kClasses);
   ok = ok && balloc(b, &b->d_pops, sizeof(BatchPop) * n);
   for (int p = 0; p < n && ok; ++p) {
     BatchPop& d = b->pops[p].d;
@@ -1044,20 +1085,23 @@ int pa_batch_init(const pa_config* cfgs, int32_t n, void* stream,
     delete b;
     return PA_ENOMEM;
   }
-  // population order: by row-width class, then by L descending
+  // population order: by sweep class, then by L descending
+  auto cls_of = [&](int p) {
+    const BatchPop& x = b->pops[p].d;
+    return sweep_class(x.W, x.rpl, x.int8, x.glass);
+  };
   std::vector<int32_t> order(n);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
-    const BatchPop &x = b->pops[a].d, &y = b->pops[c].d;
-    if (x.W != y.W) return x.W < y.W;
-    return x.L > y.L;
+    if (cls_of(a) != cls_of(c)) return cls_of(a) < cls_of(c);
+    return b->pops[a].d.L > b->pops[c].d.L;
   });
-  int cf[5] = {0}, cc[5] = {0};
-  for (int i = n - 1; i >= 0; --i) cf[b->pops[order[i]].d.W] = i;
-  for (int i = 0; i < n; ++i) cc[b->pops[order[i]].d.W] += 1;
-  for (int w = 0; w < 5; ++w) {
-    b->cls_first[w] = cc[w] ? cf[w] : 0;
-    b->cls_count[w] = cc[w];
+  int cf[kClasses] = {0}, cc[kClasses] = {0};
+  for (int i = n - 1; i >= 0; --i) cf[cls_of(order[i])] = i;
+  for (int i = 0; i < n; ++i) cc[cls_of(order[i])] += 1;
+  for (int k = 0; k < kClasses; ++k) {
+    b->cls_first[k] = cc[k] ? cf[k] : 0;
+    b->cls_count[k] = cc[k];
   }
   int rc = PA_OK;
   std::vector<BatchPop> dp(n);
@@ -1065,8 +1109,8 @@ int pa_batch_init(const pa_config* cfgs, int32_t n, void* stream,
   std::vector<int32_t> cur0(n, 0);
   if (hipMemcpy(b->d_pops, dp.data(), sizeof(BatchPop) * n, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(b->d_order, order.data(), 4 * n, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(b->d_cls_first, b->cls_first, 4 * 5, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(b->d_cls_count, b->cls_count, 4 * 5, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->d_cls_first, b->cls_first, 4 * kClasses, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->d_cls_count, b->cls_count, 4 * kClasses, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(b->d_cur, cur0.data(), 4 * n, hipMemcpyHostToDevice) != hipSuccess)
     rc = PA_EDEVICE;
   // couplings and the initial populations (the INIT stream of each)
@@ -1328,10 +1372,12 @@ int pa_batch_get_population(pa_batch* b, int32_t p, int8_t* spins, int32_t* E,
   return PA_OK;
 }
 
-int pa_batch_set_sweep_blocks(pa_batch* b, int32_t blocks) {
-  if (!b || blocks < 1 || blocks > 65535) return PA_EINVAL;
+int pa_batch_set_sweep_blocks(pa_batch* b, int32_t blocks, int32_t chunk) {
+  if (!b || blocks < 1 || blocks > 65535 || chunk < 1 || chunk > 1024)
+    return PA_EINVAL;
   drop_graph(b);
   b->sweep_blocks = blocks;
+  b->sweep_chunk = chunk;
   return PA_OK;
 }
 

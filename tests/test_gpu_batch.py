@@ -163,3 +163,22 @@ def test_autotuner_reports_valid_shapes(pa):
         assert best in valid
         for rpl, t in zip((1, 2, 4), ms):
             assert (t > 0) == (rpl in valid)
+
+
+def test_sweep_launch_shape_does_not_change_results(pa):
+    """Workgroups and work items per queue atomic of the persistent sweep
+    change only the schedule, never a bit of the populations."""
+    pops = _mixed_pops()
+    betas = np.array(W.linear_schedule(1.2, 5))
+    ref = pa.Batch(pops)
+    ref.run(betas, 3)
+    for blocks, chunk in ((1, 1), (37, 3), (4096, 16)):
+        b = pa.Batch(pops)
+        b.set_sweep_blocks(blocks, chunk)
+        b.run(betas, 3)
+        for p in range(len(pops)):
+            assert b.state(p) == ref.state(p), (blocks, chunk, p)
+            for x, y in zip(b.population(p), ref.population(p)):
+                assert np.array_equal(x, y), (blocks, chunk, p)
+        b.close()
+    ref.close()
