@@ -224,6 +224,69 @@ def bench_learned(binding, use_graph=True, target=0.85, tol=0.02):
     return out
 
 
+def bench_accuracy(binding, use_graph=True, M=64, L=32, R=2048, theta=10,
+                   beta_f=1.0):
+    """Wall time to beta_f against the free-energy error, for M independent
+    ferromagnet populations (L, R, theta) run as one batch per schedule:
+    linear schedules of several lengths, the exact bisection at two overlap
+    targets, and the network at 0.85 (trained on the exact schedules of
+    other ferromagnets).  The error is ln Z - ln Z_exact per spin at beta_f,
+    ln Z_exact from Kaufman's finite-torus solution."""
+    import numpy as np
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from exact_ising import kaufman_lnZ
+    from paper_2006_00561_amd import learned
+    N = L * L
+    exact = float(kaufman_lnZ(L, beta_f))
+    pops = [dict(L=L, R=R, seed=7000 + k, population_id=k) for k in range(M)]
+
+    def timed(fn):
+        b = binding.Batch(pops)
+        t0 = time.perf_counter()
+        info = fn(b)
+        dt = time.perf_counter() - t0
+        z = np.array([b.state(p)[3] for p in range(M)])
+        steps = max(b.state(p)[2] for p in range(M))
+        b.close()
+        err = (z - exact) / N
+        out = {"steps": int(steps), "wall_s": dt,
+               "rms_err_per_spin": float(np.sqrt(np.mean(err ** 2))),
+               "mean_err_per_spin": float(err.mean()),
+               "sd_err_per_spin": float(err.std(ddof=1))}
+        if info:
+            out.update(info)
+        return out
+
+    runs = {}
+    for K in (25, 50, 100, 200, 400):
+        betas = np.array(W.linear_schedule(beta_f, K))
+        runs["linear K=%d" % K] = timed(
+            lambda b: b.run(betas, theta, use_graph=use_graph))
+    for target in (0.7, 0.85):
+        runs["bisection alpha*=%g" % target] = timed(
+            lambda b: (b.run_adaptive(target, beta_f, 5000, theta,
+                                      use_graph=use_graph),
+                       {"host_ms": b.host_stats()["host_ms"]})[1])
+    train = [dict(L=l, R=r, seed=9000 + 10 * i + j, population_id=100 + 10 * i + j)
+             for i, l in enumerate((16, 24, 32, 48))
+             for j, r in enumerate((1024, 2048, 4096))]
+    X, T = learned.generate(train, [0.8, 0.85, 0.9], beta_f, theta)
+    mlp, _ = learned.train(X, T, iters=3000, lr=2e-3, seed=17)
+
+    def run_net(b):
+        _, src = b.run_learned(mlp, 0.85, 0.02, beta_f, 5000, theta,
+                               use_graph=use_graph)
+        return {"host_ms": b.host_stats()["host_ms"],
+                "sources": [int(v) for v in src]}
+    runs["network alpha*=0.85"] = timed(run_net)
+    mlp.close()
+    return {"workload": "%d independent ferromagnet populations, L=%d, R=%d, "
+                        "theta=%d, beta 0->%g; error of ln Z per spin against "
+                        "Kaufman's exact finite-torus value" % (M, L, R, theta,
+                                                              beta_f),
+            "lnZ_exact": exact, "training_pairs": int(len(X)), "runs": runs}
+
+
 def summarize_profiles(trace_dir, fetch_dir, write_dir, workload, command):
     """Write profiles/ summaries from rocprofv3 CSV output: per-kernel
     durations (--kernel-trace --stats) and HBM traffic (--pmc FETCH_SIZE and
@@ -308,8 +371,11 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--batched-only", action="store_true",
                     help="only the batched comparison (for profiling)")
+    ap.add_argument("--accuracy-only", action="store_true",
+                    help="only the schedule accuracy comparison")
     ap.add_argument("--eager", action="store_true",
                     help="batched runs without HIP graphs")
     ap.add_argument("--summarize-profiles", nargs=3,
@@ -321,7 +387,7 @@ def main():
     args = ap.parse_args()
     if args.summarize_profiles:
         base = ("python3 <repo>/bench.py --workload %s --no-cpu-baseline "
-                "--no-batched --no-learned" % args.workload)
+                "--no-batched --no-learned --no-accuracy" % args.workload)
         cmd = ["cd /tmp && export TMPDIR=/tmp",
                "rocprofv3 --kernel-trace --stats -T -d <TRACE_DIR> -o run "
                "--output-format csv -- %s --steps 2 --warmup 1" % base,
@@ -350,6 +416,10 @@ def main():
     if args.batched_only:
         print(json.dumps(bench_batched(binding, stream,
                                        use_graph=not args.eager)), flush=True)
+        return
+    if args.accuracy_only:
+        print(json.dumps(bench_accuracy(binding, use_graph=not args.eager)),
+              flush=True)
         return
     cfg = dict(W.CONFIGS[args.workload])
     cfg["name"] = args.workload
@@ -462,6 +532,8 @@ def main():
                                        use_graph=not args.eager)
     if not args.no_learned:
         out["learned"] = bench_learned(binding, use_graph=not args.eager)
+    if not args.no_accuracy:
+        out["accuracy"] = bench_accuracy(binding, use_graph=not args.eager)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_budget)
     print(json.dumps(out), flush=True)
