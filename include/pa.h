@@ -47,7 +47,9 @@ enum {
   PA_ECAPACITY = -3, /* resampling would exceed the capacity               */
   PA_EDEVICE = -4,   /* a HIP call failed                                  */
   PA_ESTATE = -5,    /* call out of order (e.g. sweep at another beta)     */
-  PA_EEMPTY = -6     /* resampling drew zero copies in total               */
+  PA_EEMPTY = -6,    /* resampling drew zero copies in total               */
+  PA_EIO = -7        /* population file not written / not readable / not a
+                        population file of this library                   */
 };
 
 enum { PA_FERRO = 0, PA_PMJ = 1 };     /* model                */
@@ -183,6 +185,24 @@ int pa_histogram(pa_ctx* c, uint32_t* h, int64_t cap, int32_t* nbins,
    double precision on the device histogram.  Synchronises. */
 int pa_overlap(pa_ctx* c, double dbeta, double* alpha);
 int pa_bisect_dbeta(pa_ctx* c, double target, double beta_f, double* dbeta);
+
+/* Checkpoint and resume.  pa_save writes the whole state of the context to
+   a file: configuration, couplings, beta, step, sweeps made at this step,
+   ln Z and the last ln Q, and the population in the canonical layout with
+   its E and M (a fixed 96-byte header "PAPOPv01" first; little-endian).
+   It synchronises; a pending resampling copy is made first.  pa_load
+   creates a new context on `stream` (a hipStream_t or NULL) from such a
+   file: because every random number is keyed by (step, sweep, slot,
+   population), the loaded context continues the run bit for bit as the
+   saved one would have.  The file is read and checked completely before
+   any device work (magic, sizes, spin values, no trailing bytes), and the
+   stored E and M must equal those of the stored spins; otherwise PA_EIO and
+   *out = NULL.  The copy counts of the last resampling are not saved. */
+int pa_save(pa_ctx* c, const char* path);
+int pa_load(const char* path, void* stream, pa_ctx** out);
+
+/* The configuration of a context (J is returned as NULL). */
+int pa_get_config(pa_ctx* c, pa_config* out);
 
 /* Per-kernel-class device timing with HIP events on the context's stream.
    classes: PA_TIMING_ALL times every class, otherwise a bit mask of the

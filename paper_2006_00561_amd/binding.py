@@ -15,8 +15,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SO_PATH = os.path.join(HERE, "libpa.so")
 
-PA_OK, PA_EINVAL, PA_ENOMEM, PA_ECAPACITY, PA_EDEVICE, PA_ESTATE, PA_EEMPTY = (
-    0, -1, -2, -3, -4, -5, -6)
+(PA_OK, PA_EINVAL, PA_ENOMEM, PA_ECAPACITY, PA_EDEVICE, PA_ESTATE, PA_EEMPTY,
+ PA_EIO) = (0, -1, -2, -3, -4, -5, -6, -7)
 PA_FERRO, PA_PMJ = 0, 1
 PA_INT8, PA_BITS = 0, 1
 KERNEL_CLASSES = ("init", "sweep", "hist", "counts", "scatter", "gather")
@@ -86,6 +86,9 @@ def lib():
             "pa_overlap": ([P, d, C.POINTER(d)], C.c_int),
             "pa_bisect_dbeta": ([P, d, d, C.POINTER(d)], C.c_int),
             "pa_set_timing": ([P, i32], C.c_int),
+            "pa_save": ([P, C.c_char_p], C.c_int),
+            "pa_load": ([C.c_char_p, P, C.POINTER(P)], C.c_int),
+            "pa_get_config": ([P, C.POINTER(pa_config)], C.c_int),
             "pa_get_timing": ([P, C.POINTER(pa_timing)], C.c_int),
             "pa_destroy": ([P], None),
             "pa_strerror": ([C.c_int], C.c_char_p),
@@ -164,6 +167,24 @@ class Population:
         h = C.c_void_p()
         _ck(lib().pa_init(C.byref(cfg), C.byref(h)), "pa_init")
         self._h = h
+
+    # --- checkpoint and resume
+    def save(self, path):
+        _ck(lib().pa_save(self._h, os.fsencode(path)), "pa_save")
+
+    @classmethod
+    def load(cls, path, stream=None):
+        """A population restored from a pa_save file; it continues the run
+        bit for bit."""
+        h = C.c_void_p()
+        _ck(lib().pa_load(os.fsencode(path), stream, C.byref(h)), "pa_load")
+        self = cls.__new__(cls)
+        self._h = h
+        self._J = None
+        cfg = pa_config()
+        _ck(lib().pa_get_config(h, C.byref(cfg)), "pa_get_config")
+        self.L, self.N = cfg.L, cfg.L * cfg.L
+        return self
 
     def close(self):
         if getattr(self, "_h", None):

@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -62,6 +63,7 @@ struct pa_ctx {
   unsigned long long* scal = nullptr;   // rb + nb2
   uint32_t* tab = nullptr;              // f[nl] then T[nl] of the last step
   uint32_t* jbits = nullptr;
+  std::vector<int8_t> J;                // host copy of the +-J couplings
   uint32_t* h_rb = nullptr;             // pinned host mirror of rb
   uint32_t* h_hist = nullptr;
   unsigned long long* h_scal = nullptr;
@@ -314,6 +316,7 @@ const char* pa_strerror(int code) {
     case PA_EDEVICE: return "HIP runtime error";
     case PA_ESTATE: return "call out of order";
     case PA_EEMPTY: return "resampling drew no replica";
+    case PA_EIO: return "population file could not be written or read";
     default: return "unknown error";
   }
 }
@@ -396,6 +399,7 @@ int pa_init(const pa_config* cfg, pa_ctx** out) {
   c->scal = reinterpret_cast<unsigned long long*>(c->rb + c->nb2);
   c->h_hist = c->h_rb;
   c->h_scal = reinterpret_cast<unsigned long long*>(c->h_rb + c->nb2);
+  if (c->model == PA_PMJ) c->J.assign(cfg->J, cfg->J + 2ll * L * L);
   // +-J couplings as row bit masks, bit set where J < 0
   std::vector<uint32_t> jb((size_t)2 * L * W, 0u);
   if (c->model == PA_PMJ)
@@ -708,6 +712,156 @@ int pa_set_timing(pa_ctx* c, int32_t classes) {
   if (rc) return rc;
   c->timing = (classes == PA_TIMING_ALL) ? 0x3Fu : ((uint32_t)classes & 0x3Fu);
   if (c->timing) c->acc = pa_timing{};
+  return PA_OK;
+}
+
+int pa_get_config(pa_ctx* c, pa_config* out) {
+  if (!c || !out) return PA_EINVAL;
+  pa_config k{};
+  k.L = c->L;
+  k.model = c->model;
+  k.J = nullptr;
+  k.R_target = c->R_t;
+  k.capacity = c->cap;
+  k.layout = c->layout;
+  k.rows_per_lane = c->rpl;
+  k.seed = c->seed;
+  k.population_id = c->pop;
+  k.stream = c->stream;
+  *out = k;
+  return PA_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Population file: a fixed header, the couplings (+-J only), then the
+// population in the canonical layout.  Little-endian, as the host.
+constexpr char kMagic[8] = {'P', 'A', 'P', 'O', 'P', 'v', '0', '1'};
+struct FileHeader {
+  char magic[8];
+  int64_t R_target, capacity, seed, R;
+  double beta, lnZ, lnQ_last;
+  int32_t L, model, layout, rows_per_lane;
+  uint32_t population_id;
+  int32_t step, sweeps_at_step, reserved;
+};
+static_assert(sizeof(FileHeader) == 8 + 4 * 8 + 3 * 8 + 8 * 4,
+              "population file header must have no padding");
+
+struct File {
+  FILE* f = nullptr;
+  explicit File(FILE* g) : f(g) {}
+  ~File() {
+    if (f) std::fclose(f);
+  }
+  bool write(const void* p, size_t n) { return std::fwrite(p, 1, n, f) == n; }
+  bool read(void* p, size_t n) { return std::fread(p, 1, n, f) == n; }
+};
+
+}  // namespace
+
+extern "C" {
+
+int pa_save(pa_ctx* c, const char* path) {
+  if (!c || !path) return PA_EINVAL;
+  int rc = sync(c);  // the population size, if still on the device
+  if (rc) return rc;
+  const int64_t R = c->R;
+  std::vector<int8_t> spins((size_t)R * c->N);
+  std::vector<int32_t> E((size_t)R), M((size_t)R);
+  rc = pa_get_population(c, spins.data(), E.data(), M.data(), R);
+  if (rc) return rc;
+  FileHeader h{};
+  std::memcpy(h.magic, kMagic, 8);
+  h.R_target = c->R_t;
+  h.capacity = c->cap;
+  h.seed = (int64_t)c->seed;
+  h.R = R;
+  h.beta = c->beta;
+  h.lnZ = c->lnZ;
+  h.lnQ_last = c->lnQ_last;
+  h.L = c->L;
+  h.model = c->model;
+  h.layout = c->layout;
+  h.rows_per_lane = c->rpl;
+  h.population_id = c->pop;
+  h.step = c->step;
+  h.sweeps_at_step = c->sweeps_at_step;
+  File f(std::fopen(path, "wb"));
+  if (!f.f) return PA_EIO;
+  bool ok = f.write(&h, sizeof h);
+  if (c->model == PA_PMJ) ok = ok && f.write(c->J.data(), c->J.size());
+  ok = ok && f.write(spins.data(), spins.size());
+  ok = ok && f.write(E.data(), E.size() * 4);
+  ok = ok && f.write(M.data(), M.size() * 4);
+  ok = (std::fflush(f.f) == 0) && ok;
+  return ok ? PA_OK : PA_EIO;
+}
+
+int pa_load(const char* path, void* stream, pa_ctx** out) {
+  if (!out) return PA_EINVAL;
+  *out = nullptr;
+  if (!path) return PA_EINVAL;
+  // everything is read and checked before any device work
+  File f(std::fopen(path, "rb"));
+  if (!f.f) return PA_EIO;
+  FileHeader h{};
+  if (!f.read(&h, sizeof h) || std::memcmp(h.magic, kMagic, 8) != 0)
+    return PA_EIO;
+  if (h.L < 4 || h.L > 128 || (h.L & 1) || h.R < 1 || h.R > h.capacity ||
+      h.capacity >= (1ll << 32) || (h.model != PA_FERRO && h.model != PA_PMJ) ||
+      h.step < 0 || h.step > 65535 || h.sweeps_at_step < 0 ||
+      h.sweeps_at_step > 32767 || !std::isfinite(h.beta) || !(h.beta >= 0.0))
+    return PA_EIO;
+  const int64_t N = (int64_t)h.L * h.L;
+  std::vector<int8_t> J;
+  if (h.model == PA_PMJ) {
+    J.resize((size_t)(2 * N));
+    if (!f.read(J.data(), J.size())) return PA_EIO;
+  }
+  std::vector<int8_t> spins((size_t)(h.R * N));
+  std::vector<int32_t> E((size_t)h.R), M((size_t)h.R);
+  if (!f.read(spins.data(), spins.size()) || !f.read(E.data(), E.size() * 4) ||
+      !f.read(M.data(), M.size() * 4))
+    return PA_EIO;
+  char extra;
+  if (f.read(&extra, 1)) return PA_EIO;  // trailing bytes: not our file
+  for (int8_t v : spins)
+    if (v != 1 && v != -1) return PA_EIO;
+  pa_config cfg{};
+  cfg.L = h.L;
+  cfg.model = h.model;
+  cfg.J = J.empty() ? nullptr : J.data();
+  cfg.R_target = h.R_target;
+  cfg.capacity = h.capacity;
+  cfg.layout = h.layout;
+  cfg.rows_per_lane = h.rows_per_lane;
+  cfg.seed = (uint64_t)h.seed;
+  cfg.population_id = h.population_id;
+  cfg.stream = stream;
+  pa_ctx* c = nullptr;
+  int rc = pa_init(&cfg, &c);
+  if (rc) return rc == PA_EINVAL ? PA_EIO : rc;
+  rc = pa_set_population(c, spins.data(), h.R);
+  // the energies and magnetisations the file holds must be the ones of its
+  // spins
+  std::vector<int32_t> E2((size_t)h.R), M2((size_t)h.R);
+  if (!rc) rc = pa_get_population(c, nullptr, E2.data(), M2.data(), h.R);
+  if (!rc && (E2 != E || M2 != M)) rc = PA_EIO;
+  if (rc) {
+    pa_destroy(c);
+    return rc;
+  }
+  c->beta = h.beta;
+  c->lnZ = h.lnZ;
+  c->lnQ_last = h.lnQ_last;
+  c->step = h.step;
+  c->sweeps_at_step = h.sweeps_at_step;
+  c->n_len = 0;
+  c->hist_valid = false;
+  *out = c;
   return PA_OK;
 }
 

@@ -57,3 +57,42 @@ def test_product_path_does_not_touch_the_oracle():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 src = open(os.path.join(dp, f)).read()
                 assert "oracle" not in src.lower(), f
+
+
+def _pop_file(path, L=4, R=2, spins=None, extra=b"", magic=b"PAPOPv01"):
+    """A population file written from the documented layout: 96-byte header,
+    spins [R][L][L] int8, E and M int32."""
+    import struct
+    N = L * L
+    hdr = magic + struct.pack("<qqqqdddiiiiIiii", R, R + 100, 1, R, 0.25,
+                              N * 0.6931471805599453, 0.0, L, 0, 0, 1, 0, 3,
+                              0, 0)
+    assert len(hdr) == 96
+    s = bytes([1] * (R * N)) if spins is None else spins
+    E = struct.pack("<%di" % R, *([-2 * N] * R))
+    M = struct.pack("<%di" % R, *([N] * R))
+    with open(path, "wb") as f:
+        f.write(hdr + s + E + M + extra)
+
+
+def test_load_rejects_bad_files_before_any_device_work(tmp_path):
+    from paper_2006_00561_amd import binding as b
+    lib = b.lib()
+    h = C.c_void_p()
+    missing = str(tmp_path / "missing.pa")
+    assert lib.pa_load(missing.encode(), None, C.byref(h)) == b.PA_EIO
+    bad = [("magic", dict(magic=b"NOTAPOP!")),
+           ("spin value", dict(spins=bytes([1] * 31 + [0]))),
+           ("trailing bytes", dict(extra=b"\x00"))]
+    for name, kw in bad:
+        p = str(tmp_path / (name.replace(" ", "_") + ".pa"))
+        _pop_file(p, **kw)
+        assert lib.pa_load(p.encode(), None, C.byref(h)) == b.PA_EIO, name
+        assert not h.value
+    p = str(tmp_path / "short.pa")
+    _pop_file(p)
+    with open(p, "r+b") as f:
+        f.truncate(96 + 10)
+    assert lib.pa_load(p.encode(), None, C.byref(h)) == b.PA_EIO
+    assert lib.pa_save(None, p.encode()) == b.PA_EINVAL
+    assert lib.pa_strerror(b.PA_EIO).decode().startswith("population file")

@@ -410,3 +410,40 @@ def test_deferred_population_size_matches_waiting_path(pa, layout, glass):
     fast.close()
     slow.close()
     o.close()
+
+
+@pytest.mark.parametrize("layout,glass,pending", [(0, False, False),
+                                                  (1, True, True)])
+def test_save_and_load_resume_bit_for_bit(pa, tmp_path, layout, glass,
+                                          pending):
+    """A run saved halfway and continued from the file equals the
+    uninterrupted run and the oracle, bit for bit (the saved state can sit
+    between a resampling and its sweep)."""
+    L, R, theta = 12, 700, 2
+    J = W.pmj_couplings(L, 31) if glass else None
+    betas = W.linear_schedule(1.1, 10)
+    a = pa.Population(L, R, seed=9, population_id=4, J=J, layout=layout)
+    o = oracle.OraclePA(L, R, seed=9, pop=4, J=J)
+    path = str(tmp_path / "half.pa")
+    b = None
+    for i, beta in enumerate(betas):
+        a.resample(beta, wait=False)
+        o.resample(beta)
+        if b is not None:
+            b.resample(beta, wait=False)
+        if pending and i == 5:        # saved between resampling and sweep
+            a.save(path)
+            b = pa.Population.load(path)
+        a.sweep(beta, theta)
+        o.sweep(theta)
+        if b is not None:
+            b.sweep(beta, theta)
+        if not pending and i == 4:    # saved after a complete step
+            a.save(path)
+            b = pa.Population.load(path)
+    for g in (a, b):
+        _cmp_state(g, o, "resumed")
+        assert g.state() == (o.R, o.beta, o.step)
+        _cmp_obs(g.observables(), o.observables())
+    a.close()
+    b.close()
