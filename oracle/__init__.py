@@ -12,12 +12,15 @@ from .oracle import (  # noqa: F401
     EEMPTY,
     EINVAL,
     ENOMEM,
+    NEAREST,
     OK,
+    POISSON,
     OraclePA,
     build,
     counts,
     energy,
     lib,
     philox4x32_10,
+    poisson_draw,
     sweep_replica,
 )

@@ -95,8 +95,11 @@ def lib():
         L.orc_set_visit_shuffle.restype = None
         L.orc_counts.argtypes = [C.c_int, i32p, C.c_int64, C.c_int64,
                                  C.c_double, C.c_uint64, C.c_uint32, C.c_int,
-                                 u32p, C.POINTER(C.c_int64),
+                                 C.c_int, u32p, C.POINTER(C.c_int64),
                                  C.POINTER(C.c_double)]
+        L.orc_set_resampling.argtypes = [P, C.c_int]
+        L.orc_poisson_draw.argtypes = [C.c_double, C.c_uint32]
+        L.orc_poisson_draw.restype = C.c_uint32
         L.orc_sweep_replica.argtypes = [C.c_int, P, i8p, C.POINTER(C.c_int32),
                                         C.POINTER(C.c_int32), C.c_double,
                                         C.c_uint64, C.c_uint32, C.c_int,
@@ -140,13 +143,20 @@ def energy(spins, J=None):
     return E.value, M.value
 
 
-def counts(N, E, R_t, dbeta, seed, pop, step_next):
+NEAREST, POISSON = 0, 1
+
+
+def poisson_draw(rho, r):
+    return int(lib().orc_poisson_draw(float(rho), int(r)))
+
+
+def counts(N, E, R_t, dbeta, seed, pop, step_next, law=NEAREST):
     """Copy counts and ln Q for a population given by its energies."""
     E = np.ascontiguousarray(E, dtype=np.int32)
     n = np.zeros(len(E), np.uint32)
     Rn, lnQ = C.c_int64(), C.c_double()
-    _check(lib().orc_counts(N, E, len(E), R_t, dbeta, seed, pop, step_next, n,
-                            C.byref(Rn), C.byref(lnQ)), "counts")
+    _check(lib().orc_counts(N, E, len(E), R_t, dbeta, seed, pop, step_next,
+                            law, n, C.byref(Rn), C.byref(lnQ)), "counts")
     return n, Rn.value, lnQ.value
 
 
@@ -165,13 +175,16 @@ def sweep_replica(spins, E, M, beta, seed, pop, step, t0, theta, slot, J=None):
 class OraclePA:
     """One population on the CPU oracle."""
 
-    def __init__(self, L, R_target, seed=1, pop=0, J=None, capacity=0):
+    def __init__(self, L, R_target, seed=1, pop=0, J=None, capacity=0,
+                 law=NEAREST):
         self.L, self.N = L, L * L
         self._Jc, jp = _jptr(J)
         h = C.c_void_p()
         _check(lib().orc_create(L, jp, R_target, capacity, seed, pop,
                                 C.byref(h)), "create")
         self._h = h
+        if law != NEAREST:
+            _check(lib().orc_set_resampling(h, law), "set_resampling")
 
     def close(self):
         if self._h:

@@ -25,9 +25,11 @@
  *     ln Z(beta_i) = ln Omega + sum_{l<=i} ln Q(beta_{l-1}, beta_l) with
  *     ln Omega = N ln 2 for cooling from beta_0 = 0.
  *   - Resampling law: nearest-integer (floor of the mean plus one Bernoulli
- *     draw on its fractional part) instead of Poisson; the mean number of
- *     copies is rho_j = R_target * tau_j / R_{i-1}, i.e. population control
- *     to the fixed target R_target.
+ *     draw on its fractional part) by default; Poisson, the law the paper
+ *     names, on request (inversion of its cumulative distribution with the
+ *     same 32-bit word).  The mean number of copies is
+ *     rho_j = R_target * tau_j / R_{i-1}, i.e. population control to the
+ *     fixed target R_target.
  *   - MCMC: checkerboard Metropolis, colour 0 ((x+y) even) first; integer
  *     acceptance threshold T = floor(exp(-beta dE) 2^32), accept iff
  *     dE <= 0 or r < T for a 32-bit random word r.
@@ -70,6 +72,7 @@ struct orc_pa {
   int step;
   int sweeps_at_step;
   uint64_t shuffle_seed;
+  int law;          /* ORC_NEAREST or ORC_POISSON */
 };
 
 /* ---------------------------------------------------------------- Philox */
@@ -221,19 +224,43 @@ void orc_destroy(orc_pa* p) {
    energies E[0..R): computes ln Q for the step dbeta and the copy count of
    every replica.  The resampling draws of slot j come from the RESAMPLE
    stream at step `step_next` (the index of the temperature being entered). */
+/* A Poisson(rho) draw from the 32-bit word r by inversion of its cumulative
+   distribution.  With P(k) = exp(k log rho - rho - lgamma(k + 1)) and
+   C(k) = P(0) + ... + P(k), summed in increasing k, the thresholds are
+   U_k = floor(C(k) 2^32) and the draw is the number of thresholds <= r,
+   i.e. the smallest k with r < U_k.  The thresholds stop after the first
+   k with C(k) >= 1 - 2^-32 (the rest of the mass is below one 32-bit
+   step) or before k = ceil(rho + 64 sqrt(rho) + 64). */
+uint32_t orc_poisson_draw(double rho, uint32_t r) {
+  if (!(rho > 0.0)) return 0u;
+  const double kcap = ceil(rho + 64.0 * sqrt(rho) + 64.0);
+  const double lr = log(rho);
+  double C = 0.0;
+  for (uint32_t k = 0;; ++k) {
+    if ((double)k >= kcap) return k;      /* every threshold was <= r */
+    C = C + exp((double)k * lr - ((ORC_MUTANT == 8) ? 0.0 : rho) -
+                lgamma((double)k + 1.0));
+    if ((uint64_t)r < (uint64_t)floor(ldexp(C, 32))) return k;
+    if (C >= 1.0 - ldexp(1.0, -32)) return k + 1;   /* the last threshold */
+  }
+}
+
 int orc_counts(int N, const int32_t* E, int64_t R, int64_t R_t, double dbeta,
-               uint64_t seed, uint32_t pop, int step_next, uint32_t* n_out,
-               int64_t* R_new, double* lnQ_out) {
+               uint64_t seed, uint32_t pop, int step_next, int law,
+               uint32_t* n_out, int64_t* R_new, double* lnQ_out) {
   if (N < 16 || !E || R < 1 || R_t < 1 || !n_out || !isfinite(dbeta) ||
-      dbeta < 0.0)
+      dbeta < 0.0 || (law != ORC_NEAREST && law != ORC_POISSON))
     return ORC_EINVAL;
+  for (int64_t j = 0; j < R; ++j)
+    if (E[j] < -2 * N || E[j] > 2 * N) return ORC_EINVAL;
   int nlev = 4 * N + 1; /* energies -2N..2N, index E + 2N */
   uint32_t* h = (uint32_t*)calloc((size_t)nlev, sizeof(uint32_t));
   double* w = (double*)calloc((size_t)nlev, sizeof(double));
+  double* rh = (double*)calloc((size_t)nlev, sizeof(double));
   uint32_t* f = (uint32_t*)calloc((size_t)nlev, sizeof(uint32_t));
   uint64_t* T = (uint64_t*)calloc((size_t)nlev, sizeof(uint64_t));
-  if (!h || !w || !f || !T) {
-    free(h); free(w); free(f); free(T);
+  if (!h || !w || !rh || !f || !T) {
+    free(h); free(w); free(rh); free(f); free(T);
     return ORC_ENOMEM;
   }
   /* (a) histogram of the energies and the smallest energy */
@@ -262,21 +289,25 @@ int orc_counts(int N, const int32_t* E, int64_t R, int64_t R_t, double dbeta,
   for (int e = -2 * N; e <= 2 * N; ++e) {
     if (h[e + 2 * N] == 0) continue;
     double rho = ((double)R_t * w[e + 2 * N]) / S;
+    rh[e + 2 * N] = rho;
     double fl = floor(rho);
     f[e + 2 * N] = (uint32_t)fl;
     T[e + 2 * N] = (uint64_t)floor(ldexp(rho - fl, 32));
   }
-  /* (e) copy counts: floor plus a Bernoulli draw on the fraction */
+  /* (e) copy counts: floor plus a Bernoulli draw on the fraction, or a
+     Poisson draw with mean rho; one 32-bit word per slot either way */
   int64_t total = 0;
   for (int64_t j = 0; j < R; ++j) {
     int idx = E[j] + 2 * N;
     uint32_t r = draw_word(seed, DOMAIN_RESAMPLE, 0, (uint32_t)step_next, 0,
                            (uint32_t)j, pop, 0);
-    uint32_t nj = f[idx] + ((uint64_t)r < T[idx] ? 1u : 0u);
+    uint32_t nj = (law == ORC_POISSON)
+                      ? orc_poisson_draw(rh[idx], r)
+                      : f[idx] + ((uint64_t)r < T[idx] ? 1u : 0u);
     n_out[j] = nj;
     total += nj;
   }
-  free(h); free(w); free(f); free(T);
+  free(h); free(w); free(rh); free(f); free(T);
   if (R_new) *R_new = total;
   if (lnQ_out) *lnQ_out = lnQ;
   return ORC_OK;
@@ -291,7 +322,7 @@ int orc_resample(orc_pa* p, double beta_next, int64_t* R_new) {
   int64_t total = 0;
   double lnQ = 0.0;
   int rc = orc_counts(p->N, p->E, p->R, p->R_t, beta_next - p->beta, p->seed,
-                      p->pop, p->step + 1, n, &total, &lnQ);
+                      p->pop, p->step + 1, p->law, n, &total, &lnQ);
   if (rc != ORC_OK) { free(n); return rc; }
   if (R_new) *R_new = total;
   if (total > p->cap) { free(n); return ORC_ECAPACITY; }
@@ -508,6 +539,12 @@ int orc_histogram(const orc_pa* p, uint32_t* out) {
   if (!p || !out) return ORC_EINVAL;
   memset(out, 0, (size_t)(4 * p->N + 1) * sizeof(uint32_t));
   for (int64_t j = 0; j < p->R; ++j) out[p->E[j] + 2 * p->N] += 1;
+  return ORC_OK;
+}
+
+int orc_set_resampling(orc_pa* p, int law) {
+  if (!p || (law != ORC_NEAREST && law != ORC_POISSON)) return ORC_EINVAL;
+  p->law = law;
   return ORC_OK;
 }
 

@@ -83,12 +83,21 @@ int orc_histogram(const orc_pa* p, uint32_t* out);
    of raster order (0 restores raster order). */
 void orc_set_visit_shuffle(orc_pa* p, uint64_t shuffle_seed);
 
+/* Resampling laws: nearest integer (floor of the mean plus a Bernoulli draw
+   on its fraction; the default) and Poisson (the law the paper names). */
+#define ORC_NEAREST 0
+#define ORC_POISSON 1
+int orc_set_resampling(orc_pa* p, int law);
+/* The Poisson copy count for mean rho from the 32-bit word r (inversion of
+   the cumulative distribution; exposed for its pins). */
+uint32_t orc_poisson_draw(double rho, uint32_t r);
+
 /* The reweighting and copy-count step on energies alone (for sampled checks
    at sizes where the whole population does not fit in host memory).
    step_next is the index of the temperature being entered. */
 int orc_counts(int N, const int32_t* E, int64_t R, int64_t R_t, double dbeta,
-               uint64_t seed, uint32_t pop, int step_next, uint32_t* n_out,
-               int64_t* R_new, double* lnQ_out);
+               uint64_t seed, uint32_t pop, int step_next, int law,
+               uint32_t* n_out, int64_t* R_new, double* lnQ_out);
 /* theta sweeps of one replica in place, sweeps t0..t0+theta-1 of step
    `step`, replica slot `slot`. */
 int orc_sweep_replica(int L, const int8_t* J, int8_t* spins, int32_t* E,

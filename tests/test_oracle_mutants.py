@@ -29,6 +29,8 @@ CASES = {
         ["test_oracle_resample.py::test_counts_are_floor_or_ceil_of_mean"]),
     7: ("ln Omega dropped from the free energy",
         ["test_oracle_physics.py::test_lnZ_and_Zhat_unbiased_L4"]),
+    8: ("the -rho term dropped from the Poisson probabilities",
+        ["test_oracle_poisson.py::test_draw_inverts_the_poisson_cdf"]),
 }
 
 
