@@ -54,6 +54,7 @@ enum {
 
 enum { PA_FERRO = 0, PA_PMJ = 1 };     /* model                */
 enum { PA_INT8 = 0, PA_BITS = 1 };     /* device spin layout   */
+enum { PA_NEAREST = 0, PA_POISSON = 1 }; /* resampling law      */
 
 typedef struct {
   int32_t L;          /* lattice side, even, 4 <= L <= 128 (checkerboard on
@@ -75,6 +76,15 @@ typedef struct {
   uint64_t seed;      /* Philox key                                          */
   uint32_t population_id; /* Philox counter word 3                          */
   void* stream;       /* hipStream_t to run on; NULL = the null stream      */
+  int32_t resampling; /* copy-count law (Sec. 2): PA_NEAREST (default)
+                         floor(rho) + [r < floor(frac(rho) 2^32)], or
+                         PA_POISSON, a Poisson(rho) count by inversion of
+                         its cumulative distribution C(k) (summed in
+                         double precision in increasing k): the count is
+                         the number of k with floor(C(k) 2^32) <= r, the
+                         list of k ending after C(k) >= 1 - 2^-32 or before
+                         ceil(rho + 64 sqrt(rho) + 64).  Single populations
+                         only: pa_batch_init rejects PA_POISSON.           */
 } pa_config;
 
 typedef struct {

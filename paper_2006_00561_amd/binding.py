@@ -19,6 +19,7 @@ SO_PATH = os.path.join(HERE, "libpa.so")
  PA_EIO) = (0, -1, -2, -3, -4, -5, -6, -7)
 PA_FERRO, PA_PMJ = 0, 1
 PA_INT8, PA_BITS = 0, 1
+PA_NEAREST, PA_POISSON = 0, 1
 KERNEL_CLASSES = ("init", "sweep", "hist", "counts", "scatter", "gather")
 PA_TIMING_ALL = -1
 
@@ -28,7 +29,8 @@ class pa_config(C.Structure):
                 ("J", C.c_void_p), ("R_target", C.c_int64),
                 ("capacity", C.c_int64), ("layout", C.c_int32),
                 ("rows_per_lane", C.c_int32), ("seed", C.c_uint64),
-                ("population_id", C.c_uint32), ("stream", C.c_void_p)]
+                ("population_id", C.c_uint32), ("stream", C.c_void_p),
+                ("resampling", C.c_int32)]
 
 
 class pa_obs(C.Structure):
@@ -150,7 +152,8 @@ class Population:
     """One population on the device, driven through the C ABI."""
 
     def __init__(self, L, R_target, seed=1, population_id=0, J=None,
-                 layout=PA_INT8, capacity=0, rows_per_lane=0, stream=None):
+                 layout=PA_INT8, capacity=0, rows_per_lane=0, stream=None,
+                 resampling=PA_NEAREST):
         self.L, self.N = L, L * L
         self._J = None if J is None else np.ascontiguousarray(J, np.int8)
         cfg = pa_config()
@@ -164,6 +167,7 @@ class Population:
         cfg.seed = seed
         cfg.population_id = population_id
         cfg.stream = stream
+        cfg.resampling = resampling
         h = C.c_void_p()
         _ck(lib().pa_init(C.byref(cfg), C.byref(h)), "pa_init")
         self._h = h

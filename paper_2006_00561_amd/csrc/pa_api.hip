@@ -61,13 +61,16 @@ struct pa_ctx {
   uint32_t* rb = nullptr;
   uint32_t* hist = nullptr;             // rb
   unsigned long long* scal = nullptr;   // rb + nb2
-  uint32_t* tab = nullptr;              // f[nl] then T[nl] of the last step
+  uint32_t* tab = nullptr;              // f[nl] then T[nl] of the last step,
+                                        // or the Poisson level tables
+  size_t tab_words = 0;                 // capacity of tab and h_tab
+  int law = PA_NEAREST;
   uint32_t* jbits = nullptr;
   std::vector<int8_t> J;                // host copy of the +-J couplings
   uint32_t* h_rb = nullptr;             // pinned host mirror of rb
   uint32_t* h_hist = nullptr;
   unsigned long long* h_scal = nullptr;
-  uint32_t* h_tab = nullptr;            // pinned, 2 * nbins words
+  uint32_t* h_tab = nullptr;            // pinned, tab_words words
   int nbins = 0, nb2 = 0, hshift = 0;
   bool hist_valid = false;
   bool rb_zero = false;  // the cleared part of rb is known to be zero
@@ -253,6 +256,33 @@ int compute_hist(pa_ctx* c) {
   return PA_OK;
 }
 
+// Room for `words` table words on the device and in the pinned mirror (the
+// Poisson tables grow with the means; allocation happens between steps).
+int ensure_tab(pa_ctx* c, size_t words) {
+  if (words <= c->tab_words) return PA_OK;
+  const size_t nw = words + words / 2;
+  uint32_t* d = nullptr;
+  uint32_t* h = nullptr;
+  if (hipMalloc(reinterpret_cast<void**>(&d), nw * 4) != hipSuccess)
+    return PA_ENOMEM;
+  if (hipHostMalloc(reinterpret_cast<void**>(&h), nw * 4) != hipSuccess) {
+    (void)hipFree(d);
+    return PA_ENOMEM;
+  }
+  int rc = sync(c);  // the old tables may still be read
+  if (rc) {
+    (void)hipFree(d);
+    (void)hipHostFree(h);
+    return rc;
+  }
+  (void)hipFree(c->tab);
+  (void)hipHostFree(c->h_tab);
+  c->tab = d;
+  c->h_tab = h;
+  c->tab_words = nw;
+  return PA_OK;
+}
+
 void free_all(pa_ctx* c) {
   for (int b = 0; b < 2; ++b) {
     if (c->spins[b]) (void)hipFree(c->spins[b]);
@@ -330,6 +360,8 @@ int pa_init(const pa_config* cfg, pa_ctx** out) {
   if (cfg->model != PA_FERRO && cfg->model != PA_PMJ) return PA_EINVAL;
   if (cfg->model == PA_PMJ && !cfg->J) return PA_EINVAL;
   if (cfg->layout != PA_INT8 && cfg->layout != PA_BITS) return PA_EINVAL;
+  if (cfg->resampling != PA_NEAREST && cfg->resampling != PA_POISSON)
+    return PA_EINVAL;
   if (cfg->R_target < 1 || cfg->R_target >= (1ll << 31)) return PA_EINVAL;
   int64_t cap = cfg->capacity;
   if (cap == 0)
@@ -365,6 +397,7 @@ int pa_init(const pa_config* cfg, pa_ctx** out) {
   c->R_t = cfg->R_target;
   c->cap = cap;
   c->seed = cfg->seed;
+  c->law = cfg->resampling;
   c->pop = cfg->population_id;
   c->stride = (c->layout == PA_INT8) ? round_up(c->N, 16)
                                      : round_up((int64_t)L * W * 4, 16);
@@ -384,12 +417,13 @@ int pa_init(const pa_config* cfg, pa_ctx** out) {
   ok = ok && dmalloc(&c->tile_off, (size_t)c->ntiles_cap * 4);
   c->nb2 = (c->nbins + 1) & ~1;
   ok = ok && dmalloc(&c->rb, ((size_t)c->nb2 + 16) * 4);
-  ok = ok && dmalloc(&c->tab, (size_t)c->nbins * 8);
+  c->tab_words = (size_t)c->nbins * 2;
+  ok = ok && dmalloc(&c->tab, c->tab_words * 4);
   ok = ok && dmalloc(&c->jbits, (size_t)2 * L * W * 4);
   ok = ok && hipHostMalloc(reinterpret_cast<void**>(&c->h_rb),
                            ((size_t)c->nb2 + 16) * 4) == hipSuccess;
   ok = ok && hipHostMalloc(reinterpret_cast<void**>(&c->h_tab),
-                           (size_t)c->nbins * 8) == hipSuccess;
+                           c->tab_words * 4) == hipSuccess;
   if (!ok) {
     free_all(c);
     delete c;
@@ -477,24 +511,48 @@ int pa_resample(pa_ctx* c, double beta_next, int64_t* R_new) {
   const double dbeta = beta_next - c->beta;
   TableRange tr;
   const int nbins = c->nbins;
-  rc = build_tables(c->h_hist, nbins, c->hshift, c->N, c->R, c->R_t, dbeta,
-                    c->h_tab, c->h_tab + nbins, &tr);
-  if (rc) return rc;
+  int64_t r_min = 0, r_max = 0;
+  CountsArgs ca{};
+  if (c->law == PA_POISSON) {
+    std::vector<uint32_t> pt;
+    rc = build_poisson_tables(c->h_hist, nbins, c->hshift, c->N, c->R, c->R_t,
+                              dbeta, pt, &tr, &r_min, &r_max);
+    if (rc) return rc;
+    rc = ensure_tab(c, pt.size());
+    if (rc) return rc;
+    std::memcpy(c->h_tab, pt.data(), pt.size() * 4);
+    CK(hipMemcpyAsync(c->tab, c->h_tab, pt.size() * 4, hipMemcpyHostToDevice,
+                      c->stream));
+    ca.f = c->tab;
+    ca.T = nullptr;
+    ca.poisson = 1;
+  } else {
+    rc = build_tables(c->h_hist, nbins, c->hshift, c->N, c->R, c->R_t, dbeta,
+                      c->h_tab, c->h_tab + nbins, &tr);
+    if (rc) return rc;
+    const int nl = tr.hi - tr.lo + 1;
+    // only the occupied levels go to the device: f[nl] then T[nl]
+    uint32_t* hf = c->h_tab;
+    uint32_t* hT = c->h_tab + nl;
+    std::memmove(hT, c->h_tab + nbins, (size_t)nl * 4);
+    CK(hipMemcpyAsync(c->tab, c->h_tab, (size_t)nl * 8,
+                      hipMemcpyHostToDevice, c->stream));
+    ca.f = c->tab;
+    ca.T = c->tab + nl;
+    // exact bounds of the new size: every replica at level l gets f or f + 1
+    // copies, f + 1 only where its threshold is nonzero
+    for (int i = tr.lo; i <= tr.hi; ++i) {
+      const int64_t h = c->h_hist[i];
+      r_min += h * (int64_t)hf[i - tr.lo];
+      r_max += h * ((int64_t)hf[i - tr.lo] + (hT[i - tr.lo] ? 1 : 0));
+    }
+  }
   const int lo = tr.lo, nl = tr.hi - tr.lo + 1;
   const double lnQ = tr.lnQ;
-  // only the occupied levels go to the device: f[nl] then T[nl]
-  uint32_t* hf = c->h_tab;
-  uint32_t* hT = c->h_tab + nl;
-  std::memmove(hT, c->h_tab + nbins, (size_t)nl * 4);
-  CK(hipMemcpyAsync(c->tab, c->h_tab, (size_t)nl * 8, hipMemcpyHostToDevice,
-                    c->stream));
   // (e) copy counts and their exclusive scan; the counts kernel also clears
   // the histogram and moments for the next step (their copy to the host
   // precedes it on the stream)
-  CountsArgs ca{};
   ca.E = c->E[c->cur];
-  ca.f = c->tab;
-  ca.T = c->tab + nl;
   ca.clear = c->rb;
   ca.nclear = c->nb2 + 8;
   ca.n = c->n;
@@ -509,14 +567,6 @@ int pa_resample(pa_ctx* c, double beta_next, int64_t* R_new) {
   ca.pop = c->pop;
   ca.step_next = (uint32_t)(c->step + 1);
   const int64_t ntiles = (c->R + 255) / 256;
-  // exact bounds of the new size: every replica at level l gets f or f + 1
-  // copies, f + 1 only where its threshold is nonzero
-  int64_t r_min = 0, r_max = 0;
-  for (int i = lo; i <= tr.hi; ++i) {
-    const int64_t h = c->h_hist[i];
-    r_min += h * (int64_t)hf[i - lo];
-    r_max += h * ((int64_t)hf[i - lo] + (hT[i - lo] ? 1 : 0));
-  }
   // the size need not reach the host now when it cannot be out of range and
   // the caller did not ask for it: the next synchronisation brings it
   const bool deferred = !R_new && r_min >= 1 && r_max <= c->cap;
@@ -728,6 +778,7 @@ int pa_get_config(pa_ctx* c, pa_config* out) {
   k.seed = c->seed;
   k.population_id = c->pop;
   k.stream = c->stream;
+  k.resampling = c->law;
   *out = k;
   return PA_OK;
 }
@@ -745,7 +796,7 @@ struct FileHeader {
   double beta, lnZ, lnQ_last;
   int32_t L, model, layout, rows_per_lane;
   uint32_t population_id;
-  int32_t step, sweeps_at_step, reserved;
+  int32_t step, sweeps_at_step, resampling;
 };
 static_assert(sizeof(FileHeader) == 8 + 4 * 8 + 3 * 8 + 8 * 4,
               "population file header must have no padding");
@@ -789,6 +840,7 @@ int pa_save(pa_ctx* c, const char* path) {
   h.population_id = c->pop;
   h.step = c->step;
   h.sweeps_at_step = c->sweeps_at_step;
+  h.resampling = c->law;
   File f(std::fopen(path, "wb"));
   if (!f.f) return PA_EIO;
   bool ok = f.write(&h, sizeof h);
@@ -813,7 +865,8 @@ int pa_load(const char* path, void* stream, pa_ctx** out) {
   if (h.L < 4 || h.L > 128 || (h.L & 1) || h.R < 1 || h.R > h.capacity ||
       h.capacity >= (1ll << 32) || (h.model != PA_FERRO && h.model != PA_PMJ) ||
       h.step < 0 || h.step > 65535 || h.sweeps_at_step < 0 ||
-      h.sweeps_at_step > 32767 || !std::isfinite(h.beta) || !(h.beta >= 0.0))
+      h.sweeps_at_step > 32767 || !std::isfinite(h.beta) || !(h.beta >= 0.0) ||
+      (h.resampling != PA_NEAREST && h.resampling != PA_POISSON))
     return PA_EIO;
   const int64_t N = (int64_t)h.L * h.L;
   std::vector<int8_t> J;
@@ -841,6 +894,7 @@ int pa_load(const char* path, void* stream, pa_ctx** out) {
   cfg.seed = (uint64_t)h.seed;
   cfg.population_id = h.population_id;
   cfg.stream = stream;
+  cfg.resampling = h.resampling;
   pa_ctx* c = nullptr;
   int rc = pa_init(&cfg, &c);
   if (rc) return rc == PA_EINVAL ? PA_EIO : rc;

@@ -948,6 +948,7 @@ int pa_batch_init(const pa_config* cfgs, int32_t n, void* stream,
     if (c.model != PA_FERRO && c.model != PA_PMJ) return PA_EINVAL;
     if (c.model == PA_PMJ && !c.J) return PA_EINVAL;
     if (c.layout != PA_INT8 && c.layout != PA_BITS) return PA_EINVAL;
+    if (c.resampling != PA_NEAREST) return PA_EINVAL;  // single path only
     if (c.R_target < 1 || c.R_target >= (1ll << 31)) return PA_EINVAL;
     const int rpl = c.rows_per_lane;
     if (rpl != 0 && rpl != 1 && rpl != 2 && rpl != 4) return PA_EINVAL;

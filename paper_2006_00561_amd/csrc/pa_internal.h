@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "pa.h"
 
 namespace pa {
@@ -53,6 +55,9 @@ struct CountsArgs {
   uint32_t* tile_sum;
   uint32_t* clear;    // words [0, nclear) set to zero on the way (may be null)
   int64_t nclear;
+  // Poisson law: when set, f points to the level table of
+  // build_poisson_tables (T is unused)
+  int32_t poisson;
   int64_t R;
   int32_t twoN, shift, lvl0, nlvl;
   uint32_t k0, k1, pop, step_next;
@@ -137,6 +142,10 @@ void metropolis_K(double beta, uint64_t* K4, uint64_t* K8);
 int build_tables(const uint32_t* h, int nbins, int shift, int N, int64_t R,
                  int64_t R_t, double dbeta, uint32_t* f, uint32_t* T,
                  TableRange* out);
+int build_poisson_tables(const uint32_t* h, int nbins, int shift, int N,
+                         int64_t R, int64_t R_t, double dbeta,
+                         std::vector<uint32_t>& out, TableRange* tr,
+                         int64_t* n_min, int64_t* n_max);
 double overlap_from_hist(const uint32_t* h, int nbins, int shift, int N,
                          int64_t R, double dbeta);
 void observables_from_hist(const uint32_t* h, int nbins, int shift, int N,

@@ -14,7 +14,9 @@
 //  k_hist      exact energy histogram + |M| and M^2 sums (Eqs. part-Q/tau
 //              need only the energy distribution).
 //  k_counts    copy counts floor(rho) + Bernoulli(frac rho) per replica from
-//              the host's per-level tables, plus one partial sum per tile;
+//              the host's per-level tables (or a Poisson count: the number
+//              of the level's CDF thresholds below the replica's word),
+//              plus one partial sum per tile;
 //              clears the histogram of the next step on the way.
 //  k_scan      exclusive scan of the tile sums (single workgroup).
 //  k_scatter   per-tile scan of the counts -> parent index of every new slot.
@@ -114,7 +116,23 @@ __global__ __launch_bounds__(256) void k_counts(CountsArgs a) {
     const uint4 b = philox10(make_uint4(kDomainResample << 28,
                                         a.step_next << 16, (uint32_t)j, a.pop),
                              a.k0, a.k1);
-    if (l >= 0 && l < a.nlvl) nj = a.f[l] + (b.x < a.T[l] ? 1u : 0u);
+    if (l >= 0 && l < a.nlvl) {
+      if (a.poisson) {
+        // the number of the level's thresholds <= r (they are sorted)
+        const uint32_t base = a.f[3 * l], off = a.f[3 * l + 1],
+                       len = a.f[3 * l + 2];
+        const uint32_t* U = a.f + 3 * a.nlvl + off;
+        uint32_t lo = 0, hi = len;
+        while (lo < hi) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (U[mid] <= b.x) lo = mid + 1;
+          else hi = mid;
+        }
+        nj = base + lo;
+      } else {
+        nj = a.f[l] + (b.x < a.T[l] ? 1u : 0u);
+      }
+    }
     a.n[j] = nj;
   }
   uint32_t total;

@@ -83,6 +83,74 @@ int build_tables(const uint32_t* h, int nbins, int shift, int N, int64_t R,
   return PA_OK;
 }
 
+// Poisson copy-count tables (Sec. 2 names the Poisson law).  For every
+// occupied level with mean rho the thresholds U_k = floor(C(k) 2^32) of the
+// cumulative distribution C(k) = sum_{i<=k} exp(i log rho - rho -
+// lgamma(i + 1)), summed in increasing i; the list stops after the first k
+// with C(k) >= 1 - 2^-32 or before k = ceil(rho + 64 sqrt(rho) + 64).  A
+// replica's copy count is the number of thresholds <= its 32-bit word.
+// Layout (uint32 words): level l (relative to lo) has (base, off, len) at
+// 3l; its thresholds are at 3 nl + off.  base counts the zero thresholds
+// (every word passes them); thresholds equal to 2^32 (no word passes them)
+// are left out.  n_min / n_max bound the new population size exactly.
+int build_poisson_tables(const uint32_t* h, int nbins, int shift, int N,
+                         int64_t R, int64_t R_t, double dbeta,
+                         std::vector<uint32_t>& out, TableRange* tr,
+                         int64_t* n_min, int64_t* n_max) {
+  int lo, hi;
+  occupied_range(h, nbins, &lo, &hi);
+  if (lo > hi || R < 1) return PA_ESTATE;
+  const int Emin = level_energy(N, shift, lo);
+  const int nl = hi - lo + 1;
+  // the weights, S and ln Q exactly as for the nearest-integer tables
+  std::vector<double> w((size_t)nl, 0.0);
+  double S = 0.0;
+  for (int i = lo; i <= hi; ++i) {
+    if (h[i] == 0) continue;
+    const double we =
+        std::exp(-(dbeta * (double)(level_energy(N, shift, i) - Emin)));
+    w[i - lo] = we;
+    const double term = (double)h[i] * we;
+    S = S + term;
+  }
+  tr->lnQ = (-(dbeta * (double)Emin)) + std::log(S / (double)R);
+  tr->lo = lo;
+  tr->hi = hi;
+  out.assign((size_t)3 * nl, 0u);
+  int64_t mn = 0, mx = 0;
+  const double top = 1.0 - std::ldexp(1.0, -32);
+  for (int i = lo; i <= hi; ++i) {
+    if (h[i] == 0) continue;
+    const double rho = ((double)R_t * w[i - lo]) / S;
+    uint32_t base = 0, len = 0;
+    const uint32_t off = (uint32_t)(out.size() - (size_t)3 * nl);
+    if (rho > 0.0) {
+      const double kcap = std::ceil(rho + 64.0 * std::sqrt(rho) + 64.0);
+      const double lr = std::log(rho);
+      double C = 0.0;
+      for (uint32_t k = 0; (double)k < kcap; ++k) {
+        C = C + std::exp((double)k * lr - rho - std::lgamma((double)k + 1.0));
+        const uint64_t U = (uint64_t)std::floor(std::ldexp(C, 32));
+        if (U == 0) {
+          ++base;
+        } else if (U < (1ull << 32)) {
+          out.push_back((uint32_t)U);
+          ++len;
+        }
+        if (C >= top) break;
+      }
+    }
+    out[(size_t)3 * (i - lo) + 0] = base;
+    out[(size_t)3 * (i - lo) + 1] = off;
+    out[(size_t)3 * (i - lo) + 2] = len;
+    mn += (int64_t)h[i] * base;
+    mx += (int64_t)h[i] * (base + len);
+  }
+  *n_min = mn;
+  *n_max = mx;
+  return PA_OK;
+}
+
 void observables_from_hist(const uint32_t* h, int nbins, int shift, int N,
                            int64_t R, double beta, int64_t sumAbsM,
                            int64_t sumM2, pa_obs* o) {

@@ -45,6 +45,16 @@ def test_strerror_and_validation_without_device():
     cfg = b.pa_config()
     cfg.L, cfg.R_target, cfg.model = 8, 10, b.PA_PMJ   # +-J without couplings
     assert lib.pa_init(C.byref(cfg), C.byref(h)) == b.PA_EINVAL
+    cfg = b.pa_config()
+    cfg.L, cfg.R_target, cfg.resampling = 8, 10, 2      # no such law
+    assert lib.pa_init(C.byref(cfg), C.byref(h)) == b.PA_EINVAL
+    # the batch takes the nearest-integer law only
+    cfg = b.pa_config()
+    cfg.L, cfg.R_target, cfg.resampling = 8, 10, b.PA_POISSON
+    bh = C.c_void_p()
+    assert lib.pa_batch_init(C.byref(cfg), 1, None, 0,
+                             C.byref(bh)) == b.PA_EINVAL
+    assert not bh.value
     assert lib.pa_sweep(None, 0.1, 1) == b.PA_EINVAL
     assert lib.pa_resample(None, 0.1, None) == b.PA_EINVAL
 

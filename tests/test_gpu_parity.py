@@ -52,12 +52,12 @@ def _cmp_state(g, o, tag):
 
 
 def _parity_run(pa, L, R, steps, theta, beta_f, seed=1, pop=0, J=None,
-                layout=0, rpl=0, check_every=1):
-    print("parity L=%d R=%d steps=%d theta=%d layout=%d rpl=%d J=%s"
-          % (L, R, steps, theta, layout, rpl, J is not None), flush=True)
+                layout=0, rpl=0, check_every=1, law=0):
+    print("parity L=%d R=%d steps=%d theta=%d layout=%d rpl=%d J=%s law=%d"
+          % (L, R, steps, theta, layout, rpl, J is not None, law), flush=True)
     g = pa.Population(L, R, seed=seed, population_id=pop, J=J, layout=layout,
-                      rows_per_lane=rpl)
-    o = oracle.OraclePA(L, R, seed=seed, pop=pop, J=J)
+                      rows_per_lane=rpl, resampling=law)
+    o = oracle.OraclePA(L, R, seed=seed, pop=pop, J=J, law=law)
     _cmp_state(g, o, "init")
     for i, b in enumerate(W.linear_schedule(beta_f, steps), start=1):
         R_old = g.R
@@ -412,18 +412,20 @@ def test_deferred_population_size_matches_waiting_path(pa, layout, glass):
     o.close()
 
 
-@pytest.mark.parametrize("layout,glass,pending", [(0, False, False),
-                                                  (1, True, True)])
+@pytest.mark.parametrize("layout,glass,pending,law", [(0, False, False, 0),
+                                                      (1, True, True, 0),
+                                                      (0, True, False, 1)])
 def test_save_and_load_resume_bit_for_bit(pa, tmp_path, layout, glass,
-                                          pending):
+                                          pending, law):
     """A run saved halfway and continued from the file equals the
     uninterrupted run and the oracle, bit for bit (the saved state can sit
     between a resampling and its sweep)."""
     L, R, theta = 12, 700, 2
     J = W.pmj_couplings(L, 31) if glass else None
     betas = W.linear_schedule(1.1, 10)
-    a = pa.Population(L, R, seed=9, population_id=4, J=J, layout=layout)
-    o = oracle.OraclePA(L, R, seed=9, pop=4, J=J)
+    a = pa.Population(L, R, seed=9, population_id=4, J=J, layout=layout,
+                      resampling=law)
+    o = oracle.OraclePA(L, R, seed=9, pop=4, J=J, law=law)
     path = str(tmp_path / "half.pa")
     b = None
     for i, beta in enumerate(betas):
@@ -447,3 +449,31 @@ def test_save_and_load_resume_bit_for_bit(pa, tmp_path, layout, glass,
         _cmp_obs(g.observables(), o.observables())
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("L,R,layout,glass", [(16, 1000, 0, False),
+                                              (12, 700, 1, True)])
+def test_poisson_resampling_matches_oracle(pa, L, R, layout, glass):
+    """The Poisson law (Sec. 2): copy counts, populations, ln Z and
+    observables after every step equal the oracle's."""
+    J = W.pmj_couplings(L, 61) if glass else None
+    _parity_run(pa, L, R, 40, 3, 1.2, seed=5, pop=2, J=J, layout=layout,
+                law=oracle.POISSON)
+
+
+def test_poisson_resampling_with_large_means(pa):
+    """One resampling from beta = 0 straight to beta = 2: the lowest levels
+    get means in the hundreds (long threshold lists), the rest almost none."""
+    L, R = 16, 400
+    g = pa.Population(L, R, seed=3, resampling=pa.PA_POISSON)
+    o = oracle.OraclePA(L, R, seed=3, law=oracle.POISSON)
+    R_old = g.R
+    assert g.resample(2.0) == o.resample(2.0)
+    n = g.counts()
+    assert np.array_equal(n, o.counts(R_old))
+    assert n.max() > 50
+    g.sweep(2.0, 2)
+    o.sweep(2)
+    _cmp_state(g, o, "large means")
+    g.close()
+    o.close()
