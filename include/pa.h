@@ -214,6 +214,17 @@ int pa_load(const char* path, void* stream, pa_ctx** out);
 /* The configuration of a context (J is returned as NULL). */
 int pa_get_config(pa_ctx* c, pa_config* out);
 
+/* Weighted averaging over M independent populations (Sec. 4, Large scale
+   testing, with the Machta reference): population m, with free-energy
+   estimate lnZ[m] and population averages values[m*k .. m*k+k) (linear
+   averages such as <E>, <E^2>, <|M|>; derived quantities are formed from
+   the combined averages), has weight Z_m / sum Z.  out[j] = sum_m w_m
+   values[m*k + j]; *lnZ_out (may be NULL) = ln((1/M) sum_m Z_m).  Host
+   double precision, weights exp(lnZ[m] - max lnZ) summed in increasing m.
+   No device work.  PA_EINVAL for M < 1 or a non-finite lnZ. */
+int pa_weighted_average(int32_t M, const double* lnZ, const double* values,
+                        int32_t k, double* out, double* lnZ_out);
+
 /* Per-kernel-class device timing with HIP events on the context's stream.
    classes: PA_TIMING_ALL times every class, otherwise a bit mask of the
    classes to time (bit PA_K_SWEEP = 1 << PA_K_SWEEP, ...); a nonzero value

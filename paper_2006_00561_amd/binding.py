@@ -91,6 +91,8 @@ def lib():
             "pa_save": ([P, C.c_char_p], C.c_int),
             "pa_load": ([C.c_char_p, P, C.POINTER(P)], C.c_int),
             "pa_get_config": ([P, C.POINTER(pa_config)], C.c_int),
+            "pa_weighted_average": ([i32, P, P, i32, P, C.POINTER(d)],
+                                    C.c_int),
             "pa_get_timing": ([P, C.POINTER(pa_timing)], C.c_int),
             "pa_destroy": ([P], None),
             "pa_strerror": ([C.c_int], C.c_char_p),
@@ -344,6 +346,32 @@ def tune_rows_per_lane(L, layout=PA_INT8, model=PA_FERRO, R=4096, theta=4,
                                     C.byref(best), ms),
         "pa_tune_rows_per_lane")
     return best.value, list(ms)
+
+
+def weighted_average(lnZ, values):
+    """Weighted average over independent populations (pa_weighted_average):
+    lnZ [M], values [M][k] of linear population averages; returns
+    (averages [k], combined ln Z)."""
+    z = np.ascontiguousarray(lnZ, np.float64)
+    v = np.ascontiguousarray(values, np.float64).reshape(len(z), -1)
+    out = np.zeros(v.shape[1], np.float64)
+    lz = C.c_double()
+    _ck(lib().pa_weighted_average(len(z), _ptr(z), _ptr(v), v.shape[1],
+                                  _ptr(out), C.byref(lz)),
+        "pa_weighted_average")
+    return out, lz.value
+
+
+def combine_observables(lnZ, obs, N):
+    """Energy per spin, |m|, m^2 and specific heat of M independent
+    populations together (weighted averaging), formed from the weighted
+    linear averages <E>, <E^2>, <|M|>, <M^2> of each population's pa_obs."""
+    vals = [[o["sumE"] / o["R"], o["sumE2"] / o["R"], o["sumAbsM"] / o["R"],
+             o["sumM2"] / o["R"]] for o in obs]
+    (E1, E2, A1, M2), lz = weighted_average(lnZ, vals)
+    beta = obs[0]["beta"]
+    return {"e": E1 / N, "abs_m": A1 / N, "m2": M2 / (N * N),
+            "C": beta * beta * (E2 - E1 * E1) / N, "lnZ": lz}
 
 
 class Batch:

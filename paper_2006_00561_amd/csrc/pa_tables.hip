@@ -226,3 +226,33 @@ double bisect_from_hist(const uint32_t* h, int nbins, int shift, int N,
 }  // namespace pa
 
 extern "C" const char* pa_last_error(void) { return pa::last_error(); }
+
+// Weighted averaging over independent populations (the alternative to one
+// large population discussed in Sec. 4 after the Machta reference): each
+// population m is weighted by its partition-function estimate Z_m, i.e.
+// w_m = exp(ln Z_m - max ln Z) / sum of those, summed in increasing m.
+extern "C" int pa_weighted_average(int32_t M, const double* lnZ,
+                                   const double* values, int32_t k,
+                                   double* out, double* lnZ_out) {
+  if (M < 1 || k < 0 || !lnZ || (k > 0 && (!values || !out))) return PA_EINVAL;
+  double mx = lnZ[0];
+  for (int32_t m = 0; m < M; ++m) {
+    if (!std::isfinite(lnZ[m])) return PA_EINVAL;
+    if (lnZ[m] > mx) mx = lnZ[m];
+  }
+  std::vector<double> w((size_t)M);
+  double s = 0.0;
+  for (int32_t m = 0; m < M; ++m) {
+    w[(size_t)m] = std::exp(lnZ[m] - mx);
+    s = s + w[(size_t)m];
+  }
+  for (int32_t j = 0; j < k; ++j) {
+    double a = 0.0;
+    for (int32_t m = 0; m < M; ++m)
+      a = a + w[(size_t)m] * values[(size_t)m * k + j];
+    out[j] = a / s;
+  }
+  // ln of the mean of the Z_m: the combined estimate of ln Z
+  if (lnZ_out) *lnZ_out = mx + std::log(s / (double)M);
+  return PA_OK;
+}

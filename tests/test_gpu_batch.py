@@ -182,3 +182,24 @@ def test_sweep_launch_shape_does_not_change_results(pa):
                 assert np.array_equal(x, y), (blocks, chunk, p)
         b.close()
     ref.close()
+
+
+def test_weighted_average_of_independent_populations_is_exact(pa):
+    """Many independent ferromagnet populations combined by weighted
+    averaging: the energy per spin and ln Z at beta_f agree with the exact
+    finite-torus results within the statistical error."""
+    import exact_ising
+    L, R, M, beta_f = 16, 400, 48, 0.6
+    pops = [dict(L=L, R=R, seed=500 + m, population_id=m) for m in range(M)]
+    b = pa.Batch(pops)
+    b.run(np.array(W.linear_schedule(beta_f, 60)), 4)
+    lnZ = np.array([b.state(p)[3] for p in range(M)])
+    obs = [b.trajectory(p)[0][-1] for p in range(M)]
+    assert all(o["beta"] == beta_f for o in obs)
+    comb = pa.combine_observables(lnZ, obs, L * L)
+    e = np.array([o["e"] for o in obs])
+    e_exact = float(exact_ising.kaufman_energy(L, beta_f))  # per spin
+    z_exact = float(exact_ising.kaufman_lnZ(L, beta_f))
+    assert abs(comb["e"] - e_exact) < 5 * e.std(ddof=1) / np.sqrt(M) + 1e-4
+    assert abs(comb["lnZ"] - z_exact) < 5 * lnZ.std(ddof=1) / np.sqrt(M) + 0.05
+    b.close()
