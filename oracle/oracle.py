@@ -98,6 +98,7 @@ def lib():
                                  C.c_int, u32p, C.POINTER(C.c_int64),
                                  C.POINTER(C.c_double)]
         L.orc_set_resampling.argtypes = [P, C.c_int]
+        L.orc_start_heating.argtypes = [P, C.c_double]
         L.orc_poisson_draw.argtypes = [C.c_double, C.c_uint32]
         L.orc_poisson_draw.restype = C.c_uint32
         L.orc_sweep_replica.argtypes = [C.c_int, P, i8p, C.POINTER(C.c_int32),
@@ -208,6 +209,9 @@ class OraclePA:
     @property
     def step(self):
         return lib().orc_step(self._h)
+
+    def start_heating(self, beta0):
+        _check(lib().orc_start_heating(self._h, beta0), "start_heating")
 
     def resample(self, beta_next):
         Rn = C.c_int64()

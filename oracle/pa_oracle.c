@@ -249,7 +249,7 @@ int orc_counts(int N, const int32_t* E, int64_t R, int64_t R_t, double dbeta,
                uint64_t seed, uint32_t pop, int step_next, int law,
                uint32_t* n_out, int64_t* R_new, double* lnQ_out) {
   if (N < 16 || !E || R < 1 || R_t < 1 || !n_out || !isfinite(dbeta) ||
-      dbeta < 0.0 || (law != ORC_NEAREST && law != ORC_POISSON))
+      (law != ORC_NEAREST && law != ORC_POISSON))
     return ORC_EINVAL;
   for (int64_t j = 0; j < R; ++j)
     if (E[j] < -2 * N || E[j] > 2 * N) return ORC_EINVAL;
@@ -263,14 +263,18 @@ int orc_counts(int N, const int32_t* E, int64_t R, int64_t R_t, double dbeta,
     free(h); free(w); free(rh); free(f); free(T);
     return ORC_ENOMEM;
   }
-  /* (a) histogram of the energies and the smallest energy */
-  int32_t Emin = 2 * N + 1;
+  /* (a) histogram of the energies; the energy the weights are shifted by:
+     the smallest one when cooling (dbeta >= 0), the largest when heating,
+     so that every weight is at most 1 */
+  int32_t Emin = 2 * N + 1, Emax = -2 * N - 1;
   for (int64_t j = 0; j < R; ++j) {
     h[E[j] + 2 * N] += 1;
     if (E[j] < Emin) Emin = E[j];
+    if (E[j] > Emax) Emax = E[j];
   }
-  /* (b) Boltzmann factors exp(-dbeta E) shifted by Emin, summed per energy
-     level in ascending energy order (Eq. part-Q numerator) */
+  if (dbeta < 0.0) Emin = Emax;  /* the shift energy from here on */
+  /* (b) Boltzmann factors exp(-dbeta E) shifted, summed per energy level in
+     ascending energy order (Eq. part-Q numerator) */
   double S = 0.0;
   for (int e = -2 * N; e <= 2 * N; ++e) {
     uint32_t c = h[e + 2 * N];
@@ -314,8 +318,8 @@ int orc_counts(int N, const int32_t* E, int64_t R, int64_t R_t, double dbeta,
 }
 
 int orc_resample(orc_pa* p, double beta_next, int64_t* R_new) {
-  if (!p || !isfinite(beta_next) || !(beta_next >= p->beta))
-    return ORC_EINVAL;
+  /* cooling (beta_next >= beta) or heating (beta_next < beta), beta >= 0 */
+  if (!p || !isfinite(beta_next) || !(beta_next >= 0.0)) return ORC_EINVAL;
   if (p->step + 1 > 65535) return ORC_EINVAL;
   uint32_t* n = (uint32_t*)malloc((size_t)p->R * sizeof(uint32_t));
   if (!n) return ORC_ENOMEM;
@@ -521,6 +525,30 @@ int orc_get_counts(const orc_pa* p, uint32_t* n, int64_t cap) {
   if (!p || !n || cap < p->n_len) return ORC_EINVAL;
   memcpy(n, p->n, (size_t)p->n_len * sizeof(uint32_t));
   return (int)0;
+}
+
+/* The heating protocol (Sec. 2, with the Potts reference): the population
+   starts close to zero temperature, at beta0 > 0, in the ground states of
+   the ferromagnet, all spins +1 or all -1 with probability 1/2 each (the top
+   bit of the INIT word of site (0,0) of the replica decides), and
+   ln Z(beta0) = ln 2 + 2 N beta0 (two states of energy -2N; the excited
+   states add about N exp(-8 beta0) relative to this, which is left out). */
+int orc_start_heating(orc_pa* p, double beta0) {
+  if (!p || p->J || p->step != 0 || !isfinite(beta0) || !(beta0 > 0.0))
+    return ORC_EINVAL;
+  size_t N = (size_t)p->N;
+  p->R = p->R_t;
+  for (int64_t j = 0; j < p->R; ++j) {
+    uint32_t w = draw_word(p->seed, DOMAIN_INIT, 0, 0, 0, (uint32_t)j, p->pop,
+                           0);
+    memset(p->spins + (size_t)j * N, (w >> 31) ? 1 : -1, N);
+    orc_energy(p->L, p->J, p->spins + (size_t)j * N, &p->E[j], &p->M[j]);
+  }
+  p->beta = beta0;
+  p->lnZ = log(2.0) + ((ORC_MUTANT == 9) ? 0.0 : 2.0 * (double)p->N * beta0);
+  p->lnQ_last = 0.0;
+  p->n_len = 0;
+  return ORC_OK;
 }
 
 int orc_set_population(orc_pa* p, const int8_t* spins, int64_t R) {

@@ -61,8 +61,14 @@ int orc_create(int L, const int8_t* J, int64_t R_t, int64_t cap,
                uint64_t seed, uint32_t pop, orc_pa** out);
 void orc_destroy(orc_pa* p);
 
-/* Reweight from the current beta to beta_next, draw copy counts, build the
-   new population.  On error the population is unchanged. */
+/* Heating protocol: replace a fresh ferromagnet population by ground states
+   at beta0 > 0 (all +1 or all -1, from the replica's INIT word of site
+   (0,0)), ln Z = ln 2 + 2 N beta0. */
+int orc_start_heating(orc_pa* p, double beta0);
+
+/* Reweight from the current beta to beta_next (cooling or heating), draw
+   copy counts, build the new population.  On error the population is
+   unchanged. */
 int orc_resample(orc_pa* p, double beta_next, int64_t* R_new);
 /* theta checkerboard Metropolis sweeps at the current beta. */
 int orc_sweep(orc_pa* p, int theta);

@@ -31,6 +31,8 @@ CASES = {
         ["test_oracle_physics.py::test_lnZ_and_Zhat_unbiased_L4"]),
     8: ("the -rho term dropped from the Poisson probabilities",
         ["test_oracle_poisson.py::test_draw_inverts_the_poisson_cdf"]),
+    9: ("the ground-state energy term dropped from the heating start's ln Z",
+        ["test_oracle_heating.py::test_heating_lnZ_L4_matches_enumeration"]),
 }
 
 

@@ -29,7 +29,7 @@ def _annealed(L=16, R=2000, steps=8, seed=7):
     return p
 
 
-@pytest.mark.parametrize("dbeta", [0.0, 0.01, 0.05, 0.3])
+@pytest.mark.parametrize("dbeta", [0.0, 0.01, 0.05, 0.3, -0.05, -0.3])
 def test_counts_are_floor_or_ceil_of_mean(dbeta):
     p = _annealed()
     E, _ = p.energies()
@@ -126,7 +126,7 @@ def test_capacity_overflow_leaves_population_untouched():
 def test_invalid_steps_are_rejected():
     p = oracle.OraclePA(6, 10, seed=4)
     p.resample(0.2)
-    assert p.resample_rc(0.1)[0] == oracle.EINVAL     # cooling only
+    assert p.resample_rc(-0.1)[0] == oracle.EINVAL    # beta stays >= 0
     assert p.resample_rc(float("nan"))[0] == oracle.EINVAL
 
 
