@@ -42,7 +42,7 @@ extern "C" {
 
 enum {
   PA_OK = 0,
-  PA_EINVAL = -1,    /* bad argument (also: beta not finite, cooling only) */
+  PA_EINVAL = -1,    /* bad argument (also: beta not finite or negative)   */
   PA_ENOMEM = -2,    /* device or host allocation failed                   */
   PA_ECAPACITY = -3, /* resampling would exceed the capacity               */
   PA_EDEVICE = -4,   /* a HIP call failed                                  */
@@ -127,9 +127,11 @@ int pa_init(const pa_config* cfg, pa_ctx** out);
 int pa_sweep(pa_ctx* c, double beta, int32_t theta);
 
 /* Sec. 2, reweighting and resampling (Eqs. part-Q, tau) from the current
-   beta to beta_next >= beta: exact energy histogram on the device; on the
-   host, per energy level in ascending order, w = exp(-dbeta (E - Emin)),
-   S = sum h w, ln Q = -dbeta Emin + ln(S / R), rho = R_target w / S; copy
+   beta to beta_next >= 0 (cooling, or heating when beta_next < beta):
+   exact energy histogram on the device; on the host, per energy level in
+   ascending order, w = exp(-dbeta (E - E0)) with E0 the smallest energy
+   when cooling and the largest when heating, S = sum h w,
+   ln Q = -dbeta E0 + ln(S / R), rho = R_target w / S; copy
    counts n_j = floor(rho) + [r_j < floor(frac(rho) 2^32)] (RESAMPLE word 0
    of slot j at the new step); exclusive scan; parent of every new slot
    (parents in slot order, copies contiguous).  The copies into the second
@@ -145,6 +147,17 @@ int pa_sweep(pa_ctx* c, double beta, int32_t theta);
    device, and the host learns it at the next synchronising call.
    Otherwise it waits and checks as above. */
 int pa_resample(pa_ctx* c, double beta_next, int64_t* R_new);
+
+/* Sec. 2, heating protocol (the population starts close to zero
+   temperature): replaces the population of a fresh ferromagnet context
+   (step 0) by ground states at beta0 > 0 -- every spin of replica j equals
+   the top bit of its INIT word of site (0,0) (+1 when set) -- and sets
+   beta = beta0, ln Z = ln 2 + 2 N beta0 (the two states of energy -2N; the
+   excited states' share, about N exp(-8 beta0), is left out).  Resampling
+   then steps beta down; weights are shifted by the largest energy when
+   beta decreases.  PA_EINVAL for +-J couplings or beta0 <= 0, PA_ESTATE
+   after a resampling.  Synchronises. */
+int pa_start_heating(pa_ctx* c, double beta0);
 
 /* Sec. 2, measurement after equilibration: population averages from exact
    integer sums over the current population.  Synchronises. */

@@ -91,6 +91,7 @@ def lib():
             "pa_save": ([P, C.c_char_p], C.c_int),
             "pa_load": ([C.c_char_p, P, C.POINTER(P)], C.c_int),
             "pa_get_config": ([P, C.POINTER(pa_config)], C.c_int),
+            "pa_start_heating": ([P, d], C.c_int),
             "pa_weighted_average": ([i32, P, P, i32, P, C.POINTER(d)],
                                     C.c_int),
             "pa_get_timing": ([P, C.POINTER(pa_timing)], C.c_int),
@@ -173,6 +174,10 @@ class Population:
         h = C.c_void_p()
         _ck(lib().pa_init(C.byref(cfg), C.byref(h)), "pa_init")
         self._h = h
+
+    def start_heating(self, beta0):
+        """Ground states at beta0 > 0 (heating protocol; ferromagnet)."""
+        _ck(lib().pa_start_heating(self._h, beta0), "pa_start_heating")
 
     # --- checkpoint and resume
     def save(self, path):

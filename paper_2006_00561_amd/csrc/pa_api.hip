@@ -503,7 +503,8 @@ int pa_sweep(pa_ctx* c, double beta, int32_t theta) {
 }
 
 int pa_resample(pa_ctx* c, double beta_next, int64_t* R_new) {
-  if (!c || !std::isfinite(beta_next) || !(beta_next >= c->beta))
+  // cooling (beta_next >= beta) or heating (beta_next < beta), beta >= 0
+  if (!c || !std::isfinite(beta_next) || !(beta_next >= 0.0))
     return PA_EINVAL;
   if (c->step + 1 > 65535) return PA_EINVAL;
   int rc = compute_hist(c);
@@ -608,6 +609,31 @@ int pa_resample(pa_ctx* c, double beta_next, int64_t* R_new) {
   c->sweeps_at_step = 0;
   c->lnQ_last = lnQ;
   c->lnZ = c->lnZ + lnQ;  // Eq. Free-En, read with the logarithm
+  c->hist_valid = false;
+  return PA_OK;
+}
+
+int pa_start_heating(pa_ctx* c, double beta0) {
+  if (!c || !std::isfinite(beta0) || !(beta0 > 0.0)) return PA_EINVAL;
+  if (c->model != PA_FERRO) return PA_EINVAL;
+  if (c->step != 0) return PA_ESTATE;
+  int rc = sync(c);
+  if (rc) return rc;
+  c->gather_pending = false;
+  c->R = c->R_t;
+  LatticeArgs a = lattice_args(c);
+  a.init = 2;
+  a.theta = 0;
+  rc = run_lattice(c, a, PA_K_INIT);
+  if (rc) return rc;
+  rc = sync(c);
+  if (rc) return rc;
+  c->beta = beta0;
+  // two ground states of energy -2N
+  c->lnZ = std::log(2.0) + 2.0 * (double)c->N * beta0;
+  c->lnQ_last = 0.0;
+  c->sweeps_at_step = 0;
+  c->n_len = 0;
   c->hist_valid = false;
   return PA_OK;
 }

@@ -34,7 +34,8 @@ struct LatticeArgs {
   uint32_t k0, k1;        // Philox key
   uint32_t pop, step;
   int32_t t0, theta;      // first sweep index at this step, sweep count
-  int32_t init;           // draw the spins from the INIT stream
+  int32_t init;           // 1: draw the spins from the INIT stream;
+                          // 2: ferromagnet ground states (heating start)
 };
 
 struct HistArgs {

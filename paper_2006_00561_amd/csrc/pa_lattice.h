@@ -159,7 +159,14 @@ __device__ __forceinline__ void lattice_pass(const LatticeArgs& a,
 #pragma unroll
       for (int w = 0; w < W; ++w) jr[r][w] = jl[r][w] = jd[r][w] = ju[r][w] = 0u;
     }
-    if (a.init) {
+    if (a.init == 2) {
+      // ground state of the ferromagnet: every spin equals the replica's
+      // INIT word of site (0,0)
+      const uint4 b = philox10(make_uint4(kDomainInit << 28, 0u, slot, a.pop),
+                               a.k0, a.k1);
+#pragma unroll
+      for (int w = 0; w < W; ++w) s[r][w] = (b.x >> 31) ? valid_mask(L, w) : 0u;
+    } else if (a.init) {
       // INIT stream: site x of row y <- word x%4 of group y*ceil(L/4) + x/4
       const int G4 = (L + 3) >> 2;
 #pragma unroll

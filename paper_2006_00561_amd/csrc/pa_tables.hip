@@ -53,7 +53,9 @@ int build_tables(const uint32_t* h, int nbins, int shift, int N, int64_t R,
   int lo, hi;
   occupied_range(h, nbins, &lo, &hi);
   if (lo > hi || R < 1) return PA_ESTATE;
-  const int Emin = level_energy(N, shift, lo);
+  // the energy the weights are shifted by: the smallest one when cooling,
+  // the largest one when heating (dbeta < 0), so every weight is at most 1
+  const int Emin = level_energy(N, shift, dbeta < 0.0 ? hi : lo);
   const int nl = hi - lo + 1;
   // (b) Boltzmann factors shifted by Emin, summed in ascending energy
   std::vector<double> w((size_t)nl, 0.0);
@@ -100,7 +102,7 @@ int build_poisson_tables(const uint32_t* h, int nbins, int shift, int N,
   int lo, hi;
   occupied_range(h, nbins, &lo, &hi);
   if (lo > hi || R < 1) return PA_ESTATE;
-  const int Emin = level_energy(N, shift, lo);
+  const int Emin = level_energy(N, shift, dbeta < 0.0 ? hi : lo);
   const int nl = hi - lo + 1;
   // the weights, S and ln Q exactly as for the nearest-integer tables
   std::vector<double> w((size_t)nl, 0.0);

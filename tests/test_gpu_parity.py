@@ -155,8 +155,11 @@ def test_state_errors(pa):
     assert e.value.code == pa.PA_ESTATE
     g.resample(0.2)
     with pytest.raises(pa.PAError) as e:
-        g.resample(0.1)            # heating is not supported
+        g.resample(-0.1)           # beta stays >= 0
     assert e.value.code == pa.PA_EINVAL
+    with pytest.raises(pa.PAError) as e:
+        g.start_heating(2.0)       # only before the first resampling
+    assert e.value.code == pa.PA_ESTATE
     with pytest.raises(pa.PAError):
         g.set_population(np.zeros((3, 8, 8), np.int8))
 
@@ -475,5 +478,31 @@ def test_poisson_resampling_with_large_means(pa):
     g.sweep(2.0, 2)
     o.sweep(2)
     _cmp_state(g, o, "large means")
+    g.close()
+    o.close()
+
+
+@pytest.mark.parametrize("L,R,layout,law", [(16, 800, 0, 0), (12, 600, 1, 1)])
+def test_heating_matches_oracle(pa, L, R, layout, law):
+    """Heating protocol (Sec. 2): ground states at beta0 = 2.5, then beta
+    down to 0.2; every step bit-exact with the oracle."""
+    beta0, beta_f, K, theta = 2.5, 0.2, 30, 3
+    g = pa.Population(L, R, seed=12, population_id=1, layout=layout,
+                      resampling=law)
+    o = oracle.OraclePA(L, R, seed=12, pop=1, law=law)
+    g.start_heating(beta0)
+    o.start_heating(beta0)
+    _cmp_state(g, o, "ground states")
+    for i in range(1, K + 1):
+        b = beta0 + ((beta_f - beta0) * i) / K
+        R_old = g.R
+        assert g.resample(b) == o.resample(b)
+        assert np.array_equal(g.counts(), o.counts(R_old)), i
+        g.sweep(b, theta)
+        o.sweep(theta)
+        _cmp_state(g, o, "heating step %d" % i)
+        _cmp_obs(g.observables(), o.observables())
+    with pytest.raises(pa.PAError):
+        g.start_heating(1.0)                  # only before any resampling
     g.close()
     o.close()
