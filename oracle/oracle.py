@@ -99,6 +99,11 @@ def lib():
                                  C.POINTER(C.c_double)]
         L.orc_set_resampling.argtypes = [P, C.c_int]
         L.orc_start_heating.argtypes = [P, C.c_double]
+        L.orc_create_potts.argtypes = [C.c_int, C.c_int, C.c_int64, C.c_int64,
+                                       C.c_uint64, C.c_uint32,
+                                       C.POINTER(P)]
+        L.orc_potts_energy.argtypes = [C.c_int, C.c_int, P, i32p, i32p]
+        L.orc_potts_energy.restype = None
         L.orc_poisson_draw.argtypes = [C.c_double, C.c_uint32]
         L.orc_poisson_draw.restype = C.c_uint32
         L.orc_sweep_replica.argtypes = [C.c_int, P, i8p, C.POINTER(C.c_int32),
@@ -177,12 +182,18 @@ class OraclePA:
     """One population on the CPU oracle."""
 
     def __init__(self, L, R_target, seed=1, pop=0, J=None, capacity=0,
-                 law=NEAREST):
-        self.L, self.N = L, L * L
+                 law=NEAREST, q=0):
+        """q = 0: Ising spins (ferromagnet or the couplings J); q >= 2: the
+        q-state Potts ferromagnet."""
+        self.L, self.N, self.q = L, L * L, q
         self._Jc, jp = _jptr(J)
         h = C.c_void_p()
-        _check(lib().orc_create(L, jp, R_target, capacity, seed, pop,
-                                C.byref(h)), "create")
+        if q:
+            _check(lib().orc_create_potts(L, q, R_target, capacity, seed, pop,
+                                          C.byref(h)), "create_potts")
+        else:
+            _check(lib().orc_create(L, jp, R_target, capacity, seed, pop,
+                                    C.byref(h)), "create")
         self._h = h
         if law != NEAREST:
             _check(lib().orc_set_resampling(h, law), "set_resampling")

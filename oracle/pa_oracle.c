@@ -73,6 +73,7 @@ struct orc_pa {
   int sweeps_at_step;
   uint64_t shuffle_seed;
   int law;          /* ORC_NEAREST or ORC_POISSON */
+  int q;            /* 0: Ising spins +-1; 2..16: Potts states 0..q-1 */
 };
 
 /* ---------------------------------------------------------------- Philox */
@@ -150,13 +151,36 @@ void orc_energy(int L, const int8_t* J, const int8_t* s, int32_t* E,
   *M = (int32_t)m;
 }
 
+/* The q-state Potts ferromagnet (Sec. 2 names it with the heating
+   protocol): H = -sum over the 2N bonds of delta(s, s'), so E lies in
+   [-2N, 0]; the magnetisation-like integer M = q n_0 - N counts the sites
+   in state 0 (its |M| and M^2 averages are the reported moments). */
+void orc_potts_energy(int L, int q, const int8_t* s, int32_t* E, int32_t* M) {
+  int64_t e = 0, n0 = 0;
+  for (int y = 0; y < L; ++y)
+    for (int x = 0; x < L; ++x) {
+      int sv = s[y * L + x];
+      e -= (sv == s[y * L + (x + 1) % L]);
+      e -= (sv == s[((y + 1) % L) * L + x]);
+      n0 += (sv == 0);
+    }
+  *E = (int32_t)e;
+  *M = (int32_t)((int64_t)q * n0 - (int64_t)L * L);
+}
+
+/* floor(w q / 2^32): a state in [0, q) from a 32-bit word */
+static int potts_state(uint32_t w, int q) {
+  return (int)(((uint64_t)w * (uint64_t)q) >> 32);
+}
+
 /* ------------------------------------------------------------- lifetime */
 
-int orc_create(int L, const int8_t* J, int64_t R_t, int64_t cap,
-               uint64_t seed, uint32_t pop, orc_pa** out) {
+static int create(int L, const int8_t* J, int q, int64_t R_t, int64_t cap,
+                  uint64_t seed, uint32_t pop, orc_pa** out) {
   if (!out) return ORC_EINVAL;
   *out = NULL;
   if (L < 4 || L > 128 || (L % 2) != 0) return ORC_EINVAL;
+  if (q != 0 && (q < 2 || q > 16 || J)) return ORC_EINVAL;
   if (R_t < 1 || R_t > ((int64_t)1 << 31)) return ORC_EINVAL;
   if (cap == 0) cap = R_t + 16 * (int64_t)ceil(sqrt((double)R_t)) + 1024;
   if (cap < R_t) return ORC_EINVAL;
@@ -168,6 +192,7 @@ int orc_create(int L, const int8_t* J, int64_t R_t, int64_t cap,
   p->cap = cap;
   p->seed = seed;
   p->pop = pop;
+  p->q = q;
   size_t N = (size_t)p->N;
   p->spins = (int8_t*)malloc((size_t)cap * N);
   p->E = (int32_t*)malloc((size_t)cap * sizeof(int32_t));
@@ -192,20 +217,33 @@ int orc_create(int L, const int8_t* J, int64_t R_t, int64_t cap,
       for (int x = 0; x < L; ++x) {
         uint32_t w = draw_word(seed, DOMAIN_INIT, (uint32_t)(y * G4 + x / 4), 0,
                                0, (uint32_t)j, pop, x % 4);
-        s[y * L + x] = (w >> 31) ? 1 : -1;
+        /* Potts: a uniform state floor(w q / 2^32) */
+        s[y * L + x] = q ? (int8_t)potts_state(w, q) : ((w >> 31) ? 1 : -1);
       }
-    orc_energy(L, p->J, s, &p->E[j], &p->M[j]);
+    if (q) orc_potts_energy(L, q, s, &p->E[j], &p->M[j]);
+    else orc_energy(L, p->J, s, &p->E[j], &p->M[j]);
   }
   p->R = R_t;
   p->beta = 0.0;
-  /* ln Omega: 2^N states, all with weight 1 at beta_0 = 0. */
-  p->lnZ = (ORC_MUTANT == 7) ? 0.0 : (double)p->N * log(2.0);
+  /* ln Omega: 2^N (q^N) states, all with weight 1 at beta_0 = 0. */
+  p->lnZ = (ORC_MUTANT == 7) ? 0.0 : (double)p->N * log(q ? (double)q : 2.0);
   p->lnQ_last = 0.0;
   p->step = 0;
   p->sweeps_at_step = 0;
   p->n_len = 0;
   *out = p;
   return ORC_OK;
+}
+
+int orc_create(int L, const int8_t* J, int64_t R_t, int64_t cap,
+               uint64_t seed, uint32_t pop, orc_pa** out) {
+  return create(L, J, 0, R_t, cap, seed, pop, out);
+}
+
+int orc_create_potts(int L, int q, int64_t R_t, int64_t cap, uint64_t seed,
+                     uint32_t pop, orc_pa** out) {
+  if (q < 2) return ORC_EINVAL;
+  return create(L, NULL, q, R_t, cap, seed, pop, out);
 }
 
 void orc_destroy(orc_pa* p) {
@@ -437,6 +475,59 @@ static void sweep_one(int L, const int8_t* J, int8_t* s, int32_t* E,
 
 /* Metropolis acceptance probabilities exp(-beta dE) for dE = 4, 8 as
    32-bit integer thresholds: accept iff r < floor(p 2^32). */
+/* Checkerboard Metropolis for the Potts model: colour 0 first; a colour
+   site proposes one of the other q - 1 states uniformly,
+   s' = (s + 1 + floor(w q' / 2^32)) mod q with q' = q - 1, and accepts iff
+   dE = (#neighbours in s) - (#neighbours in s') <= 0 or r < T[dE],
+   T[d] = floor(exp(-beta d) 2^32).  Colour site k = x/2 of row y uses
+   Philox group y*ceil(L/4) + k/2: words 2(k%2) (proposal w) and
+   2(k%2) + 1 (acceptance r). */
+static void sweep_potts_one(int L, int q, int8_t* s, int32_t* E, int32_t* M,
+                            uint64_t seed, uint32_t pop, int step, int t0,
+                            int theta, uint32_t slot, const uint64_t T[5]) {
+  int G4 = (L + 3) / 4;
+  for (int t = 0; t < theta; ++t) {
+    int tt = t0 + t;
+    for (int c = 0; c < 2; ++c) {
+      for (int y = 0; y < L; ++y)
+        for (int x = 0; x < L; ++x) {
+          if (((x + y) & 1) != c) continue;
+          int k = x / 2;
+          uint32_t ctr[4], key[2], out[4];
+          ctr[0] = (DOMAIN_MCMC << 28) | (uint32_t)(y * G4 + k / 2);
+          ctr[1] = ((uint32_t)step << 16) | (uint32_t)(2 * tt + c);
+          ctr[2] = slot;
+          ctr[3] = pop;
+          key[0] = (uint32_t)(seed & 0xFFFFFFFFu);
+          key[1] = (uint32_t)(seed >> 32);
+          orc_philox4x32_10(ctr, key, out);
+          uint32_t w = out[2 * (k % 2)], r = out[2 * (k % 2) + 1];
+          int sv = s[y * L + x];
+          int sn = (sv + 1 + potts_state(w, q - 1)) % q;
+          int nb[4] = {s[y * L + (x + 1) % L], s[y * L + (x + L - 1) % L],
+                       s[((y + 1) % L) * L + x], s[((y + L - 1) % L) * L + x]};
+          int n_old = 0, n_new = 0;
+          for (int i = 0; i < 4; ++i) {
+            n_old += (nb[i] == sv);
+            n_new += (nb[i] == sn);
+          }
+          int dE = (ORC_MUTANT == 10) ? n_new - n_old : n_old - n_new;
+          if (dE <= 0 || (uint64_t)r < T[dE]) {
+            s[y * L + x] = (int8_t)sn;
+            *E += dE;
+            *M += q * ((sn == 0) - (sv == 0));
+          }
+        }
+    }
+  }
+}
+
+static void potts_thresholds(double beta, uint64_t T[5]) {
+  T[0] = (uint64_t)1 << 32;
+  for (int d = 1; d <= 4; ++d)
+    T[d] = (uint64_t)floor(ldexp(exp(-(beta * (double)d)), 32));
+}
+
 static void thresholds(double beta, uint64_t* T4, uint64_t* T8) {
   *T4 = (uint64_t)floor(ldexp(exp(-(beta * 4.0)), 32));
   *T8 = (uint64_t)floor(ldexp(exp(-(beta * 8.0)), 32));
@@ -457,6 +548,16 @@ int orc_sweep_replica(int L, const int8_t* J, int8_t* spins, int32_t* E,
 int orc_sweep(orc_pa* p, int theta) {
   if (!p || theta < 0) return ORC_EINVAL;
   if (p->sweeps_at_step + theta > 32767) return ORC_EINVAL;
+  if (p->q) {
+    uint64_t T[5];
+    potts_thresholds(p->beta, T);
+    for (int64_t j = 0; j < p->R; ++j)
+      sweep_potts_one(p->L, p->q, p->spins + (size_t)j * p->N, &p->E[j],
+                      &p->M[j], p->seed, p->pop, p->step, p->sweeps_at_step,
+                      theta, (uint32_t)j, T);
+    p->sweeps_at_step += theta;
+    return ORC_OK;
+  }
   uint64_t T4, T8;
   thresholds(p->beta, &T4, &T8);
   for (int64_t j = 0; j < p->R; ++j)
@@ -541,11 +642,19 @@ int orc_start_heating(orc_pa* p, double beta0) {
   for (int64_t j = 0; j < p->R; ++j) {
     uint32_t w = draw_word(p->seed, DOMAIN_INIT, 0, 0, 0, (uint32_t)j, p->pop,
                            0);
-    memset(p->spins + (size_t)j * N, (w >> 31) ? 1 : -1, N);
-    orc_energy(p->L, p->J, p->spins + (size_t)j * N, &p->E[j], &p->M[j]);
+    int8_t* s = p->spins + (size_t)j * N;
+    if (p->q) {  /* the q ground states: every site in one state */
+      memset(s, potts_state(w, p->q), N);
+      orc_potts_energy(p->L, p->q, s, &p->E[j], &p->M[j]);
+    } else {
+      memset(s, (w >> 31) ? 1 : -1, N);
+      orc_energy(p->L, p->J, s, &p->E[j], &p->M[j]);
+    }
   }
   p->beta = beta0;
-  p->lnZ = log(2.0) + ((ORC_MUTANT == 9) ? 0.0 : 2.0 * (double)p->N * beta0);
+  /* ln(#ground states) - beta0 E_0 with E_0 = -2N */
+  p->lnZ = log(p->q ? (double)p->q : 2.0) +
+           ((ORC_MUTANT == 9) ? 0.0 : 2.0 * (double)p->N * beta0);
   p->lnQ_last = 0.0;
   p->n_len = 0;
   return ORC_OK;
@@ -554,10 +663,17 @@ int orc_start_heating(orc_pa* p, double beta0) {
 int orc_set_population(orc_pa* p, const int8_t* spins, int64_t R) {
   if (!p || !spins || R < 1 || R > p->cap) return ORC_EINVAL;
   for (int64_t i = 0; i < R * p->N; ++i)
-    if (spins[i] != 1 && spins[i] != -1) return ORC_EINVAL;
+    if (p->q ? (spins[i] < 0 || spins[i] >= p->q)
+             : (spins[i] != 1 && spins[i] != -1))
+      return ORC_EINVAL;
   memcpy(p->spins, spins, (size_t)R * p->N);
-  for (int64_t j = 0; j < R; ++j)
-    orc_energy(p->L, p->J, p->spins + (size_t)j * p->N, &p->E[j], &p->M[j]);
+  for (int64_t j = 0; j < R; ++j) {
+    if (p->q)
+      orc_potts_energy(p->L, p->q, p->spins + (size_t)j * p->N, &p->E[j],
+                       &p->M[j]);
+    else
+      orc_energy(p->L, p->J, p->spins + (size_t)j * p->N, &p->E[j], &p->M[j]);
+  }
   p->R = R;
   p->n_len = 0;
   return ORC_OK;

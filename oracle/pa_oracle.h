@@ -59,6 +59,13 @@ void orc_energy(int L, const int8_t* J, const int8_t* spins, int32_t* E,
    cap = 0 selects R_t + 16*ceil(sqrt(R_t)) + 1024. */
 int orc_create(int L, const int8_t* J, int64_t R_t, int64_t cap,
                uint64_t seed, uint32_t pop, orc_pa** out);
+/* The q-state Potts ferromagnet (2 <= q <= 16): states 0..q-1, uniform at
+   beta0 = 0 (state floor(w q / 2^32) of the site's INIT word), ln Z = N ln q;
+   H = -sum over bonds of delta(s, s'); M = q n_0 - N. */
+int orc_create_potts(int L, int q, int64_t R_t, int64_t cap, uint64_t seed,
+                     uint32_t pop, orc_pa** out);
+void orc_potts_energy(int L, int q, const int8_t* spins, int32_t* E,
+                      int32_t* M);
 void orc_destroy(orc_pa* p);
 
 /* Heating protocol: replace a fresh ferromagnet population by ground states

@@ -33,6 +33,8 @@ CASES = {
         ["test_oracle_poisson.py::test_draw_inverts_the_poisson_cdf"]),
     9: ("the ground-state energy term dropped from the heating start's ln Z",
         ["test_oracle_heating.py::test_heating_lnZ_L4_matches_enumeration"]),
+    10: ("sign of the Potts energy change flipped",
+         ["test_oracle_potts.py::test_metropolis_samples_boltzmann_q3_L4"]),
 }
 
 
