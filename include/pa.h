@@ -52,14 +52,19 @@ enum {
                         population file of this library                   */
 };
 
-enum { PA_FERRO = 0, PA_PMJ = 1 };     /* model                */
+enum { PA_FERRO = 0, PA_PMJ = 1, PA_POTTS = 2 };  /* model     */
 enum { PA_INT8 = 0, PA_BITS = 1 };     /* device spin layout   */
 enum { PA_NEAREST = 0, PA_POISSON = 1 }; /* resampling law      */
 
 typedef struct {
   int32_t L;          /* lattice side, even, 4 <= L <= 128 (checkerboard on
                          a torus needs even L)                               */
-  int32_t model;      /* PA_FERRO (J = 1 on every bond, Eq. Ham) or PA_PMJ */
+  int32_t model;      /* PA_FERRO (J = 1 on every bond, Eq. Ham), PA_PMJ, or
+                         PA_POTTS: the q-state Potts ferromagnet named with
+                         the heating protocol in Sec. 2, H = -sum over bonds
+                         of delta(s, s'), states 0..q-1 as int8 spins,
+                         M = q n_0 - N; PA_INT8 layout only, single
+                         populations only                                  */
   const int8_t* J;    /* PA_PMJ: host int8 +-1 [2][L][L]; plane 0 is the bond
                          from (x,y) to (x+1,y), plane 1 the bond to (x,y+1);
                          copied at pa_init.  NULL for PA_FERRO.             */
@@ -85,6 +90,7 @@ typedef struct {
                          list of k ending after C(k) >= 1 - 2^-32 or before
                          ceil(rho + 64 sqrt(rho) + 64).  Single populations
                          only: pa_batch_init rejects PA_POISSON.           */
+  int32_t q;          /* PA_POTTS: number of states, 2..16; else ignored   */
 } pa_config;
 
 typedef struct {
@@ -149,11 +155,13 @@ int pa_sweep(pa_ctx* c, double beta, int32_t theta);
 int pa_resample(pa_ctx* c, double beta_next, int64_t* R_new);
 
 /* Sec. 2, heating protocol (the population starts close to zero
-   temperature): replaces the population of a fresh ferromagnet context
-   (step 0) by ground states at beta0 > 0 -- every spin of replica j equals
-   the top bit of its INIT word of site (0,0) (+1 when set) -- and sets
-   beta = beta0, ln Z = ln 2 + 2 N beta0 (the two states of energy -2N; the
-   excited states' share, about N exp(-8 beta0), is left out).  Resampling
+   temperature): replaces the population of a fresh ferromagnet or Potts
+   context (step 0) by ground states at beta0 > 0 -- every spin of replica j
+   equals the top bit of its INIT word of site (0,0) (+1 when set), or for
+   Potts the state floor(w q / 2^32) of that word -- and sets beta = beta0,
+   ln Z = ln(#ground states) + 2 N beta0 (2 or q states of energy -2N; the
+   excited states' share, about N exp(-8 beta0) for Ising and
+   2qN exp(-4 beta0) for Potts, is left out).  Resampling
    then steps beta down; weights are shifted by the largest energy when
    beta decreases.  PA_EINVAL for +-J couplings or beta0 <= 0, PA_ESTATE
    after a resampling.  Synchronises. */
@@ -212,7 +220,7 @@ int pa_bisect_dbeta(pa_ctx* c, double target, double beta_f, double* dbeta);
 /* Checkpoint and resume.  pa_save writes the whole state of the context to
    a file: configuration, couplings, beta, step, sweeps made at this step,
    ln Z and the last ln Q, and the population in the canonical layout with
-   its E and M (a fixed 96-byte header "PAPOPv01" first; little-endian).
+   its E and M (a fixed 104-byte header "PAPOPv02" first; little-endian).
    It synchronises; a pending resampling copy is made first.  pa_load
    creates a new context on `stream` (a hipStream_t or NULL) from such a
    file: because every random number is keyed by (step, sweep, slot,

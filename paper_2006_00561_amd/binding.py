@@ -17,7 +17,7 @@ SO_PATH = os.path.join(HERE, "libpa.so")
 
 (PA_OK, PA_EINVAL, PA_ENOMEM, PA_ECAPACITY, PA_EDEVICE, PA_ESTATE, PA_EEMPTY,
  PA_EIO) = (0, -1, -2, -3, -4, -5, -6, -7)
-PA_FERRO, PA_PMJ = 0, 1
+PA_FERRO, PA_PMJ, PA_POTTS = 0, 1, 2
 PA_INT8, PA_BITS = 0, 1
 PA_NEAREST, PA_POISSON = 0, 1
 KERNEL_CLASSES = ("init", "sweep", "hist", "counts", "scatter", "gather")
@@ -30,7 +30,7 @@ class pa_config(C.Structure):
                 ("capacity", C.c_int64), ("layout", C.c_int32),
                 ("rows_per_lane", C.c_int32), ("seed", C.c_uint64),
                 ("population_id", C.c_uint32), ("stream", C.c_void_p),
-                ("resampling", C.c_int32)]
+                ("resampling", C.c_int32), ("q", C.c_int32)]
 
 
 class pa_obs(C.Structure):
@@ -156,12 +156,15 @@ class Population:
 
     def __init__(self, L, R_target, seed=1, population_id=0, J=None,
                  layout=PA_INT8, capacity=0, rows_per_lane=0, stream=None,
-                 resampling=PA_NEAREST):
+                 resampling=PA_NEAREST, q=0):
+        """J: +-J couplings (None = ferromagnet); q >= 2: the q-state Potts
+        ferromagnet (spins are states 0..q-1)."""
         self.L, self.N = L, L * L
         self._J = None if J is None else np.ascontiguousarray(J, np.int8)
         cfg = pa_config()
         cfg.L = L
-        cfg.model = PA_FERRO if J is None else PA_PMJ
+        cfg.model = PA_POTTS if q else (PA_FERRO if J is None else PA_PMJ)
+        cfg.q = q
         cfg.J = _ptr(self._J)
         cfg.R_target = R_target
         cfg.capacity = capacity

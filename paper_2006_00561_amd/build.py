@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 SO = os.path.join(HERE, "libpa.so")
 SOURCES = ["pa_kernels.hip", "pa_tables.hip", "pa_api.hip", "pa_batch.hip",
-           "pa_mlp.hip"]
+           "pa_mlp.hip", "pa_potts.hip"]
 ARCH = os.environ.get("PA_OFFLOAD_ARCH", "gfx950")
 
 

@@ -41,6 +41,7 @@ struct pa_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   int L = 0, N = 0, model = 0, layout = 0, W = 0, rpl = 1, lpr = 0, rpw = 0;
+  int q = 0;  // Potts states (PA_POTTS), else 0
   int64_t R_t = 0, cap = 0, R = 0, stride = 0, ntiles_cap = 0;
   uint64_t seed = 0;
   uint32_t pop = 0;
@@ -179,13 +180,18 @@ LatticeArgs lattice_args(pa_ctx* c) {
   a.step = (uint32_t)c->step;
   a.t0 = c->sweeps_at_step;
   a.one = 1u;
+  a.q = c->q;
+  if (c->model == PA_POTTS) potts_thresholds(c->beta, a.Tp);
   return a;
 }
 
 int run_lattice(pa_ctx* c, LatticeArgs& a, int cls) {
   hipEvent_t e0 = t_begin(c, cls);
-  CK(launch_lattice(a, c->W, c->rpl, c->layout == PA_INT8, c->model == PA_PMJ,
-                    c->stream));
+  if (c->model == PA_POTTS)
+    CK(launch_potts(a, c->stream));
+  else
+    CK(launch_lattice(a, c->W, c->rpl, c->layout == PA_INT8,
+                      c->model == PA_PMJ, c->stream));
   t_end(c, cls, e0, 0, 0, (a.init ? 1 : 2) * c->stride + 8,
         (int64_t)c->N * a.theta);
   return PA_OK;
@@ -357,9 +363,14 @@ int pa_init(const pa_config* cfg, pa_ctx** out) {
   if (!cfg) return PA_EINVAL;
   const int L = cfg->L;
   if (L < 4 || L > 128 || (L & 1)) return PA_EINVAL;
-  if (cfg->model != PA_FERRO && cfg->model != PA_PMJ) return PA_EINVAL;
+  if (cfg->model != PA_FERRO && cfg->model != PA_PMJ &&
+      cfg->model != PA_POTTS)
+    return PA_EINVAL;
   if (cfg->model == PA_PMJ && !cfg->J) return PA_EINVAL;
   if (cfg->layout != PA_INT8 && cfg->layout != PA_BITS) return PA_EINVAL;
+  if (cfg->model == PA_POTTS &&
+      (cfg->q < 2 || cfg->q > 16 || cfg->layout != PA_INT8))
+    return PA_EINVAL;
   if (cfg->resampling != PA_NEAREST && cfg->resampling != PA_POISSON)
     return PA_EINVAL;
   if (cfg->R_target < 1 || cfg->R_target >= (1ll << 31)) return PA_EINVAL;
@@ -401,8 +412,12 @@ int pa_init(const pa_config* cfg, pa_ctx** out) {
   c->pop = cfg->population_id;
   c->stride = (c->layout == PA_INT8) ? round_up(c->N, 16)
                                      : round_up((int64_t)L * W * 4, 16);
-  c->hshift = (c->model == PA_FERRO) ? 2 : 1;
-  c->nbins = (4 * c->N >> c->hshift) + 1;
+  c->q = (c->model == PA_POTTS) ? cfg->q : 0;
+  // energy levels: Ising E in [-2N, 2N] (steps of 4 for the ferromagnet,
+  // of 2 with +-J couplings); Potts E in [-2N, 0] in steps of 1
+  c->hshift = (c->model == PA_FERRO) ? 2 : (c->model == PA_PMJ) ? 1 : 0;
+  c->nbins = (c->model == PA_POTTS) ? 2 * c->N + 1
+                                    : (4 * c->N >> c->hshift) + 1;
   c->ntiles_cap = (cap + 255) / 256;
 
   bool ok = true;
@@ -460,7 +475,8 @@ int pa_init(const pa_config* cfg, pa_ctx** out) {
     return rc;
   }
   c->beta = 0.0;
-  c->lnZ = (double)c->N * std::log(2.0);
+  // ln Omega: 2^N Ising states, q^N Potts states, all of weight 1 at beta 0
+  c->lnZ = (double)c->N * std::log(c->q ? (double)c->q : 2.0);
   c->lnQ_last = 0.0;
   *out = c;
   return PA_OK;
@@ -615,7 +631,7 @@ int pa_resample(pa_ctx* c, double beta_next, int64_t* R_new) {
 
 int pa_start_heating(pa_ctx* c, double beta0) {
   if (!c || !std::isfinite(beta0) || !(beta0 > 0.0)) return PA_EINVAL;
-  if (c->model != PA_FERRO) return PA_EINVAL;
+  if (c->model == PA_PMJ) return PA_EINVAL;
   if (c->step != 0) return PA_ESTATE;
   int rc = sync(c);
   if (rc) return rc;
@@ -629,8 +645,8 @@ int pa_start_heating(pa_ctx* c, double beta0) {
   rc = sync(c);
   if (rc) return rc;
   c->beta = beta0;
-  // two ground states of energy -2N
-  c->lnZ = std::log(2.0) + 2.0 * (double)c->N * beta0;
+  // the ground states (2 Ising, q Potts) have energy -2N
+  c->lnZ = std::log(c->q ? (double)c->q : 2.0) + 2.0 * (double)c->N * beta0;
   c->lnQ_last = 0.0;
   c->sweeps_at_step = 0;
   c->n_len = 0;
@@ -731,7 +747,9 @@ int pa_get_counts(pa_ctx* c, uint32_t* n, int64_t cap, int64_t* len) {
 int pa_set_population(pa_ctx* c, const int8_t* spins, int64_t R) {
   if (!c || !spins || R < 1 || R > c->cap) return PA_EINVAL;
   for (int64_t i = 0; i < R * c->N; ++i)
-    if (spins[i] != 1 && spins[i] != -1) return PA_EINVAL;
+    if (c->q ? (spins[i] < 0 || spins[i] >= c->q)
+             : (spins[i] != 1 && spins[i] != -1))
+      return PA_EINVAL;
   int rc = sync(c);
   if (rc) return rc;
   c->gather_pending = false;  // the new population replaces the pending one
@@ -805,6 +823,7 @@ int pa_get_config(pa_ctx* c, pa_config* out) {
   k.population_id = c->pop;
   k.stream = c->stream;
   k.resampling = c->law;
+  k.q = c->q;
   *out = k;
   return PA_OK;
 }
@@ -815,7 +834,7 @@ namespace {
 
 // Population file: a fixed header, the couplings (+-J only), then the
 // population in the canonical layout.  Little-endian, as the host.
-constexpr char kMagic[8] = {'P', 'A', 'P', 'O', 'P', 'v', '0', '1'};
+constexpr char kMagic[8] = {'P', 'A', 'P', 'O', 'P', 'v', '0', '2'};
 struct FileHeader {
   char magic[8];
   int64_t R_target, capacity, seed, R;
@@ -823,8 +842,9 @@ struct FileHeader {
   int32_t L, model, layout, rows_per_lane;
   uint32_t population_id;
   int32_t step, sweeps_at_step, resampling;
+  int32_t q, reserved;
 };
-static_assert(sizeof(FileHeader) == 8 + 4 * 8 + 3 * 8 + 8 * 4,
+static_assert(sizeof(FileHeader) == 8 + 4 * 8 + 3 * 8 + 10 * 4,
               "population file header must have no padding");
 
 struct File {
@@ -867,6 +887,7 @@ int pa_save(pa_ctx* c, const char* path) {
   h.step = c->step;
   h.sweeps_at_step = c->sweeps_at_step;
   h.resampling = c->law;
+  h.q = c->q;
   File f(std::fopen(path, "wb"));
   if (!f.f) return PA_EIO;
   bool ok = f.write(&h, sizeof h);
@@ -889,7 +910,9 @@ int pa_load(const char* path, void* stream, pa_ctx** out) {
   if (!f.read(&h, sizeof h) || std::memcmp(h.magic, kMagic, 8) != 0)
     return PA_EIO;
   if (h.L < 4 || h.L > 128 || (h.L & 1) || h.R < 1 || h.R > h.capacity ||
-      h.capacity >= (1ll << 32) || (h.model != PA_FERRO && h.model != PA_PMJ) ||
+      h.capacity >= (1ll << 32) ||
+      (h.model != PA_FERRO && h.model != PA_PMJ && h.model != PA_POTTS) ||
+      (h.model == PA_POTTS && (h.q < 2 || h.q > 16)) ||
       h.step < 0 || h.step > 65535 || h.sweeps_at_step < 0 ||
       h.sweeps_at_step > 32767 || !std::isfinite(h.beta) || !(h.beta >= 0.0) ||
       (h.resampling != PA_NEAREST && h.resampling != PA_POISSON))
@@ -908,7 +931,8 @@ int pa_load(const char* path, void* stream, pa_ctx** out) {
   char extra;
   if (f.read(&extra, 1)) return PA_EIO;  // trailing bytes: not our file
   for (int8_t v : spins)
-    if (v != 1 && v != -1) return PA_EIO;
+    if (h.model == PA_POTTS ? (v < 0 || v >= h.q) : (v != 1 && v != -1))
+      return PA_EIO;
   pa_config cfg{};
   cfg.L = h.L;
   cfg.model = h.model;
@@ -921,6 +945,7 @@ int pa_load(const char* path, void* stream, pa_ctx** out) {
   cfg.population_id = h.population_id;
   cfg.stream = stream;
   cfg.resampling = h.resampling;
+  cfg.q = h.q;
   pa_ctx* c = nullptr;
   int rc = pa_init(&cfg, &c);
   if (rc) return rc == PA_EINVAL ? PA_EIO : rc;

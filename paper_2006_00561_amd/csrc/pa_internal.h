@@ -36,6 +36,10 @@ struct LatticeArgs {
   int32_t t0, theta;      // first sweep index at this step, sweep count
   int32_t init;           // 1: draw the spins from the INIT stream;
                           // 2: ferromagnet ground states (heating start)
+  // q-state Potts pass only: the number of states and the acceptance
+  // thresholds T[d - 1] = floor(exp(-beta d) 2^32), d = 1..4
+  int32_t q;
+  uint64_t Tp[4];
 };
 
 struct HistArgs {
@@ -140,6 +144,7 @@ struct TableRange {
 };
 void occupied_range(const uint32_t* h, int nbins, int* lo, int* hi);
 void metropolis_K(double beta, uint64_t* K4, uint64_t* K8);
+void potts_thresholds(double beta, uint64_t Tp[4]);
 int build_tables(const uint32_t* h, int nbins, int shift, int N, int64_t R,
                  int64_t R_t, double dbeta, uint32_t* f, uint32_t* T,
                  TableRange* out);
@@ -160,6 +165,7 @@ double bisect_from_hist(const uint32_t* h, int nbins, int shift, int N,
 hipError_t launch_lattice(const LatticeArgs& a, int W, int RPL, bool int8,
                           bool glass, hipStream_t st);
 hipError_t launch_hist(const HistArgs& a, hipStream_t st);
+hipError_t launch_potts(const LatticeArgs& a, hipStream_t st);
 hipError_t launch_counts(const CountsArgs& a, hipStream_t st);
 hipError_t launch_scan(const uint32_t* tile_sum, uint32_t* tile_off,
                        int64_t ntiles, unsigned long long* total,

@@ -47,6 +47,13 @@ void metropolis_K(double beta, uint64_t* K4, uint64_t* K8) {
   *K8 = (1ull << 32) - T8;
 }
 
+// Potts acceptance thresholds T[d - 1] = floor(exp(-beta d) 2^32) for an
+// energy increase d = 1..4 (beta = 0 gives 2^32: always accept).
+void potts_thresholds(double beta, uint64_t Tp[4]) {
+  for (int d = 1; d <= 4; ++d)
+    Tp[d - 1] = (uint64_t)std::floor(std::ldexp(std::exp(-(beta * (double)d)), 32));
+}
+
 int build_tables(const uint32_t* h, int nbins, int shift, int N, int64_t R,
                  int64_t R_t, double dbeta, uint32_t* f, uint32_t* T,
                  TableRange* out) {

@@ -69,15 +69,15 @@ def test_product_path_does_not_touch_the_oracle():
                 assert "oracle" not in src.lower(), f
 
 
-def _pop_file(path, L=4, R=2, spins=None, extra=b"", magic=b"PAPOPv01"):
-    """A population file written from the documented layout: 96-byte header,
-    spins [R][L][L] int8, E and M int32."""
+def _pop_file(path, L=4, R=2, spins=None, extra=b"", magic=b"PAPOPv02"):
+    """A population file written from the documented layout: 104-byte
+    header, spins [R][L][L] int8, E and M int32."""
     import struct
     N = L * L
-    hdr = magic + struct.pack("<qqqqdddiiiiIiii", R, R + 100, 1, R, 0.25,
+    hdr = magic + struct.pack("<qqqqdddiiiiIiiiii", R, R + 100, 1, R, 0.25,
                               N * 0.6931471805599453, 0.0, L, 0, 0, 1, 0, 3,
-                              0, 0)
-    assert len(hdr) == 96
+                              0, 0, 0, 0)
+    assert len(hdr) == 104
     s = bytes([1] * (R * N)) if spins is None else spins
     E = struct.pack("<%di" % R, *([-2 * N] * R))
     M = struct.pack("<%di" % R, *([N] * R))
@@ -102,7 +102,7 @@ def test_load_rejects_bad_files_before_any_device_work(tmp_path):
     p = str(tmp_path / "short.pa")
     _pop_file(p)
     with open(p, "r+b") as f:
-        f.truncate(96 + 10)
+        f.truncate(104 + 10)
     assert lib.pa_load(p.encode(), None, C.byref(h)) == b.PA_EIO
     assert lib.pa_save(None, p.encode()) == b.PA_EINVAL
     assert lib.pa_strerror(b.PA_EIO).decode().startswith("population file")

@@ -52,12 +52,13 @@ def _cmp_state(g, o, tag):
 
 
 def _parity_run(pa, L, R, steps, theta, beta_f, seed=1, pop=0, J=None,
-                layout=0, rpl=0, check_every=1, law=0):
-    print("parity L=%d R=%d steps=%d theta=%d layout=%d rpl=%d J=%s law=%d"
-          % (L, R, steps, theta, layout, rpl, J is not None, law), flush=True)
+                layout=0, rpl=0, check_every=1, law=0, q=0):
+    print("parity L=%d R=%d steps=%d theta=%d layout=%d rpl=%d J=%s law=%d "
+          "q=%d" % (L, R, steps, theta, layout, rpl, J is not None, law, q),
+          flush=True)
     g = pa.Population(L, R, seed=seed, population_id=pop, J=J, layout=layout,
-                      rows_per_lane=rpl, resampling=law)
-    o = oracle.OraclePA(L, R, seed=seed, pop=pop, J=J, law=law)
+                      rows_per_lane=rpl, resampling=law, q=q)
+    o = oracle.OraclePA(L, R, seed=seed, pop=pop, J=J, law=law, q=q)
     _cmp_state(g, o, "init")
     for i, b in enumerate(W.linear_schedule(beta_f, steps), start=1):
         R_old = g.R
@@ -504,5 +505,41 @@ def test_heating_matches_oracle(pa, L, R, layout, law):
         _cmp_obs(g.observables(), o.observables())
     with pytest.raises(pa.PAError):
         g.start_heating(1.0)                  # only before any resampling
+    g.close()
+    o.close()
+
+
+@pytest.mark.parametrize("L,R,q,beta_f,law", [(16, 600, 3, 1.2, 0),
+                                               (12, 500, 10, 1.8, 1),
+                                               (6, 300, 16, 2.0, 0),
+                                               (128, 40, 4, 1.1, 0)])
+def test_potts_matches_oracle(pa, L, R, q, beta_f, law):
+    """q-state Potts populations (Sec. 2 names the model): every step
+    bit-exact with the oracle, including q = 10 across its first-order
+    transition and the largest lattice."""
+    _parity_run(pa, L, R, 30, 3, beta_f, seed=8, pop=5, law=law, q=q)
+
+
+def test_potts_heating_and_resume(pa, tmp_path):
+    """Potts heating from ground states, saved and resumed halfway."""
+    L, R, q, beta0, beta_f, K = 10, 400, 10, 3.0, 0.8, 20
+    g = pa.Population(L, R, seed=21, q=q)
+    o = oracle.OraclePA(L, R, seed=21, q=q)
+    g.start_heating(beta0)
+    o.start_heating(beta0)
+    _cmp_state(g, o, "potts ground states")
+    path = str(tmp_path / "potts.pa")
+    for i in range(1, K + 1):
+        b = beta0 + ((beta_f - beta0) * i) / K
+        g.resample(b, wait=False)
+        o.resample(b)
+        g.sweep(b, 2)
+        o.sweep(2)
+        if i == K // 2:
+            g.save(path)
+            g.close()
+            g = pa.Population.load(path)
+        _cmp_state(g, o, "potts heating step %d" % i)
+    _cmp_obs(g.observables(), o.observables())
     g.close()
     o.close()
