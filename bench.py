@@ -43,6 +43,9 @@ VALU_OPS_PER_S = 256 * 4 * 16 * 2.4e9
 # Philox4x32-10 block (10 rounds of 2 32x32->64 multiplies and 2 three-input
 # xors = 40 ops per 4 words) plus one threshold test and one accumulate.
 ALGO_OPS_PER_ATTEMPT = 40 / 4 + 2
+# Potts: two words per attempt (proposal and acceptance, half a block) plus
+# one threshold test and one select.
+ALGO_OPS_PER_ATTEMPT_POTTS = 40 / 2 + 2
 
 
 KERNEL_SOURCES = ("paper_2006_00561_amd/csrc/pa_lattice.h",
@@ -87,7 +90,7 @@ def run_anneal(binding, cfg, stream, timing=None, rows_per_lane=0):
     L, R, theta = cfg["L"], cfg["R"], cfg["theta"]
     g = binding.Population(L, R, seed=cfg["seed"], layout=layout,
                            rows_per_lane=rows_per_lane, stream=stream,
-                           capacity=deferral_capacity(R))
+                           capacity=deferral_capacity(R), q=cfg.get("q", 0))
     if timing:
         g.set_timing(True, classes=timing)
     attempts = 0
@@ -459,7 +462,8 @@ def main():
     sw = tsum["sweep"]
     sweep_avg_ms = sw["ms"] / max(1, sw["launches"])
     sweep_rate = tsum["attempts"] / (sw["ms"] * 1e6)       # attempts/ns
-    achieved = tsum["attempts"] / sw["launches"] * ALGO_OPS_PER_ATTEMPT / (
+    ops = ALGO_OPS_PER_ATTEMPT_POTTS if cfg.get("q") else ALGO_OPS_PER_ATTEMPT
+    achieved = tsum["attempts"] / sw["launches"] * ops / (
         sweep_avg_ms * 1e-3) / 1e12
     peak = VALU_OPS_PER_S / 1e12
     # every kernel class timed, on one more anneal after the timed region
@@ -489,17 +493,20 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {
-            "workload": "%s: 2D Ising ferromagnet L=%d periodic, R=%d, %s "
+            "workload": "%s: 2D %s ferromagnet L=%d periodic, R=%d, %s "
                         "spins, beta 0->%g in %d linear steps, theta=%d, "
                         "seed %d; one step = one full anneal"
-                        % (args.workload, cfg["L"], cfg["R"], cfg["layout"],
+                        % (args.workload,
+                           ("%d-state Potts" % cfg["q"]) if cfg.get("q")
+                           else "Ising", cfg["L"], cfg["R"], cfg["layout"],
                            cfg["beta_f"], cfg["K"], cfg["theta"],
                            cfg["seed"]),
             "L": cfg["L"], "R": cfg["R"], "K": cfg["K"],
             "theta": cfg["theta"], "layout": cfg["layout"],
         },
         "roofline": {
-            "kernel": "k_lattice (theta fused Metropolis sweeps)",
+            "kernel": ("k_potts" if cfg.get("q") else "k_lattice") +
+                      " (theta fused Metropolis sweeps)",
             "bound": "alu",
             "achieved": achieved,
             "peak": peak,
@@ -508,7 +515,7 @@ def main():
             "traffic": measured_traffic(args.workload),
             "sweep_attempts_per_ns": sweep_rate,
             "sweep_avg_ms": sweep_avg_ms,
-            "ops_per_attempt": ALGO_OPS_PER_ATTEMPT,
+            "ops_per_attempt": ops,
         },
         "resample": {
             "note": "one extra anneal after the timed region with every "

@@ -16,7 +16,7 @@ from __future__ import annotations
 
 import numpy as np
 
-# name -> (L, R_target, layout, beta_f, K, theta, seed)
+# name -> (L, R_target, layout, beta_f, K, theta, seed[, q for Potts])
 CONFIGS = {
     # small case the oracle finishes in seconds
     "C1": dict(L=16, R=1000, layout="int8", beta_f=1.0, K=100, theta=5,
@@ -34,6 +34,11 @@ CONFIGS = {
                 seed=1),
     "CP10": dict(L=64, R=20480, layout="int8", beta_f=1.0, K=200, theta=10,
                  seed=1),
+    # the q = 10 Potts ferromagnet (named with the heating protocol in
+    # Sec. 2) at the same per-GPU shape, cooled across its first-order
+    # transition at beta_c = ln(1 + sqrt(10))
+    "CQ10": dict(L=64, R=20480, layout="int8", beta_f=1.6, K=200, theta=10,
+                 seed=1, q=10),
 }
 
 

@@ -2,9 +2,10 @@
 // model with the heating protocol): H = -sum over the 2N bonds of
 // delta(s, s'), states 0..q-1 stored one byte per site.
 //
-// One wave per replica (64-lane workgroups): the replica's L x L lattice is
-// staged in LDS (at most 16 KB at L = 128), swept theta times in place with
-// checkerboard Metropolis, then written back with its energy and M = q n_0 - N.
+// One wave per replica, up to 4 replicas per workgroup (at most 16 KB of LDS
+// per workgroup): the replica's L x L lattice is staged in LDS, swept theta
+// times in place with checkerboard Metropolis, then written back with its
+// energy and M = q n_0 - N.
 // As in the Ising pass, a pass after a resampling loads every new slot from
 // its parent in the other buffer, so the resampling copy costs no pass of its
 // own.
@@ -30,23 +31,27 @@ __device__ __forceinline__ uint32_t mulhi_q(uint32_t w, uint32_t q) {
   return (uint32_t)(((uint64_t)w * (uint64_t)q) >> 32);
 }
 
-__global__ __launch_bounds__(64) void k_potts(const LatticeArgs a) {
+__global__ __launch_bounds__(256) void k_potts(const LatticeArgs a) {
   extern __shared__ uint32_t lds_words[];
-  int8_t* lat = reinterpret_cast<int8_t*>(lds_words);
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wpb = blockDim.x >> 6;
   const int L = a.L, N = L * L, q = a.q;
   const int64_t R = a.Rdev ? min((int64_t)*a.Rdev, a.R) : a.R;
-  const int64_t rep = blockIdx.x;
-  if (rep >= R) return;  // the whole workgroup is this one replica
-  const uint32_t slot = (uint32_t)rep;
+  if ((int64_t)blockIdx.x * wpb >= R) return;  // the whole workgroup is idle
+  const int64_t rep = (int64_t)blockIdx.x * wpb + wave;
+  // a wave past the population keeps to the workgroup barriers only
+  const bool active = rep < R;
+  const uint32_t slot = (uint32_t)(active ? rep : 0);
   const int G4 = (L + 3) >> 2;
-  uint8_t* dst = a.spins + (size_t)rep * (size_t)a.stride;
-  const uint8_t* src =
-      a.parent ? a.src + (size_t)a.parent[rep] * (size_t)a.stride : dst;
-  uint32_t* lw = lds_words;
   const int nw = N >> 2;  // L is even, so N is a multiple of 4
+  uint32_t* lw = lds_words + (size_t)wave * nw;
+  int8_t* lat = reinterpret_cast<int8_t*>(lw);
+  uint8_t* dst = a.spins + (size_t)slot * (size_t)a.stride;
+  const uint8_t* src =
+      a.parent ? a.src + (size_t)a.parent[slot] * (size_t)a.stride : dst;
 
-  if (a.init == 2) {
+  if (!active) {
+  } else if (a.init == 2) {
     const uint4 b = philox10(make_uint4(kDomainInit << 28, 0u, slot, a.pop),
                              a.k0, a.k1);
     const uint32_t st = mulhi_q(b.x, (uint32_t)q);
@@ -69,11 +74,15 @@ __global__ __launch_bounds__(64) void k_potts(const LatticeArgs a) {
   }
   __syncthreads();
 
+  // work item g = y*G4 + m (a Philox group: sites 2m and 2m+1 of colour c
+  // in row y); lane items advance by 64 = dy rows and dm groups
+  const int dy = 64 / G4, dm = 64 - dy * G4;
+  const int y_first = lane / G4, m_first = lane - y_first * G4;
   for (int t = 0; t < a.theta; ++t) {
     for (int c = 0; c < 2; ++c) {
       const uint32_t ctr1 = (a.step << 16) | (uint32_t)(2 * (a.t0 + t) + c);
-      for (int g = lane; g < L * G4; g += 64) {
-        const int y = g / G4, m = g - y * G4;
+      int y = y_first, m = m_first;
+      for (int g = lane; active && g < L * G4; g += 64) {
         const uint4 b = philox10(make_uint4((kDomainMcmc << 28) | (uint32_t)g,
                                             ctr1, slot, a.pop),
                                  a.k0, a.k1);
@@ -94,19 +103,35 @@ __global__ __launch_bounds__(64) void k_potts(const LatticeArgs a) {
                          ((n0 == sn) + (n1 == sn) + (n2 == sn) + (n3 == sn));
           if (dE <= 0 || (uint64_t)r < a.Tp[dE - 1]) lat[y * L + x] = (int8_t)sn;
         }
+        y += dy;
+        m += dm;
+        if (m >= G4) {
+          m -= G4;
+          ++y;
+        }
       }
       __syncthreads();  // the other colour reads these sites
     }
   }
 
+  if (!active) return;  // no barrier follows
   // energy and M of the final state
   int e = 0, z = 0;
-  for (int i = lane; i < N; i += 64) {
-    const int y = i / L, x = i - y * L;
-    const int sv = lat[i];
-    e -= (sv == lat[y * L + ((x == L - 1) ? 0 : x + 1)]);
-    e -= (sv == lat[((y == L - 1) ? 0 : y + 1) * L + x]);
-    z += (sv == 0);
+  {
+    const int ey = 64 / L, ex = 64 - ey * L;  // site i advances by 64
+    int y = lane / L, x = lane - (lane / L) * L;
+    for (int i = lane; i < N; i += 64) {
+      const int sv = lat[i];
+      e -= (sv == lat[y * L + ((x == L - 1) ? 0 : x + 1)]);
+      e -= (sv == lat[((y == L - 1) ? 0 : y + 1) * L + x]);
+      z += (sv == 0);
+      y += ey;
+      x += ex;
+      if (x >= L) {
+        x -= L;
+        ++y;
+      }
+    }
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
@@ -123,9 +148,12 @@ __global__ __launch_bounds__(64) void k_potts(const LatticeArgs a) {
 
 hipError_t launch_potts(const LatticeArgs& a, hipStream_t st) {
   if (a.R <= 0) return hipSuccess;
-  if (a.R > 0x7FFFFFFF) return hipErrorInvalidValue;
-  const size_t lds = (size_t)a.L * a.L;
-  hipLaunchKernelGGL(k_potts, dim3((unsigned)a.R), dim3(64), lds, st, a);
+  const int64_t N = (int64_t)a.L * a.L;
+  const int wpb = N <= 4096 ? 4 : N <= 8192 ? 2 : 1;  // <= 16 KB of LDS
+  const int64_t blocks = (a.R + wpb - 1) / wpb;
+  if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_potts, dim3((unsigned)blocks), dim3(64 * wpb),
+                     (size_t)(wpb * N), st, a);
   return hipGetLastError();
 }
 
