@@ -149,7 +149,7 @@ def energy(spins, J=None):
     return E.value, M.value
 
 
-NEAREST, POISSON = 0, 1
+NEAREST, POISSON, SYSTEMATIC = 0, 1, 2
 
 
 def poisson_draw(rho, r):

@@ -287,7 +287,7 @@ int orc_counts(int N, const int32_t* E, int64_t R, int64_t R_t, double dbeta,
                uint64_t seed, uint32_t pop, int step_next, int law,
                uint32_t* n_out, int64_t* R_new, double* lnQ_out) {
   if (N < 16 || !E || R < 1 || R_t < 1 || !n_out || !isfinite(dbeta) ||
-      (law != ORC_NEAREST && law != ORC_POISSON))
+      (law != ORC_NEAREST && law != ORC_POISSON && law != ORC_SYSTEMATIC))
     return ORC_EINVAL;
   for (int64_t j = 0; j < R; ++j)
     if (E[j] < -2 * N || E[j] > 2 * N) return ORC_EINVAL;
@@ -337,9 +337,30 @@ int orc_counts(int N, const int32_t* E, int64_t R, int64_t R_t, double dbeta,
     T[e + 2 * N] = (uint64_t)floor(ldexp(rho - fl, 32));
   }
   /* (e) copy counts: floor plus a Bernoulli draw on the fraction, or a
-     Poisson draw with mean rho; one 32-bit word per slot either way */
+     Poisson draw with mean rho; one 32-bit word per slot either way.
+     Systematic resampling instead lays the means end to end in 32.32 fixed
+     point, P_j = floor(rho) 2^32 + T, and places one comb of unit-spaced
+     teeth offset by a single word U (RESAMPLE group 1, slot 0, word 0 at
+     the new step): replica j gets the teeth in its interval,
+     n_j = floor((C_j + U) / 2^32) - floor((C_{j-1} + U) / 2^32),
+     C_j = P_0 + ... + P_j. */
   int64_t total = 0;
-  for (int64_t j = 0; j < R; ++j) {
+  if (law == ORC_SYSTEMATIC) {
+    uint64_t U = draw_word(seed, DOMAIN_RESAMPLE, 1, (uint32_t)step_next, 0,
+                           0, pop, 0);
+    uint64_t C = 0;
+    for (int64_t j = 0; j < R; ++j) {
+      int idx = E[j] + 2 * N;
+      uint64_t P = ((uint64_t)f[idx] << 32) + T[idx];
+      uint32_t nj = (ORC_MUTANT == 11)
+                        ? (uint32_t)(((C + U) >> 32) - ((C - (j ? P : 0) + U) >> 32))
+                        : (uint32_t)(((C + P + U) >> 32) - ((C + U) >> 32));
+      C += P;
+      n_out[j] = nj;
+      total += nj;
+    }
+  }
+  for (int64_t j = 0; j < R && law != ORC_SYSTEMATIC; ++j) {
     int idx = E[j] + 2 * N;
     uint32_t r = draw_word(seed, DOMAIN_RESAMPLE, 0, (uint32_t)step_next, 0,
                            (uint32_t)j, pop, 0);
@@ -687,7 +708,9 @@ int orc_histogram(const orc_pa* p, uint32_t* out) {
 }
 
 int orc_set_resampling(orc_pa* p, int law) {
-  if (!p || (law != ORC_NEAREST && law != ORC_POISSON)) return ORC_EINVAL;
+  if (!p || (law != ORC_NEAREST && law != ORC_POISSON &&
+             law != ORC_SYSTEMATIC))
+    return ORC_EINVAL;
   p->law = law;
   return ORC_OK;
 }

@@ -97,9 +97,12 @@ int orc_histogram(const orc_pa* p, uint32_t* out);
 void orc_set_visit_shuffle(orc_pa* p, uint64_t shuffle_seed);
 
 /* Resampling laws: nearest integer (floor of the mean plus a Bernoulli draw
-   on its fraction; the default) and Poisson (the law the paper names). */
+   on its fraction; the default), Poisson (the law the paper names) and
+   systematic (one comb of unit-spaced points over the means laid end to
+   end, from the review the paper cites for variants of this step). */
 #define ORC_NEAREST 0
 #define ORC_POISSON 1
+#define ORC_SYSTEMATIC 2
 int orc_set_resampling(orc_pa* p, int law);
 /* The Poisson copy count for mean rho from the 32-bit word r (inversion of
    the cumulative distribution; exposed for its pins). */

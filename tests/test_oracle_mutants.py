@@ -35,6 +35,8 @@ CASES = {
         ["test_oracle_heating.py::test_heating_lnZ_L4_matches_enumeration"]),
     10: ("sign of the Potts energy change flipped",
          ["test_oracle_potts.py::test_metropolis_samples_boltzmann_q3_L4"]),
+    11: ("systematic comb read over the wrong interval",
+         ["test_oracle_systematic.py::test_counts_are_floor_or_ceiling_and_size_is_exact"]),
 }
 
 

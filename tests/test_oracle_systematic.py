@@ -1,0 +1,65 @@
+"""Pins of the oracle's systematic resampling (one comb of unit-spaced points
+over the mean copy numbers laid end to end, a variant of the resampling step
+in the review the paper cites): every count is the floor or the ceiling of
+its mean, the population size is the target up to one, and the counts are
+unbiased over the comb offset."""
+import numpy as np
+import pytest
+
+import oracle
+
+
+def _energies(seed, R, L=16):
+    rng = np.random.default_rng(seed)
+    N = L * L
+    return N, (rng.integers(-N // 2, N // 2, R) * 4).astype(np.int32)
+
+
+def _rho(E, R_t, dbeta):
+    x = -dbeta * E.astype(np.longdouble)
+    ex = np.exp(x - x.max())
+    return (R_t * ex / ex.sum()).astype(np.float64)
+
+
+@pytest.mark.parametrize("dbeta,R_t", [(0.0, 3000), (0.01, 3000),
+                                       (0.05, 2000), (0.2, 5000),
+                                       (-0.03, 3000)])
+def test_counts_are_floor_or_ceiling_and_size_is_exact(dbeta, R_t):
+    N, E = _energies(1, 3000)
+    n, Rn, lnQ = oracle.counts(N, E, R_t, dbeta, 9, 3, 4,
+                               law=oracle.SYSTEMATIC)
+    rho = _rho(E, R_t, dbeta)
+    fl = np.floor(rho)
+    near = np.abs(rho - np.round(rho)) < 1e-9
+    ok = (n == fl) | (n == fl + 1)
+    assert np.all(ok | near)
+    assert Rn == n.sum() and R_t - 1 <= Rn <= R_t
+    # the law does not enter ln Q
+    assert lnQ == oracle.counts(N, E, R_t, dbeta, 9, 3, 4)[2]
+
+
+def test_counts_are_unbiased_over_the_comb_offset():
+    N, E = _energies(2, 400)
+    R_t, dbeta = 400, 0.04
+    rho = _rho(E, R_t, dbeta)
+    acc = np.zeros(len(E))
+    K = 400
+    for step in range(1, K + 1):          # a fresh offset U at every step
+        acc += oracle.counts(N, E, R_t, dbeta, 5, 1, step,
+                             law=oracle.SYSTEMATIC)[0]
+    mean = acc / K
+    frac = rho - np.floor(rho)
+    sd = np.sqrt(frac * (1 - frac) / K) + 1e-12
+    z = (mean - rho) / sd
+    assert np.all(np.abs(z[frac > 0.02]) < 6)
+    assert abs(z[frac > 0.02].mean()) < 6 / np.sqrt((frac > 0.02).sum())
+
+
+def test_systematic_population_runs():
+    """A full anneal under the systematic law keeps R at the target (or one
+    below) at every step."""
+    p = oracle.OraclePA(8, 700, seed=3, law=oracle.SYSTEMATIC)
+    for i in range(1, 21):
+        Rn = p.resample(0.05 * i)
+        assert 699 <= Rn <= 700
+        p.sweep(2)
