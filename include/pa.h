@@ -54,7 +54,7 @@ enum {
 
 enum { PA_FERRO = 0, PA_PMJ = 1, PA_POTTS = 2 };  /* model     */
 enum { PA_INT8 = 0, PA_BITS = 1 };     /* device spin layout   */
-enum { PA_NEAREST = 0, PA_POISSON = 1 }; /* resampling law      */
+enum { PA_NEAREST = 0, PA_POISSON = 1, PA_SYSTEMATIC = 2 }; /* law  */
 
 typedef struct {
   int32_t L;          /* lattice side, even, 4 <= L <= 128 (checkerboard on
@@ -88,8 +88,16 @@ typedef struct {
                          double precision in increasing k): the count is
                          the number of k with floor(C(k) 2^32) <= r, the
                          list of k ending after C(k) >= 1 - 2^-32 or before
-                         ceil(rho + 64 sqrt(rho) + 64).  Single populations
-                         only: pa_batch_init rejects PA_POISSON.           */
+                         ceil(rho + 64 sqrt(rho) + 64); or PA_SYSTEMATIC,
+                         the variant of the review Sec. 2 cites: the means
+                         as P_j = floor(rho) 2^32 + floor(frac(rho) 2^32)
+                         laid end to end (C_j = P_0 + .. + P_j) and one
+                         comb offset U (RESAMPLE group 1, slot 0, word 0 at
+                         the new step), n_j = floor((C_j + U) / 2^32) -
+                         floor((C_{j-1} + U) / 2^32): every count is the
+                         floor or ceiling of its mean and the size is
+                         within one of the target.  Single populations
+                         only: pa_batch_init takes PA_NEAREST only.        */
   int32_t q;          /* PA_POTTS: number of states, 2..16; else ignored   */
 } pa_config;
 

@@ -54,6 +54,8 @@ struct pa_ctx {
   uint32_t* parent = nullptr;
   uint32_t* tile_sum = nullptr;
   uint32_t* tile_off = nullptr;
+  uint64_t* tile64 = nullptr;           // systematic law: tile sums of the
+  uint64_t* off64 = nullptr;            // fixed-point means and their scan
   // Read-back block, one device->host copy per histogram: the histogram
   // (nbins words, padded to an even count nb2), then scal = [0] sum|M|,
   // [1] sum M^2, [2] unused, [3] energies outside the histogram, all
@@ -295,8 +297,8 @@ void free_all(pa_ctx* c) {
     if (c->E[b]) (void)hipFree(c->E[b]);
     if (c->M[b]) (void)hipFree(c->M[b]);
   }
-  void* dev[] = {c->n, c->parent, c->tile_sum, c->tile_off, c->rb, c->tab,
-                 c->jbits};
+  void* dev[] = {c->n, c->parent, c->tile_sum, c->tile_off, c->tile64,
+                 c->off64, c->rb, c->tab, c->jbits};
   for (void* p : dev)
     if (p) (void)hipFree(p);
   if (c->h_rb) (void)hipHostFree(c->h_rb);
@@ -371,7 +373,8 @@ int pa_init(const pa_config* cfg, pa_ctx** out) {
   if (cfg->model == PA_POTTS &&
       (cfg->q < 2 || cfg->q > 16 || cfg->layout != PA_INT8))
     return PA_EINVAL;
-  if (cfg->resampling != PA_NEAREST && cfg->resampling != PA_POISSON)
+  if (cfg->resampling != PA_NEAREST && cfg->resampling != PA_POISSON &&
+      cfg->resampling != PA_SYSTEMATIC)
     return PA_EINVAL;
   if (cfg->R_target < 1 || cfg->R_target >= (1ll << 31)) return PA_EINVAL;
   int64_t cap = cfg->capacity;
@@ -430,6 +433,8 @@ int pa_init(const pa_config* cfg, pa_ctx** out) {
   ok = ok && dmalloc(&c->parent, (size_t)cap * 4);
   ok = ok && dmalloc(&c->tile_sum, (size_t)c->ntiles_cap * 4);
   ok = ok && dmalloc(&c->tile_off, (size_t)c->ntiles_cap * 4);
+  ok = ok && dmalloc(&c->tile64, (size_t)c->ntiles_cap * 8);
+  ok = ok && dmalloc(&c->off64, (size_t)c->ntiles_cap * 8);
   c->nb2 = (c->nbins + 1) & ~1;
   ok = ok && dmalloc(&c->rb, ((size_t)c->nb2 + 16) * 4);
   c->tab_words = (size_t)c->nbins * 2;
@@ -556,12 +561,23 @@ int pa_resample(pa_ctx* c, double beta_next, int64_t* R_new) {
                       hipMemcpyHostToDevice, c->stream));
     ca.f = c->tab;
     ca.T = c->tab + nl;
-    // exact bounds of the new size: every replica at level l gets f or f + 1
-    // copies, f + 1 only where its threshold is nonzero
-    for (int i = tr.lo; i <= tr.hi; ++i) {
-      const int64_t h = c->h_hist[i];
-      r_min += h * (int64_t)hf[i - tr.lo];
-      r_max += h * ((int64_t)hf[i - tr.lo] + (hT[i - tr.lo] ? 1 : 0));
+    if (c->law == PA_SYSTEMATIC) {
+      // the comb gives floor((C + U) / 2^32) copies in total, C the sum of
+      // the fixed-point means: one of two sizes
+      uint64_t C = 0;
+      for (int i = tr.lo; i <= tr.hi; ++i)
+        C += (uint64_t)c->h_hist[i] *
+             (((uint64_t)hf[i - tr.lo] << 32) + (uint64_t)hT[i - tr.lo]);
+      r_min = (int64_t)(C >> 32);
+      r_max = r_min + 1;
+    } else {
+      // every replica at level l gets f or f + 1 copies, f + 1 only where
+      // its threshold is nonzero
+      for (int i = tr.lo; i <= tr.hi; ++i) {
+        const int64_t h = c->h_hist[i];
+        r_min += h * (int64_t)hf[i - tr.lo];
+        r_max += h * ((int64_t)hf[i - tr.lo] + (hT[i - tr.lo] ? 1 : 0));
+      }
     }
   }
   const int lo = tr.lo, nl = tr.hi - tr.lo + 1;
@@ -588,7 +604,10 @@ int pa_resample(pa_ctx* c, double beta_next, int64_t* R_new) {
   // the caller did not ask for it: the next synchronisation brings it
   const bool deferred = !R_new && r_min >= 1 && r_max <= c->cap;
   hipEvent_t e0 = t_begin(c, PA_K_COUNTS);
-  CK(launch_counts(ca, c->stream));
+  if (c->law == PA_SYSTEMATIC)
+    CK(launch_sys_counts(ca, c->tile64, c->off64, c->stream));
+  else
+    CK(launch_counts(ca, c->stream));
   CK(launch_scan(c->tile_sum, c->tile_off, ntiles, c->scal + 4, c->stream));
   t_end(c, PA_K_COUNTS, e0, 8 * c->R + 8 * ntiles, 0);
   c->rb_zero = true;
@@ -915,7 +934,8 @@ int pa_load(const char* path, void* stream, pa_ctx** out) {
       (h.model == PA_POTTS && (h.q < 2 || h.q > 16)) ||
       h.step < 0 || h.step > 65535 || h.sweeps_at_step < 0 ||
       h.sweeps_at_step > 32767 || !std::isfinite(h.beta) || !(h.beta >= 0.0) ||
-      (h.resampling != PA_NEAREST && h.resampling != PA_POISSON))
+      (h.resampling != PA_NEAREST && h.resampling != PA_POISSON &&
+       h.resampling != PA_SYSTEMATIC))
     return PA_EIO;
   const int64_t N = (int64_t)h.L * h.L;
   std::vector<int8_t> J;

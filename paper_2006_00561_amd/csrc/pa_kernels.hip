@@ -140,6 +140,98 @@ __global__ __launch_bounds__(256) void k_counts(CountsArgs a) {
   if (threadIdx.x == 0) a.tile_sum[blockIdx.x] = total;
 }
 
+// ------------------------------------------------- systematic resampling
+// The mean copy numbers in 32.32 fixed point, P_j = f 2^32 + T from the
+// nearest-integer tables, laid end to end (C_j = P_0 + ... + P_j, exact
+// integer sums); one comb of unit-spaced points offset by the word U gives
+// n_j = floor((C_j + U) / 2^32) - floor((C_{j-1} + U) / 2^32).
+
+__device__ __forceinline__ uint64_t sys_mean(const CountsArgs& a, int64_t j) {
+  const int l = ((a.E[j] + a.twoN) >> a.shift) - a.lvl0;
+  if (l < 0 || l >= a.nlvl) return 0ull;
+  return ((uint64_t)a.f[l] << 32) + (uint64_t)a.T[l];
+}
+
+__device__ __forceinline__ uint64_t block_excl_scan64(uint64_t v,
+                                                      uint64_t* lds,
+                                                      uint64_t* total) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint64_t incl = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint64_t o = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += o;
+  }
+  if (lane == 63) lds[wid] = incl;
+  __syncthreads();
+  uint64_t wbase = 0ull, tot = 0ull;
+  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+    const uint64_t x = lds[i];
+    if (i < wid) wbase += x;
+    tot += x;
+  }
+  *total = tot;
+  return wbase + incl - v;
+}
+
+// Per 256-replica tile: the sum of P_j (and the read-back clear of k_counts).
+__global__ __launch_bounds__(256) void k_sys_tiles(CountsArgs a,
+                                                   uint64_t* tile64) {
+  __shared__ uint64_t lds[4];
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t i = j; i < a.nclear; i += (int64_t)gridDim.x * blockDim.x)
+    a.clear[i] = 0u;
+  uint64_t tot;
+  (void)block_excl_scan64(j < a.R ? sys_mean(a, j) : 0ull, lds, &tot);
+  if (threadIdx.x == 0) tile64[blockIdx.x] = tot;
+}
+
+// Single workgroup: exclusive scan of the tile sums of P (64-bit).
+__global__ __launch_bounds__(1024) void k_scan64(const uint64_t* tile64,
+                                                 uint64_t* off64,
+                                                 int64_t ntiles) {
+  __shared__ uint64_t part[1024];
+  const int tid = threadIdx.x;
+  const int64_t per = (ntiles + 1023) / 1024;
+  const int64_t b = tid * per;
+  const int64_t e = (b + per < ntiles) ? b + per : ntiles;
+  uint64_t s = 0ull;
+  for (int64_t i = b; i < e; ++i) s += tile64[i];
+  part[tid] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const uint64_t v = (tid >= off) ? part[tid - off] : 0ull;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  uint64_t run = part[tid] - s;
+  for (int64_t i = b; i < e; ++i) {
+    off64[i] = run;
+    run += tile64[i];
+  }
+}
+
+// Copy counts from the comb, and the per-tile sums of the counts.
+__global__ __launch_bounds__(256) void k_sys_counts(CountsArgs a,
+                                                    const uint64_t* off64) {
+  __shared__ uint64_t l64[4];
+  __shared__ uint32_t l32[8];
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t P = j < a.R ? sys_mean(a, j) : 0ull;
+  uint64_t tot;
+  const uint64_t C = off64[blockIdx.x] + block_excl_scan64(P, l64, &tot);
+  // the comb offset: word 0 of RESAMPLE group 1, slot 0, at the new step
+  const uint64_t U = philox10(make_uint4((kDomainResample << 28) | 1u,
+                                         a.step_next << 16, 0u, a.pop),
+                              a.k0, a.k1).x;
+  const uint32_t nj =
+      j < a.R ? (uint32_t)(((C + P + U) >> 32) - ((C + U) >> 32)) : 0u;
+  if (j < a.R) a.n[j] = nj;
+  uint32_t total;
+  (void)block_excl_scan(nj, l32, &total);
+  if (threadIdx.x == 0) a.tile_sum[blockIdx.x] = total;
+}
+
 // Single workgroup of 1024 threads: exclusive scan of ntiles tile sums.
 __global__ __launch_bounds__(1024) void k_scan(const uint32_t* tile_sum,
                                                uint32_t* tile_off,
@@ -258,6 +350,18 @@ hipError_t launch_hist(const HistArgs& a, hipStream_t st) {
 hipError_t launch_counts(const CountsArgs& a, hipStream_t st) {
   const int64_t blocks = (a.R + 255) / 256;
   hipLaunchKernelGGL(k_counts, dim3((unsigned)blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_sys_counts(const CountsArgs& a, uint64_t* tile64,
+                             uint64_t* off64, hipStream_t st) {
+  const int64_t blocks = (a.R + 255) / 256;
+  hipLaunchKernelGGL(k_sys_tiles, dim3((unsigned)blocks), dim3(256), 0, st, a,
+                     tile64);
+  hipLaunchKernelGGL(k_scan64, dim3(1), dim3(1024), 0, st, tile64, off64,
+                     blocks);
+  hipLaunchKernelGGL(k_sys_counts, dim3((unsigned)blocks), dim3(256), 0, st, a,
+                     off64);
   return hipGetLastError();
 }
 
