@@ -54,7 +54,8 @@ enum {
 
 enum { PA_FERRO = 0, PA_PMJ = 1, PA_POTTS = 2 };  /* model     */
 enum { PA_INT8 = 0, PA_BITS = 1 };     /* device spin layout   */
-enum { PA_NEAREST = 0, PA_POISSON = 1, PA_SYSTEMATIC = 2 }; /* law  */
+enum { PA_NEAREST = 0, PA_POISSON = 1, PA_SYSTEMATIC = 2,
+       PA_RESIDUAL = 3 };                /* resampling law      */
 
 typedef struct {
   int32_t L;          /* lattice side, even, 4 <= L <= 128 (checkerboard on
@@ -96,8 +97,11 @@ typedef struct {
                          the new step), n_j = floor((C_j + U) / 2^32) -
                          floor((C_{j-1} + U) / 2^32): every count is the
                          floor or ceiling of its mean and the size is
-                         within one of the target.  Single populations
-                         only: pa_batch_init takes PA_NEAREST only.        */
+                         within one of the target; or PA_RESIDUAL, floor(rho)
+                         copies for certain plus the same comb over the
+                         fractional parts alone (P_j = floor(frac(rho)
+                         2^32)).  Single populations only: pa_batch_init
+                         takes PA_NEAREST only.                            */
   int32_t q;          /* PA_POTTS: number of states, 2..16; else ignored   */
 } pa_config;
 

@@ -15,6 +15,7 @@ from .oracle import (  # noqa: F401
     NEAREST,
     OK,
     POISSON,
+    RESIDUAL,
     SYSTEMATIC,
     OraclePA,
     build,

@@ -149,7 +149,7 @@ def energy(spins, J=None):
     return E.value, M.value
 
 
-NEAREST, POISSON, SYSTEMATIC = 0, 1, 2
+NEAREST, POISSON, SYSTEMATIC, RESIDUAL = 0, 1, 2, 3
 
 
 def poisson_draw(rho, r):

@@ -287,7 +287,8 @@ int orc_counts(int N, const int32_t* E, int64_t R, int64_t R_t, double dbeta,
                uint64_t seed, uint32_t pop, int step_next, int law,
                uint32_t* n_out, int64_t* R_new, double* lnQ_out) {
   if (N < 16 || !E || R < 1 || R_t < 1 || !n_out || !isfinite(dbeta) ||
-      (law != ORC_NEAREST && law != ORC_POISSON && law != ORC_SYSTEMATIC))
+      (law != ORC_NEAREST && law != ORC_POISSON && law != ORC_SYSTEMATIC &&
+       law != ORC_RESIDUAL))
     return ORC_EINVAL;
   for (int64_t j = 0; j < R; ++j)
     if (E[j] < -2 * N || E[j] > 2 * N) return ORC_EINVAL;
@@ -344,23 +345,28 @@ int orc_counts(int N, const int32_t* E, int64_t R, int64_t R_t, double dbeta,
      the new step): replica j gets the teeth in its interval,
      n_j = floor((C_j + U) / 2^32) - floor((C_{j-1} + U) / 2^32),
      C_j = P_0 + ... + P_j. */
+  /* Residual resampling keeps floor(rho) copies and places the same comb
+     over the fractional parts alone (P_j = T). */
   int64_t total = 0;
-  if (law == ORC_SYSTEMATIC) {
+  if (law == ORC_SYSTEMATIC || law == ORC_RESIDUAL) {
     uint64_t U = draw_word(seed, DOMAIN_RESAMPLE, 1, (uint32_t)step_next, 0,
                            0, pop, 0);
     uint64_t C = 0;
     for (int64_t j = 0; j < R; ++j) {
       int idx = E[j] + 2 * N;
-      uint64_t P = ((uint64_t)f[idx] << 32) + T[idx];
+      uint64_t P = (law == ORC_RESIDUAL) ? T[idx]
+                                         : ((uint64_t)f[idx] << 32) + T[idx];
       uint32_t nj = (ORC_MUTANT == 11)
                         ? (uint32_t)(((C + U) >> 32) - ((C - (j ? P : 0) + U) >> 32))
                         : (uint32_t)(((C + P + U) >> 32) - ((C + U) >> 32));
       C += P;
+      if (law == ORC_RESIDUAL) nj += f[idx];
       n_out[j] = nj;
       total += nj;
     }
   }
-  for (int64_t j = 0; j < R && law != ORC_SYSTEMATIC; ++j) {
+  for (int64_t j = 0; j < R && law != ORC_SYSTEMATIC && law != ORC_RESIDUAL;
+       ++j) {
     int idx = E[j] + 2 * N;
     uint32_t r = draw_word(seed, DOMAIN_RESAMPLE, 0, (uint32_t)step_next, 0,
                            (uint32_t)j, pop, 0);
@@ -709,7 +715,7 @@ int orc_histogram(const orc_pa* p, uint32_t* out) {
 
 int orc_set_resampling(orc_pa* p, int law) {
   if (!p || (law != ORC_NEAREST && law != ORC_POISSON &&
-             law != ORC_SYSTEMATIC))
+             law != ORC_SYSTEMATIC && law != ORC_RESIDUAL))
     return ORC_EINVAL;
   p->law = law;
   return ORC_OK;

@@ -373,8 +373,7 @@ int pa_init(const pa_config* cfg, pa_ctx** out) {
   if (cfg->model == PA_POTTS &&
       (cfg->q < 2 || cfg->q > 16 || cfg->layout != PA_INT8))
     return PA_EINVAL;
-  if (cfg->resampling != PA_NEAREST && cfg->resampling != PA_POISSON &&
-      cfg->resampling != PA_SYSTEMATIC)
+  if (cfg->resampling < PA_NEAREST || cfg->resampling > PA_RESIDUAL)
     return PA_EINVAL;
   if (cfg->R_target < 1 || cfg->R_target >= (1ll << 31)) return PA_EINVAL;
   int64_t cap = cfg->capacity;
@@ -561,15 +560,22 @@ int pa_resample(pa_ctx* c, double beta_next, int64_t* R_new) {
                       hipMemcpyHostToDevice, c->stream));
     ca.f = c->tab;
     ca.T = c->tab + nl;
-    if (c->law == PA_SYSTEMATIC) {
+    if (c->law == PA_SYSTEMATIC || c->law == PA_RESIDUAL) {
       // the comb gives floor((C + U) / 2^32) copies in total, C the sum of
-      // the fixed-point means: one of two sizes
+      // the fixed-point means (of the fractions alone for the residual law,
+      // which adds the floors): one of two sizes
+      const bool res = c->law == PA_RESIDUAL;
       uint64_t C = 0;
-      for (int i = tr.lo; i <= tr.hi; ++i)
-        C += (uint64_t)c->h_hist[i] *
-             (((uint64_t)hf[i - tr.lo] << 32) + (uint64_t)hT[i - tr.lo]);
-      r_min = (int64_t)(C >> 32);
+      int64_t floors = 0;
+      for (int i = tr.lo; i <= tr.hi; ++i) {
+        const uint64_t h = c->h_hist[i];
+        C += h * ((res ? 0ull : ((uint64_t)hf[i - tr.lo] << 32)) +
+                  (uint64_t)hT[i - tr.lo]);
+        if (res) floors += (int64_t)h * hf[i - tr.lo];
+      }
+      r_min = floors + (int64_t)(C >> 32);
       r_max = r_min + 1;
+      ca.residual = res ? 1 : 0;
     } else {
       // every replica at level l gets f or f + 1 copies, f + 1 only where
       // its threshold is nonzero
@@ -604,7 +610,7 @@ int pa_resample(pa_ctx* c, double beta_next, int64_t* R_new) {
   // the caller did not ask for it: the next synchronisation brings it
   const bool deferred = !R_new && r_min >= 1 && r_max <= c->cap;
   hipEvent_t e0 = t_begin(c, PA_K_COUNTS);
-  if (c->law == PA_SYSTEMATIC)
+  if (c->law == PA_SYSTEMATIC || c->law == PA_RESIDUAL)
     CK(launch_sys_counts(ca, c->tile64, c->off64, c->stream));
   else
     CK(launch_counts(ca, c->stream));
@@ -934,8 +940,7 @@ int pa_load(const char* path, void* stream, pa_ctx** out) {
       (h.model == PA_POTTS && (h.q < 2 || h.q > 16)) ||
       h.step < 0 || h.step > 65535 || h.sweeps_at_step < 0 ||
       h.sweeps_at_step > 32767 || !std::isfinite(h.beta) || !(h.beta >= 0.0) ||
-      (h.resampling != PA_NEAREST && h.resampling != PA_POISSON &&
-       h.resampling != PA_SYSTEMATIC))
+      h.resampling < PA_NEAREST || h.resampling > PA_RESIDUAL)
     return PA_EIO;
   const int64_t N = (int64_t)h.L * h.L;
   std::vector<int8_t> J;

@@ -146,10 +146,11 @@ __global__ __launch_bounds__(256) void k_counts(CountsArgs a) {
 // integer sums); one comb of unit-spaced points offset by the word U gives
 // n_j = floor((C_j + U) / 2^32) - floor((C_{j-1} + U) / 2^32).
 
+// (the residual law combs the fractional parts alone: P_j = T)
 __device__ __forceinline__ uint64_t sys_mean(const CountsArgs& a, int64_t j) {
   const int l = ((a.E[j] + a.twoN) >> a.shift) - a.lvl0;
   if (l < 0 || l >= a.nlvl) return 0ull;
-  return ((uint64_t)a.f[l] << 32) + (uint64_t)a.T[l];
+  return (a.residual ? 0ull : ((uint64_t)a.f[l] << 32)) + (uint64_t)a.T[l];
 }
 
 __device__ __forceinline__ uint64_t block_excl_scan64(uint64_t v,
@@ -224,8 +225,12 @@ __global__ __launch_bounds__(256) void k_sys_counts(CountsArgs a,
   const uint64_t U = philox10(make_uint4((kDomainResample << 28) | 1u,
                                          a.step_next << 16, 0u, a.pop),
                               a.k0, a.k1).x;
-  const uint32_t nj =
+  uint32_t nj =
       j < a.R ? (uint32_t)(((C + P + U) >> 32) - ((C + U) >> 32)) : 0u;
+  if (a.residual && j < a.R) {  // the certain copies
+    const int l = ((a.E[j] + a.twoN) >> a.shift) - a.lvl0;
+    if (l >= 0 && l < a.nlvl) nj += a.f[l];
+  }
   if (j < a.R) a.n[j] = nj;
   uint32_t total;
   (void)block_excl_scan(nj, l32, &total);

@@ -545,17 +545,20 @@ def test_potts_heating_and_resume(pa, tmp_path):
     o.close()
 
 
-@pytest.mark.parametrize("L,R,layout,glass,q", [(16, 1000, 0, False, 0),
-                                                (12, 700, 1, True, 0),
-                                                (8, 500, 0, False, 5)])
-def test_systematic_resampling_matches_oracle(pa, L, R, layout, glass, q):
-    """Systematic resampling: copy counts, populations and ln Z equal the
-    oracle's at every step; the size stays within one of the target."""
+@pytest.mark.parametrize("L,R,layout,glass,q,law", [
+    (16, 1000, 0, False, 0, 2), (12, 700, 1, True, 0, 2),
+    (8, 500, 0, False, 5, 2), (16, 900, 0, False, 0, 3),
+    (12, 600, 1, True, 0, 3)])
+def test_systematic_resampling_matches_oracle(pa, L, R, layout, glass, q,
+                                              law):
+    """Systematic and residual resampling: copy counts, populations and ln Z
+    equal the oracle's at every step; the size stays within one of the
+    target."""
     J = W.pmj_couplings(L, 71) if glass else None
     _parity_run(pa, L, R, 30, 3, 1.2, seed=6, pop=3, J=J, layout=layout,
-                law=oracle.SYSTEMATIC, q=q)
+                law=law, q=q)
     g = pa.Population(L, R, seed=6, J=J, layout=layout, q=q,
-                      resampling=pa.PA_SYSTEMATIC)
+                      resampling=law)
     for b in W.linear_schedule(1.2, 10):
         assert R - 1 <= g.resample(b) <= R
         g.sweep(b, 1)

@@ -63,3 +63,36 @@ def test_systematic_population_runs():
         Rn = p.resample(0.05 * i)
         assert 699 <= Rn <= 700
         p.sweep(2)
+
+
+@pytest.mark.parametrize("dbeta", [0.0, 0.02, 0.2, -0.05])
+def test_residual_keeps_the_floors_and_combs_the_fractions(dbeta):
+    """Residual resampling: floor(rho) copies for certain, the comb only over
+    the fractional parts: counts are floor or ceiling, the total is the sum
+    of the floors plus the comb points over the sum of the fractions."""
+    N, E = _energies(4, 2500)
+    R_t = 2500
+    n, Rn, _ = oracle.counts(N, E, R_t, dbeta, 3, 2, 7, law=oracle.RESIDUAL)
+    rho = _rho(E, R_t, dbeta)
+    fl = np.floor(rho)
+    near = np.abs(rho - np.round(rho)) < 1e-9
+    assert np.all(((n == fl) | (n == fl + 1)) | near)
+    extra = Rn - fl[~near].sum() - np.round(rho[near]).sum()
+    frac_sum = (rho - fl)[~near].sum()
+    assert abs(extra - frac_sum) <= 1 + 1e-6
+    assert R_t - 1 <= Rn <= R_t
+
+
+def test_residual_counts_are_unbiased():
+    N, E = _energies(5, 300)
+    R_t, dbeta = 300, 0.05
+    rho = _rho(E, R_t, dbeta)
+    acc = np.zeros(len(E))
+    K = 300
+    for step in range(1, K + 1):
+        acc += oracle.counts(N, E, R_t, dbeta, 8, 1, step,
+                             law=oracle.RESIDUAL)[0]
+    frac = rho - np.floor(rho)
+    sd = np.sqrt(frac * (1 - frac) / K) + 1e-12
+    z = (acc / K - rho) / sd
+    assert np.all(np.abs(z[frac > 0.02]) < 6)
