@@ -563,3 +563,30 @@ def test_systematic_resampling_matches_oracle(pa, L, R, layout, glass, q,
         assert R - 1 <= g.resample(b) <= R
         g.sweep(b, 1)
     g.close()
+
+
+def test_empty_resampling_leaves_population_untouched(pa):
+    """Three replicas with a target of one: each keeps a copy with
+    probability about 1/3, so some seeds draw no copy at all.  Both sides
+    report PA_EEMPTY, and nothing changes."""
+    L = 4
+    rng = np.random.default_rng(0)
+    spins = np.where(rng.random((3, L, L)) < 0.5, 1, -1).astype(np.int8)
+    for seed in range(1, 60):
+        g = pa.Population(L, 1, seed=seed, capacity=8)
+        o = oracle.OraclePA(L, 1, seed=seed, capacity=8)
+        g.set_population(spins)
+        o.set_population(spins)
+        rc, Rn = g.resample_rc(0.1)
+        assert (rc, Rn) == o.resample_rc(0.1)
+        if rc == pa.PA_OK:
+            g.close()
+            continue
+        assert rc == pa.PA_EEMPTY and Rn == 0
+        assert g.state() == (3, 0.0, 0)
+        s, E, M = g.population()
+        assert np.array_equal(s, spins)
+        assert g.free_energy() == o.free_energy()
+        g.close()
+        return
+    raise AssertionError("no seed drew an empty population")
