@@ -55,7 +55,7 @@ enum {
 enum { PA_FERRO = 0, PA_PMJ = 1, PA_POTTS = 2 };  /* model     */
 enum { PA_INT8 = 0, PA_BITS = 1 };     /* device spin layout   */
 enum { PA_NEAREST = 0, PA_POISSON = 1, PA_SYSTEMATIC = 2,
-       PA_RESIDUAL = 3 };                /* resampling law      */
+       PA_RESIDUAL = 3, PA_MULTINOMIAL = 4 }; /* resampling law */
 
 typedef struct {
   int32_t L;          /* lattice side, even, 4 <= L <= 128 (checkerboard on
@@ -100,8 +100,12 @@ typedef struct {
                          within one of the target; or PA_RESIDUAL, floor(rho)
                          copies for certain plus the same comb over the
                          fractional parts alone (P_j = floor(frac(rho)
-                         2^32)).  Single populations only: pa_batch_init
-                         takes PA_NEAREST only.                            */
+                         2^32)); or PA_MULTINOMIAL, R_target independent
+                         draws: draw i (RESAMPLE group 2, slot i, word 0 u)
+                         lands at floor(u C / 2^32), C the total of the
+                         P_j, in the replica whose [C_{j-1}, C_j) holds it.
+                         Single populations only: pa_batch_init takes
+                         PA_NEAREST only.                                  */
   int32_t q;          /* PA_POTTS: number of states, 2..16; else ignored   */
 } pa_config;
 

@@ -13,6 +13,7 @@ from .oracle import (  # noqa: F401
     EINVAL,
     ENOMEM,
     NEAREST,
+    MULTINOMIAL,
     OK,
     POISSON,
     RESIDUAL,

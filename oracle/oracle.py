@@ -149,7 +149,7 @@ def energy(spins, J=None):
     return E.value, M.value
 
 
-NEAREST, POISSON, SYSTEMATIC, RESIDUAL = 0, 1, 2, 3
+NEAREST, POISSON, SYSTEMATIC, RESIDUAL, MULTINOMIAL = 0, 1, 2, 3, 4
 
 
 def poisson_draw(rho, r):

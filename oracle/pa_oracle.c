@@ -287,8 +287,7 @@ int orc_counts(int N, const int32_t* E, int64_t R, int64_t R_t, double dbeta,
                uint64_t seed, uint32_t pop, int step_next, int law,
                uint32_t* n_out, int64_t* R_new, double* lnQ_out) {
   if (N < 16 || !E || R < 1 || R_t < 1 || !n_out || !isfinite(dbeta) ||
-      (law != ORC_NEAREST && law != ORC_POISSON && law != ORC_SYSTEMATIC &&
-       law != ORC_RESIDUAL))
+      law < ORC_NEAREST || law > ORC_MULTINOMIAL)
     return ORC_EINVAL;
   for (int64_t j = 0; j < R; ++j)
     if (E[j] < -2 * N || E[j] > 2 * N) return ORC_EINVAL;
@@ -365,7 +364,42 @@ int orc_counts(int N, const int32_t* E, int64_t R, int64_t R_t, double dbeta,
       total += nj;
     }
   }
-  for (int64_t j = 0; j < R && law != ORC_SYSTEMATIC && law != ORC_RESIDUAL;
+  /* Multinomial resampling: R_target independent draws; draw i (its word
+     u_i: RESAMPLE group 2, slot i, word 0 at the new step) lands at
+     x_i = floor(u_i C / 2^32) on the same fixed-point axis (C the total of
+     the P_j = floor(rho) 2^32 + T) and counts for the replica whose interval
+     [C_{j-1}, C_j) holds it. */
+  if (law == ORC_MULTINOMIAL) {
+    uint64_t* cum = (uint64_t*)malloc((size_t)R * sizeof(uint64_t));
+    if (!cum) {
+      free(h); free(w); free(rh); free(f); free(T);
+      return ORC_ENOMEM;
+    }
+    uint64_t C = 0;
+    for (int64_t j = 0; j < R; ++j) {
+      int idx = E[j] + 2 * N;
+      C += ((uint64_t)f[idx] << 32) + T[idx];
+      cum[j] = C;  /* C_j, the end of replica j's interval */
+      n_out[j] = 0;
+    }
+    for (int64_t i = 0; i < ((ORC_MUTANT == 12) ? R : R_t); ++i) {
+      uint64_t u = draw_word(seed, DOMAIN_RESAMPLE, 2, (uint32_t)step_next, 0,
+                             (uint32_t)i, pop, 0);
+      uint64_t x = (uint64_t)(((unsigned __int128)u * C) >> 32);
+      /* the first j with x < C_j */
+      int64_t lo = 0, hi = R - 1;
+      while (lo < hi) {
+        int64_t mid = (lo + hi) / 2;
+        if (x < cum[mid]) hi = mid;
+        else lo = mid + 1;
+      }
+      n_out[lo] += 1;
+    }
+    free(cum);
+    total = R_t;
+  }
+  for (int64_t j = 0; j < R && law != ORC_SYSTEMATIC && law != ORC_RESIDUAL &&
+                      law != ORC_MULTINOMIAL;
        ++j) {
     int idx = E[j] + 2 * N;
     uint32_t r = draw_word(seed, DOMAIN_RESAMPLE, 0, (uint32_t)step_next, 0,
@@ -714,9 +748,7 @@ int orc_histogram(const orc_pa* p, uint32_t* out) {
 }
 
 int orc_set_resampling(orc_pa* p, int law) {
-  if (!p || (law != ORC_NEAREST && law != ORC_POISSON &&
-             law != ORC_SYSTEMATIC && law != ORC_RESIDUAL))
-    return ORC_EINVAL;
+  if (!p || law < ORC_NEAREST || law > ORC_MULTINOMIAL) return ORC_EINVAL;
   p->law = law;
   return ORC_OK;
 }

@@ -19,7 +19,7 @@ SO_PATH = os.path.join(HERE, "libpa.so")
  PA_EIO) = (0, -1, -2, -3, -4, -5, -6, -7)
 PA_FERRO, PA_PMJ, PA_POTTS = 0, 1, 2
 PA_INT8, PA_BITS = 0, 1
-PA_NEAREST, PA_POISSON, PA_SYSTEMATIC, PA_RESIDUAL = 0, 1, 2, 3
+PA_NEAREST, PA_POISSON, PA_SYSTEMATIC, PA_RESIDUAL, PA_MULTINOMIAL = range(5)
 KERNEL_CLASSES = ("init", "sweep", "hist", "counts", "scatter", "gather")
 PA_TIMING_ALL = -1
 

@@ -56,6 +56,7 @@ struct pa_ctx {
   uint32_t* tile_off = nullptr;
   uint64_t* tile64 = nullptr;           // systematic law: tile sums of the
   uint64_t* off64 = nullptr;            // fixed-point means and their scan
+  uint64_t* cum = nullptr;              // multinomial law: interval ends
   // Read-back block, one device->host copy per histogram: the histogram
   // (nbins words, padded to an even count nb2), then scal = [0] sum|M|,
   // [1] sum M^2, [2] unused, [3] energies outside the histogram, all
@@ -298,7 +299,7 @@ void free_all(pa_ctx* c) {
     if (c->M[b]) (void)hipFree(c->M[b]);
   }
   void* dev[] = {c->n, c->parent, c->tile_sum, c->tile_off, c->tile64,
-                 c->off64, c->rb, c->tab, c->jbits};
+                 c->off64, c->cum, c->rb, c->tab, c->jbits};
   for (void* p : dev)
     if (p) (void)hipFree(p);
   if (c->h_rb) (void)hipHostFree(c->h_rb);
@@ -373,7 +374,7 @@ int pa_init(const pa_config* cfg, pa_ctx** out) {
   if (cfg->model == PA_POTTS &&
       (cfg->q < 2 || cfg->q > 16 || cfg->layout != PA_INT8))
     return PA_EINVAL;
-  if (cfg->resampling < PA_NEAREST || cfg->resampling > PA_RESIDUAL)
+  if (cfg->resampling < PA_NEAREST || cfg->resampling > PA_MULTINOMIAL)
     return PA_EINVAL;
   if (cfg->R_target < 1 || cfg->R_target >= (1ll << 31)) return PA_EINVAL;
   int64_t cap = cfg->capacity;
@@ -434,6 +435,8 @@ int pa_init(const pa_config* cfg, pa_ctx** out) {
   ok = ok && dmalloc(&c->tile_off, (size_t)c->ntiles_cap * 4);
   ok = ok && dmalloc(&c->tile64, (size_t)c->ntiles_cap * 8);
   ok = ok && dmalloc(&c->off64, (size_t)c->ntiles_cap * 8);
+  if (cfg->resampling == PA_MULTINOMIAL)
+    ok = ok && dmalloc(&c->cum, (size_t)cap * 8);
   c->nb2 = (c->nbins + 1) & ~1;
   ok = ok && dmalloc(&c->rb, ((size_t)c->nb2 + 16) * 4);
   c->tab_words = (size_t)c->nbins * 2;
@@ -560,7 +563,9 @@ int pa_resample(pa_ctx* c, double beta_next, int64_t* R_new) {
                       hipMemcpyHostToDevice, c->stream));
     ca.f = c->tab;
     ca.T = c->tab + nl;
-    if (c->law == PA_SYSTEMATIC || c->law == PA_RESIDUAL) {
+    if (c->law == PA_MULTINOMIAL) {
+      r_min = r_max = c->R_t;  // exactly R_target draws
+    } else if (c->law == PA_SYSTEMATIC || c->law == PA_RESIDUAL) {
       // the comb gives floor((C + U) / 2^32) copies in total, C the sum of
       // the fixed-point means (of the fractions alone for the residual law,
       // which adds the floors): one of two sizes
@@ -610,7 +615,10 @@ int pa_resample(pa_ctx* c, double beta_next, int64_t* R_new) {
   // the caller did not ask for it: the next synchronisation brings it
   const bool deferred = !R_new && r_min >= 1 && r_max <= c->cap;
   hipEvent_t e0 = t_begin(c, PA_K_COUNTS);
-  if (c->law == PA_SYSTEMATIC || c->law == PA_RESIDUAL)
+  if (c->law == PA_MULTINOMIAL)
+    CK(launch_multi_counts(ca, c->R_t, c->tile64, c->off64, c->cum,
+                           c->stream));
+  else if (c->law == PA_SYSTEMATIC || c->law == PA_RESIDUAL)
     CK(launch_sys_counts(ca, c->tile64, c->off64, c->stream));
   else
     CK(launch_counts(ca, c->stream));
@@ -940,7 +948,7 @@ int pa_load(const char* path, void* stream, pa_ctx** out) {
       (h.model == PA_POTTS && (h.q < 2 || h.q > 16)) ||
       h.step < 0 || h.step > 65535 || h.sweeps_at_step < 0 ||
       h.sweeps_at_step > 32767 || !std::isfinite(h.beta) || !(h.beta >= 0.0) ||
-      h.resampling < PA_NEAREST || h.resampling > PA_RESIDUAL)
+      h.resampling < PA_NEAREST || h.resampling > PA_MULTINOMIAL)
     return PA_EIO;
   const int64_t N = (int64_t)h.L * h.L;
   std::vector<int8_t> J;

@@ -171,6 +171,9 @@ hipError_t launch_hist(const HistArgs& a, hipStream_t st);
 hipError_t launch_potts(const LatticeArgs& a, hipStream_t st);
 hipError_t launch_sys_counts(const CountsArgs& a, uint64_t* tile64,
                              uint64_t* off64, hipStream_t st);
+hipError_t launch_multi_counts(const CountsArgs& a, int64_t draws,
+                               uint64_t* tile64, uint64_t* off64,
+                               uint64_t* cum, hipStream_t st);
 hipError_t launch_counts(const CountsArgs& a, hipStream_t st);
 hipError_t launch_scan(const uint32_t* tile_sum, uint32_t* tile_off,
                        int64_t ntiles, unsigned long long* total,

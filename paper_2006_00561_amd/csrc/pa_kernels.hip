@@ -237,6 +237,57 @@ __global__ __launch_bounds__(256) void k_sys_counts(CountsArgs a,
   if (threadIdx.x == 0) a.tile_sum[blockIdx.x] = total;
 }
 
+// ------------------------------------------------ multinomial resampling
+// R_target independent draws on the same fixed-point axis: draw i (word 0 of
+// RESAMPLE group 2, slot i, at the new step) lands at x_i = floor(u_i C / 2^32)
+// and counts for the replica whose interval [C_{j-1}, C_j) holds it.
+
+// Interval ends C_j of every replica (and its count cleared).
+__global__ __launch_bounds__(256) void k_multi_cum(CountsArgs a,
+                                                   const uint64_t* off64,
+                                                   uint64_t* cum) {
+  __shared__ uint64_t l64[4];
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t P = j < a.R ? sys_mean(a, j) : 0ull;
+  uint64_t tot;
+  const uint64_t C = off64[blockIdx.x] + block_excl_scan64(P, l64, &tot);
+  if (j < a.R) {
+    cum[j] = C + P;
+    a.n[j] = 0u;
+  }
+}
+
+// One thread per draw: the first j with x < C_j, counted with an atomic
+// increment (the counts do not depend on the order of the increments).
+__global__ __launch_bounds__(256) void k_multi_draw(CountsArgs a,
+                                                    const uint64_t* cum,
+                                                    int64_t draws) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= draws) return;
+  const uint64_t total = cum[a.R - 1];
+  const uint64_t u = philox10(make_uint4((kDomainResample << 28) | 2u,
+                                         a.step_next << 16, (uint32_t)i, a.pop),
+                              a.k0, a.k1).x;
+  // floor(u total / 2^32) without a 96-bit product
+  const uint64_t x = u * (total >> 32) + ((u * (total & 0xFFFFFFFFull)) >> 32);
+  int64_t lo = 0, hi = a.R - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (x < cum[mid]) hi = mid;
+    else lo = mid + 1;
+  }
+  atomicAdd(&a.n[lo], 1u);
+}
+
+// Per-tile sums of the counts (for the scan and the parent scatter).
+__global__ __launch_bounds__(256) void k_count_tiles(CountsArgs a) {
+  __shared__ uint32_t lds[8];
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t total;
+  (void)block_excl_scan(j < a.R ? a.n[j] : 0u, lds, &total);
+  if (threadIdx.x == 0) a.tile_sum[blockIdx.x] = total;
+}
+
 // Single workgroup of 1024 threads: exclusive scan of ntiles tile sums.
 __global__ __launch_bounds__(1024) void k_scan(const uint32_t* tile_sum,
                                                uint32_t* tile_off,
@@ -367,6 +418,23 @@ hipError_t launch_sys_counts(const CountsArgs& a, uint64_t* tile64,
                      blocks);
   hipLaunchKernelGGL(k_sys_counts, dim3((unsigned)blocks), dim3(256), 0, st, a,
                      off64);
+  return hipGetLastError();
+}
+
+hipError_t launch_multi_counts(const CountsArgs& a, int64_t draws,
+                               uint64_t* tile64, uint64_t* off64,
+                               uint64_t* cum, hipStream_t st) {
+  const int64_t blocks = (a.R + 255) / 256;
+  hipLaunchKernelGGL(k_sys_tiles, dim3((unsigned)blocks), dim3(256), 0, st, a,
+                     tile64);
+  hipLaunchKernelGGL(k_scan64, dim3(1), dim3(1024), 0, st, tile64, off64,
+                     blocks);
+  hipLaunchKernelGGL(k_multi_cum, dim3((unsigned)blocks), dim3(256), 0, st, a,
+                     off64, cum);
+  hipLaunchKernelGGL(k_multi_draw, dim3((unsigned)((draws + 255) / 256)),
+                     dim3(256), 0, st, a, cum, draws);
+  hipLaunchKernelGGL(k_count_tiles, dim3((unsigned)blocks), dim3(256), 0, st,
+                     a);
   return hipGetLastError();
 }
 

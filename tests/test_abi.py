@@ -46,7 +46,7 @@ def test_strerror_and_validation_without_device():
     cfg.L, cfg.R_target, cfg.model = 8, 10, b.PA_PMJ   # +-J without couplings
     assert lib.pa_init(C.byref(cfg), C.byref(h)) == b.PA_EINVAL
     cfg = b.pa_config()
-    cfg.L, cfg.R_target, cfg.resampling = 8, 10, 4      # no such law
+    cfg.L, cfg.R_target, cfg.resampling = 8, 10, 5      # no such law
     assert lib.pa_init(C.byref(cfg), C.byref(h)) == b.PA_EINVAL
     # the batch takes the nearest-integer law only
     cfg = b.pa_config()

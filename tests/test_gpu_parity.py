@@ -548,12 +548,13 @@ def test_potts_heating_and_resume(pa, tmp_path):
 @pytest.mark.parametrize("L,R,layout,glass,q,law", [
     (16, 1000, 0, False, 0, 2), (12, 700, 1, True, 0, 2),
     (8, 500, 0, False, 5, 2), (16, 900, 0, False, 0, 3),
-    (12, 600, 1, True, 0, 3)])
+    (12, 600, 1, True, 0, 3), (16, 800, 0, False, 0, 4),
+    (10, 500, 1, True, 0, 4)])
 def test_systematic_resampling_matches_oracle(pa, L, R, layout, glass, q,
                                               law):
-    """Systematic and residual resampling: copy counts, populations and ln Z
-    equal the oracle's at every step; the size stays within one of the
-    target."""
+    """Systematic, residual and multinomial resampling: copy counts,
+    populations and ln Z equal the oracle's at every step; the size stays
+    within one of the target (exactly the target for multinomial)."""
     J = W.pmj_couplings(L, 71) if glass else None
     _parity_run(pa, L, R, 30, 3, 1.2, seed=6, pop=3, J=J, layout=layout,
                 law=law, q=q)

@@ -37,6 +37,8 @@ CASES = {
          ["test_oracle_potts.py::test_metropolis_samples_boltzmann_q3_L4"]),
     11: ("systematic comb read over the wrong interval",
          ["test_oracle_systematic.py::test_counts_are_floor_or_ceiling_and_size_is_exact"]),
+    12: ("multinomial draws counted from the current size, not the target",
+         ["test_oracle_systematic.py::test_multinomial_draws_follow_the_weights"]),
 }
 
 

@@ -96,3 +96,25 @@ def test_residual_counts_are_unbiased():
     sd = np.sqrt(frac * (1 - frac) / K) + 1e-12
     z = (acc / K - rho) / sd
     assert np.all(np.abs(z[frac > 0.02]) < 6)
+
+
+def test_multinomial_draws_follow_the_weights():
+    """Multinomial resampling: exactly R_target copies in total, each
+    replica's count binomial with the probability of its weight."""
+    N, E = _energies(6, 500)
+    R_t, dbeta = 20000, 0.004
+    n, Rn, lnQ = oracle.counts(N, E, R_t, dbeta, 4, 2, 9,
+                               law=oracle.MULTINOMIAL)
+    assert Rn == R_t == n.sum()
+    assert lnQ == oracle.counts(N, E, R_t, dbeta, 4, 2, 9)[2]
+    rho = _rho(E, R_t, dbeta)            # expected counts
+    p = rho / R_t
+    big = rho > 5
+    assert big.sum() > 300
+    z = ((n - rho) / np.sqrt(R_t * p * (1 - p)))[big]
+    assert abs(z.mean()) < 5 / np.sqrt(len(z)) and 0.85 < z.std() < 1.15
+    # a replica of zero weight is never drawn
+    E2 = E.copy()
+    E2[0] = 4 * N // 2                   # far above the rest
+    n2 = oracle.counts(N, E2, R_t, 3.0, 4, 2, 9, law=oracle.MULTINOMIAL)[0]
+    assert n2[0] == 0
