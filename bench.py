@@ -76,6 +76,29 @@ def measured_traffic(workload):
     return t.get("hbm_bytes_per_launch")
 
 
+def gather_copy(binding, cfg, stream, reps=5):
+    """The standalone gather-copy kernel at the workload's size: resamplings
+    whose population is read before the sweep, so the copies run as their
+    own HBM-bound pass (2 S per new slot plus E, M and the parent index)."""
+    layout = binding.PA_BITS if cfg["layout"] == "bits" else binding.PA_INT8
+    g = binding.Population(cfg["L"], cfg["R"], seed=cfg["seed"], layout=layout,
+                           stream=stream, q=cfg.get("q", 0))
+    sched = W.linear_schedule(cfg["beta_f"], cfg["K"])
+    g.resample(sched[0])
+    g.sweep(sched[0], 1)
+    g.set_timing(True, classes=("gather",))
+    for b in sched[1:reps + 1]:
+        g.resample(b)
+        g.energies()            # the read makes the copies now
+        g.sweep(b, 1)
+    t = g.timing()["gather"]
+    g.close()
+    gbps = t["bytes"] / (t["ms"] * 1e6) if t["ms"] else 0.0
+    return {"launches": t["launches"], "avg_us": 1e3 * t["ms"] / t["launches"],
+            "bytes_per_launch": t["bytes"] / t["launches"], "GBps": gbps,
+            "frac_hbm": gbps / HBM_PEAK_GBPS}
+
+
 def deferral_capacity(R):
     """Capacity at which a resampling never waits for its new size: the size
     is bounded by R_target + R_old, with R_old within R_target + 16 sqrt(R)
@@ -530,6 +553,7 @@ def main():
                          binding.KERNEL_CLASSES},
             "sweep_with_copy_GBps": copy_gbps,
             "sweep_with_copy_frac_hbm": copy_gbps / HBM_PEAK_GBPS,
+            "standalone_gather_copy": gather_copy(binding, cfg, stream),
         },
         "wall_time_to_beta_f_s": dt / args.steps,
         "lnZ_final": lnZs[-1],

@@ -219,9 +219,9 @@ int finish_gather(pa_ctx* c) {
   g.R_new = c->R;
   g.stride = c->stride;
   g.chunks = (int32_t)(c->stride / 16);
-  int lg = 0;
-  while ((1 << lg) < g.chunks && lg < 6) ++lg;
-  g.lpr_log2 = lg;
+  g.chunks_log2 = -1;
+  for (int lg = 0; lg < 31; ++lg)
+    if ((1 << lg) == g.chunks) g.chunks_log2 = lg;
   hipEvent_t e0 = t_begin(c, PA_K_GATHER);
   CK(launch_gather(g, c->stream));
   t_end(c, PA_K_GATHER, e0, 2 * c->R * c->stride + 20 * c->R, 0);

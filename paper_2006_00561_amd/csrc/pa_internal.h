@@ -81,8 +81,8 @@ struct GatherArgs {
   const uint32_t* parent;
   int64_t R_new;
   int64_t stride;   // bytes per replica, multiple of 16
-  int32_t chunks;   // stride / 16
-  int32_t lpr_log2; // log2 of the lanes that copy one row
+  int32_t chunks;      // stride / 16
+  int32_t chunks_log2; // log2(chunks) when it is a power of two, else -1
 };
 
 // ---- batched populations (pa_batch.hip)

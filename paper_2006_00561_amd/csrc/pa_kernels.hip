@@ -21,8 +21,9 @@
 //  k_scan      exclusive scan of the tile sums (single workgroup).
 //  k_scatter   per-tile scan of the counts -> parent index of every new slot.
 //  k_gather    copy of every parent's lattice, E and M into its new slots of
-//              the second buffer (16-byte chunks, one wave per row group),
-//              when no sweep follows the resampling.
+//              the second buffer (one wave per slot for replicas of 1 KB and
+//              more, else a flat array of 16-byte units with four in flight
+//              per thread), when no sweep follows the resampling.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -333,21 +334,63 @@ __global__ __launch_bounds__(256) void k_scatter(const uint32_t* n,
 
 // ---------------------------------------------------------------- gather
 
+// Replicas of at least 64 units (1 KB): one wave per new slot, each lane
+// copying every 64th 16-byte unit, one parent index per lane.
 __global__ __launch_bounds__(256) void k_gather(GatherArgs a) {
   const int lane = threadIdx.x & 63;
-  const int64_t wave =
-      ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int sub = lane >> a.lpr_log2;                 // row within the wave
-  const int c0 = lane & ((1 << a.lpr_log2) - 1);       // first chunk
-  const int64_t k = wave * (64 >> a.lpr_log2) + sub;  // new slot
+  const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   if (k >= a.R_new) return;
   const uint32_t p = a.parent[k];
   const uint4* src = reinterpret_cast<const uint4*>(a.src + (size_t)p * a.stride);
   uint4* dst = reinterpret_cast<uint4*>(a.dst + (size_t)k * a.stride);
-  for (int c = c0; c < a.chunks; c += (1 << a.lpr_log2)) dst[c] = src[c];
-  if (c0 == 0) {
+  for (int c = lane; c < a.chunks; c += 64) dst[c] = src[c];
+  if (lane == 0) {
     a.E_dst[k] = a.E_src[p];
     a.M_dst[k] = a.M_src[p];
+  }
+}
+
+// Smaller replicas: the copies as one flat array of 16-byte units (new slot
+// k, chunk c); a workgroup copies a contiguous tile of 1024 units,
+// consecutive threads take consecutive units, and every thread has four
+// units in flight (all loads before the stores).
+__global__ __launch_bounds__(256) void k_gather_flat(GatherArgs a) {
+  constexpr int U = 4;
+  const int64_t total = a.R_new * (int64_t)a.chunks;
+  // each workgroup copies one contiguous tile of U * 256 units
+  const int64_t stride = blockDim.x;
+  const int64_t first = (int64_t)blockIdx.x * (U * 256) + threadIdx.x;
+  uint4 v[U];
+  int64_t k[U];
+  int c[U];
+  uint32_t p[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t it = first + u * stride;
+    if (it >= total) {
+      k[u] = -1;
+      c[u] = 0;
+    } else if (a.chunks_log2 >= 0) {  // every benchmark layout
+      k[u] = it >> a.chunks_log2;
+      c[u] = (int)(it & ((1 << a.chunks_log2) - 1));
+    } else {
+      k[u] = it / a.chunks;
+      c[u] = (int)(it - k[u] * a.chunks);
+    }
+    p[u] = k[u] >= 0 ? a.parent[k[u]] : 0u;
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    if (k[u] >= 0)
+      v[u] = reinterpret_cast<const uint4*>(a.src + (size_t)p[u] * a.stride)[c[u]];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if (k[u] < 0) continue;
+    reinterpret_cast<uint4*>(a.dst + (size_t)k[u] * a.stride)[c[u]] = v[u];
+    if (c[u] == 0) {
+      a.E_dst[k[u]] = a.E_src[p[u]];
+      a.M_dst[k[u]] = a.M_src[p[u]];
+    }
   }
 }
 
@@ -456,11 +499,18 @@ hipError_t launch_scatter(const uint32_t* n, const uint32_t* tile_off,
 }
 
 hipError_t launch_gather(const GatherArgs& a, hipStream_t st) {
-  const int64_t rows_per_wave = 64 >> a.lpr_log2;
-  const int64_t waves = (a.R_new + rows_per_wave - 1) / rows_per_wave;
-  const int64_t blocks = (waves + 3) / 4;
-  if (blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gather, dim3((unsigned)blocks), dim3(256), 0, st, a);
+  if (a.R_new <= 0) return hipSuccess;
+  if (a.chunks >= 64) {
+    const int64_t blocks = (a.R_new + 3) / 4;  // four slots per workgroup
+    if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)blocks), dim3(256), 0, st, a);
+  } else {
+    const int64_t units = a.R_new * (int64_t)a.chunks;
+    const int64_t blocks = (units + 4 * 256 - 1) / (4 * 256);
+    if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gather_flat, dim3((unsigned)blocks), dim3(256), 0, st,
+                       a);
+  }
   return hipGetLastError();
 }
 
