@@ -386,6 +386,30 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, workload, command):
         fh.write("\n".join(lines) + "\n")
 
 
+def summarize_trace(trace_dir, name, command):
+    """profiles/kernels_<name>.md from a rocprofv3 --kernel-trace --stats
+    run: per-kernel calls and durations, with the command that made it."""
+    import csv
+    import glob
+    f = glob.glob(os.path.join(trace_dir, "*kernel_stats.csv"))
+    if not f:
+        raise SystemExit("no kernel_stats.csv in " + trace_dir)
+    stats = list(csv.DictReader(open(f[0])))
+    lines = ["# rocprofv3 kernel statistics, workload %s" % name, "",
+             "Commands:", "", "    cd /tmp && export TMPDIR=/tmp",
+             "    " + command, "",
+             "| kernel | calls | average ns | total ns | % |",
+             "|---|---|---|---|---|"]
+    for r in stats:
+        lines.append("| %s | %s | %.0f | %s | %s |" % (
+            r["Name"], r["Calls"], float(r["AverageNs"]),
+            r["TotalDurationNs"], r["Percentage"]))
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", "kernels_%s.md" % name),
+              "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -407,10 +431,16 @@ def main():
     ap.add_argument("--summarize-profiles", nargs=3,
                     metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/ summaries from rocprofv3 output")
+    ap.add_argument("--summarize-trace", nargs=3,
+                    metavar=("TRACE_DIR", "NAME", "COMMAND"),
+                    help="write profiles/kernels_NAME.md from a kernel trace")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy, the reference "
                          "for scaling FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace)
+        return
     if args.summarize_profiles:
         base = ("python3 <repo>/bench.py --workload %s --no-cpu-baseline "
                 "--no-batched --no-learned --no-accuracy" % args.workload)
