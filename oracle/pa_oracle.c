@@ -344,22 +344,18 @@ int orc_counts(int N, const int32_t* E, int64_t R, int64_t R_t, double dbeta,
      the new step): replica j gets the teeth in its interval,
      n_j = floor((C_j + U) / 2^32) - floor((C_{j-1} + U) / 2^32),
      C_j = P_0 + ... + P_j. */
-  /* Residual resampling keeps floor(rho) copies and places the same comb
-     over the fractional parts alone (P_j = T). */
   int64_t total = 0;
-  if (law == ORC_SYSTEMATIC || law == ORC_RESIDUAL) {
+  if (law == ORC_SYSTEMATIC) {
     uint64_t U = draw_word(seed, DOMAIN_RESAMPLE, 1, (uint32_t)step_next, 0,
                            0, pop, 0);
     uint64_t C = 0;
     for (int64_t j = 0; j < R; ++j) {
       int idx = E[j] + 2 * N;
-      uint64_t P = (law == ORC_RESIDUAL) ? T[idx]
-                                         : ((uint64_t)f[idx] << 32) + T[idx];
+      uint64_t P = ((uint64_t)f[idx] << 32) + T[idx];
       uint32_t nj = (ORC_MUTANT == 11)
                         ? (uint32_t)(((C + U) >> 32) - ((C - (j ? P : 0) + U) >> 32))
                         : (uint32_t)(((C + P + U) >> 32) - ((C + U) >> 32));
       C += P;
-      if (law == ORC_RESIDUAL) nj += f[idx];
       n_out[j] = nj;
       total += nj;
     }
@@ -368,21 +364,31 @@ int orc_counts(int N, const int32_t* E, int64_t R, int64_t R_t, double dbeta,
      u_i: RESAMPLE group 2, slot i, word 0 at the new step) lands at
      x_i = floor(u_i C / 2^32) on the same fixed-point axis (C the total of
      the P_j = floor(rho) 2^32 + T) and counts for the replica whose interval
-     [C_{j-1}, C_j) holds it. */
-  if (law == ORC_MULTINOMIAL) {
+     [C_{j-1}, C_j) holds it.
+     Residual resampling keeps floor(rho) copies of every replica for
+     certain and makes the remaining D = R_target - sum_j floor(rho_j) draws
+     the same way over the fractional parts alone (P_j = T; no draws when
+     every fraction is zero). */
+  if (law == ORC_MULTINOMIAL || law == ORC_RESIDUAL) {
     uint64_t* cum = (uint64_t*)malloc((size_t)R * sizeof(uint64_t));
     if (!cum) {
       free(h); free(w); free(rh); free(f); free(T);
       return ORC_ENOMEM;
     }
+    const int res = (law == ORC_RESIDUAL);
     uint64_t C = 0;
+    int64_t floors = 0;
     for (int64_t j = 0; j < R; ++j) {
       int idx = E[j] + 2 * N;
-      C += ((uint64_t)f[idx] << 32) + T[idx];
+      C += (res ? 0 : ((uint64_t)f[idx] << 32)) + T[idx];
       cum[j] = C;  /* C_j, the end of replica j's interval */
-      n_out[j] = 0;
+      n_out[j] = res ? f[idx] : 0;
+      floors += res ? (int64_t)f[idx] : 0;
     }
-    for (int64_t i = 0; i < ((ORC_MUTANT == 12) ? R : R_t); ++i) {
+    int64_t draws = res ? R_t - floors : R_t;
+    if (draws < 0 || C == 0) draws = 0;
+    if (ORC_MUTANT == 12) draws = R;
+    for (int64_t i = 0; i < draws; ++i) {
       uint64_t u = draw_word(seed, DOMAIN_RESAMPLE, 2, (uint32_t)step_next, 0,
                              (uint32_t)i, pop, 0);
       uint64_t x = (uint64_t)(((unsigned __int128)u * C) >> 32);
@@ -396,10 +402,10 @@ int orc_counts(int N, const int32_t* E, int64_t R, int64_t R_t, double dbeta,
       n_out[lo] += 1;
     }
     free(cum);
-    total = R_t;
+    total = floors + draws;
   }
-  for (int64_t j = 0; j < R && law != ORC_SYSTEMATIC && law != ORC_RESIDUAL &&
-                      law != ORC_MULTINOMIAL;
+  for (int64_t j = 0; j < R && law != ORC_SYSTEMATIC &&
+                      law != ORC_MULTINOMIAL && law != ORC_RESIDUAL;
        ++j) {
     int idx = E[j] + 2 * N;
     uint32_t r = draw_word(seed, DOMAIN_RESAMPLE, 0, (uint32_t)step_next, 0,

@@ -103,7 +103,7 @@ void orc_set_visit_shuffle(orc_pa* p, uint64_t shuffle_seed);
 #define ORC_NEAREST 0
 #define ORC_POISSON 1
 #define ORC_SYSTEMATIC 2
-#define ORC_RESIDUAL 3   /* floor(rho) copies, the comb over the fractions */
+#define ORC_RESIDUAL 3   /* floor(rho) copies, draws over the fractions */
 #define ORC_MULTINOMIAL 4 /* R_target independent draws of a parent */
 int orc_set_resampling(orc_pa* p, int law);
 /* The Poisson copy count for mean rho from the 32-bit word r (inversion of

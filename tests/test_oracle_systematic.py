@@ -1,8 +1,10 @@
-"""Pins of the oracle's systematic resampling (one comb of unit-spaced points
-over the mean copy numbers laid end to end, a variant of the resampling step
-in the review the paper cites): every count is the floor or the ceiling of
-its mean, the population size is the target up to one, and the counts are
-unbiased over the comb offset."""
+"""Pins of the oracle's systematic, residual and multinomial resampling
+(variants of the resampling step in the review the paper cites).
+Systematic: one comb of unit-spaced points over the mean copy numbers laid
+end to end; every count is the floor or the ceiling of its mean, the size is
+the target up to one, and the counts are unbiased over the comb offset.
+Residual: the floors for certain and multinomial draws over the fractions.
+Multinomial: R_target independent draws weighted by the means."""
 import numpy as np
 import pytest
 
@@ -66,36 +68,57 @@ def test_systematic_population_runs():
 
 
 @pytest.mark.parametrize("dbeta", [0.0, 0.02, 0.2, -0.05])
-def test_residual_keeps_the_floors_and_combs_the_fractions(dbeta):
-    """Residual resampling: floor(rho) copies for certain, the comb only over
-    the fractional parts: counts are floor or ceiling, the total is the sum
-    of the floors plus the comb points over the sum of the fractions."""
+def test_residual_keeps_the_floors_and_draws_over_the_fractions(dbeta):
+    """Residual resampling: floor(rho) copies for certain, then
+    R_target - sum floor(rho) multinomial draws weighted by the fractional
+    parts: no count is below its floor, the size is exactly the target, and
+    the extra copies follow the fractions."""
     N, E = _energies(4, 2500)
     R_t = 2500
     n, Rn, _ = oracle.counts(N, E, R_t, dbeta, 3, 2, 7, law=oracle.RESIDUAL)
     rho = _rho(E, R_t, dbeta)
     fl = np.floor(rho)
     near = np.abs(rho - np.round(rho)) < 1e-9
-    assert np.all(((n == fl) | (n == fl + 1)) | near)
-    extra = Rn - fl[~near].sum() - np.round(rho[near]).sum()
-    frac_sum = (rho - fl)[~near].sum()
-    assert abs(extra - frac_sum) <= 1 + 1e-6
-    assert R_t - 1 <= Rn <= R_t
+    assert np.all((n >= fl) | near)
+    assert np.all(n[near] >= np.round(rho[near]) - 1)
+    assert Rn == n.sum() == R_t
+    # a replica whose mean is an integer gets exactly that many copies
+    whole = np.abs(rho - np.round(rho)) < 1e-12
+    if whole.any():
+        assert np.all(n[whole] == np.round(rho[whole]))
+
+
+@pytest.mark.parametrize("R,R_t", [(500, 500), (500, 1000), (300, 301),
+                                   (400, 1201)])
+def test_residual_at_zero_step_is_exact_or_one_draw(R, R_t):
+    """At dbeta = 0 every replica has mean R_t / R: an integer mean gives
+    exactly that many copies of each replica (no draws), and a target one
+    above a multiple of the population is one draw over equal fractions."""
+    N, E = _energies(7, R)
+    n, Rn, _ = oracle.counts(N, E, R_t, 0.0, 3, 2, 5, law=oracle.RESIDUAL)
+    assert Rn == R_t == n.sum()
+    base = R_t // R
+    assert np.all((n == base) | (n == base + 1))
+    assert (n == base + 1).sum() == R_t - base * R
 
 
 def test_residual_counts_are_unbiased():
     N, E = _energies(5, 300)
     R_t, dbeta = 300, 0.05
     rho = _rho(E, R_t, dbeta)
+    fl = np.floor(rho)
+    frac = rho - fl
+    D = R_t - fl.sum()
+    p = frac / frac.sum()
     acc = np.zeros(len(E))
     K = 300
     for step in range(1, K + 1):
         acc += oracle.counts(N, E, R_t, dbeta, 8, 1, step,
                              law=oracle.RESIDUAL)[0]
-    frac = rho - np.floor(rho)
-    sd = np.sqrt(frac * (1 - frac) / K) + 1e-12
+    sd = np.sqrt(D * p * (1 - p) / K) + 1e-12
     z = (acc / K - rho) / sd
     assert np.all(np.abs(z[frac > 0.02]) < 6)
+    assert abs(z[frac > 0.02].mean()) < 6 / np.sqrt((frac > 0.02).sum())
 
 
 def test_multinomial_draws_follow_the_weights():
