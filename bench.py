@@ -113,7 +113,8 @@ def run_anneal(binding, cfg, stream, timing=None, rows_per_lane=0):
     L, R, theta = cfg["L"], cfg["R"], cfg["theta"]
     g = binding.Population(L, R, seed=cfg["seed"], layout=layout,
                            rows_per_lane=rows_per_lane, stream=stream,
-                           capacity=deferral_capacity(R), q=cfg.get("q", 0))
+                           capacity=deferral_capacity(R), q=cfg.get("q", 0),
+                           resampling=cfg.get("law", 0))
     if timing:
         g.set_timing(True, classes=timing)
     attempts = 0
@@ -417,6 +418,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="C2", choices=sorted(W.CONFIGS))
     ap.add_argument("--rows-per-lane", type=int, default=0)
+    ap.add_argument("--law", default="nearest",
+                    choices=["nearest", "poisson", "systematic", "residual",
+                             "multinomial"],
+                    help="resampling law of the timed anneals")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-batched", action="store_true")
@@ -479,6 +484,8 @@ def main():
         return
     cfg = dict(W.CONFIGS[args.workload])
     cfg["name"] = args.workload
+    cfg["law"] = ["nearest", "poisson", "systematic", "residual",
+                  "multinomial"].index(args.law)
     if args.calibrate_copy:
         src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
@@ -556,6 +563,7 @@ def main():
                            cfg["seed"]),
             "L": cfg["L"], "R": cfg["R"], "K": cfg["K"],
             "theta": cfg["theta"], "layout": cfg["layout"],
+            "resampling": args.law,
         },
         "roofline": {
             "kernel": ("k_potts" if cfg.get("q") else "k_lattice") +

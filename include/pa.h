@@ -97,13 +97,16 @@ typedef struct {
                          the new step), n_j = floor((C_j + U) / 2^32) -
                          floor((C_{j-1} + U) / 2^32): every count is the
                          floor or ceiling of its mean and the size is
-                         within one of the target; or PA_RESIDUAL, floor(rho)
-                         copies for certain plus the same comb over the
+                         within one of the target; or PA_MULTINOMIAL,
+                         R_target independent draws: draw i (RESAMPLE
+                         group 2, slot i, word 0 u) lands at
+                         floor(u C / 2^32), C the total of the P_j, in the
+                         replica whose [C_{j-1}, C_j) holds it; or
+                         PA_RESIDUAL, floor(rho) copies for certain plus
+                         D = R_target - sum floor(rho) such draws over the
                          fractional parts alone (P_j = floor(frac(rho)
-                         2^32)); or PA_MULTINOMIAL, R_target independent
-                         draws: draw i (RESAMPLE group 2, slot i, word 0 u)
-                         lands at floor(u C / 2^32), C the total of the
-                         P_j, in the replica whose [C_{j-1}, C_j) holds it.
+                         2^32); no draws when all are zero): the size is
+                         exactly sum floor(rho) + D.
                          Single populations only: pa_batch_init takes
                          PA_NEAREST only.                                  */
   int32_t q;          /* PA_POTTS: number of states, 2..16; else ignored   */

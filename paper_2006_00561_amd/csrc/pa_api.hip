@@ -56,7 +56,7 @@ struct pa_ctx {
   uint32_t* tile_off = nullptr;
   uint64_t* tile64 = nullptr;           // systematic law: tile sums of the
   uint64_t* off64 = nullptr;            // fixed-point means and their scan
-  uint64_t* cum = nullptr;              // multinomial law: interval ends
+  uint64_t* cum = nullptr;              // multinomial, residual: interval ends
   // Read-back block, one device->host copy per histogram: the histogram
   // (nbins words, padded to an even count nb2), then scal = [0] sum|M|,
   // [1] sum M^2, [2] unused, [3] energies outside the histogram, all
@@ -435,7 +435,7 @@ int pa_init(const pa_config* cfg, pa_ctx** out) {
   ok = ok && dmalloc(&c->tile_off, (size_t)c->ntiles_cap * 4);
   ok = ok && dmalloc(&c->tile64, (size_t)c->ntiles_cap * 8);
   ok = ok && dmalloc(&c->off64, (size_t)c->ntiles_cap * 8);
-  if (cfg->resampling == PA_MULTINOMIAL)
+  if (cfg->resampling == PA_MULTINOMIAL || cfg->resampling == PA_RESIDUAL)
     ok = ok && dmalloc(&c->cum, (size_t)cap * 8);
   c->nb2 = (c->nbins + 1) & ~1;
   ok = ok && dmalloc(&c->rb, ((size_t)c->nb2 + 16) * 4);
@@ -535,7 +535,7 @@ int pa_resample(pa_ctx* c, double beta_next, int64_t* R_new) {
   const double dbeta = beta_next - c->beta;
   TableRange tr;
   const int nbins = c->nbins;
-  int64_t r_min = 0, r_max = 0;
+  int64_t r_min = 0, r_max = 0, draws = 0;
   CountsArgs ca{};
   if (c->law == PA_POISSON) {
     std::vector<uint32_t> pt;
@@ -565,22 +565,30 @@ int pa_resample(pa_ctx* c, double beta_next, int64_t* R_new) {
     ca.T = c->tab + nl;
     if (c->law == PA_MULTINOMIAL) {
       r_min = r_max = c->R_t;  // exactly R_target draws
-    } else if (c->law == PA_SYSTEMATIC || c->law == PA_RESIDUAL) {
-      // the comb gives floor((C + U) / 2^32) copies in total, C the sum of
-      // the fixed-point means (of the fractions alone for the residual law,
-      // which adds the floors): one of two sizes
-      const bool res = c->law == PA_RESIDUAL;
+      draws = c->R_t;
+    } else if (c->law == PA_RESIDUAL) {
+      // the floors for certain, then R_target minus their sum drawn over
+      // the fractions (none when every fraction is zero): exactly one size
       uint64_t C = 0;
       int64_t floors = 0;
       for (int i = tr.lo; i <= tr.hi; ++i) {
         const uint64_t h = c->h_hist[i];
-        C += h * ((res ? 0ull : ((uint64_t)hf[i - tr.lo] << 32)) +
-                  (uint64_t)hT[i - tr.lo]);
-        if (res) floors += (int64_t)h * hf[i - tr.lo];
+        C += h * (uint64_t)hT[i - tr.lo];
+        floors += (int64_t)h * hf[i - tr.lo];
       }
-      r_min = floors + (int64_t)(C >> 32);
+      draws = c->R_t - floors;
+      if (draws < 0 || C == 0) draws = 0;
+      r_min = r_max = floors + draws;
+      ca.residual = 1;
+    } else if (c->law == PA_SYSTEMATIC) {
+      // the comb gives floor((C + U) / 2^32) copies in total, C the sum of
+      // the fixed-point means: one of two sizes
+      uint64_t C = 0;
+      for (int i = tr.lo; i <= tr.hi; ++i)
+        C += (uint64_t)c->h_hist[i] *
+             (((uint64_t)hf[i - tr.lo] << 32) + (uint64_t)hT[i - tr.lo]);
+      r_min = (int64_t)(C >> 32);
       r_max = r_min + 1;
-      ca.residual = res ? 1 : 0;
     } else {
       // every replica at level l gets f or f + 1 copies, f + 1 only where
       // its threshold is nonzero
@@ -615,10 +623,10 @@ int pa_resample(pa_ctx* c, double beta_next, int64_t* R_new) {
   // the caller did not ask for it: the next synchronisation brings it
   const bool deferred = !R_new && r_min >= 1 && r_max <= c->cap;
   hipEvent_t e0 = t_begin(c, PA_K_COUNTS);
-  if (c->law == PA_MULTINOMIAL)
-    CK(launch_multi_counts(ca, c->R_t, c->tile64, c->off64, c->cum,
+  if (c->law == PA_MULTINOMIAL || c->law == PA_RESIDUAL)
+    CK(launch_multi_counts(ca, draws, c->tile64, c->off64, c->cum,
                            c->stream));
-  else if (c->law == PA_SYSTEMATIC || c->law == PA_RESIDUAL)
+  else if (c->law == PA_SYSTEMATIC)
     CK(launch_sys_counts(ca, c->tile64, c->off64, c->stream));
   else
     CK(launch_counts(ca, c->stream));

@@ -63,8 +63,8 @@ struct CountsArgs {
   // Poisson law: when set, f points to the level table of
   // build_poisson_tables (T is unused)
   int32_t poisson;
-  // systematic kernels: residual law (floor(rho) copies kept, the comb over
-  // the fractional parts only)
+  // multinomial kernels: residual law (floor(rho) copies kept, the draws
+  // over the fractional parts only)
   int32_t residual;
   int64_t R;
   int32_t twoN, shift, lvl0, nlvl;

@@ -147,7 +147,7 @@ __global__ __launch_bounds__(256) void k_counts(CountsArgs a) {
 // integer sums); one comb of unit-spaced points offset by the word U gives
 // n_j = floor((C_j + U) / 2^32) - floor((C_{j-1} + U) / 2^32).
 
-// (the residual law combs the fractional parts alone: P_j = T)
+// (the residual law draws over the fractional parts alone: P_j = T)
 __device__ __forceinline__ uint64_t sys_mean(const CountsArgs& a, int64_t j) {
   const int l = ((a.E[j] + a.twoN) >> a.shift) - a.lvl0;
   if (l < 0 || l >= a.nlvl) return 0ull;
@@ -226,12 +226,8 @@ __global__ __launch_bounds__(256) void k_sys_counts(CountsArgs a,
   const uint64_t U = philox10(make_uint4((kDomainResample << 28) | 1u,
                                          a.step_next << 16, 0u, a.pop),
                               a.k0, a.k1).x;
-  uint32_t nj =
+  const uint32_t nj =
       j < a.R ? (uint32_t)(((C + P + U) >> 32) - ((C + U) >> 32)) : 0u;
-  if (a.residual && j < a.R) {  // the certain copies
-    const int l = ((a.E[j] + a.twoN) >> a.shift) - a.lvl0;
-    if (l >= 0 && l < a.nlvl) nj += a.f[l];
-  }
   if (j < a.R) a.n[j] = nj;
   uint32_t total;
   (void)block_excl_scan(nj, l32, &total);
@@ -242,8 +238,10 @@ __global__ __launch_bounds__(256) void k_sys_counts(CountsArgs a,
 // R_target independent draws on the same fixed-point axis: draw i (word 0 of
 // RESAMPLE group 2, slot i, at the new step) lands at x_i = floor(u_i C / 2^32)
 // and counts for the replica whose interval [C_{j-1}, C_j) holds it.
+// The residual law starts every count at floor(rho) and draws the rest,
+// R_target - sum floor(rho), over the fractional parts (P_j = T).
 
-// Interval ends C_j of every replica (and its count cleared).
+// Interval ends C_j of every replica, and its count before the draws.
 __global__ __launch_bounds__(256) void k_multi_cum(CountsArgs a,
                                                    const uint64_t* off64,
                                                    uint64_t* cum) {
@@ -254,7 +252,12 @@ __global__ __launch_bounds__(256) void k_multi_cum(CountsArgs a,
   const uint64_t C = off64[blockIdx.x] + block_excl_scan64(P, l64, &tot);
   if (j < a.R) {
     cum[j] = C + P;
-    a.n[j] = 0u;
+    uint32_t n0 = 0u;
+    if (a.residual) {  // the certain copies
+      const int l = ((a.E[j] + a.twoN) >> a.shift) - a.lvl0;
+      if (l >= 0 && l < a.nlvl) n0 = a.f[l];
+    }
+    a.n[j] = n0;
   }
 }
 
@@ -474,8 +477,9 @@ hipError_t launch_multi_counts(const CountsArgs& a, int64_t draws,
                      blocks);
   hipLaunchKernelGGL(k_multi_cum, dim3((unsigned)blocks), dim3(256), 0, st, a,
                      off64, cum);
-  hipLaunchKernelGGL(k_multi_draw, dim3((unsigned)((draws + 255) / 256)),
-                     dim3(256), 0, st, a, cum, draws);
+  if (draws > 0)  // the host passes no draws when the weights are all zero
+    hipLaunchKernelGGL(k_multi_draw, dim3((unsigned)((draws + 255) / 256)),
+                       dim3(256), 0, st, a, cum, draws);
   hipLaunchKernelGGL(k_count_tiles, dim3((unsigned)blocks), dim3(256), 0, st,
                      a);
   return hipGetLastError();
