@@ -99,21 +99,13 @@ def gather_copy(binding, cfg, stream, reps=5):
             "frac_hbm": gbps / HBM_PEAK_GBPS}
 
 
-def deferral_capacity(R):
-    """Capacity at which a resampling never waits for its new size: the size
-    is bounded by R_target + R_old, with R_old within R_target + 16 sqrt(R)
-    + 1024 (the default capacity)."""
-    import math
-    return 2 * R + 16 * math.isqrt(R - 1) + 16 + 1024
-
-
 def run_anneal(binding, cfg, stream, timing=None, rows_per_lane=0):
     """One full anneal; timing: None, or the kernel classes to time."""
     layout = binding.PA_BITS if cfg["layout"] == "bits" else binding.PA_INT8
     L, R, theta = cfg["L"], cfg["R"], cfg["theta"]
     g = binding.Population(L, R, seed=cfg["seed"], layout=layout,
                            rows_per_lane=rows_per_lane, stream=stream,
-                           capacity=deferral_capacity(R), q=cfg.get("q", 0),
+                           capacity=W.deferral_capacity(R), q=cfg.get("q", 0),
                            resampling=cfg.get("law", 0))
     if timing:
         g.set_timing(True, classes=timing)

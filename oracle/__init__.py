@@ -25,5 +25,6 @@ from .oracle import (  # noqa: F401
     lib,
     philox4x32_10,
     poisson_draw,
+    sweep_potts_replica,
     sweep_replica,
 )

@@ -110,6 +110,10 @@ def lib():
                                         C.POINTER(C.c_int32), C.c_double,
                                         C.c_uint64, C.c_uint32, C.c_int,
                                         C.c_int, C.c_int, C.c_uint32]
+        L.orc_sweep_potts_replica.argtypes = [
+            C.c_int, C.c_int, i8p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+            C.c_double, C.c_uint64, C.c_uint32, C.c_int, C.c_int, C.c_int,
+            C.c_uint32]
         L.orc_overlap.argtypes = [P, C.c_double, C.POINTER(C.c_double)]
         L.orc_bisect_dbeta.argtypes = [P, C.c_double, C.c_double,
                                        C.POINTER(C.c_double)]
@@ -175,6 +179,18 @@ def sweep_replica(spins, E, M, beta, seed, pop, step, t0, theta, slot, J=None):
     _check(lib().orc_sweep_replica(L, jp, s, C.byref(e), C.byref(m), beta,
                                    seed, pop, step, t0, theta, slot),
            "sweep_replica")
+    return s, e.value, m.value
+
+
+def sweep_potts_replica(spins, E, M, beta, q, seed, pop, step, t0, theta,
+                        slot):
+    """theta sweeps of one q-state Potts replica; returns (states, E, M)."""
+    s = np.array(spins, dtype=np.int8, copy=True, order="C")
+    L = s.shape[-1]
+    e, m = C.c_int32(int(E)), C.c_int32(int(M))
+    _check(lib().orc_sweep_potts_replica(L, q, s, C.byref(e), C.byref(m),
+                                         beta, seed, pop, step, t0, theta,
+                                         slot), "sweep_potts_replica")
     return s, e.value, m.value
 
 

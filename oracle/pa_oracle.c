@@ -612,6 +612,19 @@ int orc_sweep_replica(int L, const int8_t* J, int8_t* spins, int32_t* E,
   return ORC_OK;
 }
 
+int orc_sweep_potts_replica(int L, int q, int8_t* spins, int32_t* E,
+                            int32_t* M, double beta, uint64_t seed,
+                            uint32_t pop, int step, int t0, int theta,
+                            uint32_t slot) {
+  if (L < 4 || L > 128 || (L % 2) || q < 2 || q > 16 || !spins || !E || !M ||
+      theta < 0 || t0 < 0 || t0 + theta > 32767 || !isfinite(beta))
+    return ORC_EINVAL;
+  uint64_t T[5];
+  potts_thresholds(beta, T);
+  sweep_potts_one(L, q, spins, E, M, seed, pop, step, t0, theta, slot, T);
+  return ORC_OK;
+}
+
 int orc_sweep(orc_pa* p, int theta) {
   if (!p || theta < 0) return ORC_EINVAL;
   if (p->sweeps_at_step + theta > 32767) return ORC_EINVAL;

@@ -121,6 +121,11 @@ int orc_counts(int N, const int32_t* E, int64_t R, int64_t R_t, double dbeta,
 int orc_sweep_replica(int L, const int8_t* J, int8_t* spins, int32_t* E,
                       int32_t* M, double beta, uint64_t seed, uint32_t pop,
                       int step, int t0, int theta, uint32_t slot);
+/* The same for one replica of the q-state Potts ferromagnet. */
+int orc_sweep_potts_replica(int L, int q, int8_t* spins, int32_t* E,
+                            int32_t* M, double beta, uint64_t seed,
+                            uint32_t pop, int step, int t0, int theta,
+                            uint32_t slot);
 
 /* Overlap of successive energy distributions for a step dbeta and the
    bisection that picks the largest step meeting a target overlap. */

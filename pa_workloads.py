@@ -14,6 +14,8 @@ benchmark and the tests run.
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 # name -> (L, R_target, layout, beta_f, K, theta, seed[, q for Potts])
@@ -40,6 +42,13 @@ CONFIGS = {
     "CQ10": dict(L=64, R=20480, layout="int8", beta_f=1.6, K=200, theta=10,
                  seed=1, q=10),
 }
+
+
+def deferral_capacity(R: int) -> int:
+    """Capacity at which a resampling never waits for its new size: the size
+    is bounded by R_target + R_old, with R_old within R_target + 16 sqrt(R)
+    + 1024 (the default capacity)."""
+    return 2 * R + 16 * math.isqrt(R - 1) + 16 + 1024
 
 
 def linear_schedule(beta_f: float, K: int, beta0: float = 0.0):

@@ -244,47 +244,58 @@ def test_timing_counters(pa):
 
 
 @pytest.mark.parametrize("name,steps,sample", [("C2", 3, 48), ("C3a", 2, 24),
-                                               ("C3b", 2, 16)])
+                                               ("C3b", 2, 16),
+                                               ("CQ10", 2, 24)])
 def test_full_size_sampled(pa, name, steps, sample):
-    """At the benchmark sizes: every copy count, R_new and ln Q exactly from
-    the oracle's count step on the device energies; a sample of replicas
-    through theta sweeps with the oracle's single-replica sweep; observables
-    from the full E and M arrays."""
+    """At the benchmark sizes and in the benchmark's launch configuration
+    (the capacity at which no resampling waits for its new size, resampling
+    without waiting, the copies made by the next sweep from the parents):
+    every copy count, R_new and ln Q exactly from the oracle's count step on
+    the device energies; a sample of new replicas through theta sweeps with
+    the oracle's single-replica sweep, started from their parents' states
+    read before the resampling; observables from the full E and M arrays."""
     c = W.CONFIGS[name]
-    L, R, theta = c["L"], c["R"], c["theta"]
+    L, R, theta, q = c["L"], c["R"], c["theta"], c.get("q", 0)
     layout = 1 if c["layout"] == "bits" else 0
-    print("full-size parity %s L=%d R=%d layout=%d" % (name, L, R, layout),
-          flush=True)
-    g = pa.Population(L, R, seed=c["seed"], layout=layout)
+    print("full-size parity %s L=%d R=%d layout=%d q=%d" % (name, L, R, layout,
+                                                           q), flush=True)
+    g = pa.Population(L, R, seed=c["seed"], layout=layout, q=q,
+                      capacity=W.deferral_capacity(R))
     rng = np.random.default_rng(0)
     sched = W.linear_schedule(c["beta_f"], c["K"])
     # initial state: sampled replicas against the oracle's init
-    o = oracle.OraclePA(L, 8, seed=c["seed"])
+    o = oracle.OraclePA(L, 8, seed=c["seed"], q=q)
     so, Eo, Mo = o.population()
     sg, Eg, Mg = g.replicas(np.arange(8))
     assert np.array_equal(sg, so) and np.array_equal(Eg, Eo)
+    assert np.array_equal(Mg, Mo)
+    o.close()
     zlast = g.free_energy()[0]
     for i in range(1, steps + 1):
         b = sched[i - 1]
         E, M = g.energies()
         n_o, Rn_o, lnQ_o = oracle.counts(L * L, E, R, b - g.beta, c["seed"],
                                          0, i)
-        Rn = g.resample(b)
-        assert Rn == Rn_o
-        assert np.array_equal(g.counts(), n_o)
-        z, q = g.free_energy()
-        assert _close(q, lnQ_o) and _close(z, zlast + lnQ_o)
-        zlast = z
         parent = np.repeat(np.arange(len(E)), n_o)
-        slots = np.sort(rng.choice(Rn, size=sample, replace=False))
-        s_pre, E_pre, M_pre = g.replicas(slots)
-        assert np.array_equal(E_pre, E[parent[slots]])
+        slots = np.sort(rng.choice(Rn_o, size=sample, replace=False))
+        s_pre, E_pre, M_pre = g.replicas(parent[slots])
+        g.resample(b, wait=False)
         g.sweep(b, theta)
+        assert g.state()[0] == Rn_o
+        assert np.array_equal(g.counts(), n_o)
+        z, dq = g.free_energy()
+        assert _close(dq, lnQ_o) and _close(z, zlast + lnQ_o)
+        zlast = z
         s_post, E_post, M_post = g.replicas(slots)
         for k, j in enumerate(slots):
-            so, eo, mo = oracle.sweep_replica(s_pre[k], E_pre[k], M_pre[k],
-                                              b, c["seed"], 0, i, 0, theta,
-                                              int(j))
+            if q:
+                so, eo, mo = oracle.sweep_potts_replica(
+                    s_pre[k], E_pre[k], M_pre[k], b, q, c["seed"], 0, i, 0,
+                    theta, int(j))
+            else:
+                so, eo, mo = oracle.sweep_replica(s_pre[k], E_pre[k],
+                                                  M_pre[k], b, c["seed"], 0,
+                                                  i, 0, theta, int(j))
             assert np.array_equal(s_post[k], so), (name, i, j)
             assert (E_post[k], M_post[k]) == (eo, mo)
         E2, M2 = g.energies()

@@ -92,3 +92,24 @@ def test_q2_is_the_ising_model_at_half_coupling():
     exact = beta * N + float(X.kaufman_lnZ(L, beta / 2))
     z = _lnZ_runs(L, 2, beta, 50, 4, range(1, 7), 1000)
     assert abs(z.mean() - exact) < 5 * z.std(ddof=1) / np.sqrt(len(z)) + 0.05
+
+
+def test_single_replica_sweep_follows_the_population_sweep():
+    """The single-replica Potts sweep (used to check sampled replicas at
+    large populations) takes each replica through the same sweeps as the
+    population sweep, from the same state, step and slot; and its returned
+    E and M equal the energy and magnetisation of the state it returns."""
+    L, q, R = 6, 4, 12
+    p = oracle.OraclePA(L, R, seed=5, pop=2, q=q)
+    p.resample(0.3)
+    s0, E0, M0 = p.population()
+    p.sweep(3)
+    s1, E1, M1 = p.population()
+    for j in range(R):
+        s, e, m = oracle.sweep_potts_replica(s0[j], E0[j], M0[j], p.beta, q,
+                                             5, 2, p.step, 0, 3, j)
+        assert np.array_equal(s, s1[j]) and (e, m) == (E1[j], M1[j])
+        # H = -(number of equal nearest-neighbour pairs), M = q n_0 - N
+        ee = -int((s == np.roll(s, 1, 0)).sum() + (s == np.roll(s, 1, 1)).sum())
+        assert (e, m) == (ee, q * int((s == 0).sum()) - L * L)
+    p.close()
