@@ -558,7 +558,8 @@ def main():
             "resampling": args.law,
         },
         "roofline": {
-            "kernel": ("k_potts" if cfg.get("q") else "k_lattice") +
+            "kernel": (("k_potts_swar" if cfg["L"] in (8, 16, 32, 64, 128)
+                        else "k_potts") if cfg.get("q") else "k_lattice") +
                       " (theta fused Metropolis sweeps)",
             "bound": "alu",
             "achieved": achieved,

@@ -523,11 +523,14 @@ def test_heating_matches_oracle(pa, L, R, layout, law):
 @pytest.mark.parametrize("L,R,q,beta_f,law", [(16, 600, 3, 1.2, 0),
                                                (12, 500, 10, 1.8, 1),
                                                (6, 300, 16, 2.0, 0),
+                                               (32, 150, 7, 1.5, 0),
+                                               (8, 700, 2, 0.9, 1),
                                                (128, 40, 4, 1.1, 0)])
 def test_potts_matches_oracle(pa, L, R, q, beta_f, law):
     """q-state Potts populations (Sec. 2 names the model): every step
     bit-exact with the oracle, including q = 10 across its first-order
-    transition and the largest lattice."""
+    transition and the largest lattice.  L = 8, 16, 32, 128 take the
+    four-sites-per-word pass, L = 6 and 12 the generic one."""
     _parity_run(pa, L, R, 30, 3, beta_f, seed=8, pop=5, law=law, q=q)
 
 
