@@ -198,7 +198,7 @@ def bench_batched(binding, stream, use_graph=True):
 def bench_learned(binding, use_graph=True, target=0.85, tol=0.02):
     """Adaptive schedules on the C4 populations to beta_f = 3, theta = 10:
     the exact bisection on the overlap, and the network (trained on the
-    exact schedules of 32 other instances) with the bisection as judge and
+    exact schedules of 32 other instances) with the bisection as check and
     fallback.  Wall time to beta_f, host time of the decisions, exact
     overlap evaluations, and the ln Z agreement of the two."""
     from paper_2006_00561_amd import learned
@@ -455,9 +455,10 @@ def main():
         summarize_profiles(*args.summarize_profiles, args.workload, cmd)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU "
-              "path (the population would shard by replica slots; see the "
-              "design notes).  Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU "
+              "path (a population would shard by replica slots, with one "
+              "histogram all-reduce per temperature step).  Run with "
+              "--gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -343,7 +343,7 @@ int pa_batch_run_adaptive(pa_batch* b, double target, double beta_f,
  * standardised with (mu, sigma), the output de-standardised with
  * (mu_y, sigma_y).  Forward, backward (mean squared error on standardised
  * targets) and Adam run in the library's HIP kernels.  The exact bisection
- * remains the judge and the fallback, and the reweighting stays exact, so the
+ * remains the check and the fallback, and the reweighting stays exact, so the
  * network only changes which temperatures are visited, never the weights.
  * Parameters: one flat FP32 vector, per layer W (out x in, row-major), b.
  * ---------------------------------------------------------------------- */

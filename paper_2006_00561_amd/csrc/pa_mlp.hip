@@ -2,7 +2,7 @@
 // proposes log(dbeta) for the next annealing step from energy-histogram
 // summaries of a population.  Training (forward, backward, Adam) and
 // inference run in the hand-written kernels below; the exact bisection on the
-// energy-distribution overlap stays the judge and the fallback, and the
+// energy-distribution overlap stays the check and the fallback, and the
 // reweighting stays exact, so a poor proposal costs time, never bias.
 //
 //   u   = (x - mu) / sigma
