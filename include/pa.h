@@ -76,9 +76,12 @@ typedef struct {
   int32_t layout;     /* PA_INT8: one byte per spin; PA_BITS: one bit per
                          spin, row y in ceil(L/32) uint32 words, site x in
                          bit x%32 of word x/32, bit set = +1                */
-  int32_t rows_per_lane; /* sweep launch shape: 0 = tuned default, else 1, 2
-                         or 4 lattice rows per lane (must divide L; L/rows
-                         <= 64).  Results do not depend on it.             */
+  int32_t rows_per_lane; /* sweep launch shape: 1, 2, 3 or 4 lattice rows
+                         per lane (must divide L; L/rows <= 64; at least 2
+                         for L > 64), or 0: 3 at L = 48 and 96, 2 above
+                         L = 64, else 1 (a batch created with
+                         PA_BATCH_AUTOTUNE times the valid shapes instead).
+                         Results do not depend on it.                       */
   uint64_t seed;      /* Philox key                                          */
   uint32_t population_id; /* Philox counter word 3                          */
   void* stream;       /* hipStream_t to run on; NULL = the null stream      */
@@ -305,9 +308,9 @@ typedef struct pa_batch pa_batch;
 enum { PA_BATCH_AUTOTUNE = 1 };   /* flags of pa_batch_init */
 
 /* Launch-shape autotuner: times theta sweeps of a synthetic population of R
-   replicas of side L for 1, 2 and 4 rows per lane (those valid for L) with
-   HIP events; *best receives the fastest, ms[3] (may be NULL) the times
-   (-1 for invalid shapes).  Results never depend on the shape. */
+   replicas of side L for 1, 2, 3 and 4 rows per lane (those valid for L)
+   with HIP events; *best receives the fastest, ms[4] (may be NULL) the
+   times (-1 for invalid shapes).  Results never depend on the shape. */
 int pa_tune_rows_per_lane(int32_t L, int32_t layout, int32_t model,
                           int64_t R, int32_t theta, void* stream,
                           int32_t* best, float* ms);

@@ -349,7 +349,7 @@ def tune_rows_per_lane(L, layout=PA_INT8, model=PA_FERRO, R=4096, theta=4,
                        stream=None):
     """Fastest rows-per-lane sweep shape for side L (and the three times)."""
     best = C.c_int32()
-    ms = (C.c_float * 3)()
+    ms = (C.c_float * 4)()
     _ck(lib().pa_tune_rows_per_lane(L, layout, model, R, theta, stream,
                                     C.byref(best), ms),
         "pa_tune_rows_per_lane")

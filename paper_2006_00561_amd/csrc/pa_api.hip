@@ -384,8 +384,8 @@ int pa_init(const pa_config* cfg, pa_ctx** out) {
   if (cap < cfg->R_target || cap >= (1ll << 32)) return PA_EINVAL;
   const int W = (L + 31) / 32;
   int rpl = cfg->rows_per_lane;
-  if (rpl == 0) rpl = (L > 64) ? 2 : 1;
-  if (rpl != 1 && rpl != 2 && rpl != 4) return PA_EINVAL;
+  if (rpl == 0) rpl = default_rows_per_lane(L);
+  if (rpl < 1 || rpl > 4) return PA_EINVAL;
   if (L % rpl != 0 || L / rpl > 64) return PA_EINVAL;
   if (W >= 3 && rpl < 2) return PA_EINVAL;
   if (cfg->model == PA_PMJ) {

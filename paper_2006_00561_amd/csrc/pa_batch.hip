@@ -43,11 +43,10 @@ namespace pa {
 
 // Sweep classes: one per lattice variant (row words W, rows per lane, spin
 // layout, model), so a persistent launch carries the code of one variant.
-constexpr int kClasses = 48;
+constexpr int kClasses = 64;
 __host__ __device__ constexpr int sweep_class(int W, int rpl, int int8,
                                               int glass) {
-  return (((W - 1) * 3 + (rpl == 1 ? 0 : rpl == 2 ? 1 : 2)) * 2 + int8) * 2 +
-         glass;
+  return (((W - 1) * 4 + (rpl - 1)) * 2 + int8) * 2 + glass;
 }
 
 // -------------------------------------------------------------- kernels
@@ -720,22 +719,26 @@ hipError_t launch_bsweep(int k, int blocks, int chunk, hipStream_t st,
                          const int64_t* R, const int32_t* cur,
                          const int32_t* order, const int64_t* prefix,
                          unsigned long long* queue, int first, int count) {
-  const int glass = k & 1, int8 = (k >> 1) & 1, ri = (k >> 2) % 3,
-            W = (k >> 2) / 3 + 1;
+  const int glass = k & 1, int8 = (k >> 1) & 1, rpl = (k >> 2) % 4 + 1,
+            W = (k >> 2) / 4 + 1;
   const unsigned bl = (unsigned)blocks;
 #define PA_BS(w, r) \
   launch_bsweep_wr<w, r>(int8, glass, bl, st, P, S, R, cur, order, prefix, \
                          queue, first, count, chunk)
-  switch (W * 8 + (ri == 0 ? 1 : ri == 1 ? 2 : 4)) {
+  switch (W * 8 + rpl) {
     case 1 * 8 + 1: return PA_BS(1, 1);
     case 1 * 8 + 2: return PA_BS(1, 2);
+    case 1 * 8 + 3: return PA_BS(1, 3);
     case 1 * 8 + 4: return PA_BS(1, 4);
     case 2 * 8 + 1: return PA_BS(2, 1);
     case 2 * 8 + 2: return PA_BS(2, 2);
+    case 2 * 8 + 3: return PA_BS(2, 3);
     case 2 * 8 + 4: return PA_BS(2, 4);
     case 3 * 8 + 2: return PA_BS(3, 2);
+    case 3 * 8 + 3: return PA_BS(3, 3);
     case 3 * 8 + 4: return PA_BS(3, 4);
     case 4 * 8 + 2: return PA_BS(4, 2);
+    case 4 * 8 + 3: return PA_BS(4, 3);
     case 4 * 8 + 4: return PA_BS(4, 4);
     default: return hipErrorInvalidValue;
   }
@@ -895,15 +898,15 @@ int pa_tune_rows_per_lane(int32_t L, int32_t layout, int32_t model,
                           int32_t* best, float* ms) {
   if (!best || L < 4 || L > 128 || (L & 1) || R < 1 || theta < 1)
     return PA_EINVAL;
-  const int cand[3] = {1, 2, 4};
-  float t[3] = {-1.f, -1.f, -1.f};
+  const int cand[4] = {1, 2, 3, 4};
+  float t[4] = {-1.f, -1.f, -1.f, -1.f};
   std::vector<int8_t> J;
   if (model == PA_PMJ) {
     J.assign((size_t)2 * L * L, 1);
     for (size_t i = 0; i < J.size(); i += 3) J[i] = -1;
   }
   int bi = -1;
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < 4; ++k) {
     const int rpl = cand[k];
     if (L % rpl || L / rpl > 64 || ((L + 31) / 32 >= 3 && rpl < 2)) continue;
     pa_config cfg{};
@@ -933,7 +936,7 @@ int pa_tune_rows_per_lane(int32_t L, int32_t layout, int32_t model,
   if (bi < 0) return PA_EINVAL;
   *best = cand[bi];
   if (ms)
-    for (int k = 0; k < 3; ++k) ms[k] = t[k];
+    for (int k = 0; k < 4; ++k) ms[k] = t[k];
   return PA_OK;
 }
 
@@ -951,7 +954,7 @@ int pa_batch_init(const pa_config* cfgs, int32_t n, void* stream,
     if (c.resampling != PA_NEAREST) return PA_EINVAL;  // single path only
     if (c.R_target < 1 || c.R_target >= (1ll << 31)) return PA_EINVAL;
     const int rpl = c.rows_per_lane;
-    if (rpl != 0 && rpl != 1 && rpl != 2 && rpl != 4) return PA_EINVAL;
+    if (rpl < 0 || rpl > 4) return PA_EINVAL;
     if (rpl && (c.L % rpl || c.L / rpl > 64 || ((c.L + 31) / 32 >= 3 && rpl < 2)))
       return PA_EINVAL;
     if (c.model == PA_PMJ)
@@ -1006,7 +1009,7 @@ int pa_batch_init(const pa_config* cfgs, int32_t n, void* stream,
         rpl = best;
       }
     }
-    if (rpl == 0) rpl = (c.L > 64) ? 2 : 1;
+    if (rpl == 0) rpl = default_rows_per_lane(c.L);
     d.L = c.L;
     d.W = (c.L + 31) / 32;
     d.rpl = rpl;

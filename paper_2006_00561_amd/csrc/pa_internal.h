@@ -113,6 +113,14 @@ struct BatchStep {         // per population, rewritten by the host each step
   int32_t pad;
 };
 
+// Sweep shape when the caller leaves rows_per_lane at 0 and nothing is
+// tuned: three rows per lane fill whole waves at L = 48 and 96 (16 and 32
+// lanes per replica), where the tuner measured them fastest; two rows above
+// L = 64 keep the registers in bounds; one row otherwise.
+inline int default_rows_per_lane(int L) {
+  return (L == 48 || L == 96) ? 3 : (L > 64 ? 2 : 1);
+}
+
 // Histogram summaries fed to the temperature-step network (kFeatures per
 // population, computed on the device from the exact histogram).
 constexpr int kFeatures = 8;

@@ -428,13 +428,17 @@ hipError_t launch_lattice(const LatticeArgs& a, int W, int RPL, bool int8,
   switch (W * 8 + RPL) {
     case 1 * 8 + 1: return launch_lattice_w<1, 1>(a, int8, glass, grid, st);
     case 1 * 8 + 2: return launch_lattice_w<1, 2>(a, int8, glass, grid, st);
+    case 1 * 8 + 3: return launch_lattice_w<1, 3>(a, int8, glass, grid, st);
     case 1 * 8 + 4: return launch_lattice_w<1, 4>(a, int8, glass, grid, st);
     case 2 * 8 + 1: return launch_lattice_w<2, 1>(a, int8, glass, grid, st);
     case 2 * 8 + 2: return launch_lattice_w<2, 2>(a, int8, glass, grid, st);
+    case 2 * 8 + 3: return launch_lattice_w<2, 3>(a, int8, glass, grid, st);
     case 2 * 8 + 4: return launch_lattice_w<2, 4>(a, int8, glass, grid, st);
     case 3 * 8 + 2: return launch_lattice_w<3, 2>(a, int8, glass, grid, st);
+    case 3 * 8 + 3: return launch_lattice_w<3, 3>(a, int8, glass, grid, st);
     case 3 * 8 + 4: return launch_lattice_w<3, 4>(a, int8, glass, grid, st);
     case 4 * 8 + 2: return launch_lattice_w<4, 2>(a, int8, glass, grid, st);
+    case 4 * 8 + 3: return launch_lattice_w<4, 3>(a, int8, glass, grid, st);
     case 4 * 8 + 4: return launch_lattice_w<4, 4>(a, int8, glass, grid, st);
     default: return hipErrorInvalidValue;
   }

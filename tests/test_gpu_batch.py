@@ -157,11 +157,11 @@ def test_adaptive_schedule_matches_oracle_bisection(pa):
 
 
 def test_autotuner_reports_valid_shapes(pa):
-    for L, valid in ((16, (1, 2, 4)), (24, (1, 2, 4)), (64, (1, 2, 4)),
-                     (128, (2, 4))):
+    for L, valid in ((16, (1, 2, 4)), (24, (1, 2, 3, 4)), (64, (1, 2, 4)),
+                     (96, (2, 3, 4)), (128, (2, 4))):
         best, ms = pa.tune_rows_per_lane(L, R=2048, theta=2)
         assert best in valid
-        for rpl, t in zip((1, 2, 4), ms):
+        for rpl, t in zip((1, 2, 3, 4), ms):
             assert (t > 0) == (rpl in valid)
 
 

@@ -92,6 +92,8 @@ SHAPES = [
     (64, 129, 0, 0, False), (64, 70, 1, 2, True), (64, 70, 0, 4, False),
     (66, 20, 0, 0, False), (96, 30, 1, 0, True), (100, 12, 0, 4, False),
     (128, 24, 1, 0, False), (128, 20, 0, 4, True),
+    (12, 250, 1, 3, False), (24, 300, 0, 3, True), (48, 90, 0, 3, False),
+    (96, 30, 1, 3, True),
 ]
 
 
@@ -103,10 +105,10 @@ def test_shapes_and_layouts(pa, L, R, layout, rpl, glass):
 
 
 def test_launch_shape_and_layout_do_not_change_results(pa):
-    for L in (32, 64):
+    for L in (24, 32, 64):
         runs = []
         for layout in (0, 1):
-            for rpl in (1, 2, 4):
+            for rpl in ((1, 2, 3, 4) if L % 3 == 0 else (1, 2, 4)):
                 g = pa.Population(L, 500, seed=9, layout=layout,
                                   rows_per_lane=rpl)
                 for b in W.linear_schedule(0.7, 6):
