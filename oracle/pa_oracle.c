@@ -807,7 +807,7 @@ int orc_overlap(const orc_pa* p, double dbeta, double* alpha) {
     if (c == 0) continue;
     double pe = (double)c / (double)p->R;
     double qe = ((double)c * exp(-(dbeta * (double)(e - Emin)))) / S;
-    a = a + (pe < qe ? pe : qe);
+    a = a + ((ORC_MUTANT == 13) ? (pe < qe ? qe : pe) : (pe < qe ? pe : qe));
   }
   free(h);
   *alpha = a;
@@ -835,6 +835,6 @@ int orc_bisect_dbeta(const orc_pa* p, double target, double beta_f,
     if (a >= target) lo = mid;
     else hi = mid;
   }
-  *dbeta = lo;
+  *dbeta = (ORC_MUTANT == 14) ? hi : lo;
   return ORC_OK;
 }

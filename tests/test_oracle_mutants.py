@@ -39,6 +39,10 @@ CASES = {
          ["test_oracle_systematic.py::test_counts_are_floor_or_ceiling_and_size_is_exact"]),
     12: ("multinomial draws counted from the current size, not the target",
          ["test_oracle_systematic.py::test_multinomial_draws_follow_the_weights"]),
+    13: ("max instead of min of the two distributions in the overlap",
+         ["test_oracle_overlap.py::test_overlap_equals_the_per_replica_form"]),
+    14: ("bisection returns the end that misses the target",
+         ["test_oracle_overlap.py::test_bisection_inverts_the_two_level_overlap"]),
 }
 
 
