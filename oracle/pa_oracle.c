@@ -670,7 +670,8 @@ int orc_observables(const orc_pa* p, orc_obs* o) {
   o->e = (double)sE / (R * N);
   o->abs_m = (double)sAM / (R * N);
   o->m2 = (double)sM2 / (R * N * N);
-  o->C = ((p->beta * p->beta) * (double)var) / ((R * R) * N);
+  o->C = (((ORC_MUTANT == 15) ? p->beta : (p->beta * p->beta)) * (double)var) /
+         ((R * R) * N);
   o->sumE = sE;
   o->sumE2 = sE2;
   o->sumAbsM = sAM;

@@ -53,7 +53,8 @@ def density_of_states(L, J=None):
 
 
 def brute_thermo(L, beta, J=None):
-    """Exact ln Z, <E>/N, <|M|>/N, <M^2>/N^2 by enumeration (mpmath sums)."""
+    """Exact ln Z, <E>/N, <|M|>/N, <M^2>/N^2 and the specific heat
+    C = beta^2 (<E^2> - <E>^2) / N by enumeration (mpmath sums)."""
     E, M = enumerate_states(L, None if J is None else
                             np.ascontiguousarray(J, np.int8).tobytes())
     N = L * L
@@ -64,12 +65,14 @@ def brute_thermo(L, beta, J=None):
                           return_counts=True)
     Z = mp.mpf(0)
     sE = mp.mpf(0)
+    sE2 = mp.mpf(0)
     sAM = mp.mpf(0)
     sM2 = mp.mpf(0)
     for (e, am, m2), c in zip(keys.T.tolist(), cnt.tolist()):
         w = c * mp.exp(-b * e)
         Z += w
         sE += w * e
+        sE2 += w * e * e
         sAM += w * am
         sM2 += w * m2
     return {
@@ -77,6 +80,7 @@ def brute_thermo(L, beta, J=None):
         "e": float(sE / Z / N),
         "abs_m": float(sAM / Z / N),
         "m2": float(sM2 / Z / N / N),
+        "C": float(b * b * (sE2 / Z - (sE / Z) ** 2) / N),
     }
 
 

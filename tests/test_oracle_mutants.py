@@ -43,6 +43,8 @@ CASES = {
          ["test_oracle_overlap.py::test_overlap_equals_the_per_replica_form"]),
     14: ("bisection returns the end that misses the target",
          ["test_oracle_overlap.py::test_bisection_inverts_the_two_level_overlap"]),
+    15: ("one factor of beta dropped from the specific heat",
+         ["test_oracle_physics.py::test_observables_L4_match_enumeration"]),
 }
 
 

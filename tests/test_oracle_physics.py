@@ -40,15 +40,21 @@ def test_lnZ_and_Zhat_unbiased_L4():
 
 
 def test_observables_L4_match_enumeration():
+    """Energy, |m|, m^2 and specific heat of equilibrated L = 4 populations
+    against their exact Boltzmann averages (the specific heat from the
+    population's energy variance, as the oracle defines it)."""
     L, beta = 4, 0.5
     ex = X.brute_thermo(L, beta)
-    e, am = [], []
+    e, am, m2, cv = [], [], [], []
     for seed in range(1, 9):
         p, tr = _run(L, 2000, 10, 5, beta, seed)
         o = p.observables()
         e.append(o["e"])
         am.append(o["abs_m"])
-    for vals, want in ((e, ex["e"]), (am, ex["abs_m"])):
+        m2.append(o["m2"])
+        cv.append(o["C"])
+    for vals, want in ((e, ex["e"]), (am, ex["abs_m"]), (m2, ex["m2"]),
+                       (cv, ex["C"])):
         vals = np.array(vals)
         se = vals.std(ddof=1) / np.sqrt(len(vals))
         assert abs(vals.mean() - want) < 5 * se + 1e-3, (vals.mean(), want)
