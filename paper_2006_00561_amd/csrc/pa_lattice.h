@@ -195,6 +195,12 @@ __device__ __forceinline__ void lattice_pass(const LatticeArgs& a,
   }
 
   const int G8 = (L + 7) >> 3;
+  // the 1 of the rejection multiplies in a vector register, so that each
+  // v_mad_u64_u32 reads a single scalar operand (its threshold K) and K can
+  // stay in scalar registers instead of being copied to vector registers
+  // on every pass of the loop
+  uint32_t one_v;
+  asm("v_mov_b32 %0, %1" : "=v"(one_v) : "s"(a.one));
   for (int t = 0; t < a.theta; ++t) {
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
@@ -239,14 +245,14 @@ __device__ __forceinline__ void lattice_pass(const LatticeArgs& a,
             const uint4 b = philox10(
                 make_uint4(rowbase + (uint32_t)(4 * w + gq), ctr1, slot, a.pop),
                 a.k0, a.k1);
-            rj4 = shl2_add(rj4, reject_bit(b.w, a.one, a.K4));
-            rj8 = shl2_add(rj8, reject_bit(b.w, a.one, a.K8));
-            rj4 = shl2_add(rj4, reject_bit(b.z, a.one, a.K4));
-            rj8 = shl2_add(rj8, reject_bit(b.z, a.one, a.K8));
-            rj4 = shl2_add(rj4, reject_bit(b.y, a.one, a.K4));
-            rj8 = shl2_add(rj8, reject_bit(b.y, a.one, a.K8));
-            rj4 = shl2_add(rj4, reject_bit(b.x, a.one, a.K4));
-            rj8 = shl2_add(rj8, reject_bit(b.x, a.one, a.K8));
+            rj4 = shl2_add(rj4, reject_bit(b.w, one_v, a.K4));
+            rj8 = shl2_add(rj8, reject_bit(b.w, one_v, a.K8));
+            rj4 = shl2_add(rj4, reject_bit(b.z, one_v, a.K4));
+            rj8 = shl2_add(rj8, reject_bit(b.z, one_v, a.K8));
+            rj4 = shl2_add(rj4, reject_bit(b.y, one_v, a.K4));
+            rj8 = shl2_add(rj8, reject_bit(b.y, one_v, a.K8));
+            rj4 = shl2_add(rj4, reject_bit(b.x, one_v, a.K4));
+            rj8 = shl2_add(rj8, reject_bit(b.x, one_v, a.K8));
           }
           const uint32_t M4 = (~rj4 & 0x55555555u) << p;
           const uint32_t M8 = (~rj8 & 0x55555555u) << p;
