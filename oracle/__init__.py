@@ -22,6 +22,7 @@ from .oracle import (  # noqa: F401
     build,
     counts,
     energy,
+    family_stats,
     lib,
     philox4x32_10,
     poisson_draw,

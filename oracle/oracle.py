@@ -89,6 +89,13 @@ def lib():
         L.orc_step.argtypes = [P]
         L.orc_get_population.argtypes = [P, P, P, P, C.c_int64]
         L.orc_get_counts.argtypes = [P, u32p, C.c_int64]
+        L.orc_get_families.argtypes = [P, u32p, C.c_int64,
+                                       C.POINTER(C.c_int64)]
+        L.orc_family_stats.argtypes = [u32p, C.c_int64, C.c_int64,
+                                       C.POINTER(C.c_int64),
+                                       C.POINTER(C.c_int64),
+                                       C.POINTER(C.c_double),
+                                       C.POINTER(C.c_double)]
         L.orc_set_population.argtypes = [P, i8p, C.c_int64]
         L.orc_histogram.argtypes = [P, u32p]
         L.orc_set_visit_shuffle.argtypes = [P, C.c_uint64]
@@ -168,6 +175,17 @@ def counts(N, E, R_t, dbeta, seed, pop, step_next, law=NEAREST):
     _check(lib().orc_counts(N, E, len(E), R_t, dbeta, seed, pop, step_next,
                             law, n, C.byref(Rn), C.byref(lnQ)), "counts")
     return n, Rn.value, lnQ.value
+
+
+def family_stats(fam, n0):
+    """Families alive, largest family, rho_t and rho_s of a family array."""
+    f = np.ascontiguousarray(fam, np.uint32)
+    nf, big = C.c_int64(), C.c_int64()
+    rt, rs = C.c_double(), C.c_double()
+    _check(lib().orc_family_stats(f, len(f), n0, C.byref(nf), C.byref(big),
+                                  C.byref(rt), C.byref(rs)), "family_stats")
+    return {"families": nf.value, "largest": big.value, "rho_t": rt.value,
+            "rho_s": rs.value}
 
 
 def sweep_replica(spins, E, M, beta, seed, pop, step, t0, theta, slot, J=None):
@@ -287,6 +305,14 @@ class OraclePA:
         n = np.zeros(max(n_len, 1), np.uint32)
         _check(lib().orc_get_counts(self._h, n, n_len), "get_counts")
         return n[:n_len]
+
+    def families(self):
+        """(family of every replica, size of the founding population)."""
+        f = np.zeros(max(self.R, 1), np.uint32)
+        n0 = C.c_int64()
+        _check(lib().orc_get_families(self._h, f, self.R, C.byref(n0)),
+               "get_families")
+        return f[:self.R], n0.value
 
     def set_population(self, spins):
         s = np.ascontiguousarray(spins, dtype=np.int8)

@@ -74,6 +74,9 @@ struct orc_pa {
   uint64_t shuffle_seed;
   int law;          /* ORC_NEAREST or ORC_POISSON */
   int q;            /* 0: Ising spins +-1; 2..16: Potts states 0..q-1 */
+  uint32_t* fam;    /* family of every replica: the slot of its ancestor in
+                       the population the families start from, [cap] */
+  int64_t fam_n0;   /* size of that population */
 };
 
 /* ---------------------------------------------------------------- Philox */
@@ -175,6 +178,12 @@ static int potts_state(uint32_t w, int q) {
 
 /* ------------------------------------------------------------- lifetime */
 
+/* Every replica founds its own family. */
+static void reset_families(orc_pa* p) {
+  for (int64_t j = 0; j < p->R; ++j) p->fam[j] = (uint32_t)j;
+  p->fam_n0 = p->R;
+}
+
 static int create(int L, const int8_t* J, int q, int64_t R_t, int64_t cap,
                   uint64_t seed, uint32_t pop, orc_pa** out) {
   if (!out) return ORC_EINVAL;
@@ -198,11 +207,12 @@ static int create(int L, const int8_t* J, int q, int64_t R_t, int64_t cap,
   p->E = (int32_t*)malloc((size_t)cap * sizeof(int32_t));
   p->M = (int32_t*)malloc((size_t)cap * sizeof(int32_t));
   p->n = (uint32_t*)calloc((size_t)cap, sizeof(uint32_t));
+  p->fam = (uint32_t*)calloc((size_t)cap, sizeof(uint32_t));
   if (J) {
     p->J = (int8_t*)malloc(2 * N);
     if (p->J) memcpy(p->J, J, 2 * N);
   }
-  if (!p->spins || !p->E || !p->M || !p->n || (J && !p->J)) {
+  if (!p->spins || !p->E || !p->M || !p->n || !p->fam || (J && !p->J)) {
     orc_destroy(p);
     return ORC_ENOMEM;
   }
@@ -224,6 +234,7 @@ static int create(int L, const int8_t* J, int q, int64_t R_t, int64_t cap,
     else orc_energy(L, p->J, s, &p->E[j], &p->M[j]);
   }
   p->R = R_t;
+  reset_families(p);
   p->beta = 0.0;
   /* ln Omega: 2^N (q^N) states, all with weight 1 at beta_0 = 0. */
   p->lnZ = (ORC_MUTANT == 7) ? 0.0 : (double)p->N * log(q ? (double)q : 2.0);
@@ -252,6 +263,7 @@ void orc_destroy(orc_pa* p) {
   free(p->E);
   free(p->M);
   free(p->n);
+  free(p->fam);
   free(p->J);
   free(p);
 }
@@ -442,24 +454,27 @@ int orc_resample(orc_pa* p, double beta_next, int64_t* R_new) {
   int8_t* ns = (int8_t*)malloc((size_t)p->cap * N);
   int32_t* nE = (int32_t*)malloc((size_t)p->cap * sizeof(int32_t));
   int32_t* nM = (int32_t*)malloc((size_t)p->cap * sizeof(int32_t));
-  if (!ns || !nE || !nM) {
-    free(ns); free(nE); free(nM); free(n);
+  uint32_t* nF = (uint32_t*)malloc((size_t)p->cap * sizeof(uint32_t));
+  if (!ns || !nE || !nM || !nF) {
+    free(ns); free(nE); free(nM); free(nF); free(n);
     return ORC_ENOMEM;
   }
+  /* a copy belongs to its parent's family */
   int64_t k = 0;
   for (int64_t j = 0; j < p->R; ++j) {
     for (uint32_t c = 0; c < n[j]; ++c) {
       memcpy(ns + (size_t)k * N, p->spins + (size_t)j * N, N);
       nE[k] = p->E[j];
       nM[k] = p->M[j];
+      nF[k] = (ORC_MUTANT == 17) ? (uint32_t)j : p->fam[j];
       ++k;
     }
   }
   memcpy(p->n, n, (size_t)p->R * sizeof(uint32_t));
   p->n_len = p->R;
   free(n);
-  free(p->spins); free(p->E); free(p->M);
-  p->spins = ns; p->E = nE; p->M = nM;
+  free(p->spins); free(p->E); free(p->M); free(p->fam);
+  p->spins = ns; p->E = nE; p->M = nM; p->fam = nF;
   p->R = total;
   p->beta = beta_next;
   p->step += 1;
@@ -732,6 +747,7 @@ int orc_start_heating(orc_pa* p, double beta0) {
       orc_energy(p->L, p->J, s, &p->E[j], &p->M[j]);
     }
   }
+  reset_families(p);
   p->beta = beta0;
   /* ln(#ground states) - beta0 E_0 with E_0 = -2N */
   p->lnZ = log(p->q ? (double)p->q : 2.0) +
@@ -756,7 +772,50 @@ int orc_set_population(orc_pa* p, const int8_t* spins, int64_t R) {
       orc_energy(p->L, p->J, p->spins + (size_t)j * p->N, &p->E[j], &p->M[j]);
   }
   p->R = R;
+  reset_families(p);
   p->n_len = 0;
+  return ORC_OK;
+}
+
+int orc_get_families(const orc_pa* p, uint32_t* fam, int64_t cap,
+                     int64_t* n0) {
+  if (!p || !fam || cap < p->R) return ORC_EINVAL;
+  memcpy(fam, p->fam, (size_t)p->R * sizeof(uint32_t));
+  if (n0) *n0 = p->fam_n0;
+  return ORC_OK;
+}
+
+/* Family statistics of a population of R replicas whose families are
+   numbered 0..n0-1 (fam[j] the family of replica j).  With c_i replicas in
+   family i and nu_i = c_i / R: the number of families with c_i > 0, the
+   largest c_i, the mean square family size rho_t = R sum_i nu_i^2 =
+   sum_i c_i^2 / R, and the entropic family size rho_s = R exp(-S),
+   S = -sum_i nu_i ln nu_i, which equals exp(sum_i c_i ln c_i / R).  Sums in
+   ascending family order. */
+int orc_family_stats(const uint32_t* fam, int64_t R, int64_t n0,
+                     int64_t* families, int64_t* largest, double* rho_t,
+                     double* rho_s) {
+  if (!fam || R < 1 || n0 < 1) return ORC_EINVAL;
+  int64_t* c = (int64_t*)calloc((size_t)n0, sizeof(int64_t));
+  if (!c) return ORC_ENOMEM;
+  for (int64_t j = 0; j < R; ++j) {
+    if ((int64_t)fam[j] >= n0) { free(c); return ORC_EINVAL; }
+    c[fam[j]] += 1;
+  }
+  int64_t nf = 0, big = 0, s2 = 0;
+  double sl = 0.0;
+  for (int64_t i = 0; i < n0; ++i) {
+    if (c[i] == 0) continue;
+    nf += 1;
+    if (c[i] > big) big = c[i];
+    s2 += c[i] * c[i];
+    sl = sl + (double)c[i] * log((double)c[i]);
+  }
+  free(c);
+  if (families) *families = nf;
+  if (largest) *largest = big;
+  if (rho_t) *rho_t = (double)s2 / (double)R;
+  if (rho_s) *rho_s = (ORC_MUTANT == 16) ? exp(sl) : exp(sl / (double)R);
   return ORC_OK;
 }
 

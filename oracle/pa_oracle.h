@@ -121,6 +121,17 @@ int orc_counts(int N, const int32_t* E, int64_t R, int64_t R_t, double dbeta,
 int orc_sweep_replica(int L, const int8_t* J, int8_t* spins, int32_t* E,
                       int32_t* M, double beta, uint64_t seed, uint32_t pop,
                       int step, int t0, int theta, uint32_t slot);
+/* Families (test infrastructure, like the rest of the oracle): the family
+   of each replica is the slot of its ancestor in the population the
+   families start from (the initial one, the heating start or a set
+   population); *n0 receives that population's size.  orc_family_stats
+   summarises a family array: families alive, the largest, rho_t =
+   sum_i c_i^2 / R and rho_s = exp(sum_i c_i ln c_i / R). */
+int orc_get_families(const orc_pa* p, uint32_t* fam, int64_t cap,
+                     int64_t* n0);
+int orc_family_stats(const uint32_t* fam, int64_t R, int64_t n0,
+                     int64_t* families, int64_t* largest, double* rho_t,
+                     double* rho_s);
 /* The same for one replica of the q-state Potts ferromagnet. */
 int orc_sweep_potts_replica(int L, int q, int8_t* spins, int32_t* E,
                             int32_t* M, double beta, uint64_t seed,

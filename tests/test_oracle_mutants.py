@@ -45,6 +45,10 @@ CASES = {
          ["test_oracle_overlap.py::test_bisection_inverts_the_two_level_overlap"]),
     15: ("one factor of beta dropped from the specific heat",
          ["test_oracle_physics.py::test_observables_L4_match_enumeration"]),
+    16: ("the 1/R dropped from the entropic family size",
+         ["test_oracle_families.py::test_family_stats_closed_forms"]),
+    17: ("a copy takes its parent's slot instead of its parent's family",
+         ["test_oracle_families.py::test_families_compose_over_resamplings"]),
 }
 
 
