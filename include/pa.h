@@ -242,17 +242,52 @@ int pa_bisect_dbeta(pa_ctx* c, double target, double beta_f, double* dbeta);
 /* Checkpoint and resume.  pa_save writes the whole state of the context to
    a file: configuration, couplings, beta, step, sweeps made at this step,
    ln Z and the last ln Q, and the population in the canonical layout with
-   its E and M (a fixed 104-byte header "PAPOPv02" first; little-endian).
+   its E, M and families (a fixed 104-byte header "PAPOPv03" first, whose
+   last word is the founding population size; then the +-J couplings,
+   spins [R][L][L] int8, E and M int32 [R], families uint32 [R];
+   little-endian).
    It synchronises; a pending resampling copy is made first.  pa_load
    creates a new context on `stream` (a hipStream_t or NULL) from such a
    file: because every random number is keyed by (step, sweep, slot,
    population), the loaded context continues the run bit for bit as the
    saved one would have.  The file is read and checked completely before
    any device work (magic, sizes, spin values, no trailing bytes), and the
-   stored E and M must equal those of the stored spins; otherwise PA_EIO and
-   *out = NULL.  The copy counts of the last resampling are not saved. */
+   stored E and M must equal those of the stored spins, and every family
+   number must lie below the founding size; otherwise PA_EIO and *out =
+   NULL.  The copy counts of the last resampling are not saved. */
 int pa_save(pa_ctx* c, const char* path);
 int pa_load(const char* path, void* stream, pa_ctx** out);
+
+/* Families (the population-annealing diagnostic that accompanies weighted
+   averaging, with the Machta reference of Sec. 4): every replica belongs
+   to the family of its ancestor in the founding population, i.e. the
+   population made by pa_init, pa_start_heating or pa_set_population, whose
+   replicas found one family each (numbered by their slot).  A resampling
+   copy joins its parent's family; sweeps change no family.
+   pa_get_families copies the family number of each replica (ascending
+   slot) to fam[cap >= R] (fam may be NULL to query only) and the sizes R
+   and n0 (founding population) to *len and *n0; it synchronises.
+   pa_family_summary is host arithmetic on such an array: with c_i members
+   in family i and nu_i = c_i / R, the families with members, the largest,
+   the mean square family size rho_t = R sum nu_i^2 and the entropic family
+   size rho_s = R exp(sum nu_i ln nu_i) (both 1 when no two replicas share a
+   family, R when one family holds them all).  PA_EINVAL for a number
+   >= n0.  pa_family_stats is pa_get_families followed by
+   pa_family_summary.  Single populations only (the batch keeps no
+   families). */
+typedef struct {
+  int64_t R;          /* population size                                     */
+  int64_t n0;         /* size of the founding population                    */
+  int64_t families;   /* families with at least one member                  */
+  int64_t largest;    /* members of the largest family                      */
+  double rho_t;       /* mean square family size  R sum nu_i^2              */
+  double rho_s;       /* entropic family size  R exp(sum nu_i ln nu_i)      */
+} pa_family;
+int pa_get_families(pa_ctx* c, uint32_t* fam, int64_t cap, int64_t* len,
+                    int64_t* n0);
+int pa_family_summary(const uint32_t* fam, int64_t R, int64_t n0,
+                      pa_family* out);
+int pa_family_stats(pa_ctx* c, pa_family* out);
 
 /* The configuration of a context (J is returned as NULL). */
 int pa_get_config(pa_ctx* c, pa_config* out);

@@ -44,6 +44,15 @@ class pa_obs(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class pa_family(C.Structure):
+    _fields_ = [("R", C.c_int64), ("n0", C.c_int64), ("families", C.c_int64),
+                ("largest", C.c_int64), ("rho_t", C.c_double),
+                ("rho_s", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class pa_timing(C.Structure):
     _fields_ = [("ms", C.c_double * 6), ("launches", C.c_int64 * 6),
                 ("bytes", C.c_int64 * 6), ("attempts", C.c_int64)]
@@ -94,6 +103,11 @@ def lib():
             "pa_start_heating": ([P, d], C.c_int),
             "pa_weighted_average": ([i32, P, P, i32, P, C.POINTER(d)],
                                     C.c_int),
+            "pa_get_families": ([P, P, i64, C.POINTER(i64), C.POINTER(i64)],
+                                C.c_int),
+            "pa_family_summary": ([P, i64, i64, C.POINTER(pa_family)],
+                                  C.c_int),
+            "pa_family_stats": ([P, C.POINTER(pa_family)], C.c_int),
             "pa_get_timing": ([P, C.POINTER(pa_timing)], C.c_int),
             "pa_destroy": ([P], None),
             "pa_strerror": ([C.c_int], C.c_char_p),
@@ -288,6 +302,22 @@ class Population:
                                   _ptr(M)), "pa_get_replicas")
         return s, E, M
 
+    def families(self):
+        """(family number of every replica, size of the founding
+        population)."""
+        ln, n0 = C.c_int64(), C.c_int64()
+        _ck(lib().pa_get_families(self._h, None, 0, C.byref(ln), C.byref(n0)),
+            "pa_get_families")
+        f = np.empty(max(ln.value, 1), np.uint32)
+        _ck(lib().pa_get_families(self._h, _ptr(f), ln.value, C.byref(ln),
+                                  C.byref(n0)), "pa_get_families")
+        return f[:ln.value].copy(), n0.value
+
+    def family_stats(self):
+        out = pa_family()
+        _ck(lib().pa_family_stats(self._h, C.byref(out)), "pa_family_stats")
+        return out.as_dict()
+
     def counts(self, cap=None):
         cap = self.R * 4 + 1024 if cap is None else cap
         n = np.empty(max(cap, 1), np.uint32)
@@ -354,6 +384,15 @@ def tune_rows_per_lane(L, layout=PA_INT8, model=PA_FERRO, R=4096, theta=4,
                                     C.byref(best), ms),
         "pa_tune_rows_per_lane")
     return best.value, list(ms)
+
+
+def family_summary(fam, n0):
+    """Family statistics of a family array (pa_family_summary)."""
+    f = np.ascontiguousarray(fam, np.uint32)
+    out = pa_family()
+    _ck(lib().pa_family_summary(_ptr(f), len(f), n0, C.byref(out)),
+        "pa_family_summary")
+    return out.as_dict()
 
 
 def weighted_average(lnZ, values):

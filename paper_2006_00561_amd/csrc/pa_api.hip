@@ -57,6 +57,12 @@ struct pa_ctx {
   uint64_t* tile64 = nullptr;           // systematic law: tile sums of the
   uint64_t* off64 = nullptr;            // fixed-point means and their scan
   uint64_t* cum = nullptr;              // multinomial, residual: interval ends
+  // family of every replica (the slot of its ancestor in the population the
+  // families start from), double buffered: fam[famcur] is current; a
+  // resampling writes the other buffer from the parent map
+  uint32_t* fam[2] = {nullptr, nullptr};
+  int famcur = 0;
+  int64_t fam_n0 = 0;                   // size of the founding population
   // Read-back block, one device->host copy per histogram: the histogram
   // (nbins words, padded to an even count nb2), then scal = [0] sum|M|,
   // [1] sum M^2, [2] unused, [3] energies outside the histogram, all
@@ -297,6 +303,7 @@ void free_all(pa_ctx* c) {
     if (c->spins[b]) (void)hipFree(c->spins[b]);
     if (c->E[b]) (void)hipFree(c->E[b]);
     if (c->M[b]) (void)hipFree(c->M[b]);
+    if (c->fam[b]) (void)hipFree(c->fam[b]);
   }
   void* dev[] = {c->n, c->parent, c->tile_sum, c->tile_off, c->tile64,
                  c->off64, c->cum, c->rb, c->tab, c->jbits};
@@ -309,6 +316,14 @@ void free_all(pa_ctx* c) {
     (void)hipEventDestroy(t.ev1);
   }
   for (auto e : c->pool) (void)hipEventDestroy(e);
+}
+
+// Every replica of the current population founds its own family.
+int reset_families(pa_ctx* c) {
+  CK(launch_iota_u32(c->fam[0], c->R, c->stream));
+  c->famcur = 0;
+  c->fam_n0 = c->R;
+  return PA_OK;
 }
 
 template <typename T>
@@ -431,6 +446,8 @@ int pa_init(const pa_config* cfg, pa_ctx** out) {
   }
   ok = ok && dmalloc(&c->n, (size_t)cap * 4);
   ok = ok && dmalloc(&c->parent, (size_t)cap * 4);
+  ok = ok && dmalloc(&c->fam[0], (size_t)cap * 4);
+  ok = ok && dmalloc(&c->fam[1], (size_t)cap * 4);
   ok = ok && dmalloc(&c->tile_sum, (size_t)c->ntiles_cap * 4);
   ok = ok && dmalloc(&c->tile_off, (size_t)c->ntiles_cap * 4);
   ok = ok && dmalloc(&c->tile64, (size_t)c->ntiles_cap * 8);
@@ -475,6 +492,7 @@ int pa_init(const pa_config* cfg, pa_ctx** out) {
     a.theta = 0;
     rc = run_lattice(c, a, PA_K_INIT);
   }
+  if (rc == PA_OK) rc = reset_families(c);
   if (rc == PA_OK) rc = sync(c);
   if (rc != PA_OK) {
     free_all(c);
@@ -657,8 +675,10 @@ int pa_resample(pa_ctx* c, double beta_next, int64_t* R_new) {
   // (f) parent of every new slot; the copies into the other buffer are left
   // to the next sweep, which reads every new slot from its parent
   e0 = t_begin(c, PA_K_SCATTER);
-  CK(launch_scatter(c->n, c->tile_off, R_old, c->cap, c->parent, c->stream));
+  CK(launch_scatter(c->n, c->tile_off, R_old, c->cap, c->parent,
+                    c->fam[c->famcur], c->fam[c->famcur ^ 1], c->stream));
   t_end(c, PA_K_SCATTER, e0, 4 * R_old, 0, 4, 0);
+  c->famcur ^= 1;
   c->n_len = R_old;
   c->gather_pending = true;
   c->beta = beta_next;
@@ -682,6 +702,8 @@ int pa_start_heating(pa_ctx* c, double beta0) {
   a.init = 2;
   a.theta = 0;
   rc = run_lattice(c, a, PA_K_INIT);
+  if (rc) return rc;
+  rc = reset_families(c);
   if (rc) return rc;
   rc = sync(c);
   if (rc) return rc;
@@ -803,11 +825,38 @@ int pa_set_population(pa_ctx* c, const int8_t* spins, int64_t R) {
   a.theta = 0;
   rc = run_lattice(c, a, PA_K_SWEEP);
   if (rc) return rc;
+  rc = reset_families(c);
+  if (rc) return rc;
   rc = sync(c);
   if (rc) return rc;
   c->hist_valid = false;
   c->n_len = 0;
   return PA_OK;
+}
+
+int pa_get_families(pa_ctx* c, uint32_t* fam, int64_t cap, int64_t* len,
+                    int64_t* n0) {
+  if (!c) return PA_EINVAL;
+  int rc = sync(c);  // the population size, if still on the device
+  if (rc) return rc;
+  if (fam && cap < c->R) return PA_EINVAL;
+  if (fam)
+    CK(hipMemcpy(fam, c->fam[c->famcur], (size_t)c->R * 4,
+                 hipMemcpyDeviceToHost));
+  if (len) *len = c->R;
+  if (n0) *n0 = c->fam_n0;
+  return PA_OK;
+}
+
+int pa_family_stats(pa_ctx* c, pa_family* out) {
+  if (!c || !out) return PA_EINVAL;
+  int rc = sync(c);
+  if (rc) return rc;
+  std::vector<uint32_t> f((size_t)c->R);
+  int64_t len = 0, n0 = 0;
+  rc = pa_get_families(c, f.data(), (int64_t)f.size(), &len, &n0);
+  if (rc) return rc;
+  return pa_family_summary(f.data(), len, n0, out);
 }
 
 int pa_histogram(pa_ctx* c, uint32_t* h, int64_t cap, int32_t* nbins,
@@ -875,7 +924,7 @@ namespace {
 
 // Population file: a fixed header, the couplings (+-J only), then the
 // population in the canonical layout.  Little-endian, as the host.
-constexpr char kMagic[8] = {'P', 'A', 'P', 'O', 'P', 'v', '0', '2'};
+constexpr char kMagic[8] = {'P', 'A', 'P', 'O', 'P', 'v', '0', '3'};
 struct FileHeader {
   char magic[8];
   int64_t R_target, capacity, seed, R;
@@ -883,7 +932,8 @@ struct FileHeader {
   int32_t L, model, layout, rows_per_lane;
   uint32_t population_id;
   int32_t step, sweeps_at_step, resampling;
-  int32_t q, reserved;
+  int32_t q;
+  uint32_t fam_n0;  // size of the founding population of the families
 };
 static_assert(sizeof(FileHeader) == 8 + 4 * 8 + 3 * 8 + 10 * 4,
               "population file header must have no padding");
@@ -911,6 +961,10 @@ int pa_save(pa_ctx* c, const char* path) {
   std::vector<int32_t> E((size_t)R), M((size_t)R);
   rc = pa_get_population(c, spins.data(), E.data(), M.data(), R);
   if (rc) return rc;
+  std::vector<uint32_t> fam((size_t)R);
+  int64_t flen = 0, n0 = 0;
+  rc = pa_get_families(c, fam.data(), R, &flen, &n0);
+  if (rc) return rc;
   FileHeader h{};
   std::memcpy(h.magic, kMagic, 8);
   h.R_target = c->R_t;
@@ -929,6 +983,7 @@ int pa_save(pa_ctx* c, const char* path) {
   h.sweeps_at_step = c->sweeps_at_step;
   h.resampling = c->law;
   h.q = c->q;
+  h.fam_n0 = (uint32_t)n0;
   File f(std::fopen(path, "wb"));
   if (!f.f) return PA_EIO;
   bool ok = f.write(&h, sizeof h);
@@ -936,6 +991,7 @@ int pa_save(pa_ctx* c, const char* path) {
   ok = ok && f.write(spins.data(), spins.size());
   ok = ok && f.write(E.data(), E.size() * 4);
   ok = ok && f.write(M.data(), M.size() * 4);
+  ok = ok && f.write(fam.data(), fam.size() * 4);
   ok = (std::fflush(f.f) == 0) && ok;
   return ok ? PA_OK : PA_EIO;
 }
@@ -956,7 +1012,8 @@ int pa_load(const char* path, void* stream, pa_ctx** out) {
       (h.model == PA_POTTS && (h.q < 2 || h.q > 16)) ||
       h.step < 0 || h.step > 65535 || h.sweeps_at_step < 0 ||
       h.sweeps_at_step > 32767 || !std::isfinite(h.beta) || !(h.beta >= 0.0) ||
-      h.resampling < PA_NEAREST || h.resampling > PA_MULTINOMIAL)
+      h.resampling < PA_NEAREST || h.resampling > PA_MULTINOMIAL ||
+      h.fam_n0 < 1 || (int64_t)h.fam_n0 > h.capacity)
     return PA_EIO;
   const int64_t N = (int64_t)h.L * h.L;
   std::vector<int8_t> J;
@@ -966,9 +1023,12 @@ int pa_load(const char* path, void* stream, pa_ctx** out) {
   }
   std::vector<int8_t> spins((size_t)(h.R * N));
   std::vector<int32_t> E((size_t)h.R), M((size_t)h.R);
+  std::vector<uint32_t> fam((size_t)h.R);
   if (!f.read(spins.data(), spins.size()) || !f.read(E.data(), E.size() * 4) ||
-      !f.read(M.data(), M.size() * 4))
+      !f.read(M.data(), M.size() * 4) || !f.read(fam.data(), fam.size() * 4))
     return PA_EIO;
+  for (uint32_t v : fam)
+    if (v >= h.fam_n0) return PA_EIO;
   char extra;
   if (f.read(&extra, 1)) return PA_EIO;  // trailing bytes: not our file
   for (int8_t v : spins)
@@ -996,10 +1056,15 @@ int pa_load(const char* path, void* stream, pa_ctx** out) {
   std::vector<int32_t> E2((size_t)h.R), M2((size_t)h.R);
   if (!rc) rc = pa_get_population(c, nullptr, E2.data(), M2.data(), h.R);
   if (!rc && (E2 != E || M2 != M)) rc = PA_EIO;
+  if (!rc && hipMemcpy(c->fam[0], fam.data(), fam.size() * 4,
+                       hipMemcpyHostToDevice) != hipSuccess)
+    rc = PA_EDEVICE;
   if (rc) {
     pa_destroy(c);
     return rc;
   }
+  c->famcur = 0;
+  c->fam_n0 = h.fam_n0;
   c->beta = h.beta;
   c->lnZ = h.lnZ;
   c->lnQ_last = h.lnQ_last;

@@ -188,8 +188,10 @@ hipError_t launch_scan(const uint32_t* tile_sum, uint32_t* tile_off,
                        hipStream_t st);
 hipError_t launch_scatter(const uint32_t* n, const uint32_t* tile_off,
                           int64_t R, int64_t cap, uint32_t* parent,
+                          const uint32_t* fam_src, uint32_t* fam_dst,
                           hipStream_t st);
 hipError_t launch_gather(const GatherArgs& a, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
+hipError_t launch_iota_u32(uint32_t* p, int64_t n, hipStream_t st);
 
 }  // namespace pa

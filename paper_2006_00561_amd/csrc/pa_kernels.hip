@@ -19,7 +19,8 @@
 //              plus one partial sum per tile;
 //              clears the histogram of the next step on the way.
 //  k_scan      exclusive scan of the tile sums (single workgroup).
-//  k_scatter   per-tile scan of the counts -> parent index of every new slot.
+//  k_scatter   per-tile scan of the counts -> parent index of every new slot
+//              (and its family, the parent's family).
 //  k_gather    copy of every parent's lattice, E and M into its new slots of
 //              the second buffer (one wave per slot for replicas of 1 KB and
 //              more, else a flat array of 16-byte units with four in flight
@@ -324,15 +325,21 @@ __global__ __launch_bounds__(1024) void k_scan(const uint32_t* tile_sum,
 __global__ __launch_bounds__(256) void k_scatter(const uint32_t* n,
                                                  const uint32_t* tile_off,
                                                  int64_t R, int64_t cap,
-                                                 uint32_t* parent) {
+                                                 uint32_t* parent,
+                                                 const uint32_t* fam_src,
+                                                 uint32_t* fam_dst) {
   __shared__ uint32_t lds[8];
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t nj = (j < R) ? n[j] : 0u;
   uint32_t total;
   const uint32_t ex = block_excl_scan(nj, lds, &total);
   const int64_t o = (int64_t)tile_off[blockIdx.x] + ex;
+  const uint32_t fj = (nj && fam_src) ? fam_src[j] : 0u;
   for (uint32_t t = 0; t < nj; ++t)
-    if (o + t < cap) parent[o + t] = (uint32_t)j;
+    if (o + t < cap) {
+      parent[o + t] = (uint32_t)j;
+      if (fam_dst) fam_dst[o + t] = fj;
+    }
 }
 
 // ---------------------------------------------------------------- gather
@@ -401,6 +408,13 @@ __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     p[i] = v;
+}
+
+// p[i] = i: every replica founds its own family.
+__global__ void k_iota_u32(uint32_t* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = (uint32_t)i;
 }
 
 // --------------------------------------------------------------- launchers
@@ -499,10 +513,11 @@ hipError_t launch_scan(const uint32_t* tile_sum, uint32_t* tile_off,
 
 hipError_t launch_scatter(const uint32_t* n, const uint32_t* tile_off,
                           int64_t R, int64_t cap, uint32_t* parent,
+                          const uint32_t* fam_src, uint32_t* fam_dst,
                           hipStream_t st) {
   const int64_t blocks = (R + 255) / 256;
   hipLaunchKernelGGL(k_scatter, dim3((unsigned)blocks), dim3(256), 0, st, n,
-                     tile_off, R, cap, parent);
+                     tile_off, R, cap, parent, fam_src, fam_dst);
   return hipGetLastError();
 }
 
@@ -527,6 +542,14 @@ hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st) {
   if (blocks < 1) blocks = 1;
   if (blocks > 1024) blocks = 1024;
   hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_iota_u32(uint32_t* p, int64_t n, hipStream_t st) {
+  int64_t blocks = (n + 255) / 256;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(k_iota_u32, dim3((unsigned)blocks), dim3(256), 0, st, p, n);
   return hipGetLastError();
 }
 

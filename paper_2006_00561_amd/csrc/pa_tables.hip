@@ -265,3 +265,38 @@ extern "C" int pa_weighted_average(int32_t M, const double* lnZ,
   if (lnZ_out) *lnZ_out = mx + std::log(s / (double)M);
   return PA_OK;
 }
+
+// Family statistics (the diagnostic that accompanies weighted averaging in
+// population annealing): c_i members in family i of n0, R = sum c_i,
+// nu_i = c_i / R.  The mean square family size R sum nu_i^2 is
+// sum c_i^2 / R (the square sum kept exact in 128 bits); the entropic
+// family size R exp(sum nu_i ln nu_i) is exp(sum c_i ln c_i / R).  Both
+// equal 1 when every family has one member and R when one family holds
+// the whole population.  Sums run over ascending family number.
+extern "C" int pa_family_summary(const uint32_t* fam, int64_t R, int64_t n0,
+                                 pa_family* out) {
+  if (!fam || !out || R < 1 || n0 < 1 || n0 > (1ll << 32)) return PA_EINVAL;
+  std::vector<int64_t> cnt((size_t)n0, 0);
+  for (int64_t j = 0; j < R; ++j) {
+    if ((int64_t)fam[j] >= n0) return PA_EINVAL;
+    cnt[fam[j]] += 1;
+  }
+  unsigned __int128 sq = 0;
+  double cl = 0.0;
+  int64_t alive = 0, big = 0;
+  for (int64_t i = 0; i < n0; ++i) {
+    const int64_t v = cnt[(size_t)i];
+    if (v == 0) continue;
+    ++alive;
+    big = v > big ? v : big;
+    sq += (unsigned __int128)v * (unsigned __int128)v;
+    cl = cl + (double)v * std::log((double)v);
+  }
+  out->R = R;
+  out->n0 = n0;
+  out->families = alive;
+  out->largest = big;
+  out->rho_t = (double)sq / (double)R;
+  out->rho_s = std::exp(cl / (double)R);
+  return PA_OK;
+}

@@ -69,20 +69,24 @@ def test_product_path_does_not_touch_the_oracle():
                 assert "oracle" not in src.lower(), f
 
 
-def _pop_file(path, L=4, R=2, spins=None, extra=b"", magic=b"PAPOPv02"):
+def _pop_file(path, L=4, R=2, spins=None, extra=b"", magic=b"PAPOPv03",
+              fam=None, n0=None):
     """A population file written from the documented layout: 104-byte
-    header, spins [R][L][L] int8, E and M int32."""
+    header (its last word the founding population size), spins [R][L][L]
+    int8, E and M int32, families uint32."""
     import struct
     N = L * L
-    hdr = magic + struct.pack("<qqqqdddiiiiIiiiii", R, R + 100, 1, R, 0.25,
+    n0 = R if n0 is None else n0
+    hdr = magic + struct.pack("<qqqqdddiiiiIiiiiI", R, R + 100, 1, R, 0.25,
                               N * 0.6931471805599453, 0.0, L, 0, 0, 1, 0, 3,
-                              0, 0, 0, 0)
+                              0, 0, 0, n0)
     assert len(hdr) == 104
     s = bytes([1] * (R * N)) if spins is None else spins
     E = struct.pack("<%di" % R, *([-2 * N] * R))
     M = struct.pack("<%di" % R, *([N] * R))
+    F = struct.pack("<%dI" % R, *(range(R) if fam is None else fam))
     with open(path, "wb") as f:
-        f.write(hdr + s + E + M + extra)
+        f.write(hdr + s + E + M + F + extra)
 
 
 def test_load_rejects_bad_files_before_any_device_work(tmp_path):
@@ -92,7 +96,10 @@ def test_load_rejects_bad_files_before_any_device_work(tmp_path):
     missing = str(tmp_path / "missing.pa")
     assert lib.pa_load(missing.encode(), None, C.byref(h)) == b.PA_EIO
     bad = [("magic", dict(magic=b"NOTAPOP!")),
+           ("older format", dict(magic=b"PAPOPv02")),
            ("spin value", dict(spins=bytes([1] * 31 + [0]))),
+           ("family number", dict(fam=[0, 2])),
+           ("founding size", dict(n0=0)),
            ("trailing bytes", dict(extra=b"\x00"))]
     for name, kw in bad:
         p = str(tmp_path / (name.replace(" ", "_") + ".pa"))

@@ -49,6 +49,15 @@ def _cmp_state(g, o, tag):
     zg, qg = g.free_energy()
     zo, qo = o.free_energy()
     assert _close(zg, zo) and _close(qg, qo), (tag, zg, zo, qg, qo)
+    # families: bit-exact, and their statistics to the floating-point bar
+    fg, n0g = g.families()
+    fo, n0o = o.families()
+    assert n0g == n0o and np.array_equal(fg, fo), tag
+    sg_, so_ = g.family_stats(), oracle.family_stats(fo, n0o)
+    assert (sg_["families"], sg_["largest"]) == (so_["families"],
+                                                 so_["largest"]), tag
+    assert _close(sg_["rho_t"], so_["rho_t"]), tag
+    assert _close(sg_["rho_s"], so_["rho_s"]), tag
 
 
 def _parity_run(pa, L, R, steps, theta, beta_f, seed=1, pop=0, J=None,
@@ -273,18 +282,22 @@ def test_full_size_sampled(pa, name, steps, sample):
     assert np.array_equal(Mg, Mo)
     o.close()
     zlast = g.free_energy()[0]
+    fam, n0 = g.families()
+    assert n0 == R and np.array_equal(fam, np.arange(R))
     for i in range(1, steps + 1):
         b = sched[i - 1]
         E, M = g.energies()
         n_o, Rn_o, lnQ_o = oracle.counts(L * L, E, R, b - g.beta, c["seed"],
                                          0, i)
         parent = np.repeat(np.arange(len(E)), n_o)
+        fam = fam[parent]  # every copy joins its parent's family
         slots = np.sort(rng.choice(Rn_o, size=sample, replace=False))
         s_pre, E_pre, M_pre = g.replicas(parent[slots])
         g.resample(b, wait=False)
         g.sweep(b, theta)
         assert g.state()[0] == Rn_o
         assert np.array_equal(g.counts(), n_o)
+        assert np.array_equal(g.families()[0], fam)
         z, dq = g.free_energy()
         assert _close(dq, lnQ_o) and _close(z, zlast + lnQ_o)
         zlast = z
