@@ -99,8 +99,10 @@ def gather_copy(binding, cfg, stream, reps=5):
             "frac_hbm": gbps / HBM_PEAK_GBPS}
 
 
-def run_anneal(binding, cfg, stream, timing=None, rows_per_lane=0):
-    """One full anneal; timing: None, or the kernel classes to time."""
+def run_anneal(binding, cfg, stream, timing=None, rows_per_lane=0,
+               families=None):
+    """One full anneal; timing: None, or the kernel classes to time;
+    families: a dict that receives the final family statistics."""
     layout = binding.PA_BITS if cfg["layout"] == "bits" else binding.PA_INT8
     L, R, theta = cfg["L"], cfg["R"], cfg["theta"]
     g = binding.Population(L, R, seed=cfg["seed"], layout=layout,
@@ -116,6 +118,8 @@ def run_anneal(binding, cfg, stream, timing=None, rows_per_lane=0):
         attempts += g.observables()["R"] * L * L * theta
     lnZ, _ = g.free_energy()
     t = g.timing() if timing else None
+    if families is not None:
+        families.update(g.family_stats())
     g.close()
     return attempts, lnZ, t
 
@@ -520,8 +524,9 @@ def main():
         sweep_avg_ms * 1e-3) / 1e12
     peak = VALU_OPS_PER_S / 1e12
     # every kernel class timed, on one more anneal after the timed region
+    fam = {}
     _, _, tall = run_anneal(binding, cfg, stream, timing=binding.KERNEL_CLASSES,
-                            rows_per_lane=args.rows_per_lane)
+                            rows_per_lane=args.rows_per_lane, families=fam)
     res_k = ("hist", "counts", "scatter", "gather")
     res_ms = sum(tall[k]["ms"] for k in res_k)
     res_bytes = sum(tall[k]["bytes"] for k in res_k)
@@ -589,6 +594,8 @@ def main():
         },
         "wall_time_to_beta_f_s": dt / args.steps,
         "lnZ_final": lnZs[-1],
+        # descendants of the initial replicas at beta_f (the untimed anneal)
+        "families_final": fam,
     }
     if not args.no_batched:
         out["batched"] = bench_batched(binding, stream,
