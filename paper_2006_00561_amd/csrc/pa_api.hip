@@ -375,7 +375,7 @@ const char* pa_strerror(int code) {
   }
 }
 
-int pa_init(const pa_config* cfg, pa_ctx** out) {
+int pa_init(const pa_config* cfg, pa_ctx** out) try {
   if (!out) return PA_EINVAL;
   *out = nullptr;
   if (!cfg) return PA_EINVAL;
@@ -505,16 +505,21 @@ int pa_init(const pa_config* cfg, pa_ctx** out) {
   c->lnQ_last = 0.0;
   *out = c;
   return PA_OK;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
 
-void pa_destroy(pa_ctx* c) {
+void pa_destroy(pa_ctx* c) try {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
   free_all(c);
   delete c;
+} catch (...) {
 }
 
-int pa_sweep(pa_ctx* c, double beta, int32_t theta) {
+int pa_sweep(pa_ctx* c, double beta, int32_t theta) try {
   if (!c || theta < 0 || !std::isfinite(beta)) return PA_EINVAL;
   if (beta != c->beta) return PA_ESTATE;
   if (c->sweeps_at_step + theta > 32767) return PA_EINVAL;
@@ -541,9 +546,13 @@ int pa_sweep(pa_ctx* c, double beta, int32_t theta) {
   c->sweeps_at_step += theta;
   c->hist_valid = false;
   return PA_OK;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
 
-int pa_resample(pa_ctx* c, double beta_next, int64_t* R_new) {
+int pa_resample(pa_ctx* c, double beta_next, int64_t* R_new) try {
   // cooling (beta_next >= beta) or heating (beta_next < beta), beta >= 0
   if (!c || !std::isfinite(beta_next) || !(beta_next >= 0.0))
     return PA_EINVAL;
@@ -688,9 +697,13 @@ int pa_resample(pa_ctx* c, double beta_next, int64_t* R_new) {
   c->lnZ = c->lnZ + lnQ;  // Eq. Free-En, read with the logarithm
   c->hist_valid = false;
   return PA_OK;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
 
-int pa_start_heating(pa_ctx* c, double beta0) {
+int pa_start_heating(pa_ctx* c, double beta0) try {
   if (!c || !std::isfinite(beta0) || !(beta0 > 0.0)) return PA_EINVAL;
   if (c->model == PA_PMJ) return PA_EINVAL;
   if (c->step != 0) return PA_ESTATE;
@@ -715,25 +728,37 @@ int pa_start_heating(pa_ctx* c, double beta0) {
   c->n_len = 0;
   c->hist_valid = false;
   return PA_OK;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
 
-int pa_observables(pa_ctx* c, pa_obs* o) {
+int pa_observables(pa_ctx* c, pa_obs* o) try {
   if (!c || !o) return PA_EINVAL;
   int rc = compute_hist(c);
   if (rc) return rc;
   observables_from_hist(c->h_hist, c->nbins, c->hshift, c->N, c->R, c->beta,
                         (int64_t)c->h_scal[0], (int64_t)c->h_scal[1], o);
   return PA_OK;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
 
-int pa_free_energy(pa_ctx* c, double* lnZ, double* lnQ_last) {
+int pa_free_energy(pa_ctx* c, double* lnZ, double* lnQ_last) try {
   if (!c) return PA_EINVAL;
   if (lnZ) *lnZ = c->lnZ;
   if (lnQ_last) *lnQ_last = c->lnQ_last;
   return PA_OK;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
 
-int pa_state(pa_ctx* c, int64_t* R, double* beta, int32_t* step) {
+int pa_state(pa_ctx* c, int64_t* R, double* beta, int32_t* step) try {
   if (!c) return PA_EINVAL;
   if (R && c->R_pending) {
     const int rc = sync(c);
@@ -743,10 +768,14 @@ int pa_state(pa_ctx* c, int64_t* R, double* beta, int32_t* step) {
   if (beta) *beta = c->beta;
   if (step) *step = c->step;
   return PA_OK;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
 
 int pa_get_population(pa_ctx* c, int8_t* spins, int32_t* E, int32_t* M,
-                      int64_t cap) {
+                      int64_t cap) try {
   if (!c) return PA_EINVAL;
   int rc = sync(c);  // the population size, if still on the device
   if (rc) return rc;
@@ -770,10 +799,14 @@ int pa_get_population(pa_ctx* c, int8_t* spins, int32_t* E, int32_t* M,
   if (E) CK(hipMemcpy(E, c->E[c->cur], (size_t)c->R * 4, hipMemcpyDeviceToHost));
   if (M) CK(hipMemcpy(M, c->M[c->cur], (size_t)c->R * 4, hipMemcpyDeviceToHost));
   return PA_OK;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
 
 int pa_get_replicas(pa_ctx* c, const int64_t* slots, int64_t k, int8_t* spins,
-                    int32_t* E, int32_t* M) {
+                    int32_t* E, int32_t* M) try {
   if (!c || (k > 0 && !slots) || k < 0) return PA_EINVAL;
   int rc = sync(c);  // the population size, if still on the device
   if (rc) return rc;
@@ -795,9 +828,13 @@ int pa_get_replicas(pa_ctx* c, const int64_t* slots, int64_t k, int8_t* spins,
     if (M) CK(hipMemcpy(M + i, c->M[c->cur] + j, 4, hipMemcpyDeviceToHost));
   }
   return PA_OK;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
 
-int pa_get_counts(pa_ctx* c, uint32_t* n, int64_t cap, int64_t* len) {
+int pa_get_counts(pa_ctx* c, uint32_t* n, int64_t cap, int64_t* len) try {
   if (!c || (c->n_len > 0 && !n) || cap < c->n_len) return PA_EINVAL;
   int rc = sync(c);
   if (rc) return rc;
@@ -805,9 +842,13 @@ int pa_get_counts(pa_ctx* c, uint32_t* n, int64_t cap, int64_t* len) {
     CK(hipMemcpy(n, c->n, (size_t)c->n_len * 4, hipMemcpyDeviceToHost));
   if (len) *len = c->n_len;
   return PA_OK;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
 
-int pa_set_population(pa_ctx* c, const int8_t* spins, int64_t R) {
+int pa_set_population(pa_ctx* c, const int8_t* spins, int64_t R) try {
   if (!c || !spins || R < 1 || R > c->cap) return PA_EINVAL;
   for (int64_t i = 0; i < R * c->N; ++i)
     if (c->q ? (spins[i] < 0 || spins[i] >= c->q)
@@ -832,10 +873,14 @@ int pa_set_population(pa_ctx* c, const int8_t* spins, int64_t R) {
   c->hist_valid = false;
   c->n_len = 0;
   return PA_OK;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
 
 int pa_get_families(pa_ctx* c, uint32_t* fam, int64_t cap, int64_t* len,
-                    int64_t* n0) {
+                    int64_t* n0) try {
   if (!c) return PA_EINVAL;
   int rc = sync(c);  // the population size, if still on the device
   if (rc) return rc;
@@ -846,9 +891,13 @@ int pa_get_families(pa_ctx* c, uint32_t* fam, int64_t cap, int64_t* len,
   if (len) *len = c->R;
   if (n0) *n0 = c->fam_n0;
   return PA_OK;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
 
-int pa_family_stats(pa_ctx* c, pa_family* out) {
+int pa_family_stats(pa_ctx* c, pa_family* out) try {
   if (!c || !out) return PA_EINVAL;
   int rc = sync(c);
   if (rc) return rc;
@@ -857,10 +906,14 @@ int pa_family_stats(pa_ctx* c, pa_family* out) {
   rc = pa_get_families(c, f.data(), (int64_t)f.size(), &len, &n0);
   if (rc) return rc;
   return pa_family_summary(f.data(), len, n0, out);
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
 
 int pa_histogram(pa_ctx* c, uint32_t* h, int64_t cap, int32_t* nbins,
-                 int32_t* step) {
+                 int32_t* step) try {
   if (!c || (h && cap < c->nbins)) return PA_EINVAL;
   int rc = compute_hist(c);
   if (rc) return rc;
@@ -868,18 +921,26 @@ int pa_histogram(pa_ctx* c, uint32_t* h, int64_t cap, int32_t* nbins,
   if (nbins) *nbins = c->nbins;
   if (step) *step = 1 << c->hshift;
   return PA_OK;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
 
-int pa_overlap(pa_ctx* c, double dbeta, double* alpha) {
+int pa_overlap(pa_ctx* c, double dbeta, double* alpha) try {
   if (!c || !alpha || !std::isfinite(dbeta) || dbeta < 0.0) return PA_EINVAL;
   int rc = compute_hist(c);
   if (rc) return rc;
   *alpha = overlap_from_hist(c->h_hist, c->nbins, c->hshift, c->N, c->R,
                              dbeta);
   return PA_OK;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
 
-int pa_bisect_dbeta(pa_ctx* c, double target, double beta_f, double* dbeta) {
+int pa_bisect_dbeta(pa_ctx* c, double target, double beta_f, double* dbeta) try {
   if (!c || !dbeta || !(target > 0.0 && target <= 1.0) ||
       !std::isfinite(beta_f))
     return PA_EINVAL;
@@ -888,18 +949,26 @@ int pa_bisect_dbeta(pa_ctx* c, double target, double beta_f, double* dbeta) {
   *dbeta = bisect_from_hist(c->h_hist, c->nbins, c->hshift, c->N, c->R,
                             target, beta_f - c->beta);
   return PA_OK;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
 
-int pa_set_timing(pa_ctx* c, int32_t classes) {
+int pa_set_timing(pa_ctx* c, int32_t classes) try {
   if (!c) return PA_EINVAL;
   int rc = sync(c);
   if (rc) return rc;
   c->timing = (classes == PA_TIMING_ALL) ? 0x3Fu : ((uint32_t)classes & 0x3Fu);
   if (c->timing) c->acc = pa_timing{};
   return PA_OK;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
 
-int pa_get_config(pa_ctx* c, pa_config* out) {
+int pa_get_config(pa_ctx* c, pa_config* out) try {
   if (!c || !out) return PA_EINVAL;
   pa_config k{};
   k.L = c->L;
@@ -916,6 +985,10 @@ int pa_get_config(pa_ctx* c, pa_config* out) {
   k.q = c->q;
   *out = k;
   return PA_OK;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
 
 }  // extern "C"
@@ -952,7 +1025,7 @@ struct File {
 
 extern "C" {
 
-int pa_save(pa_ctx* c, const char* path) {
+int pa_save(pa_ctx* c, const char* path) try {
   if (!c || !path) return PA_EINVAL;
   int rc = sync(c);  // the population size, if still on the device
   if (rc) return rc;
@@ -994,9 +1067,13 @@ int pa_save(pa_ctx* c, const char* path) {
   ok = ok && f.write(fam.data(), fam.size() * 4);
   ok = (std::fflush(f.f) == 0) && ok;
   return ok ? PA_OK : PA_EIO;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
 
-int pa_load(const char* path, void* stream, pa_ctx** out) {
+int pa_load(const char* path, void* stream, pa_ctx** out) try {
   if (!out) return PA_EINVAL;
   *out = nullptr;
   if (!path) return PA_EINVAL;
@@ -1074,14 +1151,22 @@ int pa_load(const char* path, void* stream, pa_ctx** out) {
   c->hist_valid = false;
   *out = c;
   return PA_OK;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
 
-int pa_get_timing(pa_ctx* c, pa_timing* out) {
+int pa_get_timing(pa_ctx* c, pa_timing* out) try {
   if (!c || !out) return PA_EINVAL;
   int rc = sync(c);
   if (rc) return rc;
   *out = c->acc;
   return PA_OK;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
 
 }  // extern "C"

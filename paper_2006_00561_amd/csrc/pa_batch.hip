@@ -895,7 +895,7 @@ extern "C" {
 
 int pa_tune_rows_per_lane(int32_t L, int32_t layout, int32_t model,
                           int64_t R, int32_t theta, void* stream,
-                          int32_t* best, float* ms) {
+                          int32_t* best, float* ms) try {
   if (!best || L < 4 || L > 128 || (L & 1) || R < 1 || theta < 1)
     return PA_EINVAL;
   const int cand[4] = {1, 2, 3, 4};
@@ -938,10 +938,14 @@ int pa_tune_rows_per_lane(int32_t L, int32_t layout, int32_t model,
   if (ms)
     for (int k = 0; k < 4; ++k) ms[k] = t[k];
   return PA_OK;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
 
 int pa_batch_init(const pa_config* cfgs, int32_t n, void* stream,
-                  int32_t flags, pa_batch** out) {
+                  int32_t flags, pa_batch** out) try {
   if (!out) return PA_EINVAL;
   *out = nullptr;
   if (!cfgs || n < 1 || n > 4096) return PA_EINVAL;
@@ -1171,13 +1175,18 @@ int pa_batch_init(const pa_config* cfgs, int32_t n, void* stream,
   }
   *out = b;
   return PA_OK;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
 
-void pa_batch_destroy(pa_batch* b) {
+void pa_batch_destroy(pa_batch* b) try {
   if (!b) return;
   (void)hipStreamSynchronize(b->stream);
   free_batch(b);
   delete b;
+} catch (...) {
 }
 
 static int batch_run(pa_batch* b, int steps, int use_graph) {
@@ -1227,7 +1236,7 @@ static int batch_run(pa_batch* b, int steps, int use_graph) {
 }
 
 int pa_batch_run(pa_batch* b, int32_t steps, const double* betas,
-                 int32_t theta, int32_t use_graph) {
+                 int32_t theta, int32_t use_graph) try {
   if (!b || steps < 1 || !betas || theta < 0) return PA_EINVAL;
   for (int64_t i = 0; i < (int64_t)steps * b->n; ++i)
     if (!std::isfinite(betas[i])) return PA_EINVAL;
@@ -1237,11 +1246,15 @@ int pa_batch_run(pa_batch* b, int32_t steps, const double* betas,
   b->sched_steps = steps;
   b->theta = theta;
   return batch_run(b, steps, use_graph);
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
 
 int pa_batch_run_adaptive(pa_batch* b, double target, double beta_f,
                           int32_t max_steps, int32_t theta, int32_t use_graph,
-                          int32_t* steps_taken) {
+                          int32_t* steps_taken) try {
   if (!b || !(target > 0.0 && target <= 1.0) || !std::isfinite(beta_f) ||
       max_steps < 1 || theta < 0)
     return PA_EINVAL;
@@ -1258,12 +1271,16 @@ int pa_batch_run_adaptive(pa_batch* b, double target, double beta_f,
     *steps_taken = mx;
   }
   return rc;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
 
 int pa_batch_run_learned(pa_batch* b, pa_mlp* m, double target, double tol,
                          double beta_f, int32_t max_steps, int32_t theta,
                          int32_t use_graph, int32_t* steps_taken,
-                         int64_t* src_counts) {
+                         int64_t* src_counts) try {
   if (!b || !m || !(target > 0.0 && target <= 1.0) || !(tol >= 0.0) ||
       !std::isfinite(beta_f) || max_steps < 1 || theta < 0)
     return PA_EINVAL;
@@ -1284,21 +1301,29 @@ int pa_batch_run_learned(pa_batch* b, pa_mlp* m, double target, double tol,
   if (src_counts)
     for (int k = 0; k < 5; ++k) src_counts[k] = b->src_count[k];
   return rc;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
 
 int pa_batch_host_stats(pa_batch* b, double* host_ms, int64_t* overlap_evals,
-                        int64_t* src_counts) {
+                        int64_t* src_counts) try {
   if (!b) return PA_EINVAL;
   if (host_ms) *host_ms = b->host_ms;
   if (overlap_evals) *overlap_evals = b->overlap_evals;
   if (src_counts)
     for (int k = 0; k < 5; ++k) src_counts[k] = b->src_count[k];
   return PA_OK;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
 
 int pa_batch_decisions(pa_batch* b, int32_t p, float* feat, double* dbeta,
                        int32_t* src, float* proposal, int32_t cap,
-                       int32_t* len) {
+                       int32_t* len) try {
   if (!b || p < 0 || p >= b->n || cap < 0) return PA_EINVAL;
   const int steps = (int)(b->dec_src.size() / b->n);
   int k = 0;
@@ -1315,10 +1340,14 @@ int pa_batch_decisions(pa_batch* b, int32_t p, float* feat, double* dbeta,
   }
   if (len) *len = k;
   return PA_OK;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
 
 int pa_batch_state(pa_batch* b, int32_t p, int64_t* R, double* beta,
-                   int32_t* step, double* lnZ) {
+                   int32_t* step, double* lnZ) try {
   if (!b || p < 0 || p >= b->n) return PA_EINVAL;
   BK(hipStreamSynchronize(b->stream));
   if (R) *R = rb_R(b)[p];
@@ -1326,10 +1355,14 @@ int pa_batch_state(pa_batch* b, int32_t p, int64_t* R, double* beta,
   if (step) *step = b->pops[p].step;
   if (lnZ) *lnZ = b->pops[p].lnZ;
   return PA_OK;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
 
 int pa_batch_trajectory(pa_batch* b, int32_t p, pa_obs* obs, double* lnZ,
-                        int32_t cap, int32_t* len) {
+                        int32_t cap, int32_t* len) try {
   if (!b || p < 0 || p >= b->n) return PA_EINVAL;
   const int steps = b->n ? (int)(b->traj.size() / b->n) : 0;
   int k = 0;
@@ -1342,10 +1375,14 @@ int pa_batch_trajectory(pa_batch* b, int32_t p, pa_obs* obs, double* lnZ,
   }
   if (len) *len = k;
   return PA_OK;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
 
 int pa_batch_get_population(pa_batch* b, int32_t p, int8_t* spins, int32_t* E,
-                            int32_t* M, int64_t cap) {
+                            int32_t* M, int64_t cap) try {
   if (!b || p < 0 || p >= b->n) return PA_EINVAL;
   BK(hipStreamSynchronize(b->stream));
   const BatchPop& d = b->pops[p].d;
@@ -1374,15 +1411,23 @@ int pa_batch_get_population(pa_batch* b, int32_t p, int8_t* spins, int32_t* E,
   if (E) BK(hipMemcpy(E, d.E[cur], (size_t)R * 4, hipMemcpyDeviceToHost));
   if (M) BK(hipMemcpy(M, d.M[cur], (size_t)R * 4, hipMemcpyDeviceToHost));
   return PA_OK;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
 
-int pa_batch_set_sweep_blocks(pa_batch* b, int32_t blocks, int32_t chunk) {
+int pa_batch_set_sweep_blocks(pa_batch* b, int32_t blocks, int32_t chunk) try {
   if (!b || blocks < 1 || blocks > 65535 || chunk < 1 || chunk > 1024)
     return PA_EINVAL;
   drop_graph(b);
   b->sweep_blocks = blocks;
   b->sweep_chunk = chunk;
   return PA_OK;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
 
 }  // extern "C"

@@ -274,7 +274,7 @@ uint64_t sm64(uint64_t* s) {
 extern "C" {
 
 int pa_mlp_create(int32_t n_in, int32_t width, int32_t depth, uint64_t seed,
-                  void* stream, pa_mlp** out) {
+                  void* stream, pa_mlp** out) try {
   if (!out) return PA_EINVAL;
   *out = nullptr;
   if (n_in < 1 || n_in > 64 || width < 1 || width > 1024 || depth < 1 ||
@@ -339,9 +339,13 @@ int pa_mlp_create(int32_t n_in, int32_t width, int32_t depth, uint64_t seed,
   }
   *out = m;
   return PA_OK;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
 
-void pa_mlp_destroy(pa_mlp* m) {
+void pa_mlp_destroy(pa_mlp* m) try {
   if (!m) return;
   (void)hipStreamSynchronize(m->stream);
   mlp_free_scratch(m);
@@ -349,33 +353,46 @@ void pa_mlp_destroy(pa_mlp* m) {
   for (void* q : p)
     if (q) (void)hipFree(q);
   delete m;
+} catch (...) {
 }
 
-int pa_mlp_n_params(pa_mlp* m, int64_t* n) {
+int pa_mlp_n_params(pa_mlp* m, int64_t* n) try {
   if (!m || !n) return PA_EINVAL;
   *n = m->n_params;
   return PA_OK;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
 
-int pa_mlp_set_params(pa_mlp* m, const float* p, int64_t n) {
+int pa_mlp_set_params(pa_mlp* m, const float* p, int64_t n) try {
   if (!m || !p || n != m->n_params) return PA_EINVAL;
   MK(hipMemcpyAsync(m->d_params, p, (size_t)n * 4, hipMemcpyHostToDevice,
                     m->stream));
   MK(hipStreamSynchronize(m->stream));
   m->adam_t = 0;
   return PA_OK;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
 
-int pa_mlp_get_params(pa_mlp* m, float* p, int64_t n) {
+int pa_mlp_get_params(pa_mlp* m, float* p, int64_t n) try {
   if (!m || !p || n != m->n_params) return PA_EINVAL;
   MK(hipMemcpyAsync(p, m->d_params, (size_t)n * 4, hipMemcpyDeviceToHost,
                     m->stream));
   MK(hipStreamSynchronize(m->stream));
   return PA_OK;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
 
 int pa_mlp_set_norm(pa_mlp* m, const float* mu, const float* sigma,
-                    float mu_y, float sigma_y) {
+                    float mu_y, float sigma_y) try {
   if (!m || !mu || !sigma || !(sigma_y > 0.0f)) return PA_EINVAL;
   for (int i = 0; i < m->n_in; ++i) {
     if (!(sigma[i] > 0.0f)) return PA_EINVAL;
@@ -389,9 +406,13 @@ int pa_mlp_set_norm(pa_mlp* m, const float* mu, const float* sigma,
   MK(hipStreamSynchronize(m->stream));
   bump(m);
   return PA_OK;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
 
-int pa_mlp_forward(pa_mlp* m, const float* X, int32_t B, float* y) {
+int pa_mlp_forward(pa_mlp* m, const float* X, int32_t B, float* y) try {
   if (!m || !X || !y || B < 1) return PA_EINVAL;
   int rc = ensure_batch(m, B);
   if (rc) return rc;
@@ -406,10 +427,14 @@ int pa_mlp_forward(pa_mlp* m, const float* X, int32_t B, float* y) {
   const float mu_y = m->h_norm[2 * m->n_in], sy = m->h_norm[2 * m->n_in + 1];
   for (int s = 0; s < B; ++s) y[s] = mu_y + sy * z[(size_t)s];
   return PA_OK;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
 
 int pa_mlp_loss_grad(pa_mlp* m, const float* X, const float* T, int32_t B,
-                     float* loss, float* grad) {
+                     float* loss, float* grad) try {
   if (!m || !X || !T || B < 1) return PA_EINVAL;
   int rc = ensure_batch(m, B);
   if (rc) return rc;
@@ -437,11 +462,15 @@ int pa_mlp_loss_grad(pa_mlp* m, const float* X, const float* T, int32_t B,
     *loss = (float)(acc / B);
   }
   return PA_OK;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
 
 int pa_mlp_train(pa_mlp* m, const float* X, const float* T, int64_t n,
                  int32_t batch, int32_t iters, float lr, uint64_t seed,
-                 float* loss_out) {
+                 float* loss_out) try {
   if (!m || !X || !T || n < 1 || batch < 1 || iters < 1 || !(lr > 0.0f))
     return PA_EINVAL;
   const int B = (int)std::min<int64_t>(batch, n);
@@ -515,6 +544,10 @@ int pa_mlp_train(pa_mlp* m, const float* X, const float* T, int64_t n,
   (void)hipFree(dTall);
   (void)hipFree(dIdx);
   return rc;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
 
 }  // extern "C"

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
+#include <new>
 #include <vector>
 
 #include "pa.h"
@@ -242,7 +243,7 @@ extern "C" const char* pa_last_error(void) { return pa::last_error(); }
 // w_m = exp(ln Z_m - max ln Z) / sum of those, summed in increasing m.
 extern "C" int pa_weighted_average(int32_t M, const double* lnZ,
                                    const double* values, int32_t k,
-                                   double* out, double* lnZ_out) {
+                                   double* out, double* lnZ_out) try {
   if (M < 1 || k < 0 || !lnZ || (k > 0 && (!values || !out))) return PA_EINVAL;
   double mx = lnZ[0];
   for (int32_t m = 0; m < M; ++m) {
@@ -264,6 +265,10 @@ extern "C" int pa_weighted_average(int32_t M, const double* lnZ,
   // ln of the mean of the Z_m: the combined estimate of ln Z
   if (lnZ_out) *lnZ_out = mx + std::log(s / (double)M);
   return PA_OK;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
 
 // Family statistics (the diagnostic that accompanies weighted averaging in
@@ -274,7 +279,7 @@ extern "C" int pa_weighted_average(int32_t M, const double* lnZ,
 // equal 1 when every family has one member and R when one family holds
 // the whole population.  Sums run over ascending family number.
 extern "C" int pa_family_summary(const uint32_t* fam, int64_t R, int64_t n0,
-                                 pa_family* out) {
+                                 pa_family* out) try {
   if (!fam || !out || R < 1 || n0 < 1 || n0 > (1ll << 32)) return PA_EINVAL;
   std::vector<int64_t> cnt((size_t)n0, 0);
   for (int64_t j = 0; j < R; ++j) {
@@ -299,4 +304,8 @@ extern "C" int pa_family_summary(const uint32_t* fam, int64_t R, int64_t n0,
   out->rho_t = (double)sq / (double)R;
   out->rho_s = std::exp(cl / (double)R);
   return PA_OK;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
 }
