@@ -1093,6 +1093,15 @@ int pa_load(const char* path, void* stream, pa_ctx** out) try {
       h.fam_n0 < 1 || (int64_t)h.fam_n0 > h.capacity)
     return PA_EIO;
   const int64_t N = (int64_t)h.L * h.L;
+  // the body's size follows from the header: check it before allocating
+  {
+    const long here = std::ftell(f.f);
+    if (here < 0 || std::fseek(f.f, 0, SEEK_END) != 0) return PA_EIO;
+    const long end = std::ftell(f.f);
+    if (end < 0 || std::fseek(f.f, here, SEEK_SET) != 0) return PA_EIO;
+    const int64_t want = (h.model == PA_PMJ ? 2 * N : 0) + h.R * N + 12 * h.R;
+    if ((int64_t)(end - here) != want) return PA_EIO;
+  }
   std::vector<int8_t> J;
   if (h.model == PA_PMJ) {
     J.resize((size_t)(2 * N));

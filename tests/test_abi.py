@@ -70,14 +70,16 @@ def test_product_path_does_not_touch_the_oracle():
 
 
 def _pop_file(path, L=4, R=2, spins=None, extra=b"", magic=b"PAPOPv03",
-              fam=None, n0=None):
+              fam=None, n0=None, R_hdr=None, cap_hdr=None):
     """A population file written from the documented layout: 104-byte
     header (its last word the founding population size), spins [R][L][L]
     int8, E and M int32, families uint32."""
     import struct
     N = L * L
     n0 = R if n0 is None else n0
-    hdr = magic + struct.pack("<qqqqdddiiiiIiiiiI", R, R + 100, 1, R, 0.25,
+    Rh = R if R_hdr is None else R_hdr
+    cap = R + 100 if cap_hdr is None else cap_hdr
+    hdr = magic + struct.pack("<qqqqdddiiiiIiiiiI", R, cap, 1, Rh, 0.25,
                               N * 0.6931471805599453, 0.0, L, 0, 0, 1, 0, 3,
                               0, 0, 0, n0)
     assert len(hdr) == 104
@@ -99,6 +101,9 @@ def test_load_rejects_bad_files_before_any_device_work(tmp_path):
            ("older format", dict(magic=b"PAPOPv02")),
            ("spin value", dict(spins=bytes([1] * 31 + [0]))),
            ("family number", dict(fam=[0, 2])),
+           # a header that claims two billion replicas over a short body is
+           # refused by its size, before anything is allocated
+           ("size", dict(R_hdr=(1 << 31) - 1, cap_hdr=(1 << 32) - 1)),
            ("founding size", dict(n0=0)),
            ("trailing bytes", dict(extra=b"\x00"))]
     for name, kw in bad:
