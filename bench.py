@@ -410,7 +410,7 @@ def summarize_trace(trace_dir, name, command):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="C2", choices=sorted(W.CONFIGS))
     ap.add_argument("--rows-per-lane", type=int, default=0)
