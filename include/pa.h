@@ -273,8 +273,8 @@ int pa_load(const char* path, void* stream, pa_ctx** out);
    size rho_s = R exp(sum nu_i ln nu_i) (both 1 when no two replicas share a
    family, R when one family holds them all).  PA_EINVAL for a number
    >= n0.  pa_family_stats is pa_get_families followed by
-   pa_family_summary.  Single populations only (the batch keeps no
-   families). */
+   pa_family_summary.  A batch exports its populations' families with
+   pa_batch_get_families. */
 typedef struct {
   int64_t R;          /* population size                                     */
   int64_t n0;         /* size of the founding population                    */
@@ -449,6 +449,12 @@ int pa_batch_trajectory(pa_batch* b, int32_t p, pa_obs* obs, double* lnZ,
 /* Canonical export of population p (as pa_get_population). */
 int pa_batch_get_population(pa_batch* b, int32_t p, int8_t* spins, int32_t* E,
                             int32_t* M, int64_t cap);
+
+/* Families of population p, as pa_get_families: the founding population is
+   the initial one (n0 = its R_target); the batch carries the families
+   through every resampling in its segmented parent scatter. */
+int pa_batch_get_families(pa_batch* b, int32_t p, uint32_t* fam, int64_t cap,
+                          int64_t* len, int64_t* n0);
 
 /* Launch shape of the persistent sweep kernel: workgroups (default 1024,
    at most 65535) and work items taken per queue atomic (default 4,

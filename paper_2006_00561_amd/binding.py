@@ -123,6 +123,8 @@ def lib():
             "pa_batch_trajectory": ([P, i32, P, P, i32, C.POINTER(i32)],
                                     C.c_int),
             "pa_batch_get_population": ([P, i32, P, P, P, i64], C.c_int),
+            "pa_batch_get_families": ([P, i32, P, i64, C.POINTER(i64),
+                                       C.POINTER(i64)], C.c_int),
             "pa_batch_set_sweep_blocks": ([P, i32, i32], C.c_int),
             "pa_batch_destroy": ([P], None),
             "pa_batch_run_learned": ([P, P, d, d, d, i32, i32, i32,
@@ -503,6 +505,18 @@ class Batch:
                                           _ptr(M), R),
             "pa_batch_get_population")
         return s, E, M
+
+    def families(self, p):
+        """(family number of every replica of population p, founding
+        size)."""
+        ln, n0 = C.c_int64(), C.c_int64()
+        _ck(lib().pa_batch_get_families(self._h, p, None, 0, C.byref(ln),
+                                        C.byref(n0)), "pa_batch_get_families")
+        f = np.empty(max(ln.value, 1), np.uint32)
+        _ck(lib().pa_batch_get_families(self._h, p, _ptr(f), ln.value,
+                                        C.byref(ln), C.byref(n0)),
+            "pa_batch_get_families")
+        return f[:ln.value].copy(), n0.value
 
     def set_sweep_blocks(self, blocks, chunk=1):
         _ck(lib().pa_batch_set_sweep_blocks(self._h, blocks, chunk),

@@ -194,19 +194,27 @@ __global__ __launch_bounds__(1024) void k_bscan(const BatchPop* P,
 
 __global__ __launch_bounds__(256) void k_bscatter(const BatchPop* P,
                                                   const BatchStep* S,
-                                                  const int64_t* R) {
+                                                  const int64_t* R,
+                                                  const int32_t* cur) {
   __shared__ uint32_t lds[4];
   const int p = blockIdx.y;
   const int64_t Rp = R[p];
   if (!S[p].active || (int64_t)blockIdx.x * 256 >= Rp) return;  // whole block
   const BatchPop& q = P[p];
+  const int c = cur[p];
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const uint32_t nj = (j < Rp) ? q.n[j] : 0u;
   uint32_t total;
   const uint32_t ex = block_excl_scan256(nj, lds, &total);
   const int64_t o = (int64_t)q.tile_off[blockIdx.x] + ex;
+  // a copy joins its parent's family (the other family buffer becomes
+  // current when the commit adopts the new population)
+  const uint32_t fj = nj ? q.fam[c][j] : 0u;
   for (uint32_t t = 0; t < nj; ++t)
-    if (o + t < q.cap) q.parent[o + t] = (uint32_t)j;
+    if (o + t < q.cap) {
+      q.parent[o + t] = (uint32_t)j;
+      q.fam[c ^ 1][o + t] = fj;
+    }
 }
 
 // Grid-stride over row groups of every population (grid y = population).
@@ -760,7 +768,7 @@ int enqueue_back(pa_batch* b) {
                      b->d_Rnew, dflags);
   BK(hipGetLastError());
   hipLaunchKernelGGL(k_bscatter, dim3(tiles, b->n), dim3(256), 0, st,
-                     b->d_pops, dS, dR);
+                     b->d_pops, dS, dR, b->d_cur);
   BK(hipGetLastError());
   hipLaunchKernelGGL(k_bgather, dim3(256, b->n), dim3(256), 0, st, b->d_pops,
                      dS, b->d_Rnew, b->d_cur);
@@ -1078,6 +1086,8 @@ int pa_batch_init(const pa_config* cfgs, int32_t n, void* stream,
     }
     ok = ok && balloc(b, &d.n, cap * 4);
     ok = ok && balloc(b, &d.parent, cap * 4);
+    ok = ok && balloc(b, &d.fam[0], cap * 4);
+    ok = ok && balloc(b, &d.fam[1], cap * 4);
     ok = ok && balloc(b, &d.tile_sum, (cap / 256 + 2) * 4);
     ok = ok && balloc(b, &d.tile_off, (cap / 256 + 2) * 4);
     d.hist = reinterpret_cast<uint32_t*>(b->d_rb + b->pops[p].rb_hist);
@@ -1159,6 +1169,10 @@ int pa_batch_init(const pa_config* cfgs, int32_t n, void* stream,
     a.init = 1;
     if (rc == PA_OK && launch_lattice(a, d.W, d.rpl, d.int8, d.glass,
                                       b->stream) != hipSuccess)
+      rc = PA_EDEVICE;
+    // every initial replica founds its own family
+    if (rc == PA_OK &&
+        launch_iota_u32(d.fam[0], c.R_target, b->stream) != hipSuccess)
       rc = PA_EDEVICE;
   }
   // the whole readback block: sizes, zeroed sticky error flags, moments
@@ -1410,6 +1424,26 @@ int pa_batch_get_population(pa_batch* b, int32_t p, int8_t* spins, int32_t* E,
   }
   if (E) BK(hipMemcpy(E, d.E[cur], (size_t)R * 4, hipMemcpyDeviceToHost));
   if (M) BK(hipMemcpy(M, d.M[cur], (size_t)R * 4, hipMemcpyDeviceToHost));
+  return PA_OK;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (...) {
+  return PA_EDEVICE;
+}
+
+int pa_batch_get_families(pa_batch* b, int32_t p, uint32_t* fam, int64_t cap,
+                          int64_t* len, int64_t* n0) try {
+  if (!b || p < 0 || p >= b->n) return PA_EINVAL;
+  BK(hipStreamSynchronize(b->stream));
+  const BatchPop& d = b->pops[p].d;
+  int32_t cur = 0;
+  BK(hipMemcpy(&cur, b->d_cur + p, 4, hipMemcpyDeviceToHost));
+  int64_t R = 0;
+  BK(hipMemcpy(&R, b->d_rb + 8 * (size_t)p, 8, hipMemcpyDeviceToHost));
+  if (fam && cap < R) return PA_EINVAL;
+  if (fam) BK(hipMemcpy(fam, d.fam[cur], (size_t)R * 4, hipMemcpyDeviceToHost));
+  if (len) *len = R;
+  if (n0) *n0 = b->pops[p].R_t;
   return PA_OK;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;

@@ -92,6 +92,7 @@ struct BatchPop {          // static description of one population
   int32_t* M[2];
   uint32_t* n;             // copy counts            [cap]
   uint32_t* parent;        // parent of each new slot [cap]
+  uint32_t* fam[2];        // family of each replica  [cap], buffer cur
   uint32_t* tile_sum;      // per 256-replica tile   [cap/256 + 1]
   uint32_t* tile_off;
   uint32_t* hist;          // energy histogram       [nbins]

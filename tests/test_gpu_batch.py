@@ -108,7 +108,7 @@ def test_graph_replays_match_eager_across_runs(pa):
 def test_batch_equals_single_population_path(pa):
     """The batched glass workload (64 instances, L in {8..32}, R up to 2^16),
     first 12 steps of its schedule, against each instance run alone through
-    pa_init / pa_resample / pa_sweep."""
+    pa_init / pa_resample / pa_sweep: populations, ln Z and families."""
     inst = W.batched_glass_instances()
     betas = np.array(W.linear_schedule(3.0, 300)[:12])
     theta = 10
@@ -124,6 +124,9 @@ def test_batch_equals_single_population_path(pa):
         sb, Eb, Mb = b.population(p)
         assert np.array_equal(Eg, Eb) and np.array_equal(sg, sb), p
         assert g.free_energy()[0] == b.state(p)[3]
+        fg, n0g = g.families()
+        fb, n0b = b.families(p)
+        assert n0g == n0b and np.array_equal(fg, fb), p
         g.close()
     b.close()
 
