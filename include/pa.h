@@ -353,7 +353,11 @@ int pa_tune_rows_per_lane(int32_t L, int32_t layout, int32_t model,
 /* Creates n populations at beta_0 = 0 (Eq. part-F, as pa_init).  stream NULL
    = a private non-blocking stream (graph capture needs one).  flags:
    PA_BATCH_AUTOTUNE picks rows_per_lane per distinct (L, layout, model) with
-   pa_tune_rows_per_lane where a config leaves it 0 (cached per process). */
+   pa_tune_rows_per_lane where a config leaves it 0 (cached per process).
+   Models: the ferromagnet and +-J glasses in either layout, and q-state
+   Potts populations (PA_POTTS, PA_INT8, L = 8, 16, 32, 64 or 128: the
+   four-sites-per-word pass, one replica per wave, rows_per_lane ignored);
+   the nearest-integer law only.  PA_EINVAL otherwise. */
 int pa_batch_init(const pa_config* cfgs, int32_t n, void* stream,
                   int32_t flags, pa_batch** out);
 
@@ -446,7 +450,8 @@ int pa_batch_state(pa_batch* b, int32_t p, int64_t* R, double* beta,
 int pa_batch_trajectory(pa_batch* b, int32_t p, pa_obs* obs, double* lnZ,
                         int32_t cap, int32_t* len);
 
-/* Canonical export of population p (as pa_get_population). */
+/* Canonical export of population p (as pa_get_population; Potts states
+   0..q-1). */
 int pa_batch_get_population(pa_batch* b, int32_t p, int8_t* spins, int32_t* E,
                             int32_t* M, int64_t cap);
 

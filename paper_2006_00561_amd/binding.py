@@ -428,7 +428,8 @@ class Batch:
 
     def __init__(self, pops, stream=None, autotune=False):
         """pops: list of dicts with keys L, R (target), and optionally J,
-        seed, population_id, layout, capacity, rows_per_lane."""
+        q (q-state Potts), seed, population_id, layout, capacity,
+        rows_per_lane."""
         self.n = len(pops)
         self._keep = []
         cfgs = (pa_config * self.n)()
@@ -440,7 +441,9 @@ class Batch:
                 J = np.ascontiguousarray(J, np.int8)
                 self._keep.append(J)
             c.L = p["L"]
-            c.model = PA_FERRO if J is None else PA_PMJ
+            q = p.get("q", 0)
+            c.model = PA_POTTS if q else (PA_FERRO if J is None else PA_PMJ)
+            c.q = q
             c.J = _ptr(J)
             c.R_target = p["R"]
             c.capacity = p.get("capacity", 0)

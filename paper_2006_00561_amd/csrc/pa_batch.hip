@@ -38,15 +38,22 @@
 #include "pa_device.h"
 #include "pa_internal.h"
 #include "pa_lattice.h"
+#include "pa_potts.h"
 
 namespace pa {
 
 // Sweep classes: one per lattice variant (row words W, rows per lane, spin
 // layout, model), so a persistent launch carries the code of one variant.
-constexpr int kClasses = 64;
+// Sweep classes: 64 Ising variants (W, rows per lane, layout, model), then
+// the Potts pass for L = 8, 16, 32, 64, 128.
+constexpr int kIsingClasses = 64;
+constexpr int kClasses = kIsingClasses + 5;
 __host__ __device__ constexpr int sweep_class(int W, int rpl, int int8,
                                               int glass) {
   return (((W - 1) * 4 + (rpl - 1)) * 2 + int8) * 2 + glass;
+}
+__host__ __device__ constexpr int potts_class(int mpr) {
+  return kIsingClasses + (mpr == 1 ? 0 : mpr == 2 ? 1 : mpr == 4 ? 2 : mpr == 8 ? 3 : 4);
 }
 
 // -------------------------------------------------------------- kernels
@@ -422,6 +429,66 @@ __global__ __launch_bounds__(256) void k_bsweep(
   }
 }
 
+// Persistent Potts pass of one lattice size.  Workgroups are single waves,
+// so the barriers inside the pass are the wave's own; an item is one
+// replica (rpw = 1), and the barrier at the end of an item keeps the next
+// item's table and lattice writes behind this item's last reads.
+template <int MPR>
+__global__ __launch_bounds__(64) void k_bpotts(
+    const BatchPop* P, const BatchStep* S, const int64_t* R,
+    const int32_t* cur, const int32_t* order, const int64_t* prefix,
+    unsigned long long* queue, int first, int count, int chunk,
+    uint32_t one) {
+  extern __shared__ uint32_t lds_words[];
+  constexpr int cls = potts_class(MPR);
+  const int lane = threadIdx.x & 63;
+  const int64_t* pre = prefix + first + cls;
+  const int64_t total = pre[count];
+  int64_t item = 0, end = 0;
+  while (true) {
+    if (item == end) {
+      int it = 0;
+      if (lane == 0) it = (int)atomicAdd(&queue[cls], (unsigned long long)chunk);
+      item = (int64_t)__shfl(it, 0, 64);
+      end = item + chunk;
+    }
+    if (item >= total) break;
+    const int64_t this_item = item++;
+    int lo = 0, hi = count - 1;  // last i with pre[i] <= this_item
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (pre[mid] <= this_item) lo = mid;
+      else hi = mid - 1;
+    }
+    const int p = order[first + lo];
+    const BatchPop& q = P[p];
+    const BatchStep& st = S[p];
+    const int c = cur[p];
+    LatticeArgs a{};
+    a.spins = q.spins[c];
+    a.src = q.spins[c ^ 1];  // every new slot reads its parent
+    a.parent = q.parent;
+    a.Rdev = nullptr;
+    a.E = q.E[c];
+    a.M = q.M[c];
+    a.R = R[p];
+    a.stride = q.stride;
+    a.L = q.L;
+    a.one = one;
+    a.k0 = q.k0;
+    a.k1 = q.k1;
+    a.pop = q.pop;
+    a.step = st.step;
+    a.t0 = 0;
+    a.theta = st.theta;
+    a.init = 0;
+    a.q = q.q;
+    for (int d = 0; d < 4; ++d) a.Tp[d] = st.Tp[d];
+    potts_swar_pass<MPR>(a, this_item - pre[lo], true, lds_words);
+    __syncthreads();
+  }
+}
+
 }  // namespace pa
 
 using namespace pa;
@@ -647,6 +714,7 @@ void host_step(void* ud) {
       b->src_count[src] += 1;
     }
     metropolis_K(beta_next, &s.K4, &s.K8);
+    if (q.d.q) potts_thresholds(beta_next, s.Tp);
     s.lvl0 = tr.lo;
     s.nlvl = tr.hi - tr.lo + 1;
     s.step = (uint32_t)(q.step + 1);
@@ -721,6 +789,32 @@ hipError_t launch_bsweep_wr(int int8, int glass, unsigned blocks,
   return hipGetLastError();
 }
 
+// The persistent Potts pass of class k (see potts_class): as many one-wave
+// workgroups as the Ising sweep has waves.
+hipError_t launch_bpotts(int k, int blocks, int chunk, hipStream_t st,
+                         const BatchPop* P, const BatchStep* S,
+                         const int64_t* R, const int32_t* cur,
+                         const int32_t* order, const int64_t* prefix,
+                         unsigned long long* queue, int first, int count) {
+  const int mi = k - kIsingClasses;
+  const int mpr = 1 << mi;
+  const size_t shm = 72 + (size_t)64 * mpr * mpr;
+  const dim3 grid((unsigned)(4 * blocks)), block(64);
+#define PA_BP(m)                                                           \
+  hipLaunchKernelGGL(k_bpotts<m>, grid, block, shm, st, P, S, R, cur,      \
+                     order, prefix, queue, first, count, chunk, 1u)
+  switch (mpr) {
+    case 1: PA_BP(1); break;
+    case 2: PA_BP(2); break;
+    case 4: PA_BP(4); break;
+    case 8: PA_BP(8); break;
+    case 16: PA_BP(16); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef PA_BP
+  return hipGetLastError();
+}
+
 // The persistent sweep of sweep class k (see sweep_class).
 hipError_t launch_bsweep(int k, int blocks, int chunk, hipStream_t st,
                          const BatchPop* P, const BatchStep* S,
@@ -779,10 +873,15 @@ int enqueue_back(pa_batch* b) {
   BK(hipGetLastError());
   for (int k = 0; k < kClasses; ++k) {
     if (b->cls_count[k] == 0) continue;
-    BK(launch_bsweep(k, b->sweep_blocks, b->sweep_chunk, st, b->d_pops, dS,
-                     dR, b->d_cur,
-                     b->d_order, b->d_prefix, b->d_queue, b->cls_first[k],
-                     b->cls_count[k]));
+    if (k >= kIsingClasses)
+      BK(launch_bpotts(k, b->sweep_blocks, b->sweep_chunk, st, b->d_pops, dS,
+                       dR, b->d_cur, b->d_order, b->d_prefix, b->d_queue,
+                       b->cls_first[k], b->cls_count[k]));
+    else
+      BK(launch_bsweep(k, b->sweep_blocks, b->sweep_chunk, st, b->d_pops, dS,
+                       dR, b->d_cur,
+                       b->d_order, b->d_prefix, b->d_queue, b->cls_first[k],
+                       b->cls_count[k]));
   }
   return PA_OK;
 }
@@ -960,12 +1059,19 @@ int pa_batch_init(const pa_config* cfgs, int32_t n, void* stream,
   for (int p = 0; p < n; ++p) {
     const pa_config& c = cfgs[p];
     if (c.L < 4 || c.L > 128 || (c.L & 1)) return PA_EINVAL;
-    if (c.model != PA_FERRO && c.model != PA_PMJ) return PA_EINVAL;
+    if (c.model != PA_FERRO && c.model != PA_PMJ && c.model != PA_POTTS)
+      return PA_EINVAL;
+    // Potts populations: the four-sites-per-word pass (L = 8, 16, 32, 64,
+    // 128), one byte per state
+    if (c.model == PA_POTTS &&
+        (c.q < 2 || c.q > 16 || c.layout != PA_INT8 ||
+         (c.L != 8 && c.L != 16 && c.L != 32 && c.L != 64 && c.L != 128)))
+      return PA_EINVAL;
     if (c.model == PA_PMJ && !c.J) return PA_EINVAL;
     if (c.layout != PA_INT8 && c.layout != PA_BITS) return PA_EINVAL;
     if (c.resampling != PA_NEAREST) return PA_EINVAL;  // single path only
     if (c.R_target < 1 || c.R_target >= (1ll << 31)) return PA_EINVAL;
-    const int rpl = c.rows_per_lane;
+    const int rpl = c.model == PA_POTTS ? 0 : c.rows_per_lane;  // Potts: unused
     if (rpl < 0 || rpl > 4) return PA_EINVAL;
     if (rpl && (c.L % rpl || c.L / rpl > 64 || ((c.L + 31) / 32 >= 3 && rpl < 2)))
       return PA_EINVAL;
@@ -1002,7 +1108,7 @@ int pa_batch_init(const pa_config* cfgs, int32_t n, void* stream,
     const pa_config& c = cfgs[p];
     PopHost& q = b->pops[p];
     BatchPop& d = q.d;
-    int rpl = c.rows_per_lane;
+    int rpl = c.model == PA_POTTS ? 1 : c.rows_per_lane;
     if (rpl == 0 && (flags & 1)) {
       const TuneKey key{c.L, c.layout, c.model};
       auto it = tune_cache().find(key);
@@ -1027,8 +1133,15 @@ int pa_batch_init(const pa_config* cfgs, int32_t n, void* stream,
     d.rpl = rpl;
     d.lpr = c.L / rpl;
     d.rpw = 64 / d.lpr;
-    d.shift = (c.model == PA_FERRO) ? 2 : 1;
-    d.nbins = ((4 * c.L * c.L) >> d.shift) + 1;
+    d.shift = (c.model == PA_FERRO) ? 2 : (c.model == PA_PMJ) ? 1 : 0;
+    // Potts energies lie in [-2N, 0]
+    d.nbins = c.model == PA_POTTS ? 2 * c.L * c.L + 1
+                                  : ((4 * c.L * c.L) >> d.shift) + 1;
+    d.q = c.model == PA_POTTS ? c.q : 0;
+    if (d.q) {  // one replica per wave
+      d.lpr = 64;
+      d.rpw = 1;
+    }
     d.glass = c.model == PA_PMJ;
     d.int8 = c.layout == PA_INT8;
     d.stride = d.int8 ? round_up16((int64_t)c.L * c.L)
@@ -1047,7 +1160,7 @@ int pa_batch_init(const pa_config* cfgs, int32_t n, void* stream,
     q.R_t = c.R_target;
     q.N = c.L * c.L;
     q.model = c.model;
-    q.lnZ = (double)q.N * std::log(2.0);
+    q.lnZ = (double)q.N * std::log(d.q ? (double)d.q : 2.0);
     q.rb_hist = rb;
     rb += (size_t)d.nbins * 4;
     q.up_tab = up;
@@ -1106,7 +1219,7 @@ int pa_batch_init(const pa_config* cfgs, int32_t n, void* stream,
   // population order: by sweep class, then by L descending
   auto cls_of = [&](int p) {
     const BatchPop& x = b->pops[p].d;
-    return sweep_class(x.W, x.rpl, x.int8, x.glass);
+    return x.q ? potts_class(x.L / 8) : sweep_class(x.W, x.rpl, x.int8, x.glass);
   };
   std::vector<int32_t> order(n);
   std::iota(order.begin(), order.end(), 0);
@@ -1167,8 +1280,11 @@ int pa_batch_init(const pa_config* cfgs, int32_t n, void* stream,
     a.pop = d.pop;
     a.one = 1u;
     a.init = 1;
-    if (rc == PA_OK && launch_lattice(a, d.W, d.rpl, d.int8, d.glass,
-                                      b->stream) != hipSuccess)
+    a.q = d.q;
+    if (rc == PA_OK &&
+        (d.q ? launch_potts(a, b->stream)
+             : launch_lattice(a, d.W, d.rpl, d.int8, d.glass, b->stream)) !=
+            hipSuccess)
       rc = PA_EDEVICE;
     // every initial replica founds its own family
     if (rc == PA_OK &&

@@ -100,11 +100,13 @@ struct BatchPop {          // static description of one population
   const uint32_t* jbits;   // +-J couplings or null
   int64_t cap, stride;
   int32_t L, W, rpl, lpr, rpw, nbins, shift, glass, int8, chunks, lpr_log2;
+  int32_t q;               // Potts states (0: Ising)
   uint32_t k0, k1, pop;
 };
 
 struct BatchStep {         // per population, rewritten by the host each step
   uint64_t K4, K8;         // Metropolis thresholds at the new beta
+  uint64_t Tp[4];          // Potts: T[d - 1] = floor(exp(-beta d) 2^32)
   double beta;             // the population's beta after this step
   double target;           // overlap target of the adaptive schedule
   int32_t lvl0, nlvl;      // table range (histogram levels)

@@ -55,6 +55,15 @@ def test_strerror_and_validation_without_device():
     assert lib.pa_batch_init(C.byref(cfg), 1, None, 0,
                              C.byref(bh)) == b.PA_EINVAL
     assert not bh.value
+    # Potts populations in a batch: the four-sites-per-word sizes, one byte
+    # per state, 2 <= q <= 16
+    for L, q, layout in ((12, 3, 0), (64, 1, 0), (64, 17, 0), (64, 3, 1)):
+        cfg = b.pa_config()
+        cfg.L, cfg.R_target, cfg.model, cfg.q = L, 10, b.PA_POTTS, q
+        cfg.layout = layout
+        assert lib.pa_batch_init(C.byref(cfg), 1, None, 0,
+                                 C.byref(bh)) == b.PA_EINVAL, (L, q, layout)
+        assert not bh.value
     assert lib.pa_sweep(None, 0.1, 1) == b.PA_EINVAL
     assert lib.pa_resample(None, 0.1, None) == b.PA_EINVAL
 

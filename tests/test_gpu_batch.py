@@ -206,3 +206,52 @@ def test_weighted_average_of_independent_populations_is_exact(pa):
     assert abs(comb["e"] - e_exact) < 5 * e.std(ddof=1) / np.sqrt(M) + 1e-4
     assert abs(comb["lnZ"] - z_exact) < 5 * lnZ.std(ddof=1) / np.sqrt(M) + 0.05
     b.close()
+
+
+def test_potts_populations_in_a_batch_equal_their_single_runs(pa):
+    """q-state Potts populations of every four-sites-per-word size, batched
+    with a ferromagnet and a +-J glass: every population's states, E, M,
+    ln Z and families equal its run alone through the single-population
+    path, for a linear schedule through the q = 10 transition region and
+    for the adaptive schedule (to beta = 0.9, below the Potts transitions,
+    where overlap-targeted steps stay few)."""
+    pops = [dict(L=8, R=700, q=3, seed=5, population_id=0),
+            dict(L=16, R=900, q=10, seed=5, population_id=1),
+            dict(L=32, R=300, q=16, seed=6, population_id=2),
+            dict(L=64, R=200, q=10, seed=7, population_id=3),
+            dict(L=128, R=40, q=4, seed=8, population_id=4),
+            dict(L=16, R=500, seed=9, population_id=5),
+            dict(L=24, R=400, J=W.pmj_couplings(24, 77), seed=9,
+                 population_id=6)]
+    betas = np.array(W.linear_schedule(1.6, 14))
+    theta = 3
+    for adaptive in (False, True):
+        b = pa.Batch(pops)
+        if adaptive:
+            steps = b.run_adaptive(0.8, 0.9, 2000, theta, use_graph=True)
+            assert steps < 2000
+        else:
+            b.run(betas, theta, use_graph=True)
+        for p, c in enumerate(pops):
+            g = pa.Population(c["L"], c["R"], seed=c["seed"],
+                              population_id=c["population_id"], J=c.get("J"),
+                              q=c.get("q", 0))
+            if adaptive:
+                traj, _ = b.trajectory(p)
+                sched = [o["beta"] for o in traj]
+            else:
+                sched = betas
+            for beta in sched:
+                g.resample(beta)
+                g.sweep(beta, theta)
+            sg, Eg, Mg = g.population()
+            sb, Eb, Mb = b.population(p)
+            tag = (adaptive, p)
+            assert np.array_equal(Eg, Eb) and np.array_equal(Mg, Mb), tag
+            assert np.array_equal(sg, sb), tag
+            assert g.free_energy()[0] == b.state(p)[3], tag
+            fg, _ = g.families()
+            fb, _ = b.families(p)
+            assert np.array_equal(fg, fb), tag
+            g.close()
+        b.close()
