@@ -3,7 +3,9 @@ layout, sweep shape, model (ferromagnet, +-J glass, q-state Potts), resampling
 law, sweeps per step, cooling or heating, capacity, waiting or deferred
 population sizes and reads of the population between a resampling and its
 sweep.  Every step is compared with the oracle bit for bit (spins, E, M,
-copy counts, families) and to 1e-12 for ln Z and the observables."""
+copy counts, families) and to 1e-12 for ln Z and the observables.  Random
+batches of mixed populations are compared with each population's single
+run, which the oracle pins."""
 import os
 
 import numpy as np
@@ -119,3 +121,62 @@ def test_random_configuration_matches_oracle(pa, c):
             assert _close(og[k], oo[k]), (i, k)
     g.close()
     o.close()
+
+
+def _batches(n=8, seed=4242):
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n):
+        pops = []
+        for i in range(int(rng.integers(2, 8))):
+            model = ["ferro", "glass", "potts"][int(rng.integers(0, 3))]
+            if model == "potts":
+                L = int(rng.choice([8, 16, 32, 64]))
+                pop = dict(L=L, q=int(rng.integers(2, 17)))
+            else:
+                L = int(rng.choice([4, 6, 8, 12, 16, 24, 32, 48, 64]))
+                rpl = int(rng.choice([0, 1, 2, 3, 4]))
+                if rpl and (L % rpl or L // rpl > 64):
+                    rpl = 0
+                pop = dict(L=L, layout=int(rng.integers(0, 2)),
+                           rows_per_lane=rpl)
+                if model == "glass":
+                    pop["J"] = W.pmj_couplings(L, 900 + 10 * k + i)
+            pop.update(R=int(rng.integers(30, 600)),
+                       seed=int(rng.integers(1, 1 << 30)),
+                       population_id=int(rng.integers(0, 1000)))
+            pops.append(pop)
+        out.append(dict(k=k, pops=pops, steps=int(rng.integers(3, 9)),
+                        theta=int(rng.integers(1, 4)),
+                        beta_f=float(rng.uniform(0.4, 1.5)),
+                        autotune=bool(rng.random() < 0.5)))
+    return out
+
+
+BATCHES = _batches()
+
+
+@pytest.mark.parametrize("c", BATCHES, ids=lambda c: "batch%d" % c["k"])
+def test_random_batch_matches_single_runs(pa, c):
+    print("random batch", c["k"], [(p["L"], p["R"], p.get("q", 0),
+                                   "J" in p) for p in c["pops"]],
+          flush=True)
+    betas = np.array(W.linear_schedule(c["beta_f"], c["steps"]))
+    b = pa.Batch(c["pops"], autotune=c["autotune"])
+    b.run(betas, c["theta"], use_graph=True)
+    for p, pop in enumerate(c["pops"]):
+        g = pa.Population(pop["L"], pop["R"], seed=pop["seed"],
+                          population_id=pop["population_id"],
+                          J=pop.get("J"), q=pop.get("q", 0),
+                          layout=pop.get("layout", 0))
+        for beta in betas:
+            g.resample(beta)
+            g.sweep(beta, c["theta"])
+        sg, Eg, Mg = g.population()
+        sb, Eb, Mb = b.population(p)
+        assert np.array_equal(Eg, Eb) and np.array_equal(Mg, Mb), p
+        assert np.array_equal(sg, sb), p
+        assert g.free_energy()[0] == b.state(p)[3], p
+        assert np.array_equal(g.families()[0], b.families(p)[0]), p
+        g.close()
+    b.close()
