@@ -278,9 +278,12 @@ int ensure_tab(pa_ctx* c, size_t words) {
   const size_t nw = words + words / 2;
   uint32_t* d = nullptr;
   uint32_t* h = nullptr;
-  if (hipMalloc(reinterpret_cast<void**>(&d), nw * 4) != hipSuccess)
+  if (hipMalloc(reinterpret_cast<void**>(&d), nw * 4) != hipSuccess) {
+    (void)hipGetLastError();  // not left for a later launch check
     return PA_ENOMEM;
+  }
   if (hipHostMalloc(reinterpret_cast<void**>(&h), nw * 4) != hipSuccess) {
+    (void)hipGetLastError();
     (void)hipFree(d);
     return PA_ENOMEM;
   }
@@ -328,7 +331,12 @@ int reset_families(pa_ctx* c) {
 
 template <typename T>
 bool dmalloc(T** p, size_t bytes) {
-  return hipMalloc(reinterpret_cast<void**>(p), bytes ? bytes : 16) == hipSuccess;
+  if (hipMalloc(reinterpret_cast<void**>(p), bytes ? bytes : 16) == hipSuccess)
+    return true;
+  // the runtime keeps the failure as its last error, which the launch
+  // checks of a later, healthy context would read: clear it
+  (void)hipGetLastError();
+  return false;
 }
 
 // canonical int8 [L][L] -> device layout of one replica (stride bytes)
@@ -464,6 +472,7 @@ int pa_init(const pa_config* cfg, pa_ctx** out) try {
   ok = ok && hipHostMalloc(reinterpret_cast<void**>(&c->h_tab),
                            c->tab_words * 4) == hipSuccess;
   if (!ok) {
+    (void)hipGetLastError();  // a failed allocation is no later launch's error
     free_all(c);
     delete c;
     return PA_ENOMEM;

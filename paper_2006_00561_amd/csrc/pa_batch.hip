@@ -986,7 +986,10 @@ void free_batch(pa_batch* b) {
 template <typename T>
 bool balloc(pa_batch* b, T** p, size_t bytes) {
   void* q = nullptr;
-  if (hipMalloc(&q, bytes ? bytes : 16) != hipSuccess) return false;
+  if (hipMalloc(&q, bytes ? bytes : 16) != hipSuccess) {
+    (void)hipGetLastError();  // not left for a later launch check to read
+    return false;
+  }
   b->allocs.push_back(q);
   *p = static_cast<T*>(q);
   return true;
@@ -1212,6 +1215,7 @@ int pa_batch_init(const pa_config* cfgs, int32_t n, void* stream,
     }
   }
   if (!ok) {
+    (void)hipGetLastError();  // a failed allocation is no later launch's error
     free_batch(b);
     delete b;
     return PA_ENOMEM;

@@ -168,6 +168,7 @@ int ensure_batch(pa_mlp* m, int B) {
   ok = ok && hipMalloc(&m->d_r2, (size_t)B * 4) == hipSuccess;
   ok = ok && hipMalloc(&m->d_idx, (size_t)B * 4) == hipSuccess;
   if (!ok) {
+    (void)hipGetLastError();  // a failed allocation is no later launch's error
     mlp_free_scratch(m);
     return PA_ENOMEM;
   }
@@ -334,6 +335,7 @@ int pa_mlp_create(int32_t n_in, int32_t width, int32_t depth, uint64_t seed,
                    hipMemcpyHostToDevice) == hipSuccess;
   }
   if (!ok) {
+    (void)hipGetLastError();  // a failed allocation is no later launch's error
     pa_mlp_destroy(m);
     return PA_ENOMEM;
   }

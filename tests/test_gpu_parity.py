@@ -622,3 +622,24 @@ def test_empty_resampling_leaves_population_untouched(pa):
         g.close()
         return
     raise AssertionError("no seed drew an empty population")
+
+
+def test_impossible_population_reports_enomem(pa):
+    """A population whose buffers cannot fit in device memory (2^31 - 1
+    replicas of 16 KB, twice) is refused with PA_ENOMEM and no context;
+    what was allocated is released, and a normal context works after it."""
+    import ctypes as C
+    lib = pa.lib()
+    cfg = pa.pa_config()
+    cfg.L, cfg.R_target, cfg.model = 128, (1 << 31) - 1, pa.PA_FERRO
+    cfg.rows_per_lane = 2
+    h = C.c_void_p()
+    assert lib.pa_init(C.byref(cfg), C.byref(h)) == pa.PA_ENOMEM
+    assert not h.value
+    g = pa.Population(16, 200, seed=2)
+    o = oracle.OraclePA(16, 200, seed=2)
+    g.resample(0.3)
+    o.resample(0.3)
+    _cmp_state(g, o, "after ENOMEM")
+    g.close()
+    o.close()

@@ -7,6 +7,7 @@ import pytest
 
 import exact_ising as X
 import oracle
+import pa_workloads as W
 
 
 def _run(L, R, K, theta, beta_f, seed, J=None, pop=0):
@@ -146,3 +147,31 @@ def test_glass_L4_lnZ_matches_enumeration():
         z.append(tr[-1][1])
     z = np.array(z)
     assert abs(z.mean() - exact) < 4 * z.std(ddof=1) / np.sqrt(len(z)) + 5e-3
+
+
+def test_lnZ_bias_and_variance_shrink_as_one_over_R():
+    """The paper's error claims for the free-energy estimate (Sec. 4): over
+    3000 independent L = 4 runs per size, Var(ln Z_hat) and the systematic
+    error E[ln Z_hat] - ln Z both scale as 1/R (R = 8 against R = 32: ratios
+    near 4), and the bias is -Var/2 to first order (ln of an unbiased
+    estimate of Z)."""
+    L, beta_f, K, theta = 4, 1.0, 10, 2
+    ex = X.brute_thermo(L, beta_f)["lnZ"]
+    stats = {}
+    for R in (8, 32):
+        d = []
+        for s in range(1, 3001):
+            p = oracle.OraclePA(L, R, seed=s)
+            for b in W.linear_schedule(beta_f, K):
+                p.resample(b)
+                p.sweep(theta)
+            d.append(p.free_energy()[0] - ex)
+            p.close()
+        d = np.array(d)
+        stats[R] = (d.mean(), d.std(ddof=1) / np.sqrt(len(d)), d.var())
+    (b8, se8, v8), (b32, se32, v32) = stats[8], stats[32]
+    assert b8 < -10 * se8 and b32 < -5 * se32          # biased low
+    assert 2.5 < b8 / b32 < 5.5                        # ~ 1/R
+    assert 3.0 < v8 / v32 < 5.0
+    for b, se, v in (stats[8], stats[32]):
+        assert abs(b + v / 2) < 5 * se + 0.15 * abs(b)
