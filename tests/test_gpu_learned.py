@@ -154,3 +154,35 @@ def test_graph_follows_network_scratch_and_scale_changes(pa):
         big = np.random.default_rng(k).normal(0, 1, (4096, 8))
         mlp.forward(big.astype(np.float32))              # regrows scratch
         mlp.set_norm(mu, np.ones(8, np.float32), -3.0 - k, 0.5)
+
+
+@pytest.mark.parametrize("corruption", ["huge", "nan"])
+def test_corrupted_network_falls_back_to_the_exact_schedule(pa, corruption):
+    """A network whose weights are wrecked (a huge constant, or NaN)
+    proposes steps that never meet the overlap criterion: every step falls
+    back to the exact bisection, so the learned run's schedule and
+    populations equal those of the pure bisection run bit for bit."""
+    from paper_2006_00561_amd import learned
+    pops = _ferro_pops([(12, 600), (16, 400)], 40)
+    target, tol, beta_f, theta = 0.85, 0.02, 1.0, 2
+    mlp = pa.MLP(seed=3)
+    p = mlp.params()
+    p[:] = 1e6 if corruption == "huge" else np.nan
+    mlp.set_params(p)
+    b = pa.Batch(pops)
+    steps, src = b.run_learned(mlp, target, tol, beta_f, 1000, theta)
+    assert src[learned.SRC_NET] == 0
+    assert src[learned.SRC_FALLBACK] > 0
+    ref = pa.Batch(pops)
+    ref.run_adaptive(target, beta_f, 1000, theta)
+    for k in range(len(pops)):
+        obs, lnZ = b.trajectory(k)
+        obs_r, lnZ_r = ref.trajectory(k)
+        assert [o["beta"] for o in obs] == [o["beta"] for o in obs_r], k
+        assert np.array_equal(lnZ, lnZ_r), k
+        s, E, M = b.population(k)
+        sr, Er, Mr = ref.population(k)
+        assert np.array_equal(s, sr) and np.array_equal(E, Er), k
+    b.close()
+    ref.close()
+    mlp.close()
