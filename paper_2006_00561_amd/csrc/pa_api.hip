@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <exception>
 #include <new>
 #include <vector>
 
@@ -266,7 +267,10 @@ int compute_hist(pa_ctx* c) {
                     hipMemcpyDeviceToHost, c->stream));
   int rc = sync(c, true);
   if (rc) return rc;
-  if (c->h_scal[3] != 0) return PA_EDEVICE;  // an energy outside [-2N, 2N]
+  if (c->h_scal[3] != 0) {  // an energy outside [-2N, 2N]
+    note_error("a replica's energy lies outside the histogram range");
+    return PA_EDEVICE;
+  }
   c->hist_valid = true;
   return PA_OK;
 }
@@ -418,9 +422,13 @@ int pa_init(const pa_config* cfg, pa_ctx** out) try {
 
   pa_ctx* c = new (std::nothrow) pa_ctx();
   if (!c) return PA_ENOMEM;
-  if (hipGetDevice(&c->device) != hipSuccess) {
-    delete c;
-    return PA_EDEVICE;
+  {
+    const hipError_t e = hipGetDevice(&c->device);
+    if (e != hipSuccess) {
+      set_last_error("hipGetDevice", e, __LINE__);
+      delete c;
+      return PA_EDEVICE;
+    }
   }
   c->stream = reinterpret_cast<hipStream_t>(cfg->stream);
   c->L = L;
@@ -491,9 +499,14 @@ int pa_init(const pa_config* cfg, pa_ctx** out) try {
           if (cfg->J[(size_t)d * L * L + (size_t)y * L + x] < 0)
             jb[((size_t)d * L + y) * W + x / 32] |= 1u << (x % 32);
   int rc = PA_OK;
-  if (hipMemcpyAsync(c->jbits, jb.data(), jb.size() * 4, hipMemcpyHostToDevice,
-                     c->stream) != hipSuccess)
-    rc = PA_EDEVICE;
+  {
+    const hipError_t e = hipMemcpyAsync(c->jbits, jb.data(), jb.size() * 4,
+                                        hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) {
+      set_last_error("hipMemcpyAsync(couplings)", e, __LINE__);
+      rc = PA_EDEVICE;
+    }
+  }
   if (rc == PA_OK) {
     c->R = c->R_t;
     LatticeArgs a = lattice_args(c);
@@ -516,7 +529,11 @@ int pa_init(const pa_config* cfg, pa_ctx** out) try {
   return PA_OK;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 
@@ -557,7 +574,11 @@ int pa_sweep(pa_ctx* c, double beta, int32_t theta) try {
   return PA_OK;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 
@@ -708,7 +729,11 @@ int pa_resample(pa_ctx* c, double beta_next, int64_t* R_new) try {
   return PA_OK;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 
@@ -739,7 +764,11 @@ int pa_start_heating(pa_ctx* c, double beta0) try {
   return PA_OK;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 
@@ -752,7 +781,11 @@ int pa_observables(pa_ctx* c, pa_obs* o) try {
   return PA_OK;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 
@@ -763,7 +796,11 @@ int pa_free_energy(pa_ctx* c, double* lnZ, double* lnQ_last) try {
   return PA_OK;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 
@@ -779,7 +816,11 @@ int pa_state(pa_ctx* c, int64_t* R, double* beta, int32_t* step) try {
   return PA_OK;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 
@@ -810,7 +851,11 @@ int pa_get_population(pa_ctx* c, int8_t* spins, int32_t* E, int32_t* M,
   return PA_OK;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 
@@ -839,7 +884,11 @@ int pa_get_replicas(pa_ctx* c, const int64_t* slots, int64_t k, int8_t* spins,
   return PA_OK;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 
@@ -853,7 +902,11 @@ int pa_get_counts(pa_ctx* c, uint32_t* n, int64_t cap, int64_t* len) try {
   return PA_OK;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 
@@ -884,7 +937,11 @@ int pa_set_population(pa_ctx* c, const int8_t* spins, int64_t R) try {
   return PA_OK;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 
@@ -902,7 +959,11 @@ int pa_get_families(pa_ctx* c, uint32_t* fam, int64_t cap, int64_t* len,
   return PA_OK;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 
@@ -917,7 +978,11 @@ int pa_family_stats(pa_ctx* c, pa_family* out) try {
   return pa_family_summary(f.data(), len, n0, out);
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 
@@ -932,7 +997,11 @@ int pa_histogram(pa_ctx* c, uint32_t* h, int64_t cap, int32_t* nbins,
   return PA_OK;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 
@@ -945,7 +1014,11 @@ int pa_overlap(pa_ctx* c, double dbeta, double* alpha) try {
   return PA_OK;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 
@@ -960,7 +1033,11 @@ int pa_bisect_dbeta(pa_ctx* c, double target, double beta_f, double* dbeta) try 
   return PA_OK;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 
@@ -973,7 +1050,11 @@ int pa_set_timing(pa_ctx* c, int32_t classes) try {
   return PA_OK;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 
@@ -996,7 +1077,11 @@ int pa_get_config(pa_ctx* c, pa_config* out) try {
   return PA_OK;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 
@@ -1078,7 +1163,11 @@ int pa_save(pa_ctx* c, const char* path) try {
   return ok ? PA_OK : PA_EIO;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 
@@ -1171,7 +1260,11 @@ int pa_load(const char* path, void* stream, pa_ctx** out) try {
   return PA_OK;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 
@@ -1183,7 +1276,11 @@ int pa_get_timing(pa_ctx* c, pa_timing* out) try {
   return PA_OK;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 

@@ -29,6 +29,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <exception>
 #include <new>
 #include <numeric>
 #include <tuple>
@@ -1050,7 +1051,11 @@ int pa_tune_rows_per_lane(int32_t L, int32_t layout, int32_t model,
   return PA_OK;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 
@@ -1311,7 +1316,11 @@ int pa_batch_init(const pa_config* cfgs, int32_t n, void* stream,
   return PA_OK;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 
@@ -1382,7 +1391,11 @@ int pa_batch_run(pa_batch* b, int32_t steps, const double* betas,
   return batch_run(b, steps, use_graph);
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 
@@ -1407,7 +1420,11 @@ int pa_batch_run_adaptive(pa_batch* b, double target, double beta_f,
   return rc;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 
@@ -1437,7 +1454,11 @@ int pa_batch_run_learned(pa_batch* b, pa_mlp* m, double target, double tol,
   return rc;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 
@@ -1451,7 +1472,11 @@ int pa_batch_host_stats(pa_batch* b, double* host_ms, int64_t* overlap_evals,
   return PA_OK;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 
@@ -1476,7 +1501,11 @@ int pa_batch_decisions(pa_batch* b, int32_t p, float* feat, double* dbeta,
   return PA_OK;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 
@@ -1491,7 +1520,11 @@ int pa_batch_state(pa_batch* b, int32_t p, int64_t* R, double* beta,
   return PA_OK;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 
@@ -1511,7 +1544,11 @@ int pa_batch_trajectory(pa_batch* b, int32_t p, pa_obs* obs, double* lnZ,
   return PA_OK;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 
@@ -1547,7 +1584,11 @@ int pa_batch_get_population(pa_batch* b, int32_t p, int8_t* spins, int32_t* E,
   return PA_OK;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 
@@ -1567,7 +1608,11 @@ int pa_batch_get_families(pa_batch* b, int32_t p, uint32_t* fam, int64_t cap,
   return PA_OK;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 
@@ -1580,7 +1625,11 @@ int pa_batch_set_sweep_blocks(pa_batch* b, int32_t blocks, int32_t chunk) try {
   return PA_OK;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 

@@ -140,6 +140,10 @@ uint64_t mlp_generation(const pa_mlp* m);
 
 // ---- diagnostics: text of the last failing HIP call on this thread
 void set_last_error(const char* what, hipError_t e, int line);
+// a C++ exception stopped at the ABI (reported as PA_EDEVICE)
+void note_exception(const char* what);
+// another device-side inconsistency reported as PA_EDEVICE
+void note_error(const char* text);
 
 // Evaluate a HIP call; on failure record it and return PA_EDEVICE.
 #define PA_HIP(x)                                   \

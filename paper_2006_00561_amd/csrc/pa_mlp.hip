@@ -19,6 +19,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <exception>
 #include <new>
 #include <vector>
 
@@ -343,7 +344,11 @@ int pa_mlp_create(int32_t n_in, int32_t width, int32_t depth, uint64_t seed,
   return PA_OK;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 
@@ -364,7 +369,11 @@ int pa_mlp_n_params(pa_mlp* m, int64_t* n) try {
   return PA_OK;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 
@@ -377,7 +386,11 @@ int pa_mlp_set_params(pa_mlp* m, const float* p, int64_t n) try {
   return PA_OK;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 
@@ -389,7 +402,11 @@ int pa_mlp_get_params(pa_mlp* m, float* p, int64_t n) try {
   return PA_OK;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 
@@ -410,7 +427,11 @@ int pa_mlp_set_norm(pa_mlp* m, const float* mu, const float* sigma,
   return PA_OK;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 
@@ -431,7 +452,11 @@ int pa_mlp_forward(pa_mlp* m, const float* X, int32_t B, float* y) try {
   return PA_OK;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 
@@ -466,7 +491,11 @@ int pa_mlp_loss_grad(pa_mlp* m, const float* X, const float* T, int32_t B,
   return PA_OK;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 
@@ -548,7 +577,11 @@ int pa_mlp_train(pa_mlp* m, const float* X, const float* T, int64_t n,
   return rc;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
+#include <exception>
 #include <new>
 #include <vector>
 
@@ -22,6 +23,15 @@ static thread_local char g_last_error[512] = "";
 void set_last_error(const char* what, hipError_t e, int line) {
   std::snprintf(g_last_error, sizeof g_last_error, "%s failed at line %d: %s",
                 what, line, hipGetErrorString(e));
+}
+
+void note_error(const char* text) {
+  std::snprintf(g_last_error, sizeof g_last_error, "%s", text ? text : "");
+}
+
+void note_exception(const char* what) {
+  std::snprintf(g_last_error, sizeof g_last_error,
+                "C++ exception stopped at the ABI: %s", what ? what : "");
 }
 
 const char* last_error() { return g_last_error; }
@@ -267,7 +277,11 @@ extern "C" int pa_weighted_average(int32_t M, const double* lnZ,
   return PA_OK;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }
 
@@ -306,6 +320,10 @@ extern "C" int pa_family_summary(const uint32_t* fam, int64_t R, int64_t n0,
   return PA_OK;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
 } catch (...) {
+  ::pa::note_exception("unknown exception");
   return PA_EDEVICE;
 }

@@ -643,3 +643,52 @@ def test_impossible_population_reports_enomem(pa):
     _cmp_state(g, o, "after ENOMEM")
     g.close()
     o.close()
+
+
+def _hip_runtime():
+    """The HIP runtime the library already loaded (no second copy)."""
+    import ctypes
+    for name in ("libamdhip64.so.7", "libamdhip64.so.6", "libamdhip64.so"):
+        try:
+            return ctypes.CDLL(name, mode=os.RTLD_NOLOAD)
+        except OSError:
+            continue
+    pytest.skip("the library's HIP runtime is not visible to ctypes")
+
+
+def test_results_do_not_depend_on_the_stream(pa):
+    """The same run on the null stream and on a stream of its own (default
+    priority, made by the library's HIP runtime) and, for a batch, on its
+    private stream and on that stream: identical populations, ln Z and
+    families."""
+    import ctypes
+    pa.lib()
+    hip = _hip_runtime()
+    side = ctypes.c_void_p()
+    assert hip.hipStreamCreate(ctypes.byref(side)) == 0
+    runs = []
+    for st in (None, side.value):
+        g = pa.Population(24, 700, seed=12, layout=1, stream=st,
+                          J=W.pmj_couplings(24, 5))
+        for b in W.linear_schedule(1.1, 9):
+            g.resample(b, wait=False)
+            g.sweep(b, 3)
+        runs.append((g.population(), g.free_energy(), g.families()[0]))
+        g.close()
+    (s0, z0, f0), (s1, z1, f1) = runs
+    assert all(np.array_equal(a, b) for a, b in zip(s0, s1))
+    assert z0 == z1 and np.array_equal(f0, f1)
+    pops = [dict(L=16, R=400, seed=3, population_id=0),
+            dict(L=32, R=300, q=7, seed=4, population_id=1)]
+    betas = np.array(W.linear_schedule(1.0, 6))
+    out = []
+    for st in (None, side.value):
+        b = pa.Batch(pops, stream=st)
+        b.run(betas, 2, use_graph=True)
+        out.append([(b.population(p), b.state(p)[3]) for p in range(2)])
+        b.close()
+    for (pa_, za), (pb, zb) in zip(out[0], out[1]):
+        assert all(np.array_equal(a, b) for a, b in zip(pa_, pb))
+        assert za == zb
+    assert hip.hipStreamSynchronize(side) == 0
+    assert hip.hipStreamDestroy(side) == 0
