@@ -890,7 +890,10 @@ int enqueue_back(pa_batch* b) {
 int check_flags(pa_batch* b) {
   const unsigned long long* fl = rb_flags(b);
   if (b->host_err) return b->host_err;
-  if (fl[0]) return PA_EDEVICE;
+  if (fl[0]) {
+    note_error("a population's energy lies outside its histogram range");
+    return PA_EDEVICE;
+  }
   if (fl[1] & 1ull) return PA_ECAPACITY;
   if (fl[1] & 2ull) return PA_EEMPTY;
   return PA_OK;
@@ -1089,13 +1092,14 @@ int pa_batch_init(const pa_config* cfgs, int32_t n, void* stream,
   }
   pa_batch* b = new (std::nothrow) pa_batch();
   if (!b) return PA_ENOMEM;
-  if (hipGetDevice(&b->device) != hipSuccess) {
+  if (hip_ok(hipGetDevice(&b->device), "hipGetDevice", __LINE__)) {
     delete b;
     return PA_EDEVICE;
   }
   b->stream = reinterpret_cast<hipStream_t>(stream);
   if (!b->stream) {  // graph capture needs a stream other than the null one
-    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+    if (hip_ok(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking),
+               "hipStreamCreateWithFlags", __LINE__)) {
       delete b;
       return PA_EDEVICE;
     }
@@ -1247,18 +1251,29 @@ int pa_batch_init(const pa_config* cfgs, int32_t n, void* stream,
   std::vector<BatchPop> dp(n);
   for (int p = 0; p < n; ++p) dp[p] = b->pops[p].d;
   std::vector<int32_t> cur0(n, 0);
-  if (hipMemcpy(b->d_pops, dp.data(), sizeof(BatchPop) * n, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(b->d_order, order.data(), 4 * n, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(b->d_cls_first, b->cls_first, 4 * kClasses, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(b->d_cls_count, b->cls_count, 4 * kClasses, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(b->d_cur, cur0.data(), 4 * n, hipMemcpyHostToDevice) != hipSuccess)
-    rc = PA_EDEVICE;
+  rc = hip_ok(hipMemcpy(b->d_pops, dp.data(), sizeof(BatchPop) * n,
+                        hipMemcpyHostToDevice), "hipMemcpy(populations)",
+              __LINE__);
+  if (!rc)
+    rc = hip_ok(hipMemcpy(b->d_order, order.data(), 4 * n,
+                          hipMemcpyHostToDevice), "hipMemcpy(order)", __LINE__);
+  if (!rc)
+    rc = hip_ok(hipMemcpy(b->d_cls_first, b->cls_first, 4 * kClasses,
+                          hipMemcpyHostToDevice), "hipMemcpy(classes)",
+                __LINE__);
+  if (!rc)
+    rc = hip_ok(hipMemcpy(b->d_cls_count, b->cls_count, 4 * kClasses,
+                          hipMemcpyHostToDevice), "hipMemcpy(classes)",
+                __LINE__);
+  if (!rc)
+    rc = hip_ok(hipMemcpy(b->d_cur, cur0.data(), 4 * n, hipMemcpyHostToDevice),
+                "hipMemcpy(buffers)", __LINE__);
   // couplings and the initial populations (the INIT stream of each)
   std::memset(b->h_rb, 0, b->rb_bytes);
   std::memset(b->h_up, 0, b->up_bytes);
-  if (rc == PA_OK && hipMemcpy(b->d_up, b->h_up, b->up_bytes,
-                               hipMemcpyHostToDevice) != hipSuccess)
-    rc = PA_EDEVICE;
+  if (rc == PA_OK)
+    rc = hip_ok(hipMemcpy(b->d_up, b->h_up, b->up_bytes, hipMemcpyHostToDevice),
+                "hipMemcpy(upload block)", __LINE__);
   for (int p = 0; p < n && rc == PA_OK; ++p) {
     const pa_config& c = cfgs[p];
     BatchPop& d = b->pops[p].d;
@@ -1270,9 +1285,9 @@ int pa_batch_init(const pa_config* cfgs, int32_t n, void* stream,
           for (int x = 0; x < d.L; ++x)
             if (c.J[(size_t)k * d.L * d.L + (size_t)y * d.L + x] < 0)
               jb[((size_t)k * d.L + y) * d.W + x / 32] |= 1u << (x % 32);
-      if (hipMemcpy(const_cast<uint32_t*>(d.jbits), jb.data(), jb.size() * 4,
-                    hipMemcpyHostToDevice) != hipSuccess)
-        rc = PA_EDEVICE;
+      rc = hip_ok(hipMemcpy(const_cast<uint32_t*>(d.jbits), jb.data(),
+                            jb.size() * 4, hipMemcpyHostToDevice),
+                  "hipMemcpy(couplings)", __LINE__);
     }
     LatticeArgs a{};
     a.spins = d.spins[0];
@@ -1290,23 +1305,24 @@ int pa_batch_init(const pa_config* cfgs, int32_t n, void* stream,
     a.one = 1u;
     a.init = 1;
     a.q = d.q;
-    if (rc == PA_OK &&
-        (d.q ? launch_potts(a, b->stream)
-             : launch_lattice(a, d.W, d.rpl, d.int8, d.glass, b->stream)) !=
-            hipSuccess)
-      rc = PA_EDEVICE;
+    if (rc == PA_OK)
+      rc = hip_ok(d.q ? launch_potts(a, b->stream)
+                      : launch_lattice(a, d.W, d.rpl, d.int8, d.glass,
+                                       b->stream),
+                  "initial lattice pass", __LINE__);
     // every initial replica founds its own family
-    if (rc == PA_OK &&
-        launch_iota_u32(d.fam[0], c.R_target, b->stream) != hipSuccess)
-      rc = PA_EDEVICE;
+    if (rc == PA_OK)
+      rc = hip_ok(launch_iota_u32(d.fam[0], c.R_target, b->stream),
+                  "initial families", __LINE__);
   }
   // the whole readback block: sizes, zeroed sticky error flags, moments
-  if (rc == PA_OK &&
-      hipMemcpyAsync(b->d_rb, b->h_rb, b->rb_bytes, hipMemcpyHostToDevice,
-                     b->stream) != hipSuccess)
-    rc = PA_EDEVICE;
-  if (rc == PA_OK && hipStreamSynchronize(b->stream) != hipSuccess)
-    rc = PA_EDEVICE;
+  if (rc == PA_OK)
+    rc = hip_ok(hipMemcpyAsync(b->d_rb, b->h_rb, b->rb_bytes,
+                               hipMemcpyHostToDevice, b->stream),
+                "hipMemcpyAsync(readback block)", __LINE__);
+  if (rc == PA_OK)
+    rc = hip_ok(hipStreamSynchronize(b->stream), "hipStreamSynchronize",
+                __LINE__);
   if (rc != PA_OK) {
     free_batch(b);
     delete b;

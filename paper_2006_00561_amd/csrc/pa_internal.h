@@ -145,6 +145,13 @@ void note_exception(const char* what);
 // another device-side inconsistency reported as PA_EDEVICE
 void note_error(const char* text);
 
+// PA_OK, or PA_EDEVICE with the failed call recorded.
+inline int hip_ok(hipError_t e, const char* what, int line) {
+  if (e == hipSuccess) return PA_OK;
+  set_last_error(what, e, line);
+  return PA_EDEVICE;
+}
+
 // Evaluate a HIP call; on failure record it and return PA_EDEVICE.
 #define PA_HIP(x)                                   \
   do {                                              \
