@@ -430,38 +430,44 @@ __global__ __launch_bounds__(256) void k_bsweep(
   }
 }
 
-// Persistent Potts pass of one lattice size.  Workgroups are single waves,
-// so the barriers inside the pass are the wave's own; an item is one
-// replica (rpw = 1), and the barrier at the end of an item keeps the next
-// item's table and lattice writes behind this item's last reads.
+// Persistent Potts pass of one lattice size, with up to four waves per
+// workgroup as in the single-population kernel: each wave takes one replica
+// (rpw = 1), all the workgroup's waves run the pass together (its barriers
+// are the workgroup's; each wave keeps its own threshold table), and a wave
+// past the queue's end runs the pass inactive.  Thread 0 takes one item per
+// wave with a single atomic and shares the base through LDS; the loop ends
+// for the whole workgroup at once, when the base passes the total.
 template <int MPR>
-__global__ __launch_bounds__(64) void k_bpotts(
+__global__ __launch_bounds__(256) void k_bpotts(
     const BatchPop* P, const BatchStep* S, const int64_t* R,
     const int32_t* cur, const int32_t* order, const int64_t* prefix,
-    unsigned long long* queue, int first, int count, int chunk,
-    uint32_t one) {
+    unsigned long long* queue, int first, int count, uint32_t one) {
   extern __shared__ uint32_t lds_words[];
+  __shared__ unsigned long long s_base;
   constexpr int cls = potts_class(MPR);
-  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6, wpb = blockDim.x >> 6;
   const int64_t* pre = prefix + first + cls;
   const int64_t total = pre[count];
-  int64_t item = 0, end = 0;
   while (true) {
-    if (item == end) {
-      int it = 0;
-      if (lane == 0) it = (int)atomicAdd(&queue[cls], (unsigned long long)chunk);
-      item = (int64_t)__shfl(it, 0, 64);
-      end = item + chunk;
-    }
-    if (item >= total) break;
-    const int64_t this_item = item++;
-    int lo = 0, hi = count - 1;  // last i with pre[i] <= this_item
+    if (threadIdx.x == 0)
+      s_base = atomicAdd(&queue[cls], (unsigned long long)wpb);
+    __syncthreads();
+    const int64_t base = (int64_t)s_base;
+    __syncthreads();  // every wave has read the base before the next take
+    if (base >= total) break;
+    const int64_t mine = base + wave;
+    const bool active = mine < total;
+    // an inactive wave looks up a valid item (the base) for its arguments
+    const int64_t it = (int64_t)__builtin_amdgcn_readfirstlane(
+        (uint32_t)(active ? mine : base));
+    int lo = 0, hi = count - 1;  // last i with pre[i] <= it
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (pre[mid] <= this_item) lo = mid;
+      if (pre[mid] <= it) lo = mid;
       else hi = mid - 1;
     }
-    const int p = order[first + lo];
+    lo = __builtin_amdgcn_readfirstlane(lo);
+    const int p = __builtin_amdgcn_readfirstlane(order[first + lo]);
     const BatchPop& q = P[p];
     const BatchStep& st = S[p];
     const int c = cur[p];
@@ -485,8 +491,8 @@ __global__ __launch_bounds__(64) void k_bpotts(
     a.init = 0;
     a.q = q.q;
     for (int d = 0; d < 4; ++d) a.Tp[d] = st.Tp[d];
-    potts_swar_pass<MPR>(a, this_item - pre[lo], true, lds_words);
-    __syncthreads();
+    potts_swar_pass<MPR>(a, it - pre[lo], active, lds_words);
+    __syncthreads();  // the next items overwrite the tables and lattices
   }
 }
 
@@ -790,8 +796,8 @@ hipError_t launch_bsweep_wr(int int8, int glass, unsigned blocks,
   return hipGetLastError();
 }
 
-// The persistent Potts pass of class k (see potts_class): as many one-wave
-// workgroups as the Ising sweep has waves.
+// The persistent Potts pass of class k (see potts_class): as many waves as
+// the Ising sweep has, up to four per workgroup.
 hipError_t launch_bpotts(int k, int blocks, int chunk, hipStream_t st,
                          const BatchPop* P, const BatchStep* S,
                          const int64_t* R, const int32_t* cur,
@@ -799,11 +805,14 @@ hipError_t launch_bpotts(int k, int blocks, int chunk, hipStream_t st,
                          unsigned long long* queue, int first, int count) {
   const int mi = k - kIsingClasses;
   const int mpr = 1 << mi;
-  const size_t shm = 72 + (size_t)64 * mpr * mpr;
-  const dim3 grid((unsigned)(4 * blocks)), block(64);
+  const int64_t N = (int64_t)64 * mpr * mpr;
+  const int wpb = N <= 4096 ? 4 : N <= 8192 ? 2 : 1;  // <= 17 KB of LDS
+  const size_t shm = (size_t)wpb * (72 + N);
+  (void)chunk;  // one item per wave per atomic
+  const dim3 grid((unsigned)(4 * blocks / wpb)), block(64 * wpb);
 #define PA_BP(m)                                                           \
   hipLaunchKernelGGL(k_bpotts<m>, grid, block, shm, st, P, S, R, cur,      \
-                     order, prefix, queue, first, count, chunk, 1u)
+                     order, prefix, queue, first, count, 1u)
   switch (mpr) {
     case 1: PA_BP(1); break;
     case 2: PA_BP(2); break;

@@ -38,8 +38,10 @@ __device__ __forceinline__ uint32_t neq16(uint32_t a, uint32_t b) {
 }
 
 // One wave's replica `rep` (active) of a workgroup whose waves all call this
-// together (the barriers are the workgroup's); lds_words holds the
-// nine-entry threshold table and then 2 NWC dwords per wave.
+// together (the barriers are the workgroup's).  lds_words holds one
+// nine-entry threshold table per wave (its replica's beta; the waves of a
+// batch workgroup may hold different populations), then 2 NWC dwords per
+// wave.
 template <int MPR>
 __device__ __forceinline__ void potts_swar_pass(const LatticeArgs& a,
                                                 int64_t rep, bool active,
@@ -50,15 +52,15 @@ __device__ __forceinline__ void potts_swar_pass(const LatticeArgs& a,
   constexpr int IT = (NWC + 63) / 64;   // row steps
   constexpr int G4 = L / 4;             // Philox groups per row
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wpb = blockDim.x >> 6;
   const int q = a.q;
   const uint32_t slot =
       __builtin_amdgcn_readfirstlane((uint32_t)(active ? rep : 0));
   // K[e] for e = dE + 4: 0 for dE <= 0, 2^32 - T[dE - 1] above
-  uint64_t* ktab = reinterpret_cast<uint64_t*>(lds_words);
-  if (threadIdx.x < 9)
-    ktab[threadIdx.x] =
-        threadIdx.x <= 4 ? 0ull : (1ull << 32) - a.Tp[threadIdx.x - 5];
-  uint32_t* A = lds_words + 18 + (size_t)wave * 2 * NWC;
+  uint64_t* ktab = reinterpret_cast<uint64_t*>(lds_words + 18 * wave);
+  if (lane < 9)
+    ktab[lane] = lane <= 4 ? 0ull : (1ull << 32) - a.Tp[lane - 5];
+  uint32_t* A = lds_words + 18 * wpb + (size_t)wave * 2 * NWC;
   uint8_t* dst = a.spins + (size_t)slot * (size_t)a.stride;
   const uint8_t* src =
       a.parent ? a.src + (size_t)a.parent[slot] * (size_t)a.stride : dst;

@@ -160,7 +160,7 @@ hipError_t launch_potts(const LatticeArgs& a, hipStream_t st) {
   const int64_t blocks = (a.R + wpb - 1) / wpb;
   if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
   const dim3 grid((unsigned)blocks), block(64 * wpb);
-  const size_t shm = (size_t)(72 + wpb * N);
+  const size_t shm = (size_t)(wpb * (72 + N));  // a table and a lattice per wave
   switch (a.L) {
     case 8: hipLaunchKernelGGL(k_potts_swar<1>, grid, block, shm, st, a); break;
     case 16: hipLaunchKernelGGL(k_potts_swar<2>, grid, block, shm, st, a); break;
