@@ -692,3 +692,43 @@ def test_results_do_not_depend_on_the_stream(pa):
         assert za == zb
     assert hip.hipStreamSynchronize(side) == 0
     assert hip.hipStreamDestroy(side) == 0
+
+
+@pytest.mark.parametrize("law", [1, 2, 3, 4])
+def test_full_size_every_law(pa, law):
+    """The 64 x 64, 65536-replica workload under the Poisson, systematic,
+    residual and multinomial laws, in the benchmark's launch configuration
+    (no wait for the new size, copies made by the sweep): every copy count,
+    the new size and ln Q exactly from the oracle's count step on the device
+    energies; a sample of new replicas through their sweeps."""
+    c = W.CONFIGS["C2"]
+    L, R, theta = c["L"], c["R"], c["theta"]
+    print("full-size law %d" % law, flush=True)
+    g = pa.Population(L, R, seed=c["seed"], resampling=law,
+                      capacity=W.deferral_capacity(R))
+    rng = np.random.default_rng(law)
+    sched = W.linear_schedule(c["beta_f"], c["K"])
+    zlast = g.free_energy()[0]
+    for i in (1, 2):
+        b = sched[i - 1]
+        E, M = g.energies()
+        n_o, Rn_o, lnQ_o = oracle.counts(L * L, E, R, b - g.beta, c["seed"],
+                                         0, i, law=law)
+        parent = np.repeat(np.arange(len(E)), n_o)
+        slots = np.sort(rng.choice(Rn_o, size=16, replace=False))
+        s_pre, E_pre, M_pre = g.replicas(parent[slots])
+        g.resample(b, wait=False)
+        g.sweep(b, theta)
+        assert g.state()[0] == Rn_o
+        assert np.array_equal(g.counts(), n_o)
+        z, dq = g.free_energy()
+        assert _close(dq, lnQ_o) and _close(z, zlast + lnQ_o)
+        zlast = z
+        s_post, E_post, M_post = g.replicas(slots)
+        for k, j in enumerate(slots):
+            so, eo, mo = oracle.sweep_replica(s_pre[k], E_pre[k], M_pre[k], b,
+                                              c["seed"], 0, i, 0, theta,
+                                              int(j))
+            assert np.array_equal(s_post[k], so), (law, i, j)
+            assert (E_post[k], M_post[k]) == (eo, mo)
+    g.close()
