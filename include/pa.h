@@ -363,8 +363,9 @@ int pa_batch_init(const pa_config* cfgs, int32_t n, void* stream,
 
 /* Advances every population through `steps` temperatures: betas[i*n + p] is
    population p's i-th next beta (non-decreasing per population); theta
-   sweeps after each resampling.  Records the observables after each step's
-   sweeps (pa_batch_trajectory).  Synchronises at the end. */
+   sweeps (0..32767, as pa_sweep allows per step) after each resampling.
+   Records the observables after each step's sweeps (pa_batch_trajectory).
+   Synchronises at the end. */
 int pa_batch_run(pa_batch* b, int32_t steps, const double* betas,
                  int32_t theta, int32_t use_graph);
 

@@ -1405,7 +1405,9 @@ static int batch_run(pa_batch* b, int steps, int use_graph) {
 
 int pa_batch_run(pa_batch* b, int32_t steps, const double* betas,
                  int32_t theta, int32_t use_graph) try {
-  if (!b || steps < 1 || !betas || theta < 0) return PA_EINVAL;
+  // theta <= 32767: the half-sweep index 2t + c fills 16 counter bits
+  if (!b || steps < 1 || !betas || theta < 0 || theta > 32767)
+    return PA_EINVAL;
   for (int64_t i = 0; i < (int64_t)steps * b->n; ++i)
     if (!std::isfinite(betas[i])) return PA_EINVAL;
   b->mode = 0;
@@ -1428,7 +1430,7 @@ int pa_batch_run_adaptive(pa_batch* b, double target, double beta_f,
                           int32_t max_steps, int32_t theta, int32_t use_graph,
                           int32_t* steps_taken) try {
   if (!b || !(target > 0.0 && target <= 1.0) || !std::isfinite(beta_f) ||
-      max_steps < 1 || theta < 0)
+      max_steps < 1 || theta < 0 || theta > 32767)
     return PA_EINVAL;
   b->mode = 1;
   b->mlp = nullptr;
@@ -1458,7 +1460,7 @@ int pa_batch_run_learned(pa_batch* b, pa_mlp* m, double target, double tol,
                          int32_t use_graph, int32_t* steps_taken,
                          int64_t* src_counts) try {
   if (!b || !m || !(target > 0.0 && target <= 1.0) || !(tol >= 0.0) ||
-      !std::isfinite(beta_f) || max_steps < 1 || theta < 0)
+      !std::isfinite(beta_f) || max_steps < 1 || theta < 0 || theta > 32767)
     return PA_EINVAL;
   if (mlp_n_in(m) != kFeatures) return PA_EINVAL;
   b->mode = 2;
