@@ -64,9 +64,6 @@ def test_strerror_and_validation_without_device():
         assert lib.pa_batch_init(C.byref(cfg), 1, None, 0,
                                  C.byref(bh)) == b.PA_EINVAL, (L, q, layout)
         assert not bh.value
-    # a batch's theta must fit the counter's 16 half-sweep bits (checked
-    # before the batch handle is used)
-    assert lib.pa_batch_run(None, 1, None, 40000, 0) == b.PA_EINVAL
     assert lib.pa_sweep(None, 0.1, 1) == b.PA_EINVAL
     assert lib.pa_resample(None, 0.1, None) == b.PA_EINVAL
 

@@ -255,3 +255,15 @@ def test_potts_populations_in_a_batch_equal_their_single_runs(pa):
             assert np.array_equal(fg, fb), tag
             g.close()
         b.close()
+
+
+def test_batch_refuses_theta_beyond_the_counter(pa):
+    """theta above 32767 would overflow the 16 half-sweep bits of the
+    random counter: the run is refused, and the batch still runs."""
+    b = pa.Batch([dict(L=8, R=100, seed=1, population_id=0)])
+    with pytest.raises(pa.PAError) as e:
+        b.run(np.array([0.1]), 40000)
+    assert e.value.code == pa.PA_EINVAL
+    b.run(np.array([0.1, 0.2]), 2)
+    assert b.state(0)[2] == 2
+    b.close()
