@@ -47,3 +47,17 @@ def test_batched_instances_cover_the_stated_ranges():
     assert [i["population_id"] for i in inst] == list(range(64))
     again = W.batched_glass_instances()
     assert all(np.array_equal(a["J"], b["J"]) for a, b in zip(inst, again))
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus 2 exits at once with a message
+    (no device is touched)."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"),
+                        "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120, cwd=root)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and "--gpus 1" in r.stderr
