@@ -127,3 +127,23 @@ def test_load_rejects_bad_files_before_any_device_work(tmp_path):
     assert lib.pa_load(p.encode(), None, C.byref(h)) == b.PA_EIO
     assert lib.pa_save(None, p.encode()) == b.PA_EINVAL
     assert lib.pa_strerror(b.PA_EIO).decode().startswith("population file")
+
+
+def test_product_path_fails_loudly_without_the_library():
+    """Without libpa.so the binding raises: there is no CPU fallback, and no
+    population can be made (run in a subprocess so that the loaded library
+    of this process is untouched)."""
+    import subprocess
+    import sys
+    code = ("import paper_2006_00561_amd.binding as b\n"
+            "b.SO_PATH = '/nonexistent/libpa.so'\n"
+            "b._lib = None\n"
+            "try:\n"
+            "    b.Population(8, 10)\n"
+            "except RuntimeError as e:\n"
+            "    print('raised:', e)\n"
+            "else:\n"
+            "    print('computed without the library')\n")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True,
+                       text=True, timeout=120, cwd=ROOT)
+    assert "raised:" in r.stdout and "no fallback" in r.stdout, r.stdout
