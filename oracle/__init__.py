@@ -17,6 +17,8 @@ from .oracle import (  # noqa: F401
     OK,
     POISSON,
     RESIDUAL,
+    RNG_PLANES,
+    RNG_WORD,
     SYSTEMATIC,
     OraclePA,
     build,
@@ -26,6 +28,7 @@ from .oracle import (  # noqa: F401
     lib,
     philox4x32_10,
     poisson_draw,
+    site_draw,
     sweep_potts_replica,
     sweep_replica,
 )

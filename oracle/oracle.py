@@ -28,14 +28,15 @@ def build(force: bool = True, mutant: int = 0, out: str = "") -> str:
     builds a planted-mistake variant into `out` instead."""
     if mutant:
         cmd = ["gcc", "-O2", "-ffp-contract=off", "-std=c11", "-fPIC",
-               "-shared", "-DORC_MUTANT=%d" % mutant, "-o", out, _SRC, "-lm"]
+               "-shared", "-pthread", "-DORC_MUTANT=%d" % mutant, "-o", out, _SRC,
+               "-lm"]
         subprocess.run(cmd, check=True)
         return out
     if force or not os.path.exists(_SO) or (
             os.path.getmtime(_SO) < os.path.getmtime(_SRC)):
         tmp = _SO + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-O2", "-ffp-contract=off", "-std=c11", "-Wall",
-               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+               "-fPIC", "-shared", "-pthread", "-o", tmp, _SRC, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _SO)
     return _SO
@@ -79,6 +80,7 @@ def lib():
         L.orc_destroy.restype = None
         L.orc_resample.argtypes = [P, C.c_double, C.POINTER(C.c_int64)]
         L.orc_sweep.argtypes = [P, C.c_int]
+        L.orc_sweep_threads.argtypes = [P, C.c_int, C.c_int]
         L.orc_observables.argtypes = [P, C.POINTER(Obs)]
         L.orc_free_energy.argtypes = [P, C.POINTER(C.c_double),
                                       C.POINTER(C.c_double)]
@@ -121,6 +123,15 @@ def lib():
             C.c_int, C.c_int, i8p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
             C.c_double, C.c_uint64, C.c_uint32, C.c_int, C.c_int, C.c_int,
             C.c_uint32]
+        L.orc_set_rng_mode.argtypes = [P, C.c_int]
+        L.orc_site_draw.argtypes = [C.c_int, C.c_int, C.c_uint64, C.c_uint32,
+                                    C.c_int, C.c_int, C.c_uint32, C.c_int,
+                                    C.c_int]
+        L.orc_site_draw.restype = C.c_uint32
+        L.orc_sweep_replica_rng.argtypes = [
+            C.c_int, P, i8p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+            C.c_double, C.c_uint64, C.c_uint32, C.c_int, C.c_int, C.c_int,
+            C.c_uint32, C.c_int]
         L.orc_overlap.argtypes = [P, C.c_double, C.POINTER(C.c_double)]
         L.orc_bisect_dbeta.argtypes = [P, C.c_double, C.c_double,
                                        C.POINTER(C.c_double)]
@@ -161,6 +172,13 @@ def energy(spins, J=None):
 
 
 NEAREST, POISSON, SYSTEMATIC, RESIDUAL, MULTINOMIAL = 0, 1, 2, 3, 4
+RNG_WORD, RNG_PLANES = 0, 1
+
+
+def site_draw(mode, L, seed, pop, step, half_sweep, slot, y, k):
+    """The 32-bit Metropolis random number of colour site k of row y."""
+    return int(lib().orc_site_draw(mode, L, seed, pop, step, half_sweep, slot,
+                                   y, k))
 
 
 def poisson_draw(rho, r):
@@ -188,15 +206,16 @@ def family_stats(fam, n0):
             "rho_s": rs.value}
 
 
-def sweep_replica(spins, E, M, beta, seed, pop, step, t0, theta, slot, J=None):
+def sweep_replica(spins, E, M, beta, seed, pop, step, t0, theta, slot, J=None,
+                  rng_mode=RNG_WORD):
     """theta sweeps of one replica; returns (spins, E, M)."""
     s = np.array(spins, dtype=np.int8, copy=True, order="C")
     L = s.shape[-1]
     Jc, jp = _jptr(J)
     e, m = C.c_int32(int(E)), C.c_int32(int(M))
-    _check(lib().orc_sweep_replica(L, jp, s, C.byref(e), C.byref(m), beta,
-                                   seed, pop, step, t0, theta, slot),
-           "sweep_replica")
+    _check(lib().orc_sweep_replica_rng(L, jp, s, C.byref(e), C.byref(m), beta,
+                                       seed, pop, step, t0, theta, slot,
+                                       rng_mode), "sweep_replica")
     return s, e.value, m.value
 
 
@@ -216,7 +235,7 @@ class OraclePA:
     """One population on the CPU oracle."""
 
     def __init__(self, L, R_target, seed=1, pop=0, J=None, capacity=0,
-                 law=NEAREST, q=0):
+                 law=NEAREST, q=0, rng_mode=RNG_WORD):
         """q = 0: Ising spins (ferromagnet or the couplings J); q >= 2: the
         q-state Potts ferromagnet."""
         self.L, self.N, self.q = L, L * L, q
@@ -231,6 +250,8 @@ class OraclePA:
         self._h = h
         if law != NEAREST:
             _check(lib().orc_set_resampling(h, law), "set_resampling")
+        if rng_mode != RNG_WORD:
+            _check(lib().orc_set_rng_mode(h, rng_mode), "set_rng_mode")
 
     def close(self):
         if self._h:
@@ -271,8 +292,11 @@ class OraclePA:
         rc = lib().orc_resample(self._h, beta_next, C.byref(Rn))
         return rc, Rn.value
 
-    def sweep(self, theta):
-        _check(lib().orc_sweep(self._h, theta), "sweep")
+    def sweep(self, theta, threads=1):
+        if threads > 1:
+            _check(lib().orc_sweep_threads(self._h, theta, threads), "sweep")
+        else:
+            _check(lib().orc_sweep(self._h, theta), "sweep")
 
     def observables(self):
         o = Obs()

@@ -50,12 +50,14 @@
 #include "pa_oracle.h"
 
 #include <math.h>
+#include <pthread.h>
 #include <stdlib.h>
 #include <string.h>
 
 #define DOMAIN_INIT 1u
 #define DOMAIN_MCMC 2u
 #define DOMAIN_RESAMPLE 3u
+#define DOMAIN_MCMC_PLANES 5u
 
 struct orc_pa {
   int L, N;
@@ -72,6 +74,7 @@ struct orc_pa {
   int step;
   int sweeps_at_step;
   uint64_t shuffle_seed;
+  int rng_mode;     /* ORC_RNG_WORD (default) or ORC_RNG_PLANES */
   int law;          /* ORC_NEAREST or ORC_POISSON */
   int q;            /* 0: Ising spins +-1; 2..16: Potts states 0..q-1 */
   uint32_t* fam;    /* family of every replica: the slot of its ancestor in
@@ -487,6 +490,50 @@ int orc_resample(orc_pa* p, double beta_next, int64_t* R_new) {
 
 /* ---------------------------------------------------------------- sweeps */
 
+/* The 32-bit random number of the colour site with colour rank k (k = x/2)
+   of row y in half sweep hs of step `step`, replica slot `slot`.
+   ORC_RNG_WORD: word k mod 4 of MCMC group y*ceil(L/8) + k/4.
+   ORC_RNG_PLANES: r = B * 2^24 + floor(w / 2^8), with w the ORC_RNG_WORD
+   number of the same site and B a byte of bit planes: the Philox block of
+   domain MCMC_PLANES, group y*ceil(L/32) + k/16 (same step, half sweep,
+   slot and population) holds eight planes, plane m = 2i + h (i = 0..3 the
+   output word, h = 0 or 1) carrying bit 7 - m of B for every site of that
+   group, as bit 2 (k mod 16) + h of output word i.  Both parts are
+   independent uniform bits, so r is uniform on [0, 2^32) as in the default
+   mode: the acceptance probabilities are the same.  A sweep that compares
+   B with the top byte of the threshold first needs w only when they are
+   equal. */
+static uint32_t site_draw(int mode, int L, uint64_t seed, uint32_t pop,
+                          uint32_t step, uint32_t hs, uint32_t slot, int y,
+                          int k) {
+  const int G8 = (L + 7) / 8;
+  uint32_t w = draw_word(seed, DOMAIN_MCMC, (uint32_t)(y * G8 + k / 4), step,
+                         hs, slot, pop, k % 4);
+  if (mode != ORC_RNG_PLANES) return w;
+  const int W32 = (L + 31) / 32;
+  uint32_t ctr[4], key[2], out[4];
+  ctr[0] = (DOMAIN_MCMC_PLANES << 28) | (uint32_t)(y * W32 + k / 16);
+  ctr[1] = (step << 16) | hs;
+  ctr[2] = slot;
+  ctr[3] = pop;
+  key[0] = (uint32_t)(seed & 0xFFFFFFFFu);
+  key[1] = (uint32_t)(seed >> 32);
+  orc_philox4x32_10(ctr, key, out);
+  uint32_t B = 0;
+  for (int m = 0; m < 8; ++m) {
+    int pos = (ORC_MUTANT == 18) ? (m & 1) : 2 * (k % 16) + (m & 1);
+    uint32_t bit = (out[m / 2] >> pos) & 1u;
+    B |= bit << (7 - m);
+  }
+  return (B << 24) | (w >> 8);
+}
+
+uint32_t orc_site_draw(int mode, int L, uint64_t seed, uint32_t pop,
+                       int step, int half_sweep, uint32_t slot, int y, int k) {
+  return site_draw(mode, L, seed, pop, (uint32_t)step, (uint32_t)half_sweep,
+                   slot, y, k);
+}
+
 static uint64_t splitmix(uint64_t* s) {
   uint64_t z = (*s += 0x9E3779B97F4A7C15ull);
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -503,8 +550,7 @@ static uint64_t splitmix(uint64_t* s) {
 static void sweep_one(int L, const int8_t* J, int8_t* s, int32_t* E,
                       int32_t* M, uint64_t seed, uint32_t pop, int step,
                       int t0, int theta, uint32_t slot, uint64_t T4,
-                      uint64_t T8, uint64_t shuffle_seed) {
-  int G8 = (L + 7) / 8;
+                      uint64_t T8, uint64_t shuffle_seed, int mode) {
   int half = L * L / 2;
   int* order = (int*)malloc((size_t)half * sizeof(int));
   for (int t = 0; t < theta; ++t) {
@@ -537,9 +583,8 @@ static void sweep_one(int L, const int8_t* J, int8_t* s, int32_t* E,
                     s[yu * L + x] < 0);
         int dE = 8 - 4 * a;
         int k = x / 2;
-        uint32_t r = draw_word(seed, DOMAIN_MCMC, (uint32_t)(y * G8 + k / 4),
-                               (uint32_t)step, (uint32_t)(2 * tt + c), slot,
-                               pop, k % 4);
+        uint32_t r = site_draw(mode, L, seed, pop, (uint32_t)step,
+                               (uint32_t)(2 * tt + c), slot, y, k);
         int accept;
         if (dE <= 0) accept = 1;
         else if (ORC_MUTANT == 4) accept = (uint64_t)r < (dE == 4 ? T8 : T4);
@@ -615,16 +660,26 @@ static void thresholds(double beta, uint64_t* T4, uint64_t* T8) {
   *T8 = (uint64_t)floor(ldexp(exp(-(beta * 8.0)), 32));
 }
 
-int orc_sweep_replica(int L, const int8_t* J, int8_t* spins, int32_t* E,
-                      int32_t* M, double beta, uint64_t seed, uint32_t pop,
-                      int step, int t0, int theta, uint32_t slot) {
+int orc_sweep_replica_rng(int L, const int8_t* J, int8_t* spins,
+                          int32_t* E, int32_t* M, double beta, uint64_t seed,
+                          uint32_t pop, int step, int t0, int theta,
+                          uint32_t slot, int rng_mode) {
   if (L < 4 || L > 128 || (L % 2) || !spins || !E || !M || theta < 0 ||
-      t0 < 0 || t0 + theta > 32767 || !isfinite(beta))
+      t0 < 0 || t0 + theta > 32767 || !isfinite(beta) ||
+      (rng_mode != ORC_RNG_WORD && rng_mode != ORC_RNG_PLANES))
     return ORC_EINVAL;
   uint64_t T4, T8;
   thresholds(beta, &T4, &T8);
-  sweep_one(L, J, spins, E, M, seed, pop, step, t0, theta, slot, T4, T8, 0);
+  sweep_one(L, J, spins, E, M, seed, pop, step, t0, theta, slot, T4, T8, 0,
+            rng_mode);
   return ORC_OK;
+}
+
+int orc_sweep_replica(int L, const int8_t* J, int8_t* spins, int32_t* E,
+                      int32_t* M, double beta, uint64_t seed, uint32_t pop,
+                      int step, int t0, int theta, uint32_t slot) {
+  return orc_sweep_replica_rng(L, J, spins, E, M, beta, seed, pop, step, t0,
+                               theta, slot, ORC_RNG_WORD);
 }
 
 int orc_sweep_potts_replica(int L, int q, int8_t* spins, int32_t* E,
@@ -658,7 +713,62 @@ int orc_sweep(orc_pa* p, int theta) {
   for (int64_t j = 0; j < p->R; ++j)
     sweep_one(p->L, p->J, p->spins + (size_t)j * p->N, &p->E[j], &p->M[j],
               p->seed, p->pop, p->step, p->sweeps_at_step, theta, (uint32_t)j,
-              T4, T8, p->shuffle_seed);
+              T4, T8, p->shuffle_seed, p->rng_mode);
+  p->sweeps_at_step += theta;
+  return ORC_OK;
+}
+
+/* The same sweeps with the replicas split into nthreads contiguous ranges,
+   one POSIX thread each (for timing the oracle on every host core).  Each
+   replica's random numbers are keyed by its own slot, so the result is the
+   single-threaded one bit for bit. */
+typedef struct {
+  orc_pa* p;
+  int theta;
+  int64_t j0, j1;
+  uint64_t T4, T8;
+} sweep_range;
+
+static void* sweep_range_run(void* arg) {
+  sweep_range* a = (sweep_range*)arg;
+  orc_pa* p = a->p;
+  for (int64_t j = a->j0; j < a->j1; ++j)
+    sweep_one(p->L, p->J, p->spins + (size_t)j * p->N, &p->E[j], &p->M[j],
+              p->seed, p->pop, p->step, p->sweeps_at_step, a->theta,
+              (uint32_t)j, a->T4, a->T8, p->shuffle_seed, p->rng_mode);
+  return NULL;
+}
+
+int orc_sweep_threads(orc_pa* p, int theta, int nthreads) {
+  if (!p || theta < 0 || nthreads < 1 || nthreads > 1024) return ORC_EINVAL;
+  if (p->q || nthreads == 1) return orc_sweep(p, theta);
+  if (p->sweeps_at_step + theta > 32767) return ORC_EINVAL;
+  uint64_t T4, T8;
+  thresholds(p->beta, &T4, &T8);
+  sweep_range* a = (sweep_range*)calloc((size_t)nthreads, sizeof(sweep_range));
+  pthread_t* th = (pthread_t*)calloc((size_t)nthreads, sizeof(pthread_t));
+  int* started = (int*)calloc((size_t)nthreads, sizeof(int));
+  if (!a || !th || !started) {
+    free(a);
+    free(th);
+    free(started);
+    return ORC_ENOMEM;
+  }
+  for (int i = 0; i < nthreads; ++i) {
+    a[i].p = p;
+    a[i].theta = theta;
+    a[i].j0 = p->R * i / nthreads;
+    a[i].j1 = p->R * (i + 1) / nthreads;
+    a[i].T4 = T4;
+    a[i].T8 = T8;
+    started[i] = pthread_create(&th[i], NULL, sweep_range_run, &a[i]) == 0;
+    if (!started[i]) sweep_range_run(&a[i]);
+  }
+  for (int i = 0; i < nthreads; ++i)
+    if (started[i]) pthread_join(th[i], NULL);
+  free(a);
+  free(th);
+  free(started);
   p->sweeps_at_step += theta;
   return ORC_OK;
 }
@@ -834,6 +944,13 @@ int orc_set_resampling(orc_pa* p, int law) {
 
 void orc_set_visit_shuffle(orc_pa* p, uint64_t shuffle_seed) {
   if (p) p->shuffle_seed = shuffle_seed;
+}
+
+int orc_set_rng_mode(orc_pa* p, int mode) {
+  if (!p || p->q || (mode != ORC_RNG_WORD && mode != ORC_RNG_PLANES))
+    return ORC_EINVAL;
+  p->rng_mode = mode;
+  return ORC_OK;
 }
 
 /* ------------------------------------------------------ adaptive schedule */

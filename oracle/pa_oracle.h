@@ -79,6 +79,9 @@ int orc_start_heating(orc_pa* p, double beta0);
 int orc_resample(orc_pa* p, double beta_next, int64_t* R_new);
 /* theta checkerboard Metropolis sweeps at the current beta. */
 int orc_sweep(orc_pa* p, int theta);
+/* The same with the replicas split over nthreads threads (contiguous slot
+   ranges); identical results, for timing on every host core. */
+int orc_sweep_threads(orc_pa* p, int theta, int nthreads);
 int orc_observables(const orc_pa* p, orc_obs* out);
 int orc_free_energy(const orc_pa* p, double* lnZ, double* lnQ_last);
 
@@ -137,6 +140,23 @@ int orc_sweep_potts_replica(int L, int q, int8_t* spins, int32_t* E,
                             int32_t* M, double beta, uint64_t seed,
                             uint32_t pop, int step, int t0, int theta,
                             uint32_t slot);
+
+/* Source of the Metropolis random numbers of the Ising sweeps (the
+   acceptance rule r < T is the same in both): ORC_RNG_WORD, one Philox word
+   per site (the default); ORC_RNG_PLANES, r = B 2^24 + floor(w / 2^8) with
+   B a byte of bit planes shared out of one Philox block per 16 colour
+   sites and w the site's default word (see site_draw in pa_oracle.c).
+   orc_site_draw returns the number a site uses; orc_sweep_replica_rng is
+   orc_sweep_replica with a mode. */
+#define ORC_RNG_WORD 0
+#define ORC_RNG_PLANES 1
+int orc_set_rng_mode(orc_pa* p, int mode);
+uint32_t orc_site_draw(int mode, int L, uint64_t seed, uint32_t pop,
+                       int step, int half_sweep, uint32_t slot, int y, int k);
+int orc_sweep_replica_rng(int L, const int8_t* J, int8_t* spins,
+                          int32_t* E, int32_t* M, double beta, uint64_t seed,
+                          uint32_t pop, int step, int t0, int theta,
+                          uint32_t slot, int rng_mode);
 
 /* Overlap of successive energy distributions for a step dbeta and the
    bisection that picks the largest step meeting a target overlap. */

@@ -157,3 +157,21 @@ def test_tracked_energy_equals_recomputed_after_annealing():
         s, E, M = p.population()
         for j in range(len(E)):
             assert (E[j], M[j]) == oracle.energy(s[j], J)
+
+
+def test_threaded_sweep_equals_single_thread():
+    """The replica-parallel sweep (used to time the oracle on all host
+    cores) gives the single-threaded result bit for bit."""
+    import oracle as O
+    import pa_workloads as W
+    a = O.OraclePA(8, 333, seed=5)
+    b = O.OraclePA(8, 333, seed=5)
+    for beta in W.linear_schedule(0.6, 4):
+        assert a.resample(beta) == b.resample(beta)
+        a.sweep(3)
+        b.sweep(3, threads=7)
+    sa, Ea, Ma = a.population()
+    sb, Eb, Mb = b.population()
+    assert np.array_equal(sa, sb) and np.array_equal(Ea, Eb)
+    assert np.array_equal(Ma, Mb)
+    assert a.free_energy() == b.free_energy()

@@ -49,6 +49,9 @@ CASES = {
          ["test_oracle_families.py::test_family_stats_closed_forms"]),
     17: ("a copy takes its parent's slot instead of its parent's family",
          ["test_oracle_families.py::test_families_compose_over_resamplings"]),
+    18: ("every colour site of a plane group reads the same plane bits",
+         ["test_oracle_rng_planes.py::test_plane_draws_are_fair_and_independent",
+          "test_oracle_rng_planes.py::test_planes_metropolis_samples_boltzmann_L4"]),
 }
 
 
