@@ -303,6 +303,28 @@ int pa_get_config(pa_ctx* c, pa_config* out);
 int pa_weighted_average(int32_t M, const double* lnZ, const double* values,
                         int32_t k, double* out, double* lnZ_out);
 
+/* Weighted averaging of the observables themselves (Sec. 4, Large scale
+   testing): M populations at the same beta (obs[m].beta all equal, else
+   PA_EINVAL), each described by its pa_obs (exact integer sums sumE,
+   sumE2, sumAbsM, sumM2 over its R replicas) and its ln Z, combined with
+   weights w_m = Z_m / sum Z.  <E> = sum w_m sumE_m / R_m; the energy
+   variance is sum w_m Var_m + sum w_m (<E>_m - <E>)^2 (law of total
+   variance), where Var_m = (R sumE2 - sumE^2) / R^2 is formed exactly in
+   128-bit integers per population; e = <E>/N, |m| = <|M|>/N,
+   m2 = <M^2>/N^2, C = beta^2 Var(E) / N, lnZ = ln((1/M) sum Z_m).  Host
+   double precision, sums in increasing m.  No device work.  PA_EINVAL for
+   M < 1, N < 1, a population with R < 1 or a non-finite lnZ. */
+typedef struct {
+  int32_t M;          /* populations combined                               */
+  int64_t R;          /* their replicas in total                            */
+  double beta;
+  double e, abs_m, m2, C;
+  double varE;        /* combined variance of E                             */
+  double lnZ;         /* ln((1/M) sum_m Z_m)                                 */
+} pa_combined;
+int pa_weighted_observables(int32_t M, const double* lnZ, const pa_obs* obs,
+                            int32_t N, pa_combined* out);
+
 /* Per-kernel-class device timing with HIP events on the context's stream.
    classes: PA_TIMING_ALL times every class, otherwise a bit mask of the
    classes to time (bit PA_K_SWEEP = 1 << PA_K_SWEEP, ...); a nonzero value

@@ -53,6 +53,15 @@ class pa_family(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class pa_combined(C.Structure):
+    _fields_ = [("M", C.c_int32), ("R", C.c_int64), ("beta", C.c_double),
+                ("e", C.c_double), ("abs_m", C.c_double), ("m2", C.c_double),
+                ("C", C.c_double), ("varE", C.c_double), ("lnZ", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class pa_timing(C.Structure):
     _fields_ = [("ms", C.c_double * 6), ("launches", C.c_int64 * 6),
                 ("bytes", C.c_int64 * 6), ("attempts", C.c_int64)]
@@ -103,6 +112,8 @@ def lib():
             "pa_start_heating": ([P, d], C.c_int),
             "pa_weighted_average": ([i32, P, P, i32, P, C.POINTER(d)],
                                     C.c_int),
+            "pa_weighted_observables": ([i32, P, P, i32,
+                                         C.POINTER(pa_combined)], C.c_int),
             "pa_get_families": ([P, P, i64, C.POINTER(i64), C.POINTER(i64)],
                                 C.c_int),
             "pa_family_summary": ([P, i64, i64, C.POINTER(pa_family)],
@@ -412,15 +423,19 @@ def weighted_average(lnZ, values):
 
 
 def combine_observables(lnZ, obs, N):
-    """Energy per spin, |m|, m^2 and specific heat of M independent
-    populations together (weighted averaging), formed from the weighted
-    linear averages <E>, <E^2>, <|M|>, <M^2> of each population's pa_obs."""
-    vals = [[o["sumE"] / o["R"], o["sumE2"] / o["R"], o["sumAbsM"] / o["R"],
-             o["sumM2"] / o["R"]] for o in obs]
-    (E1, E2, A1, M2), lz = weighted_average(lnZ, vals)
-    beta = obs[0]["beta"]
-    return {"e": E1 / N, "abs_m": A1 / N, "m2": M2 / (N * N),
-            "C": beta * beta * (E2 - E1 * E1) / N, "lnZ": lz}
+    """Energy per spin, |m|, m^2, the energy variance and the specific heat
+    of M independent populations together (pa_weighted_observables), from
+    each population's pa_obs (a dict as returned by observables())."""
+    z = np.ascontiguousarray(lnZ, np.float64)
+    arr = (pa_obs * len(obs))()
+    for i, o in enumerate(obs):
+        for k, _ in pa_obs._fields_:
+            setattr(arr[i], k, o[k])
+    out = pa_combined()
+    _ck(lib().pa_weighted_observables(len(z), _ptr(z), arr, int(N),
+                                      C.byref(out)),
+        "pa_weighted_observables")
+    return out.as_dict()
 
 
 class Batch:

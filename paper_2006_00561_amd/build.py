@@ -29,21 +29,47 @@ def hipcc() -> str:
     return p
 
 
+def _flags() -> list:
+    return ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
+            "-ffp-contract=off", "-Wall", "-Wno-unused-function",
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-I", INCLUDE, "-I", CSRC]
+
+
 def build(verbose: bool = False) -> str:
-    """Compile libpa.so (always recompiles) and return its path."""
-    tmp = SO + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
-           "-shared", "-ffp-contract=off", "-Wall", "-Wno-unused-function",
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-I", INCLUDE, "-I", CSRC, "-o", tmp]
-    cmd += [os.path.join(CSRC, s) for s in SOURCES]
+    """Compile libpa.so (always recompiles) and return its path.  Each
+    source is compiled to an object of its own in parallel, then linked."""
+    from concurrent.futures import ThreadPoolExecutor
+    tag = "%d" % os.getpid()
+    objs = [os.path.join(HERE, "_obj_%s_%s.o" % (os.path.splitext(s)[0], tag))
+            for s in SOURCES]
+    cmds = [[hipcc()] + _flags() + ["-c", "-o", o, os.path.join(CSRC, s)]
+            for s, o in zip(SOURCES, objs)]
     if verbose:
-        print(" ".join(cmd), flush=True)
-    r = subprocess.run(cmd, capture_output=True, text=True, cwd=ROOT)
-    if r.returncode != 0:
-        sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building libpa.so")
-    os.replace(tmp, SO)
+        for c in cmds:
+            print(" ".join(c), flush=True)
+    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", "0") or 0)
+                      or (os.cpu_count() or 1)))
+    try:
+        with ThreadPoolExecutor(jobs) as ex:
+            res = list(ex.map(lambda c: subprocess.run(
+                c, capture_output=True, text=True, cwd=ROOT), cmds))
+        for r in res:
+            if r.returncode != 0:
+                sys.stderr.write(r.stdout + r.stderr)
+                raise RuntimeError("hipcc failed building libpa.so")
+        tmp = SO + ".tmp" + tag
+        link = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o",
+                tmp] + objs
+        r = subprocess.run(link, capture_output=True, text=True, cwd=ROOT)
+        if r.returncode != 0:
+            sys.stderr.write(r.stdout + r.stderr)
+            raise RuntimeError("hipcc failed linking libpa.so")
+        os.replace(tmp, SO)
+    finally:
+        for o in objs:
+            if os.path.exists(o):
+                os.remove(o)
     return SO
 
 

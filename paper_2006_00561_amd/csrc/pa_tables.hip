@@ -285,6 +285,71 @@ extern "C" int pa_weighted_average(int32_t M, const double* lnZ,
   return PA_EDEVICE;
 }
 
+// Observables of M independent populations at one beta, combined with the
+// weights Z_m / sum Z (Sec. 4, Large scale testing).  Each population's
+// mean energy is its exact integer sum over its size; its energy variance
+// (R sum E^2 - (sum E)^2) / R^2 is formed in 128-bit integers before the
+// one conversion, so no population's variance loses digits to
+// cancellation.  The combined variance is the law of total variance:
+// the weighted mean of the population variances plus the weighted spread
+// of the population means about the combined mean.  Sums run over
+// ascending m.
+extern "C" int pa_weighted_observables(int32_t M, const double* lnZ,
+                                       const pa_obs* obs, int32_t N,
+                                       pa_combined* out) try {
+  if (M < 1 || !lnZ || !obs || !out || N < 1) return PA_EINVAL;
+  double mx = lnZ[0];
+  for (int32_t m = 0; m < M; ++m) {
+    if (!std::isfinite(lnZ[m]) || obs[m].R < 1) return PA_EINVAL;
+    if (obs[m].beta != obs[0].beta) return PA_EINVAL;
+    if (lnZ[m] > mx) mx = lnZ[m];
+  }
+  std::vector<double> w((size_t)M), mu((size_t)M), var((size_t)M);
+  double s = 0.0, a = 0.0, am = 0.0, m2 = 0.0;
+  int64_t Rtot = 0;
+  for (int32_t m = 0; m < M; ++m) {
+    const pa_obs& o = obs[m];
+    const double Rd = (double)o.R;
+    w[(size_t)m] = std::exp(lnZ[m] - mx);
+    s = s + w[(size_t)m];
+    mu[(size_t)m] = (double)o.sumE / Rd;
+    const __int128 v = (__int128)o.R * (__int128)o.sumE2 -
+                       (__int128)o.sumE * (__int128)o.sumE;
+    var[(size_t)m] = (double)v / (Rd * Rd);
+    a = a + w[(size_t)m] * mu[(size_t)m];
+    am = am + w[(size_t)m] * ((double)o.sumAbsM / Rd);
+    m2 = m2 + w[(size_t)m] * ((double)o.sumM2 / Rd);
+    Rtot += o.R;
+  }
+  const double E1 = a / s;
+  double within = 0.0, between = 0.0;
+  for (int32_t m = 0; m < M; ++m) {
+    const double d = mu[(size_t)m] - E1;
+    within = within + w[(size_t)m] * var[(size_t)m];
+    between = between + w[(size_t)m] * (d * d);
+  }
+  const double varE = within / s + between / s;
+  const double Nd = (double)N, beta = obs[0].beta;
+  out->M = M;
+  out->R = Rtot;
+  out->beta = beta;
+  out->e = E1 / Nd;
+  out->abs_m = (am / s) / Nd;
+  out->m2 = (m2 / s) / (Nd * Nd);
+  out->varE = varE;
+  out->C = ((beta * beta) * varE) / Nd;
+  out->lnZ = mx + std::log(s / (double)M);
+  return PA_OK;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
+} catch (...) {
+  ::pa::note_exception("unknown exception");
+  return PA_EDEVICE;
+}
+
 // Family statistics (the diagnostic that accompanies weighted averaging in
 // population annealing): c_i members in family i of n0, R = sum c_i,
 // nu_i = c_i / R.  The mean square family size R sum nu_i^2 is

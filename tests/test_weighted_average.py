@@ -53,3 +53,74 @@ def test_invariants(B):
     # bad arguments
     with pytest.raises(B.PAError):
         B.weighted_average(np.array([np.inf, 0.0]), vals[:2])
+
+
+def _combined_definition(lnZ, obs, N):
+    """The combined observables from their definition in 60-digit
+    arithmetic: weights Z_m / sum Z, <E^k> = sum_m w_m sumE^k_m / R_m,
+    Var(E) = <E^2> - <E>^2, C = beta^2 Var(E) / N."""
+    import mpmath as mp
+    mp.mp.dps = 60
+    z = [mp.mpf(v) for v in lnZ]
+    mx = max(z)
+    Z = [mp.e ** (v - mx) for v in z]
+    S = sum(Z)
+    w = [v / S for v in Z]
+    E1 = sum(wi * mp.mpf(o["sumE"]) / o["R"] for wi, o in zip(w, obs))
+    E2 = sum(wi * mp.mpf(o["sumE2"]) / o["R"] for wi, o in zip(w, obs))
+    A1 = sum(wi * mp.mpf(o["sumAbsM"]) / o["R"] for wi, o in zip(w, obs))
+    M2 = sum(wi * mp.mpf(o["sumM2"]) / o["R"] for wi, o in zip(w, obs))
+    beta = mp.mpf(obs[0]["beta"])
+    var = E2 - E1 * E1
+    return {"e": E1 / N, "abs_m": A1 / N, "m2": M2 / (N * N), "varE": var,
+            "C": beta * beta * var / N,
+            "lnZ": mx + mp.log(S / len(z))}
+
+
+def _fake_obs(rng, N, R, beta, spread):
+    """Integer sums of a population of R energies near -1.6 N (a narrow
+    ordered-phase distribution: the variance is a tiny difference of two
+    large moments, where a double-precision subtraction loses digits)."""
+    E = np.round(-1.6 * N + rng.normal(0, spread, R)).astype(np.int64)
+    M = rng.integers(-N, N + 1, R)
+    return {"R": R, "beta": beta, "e": 0.0, "abs_m": 0.0, "m2": 0.0,
+            "C": 0.0, "sumE": int(E.sum()), "sumE2": int((E * E).sum()),
+            "sumAbsM": int(np.abs(M).sum()), "sumM2": int((M * M).sum()),
+            "Emin": int(E.min()), "Emax": int(E.max())}
+
+
+def test_combined_observables_match_the_definition(B):
+    rng = np.random.default_rng(3)
+    for M, N, R, spread in ((1, 4096, 65536, 40.0), (16, 4096, 20480, 30.0),
+                            (48, 256, 1000, 5.0), (5, 16384, 4096, 0.7)):
+        beta = 0.4406868
+        obs = [_fake_obs(rng, N, R + 17 * m, beta, spread) for m in range(M)]
+        lnZ = 3000.0 + rng.normal(0, 0.5, M)
+        got = B.combine_observables(lnZ, obs, N)
+        ref = _combined_definition(lnZ, obs, N)
+        for k in ("e", "abs_m", "m2", "varE", "C", "lnZ"):
+            assert abs(got[k] - float(ref[k])) <= 1e-12 * abs(float(ref[k])), k
+        assert got["M"] == M and got["R"] == sum(o["R"] for o in obs)
+
+
+def test_combined_observables_single_population_equals_its_own(B):
+    # one population: the combination is that population's own observables
+    rng = np.random.default_rng(4)
+    N = 1024
+    o = _fake_obs(rng, N, 5000, 0.3, 10.0)
+    got = B.combine_observables([17.0], [o], N)
+    R = o["R"]
+    var = (R * o["sumE2"] - o["sumE"] ** 2) / R ** 2   # exact integers
+    assert got["e"] == o["sumE"] / R / N
+    assert abs(got["varE"] - var) <= 1e-15 * var
+    assert got["lnZ"] == 17.0
+
+
+def test_combined_observables_reject_bad_input(B):
+    rng = np.random.default_rng(5)
+    a = _fake_obs(rng, 256, 100, 0.3, 3.0)
+    b = _fake_obs(rng, 256, 100, 0.31, 3.0)
+    with pytest.raises(B.PAError):      # two temperatures
+        B.combine_observables([0.0, 0.0], [a, b], 256)
+    with pytest.raises(B.PAError):
+        B.combine_observables([np.nan], [a], 256)
