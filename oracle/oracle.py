@@ -175,10 +175,10 @@ NEAREST, POISSON, SYSTEMATIC, RESIDUAL, MULTINOMIAL = 0, 1, 2, 3, 4
 RNG_WORD, RNG_PLANES = 0, 1
 
 
-def site_draw(mode, L, seed, pop, step, half_sweep, slot, y, k):
-    """The 32-bit Metropolis random number of colour site k of row y."""
+def site_draw(mode, L, seed, pop, step, half_sweep, slot, y, x):
+    """The 32-bit Metropolis random number of site (x, y)."""
     return int(lib().orc_site_draw(mode, L, seed, pop, step, half_sweep, slot,
-                                   y, k))
+                                   y, x))
 
 
 def poisson_draw(rho, r):

@@ -490,29 +490,31 @@ int orc_resample(orc_pa* p, double beta_next, int64_t* R_new) {
 
 /* ---------------------------------------------------------------- sweeps */
 
-/* The 32-bit random number of the colour site with colour rank k (k = x/2)
-   of row y in half sweep hs of step `step`, replica slot `slot`.
+/* The 32-bit random number of the colour site (x, y) in half sweep hs of
+   step `step`, replica slot `slot`; k = x/2 is its colour rank in the row.
    ORC_RNG_WORD: word k mod 4 of MCMC group y*ceil(L/8) + k/4.
    ORC_RNG_PLANES: r = B * 2^24 + floor(w / 2^8), with w the ORC_RNG_WORD
    number of the same site and B a byte of bit planes: the Philox block of
-   domain MCMC_PLANES, group y*ceil(L/32) + k/16 (same step, half sweep,
+   domain MCMC_PLANES, group y*ceil(L/32) + x/32 (same step, half sweep,
    slot and population) holds eight planes, plane m = 2i + h (i = 0..3 the
-   output word, h = 0 or 1) carrying bit 7 - m of B for every site of that
-   group, as bit 2 (k mod 16) + h of output word i.  Both parts are
-   independent uniform bits, so r is uniform on [0, 2^32) as in the default
-   mode: the acceptance probabilities are the same.  A sweep that compares
-   B with the top byte of the threshold first needs w only when they are
-   equal. */
+   output word, h = 0 or 1) carrying bit 7 - m of B for the sites of that
+   32-site stretch of the row, as bit ((x mod 32) XOR h) of output word i.
+   The sites of one colour in a stretch sit at bit positions of one parity,
+   so no two of them share a bit.  Both parts of r are independent uniform
+   bits, so r is uniform on [0, 2^32) as in the default mode: the
+   acceptance probabilities are the same.  A sweep that compares B with the
+   top byte of the threshold first needs w only when they are equal. */
 static uint32_t site_draw(int mode, int L, uint64_t seed, uint32_t pop,
                           uint32_t step, uint32_t hs, uint32_t slot, int y,
-                          int k) {
+                          int x) {
   const int G8 = (L + 7) / 8;
+  const int k = x / 2;
   uint32_t w = draw_word(seed, DOMAIN_MCMC, (uint32_t)(y * G8 + k / 4), step,
                          hs, slot, pop, k % 4);
   if (mode != ORC_RNG_PLANES) return w;
   const int W32 = (L + 31) / 32;
   uint32_t ctr[4], key[2], out[4];
-  ctr[0] = (DOMAIN_MCMC_PLANES << 28) | (uint32_t)(y * W32 + k / 16);
+  ctr[0] = (DOMAIN_MCMC_PLANES << 28) | (uint32_t)(y * W32 + x / 32);
   ctr[1] = (step << 16) | hs;
   ctr[2] = slot;
   ctr[3] = pop;
@@ -521,7 +523,7 @@ static uint32_t site_draw(int mode, int L, uint64_t seed, uint32_t pop,
   orc_philox4x32_10(ctr, key, out);
   uint32_t B = 0;
   for (int m = 0; m < 8; ++m) {
-    int pos = (ORC_MUTANT == 18) ? (m & 1) : 2 * (k % 16) + (m & 1);
+    int pos = (ORC_MUTANT == 18) ? (m & 1) : ((x % 32) ^ (m & 1));
     uint32_t bit = (out[m / 2] >> pos) & 1u;
     B |= bit << (7 - m);
   }
@@ -529,9 +531,9 @@ static uint32_t site_draw(int mode, int L, uint64_t seed, uint32_t pop,
 }
 
 uint32_t orc_site_draw(int mode, int L, uint64_t seed, uint32_t pop,
-                       int step, int half_sweep, uint32_t slot, int y, int k) {
+                       int step, int half_sweep, uint32_t slot, int y, int x) {
   return site_draw(mode, L, seed, pop, (uint32_t)step, (uint32_t)half_sweep,
-                   slot, y, k);
+                   slot, y, x);
 }
 
 static uint64_t splitmix(uint64_t* s) {
@@ -582,9 +584,8 @@ static void sweep_one(int L, const int8_t* J, int8_t* s, int32_t* E,
           a += (bond(J, L, 1, x, (ORC_MUTANT == 3) ? y : yu) * sv *
                     s[yu * L + x] < 0);
         int dE = 8 - 4 * a;
-        int k = x / 2;
         uint32_t r = site_draw(mode, L, seed, pop, (uint32_t)step,
-                               (uint32_t)(2 * tt + c), slot, y, k);
+                               (uint32_t)(2 * tt + c), slot, y, x);
         int accept;
         if (dE <= 0) accept = 1;
         else if (ORC_MUTANT == 4) accept = (uint64_t)r < (dE == 4 ? T8 : T4);

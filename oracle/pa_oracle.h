@@ -146,13 +146,13 @@ int orc_sweep_potts_replica(int L, int q, int8_t* spins, int32_t* E,
    per site (the default); ORC_RNG_PLANES, r = B 2^24 + floor(w / 2^8) with
    B a byte of bit planes shared out of one Philox block per 16 colour
    sites and w the site's default word (see site_draw in pa_oracle.c).
-   orc_site_draw returns the number a site uses; orc_sweep_replica_rng is
-   orc_sweep_replica with a mode. */
+   orc_site_draw returns the number site (x, y) uses; orc_sweep_replica_rng
+   is orc_sweep_replica with a mode. */
 #define ORC_RNG_WORD 0
 #define ORC_RNG_PLANES 1
 int orc_set_rng_mode(orc_pa* p, int mode);
 uint32_t orc_site_draw(int mode, int L, uint64_t seed, uint32_t pop,
-                       int step, int half_sweep, uint32_t slot, int y, int k);
+                       int step, int half_sweep, uint32_t slot, int y, int x);
 int orc_sweep_replica_rng(int L, const int8_t* J, int8_t* spins,
                           int32_t* E, int32_t* M, double beta, uint64_t seed,
                           uint32_t pop, int step, int t0, int theta,

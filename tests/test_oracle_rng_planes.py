@@ -13,14 +13,15 @@ import oracle
 
 
 def _draws(mode, L, n_slots, hs=3, step=7, seed=11, pop=2):
-    """r of every colour site of every row for n_slots replica slots:
-    array [n_slots][L][L/2]."""
+    """r of every site of colour hs mod 2 of every row for n_slots replica
+    slots: array [n_slots][L][L/2], index k = x/2."""
     out = np.zeros((n_slots, L, L // 2), np.uint64)
     for j in range(n_slots):
         for y in range(L):
             for k in range(L // 2):
+                x = 2 * k + ((hs + y) & 1)
                 out[j, y, k] = oracle.site_draw(mode, L, seed, pop, step, hs, j,
-                                                y, k)
+                                                y, x)
     return out
 
 
