@@ -7,16 +7,20 @@ temperatures the energy histogram, the host reweighting tables, copy counts,
 scan, gather-copy, theta Metropolis sweeps and the observables, with the
 free energy accumulated on the way.
 
-Default workload: the 2D Ising ferromagnet, L = 64 periodic, R = 65536
-replicas, int8 spins, beta 0 -> 1 in 200 linear steps, theta = 10.
+Default workload: the paper's total replica count on one device, the 2D
+Ising ferromagnet with L = 64 periodic, R = 2^21 replicas, bit-packed spins,
+beta 0 -> 0.5 in 100 linear steps, theta = 10.  The int8 workload (L = 64,
+R = 65536, beta 0 -> 1 in 200 steps) and the paper's per-GPU shape (R =
+20480) are timed as secondary figures of the same line.
 
 Prints one JSON line (rank 0):
   value           spin-flip attempts per ns over the whole timed anneals
   roofline        the sweep kernel (dominant) against the integer VALU peak,
                   from HIP events on the library's stream
   resample        achieved HBM bandwidth of histogram+counts+scatter+gather
-  cpu_baseline    the single-threaded oracle timed on a bounded sample of the
-                  same workload on this host
+  cpu_baseline    the oracle timed on a bounded sample of the same workload
+                  on this host, on every core (replica-parallel sweeps) and
+                  on one
 """
 from __future__ import annotations
 
@@ -35,22 +39,45 @@ import pa_workloads as W  # noqa: E402
 METRIC = ("spin-flip attempts/ns + resample GB/s (% HBM peak); wall time to "
           "β_f plain vs batched+MLP Δβ")
 HBM_PEAK_GBPS = 8000.0
-# Integer VALU peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one
-# 32-bit operation per lane per cycle (gfx950 issues v_mad_u64_u32 and
-# v_bitop3_b32 at that rate; packed FP32 does not apply to integer work).
-VALU_OPS_PER_S = 256 * 4 * 16 * 2.4e9
-# Algorithmic integer work of one spin-flip attempt: a quarter of a
-# Philox4x32-10 block (10 rounds of 2 32x32->64 multiplies and 2 three-input
-# xors = 40 ops per 4 words) plus one threshold test and one accumulate.
-ALGO_OPS_PER_ATTEMPT = 40 / 4 + 2
+# Vector ALU of MI355X: 256 CUs x 4 SIMDs at 2.4 GHz.  A wave64 instruction
+# that forms a 64-bit product (v_mad_u64_u32, the Philox multiply) holds its
+# SIMD for 4 cycles, the rate of the fp64 FMA (78.6 TFLOP/s = 39.3 T lane
+# operations/s); plain 32-bit logic and integer instructions take 2 cycles,
+# the rate of the fp32 FMA (157.3 TFLOP/s = 78.6 T lane operations/s).  The
+# probe in libpa_probe.so measures both rates on the device.  Work is priced
+# in multiply-equivalents: a 64-bit-product multiply counts 1, a plain 32-bit
+# operation 1/2, so the peak is the multiply rate.
+MAD_PER_S = 256 * 4 * 16 * 2.4e9
+SIMPLE_PER_S = 2 * MAD_PER_S
+VALU_OPS_PER_S = MAD_PER_S
+# Algorithmic work of one spin-flip attempt (multiplies, plain operations).
+# Word stream: a quarter of a Philox4x32-10 block (10 rounds of 2 multiplies
+# and 2 three-input xors, per 4 words) and the decision (threshold test and
+# flip).  Plane stream: a sixteenth of a block, a bit-sliced byte comparison
+# (16 plane steps per 32 positions), the flip, and for the 1/256 of the
+# draws whose byte ties with the threshold the site's own word and a test.
+ALGO_WORK = {"word": (5.0, 5.0 + 2.0),
+             "planes": (20 / 16 + 5 / 256, 20 / 16 + 0.5 + 1.0 + 6 / 256)}
 # Potts: two words per attempt (proposal and acceptance, half a block) plus
 # one threshold test and one select.
-ALGO_OPS_PER_ATTEMPT_POTTS = 40 / 2 + 2
+ALGO_WORK_POTTS = (10.0, 10.0 + 2.0)
+
+
+def mad_equivalents(work):
+    mads, simple = work
+    return mads + simple * (MAD_PER_S / SIMPLE_PER_S)
 
 
 KERNEL_SOURCES = ("paper_2006_00561_amd/csrc/pa_lattice.h",
                   "paper_2006_00561_amd/csrc/pa_device.h")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_lattice_C2_traffic.json")
+
+
+def traffic_file(workload):
+    return os.path.join(ROOT, "profiles", "k_lattice_%s_traffic.json" % workload)
+
+
+def valu_file(workload):
+    return os.path.join(ROOT, "profiles", "k_lattice_%s_valu.json" % workload)
 
 
 def kernel_hash():
@@ -66,14 +93,29 @@ def measured_traffic(workload):
     """HBM bytes per k_lattice launch from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known
     size), or None if it was taken on another workload or an older kernel."""
+    t = _load_keyed(traffic_file(workload), workload)
+    return t.get("hbm_bytes_per_launch") if t else None
+
+
+def _load_keyed(path, workload):
+    """A committed counter summary, or None if it was taken on another
+    workload or an older kernel."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
     if t.get("workload") != workload or t.get("kernel_sha256") != kernel_hash():
         return None
-    return t.get("hbm_bytes_per_launch")
+    return t
+
+
+def measured_valu(workload):
+    """Issued VALU instructions of k_lattice per spin-flip attempt, in lane
+    operations (SQ_INSTS_VALU x 64 / attempts), from the committed rocprofv3
+    counter summary, or None."""
+    t = _load_keyed(valu_file(workload), workload)
+    return t.get("valu_lane_ops_per_attempt") if t else None
 
 
 def gather_copy(binding, cfg, stream, reps=5):
@@ -108,7 +150,8 @@ def run_anneal(binding, cfg, stream, timing=None, rows_per_lane=0,
     g = binding.Population(L, R, seed=cfg["seed"], layout=layout,
                            rows_per_lane=rows_per_lane, stream=stream,
                            capacity=W.deferral_capacity(R), q=cfg.get("q", 0),
-                           resampling=cfg.get("law", 0))
+                           resampling=cfg.get("law", 0),
+                           rng_mode=cfg.get("rng_mode", 0))
     if timing:
         g.set_timing(True, classes=timing)
     attempts = 0
@@ -124,13 +167,41 @@ def run_anneal(binding, cfg, stream, timing=None, rows_per_lane=0,
     return attempts, lnZ, t
 
 
-def cpu_baseline(cfg, budget_s=15.0):
-    """The oracle (single thread) on the first temperature steps of the same
-    workload with a reduced population, scaled to attempts/ns."""
+def host_cpu():
+    """CPU model and core counts of this host."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        avail = os.cpu_count() or 1
+    return {"model": model, "nproc": avail, "cpu_count": os.cpu_count()}
+
+
+def cpu_threads():
+    """Threads for the all-core oracle leg: the cores this process may use,
+    at most the OMP_NUM_THREADS share when that is set."""
+    n = host_cpu()["nproc"]
+    try:
+        share = int(os.environ.get("OMP_NUM_THREADS", "0"))
+    except ValueError:
+        share = 0
+    return max(1, min(n, share) if share > 0 else n)
+
+
+def _oracle_leg(cfg, R, threads, budget_s):
+    """The oracle on the first temperature steps of cfg's schedule with R
+    replicas; sweeps split over `threads` POSIX threads (bit-identical to
+    one thread).  Returns (attempts/ns, steps, seconds, ln Z)."""
     import oracle
-    oracle.build(force=False)
     L, theta = cfg["L"], cfg["theta"]
-    R = 2048
     sched = W.linear_schedule(cfg["beta_f"], cfg["K"])
     p = oracle.OraclePA(L, R, seed=cfg["seed"])
     t0 = time.perf_counter()
@@ -138,18 +209,42 @@ def cpu_baseline(cfg, budget_s=15.0):
     for b in sched:
         p.resample(b)
         attempts += p.R * L * L * theta
-        p.sweep(theta)
+        p.sweep(theta, threads=threads)
         p.observables()
         steps += 1
         if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
-    return {"value": attempts / (dt * 1e9), "unit": "spin-flip attempts/ns",
-            "cores": 1, "kind": "oracle",
-            "sample": "%s shape with R=%d replicas, first %d of %d temperature "
-                      "steps (resample + %d sweeps + observables), %.1f s, "
-                      "single thread" % (cfg.get("name", "?"), R, steps,
-                                         cfg["K"], theta, dt)}
+    lnZ = p.free_energy()[0]
+    p.close()
+    return attempts / (dt * 1e9), steps, dt, lnZ
+
+
+def cpu_baseline(cfg, budget_s=24.0):
+    """The oracle as it stands on the first temperature steps of the same
+    workload with a reduced population, scaled to attempts/ns: once with
+    the sweeps split over every core this process may use (the headline
+    value) and once on one thread."""
+    import oracle
+    oracle.build(force=False)
+    host = host_cpu()
+    nt = cpu_threads()
+    R1, RN = 2048, 2048 * nt
+    v1, s1, d1, _ = _oracle_leg(cfg, R1, 1, budget_s / 2)
+    vN, sN, dN, _ = _oracle_leg(cfg, RN, nt, budget_s / 2)
+    return {"value": vN, "unit": "spin-flip attempts/ns", "cores": nt,
+            "kind": "oracle",
+            "sample": "%s shape (L=%d, theta=%d, beta 0->%g in %d steps) with "
+                      "R=%d replicas, first %d of %d temperature steps "
+                      "(resample + sweeps + observables), %.1f s, sweeps on "
+                      "%d threads" % (cfg.get("name", "?"), cfg["L"],
+                                      cfg["theta"], cfg["beta_f"], cfg["K"],
+                                      RN, sN, cfg["K"], dN, nt),
+            "single_thread": {"value": v1, "cores": 1,
+                              "sample": "R=%d, first %d steps, %.1f s"
+                                        % (R1, s1, d1)},
+            "per_core": vN / nt,
+            "host": host}
 
 
 def bench_batched(binding, stream, use_graph=True):
@@ -310,6 +405,14 @@ def bench_accuracy(binding, use_graph=True, M=64, L=32, R=2048, theta=10,
             "lnZ_exact": exact, "training_pairs": int(len(X)), "runs": runs}
 
 
+def _find(path):
+    """rocprofv3 output files ending in basename(path) anywhere under
+    dirname(path) (the profiler writes them into a per-host folder)."""
+    import glob
+    d, name = os.path.split(path)
+    return sorted(glob.glob(os.path.join(d, "**", "*" + name), recursive=True))
+
+
 def summarize_profiles(trace_dir, fetch_dir, write_dir, workload, command):
     """Write profiles/ summaries from rocprofv3 CSV output: per-kernel
     durations (--kernel-trace --stats) and HBM traffic (--pmc FETCH_SIZE and
@@ -319,17 +422,17 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, workload, command):
     import glob
 
     def one(pattern):
-        f = glob.glob(os.path.join(pattern))
+        f = _find(pattern)
         if not f:
             raise SystemExit("no file matches " + pattern)
         return f[0]
 
     stats = list(csv.DictReader(open(one(os.path.join(trace_dir,
-                                                       "*kernel_stats.csv")))))
+                                                       "kernel_stats.csv")))))
     per = {}
     for cnt, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         rows = list(csv.DictReader(open(one(os.path.join(
-            d, "*counter_collection.csv")))))
+            d, "counter_collection.csv")))))
         agg = {}
         for r in rows:
             agg.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
@@ -351,7 +454,7 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, workload, command):
     fetch_b = (sum(lat_f) / len(lat_f)) * 1024 * per["FETCH_SIZE"][1]
     write_b = (sum(lat_w) / len(lat_w)) * 1024 * per["WRITE_SIZE"][1]
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
-    with open(TRAFFIC_FILE, "w") as fh:
+    with open(traffic_file(workload), "w") as fh:
         json.dump({
             "workload": workload, "kernel": "k_lattice",
             "kernel_sha256": kernel_hash(),
@@ -383,12 +486,59 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, workload, command):
         fh.write("\n".join(lines) + "\n")
 
 
+def summarize_valu(pmc_dir, run_json, trace_dir, workload, command):
+    """profiles/k_lattice_<workload>_valu.json and a line in
+    profiles/kernels_<workload>.md from a rocprofv3 --pmc run of
+    `bench.py --profile-run` (SQ_INSTS_VALU and the other counters of the
+    pass, summed over the k_lattice dispatches) and the run's own count of
+    spin-flip attempts; the kernel durations come from a --kernel-trace run
+    of the same command."""
+    import csv
+    import glob
+    f = _find(os.path.join(pmc_dir, "counter_collection.csv"))
+    if not f:
+        raise SystemExit("no counter_collection.csv in " + pmc_dir)
+    tot, disp = {}, set()
+    for r in csv.DictReader(open(f[0])):
+        if not r["Kernel_Name"].startswith("k_lattice"):
+            continue
+        disp.add(r.get("Dispatch_Id", r.get("Correlation_Id", "")))
+        tot[r["Counter_Name"]] = tot.get(r["Counter_Name"], 0.0) + float(
+            r["Counter_Value"])
+    with open(run_json) as fh:
+        run = json.loads(fh.read().strip().splitlines()[-1])
+    att = run["attempts"]
+    tf = _find(os.path.join(trace_dir, "kernel_stats.csv"))
+    dur_ns = None
+    for r in csv.DictReader(open(tf[0])) if tf else []:
+        if r["Name"].startswith("k_lattice"):
+            dur_ns = float(r["TotalDurationNs"])
+    out = {"workload": workload, "kernel": "k_lattice",
+           "kernel_sha256": kernel_hash(), "dispatches": len(disp),
+           "attempts": att, "counters": tot, "commands": command}
+    if "SQ_INSTS_VALU" in tot:
+        out["valu_lane_ops_per_attempt"] = tot["SQ_INSTS_VALU"] * 64.0 / att
+    if "SQ_INSTS_SALU" in tot:
+        out["salu_per_attempt_per_wave64"] = tot["SQ_INSTS_SALU"] * 64.0 / att
+    if dur_ns and "SQ_INSTS_VALU" in tot:
+        # a wave64 VALU instruction occupies a 16-lane SIMD for 4 cycles;
+        # 1024 SIMDs at 2.4 GHz
+        out["kernel_ns_total"] = dur_ns
+        out["valu_issue_frac_at_2p4GHz"] = (
+            tot["SQ_INSTS_VALU"] * 4.0 / 1024.0) / (dur_ns * 2.4)
+        if "GRBM_GUI_ACTIVE" in tot:
+            out["grbm_gui_active_per_ns"] = tot["GRBM_GUI_ACTIVE"] / dur_ns
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(valu_file(workload), "w") as fh:
+        json.dump(out, fh, indent=1)
+
+
 def summarize_trace(trace_dir, name, command):
     """profiles/kernels_<name>.md from a rocprofv3 --kernel-trace --stats
     run: per-kernel calls and durations, with the command that made it."""
     import csv
     import glob
-    f = glob.glob(os.path.join(trace_dir, "*kernel_stats.csv"))
+    f = _find(os.path.join(trace_dir, "kernel_stats.csv"))
     if not f:
         raise SystemExit("no kernel_stats.csv in " + trace_dir)
     stats = list(csv.DictReader(open(f[0])))
@@ -412,14 +562,29 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="C2", choices=sorted(W.CONFIGS))
+    ap.add_argument("--workload", default="C3a", choices=sorted(W.CONFIGS))
     ap.add_argument("--rows-per-lane", type=int, default=0)
     ap.add_argument("--law", default="nearest",
                     choices=["nearest", "poisson", "systematic", "residual",
                              "multinomial"],
                     help="resampling law of the timed anneals")
+    ap.add_argument("--rng", default="word", choices=["word", "planes"],
+                    help="random numbers of the sweep: one Philox word per "
+                         "site, or bit planes (one block per 16 sites)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-budget", type=float, default=24.0,
+                    help="seconds of oracle work, split over its two legs")
+    ap.add_argument("--no-probe", action="store_true",
+                    help="skip the vector-ALU issue-rate probe")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the C2 and CP10 figures")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="only --steps anneals with no timing events, then "
+                         "a JSON line with their spin-flip attempts (for "
+                         "rocprofv3 counter passes)")
+    ap.add_argument("--summarize-valu", nargs=3,
+                    metavar=("PMC_DIR", "RUN_JSON", "TRACE_DIR"),
+                    help="write profiles/k_lattice_<workload>_valu.json")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
@@ -442,9 +607,25 @@ def main():
     if args.summarize_trace:
         summarize_trace(*args.summarize_trace)
         return
+    rng_flag = "" if args.rng == "word" else " --rng planes"
+    tag = args.workload + ("" if args.rng == "word" else "_planes")
+    if args.summarize_valu:
+        base = "python3 <repo>/bench.py --workload %s%s --profile-run " \
+               "--steps 1 --warmup 0" % (args.workload, rng_flag)
+        cmd = ["cd /tmp && export TMPDIR=/tmp",
+               "rocprofv3 --kernel-trace --stats -T -d <TRACE_DIR> -o run "
+               "--output-format csv -- %s" % base,
+               "rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_SALU SQ_WAVES "
+               "SQ_BUSY_CYCLES GRBM_GUI_ACTIVE -T -d <PMC_DIR> -o run "
+               "--output-format csv -- %s > <RUN_JSON>" % base,
+               "python3 bench.py --workload %s%s --summarize-valu <PMC_DIR> "
+               "<RUN_JSON> <TRACE_DIR>" % (args.workload, rng_flag)]
+        summarize_valu(*args.summarize_valu, tag, cmd)
+        return
     if args.summarize_profiles:
-        base = ("python3 <repo>/bench.py --workload %s --no-cpu-baseline "
-                "--no-batched --no-learned --no-accuracy" % args.workload)
+        base = ("python3 <repo>/bench.py --workload %s%s --no-cpu-baseline "
+                "--no-batched --no-learned --no-accuracy --no-secondary "
+                "--no-probe" % (args.workload, rng_flag))
         cmd = ["cd /tmp && export TMPDIR=/tmp",
                "rocprofv3 --kernel-trace --stats -T -d <TRACE_DIR> -o run "
                "--output-format csv -- %s --steps 2 --warmup 1" % base,
@@ -454,9 +635,10 @@ def main():
                "rocprofv3 --pmc WRITE_SIZE -T -d <WRITE_DIR> -o run "
                "--output-format csv -- %s --steps 1 --warmup 0 "
                "--calibrate-copy" % base,
-               "python3 bench.py --workload %s --summarize-profiles "
-               "<TRACE_DIR> <FETCH_DIR> <WRITE_DIR>" % args.workload]
-        summarize_profiles(*args.summarize_profiles, args.workload, cmd)
+               "python3 bench.py --workload %s%s --summarize-profiles "
+               "<TRACE_DIR> <FETCH_DIR> <WRITE_DIR>" % (args.workload,
+                                                        rng_flag)]
+        summarize_profiles(*args.summarize_profiles, tag, cmd)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU "
@@ -479,10 +661,12 @@ def main():
         print(json.dumps(bench_accuracy(binding, use_graph=not args.eager)),
               flush=True)
         return
+    law = ["nearest", "poisson", "systematic", "residual",
+           "multinomial"].index(args.law)
     cfg = dict(W.CONFIGS[args.workload])
     cfg["name"] = args.workload
-    cfg["law"] = ["nearest", "poisson", "systematic", "residual",
-                  "multinomial"].index(args.law)
+    cfg["law"] = law
+    cfg["rng_mode"] = ["word", "planes"].index(args.rng)
     if args.calibrate_copy:
         src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
@@ -491,38 +675,19 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.profile_run:
+        att = 0
+        for _ in range(args.steps):
+            att += run_anneal(binding, cfg, stream,
+                              rows_per_lane=args.rows_per_lane)[0]
+        torch.cuda.synchronize()
+        print(json.dumps({"workload": args.workload, "anneals": args.steps,
+                          "attempts": att}), flush=True)
+        return
 
-    for _ in range(args.warmup):
-        run_anneal(binding, cfg, stream, rows_per_lane=args.rows_per_lane)
-    torch.cuda.synchronize()
-
-    total_attempts = 0
-    tsum = None
-    lnZs = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        # events on the sweep launches only (two markers per timed launch)
-        a, lnZ, t = run_anneal(binding, cfg, stream, timing=("sweep",),
-                               rows_per_lane=args.rows_per_lane)
-        total_attempts += a
-        lnZs.append(lnZ)
-        if tsum is None:
-            tsum = t
-        else:
-            for k in binding.KERNEL_CLASSES:
-                for f in ("ms", "launches", "bytes"):
-                    tsum[k][f] += t[k][f]
-            tsum["attempts"] += t["attempts"]
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-
-    sw = tsum["sweep"]
-    sweep_avg_ms = sw["ms"] / max(1, sw["launches"])
-    sweep_rate = tsum["attempts"] / (sw["ms"] * 1e6)       # attempts/ns
-    ops = ALGO_OPS_PER_ATTEMPT_POTTS if cfg.get("q") else ALGO_OPS_PER_ATTEMPT
-    achieved = tsum["attempts"] / sw["launches"] * ops / (
-        sweep_avg_ms * 1e-3) / 1e12
-    peak = VALU_OPS_PER_S / 1e12
+    head = time_workload(binding, cfg, stream, args.steps, args.warmup,
+                         args.rows_per_lane, verbose=True)
+    dt = head["seconds"]
     # every kernel class timed, on one more anneal after the timed region
     fam = {}
     _, _, tall = run_anneal(binding, cfg, stream, timing=binding.KERNEL_CLASSES,
@@ -536,10 +701,18 @@ def main():
     # (each new slot loaded from its parent): its read + write of the whole
     # population per launch against HBM
     copy_gbps = sw_all["bytes"] / (sw_all["ms"] * 1e6) if sw_all["ms"] else 0.0
+    progress("resampling kernels timed: %.2f ms per anneal" % res_ms)
 
+    roof = head["roofline"]
+    tag = args.workload + ("" if cfg["rng_mode"] == 0 else "_planes")
+    roof["traffic"] = measured_traffic(tag)
+    roof["valu_lane_ops_per_attempt_counted"] = measured_valu(tag)
+    if not args.no_probe:
+        roof["valu_probe"] = valu_probe()
+        progress("VALU probe done")
     out = {
         "metric": METRIC,
-        "value": total_attempts / (dt * 1e9),
+        "value": head["value"],
         "unit": "spin-flip attempts/ns",
         "n_gpus": 1,
         "steps": args.steps,
@@ -551,32 +724,12 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {
-            "workload": "%s: 2D %s ferromagnet L=%d periodic, R=%d, %s "
-                        "spins, beta 0->%g in %d linear steps, theta=%d, "
-                        "seed %d; one step = one full anneal"
-                        % (args.workload,
-                           ("%d-state Potts" % cfg["q"]) if cfg.get("q")
-                           else "Ising", cfg["L"], cfg["R"], cfg["layout"],
-                           cfg["beta_f"], cfg["K"], cfg["theta"],
-                           cfg["seed"]),
+            "workload": describe(args.workload, cfg),
             "L": cfg["L"], "R": cfg["R"], "K": cfg["K"],
             "theta": cfg["theta"], "layout": cfg["layout"],
             "resampling": args.law,
         },
-        "roofline": {
-            "kernel": (("k_potts_swar" if cfg["L"] in (8, 16, 32, 64, 128)
-                        else "k_potts") if cfg.get("q") else "k_lattice") +
-                      " (theta fused Metropolis sweeps)",
-            "bound": "alu",
-            "achieved": achieved,
-            "peak": peak,
-            "unit": "TOP/s (32-bit integer VALU)",
-            "frac": achieved / peak,
-            "traffic": measured_traffic(args.workload),
-            "sweep_attempts_per_ns": sweep_rate,
-            "sweep_avg_ms": sweep_avg_ms,
-            "ops_per_attempt": ops,
-        },
+        "roofline": roof,
         "resample": {
             "note": "one extra anneal after the timed region with every "
                     "kernel class timed; the replica copies are fused into "
@@ -593,20 +746,147 @@ def main():
             "standalone_gather_copy": gather_copy(binding, cfg, stream),
         },
         "wall_time_to_beta_f_s": dt / args.steps,
-        "lnZ_final": lnZs[-1],
+        "lnZ_final": head["lnZ"],
         # descendants of the initial replicas at beta_f (the untimed anneal)
         "families_final": fam,
     }
+    if not args.no_secondary:
+        sec = {}
+        for name in ("C2", "CP10"):
+            if name == args.workload:
+                continue
+            c2 = dict(W.CONFIGS[name])
+            c2["name"] = name
+            c2["law"] = law
+            c2["rng_mode"] = cfg["rng_mode"]
+            r = time_workload(binding, c2, stream, 3, 1, 0)
+            r["roofline"]["traffic"] = measured_traffic(
+                name + ("" if cfg["rng_mode"] == 0 else "_planes"))
+            sec[name] = {"workload": describe(name, c2), "value": r["value"],
+                         "ms_per_anneal": r["seconds"] * 1e3 / 3,
+                         "roofline": r["roofline"], "lnZ_final": r["lnZ"]}
+            progress("secondary %s: %.1f attempts/ns" % (name, r["value"]))
+        out["secondary"] = sec
     if not args.no_batched:
         out["batched"] = bench_batched(binding, stream,
                                        use_graph=not args.eager)
+        progress("batched comparison done")
     if not args.no_learned:
         out["learned"] = bench_learned(binding, use_graph=not args.eager)
+        progress("learned comparison done")
     if not args.no_accuracy:
         out["accuracy"] = bench_accuracy(binding, use_graph=not args.eager)
+        progress("accuracy comparison done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_budget)
+        progress("cpu baseline done")
     print(json.dumps(out), flush=True)
+
+
+def progress(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def describe(name, cfg):
+    return ("%s: 2D %s ferromagnet L=%d periodic, R=%d, %s spins, beta "
+            "0->%g in %d linear steps, theta=%d, seed %d; one step = one "
+            "full anneal" % (name, ("%d-state Potts" % cfg["q"])
+                             if cfg.get("q") else "Ising", cfg["L"], cfg["R"],
+                             cfg["layout"], cfg["beta_f"], cfg["K"],
+                             cfg["theta"], cfg["seed"]))
+
+
+def time_workload(binding, cfg, stream, steps, warmup, rows_per_lane,
+                  verbose=False):
+    """`warmup` untimed anneals, then `steps` timed ones between device
+    synchronisations, with HIP events around each sweep launch on the
+    library's stream.  Returns the whole-anneal rate, the wall seconds of
+    the timed anneals and the sweep kernel against its roofline."""
+    import torch
+    for i in range(warmup):
+        run_anneal(binding, cfg, stream, rows_per_lane=rows_per_lane)
+        if verbose:
+            progress("warmup anneal %d/%d" % (i + 1, warmup))
+    torch.cuda.synchronize()
+    total_attempts = 0
+    tsum = None
+    lnZ = None
+    t0 = time.perf_counter()
+    for i in range(steps):
+        # events on the sweep launches only (two markers per timed launch)
+        a, lnZ, t = run_anneal(binding, cfg, stream, timing=("sweep",),
+                               rows_per_lane=rows_per_lane)
+        total_attempts += a
+        if tsum is None:
+            tsum = t
+        else:
+            for k in binding.KERNEL_CLASSES:
+                for f in ("ms", "launches", "bytes"):
+                    tsum[k][f] += t[k][f]
+            tsum["attempts"] += t["attempts"]
+        if verbose:
+            progress("timed anneal %d/%d" % (i + 1, steps))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    sw = tsum["sweep"]
+    sweep_avg_ms = sw["ms"] / max(1, sw["launches"])
+    sweep_rate = tsum["attempts"] / (sw["ms"] * 1e6)       # attempts/ns
+    work = ALGO_WORK_POTTS if cfg.get("q") else ALGO_WORK[
+        ["word", "planes"][cfg.get("rng_mode", 0)]]
+    ops = mad_equivalents(work)
+    achieved = tsum["attempts"] / sw["launches"] * ops / (
+        sweep_avg_ms * 1e-3) / 1e12
+    peak = VALU_OPS_PER_S / 1e12
+    L = cfg["L"]
+    return {
+        "value": total_attempts / (dt * 1e9), "seconds": dt, "lnZ": lnZ,
+        "roofline": {
+            "kernel": (("k_potts_swar" if L in (8, 16, 32, 64, 128)
+                        else "k_potts") if cfg.get("q") else "k_lattice") +
+                      " (theta fused Metropolis sweeps)",
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": peak,
+            "unit": "T multiply-equivalent VALU ops/s (64-bit-product "
+                    "multiply 1, plain 32-bit op 1/2)",
+            "frac": achieved / peak,
+            "traffic": None,
+            "sweep_attempts_per_ns": sweep_rate,
+            "sweep_avg_ms": sweep_avg_ms,
+            "sweep_launches": sw["launches"],
+            "ops_per_attempt": ops,
+            "algorithmic_multiplies_and_plain_ops_per_attempt": list(work),
+            "rng": ["word", "planes"][cfg.get("rng_mode", 0)],
+        }}
+
+
+# VALU instructions per lane and round of the probe kernels (from the gfx950
+# assembly of libpa_probe.so: 128 three-input xors + 8, 128 v_mad_u64_u32 +
+# 2, 8 Philox blocks = 331)
+PROBE_VALU = {0: 136, 1: 130, 3: 331}
+
+
+def valu_probe(stream=None):
+    """Measured issue rates of the vector ALU: lane operations per second of
+    the three-input xor, the 64-bit-product multiply-add and the Philox
+    block mix, each as 8192 workgroups of 256 lanes."""
+    import ctypes as C
+    path = os.path.join(ROOT, "paper_2006_00561_amd", "libpa_probe.so")
+    lib = C.CDLL(path)
+    lib.pa_probe_valu.argtypes = [C.c_int32, C.c_int32, C.c_int32,
+                                  C.c_void_p, C.POINTER(C.c_double)]
+    out = {}
+    for kind, name in ((0, "xor3"), (1, "mad_u64_u32"), (3, "philox")):
+        blocks, iters = 8192, (2000 if kind != 3 else 800)
+        ms = C.c_double()
+        rc = lib.pa_probe_valu(kind, blocks, iters, stream, C.byref(ms))
+        if rc != 0:
+            raise RuntimeError("VALU probe failed: %d" % rc)
+        instr = blocks * 4.0 * iters * PROBE_VALU[kind]
+        out[name] = {"lane_ops_per_s": instr * 64 / (ms.value * 1e-3),
+                     "wave64_instr_per_simd_cycle_at_2p4GHz":
+                         instr / 1024 / (ms.value * 1e-3 * 2.4e9)}
+    return out
 
 
 if __name__ == "__main__":

@@ -56,6 +56,7 @@ enum { PA_FERRO = 0, PA_PMJ = 1, PA_POTTS = 2 };  /* model     */
 enum { PA_INT8 = 0, PA_BITS = 1 };     /* device spin layout   */
 enum { PA_NEAREST = 0, PA_POISSON = 1, PA_SYSTEMATIC = 2,
        PA_RESIDUAL = 3, PA_MULTINOMIAL = 4 }; /* resampling law */
+enum { PA_RNG_WORD = 0, PA_RNG_PLANES = 1 };  /* sweep random numbers */
 
 typedef struct {
   int32_t L;          /* lattice side, even, 4 <= L <= 128 (checkerboard on
@@ -113,6 +114,21 @@ typedef struct {
                          Single populations only: pa_batch_init takes
                          PA_NEAREST only.                                  */
   int32_t q;          /* PA_POTTS: number of states, 2..16; else ignored   */
+  int32_t rng_mode;   /* random number r of a Metropolis decision (accept
+                         iff dE <= 0 or r < T, T = floor(exp(-beta dE)
+                         2^32), Sec. 2 equilibration step).  PA_RNG_WORD
+                         (default): r is the site's own Philox word, word
+                         k%4 of MCMC group y*ceil(L/8) + k/4, k = x/2.
+                         PA_RNG_PLANES: r = B 2^24 + floor(w / 2^8), w that
+                         same word and B a byte of bit planes: the Philox
+                         block of domain 5, group y*ceil(L/32) + x/32 (same
+                         counter words 1-3) gives bit 7 - m of B, m = 2i+h,
+                         as bit (x mod 32) XOR h of its output word i.
+                         r is uniform on [0, 2^32) in both modes, so the
+                         acceptance probabilities are the same; the plane
+                         mode draws one block per 16 sites and needs w only
+                         when B equals the top byte of T.  PA_FERRO and
+                         PA_PMJ single populations only.                  */
 } pa_config;
 
 typedef struct {

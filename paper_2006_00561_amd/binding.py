@@ -20,6 +20,7 @@ SO_PATH = os.path.join(HERE, "libpa.so")
 PA_FERRO, PA_PMJ, PA_POTTS = 0, 1, 2
 PA_INT8, PA_BITS = 0, 1
 PA_NEAREST, PA_POISSON, PA_SYSTEMATIC, PA_RESIDUAL, PA_MULTINOMIAL = range(5)
+PA_RNG_WORD, PA_RNG_PLANES = 0, 1
 KERNEL_CLASSES = ("init", "sweep", "hist", "counts", "scatter", "gather")
 PA_TIMING_ALL = -1
 
@@ -30,7 +31,8 @@ class pa_config(C.Structure):
                 ("capacity", C.c_int64), ("layout", C.c_int32),
                 ("rows_per_lane", C.c_int32), ("seed", C.c_uint64),
                 ("population_id", C.c_uint32), ("stream", C.c_void_p),
-                ("resampling", C.c_int32), ("q", C.c_int32)]
+                ("resampling", C.c_int32), ("q", C.c_int32),
+                ("rng_mode", C.c_int32)]
 
 
 class pa_obs(C.Structure):
@@ -79,6 +81,19 @@ class PAError(RuntimeError):
 _lib = None
 
 
+def _torch_runtime_first():
+    """Let torch bring up the HIP runtime before the library is loaded, so
+    that the library shares it and torch's device memory and streams can be
+    handed to the library (loaded the other way round, torch finds no
+    device).  Nothing happens where torch or a GPU is absent."""
+    try:
+        import torch
+    except ImportError:
+        return
+    if torch.cuda.is_available():
+        torch.cuda.init()
+
+
 def lib():
     """Load libpa.so (raises if it has not been built)."""
     global _lib
@@ -87,6 +102,7 @@ def lib():
             raise RuntimeError(
                 "libpa.so is not built (run paper_2006_00561_amd/build.py); "
                 "there is no fallback path")
+        _torch_runtime_first()
         L = C.CDLL(SO_PATH)
         P, i64, i32, d = C.c_void_p, C.c_int64, C.c_int32, C.c_double
         sig = {
@@ -183,9 +199,10 @@ class Population:
 
     def __init__(self, L, R_target, seed=1, population_id=0, J=None,
                  layout=PA_INT8, capacity=0, rows_per_lane=0, stream=None,
-                 resampling=PA_NEAREST, q=0):
+                 resampling=PA_NEAREST, q=0, rng_mode=PA_RNG_WORD):
         """J: +-J couplings (None = ferromagnet); q >= 2: the q-state Potts
-        ferromagnet (spins are states 0..q-1)."""
+        ferromagnet (spins are states 0..q-1); rng_mode: the sweep's
+        random numbers (PA_RNG_WORD or PA_RNG_PLANES)."""
         self.L, self.N = L, L * L
         self._J = None if J is None else np.ascontiguousarray(J, np.int8)
         cfg = pa_config()
@@ -201,6 +218,7 @@ class Population:
         cfg.population_id = population_id
         cfg.stream = stream
         cfg.resampling = resampling
+        cfg.rng_mode = rng_mode
         h = C.c_void_p()
         _ck(lib().pa_init(C.byref(cfg), C.byref(h)), "pa_init")
         self._h = h

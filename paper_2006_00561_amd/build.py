@@ -17,6 +17,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 SO = os.path.join(HERE, "libpa.so")
+# the vector-ALU issue-rate probe, a measuring instrument of the benchmark
+PROBE_SO = os.path.join(HERE, "libpa_probe.so")
+PROBE_SOURCE = "pa_probe.hip"
 SOURCES = ["pa_kernels.hip", "pa_tables.hip", "pa_api.hip", "pa_batch.hip",
            "pa_mlp.hip", "pa_potts.hip"]
 ARCH = os.environ.get("PA_OFFLOAD_ARCH", "gfx950")
@@ -70,7 +73,25 @@ def build(verbose: bool = False) -> str:
         for o in objs:
             if os.path.exists(o):
                 os.remove(o)
+    build_probe(verbose)
     return SO
+
+
+def build_probe(verbose: bool = False) -> str:
+    """Compile libpa_probe.so (always recompiles) and return its path."""
+    tmp = PROBE_SO + ".tmp%d" % os.getpid()
+    cmd = [hipcc()] + _flags() + ["-shared", "-o", tmp,
+                                  os.path.join(CSRC, PROBE_SOURCE)]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True, cwd=ROOT)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        if os.path.exists(tmp):
+            os.remove(tmp)
+        raise RuntimeError("hipcc failed building libpa_probe.so")
+    os.replace(tmp, PROBE_SO)
+    return PROBE_SO
 
 
 if __name__ == "__main__":

@@ -43,6 +43,8 @@ struct pa_ctx {
   hipStream_t stream = nullptr;
   int L = 0, N = 0, model = 0, layout = 0, W = 0, rpl = 1, lpr = 0, rpw = 0;
   int q = 0;  // Potts states (PA_POTTS), else 0
+  int rng_mode = PA_RNG_WORD;  // sweep random numbers
+  int hist_lo = -1;  // lowest occupied bin of the last histogram (-1: none)
   int64_t R_t = 0, cap = 0, R = 0, stride = 0, ntiles_cap = 0;
   uint64_t seed = 0;
   uint32_t pop = 0;
@@ -201,7 +203,8 @@ int run_lattice(pa_ctx* c, LatticeArgs& a, int cls) {
     CK(launch_potts(a, c->stream));
   else
     CK(launch_lattice(a, c->W, c->rpl, c->layout == PA_INT8,
-                      c->model == PA_PMJ, c->stream));
+                      c->model == PA_PMJ, c->rng_mode == PA_RNG_PLANES,
+                      c->stream));
   t_end(c, cls, e0, 0, 0, (a.init ? 1 : 2) * c->stride + 8,
         (int64_t)c->N * a.theta);
   return PA_OK;
@@ -257,7 +260,17 @@ int compute_hist(pa_ctx* c) {
   h.twoN = 2 * c->N;
   h.shift = c->hshift;
   h.nbins = c->nbins;
-  h.use_lds = (int64_t)c->nbins * 4 <= 64 * 1024;
+  // the LDS window: every bin when they fit in 64 KB, else 16384 bins from
+  // a little below the lowest occupied bin of the last histogram (the
+  // middle of the range before the first); bins outside it are counted in
+  // the global histogram directly, so the result never depends on it
+  h.win_n = std::min(c->nbins, 16384);
+  if (h.win_n == c->nbins)
+    h.win_lo = 0;
+  else if (c->hist_lo >= 0)
+    h.win_lo = std::max(0, std::min(c->hist_lo - 1024, c->nbins - h.win_n));
+  else
+    h.win_lo = (c->nbins - h.win_n) / 2;
   hipEvent_t e0 = t_begin(c, PA_K_HIST);
   CK(launch_hist(h, c->stream));
   t_end(c, PA_K_HIST, e0, 0, 0, 8, 0);
@@ -270,6 +283,11 @@ int compute_hist(pa_ctx* c) {
   if (c->h_scal[3] != 0) {  // an energy outside [-2N, 2N]
     note_error("a replica's energy lies outside the histogram range");
     return PA_EDEVICE;
+  }
+  {
+    int lo = -1, hi = -1;
+    occupied_range(c->h_hist, c->nbins, &lo, &hi);
+    c->hist_lo = lo;
   }
   c->hist_valid = true;
   return PA_OK;
@@ -403,6 +421,9 @@ int pa_init(const pa_config* cfg, pa_ctx** out) try {
     return PA_EINVAL;
   if (cfg->resampling < PA_NEAREST || cfg->resampling > PA_MULTINOMIAL)
     return PA_EINVAL;
+  if (cfg->rng_mode != PA_RNG_WORD &&
+      (cfg->rng_mode != PA_RNG_PLANES || cfg->model == PA_POTTS))
+    return PA_EINVAL;
   if (cfg->R_target < 1 || cfg->R_target >= (1ll << 31)) return PA_EINVAL;
   int64_t cap = cfg->capacity;
   if (cap == 0)
@@ -443,6 +464,7 @@ int pa_init(const pa_config* cfg, pa_ctx** out) try {
   c->cap = cap;
   c->seed = cfg->seed;
   c->law = cfg->resampling;
+  c->rng_mode = cfg->rng_mode;
   c->pop = cfg->population_id;
   c->stride = (c->layout == PA_INT8) ? round_up(c->N, 16)
                                      : round_up((int64_t)L * W * 4, 16);
@@ -1073,6 +1095,7 @@ int pa_get_config(pa_ctx* c, pa_config* out) try {
   k.stream = c->stream;
   k.resampling = c->law;
   k.q = c->q;
+  k.rng_mode = c->rng_mode;
   *out = k;
   return PA_OK;
 } catch (const std::bad_alloc&) {
@@ -1091,7 +1114,7 @@ namespace {
 
 // Population file: a fixed header, the couplings (+-J only), then the
 // population in the canonical layout.  Little-endian, as the host.
-constexpr char kMagic[8] = {'P', 'A', 'P', 'O', 'P', 'v', '0', '3'};
+constexpr char kMagic[8] = {'P', 'A', 'P', 'O', 'P', 'v', '0', '4'};
 struct FileHeader {
   char magic[8];
   int64_t R_target, capacity, seed, R;
@@ -1101,8 +1124,9 @@ struct FileHeader {
   int32_t step, sweeps_at_step, resampling;
   int32_t q;
   uint32_t fam_n0;  // size of the founding population of the families
+  int32_t rng_mode, reserved;
 };
-static_assert(sizeof(FileHeader) == 8 + 4 * 8 + 3 * 8 + 10 * 4,
+static_assert(sizeof(FileHeader) == 8 + 4 * 8 + 3 * 8 + 12 * 4,
               "population file header must have no padding");
 
 struct File {
@@ -1151,6 +1175,7 @@ int pa_save(pa_ctx* c, const char* path) try {
   h.resampling = c->law;
   h.q = c->q;
   h.fam_n0 = (uint32_t)n0;
+  h.rng_mode = c->rng_mode;
   File f(std::fopen(path, "wb"));
   if (!f.f) return PA_EIO;
   bool ok = f.write(&h, sizeof h);
@@ -1188,7 +1213,9 @@ int pa_load(const char* path, void* stream, pa_ctx** out) try {
       h.step < 0 || h.step > 65535 || h.sweeps_at_step < 0 ||
       h.sweeps_at_step > 32767 || !std::isfinite(h.beta) || !(h.beta >= 0.0) ||
       h.resampling < PA_NEAREST || h.resampling > PA_MULTINOMIAL ||
-      h.fam_n0 < 1 || (int64_t)h.fam_n0 > h.capacity)
+      h.fam_n0 < 1 || (int64_t)h.fam_n0 > h.capacity ||
+      (h.rng_mode != PA_RNG_WORD && h.rng_mode != PA_RNG_PLANES) ||
+      h.reserved != 0)
     return PA_EIO;
   const int64_t N = (int64_t)h.L * h.L;
   // the body's size follows from the header: check it before allocating
@@ -1231,6 +1258,7 @@ int pa_load(const char* path, void* stream, pa_ctx** out) try {
   cfg.stream = stream;
   cfg.resampling = h.resampling;
   cfg.q = h.q;
+  cfg.rng_mode = h.rng_mode;
   pa_ctx* c = nullptr;
   int rc = pa_init(&cfg, &c);
   if (rc) return rc == PA_EINVAL ? PA_EIO : rc;

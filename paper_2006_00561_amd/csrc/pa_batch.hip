@@ -1090,6 +1090,7 @@ int pa_batch_init(const pa_config* cfgs, int32_t n, void* stream,
     if (c.model == PA_PMJ && !c.J) return PA_EINVAL;
     if (c.layout != PA_INT8 && c.layout != PA_BITS) return PA_EINVAL;
     if (c.resampling != PA_NEAREST) return PA_EINVAL;  // single path only
+    if (c.rng_mode != PA_RNG_WORD) return PA_EINVAL;   // single path only
     if (c.R_target < 1 || c.R_target >= (1ll << 31)) return PA_EINVAL;
     const int rpl = c.model == PA_POTTS ? 0 : c.rows_per_lane;  // Potts: unused
     if (rpl < 0 || rpl > 4) return PA_EINVAL;
@@ -1317,7 +1318,7 @@ int pa_batch_init(const pa_config* cfgs, int32_t n, void* stream,
     if (rc == PA_OK)
       rc = hip_ok(d.q ? launch_potts(a, b->stream)
                       : launch_lattice(a, d.W, d.rpl, d.int8, d.glass,
-                                       b->stream),
+                                       false, b->stream),
                   "initial lattice pass", __LINE__);
     // every initial replica founds its own family
     if (rc == PA_OK)

@@ -12,6 +12,8 @@ namespace pa {
 constexpr uint32_t kDomainInit = 1u;
 constexpr uint32_t kDomainMcmc = 2u;
 constexpr uint32_t kDomainResample = 3u;
+// bit planes of the sweep's second random-number mode
+constexpr uint32_t kDomainMcmcPlanes = 5u;
 
 // Three-input XOR in one VALU instruction (gfx950 v_bitop3_b32, truth
 // table 0x96).
@@ -45,6 +47,46 @@ __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
     k1 += 0xBB67AE85u;
   }
   return c;
+}
+
+// Truth tables of v_bitop3_b32 are written as expressions over the bit
+// patterns of its three sources: source 0 is 0xF0, source 1 0xCC, source 2
+// 0xAA (entry {s0, s1, s2} of the table is bit s0*4 + s1*2 + s2).
+constexpr uint32_t kS0 = 0xF0u, kS1 = 0xCCu, kS2 = 0xAAu;
+
+// One bit of a bit-sliced borrow chain against a constant: with b the bits
+// of the minuend's plane, br the incoming borrow and t all ones where the
+// constant's bit is 1, the outgoing borrow is t ? (~b | br) : (~b & br).
+__device__ __forceinline__ uint32_t borrow_step(uint32_t b, uint32_t br,
+                                                uint32_t t) {
+  constexpr uint32_t tt =
+      ((kS2 & (~kS0 | kS1)) | (~kS2 & ~kS0 & kS1)) & 0xFFu;
+  return __builtin_amdgcn_bitop3_b32(b, br, t, tt);
+}
+
+// e & ~(b ^ t): the equality mask after one more plane.
+__device__ __forceinline__ uint32_t equal_step(uint32_t e, uint32_t b,
+                                               uint32_t t) {
+  constexpr uint32_t tt = (kS0 & ~(kS1 ^ kS2)) & 0xFFu;
+  return __builtin_amdgcn_bitop3_b32(e, b, t, tt);
+}
+
+// Bit-sliced comparison of eight planes against a byte: P[k] holds bit k of
+// every position's byte B (k = 0 least significant), tm[k] is all ones
+// where bit k of the constant byte t is set.  lt gets B < t, eq B == t, per
+// bit position.
+__device__ __forceinline__ void compare_byte(const uint32_t P[8],
+                                             const uint32_t tm[8],
+                                             uint32_t& lt, uint32_t& eq) {
+  uint32_t br = ~P[0] & tm[0];
+  uint32_t e = ~(P[0] ^ tm[0]);
+#pragma unroll
+  for (int k = 1; k < 8; ++k) {
+    br = borrow_step(P[k], br, tm[k]);
+    e = equal_step(e, P[k], tm[k]);
+  }
+  lt = br;
+  eq = e;
 }
 
 // acc * 4 + bit as one v_lshl_add_u32.  Written as an instruction so that the

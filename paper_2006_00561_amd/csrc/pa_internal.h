@@ -49,7 +49,10 @@ struct HistArgs {
   unsigned long long* moments;  // [0] sum |M|, [1] sum M^2, [3] bad energies
   int64_t R;
   const unsigned long long* Rdev;  // as in LatticeArgs
-  int32_t twoN, shift, nbins, use_lds;
+  int32_t twoN, shift, nbins;
+  // bins [win_lo, win_lo + win_n) are counted in LDS first (win_n <= 16384);
+  // a replica outside the window goes to the global histogram directly
+  int32_t win_lo, win_n;
 };
 
 struct CountsArgs {
@@ -188,7 +191,7 @@ double bisect_from_hist(const uint32_t* h, int nbins, int shift, int N,
 
 // ---- kernel launchers (pa_kernels.hip)
 hipError_t launch_lattice(const LatticeArgs& a, int W, int RPL, bool int8,
-                          bool glass, hipStream_t st);
+                          bool glass, bool planes, hipStream_t st);
 hipError_t launch_hist(const HistArgs& a, hipStream_t st);
 hipError_t launch_potts(const LatticeArgs& a, hipStream_t st);
 hipError_t launch_sys_counts(const CountsArgs& a, uint64_t* tile64,

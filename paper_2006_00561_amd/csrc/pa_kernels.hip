@@ -36,51 +36,78 @@ namespace pa {
 
 // ------------------------------------------------------------- lattice pass
 
-template <int W, int RPL, bool INT8, bool GLASS>
+template <int W, int RPL, bool INT8, bool GLASS, bool PLANES>
 __global__ __launch_bounds__(256) void k_lattice(const LatticeArgs a) {
-  lattice_pass<W, RPL, INT8, GLASS>(
+  lattice_pass<W, RPL, INT8, GLASS, PLANES>(
       a, ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
 }
 
 // -------------------------------------------------------------- histogram
 
+// Workgroup histogram in LDS over the window of bins the host expects the
+// energies in.  In every wave the lanes whose bin equals that of the lowest
+// pending lane add as one (at low temperatures most replicas share an energy,
+// and 64 lanes adding 1 to one LDS word would serialise); the rest add their
+// own 1.  The |M| and M^2 sums are reduced over the workgroup before one
+// atomic each, and every nonzero window bin is added to the global
+// histogram once per workgroup.
 __global__ __launch_bounds__(256) void k_hist(HistArgs a) {
   extern __shared__ uint32_t sh[];
-  if (a.use_lds) {
-    for (int i = threadIdx.x; i < a.nbins; i += blockDim.x) sh[i] = 0u;
-    __syncthreads();
-  }
+  __shared__ unsigned long long red[2][4];
+  for (int i = threadIdx.x; i < a.win_n; i += blockDim.x) sh[i] = 0u;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   unsigned long long sam = 0ull, sm2 = 0ull;
   const int64_t R = a.Rdev ? min((int64_t)*a.Rdev, a.R) : a.R;
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < R;
-       j += (int64_t)gridDim.x * blockDim.x) {
-    const int idx = (a.E[j] + a.twoN) >> a.shift;
-    if (idx < 0 || idx >= a.nbins) {  // corrupt energy: report, never index
-      atomicAdd(&a.moments[3], 1ull);
-      continue;
+  // the loop bound is uniform over the workgroup, so every wave runs whole
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < R;
+       base += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = base + threadIdx.x;
+    int w = -1;
+    if (j < R) {
+      const int idx = (a.E[j] + a.twoN) >> a.shift;
+      if (idx < 0 || idx >= a.nbins) {  // corrupt energy: report, never index
+        atomicAdd(&a.moments[3], 1ull);
+      } else {
+        w = idx - a.win_lo;
+        if (w < 0 || w >= a.win_n) {
+          atomicAdd(&a.hist[idx], 1u);
+          w = -1;
+        }
+      }
+      const int m = a.M[j];
+      sam += (unsigned long long)(m < 0 ? -m : m);
+      sm2 += (unsigned long long)((long long)m * m);
     }
-    if (a.use_lds)
-      atomicAdd(&sh[idx], 1u);
-    else
-      atomicAdd(&a.hist[idx], 1u);
-    const int m = a.M[j];
-    sam += (unsigned long long)(m < 0 ? -m : m);
-    sm2 += (unsigned long long)((long long)m * m);
+    const unsigned long long pend = __ballot(w >= 0);
+    if (pend) {
+      const int first = __builtin_ctzll(pend);
+      const int lb = __shfl(w, first, 64);
+      const unsigned long long same = __ballot(w == lb);
+      if (lane == first) atomicAdd(&sh[lb], (uint32_t)__popcll(same));
+      else if (w >= 0 && w != lb) atomicAdd(&sh[w], 1u);
+    }
   }
-  if (a.use_lds) {
-    __syncthreads();
-    for (int i = threadIdx.x; i < a.nbins; i += blockDim.x)
-      if (sh[i]) atomicAdd(&a.hist[i], sh[i]);
-  }
-  // wave reduction of the |M| and M^2 sums
   for (int off = 32; off > 0; off >>= 1) {
     sam += __shfl_down(sam, off, 64);
     sm2 += __shfl_down(sm2, off, 64);
   }
-  if ((threadIdx.x & 63) == 0) {
-    atomicAdd(&a.moments[0], sam);
-    atomicAdd(&a.moments[1], sm2);
+  if (lane == 0) {
+    red[0][wid] = sam;
+    red[1][wid] = sm2;
   }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long s0 = 0ull, s1 = 0ull;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+      s0 += red[0][i];
+      s1 += red[1][i];
+    }
+    atomicAdd(&a.moments[0], s0);
+    atomicAdd(&a.moments[1], s1);
+  }
+  for (int i = threadIdx.x; i < a.win_n; i += blockDim.x)
+    if (sh[i]) atomicAdd(&a.hist[a.win_lo + i], sh[i]);
 }
 
 // ------------------------------------------------------------ copy counts
@@ -419,50 +446,62 @@ __global__ void k_iota_u32(uint32_t* p, int64_t n) {
 
 // --------------------------------------------------------------- launchers
 
-template <int W, int RPL>
+template <int W, int RPL, bool PLANES>
 static hipError_t launch_lattice_w(const LatticeArgs& a, bool int8, bool glass,
                                    dim3 grid, hipStream_t st) {
   if (int8) {
-    if (glass) hipLaunchKernelGGL((k_lattice<W, RPL, true, true>), grid, dim3(256), 0, st, a);
-    else hipLaunchKernelGGL((k_lattice<W, RPL, true, false>), grid, dim3(256), 0, st, a);
+    if (glass) hipLaunchKernelGGL((k_lattice<W, RPL, true, true, PLANES>), grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_lattice<W, RPL, true, false, PLANES>), grid, dim3(256), 0, st, a);
   } else {
-    if (glass) hipLaunchKernelGGL((k_lattice<W, RPL, false, true>), grid, dim3(256), 0, st, a);
-    else hipLaunchKernelGGL((k_lattice<W, RPL, false, false>), grid, dim3(256), 0, st, a);
+    if (glass) hipLaunchKernelGGL((k_lattice<W, RPL, false, true, PLANES>), grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_lattice<W, RPL, false, false, PLANES>), grid, dim3(256), 0, st, a);
   }
   return hipGetLastError();
 }
 
+template <int W, int RPL>
+static hipError_t launch_lattice_p(const LatticeArgs& a, bool int8, bool glass,
+                                   bool planes, dim3 grid, hipStream_t st) {
+  return planes ? launch_lattice_w<W, RPL, true>(a, int8, glass, grid, st)
+                : launch_lattice_w<W, RPL, false>(a, int8, glass, grid, st);
+}
+
 hipError_t launch_lattice(const LatticeArgs& a, int W, int RPL, bool int8,
-                          bool glass, hipStream_t st) {
+                          bool glass, bool planes, hipStream_t st) {
   const int64_t waves = (a.R + a.rpw - 1) / a.rpw;
   const int64_t blocks = (waves + 3) / 4;
   if (blocks <= 0) return hipSuccess;
   if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
   const dim3 grid((unsigned)blocks);
   switch (W * 8 + RPL) {
-    case 1 * 8 + 1: return launch_lattice_w<1, 1>(a, int8, glass, grid, st);
-    case 1 * 8 + 2: return launch_lattice_w<1, 2>(a, int8, glass, grid, st);
-    case 1 * 8 + 3: return launch_lattice_w<1, 3>(a, int8, glass, grid, st);
-    case 1 * 8 + 4: return launch_lattice_w<1, 4>(a, int8, glass, grid, st);
-    case 2 * 8 + 1: return launch_lattice_w<2, 1>(a, int8, glass, grid, st);
-    case 2 * 8 + 2: return launch_lattice_w<2, 2>(a, int8, glass, grid, st);
-    case 2 * 8 + 3: return launch_lattice_w<2, 3>(a, int8, glass, grid, st);
-    case 2 * 8 + 4: return launch_lattice_w<2, 4>(a, int8, glass, grid, st);
-    case 3 * 8 + 2: return launch_lattice_w<3, 2>(a, int8, glass, grid, st);
-    case 3 * 8 + 3: return launch_lattice_w<3, 3>(a, int8, glass, grid, st);
-    case 3 * 8 + 4: return launch_lattice_w<3, 4>(a, int8, glass, grid, st);
-    case 4 * 8 + 2: return launch_lattice_w<4, 2>(a, int8, glass, grid, st);
-    case 4 * 8 + 3: return launch_lattice_w<4, 3>(a, int8, glass, grid, st);
-    case 4 * 8 + 4: return launch_lattice_w<4, 4>(a, int8, glass, grid, st);
+    case 1 * 8 + 1: return launch_lattice_p<1, 1>(a, int8, glass, planes, grid, st);
+    case 1 * 8 + 2: return launch_lattice_p<1, 2>(a, int8, glass, planes, grid, st);
+    case 1 * 8 + 3: return launch_lattice_p<1, 3>(a, int8, glass, planes, grid, st);
+    case 1 * 8 + 4: return launch_lattice_p<1, 4>(a, int8, glass, planes, grid, st);
+    case 2 * 8 + 1: return launch_lattice_p<2, 1>(a, int8, glass, planes, grid, st);
+    case 2 * 8 + 2: return launch_lattice_p<2, 2>(a, int8, glass, planes, grid, st);
+    case 2 * 8 + 3: return launch_lattice_p<2, 3>(a, int8, glass, planes, grid, st);
+    case 2 * 8 + 4: return launch_lattice_p<2, 4>(a, int8, glass, planes, grid, st);
+    case 3 * 8 + 2: return launch_lattice_p<3, 2>(a, int8, glass, planes, grid, st);
+    case 3 * 8 + 3: return launch_lattice_p<3, 3>(a, int8, glass, planes, grid, st);
+    case 3 * 8 + 4: return launch_lattice_p<3, 4>(a, int8, glass, planes, grid, st);
+    case 4 * 8 + 2: return launch_lattice_p<4, 2>(a, int8, glass, planes, grid, st);
+    case 4 * 8 + 3: return launch_lattice_p<4, 3>(a, int8, glass, planes, grid, st);
+    case 4 * 8 + 4: return launch_lattice_p<4, 4>(a, int8, glass, planes, grid, st);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_hist(const HistArgs& a, hipStream_t st) {
-  int64_t blocks = (a.R + 256 * 8 - 1) / (256 * 8);
+  // at most one workgroup per compute unit, each over 16 or more replicas
+  // per lane: the window merge and the moment atomics are per workgroup
+  int64_t blocks = (a.R + 256 * 16 - 1) / (256 * 16);
   if (blocks < 1) blocks = 1;
-  if (blocks > 2048) blocks = 2048;
-  const size_t shm = a.use_lds ? (size_t)a.nbins * sizeof(uint32_t) : 0;
+  if (blocks > 256) blocks = 256;
+  if (a.win_n < 0 || a.win_n > 16384 || a.win_lo < 0 ||
+      a.win_lo + a.win_n > a.nbins)
+    return hipErrorInvalidValue;
+  const size_t shm = (size_t)a.win_n * sizeof(uint32_t);
   hipLaunchKernelGGL(k_hist, dim3((unsigned)blocks), dim3(256), shm, st, a);
   return hipGetLastError();
 }

@@ -113,9 +113,76 @@ __device__ __forceinline__ void store_row(uint8_t* rp, int L, int y,
   }
 }
 
+// Acceptance by bit planes (the sweep's second random-number mode): the
+// number a colour site compares with its threshold T is r = B 2^24 +
+// floor(w / 2^8), with B a byte of bit planes and w the site's word of the
+// default stream.  The block of domain MCMC_PLANES for row y, 32-site word
+// `word` holds eight planes: plane m = 2i + h is bit 7 - m of B, taken for
+// the site at bit position b of the word from bit b XOR h of output word i.
+// All 16 colour sites of the word sit at positions of parity p, so planes
+// 2i come from output word i as it is and planes 2i + 1 from it rotated by
+// one place towards them.  r < T iff B < T >> 24, or B == T >> 24 and
+// floor(w / 2^8) < T mod 2^24: the comparison runs bit-sliced over the
+// word, and only the ties need w.
+struct PlaneThr {
+  uint32_t tm4[8], tm8[8];  // all ones where bit k of T >> 24 is set
+  uint32_t lo4, lo8;        // T mod 2^24
+  bool big4, big8;          // T = 2^32: every draw accepts
+};
+
+__device__ __forceinline__ PlaneThr plane_thresholds(const LatticeArgs& a) {
+  PlaneThr t;
+  const uint64_t T4 = (1ull << 32) - a.K4, T8 = (1ull << 32) - a.K8;
+  const uint32_t b4 = (uint32_t)(T4 >> 24) & 0xFFu;
+  const uint32_t b8 = (uint32_t)(T8 >> 24) & 0xFFu;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    t.tm4[k] = 0u - ((b4 >> k) & 1u);
+    t.tm8[k] = 0u - ((b8 >> k) & 1u);
+  }
+  t.lo4 = (uint32_t)T4 & 0xFFFFFFu;
+  t.lo8 = (uint32_t)T8 & 0xFFFFFFu;
+  t.big4 = (T4 >> 32) != 0;
+  t.big8 = (T8 >> 32) != 0;
+  return t;
+}
+
+// The plane block of one word: lt4/lt8 get B < T >> 24 and tie4/tie8
+// B == T >> 24 for the thresholds of dE = 4 and 8, per bit position (only
+// positions of parity p are meaningful).
+__device__ __forceinline__ void plane_decide(const uint4 o, uint32_t p,
+                                             const PlaneThr& t, uint32_t& lt4,
+                                             uint32_t& tie4, uint32_t& lt8,
+                                             uint32_t& tie8) {
+  // rotation by one place that brings bit b XOR 1 to position b for the
+  // positions b of parity p: right by 1 for even b, left by 1 for odd b
+  const uint32_t sh = p ? 31u : 1u;
+  uint32_t P[8];
+  P[7] = o.x;
+  P[6] = __builtin_amdgcn_alignbit(o.x, o.x, sh);
+  P[5] = o.y;
+  P[4] = __builtin_amdgcn_alignbit(o.y, o.y, sh);
+  P[3] = o.z;
+  P[2] = __builtin_amdgcn_alignbit(o.z, o.z, sh);
+  P[1] = o.w;
+  P[0] = __builtin_amdgcn_alignbit(o.w, o.w, sh);
+  compare_byte(P, t.tm4, lt4, tie4);
+  compare_byte(P, t.tm8, lt8, tie8);
+  if (t.big4) {
+    lt4 = ~0u;
+    tie4 = 0u;
+  }
+  if (t.big8) {
+    lt8 = ~0u;
+    tie8 = 0u;
+  }
+}
+
 // One wave's share of a lattice pass: replicas wave*rpw .. wave*rpw+rpw-1.
 // No workgroup barrier, so persistent kernels can call it per work item.
-template <int W, int RPL, bool INT8, bool GLASS>
+// PLANES selects the bit-plane random numbers, else one Philox word per
+// site.
+template <int W, int RPL, bool INT8, bool GLASS, bool PLANES = false>
 __device__ __forceinline__ void lattice_pass(const LatticeArgs& a,
                                              int64_t wave) {
   const int lane = threadIdx.x & 63;
@@ -201,6 +268,8 @@ __device__ __forceinline__ void lattice_pass(const LatticeArgs& a,
   // on every pass of the loop
   uint32_t one_v;
   asm("v_mov_b32 %0, %1" : "=v"(one_v) : "s"(a.one));
+  PlaneThr pt;
+  if (PLANES) pt = plane_thresholds(a);
   for (int t = 0; t < a.theta; ++t) {
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
@@ -211,6 +280,9 @@ __device__ __forceinline__ void lattice_pass(const LatticeArgs& a,
         dnl[w] = shfl(s[0][w], dn_lane);
       }
       const uint32_t ctr1 = (a.step << 16) | (uint32_t)(2 * (a.t0 + t) + c);
+      // bit-plane mode: flips decided by the planes, and the sites whose
+      // byte ties with the threshold's top byte (dE = 4 and 8 apart)
+      uint32_t flip[RPL][W], tie4[RPL][W], tie8[RPL][W];
 #pragma unroll
       for (int r = 0; r < RPL; ++r) {
         const int y = lr * RPL + r;
@@ -233,6 +305,21 @@ __device__ __forceinline__ void lattice_pass(const LatticeArgs& a,
           const uint32_t eq0 = ~(d1 | d2 | d3 | d4);  // dE = +8
           const uint32_t eq1 = (x1 ^ x2) & ~(a1 | a2); // dE = +4
           const uint32_t ge2 = ~(eq0 | eq1);           // dE <= 0
+          const uint32_t col = (p ? 0xAAAAAAAAu : 0x55555555u) & valid_mask(L, w);
+          if (PLANES) {
+            const uint4 o = philox10(
+                make_uint4((kDomainMcmcPlanes << 28) | (uint32_t)(y * W + w),
+                           ctr1, slot, a.pop),
+                a.k0, a.k1);
+            uint32_t lt4, e4, lt8, e8;
+            plane_decide(o, p, pt, lt4, e4, lt8, e8);
+            // lanes past the population hold no replica: no ties to resolve
+            const uint32_t cola = active ? col : 0u;
+            flip[r][w] = col & (ge2 | (eq1 & lt4) | (eq0 & lt8));
+            tie4[r][w] = cola & eq1 & e4;
+            tie8[r][w] = cola & eq0 & e8;
+            continue;
+          }
           // The 16 colour sites of this word (k = 16w + j, x = 2k + p) draw
           // word j%4 of group 4w + j/4.  The rejection bit of a site is the
           // carry of r + (2^32 - T): hi(r * 1 + K) is 1 iff r >= T, one
@@ -256,10 +343,59 @@ __device__ __forceinline__ void lattice_pass(const LatticeArgs& a,
           }
           const uint32_t M4 = (~rj4 & 0x55555555u) << p;
           const uint32_t M8 = (~rj8 & 0x55555555u) << p;
-          const uint32_t col = (p ? 0xAAAAAAAAu : 0x55555555u) & valid_mask(L, w);
-          const uint32_t flip = col & (ge2 | (eq1 & M4) | (eq0 & M8));
-          s[r][w] = sv ^ flip;
+          const uint32_t flp = col & (ge2 | (eq1 & M4) | (eq0 & M8));
+          s[r][w] = sv ^ flp;
         }
+      }
+      if (PLANES) {
+        // Ties: each pass takes the lowest pending tie of every lane that
+        // has one (first by row and word, then by bit), draws that site's
+        // default-stream word and decides it on the low 24 bits of T.  The
+        // wave leaves when no lane has a tie left.
+        for (;;) {
+          uint32_t tm = 0u;
+          int sel = 0;
+#pragma unroll
+          for (int i = RPL * W - 1; i >= 0; --i) {
+            const uint32_t ti = tie4[i / W][i % W] | tie8[i / W][i % W];
+            if (ti) {
+              tm = ti;
+              sel = i;
+            }
+          }
+          if (!__any(tm != 0u)) break;
+          if (tm) {
+            const uint32_t bit = (uint32_t)__builtin_ctz(tm);
+            const uint32_t bm = 1u << bit;
+            const int r = sel / W, w = sel - (sel / W) * W;
+            const int y = lr * RPL + r;
+            const uint32_t k = 16u * (uint32_t)w + (bit >> 1);
+            const uint4 b = philox10(
+                make_uint4((kDomainMcmc << 28) | (uint32_t)(y * G8 + (k >> 2)),
+                           ctr1, slot, a.pop),
+                a.k0, a.k1);
+            const uint32_t sub = k & 3u;
+            const uint32_t wv = (sub & 2u) ? ((sub & 1u) ? b.w : b.z)
+                                           : ((sub & 1u) ? b.y : b.x);
+            uint32_t is4 = 0u;
+#pragma unroll
+            for (int i = 0; i < RPL * W; ++i)
+              if (sel == i) is4 = tie4[i / W][i % W] & bm;
+            const uint32_t acc =
+                ((wv >> 8) < (is4 ? pt.lo4 : pt.lo8)) ? bm : 0u;
+#pragma unroll
+            for (int i = 0; i < RPL * W; ++i)
+              if (sel == i) {
+                tie4[i / W][i % W] &= ~bm;
+                tie8[i / W][i % W] &= ~bm;
+                flip[i / W][i % W] |= acc;
+              }
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < RPL; ++r)
+#pragma unroll
+          for (int w = 0; w < W; ++w) s[r][w] ^= flip[r][w];
       }
     }
   }

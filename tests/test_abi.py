@@ -48,10 +48,23 @@ def test_strerror_and_validation_without_device():
     cfg = b.pa_config()
     cfg.L, cfg.R_target, cfg.resampling = 8, 10, 5      # no such law
     assert lib.pa_init(C.byref(cfg), C.byref(h)) == b.PA_EINVAL
-    # the batch takes the nearest-integer law only
+    cfg = b.pa_config()
+    cfg.L, cfg.R_target, cfg.rng_mode = 8, 10, 2        # no such stream
+    assert lib.pa_init(C.byref(cfg), C.byref(h)) == b.PA_EINVAL
+    cfg = b.pa_config()                                 # Potts: word mode only
+    cfg.L, cfg.R_target, cfg.model, cfg.q = 8, 10, b.PA_POTTS, 3
+    cfg.rng_mode = b.PA_RNG_PLANES
+    assert lib.pa_init(C.byref(cfg), C.byref(h)) == b.PA_EINVAL
+    assert not h.value
+    # the batch takes the nearest-integer law and the word stream only
     cfg = b.pa_config()
     cfg.L, cfg.R_target, cfg.resampling = 8, 10, b.PA_POISSON
     bh = C.c_void_p()
+    assert lib.pa_batch_init(C.byref(cfg), 1, None, 0,
+                             C.byref(bh)) == b.PA_EINVAL
+    assert not bh.value
+    cfg = b.pa_config()
+    cfg.L, cfg.R_target, cfg.rng_mode = 8, 10, b.PA_RNG_PLANES
     assert lib.pa_batch_init(C.byref(cfg), 1, None, 0,
                              C.byref(bh)) == b.PA_EINVAL
     assert not bh.value
@@ -78,20 +91,22 @@ def test_product_path_does_not_touch_the_oracle():
                 assert "oracle" not in src.lower(), f
 
 
-def _pop_file(path, L=4, R=2, spins=None, extra=b"", magic=b"PAPOPv03",
-              fam=None, n0=None, R_hdr=None, cap_hdr=None):
-    """A population file written from the documented layout: 104-byte
-    header (its last word the founding population size), spins [R][L][L]
-    int8, E and M int32, families uint32."""
+def _pop_file(path, L=4, R=2, spins=None, extra=b"", magic=b"PAPOPv04",
+              fam=None, n0=None, R_hdr=None, cap_hdr=None, rng_mode=0,
+              reserved=0):
+    """A population file written from the documented layout: 112-byte
+    header (its last words the founding population size, the sweep's
+    random-number mode and a zero word), spins [R][L][L] int8, E and M
+    int32, families uint32."""
     import struct
     N = L * L
     n0 = R if n0 is None else n0
     Rh = R if R_hdr is None else R_hdr
     cap = R + 100 if cap_hdr is None else cap_hdr
-    hdr = magic + struct.pack("<qqqqdddiiiiIiiiiI", R, cap, 1, Rh, 0.25,
+    hdr = magic + struct.pack("<qqqqdddiiiiIiiiiIii", R, cap, 1, Rh, 0.25,
                               N * 0.6931471805599453, 0.0, L, 0, 0, 1, 0, 3,
-                              0, 0, 0, n0)
-    assert len(hdr) == 104
+                              0, 0, 0, n0, rng_mode, reserved)
+    assert len(hdr) == 112
     s = bytes([1] * (R * N)) if spins is None else spins
     E = struct.pack("<%di" % R, *([-2 * N] * R))
     M = struct.pack("<%di" % R, *([N] * R))
@@ -107,7 +122,9 @@ def test_load_rejects_bad_files_before_any_device_work(tmp_path):
     missing = str(tmp_path / "missing.pa")
     assert lib.pa_load(missing.encode(), None, C.byref(h)) == b.PA_EIO
     bad = [("magic", dict(magic=b"NOTAPOP!")),
-           ("older format", dict(magic=b"PAPOPv02")),
+           ("older format", dict(magic=b"PAPOPv03")),
+           ("random-number mode", dict(rng_mode=2)),
+           ("reserved word", dict(reserved=1)),
            ("spin value", dict(spins=bytes([1] * 31 + [0]))),
            ("family number", dict(fam=[0, 2])),
            # a header that claims two billion replicas over a short body is
@@ -123,7 +140,7 @@ def test_load_rejects_bad_files_before_any_device_work(tmp_path):
     p = str(tmp_path / "short.pa")
     _pop_file(p)
     with open(p, "r+b") as f:
-        f.truncate(104 + 10)
+        f.truncate(112 + 10)
     assert lib.pa_load(p.encode(), None, C.byref(h)) == b.PA_EIO
     assert lib.pa_save(None, p.encode()) == b.PA_EINVAL
     assert lib.pa_strerror(b.PA_EIO).decode().startswith("population file")
