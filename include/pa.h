@@ -440,6 +440,21 @@ int pa_mlp_set_norm(pa_mlp* m, const float* mu, const float* sigma,
                     float mu_y, float sigma_y);
 /* y[s] = mu_y + sigma_y z(x_s) for B host rows X [B][n_in]. */
 int pa_mlp_forward(pa_mlp* m, const float* X, int32_t B, float* y);
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid allocation): the
+   forward pass of pa_mlp_forward with device pointers and no allocation.
+   X: device [B][n_in] raw features; y: device [B], receives
+   mu_y + sigma_y z(x_s), equal bit for bit to pa_mlp_forward's output.
+   Asynchronous on the network's stream; no synchronisation.  The
+   activations live in one fixed per-device scratch array of
+   2 x PA_MLP_NOALLOC_MAX_ELEMS floats (2 MiB, held until the process ends),
+   so B * max(width, n_in) must not exceed PA_MLP_NOALLOC_MAX_ELEMS
+   (PA_EINVAL otherwise, nothing launched).  Every call on a device shares
+   that array: calls that overlap on one device (other streams, other
+   threads) race and must be ordered by the caller.  Nothing in it needs
+   to start at zero. */
+#define PA_MLP_NOALLOC_MAX_ELEMS 262144
+int pa_mlp_forward_noalloc(pa_mlp* m, const float* X, int32_t B, float* y);
 /* Mean squared error of the standardised outputs against standardised
    targets T [B], and its gradient w.r.t. the parameters (host, may be
    NULL). */

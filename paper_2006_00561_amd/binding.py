@@ -167,6 +167,7 @@ def lib():
             "pa_mlp_get_params": ([P, P, i64], C.c_int),
             "pa_mlp_set_norm": ([P, P, P, C.c_float, C.c_float], C.c_int),
             "pa_mlp_forward": ([P, P, i32, P], C.c_int),
+            "pa_mlp_forward_noalloc": ([P, P, i32, P], C.c_int),
             "pa_mlp_loss_grad": ([P, P, P, i32, C.POINTER(C.c_float), P],
                                  C.c_int),
             "pa_mlp_train": ([P, P, P, i64, i32, i32, C.c_float, C.c_uint64,
@@ -643,6 +644,14 @@ class MLP:
         _ck(lib().pa_mlp_forward(self._h, _ptr(X), len(X), _ptr(y)),
             "pa_mlp_forward")
         return y
+
+    def forward_noalloc(self, X_dev, B, y_dev):
+        """pa_mlp_forward_noalloc: X_dev and y_dev are device addresses
+        (ints) of B x n_in and B floats; asynchronous on the network's
+        stream."""
+        _ck(lib().pa_mlp_forward_noalloc(self._h, C.c_void_p(X_dev), int(B),
+                                         C.c_void_p(y_dev)),
+            "pa_mlp_forward_noalloc")
 
     def loss_grad(self, X, T):
         X = np.ascontiguousarray(X, np.float32)

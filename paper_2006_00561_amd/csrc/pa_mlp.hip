@@ -16,10 +16,12 @@
 // (a loop over the samples in order, so gradients are deterministic).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstring>
 #include <exception>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -107,9 +109,57 @@ __global__ void k_mlp_adam(float* p, const float* g, float* m, float* v, int n,
   p[k] -= lr * (mk * c1) / (sqrtf(vk * c2) + eps);
 }
 
+// y[s] = mu_y + sigma_y z[s] in place, each operation rounded on its own (no
+// fused multiply-add), as the host does it for pa_mlp_forward.
+__global__ void k_mlp_out_affine(float* y, int B, float mu_y, float sigma_y) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= B) return;
+  y[s] = __fadd_rn(mu_y, __fmul_rn(sigma_y, y[s]));
+}
+
 static unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace pa
+
+// Activations of pa_mlp_forward_noalloc: two ping-pong slots of
+// PA_MLP_NOALLOC_MAX_ELEMS floats (2 MiB in all), one copy on every device
+// the library runs on, held until the process ends.  Host code never uses
+// this name as an address: the device address comes from
+// hipGetSymbolAddress, once per device, and is kept in g_scratch_dev.
+static __device__ __align__(256) float scratch[2 * PA_MLP_NOALLOC_MAX_ELEMS];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, which must be the current device;
+// looked up on the first call for that device.  nullptr on failure.
+float* scratch_on(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      ::pa::set_last_error("hipGetSymbolAddress", e, __LINE__);
+      return nullptr;
+    }
+    g_scratch_dev[device] = static_cast<float*>(p);
+  }
+  return g_scratch_dev[device];
+}
+
+// The address looked up before for `device`, or nullptr.
+float* scratch_known(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_dev[device];
+}
+
+}  // namespace
 
 using namespace pa;
 
@@ -288,6 +338,9 @@ int pa_mlp_create(int32_t n_in, int32_t width, int32_t depth, uint64_t seed,
     delete m;
     return PA_EDEVICE;
   }
+  // the no-allocation forward pass's scratch address on this device (a
+  // failed lookup only disables pa_mlp_forward_noalloc)
+  (void)scratch_on(m->device);
   m->stream = reinterpret_cast<hipStream_t>(stream);
   m->n_in = n_in;
   m->width = width;
@@ -449,6 +502,49 @@ int pa_mlp_forward(pa_mlp* m, const float* X, int32_t B, float* y) try {
   MK(hipStreamSynchronize(m->stream));
   const float mu_y = m->h_norm[2 * m->n_in], sy = m->h_norm[2 * m->n_in + 1];
   for (int s = 0; s < B; ++s) y[s] = mu_y + sy * z[(size_t)s];
+  return PA_OK;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
+} catch (...) {
+  ::pa::note_exception("unknown exception");
+  return PA_EDEVICE;
+}
+
+int pa_mlp_forward_noalloc(pa_mlp* m, const float* X, int32_t B,
+                           float* y) try {
+  if (!m || !X || !y || B < 1) return PA_EINVAL;
+  const int64_t wmax = std::max(m->width, m->n_in);
+  if ((int64_t)B * wmax > PA_MLP_NOALLOC_MAX_ELEMS) {
+    note_error("pa_mlp_forward_noalloc: batch x max(width, n_in) exceeds "
+               "PA_MLP_NOALLOC_MAX_ELEMS");
+    return PA_EINVAL;
+  }
+  float* base = scratch_known(m->device);  // looked up by pa_mlp_create
+  if (!base) {
+    note_error("pa_mlp_forward_noalloc: no scratch address for the device");
+    return PA_EDEVICE;
+  }
+  float* slot[2] = {base, base + PA_MLP_NOALLOC_MAX_ELEMS};
+  hipLaunchKernelGGL(k_mlp_standardize, dim3(blocks_for((int64_t)B * m->n_in)),
+                     dim3(256), 0, m->stream, X, nullptr, nullptr, m->d_norm,
+                     slot[0], nullptr, B, m->n_in);
+  MK(hipGetLastError());
+  for (int l = 0; l <= m->depth; ++l) {
+    const int n_out = (int)m->fan_out[l], n_in = (int)m->fan_in[l];
+    float* out = (l == m->depth) ? y : slot[(l + 1) & 1];
+    hipLaunchKernelGGL(k_mlp_fwd, dim3(blocks_for((int64_t)B * n_out)),
+                       dim3(256), 0, m->stream, m->d_params + m->w_off[l],
+                       m->d_params + m->b_off[l], slot[l & 1], out, B, n_in,
+                       n_out, l < m->depth ? 1 : 0);
+    MK(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_mlp_out_affine, dim3(blocks_for(B)), dim3(256), 0,
+                     m->stream, y, B, m->h_norm[2 * m->n_in],
+                     m->h_norm[2 * m->n_in + 1]);
+  MK(hipGetLastError());
   return PA_OK;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
