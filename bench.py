@@ -203,7 +203,8 @@ def _oracle_leg(cfg, R, threads, budget_s):
     import oracle
     L, theta = cfg["L"], cfg["theta"]
     sched = W.linear_schedule(cfg["beta_f"], cfg["K"])
-    p = oracle.OraclePA(L, R, seed=cfg["seed"])
+    p = oracle.OraclePA(L, R, seed=cfg["seed"],
+                        rng_mode=cfg.get("rng_mode", 0))
     t0 = time.perf_counter()
     attempts, steps = 0, 0
     for b in sched:
@@ -247,13 +248,15 @@ def cpu_baseline(cfg, budget_s=24.0):
             "host": host}
 
 
-def bench_batched(binding, stream, use_graph=True):
+def bench_batched(binding, stream, use_graph=True, rng_mode=0):
     """C4: 64 +-J populations (L in {8..32}, R in [2^10, 2^16]), beta 0 -> 3
     in 300 linear steps, theta = 10; each population alone through the
     single-population path, then all of them in one batch.  Both runs give
     bit-identical ln Z, so accuracy is equal by construction."""
     import torch
     inst = W.batched_glass_instances()
+    for c in inst:
+        c["rng_mode"] = rng_mode
     betas = W.linear_schedule(3.0, 300)
     theta = 10
     torch.cuda.synchronize()
@@ -262,7 +265,7 @@ def bench_batched(binding, stream, use_graph=True):
     for c in inst:
         g = binding.Population(c["L"], c["R"], seed=c["seed"],
                                population_id=c["population_id"], J=c["J"],
-                               stream=stream)
+                               stream=stream, rng_mode=rng_mode)
         for b in betas:
             g.resample(b, wait=False)
             g.sweep(b, theta)
@@ -290,11 +293,13 @@ def bench_batched(binding, stream, use_graph=True):
         "speedup": t_plain / t_batch,
         "batched_attempts_per_ns": attempts / (t_batch * 1e9),
         "graph": bool(use_graph),
+        "rng": ["word", "planes"][rng_mode],
         "lnZ_bitwise_equal": lnz_plain == lnz_batch,
     }
 
 
-def bench_learned(binding, use_graph=True, target=0.85, tol=0.02):
+def bench_learned(binding, use_graph=True, target=0.85, tol=0.02,
+                  rng_mode=0):
     """Adaptive schedules on the C4 populations to beta_f = 3, theta = 10:
     the exact bisection on the overlap, and the network (trained on the
     exact schedules of 32 other instances) with the bisection as check and
@@ -307,6 +312,8 @@ def bench_learned(binding, use_graph=True, target=0.85, tol=0.02):
                                            coupling_seed0=10001)
     for k, c in enumerate(train_inst):
         c["population_id"] = 1000 + k
+    for c in inst + train_inst:
+        c["rng_mode"] = rng_mode
     theta, beta_f = 10, 3.0
     t0 = time.perf_counter()
     X, T = learned.generate(train_inst, [0.8, 0.85, 0.9], beta_f, theta)
@@ -315,12 +322,15 @@ def bench_learned(binding, use_graph=True, target=0.85, tol=0.02):
     out = {"training_pairs": int(len(X)), "training_s": t_train,
            "final_loss": loss, "target": target, "tol": tol}
     res = {}
-    for mode in ("bisection", "learned"):
+    for mode in ("bisection", "bisection_tol", "learned"):
         b = binding.Batch(inst, autotune=True)
         t0 = time.perf_counter()
         if mode == "bisection":
             steps = b.run_adaptive(target, beta_f, 20000, theta,
                                    use_graph=use_graph)
+        elif mode == "bisection_tol":
+            steps = b.run_adaptive(target, beta_f, 20000, theta,
+                                   use_graph=use_graph, tol=tol)
         else:
             steps, _ = b.run_learned(mlp, target, tol, beta_f, 20000, theta,
                                      use_graph=use_graph)
@@ -338,25 +348,70 @@ def bench_learned(binding, use_graph=True, target=0.85, tol=0.02):
     d = (res["learned"][3] - res["bisection"][3]) / Ns
     out["lnZ_per_spin_rms_diff"] = float(np.sqrt(np.mean(d * d)))
     out["speedup"] = res["bisection"][0] / res["learned"][0]
+    # against the bisection that stops at the network's own acceptance test
+    out["speedup_vs_tol_bisection"] = (res["bisection_tol"][0] /
+                                       res["learned"][0])
     mlp.close()
     return out
 
 
+def _rms_and_se(err):
+    """RMS of the errors and its standard error (delta method on the mean
+    of the squares)."""
+    import numpy as np
+    e2 = err * err
+    rms = float(np.sqrt(e2.mean()))
+    se = float(e2.std(ddof=1) / np.sqrt(len(e2)) / (2.0 * rms)) if rms else 0.0
+    return rms, se
+
+
+def matched_linear_time(runs, rms):
+    """Wall time of the linear schedule at the RMS error `rms`, by
+    interpolating log(wall time) linearly in log(RMS error) between the two
+    linear runs that bracket it, or, below the longest schedule's error,
+    extrapolating the line through the two longest (flagged); None if the
+    error is above every linear run's."""
+    import math
+    lin = sorted((r["steps"], r["wall_s"], r["rms_err_per_spin"])
+                 for k, r in runs.items() if k.startswith("linear"))
+
+    def at(p1, p2, extrapolated):
+        (k1, t1, e1), (k2, t2, e2) = p1, p2
+        f = (math.log(e1) - math.log(rms)) / (math.log(e1) - math.log(e2))
+        return {"K": math.exp(math.log(k1) + f * (math.log(k2) -
+                                                  math.log(k1))),
+                "wall_s": math.exp(math.log(t1) + f * (math.log(t2) -
+                                                        math.log(t1))),
+                "extrapolated": extrapolated}
+    for p1, p2 in zip(lin, lin[1:]):
+        if p1[2] >= rms >= p2[2] and p1[2] > p2[2]:
+            return at(p1, p2, False)
+    if len(lin) >= 2 and rms < lin[-1][2] and lin[-2][2] > lin[-1][2]:
+        return at(lin[-2], lin[-1], True)
+    return None
+
+
 def bench_accuracy(binding, use_graph=True, M=64, L=32, R=2048, theta=10,
-                   beta_f=1.0):
+                   beta_f=1.0, Ks=(25, 50, 100, 200, 400),
+                   train_LR=((16, 24, 32, 48), (1024, 2048, 4096)),
+                   target=0.85, tol=0.02, label=None, rng_mode=0):
     """Wall time to beta_f against the free-energy error, for M independent
     ferromagnet populations (L, R, theta) run as one batch per schedule:
-    linear schedules of several lengths, the exact bisection at two overlap
-    targets, and the network at 0.85 (trained on the exact schedules of
-    other ferromagnets).  The error is ln Z - ln Z_exact per spin at beta_f,
-    ln Z_exact from Kaufman's finite-torus solution."""
+    linear schedules of several lengths, the exact bisection on the overlap
+    (64 halvings), the bisection stopped at the first step within tol of
+    the target (the network's own acceptance test, without a network), and
+    the network (trained on the exact schedules of other ferromagnets).
+    The error is ln Z - ln Z_exact per spin at beta_f, ln Z_exact from
+    Kaufman's finite-torus solution.  `matched` compares the network with
+    the linear schedule interpolated to the network's RMS error."""
     import numpy as np
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     from exact_ising import kaufman_lnZ
     from paper_2006_00561_amd import learned
     N = L * L
     exact = float(kaufman_lnZ(L, beta_f))
-    pops = [dict(L=L, R=R, seed=7000 + k, population_id=k) for k in range(M)]
+    pops = [dict(L=L, R=R, seed=7000 + k, population_id=k, rng_mode=rng_mode)
+            for k in range(M)]
 
     def timed(fn):
         b = binding.Batch(pops)
@@ -365,44 +420,75 @@ def bench_accuracy(binding, use_graph=True, M=64, L=32, R=2048, theta=10,
         dt = time.perf_counter() - t0
         z = np.array([b.state(p)[3] for p in range(M)])
         steps = max(b.state(p)[2] for p in range(M))
+        st = b.host_stats()
         b.close()
         err = (z - exact) / N
+        rms, se = _rms_and_se(err)
         out = {"steps": int(steps), "wall_s": dt,
-               "rms_err_per_spin": float(np.sqrt(np.mean(err ** 2))),
+               "rms_err_per_spin": rms, "rms_se": se,
                "mean_err_per_spin": float(err.mean()),
-               "sd_err_per_spin": float(err.std(ddof=1))}
+               "sd_err_per_spin": float(err.std(ddof=1)),
+               "host_ms": st["host_ms"], "overlap_evals": st["overlap_evals"]}
         if info:
             out.update(info)
         return out
 
     runs = {}
-    for K in (25, 50, 100, 200, 400):
+    for K in Ks:
         betas = np.array(W.linear_schedule(beta_f, K))
         runs["linear K=%d" % K] = timed(
             lambda b: b.run(betas, theta, use_graph=use_graph))
-    for target in (0.7, 0.85):
-        runs["bisection alpha*=%g" % target] = timed(
-            lambda b: (b.run_adaptive(target, beta_f, 5000, theta,
-                                      use_graph=use_graph),
-                       {"host_ms": b.host_stats()["host_ms"]})[1])
-    train = [dict(L=l, R=r, seed=9000 + 10 * i + j, population_id=100 + 10 * i + j)
-             for i, l in enumerate((16, 24, 32, 48))
-             for j, r in enumerate((1024, 2048, 4096))]
+        progress("accuracy %s: linear K=%d" % (label or L, K))
+    runs["bisection alpha*=%g" % target] = timed(
+        lambda b: b.run_adaptive(target, beta_f, 5000, theta,
+                                 use_graph=use_graph) and None)
+    runs["bisection alpha*=%g tol=%g" % (target, tol)] = timed(
+        lambda b: b.run_adaptive(target, beta_f, 5000, theta,
+                                 use_graph=use_graph, tol=tol) and None)
+    train = [dict(L=l, R=r, seed=9000 + 10 * i + j,
+                  population_id=100 + 10 * i + j, rng_mode=rng_mode)
+             for i, l in enumerate(train_LR[0])
+             for j, r in enumerate(train_LR[1])]
+    t0 = time.perf_counter()
     X, T = learned.generate(train, [0.8, 0.85, 0.9], beta_f, theta)
     mlp, _ = learned.train(X, T, iters=3000, lr=2e-3, seed=17)
+    t_train = time.perf_counter() - t0
+    progress("accuracy %s: network trained" % (label or L))
 
     def run_net(b):
-        _, src = b.run_learned(mlp, 0.85, 0.02, beta_f, 5000, theta,
+        _, src = b.run_learned(mlp, target, tol, beta_f, 5000, theta,
                                use_graph=use_graph)
-        return {"host_ms": b.host_stats()["host_ms"],
-                "sources": [int(v) for v in src]}
-    runs["network alpha*=0.85"] = timed(run_net)
+        return {"sources": [int(v) for v in src]}
+    net_key = "network alpha*=%g tol=%g" % (target, tol)
+    runs[net_key] = timed(run_net)
     mlp.close()
+    net = runs[net_key]
+    m = matched_linear_time(runs, net["rms_err_per_spin"])
+    matched = {"network_rms": net["rms_err_per_spin"],
+               "network_rms_se": net["rms_se"],
+               "network_wall_s": net["wall_s"]}
+    if m:
+        matched.update({"linear_K_at_network_rms": m["K"],
+                        "linear_wall_s_at_network_rms": m["wall_s"],
+                        "linear_extrapolated": m["extrapolated"],
+                        "speedup_vs_linear": m["wall_s"] / net["wall_s"]})
+        # the same at the network's RMS error plus and minus one standard
+        # error: how far the comparison moves within the noise
+        for sgn, tag in ((1, "hi"), (-1, "lo")):
+            mm = matched_linear_time(
+                runs, net["rms_err_per_spin"] + sgn * net["rms_se"])
+            if mm:
+                matched["speedup_vs_linear_rms_%s" % tag] = (
+                    mm["wall_s"] / net["wall_s"])
+    tb = runs["bisection alpha*=%g tol=%g" % (target, tol)]
+    matched["speedup_vs_tol_bisection"] = tb["wall_s"] / net["wall_s"]
     return {"workload": "%d independent ferromagnet populations, L=%d, R=%d, "
                         "theta=%d, beta 0->%g; error of ln Z per spin against "
                         "Kaufman's exact finite-torus value" % (M, L, R, theta,
                                                               beta_f),
-            "lnZ_exact": exact, "training_pairs": int(len(X)), "runs": runs}
+            "lnZ_exact": exact, "training_pairs": int(len(X)),
+            "training_s": t_train, "rng": ["word", "planes"][rng_mode],
+            "runs": runs, "matched": matched}
 
 
 def _find(path):
@@ -476,6 +562,19 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, workload, command):
         lines.append("| %s | %s | %.0f | %s | %s |" % (
             r["Name"], r["Calls"], float(r["AverageNs"]),
             r["TotalDurationNs"], r["Percentage"]))
+    # the sweep launches alone: the trace also holds the initial passes
+    # (theta = 0) and the gather timing's single sweeps
+    durs = []
+    for f in _find(os.path.join(trace_dir, "kernel_trace.csv")):
+        for r in csv.DictReader(open(f)):
+            if r.get("Kernel_Name", "").startswith("k_lattice"):
+                durs.append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    if durs:
+        durs.sort()
+        lines += ["", "k_lattice launch durations: median %.0f ns over %d "
+                  "launches (the initial theta = 0 passes and the single "
+                  "sweeps of the gather timing pull the average down)."
+                  % (durs[len(durs) // 2], len(durs))]
     lines += ["", "HBM traffic of k_lattice per launch (counters scaled by "
               "a 1 GiB copy: FETCH_SIZE x%.3f, WRITE_SIZE x%.3f): fetch "
               "%.1f MB, write %.1f MB, total %.1f MB over %d launches." % (
@@ -568,7 +667,7 @@ def main():
                     choices=["nearest", "poisson", "systematic", "residual",
                              "multinomial"],
                     help="resampling law of the timed anneals")
-    ap.add_argument("--rng", default="word", choices=["word", "planes"],
+    ap.add_argument("--rng", default="planes", choices=["word", "planes"],
                     help="random numbers of the sweep: one Philox word per "
                          "site, or bit planes (one block per 16 sites)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -607,7 +706,7 @@ def main():
     if args.summarize_trace:
         summarize_trace(*args.summarize_trace)
         return
-    rng_flag = "" if args.rng == "word" else " --rng planes"
+    rng_flag = " --rng " + args.rng
     tag = args.workload + ("" if args.rng == "word" else "_planes")
     if args.summarize_valu:
         base = "python3 <repo>/bench.py --workload %s%s --profile-run " \
@@ -658,8 +757,14 @@ def main():
                                        use_graph=not args.eager)), flush=True)
         return
     if args.accuracy_only:
-        print(json.dumps(bench_accuracy(binding, use_graph=not args.eager)),
-              flush=True)
+        print(json.dumps({
+            "accuracy": bench_accuracy(binding, use_graph=not args.eager,
+                                       label="L32"),
+            "accuracy_C2": bench_accuracy(
+                binding, use_graph=not args.eager, M=16, L=64, R=65536,
+                Ks=(50, 100, 200, 400),
+                train_LR=((32, 48, 64), (4096, 16384, 65536)),
+                label="C2")}), flush=True)
         return
     law = ["nearest", "poisson", "systematic", "residual",
            "multinomial"].index(args.law)
@@ -728,6 +833,7 @@ def main():
             "L": cfg["L"], "R": cfg["R"], "K": cfg["K"],
             "theta": cfg["theta"], "layout": cfg["layout"],
             "resampling": args.law,
+            "rng": args.rng,
         },
         "roofline": roof,
         "resample": {
@@ -751,32 +857,48 @@ def main():
         "families_final": fam,
     }
     if not args.no_secondary:
+        # the headline workload in the other random-number stream, and the
+        # int8 workload and the paper's per-GPU shape in the headline's
         sec = {}
-        for name in ("C2", "CP10"):
-            if name == args.workload:
-                continue
+        other = 1 - cfg["rng_mode"]
+        todo = [(args.workload, other)] + [
+            (n, cfg["rng_mode"]) for n in ("C2", "CP10") if n != args.workload]
+        for name, rm in todo:
             c2 = dict(W.CONFIGS[name])
             c2["name"] = name
             c2["law"] = law
-            c2["rng_mode"] = cfg["rng_mode"]
-            r = time_workload(binding, c2, stream, 3, 1, 0)
+            c2["rng_mode"] = rm
+            reps = 2 if c2["R"] > (1 << 20) else 3
+            r = time_workload(binding, c2, stream, reps, 1, 0)
             r["roofline"]["traffic"] = measured_traffic(
-                name + ("" if cfg["rng_mode"] == 0 else "_planes"))
-            sec[name] = {"workload": describe(name, c2), "value": r["value"],
-                         "ms_per_anneal": r["seconds"] * 1e3 / 3,
-                         "roofline": r["roofline"], "lnZ_final": r["lnZ"]}
-            progress("secondary %s: %.1f attempts/ns" % (name, r["value"]))
+                name + ("" if rm == 0 else "_planes"))
+            key = "%s_%s" % (name, ["word", "planes"][rm])
+            sec[key] = {"workload": describe(name, c2), "value": r["value"],
+                        "ms_per_anneal": r["seconds"] * 1e3 / reps,
+                        "roofline": r["roofline"], "lnZ_final": r["lnZ"]}
+            progress("secondary %s: %.1f attempts/ns" % (key, r["value"]))
         out["secondary"] = sec
     if not args.no_batched:
         out["batched"] = bench_batched(binding, stream,
-                                       use_graph=not args.eager)
+                                       use_graph=not args.eager,
+                                       rng_mode=cfg["rng_mode"])
         progress("batched comparison done")
     if not args.no_learned:
-        out["learned"] = bench_learned(binding, use_graph=not args.eager)
+        out["learned"] = bench_learned(binding, use_graph=not args.eager,
+                                       rng_mode=cfg["rng_mode"])
         progress("learned comparison done")
     if not args.no_accuracy:
-        out["accuracy"] = bench_accuracy(binding, use_graph=not args.eager)
+        out["accuracy"] = bench_accuracy(binding, use_graph=not args.eager,
+                                         label="L32",
+                                         rng_mode=cfg["rng_mode"])
         progress("accuracy comparison done")
+        # the same comparison on C2-shaped populations
+        out["accuracy_C2"] = bench_accuracy(
+            binding, use_graph=not args.eager, M=16, L=64, R=65536,
+            Ks=(50, 100, 200, 400),
+            train_LR=((32, 48, 64), (4096, 16384, 65536)), label="C2",
+            rng_mode=cfg["rng_mode"])
+        progress("C2-shape accuracy comparison done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_budget)
         progress("cpu baseline done")
@@ -789,11 +911,13 @@ def progress(msg):
 
 def describe(name, cfg):
     return ("%s: 2D %s ferromagnet L=%d periodic, R=%d, %s spins, beta "
-            "0->%g in %d linear steps, theta=%d, seed %d; one step = one "
-            "full anneal" % (name, ("%d-state Potts" % cfg["q"])
-                             if cfg.get("q") else "Ising", cfg["L"], cfg["R"],
-                             cfg["layout"], cfg["beta_f"], cfg["K"],
-                             cfg["theta"], cfg["seed"]))
+            "0->%g in %d linear steps, theta=%d, seed %d, %s random numbers; "
+            "one step = one full anneal"
+            % (name, ("%d-state Potts" % cfg["q"]) if cfg.get("q") else
+               "Ising", cfg["L"], cfg["R"], cfg["layout"], cfg["beta_f"],
+               cfg["K"], cfg["theta"], cfg["seed"],
+               "bit-plane" if cfg.get("rng_mode") else "one Philox word per "
+               "site"))
 
 
 def time_workload(binding, cfg, stream, steps, warmup, rows_per_lane,

@@ -80,7 +80,8 @@ typedef struct {
   int32_t rows_per_lane; /* sweep launch shape: 1, 2, 3 or 4 lattice rows
                          per lane (must divide L; L/rows <= 64; at least 2
                          for L > 64), or 0: 3 at L = 48 and 96, 2 above
-                         L = 64, else 1 (a batch created with
+                         L = 64 (and at L = 64 with PA_RNG_PLANES), else 1
+                         (a batch created with
                          PA_BATCH_AUTOTUNE times the valid shapes instead).
                          Results do not depend on it.                       */
   uint64_t seed;      /* Philox key                                          */
@@ -416,6 +417,14 @@ int pa_batch_run(pa_batch* b, int32_t steps, const double* betas,
 int pa_batch_run_adaptive(pa_batch* b, double target, double beta_f,
                           int32_t max_steps, int32_t theta, int32_t use_graph,
                           int32_t* steps_taken);
+/* The same schedule rule with the bisection stopped at the first midpoint
+   whose exact overlap lies within `tol` of `target` (tol = 0: the 64
+   halvings of pa_batch_run_adaptive): the step the learned schedule would
+   accept from its network, found without one.  The baseline against which
+   the network's saving is measured. */
+int pa_batch_run_adaptive_tol(pa_batch* b, double target, double tol,
+                              double beta_f, int32_t max_steps, int32_t theta,
+                              int32_t use_graph, int32_t* steps_taken);
 
 /* ------------------------------------------------------------------------
  * Temperature-step network: an FP32 multilayer perceptron (n_in inputs,

@@ -145,6 +145,8 @@ def lib():
             "pa_batch_run": ([P, i32, P, i32, i32], C.c_int),
             "pa_batch_run_adaptive": ([P, d, d, i32, i32, i32,
                                        C.POINTER(i32)], C.c_int),
+            "pa_batch_run_adaptive_tol": ([P, d, d, d, i32, i32, i32,
+                                           C.POINTER(i32)], C.c_int),
             "pa_batch_state": ([P, i32, C.POINTER(i64), C.POINTER(d),
                                 C.POINTER(i32), C.POINTER(d)], C.c_int),
             "pa_batch_trajectory": ([P, i32, P, P, i32, C.POINTER(i32)],
@@ -463,7 +465,7 @@ class Batch:
     def __init__(self, pops, stream=None, autotune=False):
         """pops: list of dicts with keys L, R (target), and optionally J,
         q (q-state Potts), seed, population_id, layout, capacity,
-        rows_per_lane."""
+        rows_per_lane, rng_mode."""
         self.n = len(pops)
         self._keep = []
         cfgs = (pa_config * self.n)()
@@ -485,6 +487,7 @@ class Batch:
             c.rows_per_lane = p.get("rows_per_lane", 0)
             c.seed = p.get("seed", 1)
             c.population_id = p.get("population_id", i)
+            c.rng_mode = p.get("rng_mode", PA_RNG_WORD)
             self.L.append(p["L"])
         h = C.c_void_p()
         _ck(lib().pa_batch_init(cfgs, self.n, stream, 1 if autotune else 0,
@@ -511,11 +514,23 @@ class Batch:
         _ck(lib().pa_batch_run(self._h, b.shape[0], _ptr(b), theta,
                                1 if use_graph else 0), "pa_batch_run")
 
-    def run_adaptive(self, target, beta_f, max_steps, theta, use_graph=True):
+    def run_adaptive(self, target, beta_f, max_steps, theta, use_graph=True,
+                     tol=0.0):
+        """Overlap-targeted schedule by bisection; tol > 0 stops each
+        bisection at the first step whose overlap is within tol of the
+        target (pa_batch_run_adaptive_tol)."""
         st = C.c_int32()
-        _ck(lib().pa_batch_run_adaptive(self._h, target, beta_f, max_steps,
-                                        theta, 1 if use_graph else 0,
-                                        C.byref(st)), "pa_batch_run_adaptive")
+        if tol > 0.0:
+            _ck(lib().pa_batch_run_adaptive_tol(
+                self._h, target, tol, beta_f, max_steps, theta,
+                1 if use_graph else 0, C.byref(st)),
+                "pa_batch_run_adaptive_tol")
+        else:
+            _ck(lib().pa_batch_run_adaptive(self._h, target, beta_f,
+                                            max_steps, theta,
+                                            1 if use_graph else 0,
+                                            C.byref(st)),
+                "pa_batch_run_adaptive")
         return st.value
 
     def state(self, p):

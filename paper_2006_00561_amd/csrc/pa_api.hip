@@ -432,7 +432,7 @@ int pa_init(const pa_config* cfg, pa_ctx** out) try {
   if (cap < cfg->R_target || cap >= (1ll << 32)) return PA_EINVAL;
   const int W = (L + 31) / 32;
   int rpl = cfg->rows_per_lane;
-  if (rpl == 0) rpl = default_rows_per_lane(L);
+  if (rpl == 0) rpl = default_rows_per_lane(L, cfg->rng_mode == PA_RNG_PLANES);
   if (rpl < 1 || rpl > 4) return PA_EINVAL;
   if (L % rpl != 0 || L / rpl > 64) return PA_EINVAL;
   if (W >= 3 && rpl < 2) return PA_EINVAL;

@@ -47,11 +47,11 @@ namespace pa {
 // layout, model), so a persistent launch carries the code of one variant.
 // Sweep classes: 64 Ising variants (W, rows per lane, layout, model), then
 // the Potts pass for L = 8, 16, 32, 64, 128.
-constexpr int kIsingClasses = 64;
+constexpr int kIsingClasses = 128;
 constexpr int kClasses = kIsingClasses + 5;
 __host__ __device__ constexpr int sweep_class(int W, int rpl, int int8,
-                                              int glass) {
-  return (((W - 1) * 4 + (rpl - 1)) * 2 + int8) * 2 + glass;
+                                              int glass, int planes) {
+  return ((((W - 1) * 4 + (rpl - 1)) * 2 + int8) * 2 + glass) + 64 * planes;
 }
 __host__ __device__ constexpr int potts_class(int mpr) {
   return kIsingClasses + (mpr == 1 ? 0 : mpr == 2 ? 1 : mpr == 4 ? 2 : mpr == 8 ? 3 : 4);
@@ -370,13 +370,14 @@ __global__ void k_bpred(const float* z, float* pred, int n, float mu_y,
 // items (population, wave of replicas) from the class queue until the queue
 // is exhausted; every wave reaches the exit once the counter passes the
 // total, which k_bcommit fixed before the launch.
-template <int W, int RPL, bool INT8, bool GLASS>
+template <int W, int RPL, bool INT8, bool GLASS, bool PLANES>
 __global__ __launch_bounds__(256) void k_bsweep(
     const BatchPop* P, const BatchStep* S, const int64_t* R,
     const int32_t* cur, const int32_t* order, const int64_t* prefix,
     unsigned long long* queue, int first, int count, int chunk,
     uint32_t one) {
-  constexpr int cls = sweep_class(W, RPL, INT8 ? 1 : 0, GLASS ? 1 : 0);
+  constexpr int cls =
+      sweep_class(W, RPL, INT8 ? 1 : 0, GLASS ? 1 : 0, PLANES ? 1 : 0);
   const int lane = threadIdx.x & 63;
   const int64_t* pre = prefix + first + cls;
   const int64_t total = pre[count];
@@ -426,7 +427,7 @@ __global__ __launch_bounds__(256) void k_bsweep(
     a.t0 = 0;
     a.theta = st.theta;
     a.init = 0;
-    lattice_pass<W, RPL, INT8, GLASS>(a, this_item - pre[lo]);
+    lattice_pass<W, RPL, INT8, GLASS, PLANES>(a, this_item - pre[lo]);
   }
 }
 
@@ -516,9 +517,10 @@ struct PopHost {
 };
 
 struct TuneKey {
-  int L, layout, model;
+  int L, layout, model, rng_mode;
   bool operator<(const TuneKey& o) const {
-    return std::tie(L, layout, model) < std::tie(o.L, o.layout, o.model);
+    return std::tie(L, layout, model, rng_mode) <
+           std::tie(o.L, o.layout, o.model, o.rng_mode);
   }
 };
 std::map<TuneKey, int>& tune_cache() {
@@ -567,6 +569,7 @@ struct pa_batch {
   pa_mlp* graph_mlp = nullptr;  // the network the graph was built with
   uint64_t graph_mlp_gen = 0;   // and its scratch/scale generation
   double tol = 0.02;
+  double bisect_tol = 0.0;      // mode 1: 0 = the exact 64 halvings
   // schedule
   int mode = 0;                 // 0 explicit schedule, 1 bisection, 2 learned
   std::vector<double> sched;    // [steps][n]
@@ -691,9 +694,11 @@ void host_step(void* ud) {
       } else {
         src = 1;
       }
+      // the exact bisection; as the baseline of the network, the bisection
+      // that stops as soon as a midpoint passes the network's own test
       if (d < 0.0)
         d = bisect_from_hist(h, q.d.nbins, q.d.shift, q.N, R[p], b->target,
-                             span, &ev);
+                             span, &ev, b->mode == 1 ? b->bisect_tol : 0.0);
       b->overlap_evals += ev;
       beta_next = (d == span) ? b->beta_f : q.beta + d;
       if (!(beta_next > q.beta)) beta_next = b->beta_f;  // no progress
@@ -777,23 +782,38 @@ int enqueue_front(pa_batch* b) {
   return PA_OK;
 }
 
+template <int W, int RPL, bool PLANES>
+hipError_t launch_bsweep_wrp(int int8, int glass, unsigned blocks,
+                             hipStream_t st, const BatchPop* P,
+                             const BatchStep* S, const int64_t* R,
+                             const int32_t* cur, const int32_t* order,
+                             const int64_t* prefix, unsigned long long* queue,
+                             int first, int count, int chunk) {
+  const dim3 g(blocks), t(256);
+  if (int8 && glass)
+    hipLaunchKernelGGL((k_bsweep<W, RPL, true, true, PLANES>), g, t, 0, st, P, S, R, cur, order, prefix, queue, first, count, chunk, 1u);
+  else if (int8)
+    hipLaunchKernelGGL((k_bsweep<W, RPL, true, false, PLANES>), g, t, 0, st, P, S, R, cur, order, prefix, queue, first, count, chunk, 1u);
+  else if (glass)
+    hipLaunchKernelGGL((k_bsweep<W, RPL, false, true, PLANES>), g, t, 0, st, P, S, R, cur, order, prefix, queue, first, count, chunk, 1u);
+  else
+    hipLaunchKernelGGL((k_bsweep<W, RPL, false, false, PLANES>), g, t, 0, st, P, S, R, cur, order, prefix, queue, first, count, chunk, 1u);
+  return hipGetLastError();
+}
+
 template <int W, int RPL>
-hipError_t launch_bsweep_wr(int int8, int glass, unsigned blocks,
+hipError_t launch_bsweep_wr(int int8, int glass, int planes, unsigned blocks,
                             hipStream_t st, const BatchPop* P,
                             const BatchStep* S, const int64_t* R,
                             const int32_t* cur, const int32_t* order,
                             const int64_t* prefix, unsigned long long* queue,
                             int first, int count, int chunk) {
-  const dim3 g(blocks), t(256);
-  if (int8 && glass)
-    hipLaunchKernelGGL((k_bsweep<W, RPL, true, true>), g, t, 0, st, P, S, R, cur, order, prefix, queue, first, count, chunk, 1u);
-  else if (int8)
-    hipLaunchKernelGGL((k_bsweep<W, RPL, true, false>), g, t, 0, st, P, S, R, cur, order, prefix, queue, first, count, chunk, 1u);
-  else if (glass)
-    hipLaunchKernelGGL((k_bsweep<W, RPL, false, true>), g, t, 0, st, P, S, R, cur, order, prefix, queue, first, count, chunk, 1u);
-  else
-    hipLaunchKernelGGL((k_bsweep<W, RPL, false, false>), g, t, 0, st, P, S, R, cur, order, prefix, queue, first, count, chunk, 1u);
-  return hipGetLastError();
+  return planes ? launch_bsweep_wrp<W, RPL, true>(int8, glass, blocks, st, P,
+                                                  S, R, cur, order, prefix,
+                                                  queue, first, count, chunk)
+                : launch_bsweep_wrp<W, RPL, false>(int8, glass, blocks, st, P,
+                                                   S, R, cur, order, prefix,
+                                                   queue, first, count, chunk);
 }
 
 // The persistent Potts pass of class k (see potts_class): as many waves as
@@ -831,12 +851,13 @@ hipError_t launch_bsweep(int k, int blocks, int chunk, hipStream_t st,
                          const int64_t* R, const int32_t* cur,
                          const int32_t* order, const int64_t* prefix,
                          unsigned long long* queue, int first, int count) {
-  const int glass = k & 1, int8 = (k >> 1) & 1, rpl = (k >> 2) % 4 + 1,
-            W = (k >> 2) / 4 + 1;
+  const int planes = k >> 6, kk = k & 63;
+  const int glass = kk & 1, int8 = (kk >> 1) & 1, rpl = (kk >> 2) % 4 + 1,
+            W = (kk >> 2) / 4 + 1;
   const unsigned bl = (unsigned)blocks;
 #define PA_BS(w, r) \
-  launch_bsweep_wr<w, r>(int8, glass, bl, st, P, S, R, cur, order, prefix, \
-                         queue, first, count, chunk)
+  launch_bsweep_wr<w, r>(int8, glass, planes, bl, st, P, S, R, cur, order, \
+                         prefix, queue, first, count, chunk)
   switch (W * 8 + rpl) {
     case 1 * 8 + 1: return PA_BS(1, 1);
     case 1 * 8 + 2: return PA_BS(1, 2);
@@ -1018,7 +1039,21 @@ extern "C" {
 
 int pa_tune_rows_per_lane(int32_t L, int32_t layout, int32_t model,
                           int64_t R, int32_t theta, void* stream,
-                          int32_t* best, float* ms) try {
+                          int32_t* best, float* ms) {
+  return tune_rows_per_lane(L, layout, model, PA_RNG_WORD, R, theta, stream,
+                            best, ms);
+}
+
+}  // extern "C"
+
+namespace pa {
+
+// The launch shape of a single population's sweep that takes least time:
+// every valid rows-per-lane of one test population (R replicas, theta
+// sweeps at beta = 0.4, after a warm-up), in the given random-number mode.
+int tune_rows_per_lane(int32_t L, int32_t layout, int32_t model,
+                       int32_t rng_mode, int64_t R, int32_t theta,
+                       void* stream, int32_t* best, float* ms) try {
   if (!best || L < 4 || L > 128 || (L & 1) || R < 1 || theta < 1)
     return PA_EINVAL;
   const int cand[4] = {1, 2, 3, 4};
@@ -1041,6 +1076,7 @@ int pa_tune_rows_per_lane(int32_t L, int32_t layout, int32_t model,
     cfg.rows_per_lane = rpl;
     cfg.seed = 12345;
     cfg.stream = stream;
+    cfg.rng_mode = rng_mode;
     pa_ctx* c = nullptr;
     int rc = pa_init(&cfg, &c);
     if (rc) return rc;
@@ -1071,6 +1107,10 @@ int pa_tune_rows_per_lane(int32_t L, int32_t layout, int32_t model,
   return PA_EDEVICE;
 }
 
+}  // namespace pa
+
+extern "C" {
+
 int pa_batch_init(const pa_config* cfgs, int32_t n, void* stream,
                   int32_t flags, pa_batch** out) try {
   if (!out) return PA_EINVAL;
@@ -1090,7 +1130,9 @@ int pa_batch_init(const pa_config* cfgs, int32_t n, void* stream,
     if (c.model == PA_PMJ && !c.J) return PA_EINVAL;
     if (c.layout != PA_INT8 && c.layout != PA_BITS) return PA_EINVAL;
     if (c.resampling != PA_NEAREST) return PA_EINVAL;  // single path only
-    if (c.rng_mode != PA_RNG_WORD) return PA_EINVAL;   // single path only
+    if (c.rng_mode != PA_RNG_WORD &&
+        (c.rng_mode != PA_RNG_PLANES || c.model == PA_POTTS))
+      return PA_EINVAL;
     if (c.R_target < 1 || c.R_target >= (1ll << 31)) return PA_EINVAL;
     const int rpl = c.model == PA_POTTS ? 0 : c.rows_per_lane;  // Potts: unused
     if (rpl < 0 || rpl > 4) return PA_EINVAL;
@@ -1131,15 +1173,16 @@ int pa_batch_init(const pa_config* cfgs, int32_t n, void* stream,
     PopHost& q = b->pops[p];
     BatchPop& d = q.d;
     int rpl = c.model == PA_POTTS ? 1 : c.rows_per_lane;
+    const bool planes = c.rng_mode == PA_RNG_PLANES;
     if (rpl == 0 && (flags & 1)) {
-      const TuneKey key{c.L, c.layout, c.model};
+      const TuneKey key{c.L, c.layout, c.model, c.rng_mode};
       auto it = tune_cache().find(key);
       if (it != tune_cache().end()) {
         rpl = it->second;
       } else {
         int32_t best = 0;
-        const int rc = pa_tune_rows_per_lane(c.L, c.layout, c.model, 4096, 4,
-                                             b->stream, &best, nullptr);
+        const int rc = tune_rows_per_lane(c.L, c.layout, c.model, c.rng_mode,
+                                          4096, 4, b->stream, &best, nullptr);
         if (rc) {
           free_batch(b);
           delete b;
@@ -1149,8 +1192,9 @@ int pa_batch_init(const pa_config* cfgs, int32_t n, void* stream,
         rpl = best;
       }
     }
-    if (rpl == 0) rpl = default_rows_per_lane(c.L);
+    if (rpl == 0) rpl = default_rows_per_lane(c.L, planes);
     d.L = c.L;
+    d.planes = planes ? 1 : 0;
     d.W = (c.L + 31) / 32;
     d.rpl = rpl;
     d.lpr = c.L / rpl;
@@ -1242,7 +1286,8 @@ int pa_batch_init(const pa_config* cfgs, int32_t n, void* stream,
   // population order: by sweep class, then by L descending
   auto cls_of = [&](int p) {
     const BatchPop& x = b->pops[p].d;
-    return x.q ? potts_class(x.L / 8) : sweep_class(x.W, x.rpl, x.int8, x.glass);
+    return x.q ? potts_class(x.L / 8)
+               : sweep_class(x.W, x.rpl, x.int8, x.glass, x.planes);
   };
   std::vector<int32_t> order(n);
   std::iota(order.begin(), order.end(), 0);
@@ -1318,7 +1363,7 @@ int pa_batch_init(const pa_config* cfgs, int32_t n, void* stream,
     if (rc == PA_OK)
       rc = hip_ok(d.q ? launch_potts(a, b->stream)
                       : launch_lattice(a, d.W, d.rpl, d.int8, d.glass,
-                                       false, b->stream),
+                                       d.planes != 0, b->stream),
                   "initial lattice pass", __LINE__);
     // every initial replica founds its own family
     if (rc == PA_OK)
@@ -1429,11 +1474,19 @@ int pa_batch_run(pa_batch* b, int32_t steps, const double* betas,
 
 int pa_batch_run_adaptive(pa_batch* b, double target, double beta_f,
                           int32_t max_steps, int32_t theta, int32_t use_graph,
-                          int32_t* steps_taken) try {
+                          int32_t* steps_taken) {
+  return pa_batch_run_adaptive_tol(b, target, 0.0, beta_f, max_steps, theta,
+                                   use_graph, steps_taken);
+}
+
+int pa_batch_run_adaptive_tol(pa_batch* b, double target, double tol,
+                              double beta_f, int32_t max_steps, int32_t theta,
+                              int32_t use_graph, int32_t* steps_taken) try {
   if (!b || !(target > 0.0 && target <= 1.0) || !std::isfinite(beta_f) ||
-      max_steps < 1 || theta < 0 || theta > 32767)
+      !(tol >= 0.0) || max_steps < 1 || theta < 0 || theta > 32767)
     return PA_EINVAL;
   b->mode = 1;
+  b->bisect_tol = tol;
   b->mlp = nullptr;
   b->target = target;
   b->beta_f = beta_f;

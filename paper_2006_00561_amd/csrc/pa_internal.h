@@ -105,6 +105,8 @@ struct BatchPop {          // static description of one population
   int32_t L, W, rpl, lpr, rpw, nbins, shift, glass, int8, chunks, lpr_log2;
   int32_t q;               // Potts states (0: Ising)
   uint32_t k0, k1, pop;
+  int32_t planes;          // sweep random numbers: 1 bit planes, 0 words
+  int32_t pad_;
 };
 
 struct BatchStep {         // per population, rewritten by the host each step
@@ -122,10 +124,20 @@ struct BatchStep {         // per population, rewritten by the host each step
 // Sweep shape when the caller leaves rows_per_lane at 0 and nothing is
 // tuned: three rows per lane fill whole waves at L = 48 and 96 (16 and 32
 // lanes per replica), where the tuner measured them fastest; two rows above
-// L = 64 keep the registers in bounds; one row otherwise.
-inline int default_rows_per_lane(int L) {
+// L = 64 keep the registers in bounds; one row otherwise.  The plane stream
+// takes two rows at L = 64: a lane then resolves the ties of 64 draws per
+// half sweep in one pass more often than of 32 (4977 against 4844
+// attempts/ns at L = 64, R = 2^21).
+inline int default_rows_per_lane(int L, bool planes = false) {
+  if (planes && L == 64) return 2;
   return (L == 48 || L == 96) ? 3 : (L > 64 ? 2 : 1);
 }
+
+// Fastest rows-per-lane of a single population's sweep, timed on a test
+// population (pa_batch.hip; pa_tune_rows_per_lane is its word-stream form).
+int tune_rows_per_lane(int32_t L, int32_t layout, int32_t model,
+                       int32_t rng_mode, int64_t R, int32_t theta,
+                       void* stream, int32_t* best, float* ms);
 
 // Histogram summaries fed to the temperature-step network (kFeatures per
 // population, computed on the device from the exact histogram).
@@ -187,7 +199,7 @@ void observables_from_hist(const uint32_t* h, int nbins, int shift, int N,
                            int64_t sumM2, pa_obs* o);
 double bisect_from_hist(const uint32_t* h, int nbins, int shift, int N,
                         int64_t R, double target, double span,
-                        int* evals = nullptr);
+                        int* evals = nullptr, double tol = 0.0);
 
 // ---- kernel launchers (pa_kernels.hip)
 hipError_t launch_lattice(const LatticeArgs& a, int W, int RPL, bool int8,

@@ -224,20 +224,30 @@ double overlap_from_hist(const uint32_t* h, int nbins, int shift, int N,
 
 // Largest dbeta <= span with alpha(dbeta) >= target: the whole span if it
 // qualifies, else 64 halvings of [0, span] keeping the lower end qualified.
+// With tol > 0 the halving stops at the first midpoint whose overlap is
+// within tol of the target (the acceptance test of a proposed step) and
+// returns it.
 double bisect_from_hist(const uint32_t* h, int nbins, int shift, int N,
-                        int64_t R, double target, double span, int* evals) {
+                        int64_t R, double target, double span, int* evals,
+                        double tol) {
   if (!(span > 0.0)) return 0.0;
   int k = 1;
   double d = span;
   if (overlap_from_hist(h, nbins, shift, N, R, span) < target) {
     double lo = 0.0, hi = span;
+    d = -1.0;
     for (int it = 0; it < 64; ++it) {
       const double mid = 0.5 * (lo + hi);
       ++k;
-      if (overlap_from_hist(h, nbins, shift, N, R, mid) >= target) lo = mid;
+      const double a = overlap_from_hist(h, nbins, shift, N, R, mid);
+      if (tol > 0.0 && std::fabs(a - target) <= tol) {
+        d = mid;
+        break;
+      }
+      if (a >= target) lo = mid;
       else hi = mid;
     }
-    d = lo;
+    if (d < 0.0) d = lo;
   }
   if (evals) *evals += k;
   return d;

@@ -56,7 +56,7 @@ def test_strerror_and_validation_without_device():
     cfg.rng_mode = b.PA_RNG_PLANES
     assert lib.pa_init(C.byref(cfg), C.byref(h)) == b.PA_EINVAL
     assert not h.value
-    # the batch takes the nearest-integer law and the word stream only
+    # the batch takes the nearest-integer law only
     cfg = b.pa_config()
     cfg.L, cfg.R_target, cfg.resampling = 8, 10, b.PA_POISSON
     bh = C.c_void_p()
@@ -64,7 +64,13 @@ def test_strerror_and_validation_without_device():
                              C.byref(bh)) == b.PA_EINVAL
     assert not bh.value
     cfg = b.pa_config()
-    cfg.L, cfg.R_target, cfg.rng_mode = 8, 10, b.PA_RNG_PLANES
+    cfg.L, cfg.R_target, cfg.rng_mode = 8, 10, 2           # no such stream
+    assert lib.pa_batch_init(C.byref(cfg), 1, None, 0,
+                             C.byref(bh)) == b.PA_EINVAL
+    assert not bh.value
+    cfg = b.pa_config()                                    # Potts: words only
+    cfg.L, cfg.R_target, cfg.model, cfg.q = 16, 10, b.PA_POTTS, 3
+    cfg.rng_mode = b.PA_RNG_PLANES
     assert lib.pa_batch_init(C.byref(cfg), 1, None, 0,
                              C.byref(bh)) == b.PA_EINVAL
     assert not bh.value

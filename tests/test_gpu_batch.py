@@ -45,7 +45,8 @@ def _mixed_pops():
 
 def _oracle_run(pop, betas, theta):
     o = oracle.OraclePA(pop["L"], pop["R"], seed=pop["seed"],
-                        pop=pop["population_id"], J=pop["J"])
+                        pop=pop["population_id"], J=pop["J"],
+                        rng_mode=pop.get("rng_mode", 0))
     traj = []
     for b in betas:
         o.resample(b)
@@ -79,6 +80,25 @@ def test_mixed_batch_matches_oracle(pa, use_graph):
     theta = 3
     print("batch parity graph=%s" % use_graph, flush=True)
     b = pa.Batch(pops)
+    b.run(np.array(betas), theta, use_graph=use_graph)
+    for p, pop in enumerate(pops):
+        o, traj = _oracle_run(pop, betas, theta)
+        _check_pop(b, p, o, traj)
+    b.close()
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_plane_stream_batch_matches_oracle(pa, use_graph):
+    """Populations in the bit-plane random-number stream beside populations
+    in the word stream, in one batch (both persistent sweep classes in one
+    step): every population equals the oracle's run in its own stream."""
+    pops = _mixed_pops()
+    for k, p in enumerate(pops):
+        p["rng_mode"] = pa.PA_RNG_PLANES if k % 3 != 1 else pa.PA_RNG_WORD
+    betas = W.linear_schedule(1.4, 6)
+    theta = 3
+    print("plane-stream batch parity graph=%s" % use_graph, flush=True)
+    b = pa.Batch(pops, autotune=use_graph)
     b.run(np.array(betas), theta, use_graph=use_graph)
     for p, pop in enumerate(pops):
         o, traj = _oracle_run(pop, betas, theta)

@@ -186,3 +186,71 @@ def test_corrupted_network_falls_back_to_the_exact_schedule(pa, corruption):
     b.close()
     ref.close()
     mlp.close()
+
+
+def _replay_on_oracle(b, pops, theta, target, tol, n_steps=None):
+    """Replays each population's schedule of the batch on the oracle: equal
+    ln Z after every replayed step and equal populations at the end; every
+    step that came from a bisection or the network meets the overlap test
+    exactly.  n_steps limits the replay to the first steps."""
+    from paper_2006_00561_amd import learned
+    for p, pop in enumerate(pops):
+        obs, lnZ = b.trajectory(p)
+        f, db, srcs = b.decisions(p)
+        o = oracle.OraclePA(pop["L"], pop["R"], seed=pop["seed"],
+                            pop=pop["population_id"])
+        last = len(obs) if n_steps is None else min(n_steps, len(obs))
+        for k in range(last):
+            beta = obs[k]["beta"]
+            if srcs[k] in (learned.SRC_NET, learned.SRC_BISECT):
+                a = o.overlap(beta - o.beta)
+                assert abs(a - target) <= tol + 1e-12, (p, k, a)
+            o.resample(beta)
+            o.sweep(theta)
+            assert o.free_energy()[0] == lnZ[k], (p, k)
+        if last == len(obs):
+            s, E, M = b.population(p)
+            so, Eo, Mo = o.population()
+            assert np.array_equal(s, so) and np.array_equal(E, Eo)
+        o.close()
+
+
+def test_tolerance_bisection_meets_the_network_test_and_replays(pa):
+    """The bisection stopped at the first step within tol of the target
+    (the baseline of the learned schedule): every bisection step passes the
+    network's acceptance test on the oracle, the run replays bit for bit,
+    and it needs fewer exact overlap evaluations than the 64 halvings."""
+    pops = _ferro_pops([(12, 700), (16, 500), (20, 400)], 800, id0=50)
+    target, tol, beta_f, theta = 0.85, 0.02, 1.2, 2
+    b = pa.Batch(pops)
+    b.run_adaptive(target, beta_f, 1000, theta, tol=tol)
+    ev_tol = b.host_stats()["overlap_evals"]
+    _replay_on_oracle(b, pops, theta, target, tol)
+    ref = pa.Batch(pops)
+    ref.run_adaptive(target, beta_f, 1000, theta)
+    ev_exact = ref.host_stats()["overlap_evals"]
+    print("overlap evaluations: tol-stopped %d, exact %d" % (ev_tol, ev_exact))
+    assert ev_tol < 0.5 * ev_exact
+    b.close()
+    ref.close()
+
+
+def test_learned_schedule_at_L64_replays_on_the_oracle(pa):
+    """A network trained on exact schedules of L = 32..64 ferromagnets runs
+    an L = 64 population (the benchmark's lattice): the first steps of its
+    schedule, replayed on the oracle, give the same ln Z, and each accepted
+    proposal meets the overlap test exactly."""
+    from paper_2006_00561_amd import learned
+    train = _ferro_pops([(32, 1500), (48, 1000), (64, 800), (64, 1600)],
+                        900, id0=60)
+    target, tol, beta_f, theta = 0.85, 0.02, 1.0, 10
+    X, T = learned.generate(train, [0.8, 0.85, 0.9], beta_f, theta)
+    mlp, loss = learned.train(X, T, iters=3000, lr=2e-3, seed=21)
+    pops = _ferro_pops([(64, 300)], 990, id0=70)
+    b = pa.Batch(pops)
+    steps, src = b.run_learned(mlp, target, tol, beta_f, 1000, theta)
+    print("L=64 learned schedule: %d steps, sources %s" % (steps, list(src)))
+    assert src[learned.SRC_NET] > 0
+    _replay_on_oracle(b, pops, theta, target, tol, n_steps=6)
+    mlp.close()
+    b.close()

@@ -254,44 +254,59 @@ def test_timing_counters(pa):
         assert t[k]["launches"] == 0 and t[k]["ms"] == 0.0
 
 
-@pytest.mark.parametrize("name,steps,sample", [("C2", 3, 48), ("C3a", 2, 24),
-                                               ("C3b", 2, 16),
-                                               ("CQ10", 2, 24)])
-def test_full_size_sampled(pa, name, steps, sample):
+@pytest.mark.parametrize("name,start,steps,sample,rng", [
+    ("C2", 1, 3, 48, 0), ("C3a", 1, 2, 24, 0), ("C3b", 1, 2, 16, 0),
+    ("CQ10", 1, 2, 24, 0),
+    # the steps nearest the critical point beta_c = ln(1 + sqrt 2)/2 = 0.4407
+    # (beta = 0.44 at step 88 of both schedules), where the copy counts
+    # spread widest
+    ("C2", 88, 2, 48, 0), ("C3a", 88, 2, 24, 0),
+    # the bit-plane random numbers at the paper's scale
+    ("C3a", 1, 2, 24, 1), ("C3a", 88, 2, 24, 1)])
+def test_full_size_sampled(pa, name, start, steps, sample, rng):
     """At the benchmark sizes and in the benchmark's launch configuration
     (the capacity at which no resampling waits for its new size, resampling
     without waiting, the copies made by the next sweep from the parents):
-    every copy count, R_new and ln Q exactly from the oracle's count step on
-    the device energies; a sample of new replicas through theta sweeps with
-    the oracle's single-replica sweep, started from their parents' states
-    read before the resampling; observables from the full E and M arrays."""
+    the population first runs unchecked on the device up to step start - 1;
+    then, for `steps` steps, every copy count, R_new and ln Q exactly from
+    the oracle's count step on the device energies; a sample of new
+    replicas through theta sweeps with the oracle's single-replica sweep,
+    started from their parents' states read before the resampling;
+    observables from the full E and M arrays."""
     c = W.CONFIGS[name]
     L, R, theta, q = c["L"], c["R"], c["theta"], c.get("q", 0)
     layout = 1 if c["layout"] == "bits" else 0
-    print("full-size parity %s L=%d R=%d layout=%d q=%d" % (name, L, R, layout,
-                                                           q), flush=True)
+    print("full-size parity %s L=%d R=%d layout=%d q=%d start=%d rng=%d"
+          % (name, L, R, layout, q, start, rng), flush=True)
     g = pa.Population(L, R, seed=c["seed"], layout=layout, q=q,
-                      capacity=W.deferral_capacity(R))
-    rng = np.random.default_rng(0)
+                      capacity=W.deferral_capacity(R), rng_mode=rng)
+    rng_o = oracle.RNG_PLANES if rng else oracle.RNG_WORD
+    gen = np.random.default_rng(start)
     sched = W.linear_schedule(c["beta_f"], c["K"])
-    # initial state: sampled replicas against the oracle's init
-    o = oracle.OraclePA(L, 8, seed=c["seed"], q=q)
-    so, Eo, Mo = o.population()
-    sg, Eg, Mg = g.replicas(np.arange(8))
-    assert np.array_equal(sg, so) and np.array_equal(Eg, Eo)
-    assert np.array_equal(Mg, Mo)
-    o.close()
+    if start == 1:
+        # initial state: sampled replicas against the oracle's init
+        o = oracle.OraclePA(L, 8, seed=c["seed"], q=q)
+        so, Eo, Mo = o.population()
+        sg, Eg, Mg = g.replicas(np.arange(8))
+        assert np.array_equal(sg, so) and np.array_equal(Eg, Eo)
+        assert np.array_equal(Mg, Mo)
+        o.close()
+        fam, n0 = g.families()
+        assert n0 == R and np.array_equal(fam, np.arange(R))
+    else:
+        for b in sched[:start - 1]:
+            g.resample(b, wait=False)
+            g.sweep(b, theta)
+        fam, n0 = g.families()
     zlast = g.free_energy()[0]
-    fam, n0 = g.families()
-    assert n0 == R and np.array_equal(fam, np.arange(R))
-    for i in range(1, steps + 1):
+    for i in range(start, start + steps):
         b = sched[i - 1]
         E, M = g.energies()
         n_o, Rn_o, lnQ_o = oracle.counts(L * L, E, R, b - g.beta, c["seed"],
                                          0, i)
         parent = np.repeat(np.arange(len(E)), n_o)
         fam = fam[parent]  # every copy joins its parent's family
-        slots = np.sort(rng.choice(Rn_o, size=sample, replace=False))
+        slots = np.sort(gen.choice(Rn_o, size=sample, replace=False))
         s_pre, E_pre, M_pre = g.replicas(parent[slots])
         g.resample(b, wait=False)
         g.sweep(b, theta)
@@ -310,7 +325,8 @@ def test_full_size_sampled(pa, name, steps, sample):
             else:
                 so, eo, mo = oracle.sweep_replica(s_pre[k], E_pre[k],
                                                   M_pre[k], b, c["seed"], 0,
-                                                  i, 0, theta, int(j))
+                                                  i, 0, theta, int(j),
+                                                  rng_mode=rng_o)
             assert np.array_equal(s_post[k], so), (name, i, j)
             assert (E_post[k], M_post[k]) == (eo, mo)
         E2, M2 = g.energies()
