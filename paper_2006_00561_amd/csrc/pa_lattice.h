@@ -121,61 +121,88 @@ __device__ __forceinline__ void store_row(uint8_t* rp, int L, int y,
 // the site at bit position b of the word from bit b XOR h of output word i.
 // All 16 colour sites of the word sit at positions of parity p, so planes
 // 2i come from output word i as it is and planes 2i + 1 from it rotated by
-// one place towards them.  r < T iff B < T >> 24, or B == T >> 24 and
-// floor(w / 2^8) < T mod 2^24: the comparison runs bit-sliced over the
-// word, and only the ties need w.
+// one place towards them.  r < T iff B < t, or B == t and floor(w / 2^8) <
+// T - t 2^24, with t = min(T >> 24, 255): the comparison runs bit-sliced
+// over the word, and only the ties need w.  (T = 2^32, which accepts every
+// draw, becomes t = 255 with a low part of 2^24 that every tie passes.)
 struct PlaneThr {
-  uint32_t tm4[8], tm8[8];  // all ones where bit k of T >> 24 is set
-  uint32_t lo4, lo8;        // T mod 2^24
-  bool big4, big8;          // T = 2^32: every draw accepts
+  uint32_t tm4[8], tm8[8];  // all ones where bit k of t is set
+  uint32_t lo4, lo8;        // T - t 2^24, at most 2^24
 };
 
 __device__ __forceinline__ PlaneThr plane_thresholds(const LatticeArgs& a) {
   PlaneThr t;
   const uint64_t T4 = (1ull << 32) - a.K4, T8 = (1ull << 32) - a.K8;
-  const uint32_t b4 = (uint32_t)(T4 >> 24) & 0xFFu;
-  const uint32_t b8 = (uint32_t)(T8 >> 24) & 0xFFu;
+  const uint64_t b4 = (T4 >> 24) < 255 ? (T4 >> 24) : 255;
+  const uint64_t b8 = (T8 >> 24) < 255 ? (T8 >> 24) : 255;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    t.tm4[k] = 0u - ((b4 >> k) & 1u);
-    t.tm8[k] = 0u - ((b8 >> k) & 1u);
+    t.tm4[k] = 0u - (uint32_t)((b4 >> k) & 1u);
+    t.tm8[k] = 0u - (uint32_t)((b8 >> k) & 1u);
   }
-  t.lo4 = (uint32_t)T4 & 0xFFFFFFu;
-  t.lo8 = (uint32_t)T8 & 0xFFFFFFu;
-  t.big4 = (T4 >> 32) != 0;
-  t.big8 = (T8 >> 32) != 0;
+  t.lo4 = (uint32_t)(T4 - (b4 << 24));
+  t.lo8 = (uint32_t)(T8 - (b8 << 24));
   return t;
 }
 
-// The plane block of one word: lt4/lt8 get B < T >> 24 and tie4/tie8
-// B == T >> 24 for the thresholds of dE = 4 and 8, per bit position (only
-// positions of parity p are meaningful).
+// Rotation by one place that brings bit b XOR 1 to position b for the
+// positions b of parity par: right by 1 for even b, left by 1 for odd b.
+__device__ __forceinline__ uint32_t to_parity(uint32_t x, uint32_t par) {
+  return __builtin_amdgcn_alignbit(x, x, par ? 31u : 1u);
+}
+
+// The plane block of one word: lt4/lt8 get B < t and e4/e8 B == t for the
+// thresholds of dE = 4 and 8, per bit position (only positions of parity p
+// are meaningful).
 __device__ __forceinline__ void plane_decide(const uint4 o, uint32_t p,
                                              const PlaneThr& t, uint32_t& lt4,
-                                             uint32_t& tie4, uint32_t& lt8,
-                                             uint32_t& tie8) {
-  // rotation by one place that brings bit b XOR 1 to position b for the
-  // positions b of parity p: right by 1 for even b, left by 1 for odd b
-  const uint32_t sh = p ? 31u : 1u;
+                                             uint32_t& e4, uint32_t& lt8,
+                                             uint32_t& e8) {
   uint32_t P[8];
   P[7] = o.x;
-  P[6] = __builtin_amdgcn_alignbit(o.x, o.x, sh);
+  P[6] = to_parity(o.x, p);
   P[5] = o.y;
-  P[4] = __builtin_amdgcn_alignbit(o.y, o.y, sh);
+  P[4] = to_parity(o.y, p);
   P[3] = o.z;
-  P[2] = __builtin_amdgcn_alignbit(o.z, o.z, sh);
+  P[2] = to_parity(o.z, p);
   P[1] = o.w;
-  P[0] = __builtin_amdgcn_alignbit(o.w, o.w, sh);
-  compare_byte(P, t.tm4, lt4, tie4);
-  compare_byte(P, t.tm8, lt8, tie8);
-  if (t.big4) {
-    lt4 = ~0u;
-    tie4 = 0u;
+  P[0] = to_parity(o.w, p);
+  compare_byte(P, t.tm4, lt4, e4);
+  compare_byte(P, t.tm8, lt8, e8);
+}
+
+// Two words of one row in one comparison: word A's colour sites keep their
+// positions (parity p) and word B's colour site at position b moves to b
+// XOR 1 (parity 1 - p), so all 32 positions are colour sites.  Results come
+// back per word at the sites' own positions.
+__device__ __forceinline__ void plane_decide2(const uint4 oA, const uint4 oB,
+                                              uint32_t p, const PlaneThr& t,
+                                              uint32_t* lt4, uint32_t* e4,
+                                              uint32_t* lt8, uint32_t* e8) {
+  const uint32_t cm = p ? 0xAAAAAAAAu : 0x55555555u;  // positions of parity p
+  const uint32_t q = p ^ 1u;
+  const uint32_t a[4] = {oA.x, oA.y, oA.z, oA.w};
+  const uint32_t b[4] = {oB.x, oB.y, oB.z, oB.w};
+  uint32_t P[8];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    // plane 2i: A's bit at its site, B's bit at its site (now one over)
+    P[7 - 2 * i] = (a[i] & cm) | (to_parity(b[i], q) & ~cm);
+    // plane 2i + 1: A's bit next to its site, B's bit next to its site,
+    // which is where B's site now sits
+    P[6 - 2 * i] = (to_parity(a[i], p) & cm) | (b[i] & ~cm);
   }
-  if (t.big8) {
-    lt8 = ~0u;
-    tie8 = 0u;
-  }
+  uint32_t l4, q4, l8, q8;
+  compare_byte(P, t.tm4, l4, q4);
+  compare_byte(P, t.tm8, l8, q8);
+  lt4[0] = l4;
+  e4[0] = q4;
+  lt8[0] = l8;
+  e8[0] = q8;
+  lt4[1] = to_parity(l4, p);
+  e4[1] = to_parity(q4, p);
+  lt8[1] = to_parity(l8, p);
+  e8[1] = to_parity(q8, p);
 }
 
 // One wave's share of a lattice pass: replicas wave*rpw .. wave*rpw+rpw-1.
@@ -280,9 +307,9 @@ __device__ __forceinline__ void lattice_pass(const LatticeArgs& a,
         dnl[w] = shfl(s[0][w], dn_lane);
       }
       const uint32_t ctr1 = (a.step << 16) | (uint32_t)(2 * (a.t0 + t) + c);
-      // bit-plane mode: flips decided by the planes, and the sites whose
-      // byte ties with the threshold's top byte (dE = 4 and 8 apart)
-      uint32_t flip[RPL][W], tie4[RPL][W], tie8[RPL][W];
+      // bit-plane mode: flips decided by the planes, the sites whose byte
+      // ties with the threshold's top byte, and their dE = +4 mask
+      uint32_t flip[RPL][W], tie[RPL][W], cls4[RPL][W];
 #pragma unroll
       for (int r = 0; r < RPL; ++r) {
         const int y = lr * RPL + r;
@@ -293,6 +320,7 @@ __device__ __forceinline__ void lattice_pass(const LatticeArgs& a,
         uint32_t lf[W], rt[W];
         row_from_left<W>(s[r], lf, L);
         row_from_right<W>(s[r], rt, L);
+        uint32_t e0[W], e1[W], g2[W], cl[W];
 #pragma unroll
         for (int w = 0; w < W; ++w) {
           const uint32_t sv = s[r][w];
@@ -302,24 +330,39 @@ __device__ __forceinline__ void lattice_pass(const LatticeArgs& a,
           const uint32_t d4 = sv ^ dn[w] ^ jd[r][w];
           const uint32_t x1 = d1 ^ d2, a1 = d1 & d2;
           const uint32_t x2 = d3 ^ d4, a2 = d3 & d4;
-          const uint32_t eq0 = ~(d1 | d2 | d3 | d4);  // dE = +8
-          const uint32_t eq1 = (x1 ^ x2) & ~(a1 | a2); // dE = +4
-          const uint32_t ge2 = ~(eq0 | eq1);           // dE <= 0
-          const uint32_t col = (p ? 0xAAAAAAAAu : 0x55555555u) & valid_mask(L, w);
-          if (PLANES) {
-            const uint4 o = philox10(
+          e0[w] = ~(d1 | d2 | d3 | d4);        // dE = +8
+          e1[w] = (x1 ^ x2) & ~(a1 | a2);      // dE = +4
+          g2[w] = ~(e0[w] | e1[w]);            // dE <= 0
+          cl[w] = (p ? 0xAAAAAAAAu : 0x55555555u) & valid_mask(L, w);
+        }
+        if (PLANES) {
+          uint4 o[W];
+#pragma unroll
+          for (int w = 0; w < W; ++w)
+            o[w] = philox10(
                 make_uint4((kDomainMcmcPlanes << 28) | (uint32_t)(y * W + w),
                            ctr1, slot, a.pop),
                 a.k0, a.k1);
-            uint32_t lt4, e4, lt8, e8;
-            plane_decide(o, p, pt, lt4, e4, lt8, e8);
-            // lanes past the population hold no replica: no ties to resolve
-            const uint32_t cola = active ? col : 0u;
-            flip[r][w] = col & (ge2 | (eq1 & lt4) | (eq0 & lt8));
-            tie4[r][w] = cola & eq1 & e4;
-            tie8[r][w] = cola & eq0 & e8;
-            continue;
+          uint32_t lt4[W], e4[W], lt8[W], e8[W];
+#pragma unroll
+          for (int w = 0; w + 1 < W; w += 2)
+            plane_decide2(o[w], o[w + 1], p, pt, &lt4[w], &e4[w], &lt8[w],
+                          &e8[w]);
+          if (W & 1)
+            plane_decide(o[W - 1], p, pt, lt4[W - 1], e4[W - 1], lt8[W - 1],
+                         e8[W - 1]);
+          // lanes past the population hold no replica: no ties to resolve
+          const uint32_t act = active ? ~0u : 0u;
+#pragma unroll
+          for (int w = 0; w < W; ++w) {
+            flip[r][w] = cl[w] & (g2[w] | (e1[w] & lt4[w]) | (e0[w] & lt8[w]));
+            tie[r][w] = cl[w] & act & ((e1[w] & e4[w]) | (e0[w] & e8[w]));
+            cls4[r][w] = e1[w];
           }
+          continue;
+        }
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
           // The 16 colour sites of this word (k = 16w + j, x = 2k + p) draw
           // word j%4 of group 4w + j/4.  The rejection bit of a site is the
           // carry of r + (2^32 - T): hi(r * 1 + K) is 1 iff r >= T, one
@@ -343,21 +386,21 @@ __device__ __forceinline__ void lattice_pass(const LatticeArgs& a,
           }
           const uint32_t M4 = (~rj4 & 0x55555555u) << p;
           const uint32_t M8 = (~rj8 & 0x55555555u) << p;
-          const uint32_t flp = col & (ge2 | (eq1 & M4) | (eq0 & M8));
-          s[r][w] = sv ^ flp;
+          const uint32_t flp = cl[w] & (g2[w] | (e1[w] & M4) | (e0[w] & M8));
+          s[r][w] ^= flp;
         }
       }
       if (PLANES) {
         // Ties: each pass takes the lowest pending tie of every lane that
         // has one (first by row and word, then by bit), draws that site's
-        // default-stream word and decides it on the low 24 bits of T.  The
+        // default-stream word and decides it on the low part of T.  The
         // wave leaves when no lane has a tie left.
         for (;;) {
           uint32_t tm = 0u;
           int sel = 0;
 #pragma unroll
           for (int i = RPL * W - 1; i >= 0; --i) {
-            const uint32_t ti = tie4[i / W][i % W] | tie8[i / W][i % W];
+            const uint32_t ti = tie[i / W][i % W];
             if (ti) {
               tm = ti;
               sel = i;
@@ -380,14 +423,13 @@ __device__ __forceinline__ void lattice_pass(const LatticeArgs& a,
             uint32_t is4 = 0u;
 #pragma unroll
             for (int i = 0; i < RPL * W; ++i)
-              if (sel == i) is4 = tie4[i / W][i % W] & bm;
+              if (sel == i) is4 = cls4[i / W][i % W] & bm;
             const uint32_t acc =
                 ((wv >> 8) < (is4 ? pt.lo4 : pt.lo8)) ? bm : 0u;
 #pragma unroll
             for (int i = 0; i < RPL * W; ++i)
               if (sel == i) {
-                tie4[i / W][i % W] &= ~bm;
-                tie8[i / W][i % W] &= ~bm;
+                tie[i / W][i % W] &= ~bm;
                 flip[i / W][i % W] |= acc;
               }
           }
