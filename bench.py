@@ -76,8 +76,9 @@ def traffic_file(workload):
     return os.path.join(ROOT, "profiles", "k_lattice_%s_traffic.json" % workload)
 
 
-def valu_file(workload):
-    return os.path.join(ROOT, "profiles", "k_lattice_%s_valu.json" % workload)
+def valu_file(workload, kernel="k_lattice"):
+    return os.path.join(ROOT, "profiles", "%s_%s_valu.json" % (kernel,
+                                                               workload))
 
 
 def kernel_hash():
@@ -292,6 +293,7 @@ def bench_batched(binding, stream, use_graph=True, rng_mode=0):
         "batched_init_s": t_init, "batched_host_ms": host_ms,
         "speedup": t_plain / t_batch,
         "batched_attempts_per_ns": attempts / (t_batch * 1e9),
+        "attempts": attempts,
         "graph": bool(use_graph),
         "rng": ["word", "planes"][rng_mode],
         "lnZ_bitwise_equal": lnz_plain == lnz_batch,
@@ -585,7 +587,8 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, workload, command):
         fh.write("\n".join(lines) + "\n")
 
 
-def summarize_valu(pmc_dir, run_json, trace_dir, workload, command):
+def summarize_valu(pmc_dir, run_json, trace_dir, workload, command,
+                   kernel="k_lattice"):
     """profiles/k_lattice_<workload>_valu.json and a line in
     profiles/kernels_<workload>.md from a rocprofv3 --pmc run of
     `bench.py --profile-run` (SQ_INSTS_VALU and the other counters of the
@@ -599,7 +602,7 @@ def summarize_valu(pmc_dir, run_json, trace_dir, workload, command):
         raise SystemExit("no counter_collection.csv in " + pmc_dir)
     tot, disp = {}, set()
     for r in csv.DictReader(open(f[0])):
-        if not r["Kernel_Name"].startswith("k_lattice"):
+        if not r["Kernel_Name"].startswith(kernel):
             continue
         disp.add(r.get("Dispatch_Id", r.get("Correlation_Id", "")))
         tot[r["Counter_Name"]] = tot.get(r["Counter_Name"], 0.0) + float(
@@ -610,9 +613,9 @@ def summarize_valu(pmc_dir, run_json, trace_dir, workload, command):
     tf = _find(os.path.join(trace_dir, "kernel_stats.csv"))
     dur_ns = None
     for r in csv.DictReader(open(tf[0])) if tf else []:
-        if r["Name"].startswith("k_lattice"):
-            dur_ns = float(r["TotalDurationNs"])
-    out = {"workload": workload, "kernel": "k_lattice",
+        if r["Name"].startswith(kernel):
+            dur_ns = (dur_ns or 0.0) + float(r["TotalDurationNs"])
+    out = {"workload": workload, "kernel": kernel,
            "kernel_sha256": kernel_hash(), "dispatches": len(disp),
            "attempts": att, "counters": tot, "commands": command}
     if "SQ_INSTS_VALU" in tot:
@@ -627,8 +630,10 @@ def summarize_valu(pmc_dir, run_json, trace_dir, workload, command):
             tot["SQ_INSTS_VALU"] * 4.0 / 1024.0) / (dur_ns * 2.4)
         if "GRBM_GUI_ACTIVE" in tot:
             out["grbm_gui_active_per_ns"] = tot["GRBM_GUI_ACTIVE"] / dur_ns
+    if dur_ns:
+        out["attempts_per_ns"] = att / dur_ns
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
-    with open(valu_file(workload), "w") as fh:
+    with open(valu_file(workload, kernel), "w") as fh:
         json.dump(out, fh, indent=1)
 
 
@@ -683,7 +688,14 @@ def main():
                          "rocprofv3 counter passes)")
     ap.add_argument("--summarize-valu", nargs=3,
                     metavar=("PMC_DIR", "RUN_JSON", "TRACE_DIR"),
-                    help="write profiles/k_lattice_<workload>_valu.json")
+                    help="write profiles/<kernel>_<workload>_valu.json")
+    ap.add_argument("--valu-kernel", default="k_lattice",
+                    help="kernel name prefix for --summarize-valu")
+    ap.add_argument("--valu-command", default=None,
+                    help="the profiled command, for --summarize-valu of "
+                         "another run than --profile-run")
+    ap.add_argument("--valu-tag", default=None,
+                    help="workload name of that run (default --workload)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
@@ -709,17 +721,23 @@ def main():
     rng_flag = " --rng " + args.rng
     tag = args.workload + ("" if args.rng == "word" else "_planes")
     if args.summarize_valu:
-        base = "python3 <repo>/bench.py --workload %s%s --profile-run " \
-               "--steps 1 --warmup 0" % (args.workload, rng_flag)
+        base = args.valu_command or (
+            "python3 <repo>/bench.py --workload %s%s --profile-run "
+            "--steps 1 --warmup 0" % (args.workload, rng_flag))
         cmd = ["cd /tmp && export TMPDIR=/tmp",
                "rocprofv3 --kernel-trace --stats -T -d <TRACE_DIR> -o run "
                "--output-format csv -- %s" % base,
                "rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_SALU SQ_WAVES "
                "SQ_BUSY_CYCLES GRBM_GUI_ACTIVE -T -d <PMC_DIR> -o run "
                "--output-format csv -- %s > <RUN_JSON>" % base,
-               "python3 bench.py --workload %s%s --summarize-valu <PMC_DIR> "
-               "<RUN_JSON> <TRACE_DIR>" % (args.workload, rng_flag)]
-        summarize_valu(*args.summarize_valu, tag, cmd)
+               "python3 bench.py --workload %s%s --valu-kernel %s%s "
+               "--summarize-valu <PMC_DIR> <RUN_JSON> <TRACE_DIR>"
+               % (args.workload, rng_flag, args.valu_kernel,
+                  (" --valu-tag %s" % args.valu_tag) if args.valu_tag else "")]
+        if args.valu_tag:
+            tag = args.valu_tag
+        summarize_valu(*args.summarize_valu, tag, cmd,
+                       kernel=args.valu_kernel)
         return
     if args.summarize_profiles:
         base = ("python3 <repo>/bench.py --workload %s%s --no-cpu-baseline "
@@ -752,19 +770,21 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream().cuda_stream
+    rng_mode = ["word", "planes"].index(args.rng)
     if args.batched_only:
         print(json.dumps(bench_batched(binding, stream,
-                                       use_graph=not args.eager)), flush=True)
+                                       use_graph=not args.eager,
+                                       rng_mode=rng_mode)), flush=True)
         return
     if args.accuracy_only:
         print(json.dumps({
             "accuracy": bench_accuracy(binding, use_graph=not args.eager,
-                                       label="L32"),
+                                       label="L32", rng_mode=rng_mode),
             "accuracy_C2": bench_accuracy(
                 binding, use_graph=not args.eager, M=16, L=64, R=65536,
                 Ks=(50, 100, 200, 400),
                 train_LR=((32, 48, 64), (4096, 16384, 65536)),
-                label="C2")}), flush=True)
+                label="C2", rng_mode=rng_mode)}), flush=True)
         return
     law = ["nearest", "poisson", "systematic", "residual",
            "multinomial"].index(args.law)

@@ -51,6 +51,8 @@ __global__ __launch_bounds__(256) void k_lattice(const LatticeArgs a) {
 // own 1.  The |M| and M^2 sums are reduced over the workgroup before one
 // atomic each, and every nonzero window bin is added to the global
 // histogram once per workgroup.
+constexpr int kHistU = 8;
+
 __global__ __launch_bounds__(256) void k_hist(HistArgs a) {
   extern __shared__ uint32_t sh[];
   __shared__ unsigned long long red[2][4];
@@ -59,33 +61,45 @@ __global__ __launch_bounds__(256) void k_hist(HistArgs a) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   unsigned long long sam = 0ull, sm2 = 0ull;
   const int64_t R = a.Rdev ? min((int64_t)*a.Rdev, a.R) : a.R;
-  // the loop bound is uniform over the workgroup, so every wave runs whole
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < R;
-       base += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t j = base + threadIdx.x;
-    int w = -1;
-    if (j < R) {
-      const int idx = (a.E[j] + a.twoN) >> a.shift;
-      if (idx < 0 || idx >= a.nbins) {  // corrupt energy: report, never index
-        atomicAdd(&a.moments[3], 1ull);
-      } else {
-        w = idx - a.win_lo;
-        if (w < 0 || w >= a.win_n) {
-          atomicAdd(&a.hist[idx], 1u);
-          w = -1;
-        }
-      }
-      const int m = a.M[j];
-      sam += (unsigned long long)(m < 0 ? -m : m);
-      sm2 += (unsigned long long)((long long)m * m);
+  // kHistU replicas per lane and pass, their loads all issued before any is
+  // counted; the loop bound is uniform over the workgroup, so every wave
+  // runs whole
+  constexpr int U = kHistU;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x * U; base < R;
+       base += (int64_t)gridDim.x * blockDim.x * U) {
+    int32_t e[U], m[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t j = base + (int64_t)u * blockDim.x + threadIdx.x;
+      e[u] = j < R ? a.E[j] : 0;
+      m[u] = j < R ? a.M[j] : 0;
     }
-    const unsigned long long pend = __ballot(w >= 0);
-    if (pend) {
-      const int first = __builtin_ctzll(pend);
-      const int lb = __shfl(w, first, 64);
-      const unsigned long long same = __ballot(w == lb);
-      if (lane == first) atomicAdd(&sh[lb], (uint32_t)__popcll(same));
-      else if (w >= 0 && w != lb) atomicAdd(&sh[w], 1u);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      int w = -1;
+      if (base + (int64_t)u * blockDim.x + threadIdx.x < R) {
+        const int idx = (e[u] + a.twoN) >> a.shift;
+        if (idx < 0 || idx >= a.nbins) {  // corrupt energy: report, never index
+          atomicAdd(&a.moments[3], 1ull);
+        } else {
+          w = idx - a.win_lo;
+          if (w < 0 || w >= a.win_n) {
+            atomicAdd(&a.hist[idx], 1u);
+            w = -1;
+          }
+        }
+        const int mm = m[u];
+        sam += (unsigned long long)(mm < 0 ? -mm : mm);
+        sm2 += (unsigned long long)((long long)mm * mm);
+      }
+      const unsigned long long pend = __ballot(w >= 0);
+      if (pend) {
+        const int first = __builtin_ctzll(pend);
+        const int lb = __shfl(w, first, 64);
+        const unsigned long long same = __ballot(w == lb);
+        if (lane == first) atomicAdd(&sh[lb], (uint32_t)__popcll(same));
+        else if (w >= 0 && w != lb) atomicAdd(&sh[w], 1u);
+      }
     }
   }
   for (int off = 32; off > 0; off >>= 1) {
@@ -493,9 +507,10 @@ hipError_t launch_lattice(const LatticeArgs& a, int W, int RPL, bool int8,
 }
 
 hipError_t launch_hist(const HistArgs& a, hipStream_t st) {
-  // at most one workgroup per compute unit, each over 16 or more replicas
-  // per lane: the window merge and the moment atomics are per workgroup
-  int64_t blocks = (a.R + 256 * 16 - 1) / (256 * 16);
+  // at most one workgroup per compute unit, each over kHistU or more
+  // replicas per lane: the window merge and the moment atomics are per
+  // workgroup
+  int64_t blocks = (a.R + 256 * kHistU - 1) / (256 * kHistU);
   if (blocks < 1) blocks = 1;
   if (blocks > 256) blocks = 256;
   if (a.win_n < 0 || a.win_n > 16384 || a.win_lo < 0 ||
