@@ -9,6 +9,8 @@
 // -ffp-contract=off, so every table entry is reproducible bit for bit.
 #include <hip/hip_runtime.h>
 
+#include <chrono>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -159,11 +161,24 @@ void t_harvest(pa_ctx* c) {
 }
 
 // size_copied: the caller already queued the copy of scal[4] to the host.
+// Waits for the stream by polling it for up to 50 ms, then blocks: a
+// blocking wait wakes up tens of microseconds late, which a resampling step
+// (a histogram read-back, host tables, the counts) pays at every step.
+hipError_t wait_stream(hipStream_t st) {
+  const auto t0 = std::chrono::steady_clock::now();
+  for (;;) {
+    const hipError_t e = hipStreamQuery(st);
+    if (e != hipErrorNotReady) return e;
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(50))
+      return hipStreamSynchronize(st);
+  }
+}
+
 int sync(pa_ctx* c, bool size_copied = false) {
   if (c->R_pending && !size_copied)
     CK(hipMemcpyAsync(c->h_scal + 4, c->scal + 4, sizeof(unsigned long long),
                       hipMemcpyDeviceToHost, c->stream));
-  CK(hipStreamSynchronize(c->stream));
+  CK(wait_stream(c->stream));
   if (c->R_pending) {
     c->R = (int64_t)c->h_scal[4];
     c->R_pending = false;
@@ -432,7 +447,9 @@ int pa_init(const pa_config* cfg, pa_ctx** out) try {
   if (cap < cfg->R_target || cap >= (1ll << 32)) return PA_EINVAL;
   const int W = (L + 31) / 32;
   int rpl = cfg->rows_per_lane;
-  if (rpl == 0) rpl = default_rows_per_lane(L, cfg->rng_mode == PA_RNG_PLANES);
+  if (rpl == 0)
+    rpl = default_rows_per_lane(L, cfg->rng_mode == PA_RNG_PLANES,
+                                cfg->R_target);
   if (rpl < 1 || rpl > 4) return PA_EINVAL;
   if (L % rpl != 0 || L / rpl > 64) return PA_EINVAL;
   if (W >= 3 && rpl < 2) return PA_EINVAL;

@@ -1192,7 +1192,7 @@ int pa_batch_init(const pa_config* cfgs, int32_t n, void* stream,
         rpl = best;
       }
     }
-    if (rpl == 0) rpl = default_rows_per_lane(c.L, planes);
+    if (rpl == 0) rpl = default_rows_per_lane(c.L, planes, c.R_target);
     d.L = c.L;
     d.planes = planes ? 1 : 0;
     d.W = (c.L + 31) / 32;

@@ -125,11 +125,14 @@ struct BatchStep {         // per population, rewritten by the host each step
 // tuned: three rows per lane fill whole waves at L = 48 and 96 (16 and 32
 // lanes per replica), where the tuner measured them fastest; two rows above
 // L = 64 keep the registers in bounds; one row otherwise.  The plane stream
-// takes two rows at L = 64: a lane then resolves the ties of 64 draws per
-// half sweep in one pass more often than of 32 (4977 against 4844
-// attempts/ns at L = 64, R = 2^21).
-inline int default_rows_per_lane(int L, bool planes = false) {
-  if (planes && L == 64) return 2;
+// takes two rows at L = 64 for large populations: a lane then resolves the
+// ties of 64 draws per half sweep in one pass more often than of 32 (4977
+// against 4844 attempts/ns at R = 2^21); for R = 20480 the half-filled
+// last round of waves of the wider shape costs more (4296 against 3768
+// with one row).
+inline int default_rows_per_lane(int L, bool planes = false,
+                                 int64_t R = 0) {
+  if (planes && L == 64 && R >= (1 << 18)) return 2;
   return (L == 48 || L == 96) ? 3 : (L > 64 ? 2 : 1);
 }
 
