@@ -105,9 +105,9 @@ typedef struct {
                          floor or ceiling of its mean and the size is
                          within one of the target; or PA_MULTINOMIAL,
                          R_target independent draws: draw i (RESAMPLE
-                         group 2, slot i, word 0 u) lands at
-                         floor(u C / 2^32), C the total of the P_j, in the
-                         replica whose [C_{j-1}, C_j) holds it; or
+                         group 2, slot i, u = word 1 2^32 + word 0) lands
+                         at floor(u C / 2^64), C the total of the P_j, in
+                         the replica whose [C_{j-1}, C_j) holds it; or
                          PA_RESIDUAL, floor(rho) copies for certain plus
                          D = R_target - sum floor(rho) such draws over the
                          fractional parts alone (P_j = floor(frac(rho)

@@ -26,6 +26,7 @@ from .oracle import (  # noqa: F401
     energy,
     family_stats,
     lib,
+    multinomial_pick,
     philox4x32_10,
     poisson_draw,
     site_draw,

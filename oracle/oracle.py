@@ -102,6 +102,10 @@ def lib():
         L.orc_histogram.argtypes = [P, u32p]
         L.orc_set_visit_shuffle.argtypes = [P, C.c_uint64]
         L.orc_set_visit_shuffle.restype = None
+        L.orc_multinomial_pick.argtypes = [
+            C.c_uint64, np.ctypeslib.ndpointer(np.uint64, flags="C_CONTIGUOUS"),
+            C.c_int64]
+        L.orc_multinomial_pick.restype = C.c_int64
         L.orc_counts.argtypes = [C.c_int, i32p, C.c_int64, C.c_int64,
                                  C.c_double, C.c_uint64, C.c_uint32, C.c_int,
                                  C.c_int, u32p, C.POINTER(C.c_int64),
@@ -183,6 +187,13 @@ def site_draw(mode, L, seed, pop, step, half_sweep, slot, y, x):
 
 def poisson_draw(rho, r):
     return int(lib().orc_poisson_draw(float(rho), int(r)))
+
+
+def multinomial_pick(u, cum):
+    """The replica a 64-bit multinomial draw u lands in (cum: the interval
+    ends C_0 <= ... <= C_{R-1})."""
+    cum = np.ascontiguousarray(cum, np.uint64)
+    return int(lib().orc_multinomial_pick(int(u), cum, len(cum)))
 
 
 def counts(N, E, R_t, dbeta, seed, pop, step_next, law=NEAREST):

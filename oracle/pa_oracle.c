@@ -298,6 +298,19 @@ uint32_t orc_poisson_draw(double rho, uint32_t r) {
   }
 }
 
+/* The replica a multinomial draw u lands in: the first j with
+   floor(u C / 2^64) < C_j, C = cum[R - 1] the end of the last interval. */
+int64_t orc_multinomial_pick(uint64_t u, const uint64_t* cum, int64_t R) {
+  const uint64_t x = (uint64_t)(((unsigned __int128)u * cum[R - 1]) >> 64);
+  int64_t lo = 0, hi = R - 1;
+  while (lo < hi) {
+    int64_t mid = (lo + hi) / 2;
+    if (x < cum[mid]) hi = mid;
+    else lo = mid + 1;
+  }
+  return lo;
+}
+
 int orc_counts(int N, const int32_t* E, int64_t R, int64_t R_t, double dbeta,
                uint64_t seed, uint32_t pop, int step_next, int law,
                uint32_t* n_out, int64_t* R_new, double* lnQ_out) {
@@ -375,11 +388,14 @@ int orc_counts(int N, const int32_t* E, int64_t R, int64_t R_t, double dbeta,
       total += nj;
     }
   }
-  /* Multinomial resampling: R_target independent draws; draw i (its word
-     u_i: RESAMPLE group 2, slot i, word 0 at the new step) lands at
-     x_i = floor(u_i C / 2^32) on the same fixed-point axis (C the total of
-     the P_j = floor(rho) 2^32 + T) and counts for the replica whose interval
-     [C_{j-1}, C_j) holds it.
+  /* Multinomial resampling: R_target independent draws; draw i (the 64-bit
+     number u_i = w1 2^32 + w0 from words 0 and 1 of RESAMPLE group 2, slot
+     i, at the new step) lands at x_i = floor(u_i C / 2^64) on the same
+     fixed-point axis (C the total of the P_j = floor(rho) 2^32 + T) and
+     counts for the replica whose interval [C_{j-1}, C_j) holds it.  A
+     64-bit u makes every interval's probability exact to 2^-64 per draw
+     (a 32-bit one would quantise it to 2^-32, R_target 2^-32 copies over a
+     step: a replica whose expected count is below that could get none).
      Residual resampling keeps floor(rho) copies of every replica for
      certain and makes the remaining D = R_target - sum_j floor(rho_j) draws
      the same way over the fractional parts alone (P_j = T; no draws when
@@ -404,17 +420,12 @@ int orc_counts(int N, const int32_t* E, int64_t R, int64_t R_t, double dbeta,
     if (draws < 0 || C == 0) draws = 0;
     if (ORC_MUTANT == 12) draws = R;
     for (int64_t i = 0; i < draws; ++i) {
-      uint64_t u = draw_word(seed, DOMAIN_RESAMPLE, 2, (uint32_t)step_next, 0,
-                             (uint32_t)i, pop, 0);
-      uint64_t x = (uint64_t)(((unsigned __int128)u * C) >> 32);
-      /* the first j with x < C_j */
-      int64_t lo = 0, hi = R - 1;
-      while (lo < hi) {
-        int64_t mid = (lo + hi) / 2;
-        if (x < cum[mid]) hi = mid;
-        else lo = mid + 1;
-      }
-      n_out[lo] += 1;
+      uint64_t u =
+          ((uint64_t)draw_word(seed, DOMAIN_RESAMPLE, 2, (uint32_t)step_next,
+                               0, (uint32_t)i, pop, 1) << 32) |
+          draw_word(seed, DOMAIN_RESAMPLE, 2, (uint32_t)step_next, 0,
+                    (uint32_t)i, pop, 0);
+      n_out[orc_multinomial_pick(u, cum, R)] += 1;
     }
     free(cum);
     total = floors + draws;

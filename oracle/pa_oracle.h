@@ -116,6 +116,9 @@ uint32_t orc_poisson_draw(double rho, uint32_t r);
 /* The reweighting and copy-count step on energies alone (for sampled checks
    at sizes where the whole population does not fit in host memory).
    step_next is the index of the temperature being entered. */
+/* Multinomial and residual laws: the replica a 64-bit draw u lands in,
+   the first j with floor(u C / 2^64) < cum[j], C = cum[R - 1]. */
+int64_t orc_multinomial_pick(uint64_t u, const uint64_t* cum, int64_t R);
 int orc_counts(int N, const int32_t* E, int64_t R, int64_t R_t, double dbeta,
                uint64_t seed, uint32_t pop, int step_next, int law,
                uint32_t* n_out, int64_t* R_new, double* lnQ_out);

@@ -295,6 +295,7 @@ int compute_hist(pa_ctx* c) {
                     hipMemcpyDeviceToHost, c->stream));
   int rc = sync(c, true);
   if (rc) return rc;
+  if (fault_injected("energy")) c->h_scal[3] = 1;
   if (c->h_scal[3] != 0) {  // an energy outside [-2N, 2N]
     note_error("a replica's energy lies outside the histogram range");
     return PA_EDEVICE;
@@ -496,6 +497,7 @@ int pa_init(const pa_config* cfg, pa_ctx** out) try {
   bool ok = true;
   for (int b = 0; b < 2 && ok; ++b) {
     ok = ok && dmalloc(&c->spins[b], (size_t)(cap * c->stride));
+    ok = ok && !fault_injected("alloc");  // a failure after the first one
     ok = ok && dmalloc(&c->E[b], (size_t)cap * 4);
     ok = ok && dmalloc(&c->M[b], (size_t)cap * 4);
   }
@@ -717,7 +719,9 @@ int pa_resample(pa_ctx* c, double beta_next, int64_t* R_new) try {
   const int64_t ntiles = (c->R + 255) / 256;
   // the size need not reach the host now when it cannot be out of range and
   // the caller did not ask for it: the next synchronisation brings it
-  const bool deferred = !R_new && r_min >= 1 && r_max <= c->cap;
+  const bool forced_full = fault_injected("capacity");
+  const bool deferred =
+      !R_new && r_min >= 1 && r_max <= c->cap && !forced_full;
   hipEvent_t e0 = t_begin(c, PA_K_COUNTS);
   if (c->law == PA_MULTINOMIAL || c->law == PA_RESIDUAL)
     CK(launch_multi_counts(ca, draws, c->tile64, c->off64, c->cum,
@@ -735,7 +739,8 @@ int pa_resample(pa_ctx* c, double beta_next, int64_t* R_new) try {
                       hipMemcpyDeviceToHost, c->stream));
     rc = sync(c);
     if (rc) return rc;
-    const int64_t total = (int64_t)c->h_scal[4];
+    const int64_t total =
+        forced_full ? c->cap + 1 : (int64_t)c->h_scal[4];
     if (R_new) *R_new = total;
     if (total > c->cap) {
       c->n_len = 0;
@@ -759,6 +764,28 @@ int pa_resample(pa_ctx* c, double beta_next, int64_t* R_new) try {
   c->famcur ^= 1;
   c->n_len = R_old;
   c->gather_pending = true;
+  if (std::getenv("PA_LOG_JSONL")) {
+    StepLog sl{};
+    pa_obs o{};
+    observables_from_hist(c->h_hist, c->nbins, c->hshift, c->N, R_old,
+                          c->beta, (int64_t)c->h_scal[0],
+                          (int64_t)c->h_scal[1], &o);
+    sl.pop = c->pop;
+    sl.step = c->step + 1;
+    sl.R_prev = R_old;
+    sl.R = c->R_pending ? -1 : c->R;
+    sl.beta = beta_next;
+    sl.dbeta = dbeta;
+    sl.lnQ = lnQ;
+    sl.lnZ = c->lnZ + lnQ;
+    sl.overlap = overlap_from_hist(c->h_hist, c->nbins, c->hshift, c->N,
+                                   R_old, dbeta);
+    sl.e_prev = o.e;
+    sl.abs_m_prev = o.abs_m;
+    sl.C_prev = o.C;
+    sl.source = "caller";
+    log_step(sl);
+  }
   c->beta = beta_next;
   c->step += 1;
   c->sweeps_at_step = 0;

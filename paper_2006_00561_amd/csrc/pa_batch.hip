@@ -27,6 +27,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <exception>
@@ -735,6 +736,29 @@ void host_step(void* ud) {
     ++active;
     q.lnQ_last = tr.lnQ;
     q.lnZ = q.lnZ + tr.lnQ;  // Eq. Free-En, read with the logarithm
+    if (std::getenv("PA_LOG_JSONL")) {
+      static const char* kSrc[5] = {"schedule", "bisection", "network",
+                                    "fallback", "rest"};
+      pa_obs o{};
+      observables_from_hist(h, q.d.nbins, q.d.shift, q.N, R[p], q.beta,
+                            (int64_t)mom[2 * p], (int64_t)mom[2 * p + 1], &o);
+      StepLog sl{};
+      sl.pop = q.d.pop;
+      sl.step = q.step + 1;
+      sl.R_prev = R[p];
+      sl.R = -1;  // drawn on the device after this decision
+      sl.beta = beta_next;
+      sl.dbeta = beta_next - q.beta;
+      sl.lnQ = tr.lnQ;
+      sl.lnZ = q.lnZ;
+      sl.overlap = overlap_from_hist(h, q.d.nbins, q.d.shift, q.N, R[p],
+                                     beta_next - q.beta);
+      sl.e_prev = o.e;
+      sl.abs_m_prev = o.abs_m;
+      sl.C_prev = o.C;
+      sl.source = kSrc[src];
+      log_step(sl);
+    }
     q.beta = beta_next;
     q.step += 1;
     q.moved = 1;

@@ -204,6 +204,21 @@ double bisect_from_hist(const uint32_t* h, int nbins, int shift, int N,
                         int64_t R, double target, double span,
                         int* evals = nullptr, double tol = 0.0);
 
+// ---- debug and metrics hooks, read from the environment at each use
+// (pa_tables.hip):
+//   PA_FAULT=alloc|energy|capacity  force a failure from the host: pa_init's
+//     device allocations fail; the next histogram reports an energy outside
+//     its range; the next resampling exceeds the capacity
+//   PA_LOG_JSONL=<path>  append one JSON object per resampling step
+bool fault_injected(const char* what);
+struct StepLog {
+  int64_t pop, step, R_prev, R;  // R < 0: the new size is still on the device
+  double beta, dbeta, lnQ, lnZ, overlap;
+  double e_prev, abs_m_prev, C_prev;  // observables before the resampling
+  const char* source;                 // how the step was chosen
+};
+void log_step(const StepLog& s);
+
 // ---- kernel launchers (pa_kernels.hip)
 hipError_t launch_lattice(const LatticeArgs& a, int W, int RPL, bool int8,
                           bool glass, bool planes, hipStream_t st);

@@ -311,11 +311,13 @@ __global__ __launch_bounds__(256) void k_multi_draw(CountsArgs a,
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= draws) return;
   const uint64_t total = cum[a.R - 1];
-  const uint64_t u = philox10(make_uint4((kDomainResample << 28) | 2u,
-                                         a.step_next << 16, (uint32_t)i, a.pop),
-                              a.k0, a.k1).x;
-  // floor(u total / 2^32) without a 96-bit product
-  const uint64_t x = u * (total >> 32) + ((u * (total & 0xFFFFFFFFull)) >> 32);
+  const uint4 b = philox10(make_uint4((kDomainResample << 28) | 2u,
+                                      a.step_next << 16, (uint32_t)i, a.pop),
+                           a.k0, a.k1);
+  // a 64-bit uniform u from words 0 and 1, and x = floor(u total / 2^64):
+  // every replica's probability is exact to 2^-64 per draw
+  const uint64_t u = ((uint64_t)b.y << 32) | b.x;
+  const uint64_t x = __umul64hi(u, total);
   int64_t lo = 0, hi = a.R - 1;
   while (lo < hi) {
     const int64_t mid = (lo + hi) >> 1;

@@ -7,6 +7,8 @@
 // Every quantity is a plain IEEE operation in a fixed order (per energy
 // level, ascending energy); the library is compiled with -ffp-contract=off.
 #include <cmath>
+#include <cstdlib>
+#include <cstring>
 #include <cstdint>
 #include <cstdio>
 #include <exception>
@@ -35,6 +37,33 @@ void note_exception(const char* what) {
 }
 
 const char* last_error() { return g_last_error; }
+
+bool fault_injected(const char* what) {
+  const char* f = std::getenv("PA_FAULT");
+  return f && std::strcmp(f, what) == 0;
+}
+
+void log_step(const StepLog& s) {
+  const char* path = std::getenv("PA_LOG_JSONL");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  char R[32];
+  if (s.R >= 0) std::snprintf(R, sizeof R, "%lld", (long long)s.R);
+  else std::snprintf(R, sizeof R, "null");
+  std::fprintf(f,
+               "{\"pop\": %lld, \"step\": %lld, \"beta\": %.17g, "
+               "\"dbeta\": %.17g, \"R_prev\": %lld, \"R\": %s, "
+               "\"lnQ\": %.17g, \"lnZ\": %.17g, \"overlap\": %.17g, "
+               "\"culling\": %.17g, \"e_prev\": %.17g, "
+               "\"abs_m_prev\": %.17g, \"C_prev\": %.17g, "
+               "\"source\": \"%s\"}\n",
+               (long long)s.pop, (long long)s.step, s.beta, s.dbeta,
+               (long long)s.R_prev, R, s.lnQ, s.lnZ, s.overlap,
+               1.0 - s.overlap, s.e_prev, s.abs_m_prev, s.C_prev,
+               s.source ? s.source : "");
+  std::fclose(f);
+}
 
 static inline int level_energy(int N, int shift, int i) {
   return -2 * N + (i << shift);

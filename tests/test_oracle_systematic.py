@@ -141,3 +141,35 @@ def test_multinomial_draws_follow_the_weights():
     E2[0] = 4 * N // 2                   # far above the rest
     n2 = oracle.counts(N, E2, R_t, 3.0, 4, 2, 9, law=oracle.MULTINOMIAL)[0]
     assert n2[0] == 0
+
+
+def test_multinomial_draw_maps_exactly_at_interval_ends():
+    """A 64-bit draw u lands at x = floor(u C / 2^64): for each interval
+    [C_{j-1}, C_j) the smallest u that reaches it is ceil(C_{j-1} 2^64 / C)
+    (exact integers), so u one below lands in the previous nonempty
+    interval and u itself in j.  Intervals far below 2^-32 of the axis
+    (a replica with a tiny mean) are still reached by their exact share of
+    the 2^64 draws."""
+    import numpy as np
+    rng = np.random.default_rng(5)
+    for R, big in ((5, False), (40, True), (300, True)):
+        P = rng.integers(1, 1 << 40, size=R, dtype=np.uint64)
+        if big:
+            # one replica with mean 1e-6 copies among weights of order 2^32
+            P[R // 2] = 4295
+            P[:R // 2] = (rng.integers(1, 8, size=R // 2, dtype=np.uint64)
+                          << np.uint64(32))
+        cum = np.cumsum(P).astype(np.uint64)
+        C = int(cum[-1])
+        for j in range(R):
+            lo_end = 0 if j == 0 else int(cum[j - 1])
+            first_u = -(-(lo_end << 64) // C)          # ceil
+            if first_u >= 1 << 64:
+                continue
+            assert oracle.multinomial_pick(first_u, cum) == j
+            if first_u > 0:
+                assert oracle.multinomial_pick(first_u - 1, cum) < j
+            # the share of the 2^64 draws of interval j is its length
+            # over C to within one draw in 2^64 (exact integers)
+            last_u = -(-(int(cum[j]) << 64) // C)
+            assert abs((last_u - first_u) * C - (int(P[j]) << 64)) <= C
