@@ -380,7 +380,8 @@ const char* pa_last_error(void);
  * from pa_batch_run* the batch must only be destroyed.
  * ---------------------------------------------------------------------- */
 typedef struct pa_batch pa_batch;
-enum { PA_BATCH_AUTOTUNE = 1 };   /* flags of pa_batch_init */
+enum { PA_BATCH_AUTOTUNE = 1,     /* flags of pa_batch_init */
+       PA_BATCH_TUNE_SWEEP = 2 };
 
 /* Launch-shape autotuner: times theta sweeps of a synthetic population of R
    replicas of side L for 1, 2, 3 and 4 rows per lane (those valid for L)
@@ -397,7 +398,12 @@ int pa_tune_rows_per_lane(int32_t L, int32_t layout, int32_t model,
    Models: the ferromagnet and +-J glasses in either layout, and q-state
    Potts populations (PA_POTTS, PA_INT8, L = 8, 16, 32, 64 or 128: the
    four-sites-per-word pass, one replica per wave, rows_per_lane ignored);
-   the nearest-integer law only.  PA_EINVAL otherwise. */
+   the nearest-integer law only.  PA_EINVAL otherwise.
+   PA_BATCH_TUNE_SWEEP times the persistent sweep's workgroups and items
+   per queue atomic on a scratch batch of the same configurations (one
+   step to beta = 0.3, then two steps per candidate; cached per process
+   by the configurations) and keeps the fastest; results never depend on
+   the shape. */
 int pa_batch_init(const pa_config* cfgs, int32_t n, void* stream,
                   int32_t flags, pa_batch** out);
 
@@ -529,6 +535,7 @@ int pa_batch_get_families(pa_batch* b, int32_t p, uint32_t* fam, int64_t cap,
    at most 65535) and work items taken per queue atomic (default 4,
    1..1024).  Results do not depend on either. */
 int pa_batch_set_sweep_blocks(pa_batch* b, int32_t blocks, int32_t chunk);
+int pa_batch_get_sweep_blocks(pa_batch* b, int32_t* blocks, int32_t* chunk);
 
 void pa_batch_destroy(pa_batch* b);
 

@@ -155,6 +155,8 @@ def lib():
             "pa_batch_get_families": ([P, i32, P, i64, C.POINTER(i64),
                                        C.POINTER(i64)], C.c_int),
             "pa_batch_set_sweep_blocks": ([P, i32, i32], C.c_int),
+            "pa_batch_get_sweep_blocks": ([P, C.POINTER(i32), C.POINTER(i32)],
+                                          C.c_int),
             "pa_batch_destroy": ([P], None),
             "pa_batch_run_learned": ([P, P, d, d, d, i32, i32, i32,
                                       C.POINTER(i32), P], C.c_int),
@@ -462,7 +464,7 @@ def combine_observables(lnZ, obs, N):
 class Batch:
     """Many independent populations advanced together (pa_batch_*)."""
 
-    def __init__(self, pops, stream=None, autotune=False):
+    def __init__(self, pops, stream=None, autotune=False, tune_sweep=False):
         """pops: list of dicts with keys L, R (target), and optionally J,
         q (q-state Potts), seed, population_id, layout, capacity,
         rows_per_lane, rng_mode."""
@@ -490,8 +492,9 @@ class Batch:
             c.rng_mode = p.get("rng_mode", PA_RNG_WORD)
             self.L.append(p["L"])
         h = C.c_void_p()
-        _ck(lib().pa_batch_init(cfgs, self.n, stream, 1 if autotune else 0,
-                                C.byref(h)), "pa_batch_init")
+        flags = (1 if autotune else 0) | (2 if tune_sweep else 0)
+        _ck(lib().pa_batch_init(cfgs, self.n, stream, flags, C.byref(h)),
+            "pa_batch_init")
         self._h = h
 
     def close(self):
@@ -569,6 +572,14 @@ class Batch:
                                         C.byref(ln), C.byref(n0)),
             "pa_batch_get_families")
         return f[:ln.value].copy(), n0.value
+
+    def sweep_blocks(self):
+        """(workgroups, items per queue atomic) of the persistent sweep."""
+        bl, ch = C.c_int32(), C.c_int32()
+        _ck(lib().pa_batch_get_sweep_blocks(self._h, C.byref(bl),
+                                            C.byref(ch)),
+            "pa_batch_get_sweep_blocks")
+        return bl.value, ch.value
 
     def set_sweep_blocks(self, blocks, chunk=1):
         _ck(lib().pa_batch_set_sweep_blocks(self._h, blocks, chunk),

@@ -1131,6 +1131,58 @@ int tune_rows_per_lane(int32_t L, int32_t layout, int32_t model,
   return PA_EDEVICE;
 }
 
+// Launch shape of the persistent sweep (workgroups, items per queue
+// atomic) that runs the given populations fastest: a scratch batch of the
+// same configurations takes one step to beta = 0.3, then each candidate
+// times two more steps at that beta (theta = 4, no graph), timed on the
+// host around the synchronising run.  Cached per process by the list of
+// (L, R, layout, model, q, stream) of the populations.
+int tune_sweep_shape(const pa_config* cfgs, int n, void* stream,
+                     int* blocks, int* chunk) {
+  static std::map<std::vector<int64_t>, std::pair<int, int>> cache;
+  std::vector<int64_t> key;
+  for (int p = 0; p < n; ++p) {
+    const pa_config& c = cfgs[p];
+    key.insert(key.end(), {c.L, c.R_target, c.layout, c.model, c.q,
+                           c.rng_mode, c.rows_per_lane});
+  }
+  auto it = cache.find(key);
+  if (it != cache.end()) {
+    *blocks = it->second.first;
+    *chunk = it->second.second;
+    return PA_OK;
+  }
+  static const int cand[][2] = {{1024, 4}, {512, 4}, {2048, 4},
+                                {1024, 8}, {2048, 8}, {1024, 2}};
+  pa_batch* t = nullptr;
+  int rc = pa_batch_init(cfgs, n, stream, PA_BATCH_AUTOTUNE, &t);
+  if (rc) return rc;
+  std::vector<double> betas((size_t)2 * n, 0.3);
+  rc = pa_batch_run(t, 1, betas.data(), 2, 0);
+  double best = -1.0;
+  int bb = 1024, bc = 4;
+  for (const auto& c : cand) {
+    if (rc) break;
+    rc = pa_batch_set_sweep_blocks(t, c[0], c[1]);
+    if (rc) break;
+    const auto t0 = std::chrono::steady_clock::now();
+    rc = pa_batch_run(t, 2, betas.data(), 4, 0);
+    const double ms = std::chrono::duration<double, std::milli>(
+                          std::chrono::steady_clock::now() - t0).count();
+    if (!rc && (best < 0.0 || ms < best)) {
+      best = ms;
+      bb = c[0];
+      bc = c[1];
+    }
+  }
+  pa_batch_destroy(t);
+  if (rc) return rc;
+  cache[key] = {bb, bc};
+  *blocks = bb;
+  *chunk = bc;
+  return PA_OK;
+}
+
 }  // namespace pa
 
 extern "C" {
@@ -1402,6 +1454,14 @@ int pa_batch_init(const pa_config* cfgs, int32_t n, void* stream,
   if (rc == PA_OK)
     rc = hip_ok(hipStreamSynchronize(b->stream), "hipStreamSynchronize",
                 __LINE__);
+  if (rc == PA_OK && (flags & PA_BATCH_TUNE_SWEEP)) {
+    int tb = 0, tc = 0;
+    rc = tune_sweep_shape(cfgs, n, stream, &tb, &tc);
+    if (rc == PA_OK) {
+      b->sweep_blocks = tb;
+      b->sweep_chunk = tc;
+    }
+  }
   if (rc != PA_OK) {
     free_batch(b);
     delete b;
@@ -1716,6 +1776,17 @@ int pa_batch_get_families(pa_batch* b, int32_t p, uint32_t* fam, int64_t cap,
 } catch (const std::exception& e) {
   ::pa::note_exception(e.what());
   return PA_EDEVICE;
+} catch (...) {
+  ::pa::note_exception("unknown exception");
+  return PA_EDEVICE;
+}
+
+int pa_batch_get_sweep_blocks(pa_batch* b, int32_t* blocks,
+                              int32_t* chunk) try {
+  if (!b || !blocks || !chunk) return PA_EINVAL;
+  *blocks = b->sweep_blocks;
+  *chunk = b->sweep_chunk;
+  return PA_OK;
 } catch (...) {
   ::pa::note_exception("unknown exception");
   return PA_EDEVICE;

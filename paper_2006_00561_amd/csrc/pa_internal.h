@@ -142,6 +142,11 @@ int tune_rows_per_lane(int32_t L, int32_t layout, int32_t model,
                        int32_t rng_mode, int64_t R, int32_t theta,
                        void* stream, int32_t* best, float* ms);
 
+// Fastest persistent-sweep launch shape of a batch of these populations,
+// timed on a scratch batch (pa_batch.hip).
+int tune_sweep_shape(const pa_config* cfgs, int n, void* stream,
+                     int* blocks, int* chunk);
+
 // Histogram summaries fed to the temperature-step network (kFeatures per
 // population, computed on the device from the exact histogram).
 constexpr int kFeatures = 8;

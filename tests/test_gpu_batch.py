@@ -287,3 +287,24 @@ def test_batch_refuses_theta_beyond_the_counter(pa):
     b.run(np.array([0.1, 0.2]), 2)
     assert b.state(0)[2] == 2
     b.close()
+
+
+def test_sweep_shape_tuner_keeps_results(pa):
+    """PA_BATCH_TUNE_SWEEP times the persistent sweep's launch shapes on a
+    scratch batch; the tuned batch's results equal the default batch's bit
+    for bit, and the chosen shape is one of the candidates."""
+    pops = _mixed_pops()
+    betas = np.array(W.linear_schedule(1.0, 4))
+    t = pa.Batch(pops, autotune=True, tune_sweep=True)
+    d = pa.Batch(pops, autotune=True)
+    assert t.sweep_blocks() in [(1024, 4), (512, 4), (2048, 4), (1024, 8),
+                                (2048, 8), (1024, 2)]
+    assert d.sweep_blocks() == (1024, 4)
+    t.run(betas, 3)
+    d.run(betas, 3)
+    for p in range(len(pops)):
+        assert t.state(p) == d.state(p)
+        for a, b in zip(t.population(p), d.population(p)):
+            assert np.array_equal(a, b)
+    t.close()
+    d.close()
