@@ -83,6 +83,12 @@ struct pa_ctx {
   uint32_t* jbits = nullptr;
   std::vector<int8_t> J;                // host copy of the +-J couplings
   uint32_t* h_rb = nullptr;             // pinned host mirror of rb
+  // the histogram kernel writes the read-back block straight into h_rb
+  // (through d_hrb, its device address) and raises a flag there, word
+  // nb2 + 12, to the sequence number hist_seq; a device counter at word
+  // nb2 + 12 of rb finds its last workgroup
+  uint32_t* d_hrb = nullptr;
+  uint32_t hist_seq = 0;
   uint32_t* h_hist = nullptr;
   unsigned long long* h_scal = nullptr;
   uint32_t* h_tab = nullptr;            // pinned, tab_words words
@@ -145,8 +151,15 @@ void t_end(pa_ctx* c, int cls, hipEvent_t e0, int64_t bytes,
 }
 
 // After a stream synchronisation: fold finished launches into the totals.
-void t_harvest(pa_ctx* c) {
+// Without one (only_done), launches whose end event has not completed stay
+// pending.
+void t_harvest(pa_ctx* c, bool only_done = false) {
+  std::vector<TimedLaunch> keep;
   for (auto& t : c->pending) {
+    if (only_done && hipEventQuery(t.ev1) != hipSuccess) {
+      keep.push_back(t);
+      continue;
+    }
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, t.ev0, t.ev1) == hipSuccess) {
       c->acc.ms[t.cls] += ms;
@@ -157,7 +170,8 @@ void t_harvest(pa_ctx* c) {
     c->pool.push_back(t.ev0);
     c->pool.push_back(t.ev1);
   }
-  c->pending.clear();
+  (void)hipGetLastError();  // a query of an unfinished event is no error
+  c->pending.swap(keep);
 }
 
 // size_copied: the caller already queued the copy of scal[4] to the host.
@@ -171,6 +185,23 @@ hipError_t wait_stream(hipStream_t st) {
     if (e != hipErrorNotReady) return e;
     if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(50))
       return hipStreamSynchronize(st);
+  }
+}
+
+// Watches the read-back flag of the last histogram (see compute_hist):
+// true once it shows this call's sequence number.  False if the stream
+// ends, or fails, without it (the caller then copies and synchronises,
+// which also reports a failure).
+bool wait_flag(pa_ctx* c) {
+  const uint32_t* flag = c->h_rb + c->nb2 + 12;
+  for (int64_t k = 0;; ++k) {
+    if (__atomic_load_n(flag, __ATOMIC_ACQUIRE) == c->hist_seq) return true;
+    if ((k & 1023) == 1023) {
+      const hipError_t e = hipStreamQuery(c->stream);
+      if (e == hipSuccess)
+        return __atomic_load_n(flag, __ATOMIC_ACQUIRE) == c->hist_seq;
+      if (e != hipErrorNotReady) return false;
+    }
   }
 }
 
@@ -286,14 +317,46 @@ int compute_hist(pa_ctx* c) {
     h.win_lo = std::max(0, std::min(c->hist_lo - 1024, c->nbins - h.win_n));
   else
     h.win_lo = (c->nbins - h.win_n) / 2;
+  // the kernel's last workgroup sends histogram, moments and population
+  // size to the host itself and raises a flag, which the host watches:
+  // no copy of its own and no stream synchronisation per step
+  const bool mapped = c->d_hrb != nullptr;
+  if (mapped) {
+    c->hist_seq += 1;
+    h.rb = c->rb;
+    h.host_rb = c->d_hrb;
+    h.host_flag = c->d_hrb + c->nb2 + 12;
+    h.counter = c->rb + c->nb2 + 12;
+    h.seq = c->hist_seq;
+    // hist and the five scalars, rounded up to 16-byte units (nb2 is even,
+    // so this stays below the flag word nb2 + 12)
+    h.rb_words = (c->nb2 + 10 + 3) & ~3;
+  }
   hipEvent_t e0 = t_begin(c, PA_K_HIST);
   CK(launch_hist(h, c->stream));
   t_end(c, PA_K_HIST, e0, 0, 0, 8, 0);
   c->rb_zero = false;
-  // histogram, moments and population size in one copy
-  CK(hipMemcpyAsync(c->h_rb, c->rb, ((size_t)c->nb2 + 10) * 4,
-                    hipMemcpyDeviceToHost, c->stream));
-  int rc = sync(c, true);
+  int rc = PA_OK;
+  if (mapped && wait_flag(c)) {
+    if (c->R_pending) {
+      c->R = (int64_t)c->h_scal[4];
+      c->R_pending = false;
+      // the launches timed since the size was last known act on this
+      // population: their per-replica parts count with its size now, as
+      // their events may finish later
+      for (auto& t : c->pending) {
+        t.bytes += t.bytes_rep * c->R;
+        t.attempts += t.attempts_rep * c->R;
+        t.bytes_rep = t.attempts_rep = 0;
+      }
+    }
+    t_harvest(c, true);
+  } else {
+    // histogram, moments and population size in one copy
+    CK(hipMemcpyAsync(c->h_rb, c->rb, ((size_t)c->nb2 + 10) * 4,
+                      hipMemcpyDeviceToHost, c->stream));
+    rc = sync(c, true);
+  }
   if (rc) return rc;
   if (fault_injected("energy")) c->h_scal[3] = 1;
   if (c->h_scal[3] != 0) {  // an energy outside [-2N, 2N]
@@ -530,6 +593,14 @@ int pa_init(const pa_config* cfg, pa_ctx** out) try {
   c->scal = reinterpret_cast<unsigned long long*>(c->rb + c->nb2);
   c->h_hist = c->h_rb;
   c->h_scal = reinterpret_cast<unsigned long long*>(c->h_rb + c->nb2);
+  c->h_rb[c->nb2 + 12] = 0u;
+  {
+    void* d = nullptr;
+    if (hipHostGetDevicePointer(&d, c->h_rb, 0) == hipSuccess && d)
+      c->d_hrb = static_cast<uint32_t*>(d);
+    else
+      (void)hipGetLastError();  // the copy path serves instead
+  }
   if (c->model == PA_PMJ) c->J.assign(cfg->J, cfg->J + 2ll * L * L);
   // +-J couplings as row bit masks, bit set where J < 0
   std::vector<uint32_t> jb((size_t)2 * L * W, 0u);
@@ -541,6 +612,14 @@ int pa_init(const pa_config* cfg, pa_ctx** out) try {
             jb[((size_t)d * L + y) * W + x / 32] |= 1u << (x % 32);
   int rc = PA_OK;
   {
+    const hipError_t e = launch_fill_u32(c->rb + c->nb2 + 12, 4, 0u,
+                                         c->stream);
+    if (e != hipSuccess) {
+      set_last_error("launch_fill_u32", e, __LINE__);
+      rc = PA_EDEVICE;
+    }
+  }
+  if (rc == PA_OK) {
     const hipError_t e = hipMemcpyAsync(c->jbits, jb.data(), jb.size() * 4,
                                         hipMemcpyHostToDevice, c->stream);
     if (e != hipSuccess) {
@@ -635,6 +714,8 @@ int pa_resample(pa_ctx* c, double beta_next, int64_t* R_new) try {
   const int nbins = c->nbins;
   int64_t r_min = 0, r_max = 0, draws = 0;
   CountsArgs ca{};
+  bool args_tables = false;
+  ArgTables at;
   if (c->law == PA_POISSON) {
     std::vector<uint32_t> pt;
     rc = build_poisson_tables(c->h_hist, nbins, c->hshift, c->N, c->R, c->R_t,
@@ -653,12 +734,19 @@ int pa_resample(pa_ctx* c, double beta_next, int64_t* R_new) try {
                       c->h_tab, c->h_tab + nbins, &tr);
     if (rc) return rc;
     const int nl = tr.hi - tr.lo + 1;
-    // only the occupied levels go to the device: f[nl] then T[nl]
+    // only the occupied levels go to the device: f[nl] then T[nl], in the
+    // counts kernel's arguments when they fit there (nearest-integer law)
     uint32_t* hf = c->h_tab;
     uint32_t* hT = c->h_tab + nl;
     std::memmove(hT, c->h_tab + nbins, (size_t)nl * 4);
-    CK(hipMemcpyAsync(c->tab, c->h_tab, (size_t)nl * 8,
-                      hipMemcpyHostToDevice, c->stream));
+    args_tables = c->law == PA_NEAREST && nl <= kArgLevels;
+    if (args_tables) {
+      std::memcpy(at.f, hf, (size_t)nl * 4);
+      std::memcpy(at.T, hT, (size_t)nl * 4);
+    } else {
+      CK(hipMemcpyAsync(c->tab, c->h_tab, (size_t)nl * 8,
+                        hipMemcpyHostToDevice, c->stream));
+    }
     ca.f = c->tab;
     ca.T = c->tab + nl;
     if (c->law == PA_MULTINOMIAL) {
@@ -722,16 +810,32 @@ int pa_resample(pa_ctx* c, double beta_next, int64_t* R_new) try {
   const bool forced_full = fault_injected("capacity");
   const bool deferred =
       !R_new && r_min >= 1 && r_max <= c->cap && !forced_full;
+  // up to 256 tiles of the plain counts kernel, the parent map scans the
+  // tile sums itself and writes the new size: it runs now, before the size
+  // is checked (the parent map and the second family buffer are scratch
+  // until the step commits)
+  const bool scatter_scans = (c->law == PA_NEAREST || c->law == PA_POISSON) &&
+                             ntiles <= 256;
   hipEvent_t e0 = t_begin(c, PA_K_COUNTS);
   if (c->law == PA_MULTINOMIAL || c->law == PA_RESIDUAL)
     CK(launch_multi_counts(ca, draws, c->tile64, c->off64, c->cum,
                            c->stream));
   else if (c->law == PA_SYSTEMATIC)
     CK(launch_sys_counts(ca, c->tile64, c->off64, c->stream));
+  else if (args_tables)
+    CK(launch_counts_args(ca, at, c->stream));
   else
     CK(launch_counts(ca, c->stream));
-  CK(launch_scan(c->tile_sum, c->tile_off, ntiles, c->scal + 4, c->stream));
+  if (!scatter_scans)
+    CK(launch_scan(c->tile_sum, c->tile_off, ntiles, c->scal + 4, c->stream));
   t_end(c, PA_K_COUNTS, e0, 8 * c->R + 8 * ntiles, 0);
+  if (scatter_scans) {
+    e0 = t_begin(c, PA_K_SCATTER);
+    CK(launch_scatter_scan(c->n, c->tile_sum, c->R, c->cap, c->parent,
+                           c->fam[c->famcur], c->fam[c->famcur ^ 1],
+                           c->scal + 4, c->stream));
+    t_end(c, PA_K_SCATTER, e0, 4 * c->R, 0, 4, 0);
+  }
   c->rb_zero = true;
   const int64_t R_old = c->R;
   if (!deferred) {
@@ -757,10 +861,12 @@ int pa_resample(pa_ctx* c, double beta_next, int64_t* R_new) try {
   }
   // (f) parent of every new slot; the copies into the other buffer are left
   // to the next sweep, which reads every new slot from its parent
-  e0 = t_begin(c, PA_K_SCATTER);
-  CK(launch_scatter(c->n, c->tile_off, R_old, c->cap, c->parent,
-                    c->fam[c->famcur], c->fam[c->famcur ^ 1], c->stream));
-  t_end(c, PA_K_SCATTER, e0, 4 * R_old, 0, 4, 0);
+  if (!scatter_scans) {
+    e0 = t_begin(c, PA_K_SCATTER);
+    CK(launch_scatter(c->n, c->tile_off, R_old, c->cap, c->parent,
+                      c->fam[c->famcur], c->fam[c->famcur ^ 1], c->stream));
+    t_end(c, PA_K_SCATTER, e0, 4 * R_old, 0, 4, 0);
+  }
   c->famcur ^= 1;
   c->n_len = R_old;
   c->gather_pending = true;

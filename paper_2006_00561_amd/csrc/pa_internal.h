@@ -53,6 +53,17 @@ struct HistArgs {
   // bins [win_lo, win_lo + win_n) are counted in LDS first (win_n <= 16384);
   // a replica outside the window goes to the global histogram directly
   int32_t win_lo, win_n;
+  // when host_rb is set, the last workgroup to finish copies the read-back
+  // block (rb_words words, a multiple of 4, from `rb`, which holds hist and
+  // the moments) to
+  // host memory and then writes `seq` to *host_flag; `counter` (device,
+  // zero between calls) finds that workgroup
+  const uint32_t* rb;
+  uint32_t* host_rb;
+  uint32_t* host_flag;
+  uint32_t* counter;
+  uint32_t seq;
+  int32_t rb_words;
 };
 
 struct CountsArgs {
@@ -72,6 +83,14 @@ struct CountsArgs {
   int64_t R;
   int32_t twoN, shift, lvl0, nlvl;
   uint32_t k0, k1, pop, step_next;
+};
+
+// Nearest-integer tables of at most kArgLevels occupied levels, passed by
+// value in the kernel arguments: no upload of their own.
+constexpr int kArgLevels = 448;
+struct ArgTables {
+  uint32_t f[kArgLevels];
+  uint32_t T[kArgLevels];
 };
 
 struct GatherArgs {
@@ -228,6 +247,15 @@ void log_step(const StepLog& s);
 hipError_t launch_lattice(const LatticeArgs& a, int W, int RPL, bool int8,
                           bool glass, bool planes, hipStream_t st);
 hipError_t launch_hist(const HistArgs& a, hipStream_t st);
+// parent map of at most 256 tiles with its own scan of the tile sums (the
+// new size to *total)
+hipError_t launch_scatter_scan(const uint32_t* n, const uint32_t* tile_sum,
+                               int64_t R, int64_t cap, uint32_t* parent,
+                               const uint32_t* fam_src, uint32_t* fam_dst,
+                               unsigned long long* total, hipStream_t st);
+// copy counts of the nearest-integer law with the tables in the arguments
+hipError_t launch_counts_args(const CountsArgs& a, const ArgTables& t,
+                              hipStream_t st);
 hipError_t launch_potts(const LatticeArgs& a, hipStream_t st);
 hipError_t launch_sys_counts(const CountsArgs& a, uint64_t* tile64,
                              uint64_t* off64, hipStream_t st);

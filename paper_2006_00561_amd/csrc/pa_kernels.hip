@@ -122,6 +122,31 @@ __global__ __launch_bounds__(256) void k_hist(HistArgs a) {
   }
   for (int i = threadIdx.x; i < a.win_n; i += blockDim.x)
     if (sh[i]) atomicAdd(&a.hist[a.win_lo + i], sh[i]);
+  if (!a.host_rb) return;
+  // the last workgroup to finish sends the read-back block to the host:
+  // every workgroup's additions are made before its count (release), the
+  // last one reads them after (acquire) with atomic reads, writes them to
+  // host memory, and raises the flag after a system-scope fence
+  __shared__ bool last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(a.counter, 1u) == gridDim.x - 1;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  // 16-byte units (rb_words is a multiple of 4; both blocks 16-byte aligned)
+  const uint4* src = reinterpret_cast<const uint4*>(a.rb);
+  uint4* dst = reinterpret_cast<uint4*>(a.host_rb);
+  for (int i = threadIdx.x; i < a.rb_words / 4; i += blockDim.x)
+    dst[i] = src[i];
+  __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    *a.counter = 0u;
+    __threadfence_system();
+    __hip_atomic_store(a.host_flag, a.seq, __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
+  }
 }
 
 // ------------------------------------------------------------ copy counts
@@ -148,39 +173,62 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* lds,
   return wbase + incl - v;
 }
 
-__global__ __launch_bounds__(256) void k_counts(CountsArgs a) {
-  __shared__ uint32_t lds[8];
+// The copy count of replica j (nearest-integer or Poisson law) from the
+// level tables f, T.
+__device__ __forceinline__ uint32_t count_of(const CountsArgs& a, int64_t j,
+                                            const uint32_t* f,
+                                            const uint32_t* T) {
+  uint32_t nj = 0u;
+  const int l = ((a.E[j] + a.twoN) >> a.shift) - a.lvl0;
+  const uint4 b = philox10(make_uint4(kDomainResample << 28,
+                                      a.step_next << 16, (uint32_t)j, a.pop),
+                           a.k0, a.k1);
+  if (l >= 0 && l < a.nlvl) {
+    if (a.poisson) {
+      // the number of the level's thresholds <= r (they are sorted)
+      const uint32_t base = f[3 * l], off = f[3 * l + 1], len = f[3 * l + 2];
+      const uint32_t* U = f + 3 * a.nlvl + off;
+      uint32_t lo = 0, hi = len;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (U[mid] <= b.x) lo = mid + 1;
+        else hi = mid;
+      }
+      nj = base + lo;
+    } else {
+      nj = f[l] + (b.x < T[l] ? 1u : 0u);
+    }
+  }
+  return nj;
+}
+
+__device__ __forceinline__ void counts_body(const CountsArgs& a,
+                                            const uint32_t* f,
+                                            const uint32_t* T,
+                                            uint32_t* lds) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t i = j; i < a.nclear; i += (int64_t)gridDim.x * blockDim.x)
     a.clear[i] = 0u;
   uint32_t nj = 0u;
   if (j < a.R) {
-    const int l = ((a.E[j] + a.twoN) >> a.shift) - a.lvl0;
-    const uint4 b = philox10(make_uint4(kDomainResample << 28,
-                                        a.step_next << 16, (uint32_t)j, a.pop),
-                             a.k0, a.k1);
-    if (l >= 0 && l < a.nlvl) {
-      if (a.poisson) {
-        // the number of the level's thresholds <= r (they are sorted)
-        const uint32_t base = a.f[3 * l], off = a.f[3 * l + 1],
-                       len = a.f[3 * l + 2];
-        const uint32_t* U = a.f + 3 * a.nlvl + off;
-        uint32_t lo = 0, hi = len;
-        while (lo < hi) {
-          const uint32_t mid = (lo + hi) >> 1;
-          if (U[mid] <= b.x) lo = mid + 1;
-          else hi = mid;
-        }
-        nj = base + lo;
-      } else {
-        nj = a.f[l] + (b.x < a.T[l] ? 1u : 0u);
-      }
-    }
+    nj = count_of(a, j, f, T);
     a.n[j] = nj;
   }
   uint32_t total;
   (void)block_excl_scan(nj, lds, &total);
   if (threadIdx.x == 0) a.tile_sum[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(256) void k_counts(CountsArgs a) {
+  __shared__ uint32_t lds[8];
+  counts_body(a, a.f, a.T, lds);
+}
+
+// The same with the level tables in the kernel arguments.
+__global__ __launch_bounds__(256) void k_counts_args(CountsArgs a,
+                                                     ArgTables t) {
+  __shared__ uint32_t lds[8];
+  counts_body(a, t.f, t.T, lds);
 }
 
 // ------------------------------------------------- systematic resampling
@@ -385,6 +433,44 @@ __global__ __launch_bounds__(256) void k_scatter(const uint32_t* n,
     }
 }
 
+// The parent map of a population of at most kScatterTiles tiles without a
+// scan of its own: every workgroup sums the tile sums before its tile (in
+// tile order, as k_scan does), and workgroup 0 also the total, the new size.
+constexpr int kScatterTiles = 256;
+
+__global__ __launch_bounds__(256) void k_scatter_scan(
+    const uint32_t* n, const uint32_t* tile_sum, int64_t ntiles, int64_t R,
+    int64_t cap, uint32_t* parent, const uint32_t* fam_src, uint32_t* fam_dst,
+    unsigned long long* total_out) {
+  __shared__ uint32_t lds[8];
+  __shared__ uint32_t base_sh;
+  // the tile sums before this tile, one per lane, then summed
+  const uint32_t v = (threadIdx.x < blockIdx.x) ? tile_sum[threadIdx.x] : 0u;
+  uint32_t before;
+  (void)block_excl_scan(v, lds, &before);
+  if (threadIdx.x == 0) base_sh = before;
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    const uint32_t w = (threadIdx.x < ntiles) ? tile_sum[threadIdx.x] : 0u;
+    uint32_t all;
+    (void)block_excl_scan(w, lds, &all);
+    if (threadIdx.x == 0) *total_out = all;
+  }
+  __syncthreads();  // every wave has read lds before its next use
+  const uint32_t base = base_sh;
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t nj = (j < R) ? n[j] : 0u;
+  uint32_t tile_total;
+  const uint32_t ex = block_excl_scan(nj, lds, &tile_total);
+  const int64_t o = (int64_t)base + ex;
+  const uint32_t fj = (nj && fam_src) ? fam_src[j] : 0u;
+  for (uint32_t t = 0; t < nj; ++t)
+    if (o + t < cap) {
+      parent[o + t] = (uint32_t)j;
+      if (fam_dst) fam_dst[o + t] = fj;
+    }
+}
+
 // ---------------------------------------------------------------- gather
 
 // Replicas of at least 64 units (1 KB): one wave per new slot, each lane
@@ -520,6 +606,27 @@ hipError_t launch_hist(const HistArgs& a, hipStream_t st) {
     return hipErrorInvalidValue;
   const size_t shm = (size_t)a.win_n * sizeof(uint32_t);
   hipLaunchKernelGGL(k_hist, dim3((unsigned)blocks), dim3(256), shm, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_counts_args(const CountsArgs& a, const ArgTables& t,
+                              hipStream_t st) {
+  if (a.nlvl > kArgLevels || a.poisson) return hipErrorInvalidValue;
+  const int64_t blocks = (a.R + 255) / 256;
+  hipLaunchKernelGGL(k_counts_args, dim3((unsigned)blocks), dim3(256), 0, st,
+                     a, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_scan(const uint32_t* n, const uint32_t* tile_sum,
+                               int64_t R, int64_t cap, uint32_t* parent,
+                               const uint32_t* fam_src, uint32_t* fam_dst,
+                               unsigned long long* total, hipStream_t st) {
+  const int64_t blocks = (R + 255) / 256;
+  if (blocks > kScatterTiles) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_scatter_scan, dim3((unsigned)(blocks ? blocks : 1)),
+                     dim3(256), 0, st, n, tile_sum, blocks, R, cap, parent,
+                     fam_src, fam_dst, total);
   return hipGetLastError();
 }
 
