@@ -150,23 +150,33 @@ def gather_copy(binding, cfg, stream, reps=5):
 
 
 def run_anneal(binding, cfg, stream, timing=None, rows_per_lane=0,
-               families=None):
-    """One full anneal; timing: None, or the kernel classes to time;
-    families: a dict that receives the final family statistics."""
+               families=None, step_calls=False):
+    """One full anneal: the whole schedule in one pa_anneal call (the
+    device runs it with no host stop between steps), or with step_calls the
+    pa_resample / pa_sweep / pa_observables calls of every step (at the
+    capacity where no resampling waits for its size).  timing: None, or the
+    kernel classes to time; families: a dict that receives the final family
+    statistics."""
     layout = binding.PA_BITS if cfg["layout"] == "bits" else binding.PA_INT8
     L, R, theta = cfg["L"], cfg["R"], cfg["theta"]
     g = binding.Population(L, R, seed=cfg["seed"], layout=layout,
                            rows_per_lane=rows_per_lane, stream=stream,
-                           capacity=W.deferral_capacity(R), q=cfg.get("q", 0),
+                           capacity=W.deferral_capacity(R) if step_calls
+                           else 0, q=cfg.get("q", 0),
                            resampling=cfg.get("law", 0),
                            rng_mode=cfg.get("rng_mode", 0))
     if timing:
         g.set_timing(True, classes=timing)
+    sched = W.linear_schedule(cfg["beta_f"], cfg["K"])
     attempts = 0
-    for b in W.linear_schedule(cfg["beta_f"], cfg["K"]):
-        g.resample(b, wait=False)
-        g.sweep(b, theta)
-        attempts += g.observables()["R"] * L * L * theta
+    if step_calls:
+        for b in sched:
+            g.resample(b, wait=False)
+            g.sweep(b, theta)
+            attempts += g.observables()["R"] * L * L * theta
+    else:
+        obs, _ = g.anneal(sched, theta, as_dicts=False)
+        attempts = int(obs["R"].sum()) * L * L * theta
     lnZ, _ = g.free_energy()
     t = g.timing() if timing else None
     if families is not None:
@@ -725,6 +735,9 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--batched-only", action="store_true",
                     help="only the batched comparison (for profiling)")
+    ap.add_argument("--step-calls", action="store_true",
+                    help="time the step-by-step calls (pa_resample, pa_sweep, "
+                         "pa_observables per step) instead of pa_anneal")
     ap.add_argument("--no-tune-sweep", action="store_true",
                     help="batched runs at the default persistent-sweep shape "
                          "(no scratch-batch timing, e.g. under a profiler)")
@@ -833,19 +846,22 @@ def main():
         att = 0
         for _ in range(args.steps):
             att += run_anneal(binding, cfg, stream,
-                              rows_per_lane=args.rows_per_lane)[0]
+                              rows_per_lane=args.rows_per_lane,
+                              step_calls=args.step_calls)[0]
         torch.cuda.synchronize()
         print(json.dumps({"workload": args.workload, "anneals": args.steps,
                           "attempts": att}), flush=True)
         return
 
     head = time_workload(binding, cfg, stream, args.steps, args.warmup,
-                         args.rows_per_lane, verbose=True)
+                         args.rows_per_lane, verbose=True,
+                         step_calls=args.step_calls)
     dt = head["seconds"]
     # every kernel class timed, on one more anneal after the timed region
     fam = {}
     _, _, tall = run_anneal(binding, cfg, stream, timing=binding.KERNEL_CLASSES,
-                            rows_per_lane=args.rows_per_lane, families=fam)
+                            rows_per_lane=args.rows_per_lane, families=fam,
+                            step_calls=args.step_calls)
     res_k = ("hist", "counts", "scatter", "gather")
     res_ms = sum(tall[k]["ms"] for k in res_k)
     res_bytes = sum(tall[k]["bytes"] for k in res_k)
@@ -910,18 +926,23 @@ def main():
         # int8 workload and the paper's per-GPU shape in the headline's
         sec = {}
         other = 1 - cfg["rng_mode"]
-        todo = [(args.workload, other)] + [
-            (n, cfg["rng_mode"]) for n in ("C2", "CP10") if n != args.workload]
-        for name, rm in todo:
+        todo = [(args.workload, other, False)] + [
+            (n, cfg["rng_mode"], False) for n in ("C2", "CP10", "CP1")
+            if n != args.workload]
+        # the paper's theta = 1 shape also through the step-by-step calls
+        todo.append(("CP1", cfg["rng_mode"], True))
+        for name, rm, calls in todo:
             c2 = dict(W.CONFIGS[name])
             c2["name"] = name
             c2["law"] = law
             c2["rng_mode"] = rm
             reps = 2 if c2["R"] > (1 << 20) else 3
-            r = time_workload(binding, c2, stream, reps, 1, 0)
+            r = time_workload(binding, c2, stream, reps, 1, 0,
+                              step_calls=calls)
             r["roofline"]["traffic"] = measured_traffic(
                 name + ("" if rm == 0 else "_planes"))
-            key = "%s_%s" % (name, ["word", "planes"][rm])
+            key = "%s_%s%s" % (name, ["word", "planes"][rm],
+                               "_step_calls" if calls else "")
             sec[key] = {"workload": describe(name, c2), "value": r["value"],
                         "ms_per_anneal": r["seconds"] * 1e3 / reps,
                         "roofline": r["roofline"], "lnZ_final": r["lnZ"]}
@@ -970,14 +991,15 @@ def describe(name, cfg):
 
 
 def time_workload(binding, cfg, stream, steps, warmup, rows_per_lane,
-                  verbose=False):
+                  verbose=False, step_calls=False):
     """`warmup` untimed anneals, then `steps` timed ones between device
     synchronisations, with HIP events around each sweep launch on the
     library's stream.  Returns the whole-anneal rate, the wall seconds of
     the timed anneals and the sweep kernel against its roofline."""
     import torch
     for i in range(warmup):
-        run_anneal(binding, cfg, stream, rows_per_lane=rows_per_lane)
+        run_anneal(binding, cfg, stream, rows_per_lane=rows_per_lane,
+                   step_calls=step_calls)
         if verbose:
             progress("warmup anneal %d/%d" % (i + 1, warmup))
     torch.cuda.synchronize()
@@ -988,7 +1010,8 @@ def time_workload(binding, cfg, stream, steps, warmup, rows_per_lane,
     for i in range(steps):
         # events on the sweep launches only (two markers per timed launch)
         a, lnZ, t = run_anneal(binding, cfg, stream, timing=("sweep",),
-                               rows_per_lane=rows_per_lane)
+                               rows_per_lane=rows_per_lane,
+                               step_calls=step_calls)
         total_attempts += a
         if tsum is None:
             tsum = t

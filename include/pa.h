@@ -194,6 +194,28 @@ int pa_sweep(pa_ctx* c, double beta, int32_t theta);
    Otherwise it waits and checks as above. */
 int pa_resample(pa_ctx* c, double beta_next, int64_t* R_new);
 
+/* Sec. 2, the whole annealing loop for a schedule of K temperatures: for
+   k = 0..K-1 the same as pa_resample(c, betas[k], NULL), then
+   pa_sweep(c, betas[k], theta), then pa_observables into obs[k]; lnQ[k]
+   receives the ln Q of step k (obs and lnQ are caller arrays of K entries,
+   either may be NULL).  With the nearest-integer law, theta >= 1 and betas
+   non-decreasing from the current beta, the device runs the schedule with no
+   host stop between steps: the last workgroup of each step's histogram
+   builds the step's tables in the host tables' order of operations from
+   weights exp(-dbeta (E - E0)) the host evaluates ahead for every level
+   (so the tables, counts and ln Q are those of the step-by-step calls, bit
+   for bit), and every later kernel reads the population size on the
+   device (grids cover the capacity).  Other laws, heating steps or
+   theta = 0 run the step-by-step calls.  *done (may be NULL) receives the
+   number of completed steps.  A resampling whose size would exceed the
+   capacity (PA_ECAPACITY) or be 0 (PA_EEMPTY) ends the schedule at that
+   step with the context as the failed pa_resample leaves it: the
+   population after the sweeps of the step before.  PA_EINVAL for K < 0,
+   theta outside 0..32767, a non-finite or negative beta, or more than
+   65535 steps in all.  Synchronises once, at the end. */
+int pa_anneal(pa_ctx* c, const double* betas, int32_t K, int32_t theta,
+              pa_obs* obs, double* lnQ, int32_t* done);
+
 /* Sec. 2, heating protocol (the population starts close to zero
    temperature): replaces the population of a fresh ferromagnet or Potts
    context (step 0) by ground states at beta0 > 0 -- every spin of replica j

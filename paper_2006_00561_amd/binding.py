@@ -109,6 +109,7 @@ def lib():
             "pa_init": ([C.POINTER(pa_config), C.POINTER(P)], C.c_int),
             "pa_sweep": ([P, d, i32], C.c_int),
             "pa_resample": ([P, d, C.POINTER(i64)], C.c_int),
+            "pa_anneal": ([P, P, i32, i32, P, P, C.POINTER(i32)], C.c_int),
             "pa_observables": ([P, C.POINTER(pa_obs)], C.c_int),
             "pa_free_energy": ([P, C.POINTER(d), C.POINTER(d)], C.c_int),
             "pa_state": ([P, C.POINTER(i64), C.POINTER(d), C.POINTER(i32)],
@@ -275,6 +276,29 @@ class Population:
         Rn = C.c_int64()
         _ck(lib().pa_resample(self._h, beta_next, C.byref(Rn)), "pa_resample")
         return Rn.value
+
+    def anneal_rc(self, betas, theta, as_dicts=True):
+        """The whole loop over the schedule `betas` (pa_anneal): returns the
+        status code, the number of completed steps, their observables (one
+        dict per completed step, or with as_dicts=False a numpy structured
+        array with pa_obs's fields) and their ln Q."""
+        b = np.ascontiguousarray(betas, dtype=np.float64)
+        K = len(b)
+        obs = (pa_obs * max(1, K))()
+        q = np.zeros(max(1, K), dtype=np.float64)
+        done = C.c_int32()
+        rc = lib().pa_anneal(self._h, _ptr(b), K, theta,
+                             C.cast(obs, C.c_void_p), _ptr(q), C.byref(done))
+        n = done.value
+        if not as_dicts:
+            return rc, n, np.ctypeslib.as_array(obs)[:n], q[:n]
+        return rc, n, [obs[i].as_dict() for i in range(n)], list(q[:n])
+
+    def anneal(self, betas, theta, as_dicts=True):
+        """As anneal_rc, raising on failure; returns (observables, ln Q)."""
+        rc, _, obs, q = self.anneal_rc(betas, theta, as_dicts)
+        _ck(rc, "pa_anneal")
+        return obs, q
 
     def resample_rc(self, beta_next):
         Rn = C.c_int64()

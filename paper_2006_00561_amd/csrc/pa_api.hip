@@ -34,7 +34,15 @@ struct TimedLaunch {
   // parts proportional to a population size that was not yet known on the
   // host at launch time; multiplied by it when the launch is harvested
   int64_t bytes_rep, attempts_rep;
+  // launches of a schedule run on the device: the index of the population
+  // size (in that run's records) the per-replica parts count with; -1 else
+  int rseq;
 };
+
+// Weight tables of a schedule run on the device: one slot of pinned host
+// memory per queued step, reused kWSlots tables later, once the histogram
+// that read it has reported its sequence number.
+constexpr int kWSlots = 8;
 
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
@@ -108,6 +116,21 @@ struct pa_ctx {
   std::vector<TimedLaunch> pending;
   std::vector<hipEvent_t> pool;
   pa_timing acc{};
+  int rseq_tag = -1;  // rseq of the launches timed now
+  // schedule on the device (pa_anneal): a halt block and one record per
+  // step (AnnealRec) on the device, their pinned mirror, the histogram
+  // tail's scratch, and the weight-table ring (pinned, read by the kernels
+  // through d_w), followed by the word the kernels write the sequence
+  // number of the last weights they read to (h_prog; d_prog on the device)
+  unsigned char* arec = nullptr;
+  unsigned char* h_arec = nullptr;
+  int64_t arec_steps = 0;
+  double* wscr = nullptr;
+  double* h_w = nullptr;
+  double* d_w = nullptr;
+  uint32_t* h_prog = nullptr;
+  uint32_t* d_prog = nullptr;
+  uint32_t wseq = 0;  // weight tables queued so far
 };
 
 #define CK(x) PA_HIP(x)
@@ -147,7 +170,8 @@ void t_end(pa_ctx* c, int cls, hipEvent_t e0, int64_t bytes,
     attempts += attempts_rep * c->R;
     bytes_rep = attempts_rep = 0;
   }
-  c->pending.push_back({cls, e0, e1, bytes, attempts, bytes_rep, attempts_rep});
+  c->pending.push_back(
+      {cls, e0, e1, bytes, attempts, bytes_rep, attempts_rep, c->rseq_tag});
 }
 
 // After a stream synchronisation: fold finished launches into the totals.
@@ -200,6 +224,23 @@ bool wait_flag(pa_ctx* c) {
       const hipError_t e = hipStreamQuery(c->stream);
       if (e == hipSuccess)
         return __atomic_load_n(flag, __ATOMIC_ACQUIRE) == c->hist_seq;
+      if (e != hipErrorNotReady) return false;
+    }
+  }
+}
+
+// Waits until the kernels have read weight table number `seq` of a
+// schedule run on the device (its histogram writes the number to h_prog).
+// False if the stream ends, or fails, first.
+bool wait_progress(pa_ctx* c, uint32_t seq) {
+  for (int64_t k = 0;; ++k) {
+    if ((int32_t)(__atomic_load_n(c->h_prog, __ATOMIC_ACQUIRE) - seq) >= 0)
+      return true;
+    if ((k & 1023) == 1023) {
+      const hipError_t e = hipStreamQuery(c->stream);
+      if (e == hipSuccess)
+        return (int32_t)(__atomic_load_n(c->h_prog, __ATOMIC_ACQUIRE) -
+                         seq) >= 0;
       if (e != hipErrorNotReady) return false;
     }
   }
@@ -409,12 +450,14 @@ void free_all(pa_ctx* c) {
     if (c->M[b]) (void)hipFree(c->M[b]);
     if (c->fam[b]) (void)hipFree(c->fam[b]);
   }
-  void* dev[] = {c->n, c->parent, c->tile_sum, c->tile_off, c->tile64,
-                 c->off64, c->cum, c->rb, c->tab, c->jbits};
+  void* dev[] = {c->n,  c->parent, c->tile_sum, c->tile_off, c->tile64,
+                 c->off64, c->cum, c->rb, c->tab, c->jbits, c->arec, c->wscr};
   for (void* p : dev)
     if (p) (void)hipFree(p);
   if (c->h_rb) (void)hipHostFree(c->h_rb);
   if (c->h_tab) (void)hipHostFree(c->h_tab);
+  if (c->h_arec) (void)hipHostFree(c->h_arec);
+  if (c->h_w) (void)hipHostFree(c->h_w);
   for (auto& t : c->pending) {
     (void)hipEventDestroy(t.ev0);
     (void)hipEventDestroy(t.ev1);
@@ -441,6 +484,48 @@ bool dmalloc(T** p, size_t bytes) {
 }
 
 // canonical int8 [L][L] -> device layout of one replica (stride bytes)
+// Buffers of a schedule of K steps run on the device (pa_anneal); called
+// with the stream idle, so old buffers may be freed.
+int ensure_anneal(pa_ctx* c, int64_t K) {
+  const size_t nb = (size_t)c->nbins;
+  if (!c->wscr && !dmalloc(&c->wscr, 2 * nb * sizeof(double)))
+    return PA_ENOMEM;
+  if (!c->h_w) {
+    void* h = nullptr;
+    if (hipHostMalloc(&h, kWSlots * nb * sizeof(double) + 64,
+                      hipHostMallocCoherent) != hipSuccess) {
+      (void)hipGetLastError();
+      return PA_ENOMEM;
+    }
+    c->h_w = static_cast<double*>(h);
+    void* d = nullptr;
+    CK(hipHostGetDevicePointer(&d, h, 0));
+    c->d_w = static_cast<double*>(d);
+    c->h_prog = reinterpret_cast<uint32_t*>(c->h_w + kWSlots * nb);
+    c->d_prog = reinterpret_cast<uint32_t*>(c->d_w + kWSlots * nb);
+    *c->h_prog = 0u;
+    c->wseq = 0u;
+  }
+  if (K + 1 > c->arec_steps) {
+    const int64_t n = std::max<int64_t>(K + 1, 2 * c->arec_steps);
+    const size_t bytes = 64 + (size_t)n * sizeof(AnnealRec);
+    unsigned char* d = nullptr;
+    void* h = nullptr;
+    if (!dmalloc(&d, bytes)) return PA_ENOMEM;
+    if (hipHostMalloc(&h, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipFree(d);
+      return PA_ENOMEM;
+    }
+    if (c->arec) (void)hipFree(c->arec);
+    if (c->h_arec) (void)hipHostFree(c->h_arec);
+    c->arec = d;
+    c->h_arec = static_cast<unsigned char*>(h);
+    c->arec_steps = n;
+  }
+  return PA_OK;
+}
+
 void pack_replica(const pa_ctx* c, const int8_t* s, uint8_t* out) {
   std::memset(out, 0, (size_t)c->stride);
   if (c->layout == PA_INT8) {
@@ -899,6 +984,252 @@ int pa_resample(pa_ctx* c, double beta_next, int64_t* R_new) try {
   c->lnZ = c->lnZ + lnQ;  // Eq. Free-En, read with the logarithm
   c->hist_valid = false;
   return PA_OK;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
+} catch (...) {
+  ::pa::note_exception("unknown exception");
+  return PA_EDEVICE;
+}
+
+int pa_anneal(pa_ctx* c, const double* betas, int32_t K, int32_t theta,
+              pa_obs* obs, double* lnQ, int32_t* done) try {
+  if (done) *done = 0;
+  if (!c || K < 0 || (K > 0 && !betas) || theta < 0 || theta > 32767)
+    return PA_EINVAL;
+  if ((int64_t)c->step + K > 65535) return PA_EINVAL;
+  // the device runs the schedule alone for the nearest-integer law when
+  // beta never decreases and every step sweeps; else the same calls one by
+  // one
+  bool on_device = c->law == PA_NEAREST && theta > 0;
+  double prev = c->beta;
+  for (int k = 0; k < K; ++k) {
+    if (!std::isfinite(betas[k]) || !(betas[k] >= 0.0)) return PA_EINVAL;
+    if (betas[k] < prev) on_device = false;
+    prev = betas[k];
+  }
+  if (K == 0) return PA_OK;
+  if (!on_device) {
+    for (int k = 0; k < K; ++k) {
+      int rc = pa_resample(c, betas[k], nullptr);
+      if (rc == PA_OK && theta > 0) rc = pa_sweep(c, betas[k], theta);
+      pa_obs o{};
+      if (rc == PA_OK && obs) rc = pa_observables(c, &o);
+      if (rc) return rc;
+      if (obs) obs[k] = o;
+      if (lnQ) lnQ[k] = c->lnQ_last;
+      if (done) *done = k + 1;
+    }
+    return PA_OK;
+  }
+  int rc = PA_OK;
+  if (c->R_pending) {
+    rc = sync(c);
+    if (rc) return rc;
+  }
+  rc = finish_gather(c);
+  if (rc) return rc;
+  rc = ensure_anneal(c, K);
+  if (rc) return rc;
+  AnnealHalt* d_halt = reinterpret_cast<AnnealHalt*>(c->arec);
+  AnnealRec* d_rec = reinterpret_cast<AnnealRec*>(c->arec + 64);
+  CK(launch_fill_u32(reinterpret_cast<uint32_t*>(c->arec), 16, 0u,
+                     c->stream));
+  if (!c->rb_zero) CK(launch_fill_u32(c->rb, c->nb2 + 8, 0u, c->stream));
+  const int cur0 = c->cur, fam0 = c->famcur, step0 = c->step;
+  const int sw0 = c->sweeps_at_step;
+  const double beta0 = c->beta, lnZ0 = c->lnZ, lnQ0 = c->lnQ_last;
+  const int64_t R0 = c->R, cap = c->cap, nb = c->nbins;
+  const bool one_pass_scatter = c->ntiles_cap <= 256;
+  HistArgs h{};
+  h.hist = c->hist;
+  h.moments = c->scal;
+  h.twoN = 2 * c->N;
+  h.shift = c->hshift;
+  h.nbins = c->nbins;
+  h.win_n = std::min(c->nbins, 16384);
+  if (h.win_n == c->nbins)
+    h.win_lo = 0;
+  else if (c->hist_lo >= 0)
+    h.win_lo = std::max(0, std::min(c->hist_lo - 1024, c->nbins - h.win_n));
+  else
+    h.win_lo = (c->nbins - h.win_n) / 2;
+  h.counter = c->rb + c->nb2 + 12;
+  h.halt = d_halt;
+  h.acc = reinterpret_cast<SchedAcc*>(c->arec + sizeof(AnnealHalt));
+  h.Rw = c->scal + 4;
+  h.wscr = c->wscr;
+  h.R_t = c->R_t;
+  ArgWeights wk{};
+  // the sizes stay on the device until the end: grids cover the capacity
+  c->R = cap;
+  c->R_pending = true;
+  for (int k = 0; k <= K; ++k) {
+    // (a) histogram of the population at the current beta; for k < K the
+    // tables of the step to betas[k] from it (Eqs. part-Q, tau)
+    h.E = c->E[c->cur];
+    h.M = c->M[c->cur];
+    h.R = (k == 0) ? R0 : cap;
+    h.Rdev = (k == 0) ? nullptr : c->scal + 4;
+    h.rec = d_rec + k;
+    h.step = (uint32_t)k;
+    h.wtab = nullptr;
+    h.tab_f = c->tab;
+    h.tab_T = c->tab + nb;
+    h.progress = nullptr;
+    if (k < K) {
+      // table number wseq + 1 takes the slot of number wseq + 1 - kWSlots
+      const uint32_t seq = c->wseq + 1u;
+      if (seq > (uint32_t)kWSlots && !wait_progress(c, seq - kWSlots)) {
+        CK(wait_stream(c->stream));
+        note_error("a histogram of the schedule did not report its weights");
+        return PA_EDEVICE;
+      }
+      c->wseq = seq;
+      const int slot = (int)(seq % kWSlots);
+      // w = exp(-dbeta (E - E0)) for E - E0 = d 2^shift, every level the
+      // histogram may start at: the first ones in the kernel's arguments,
+      // the rest in the slot
+      const double dbeta = betas[k] - c->beta;
+      double* w = c->h_w + (size_t)slot * nb;
+      const int64_t na = std::min<int64_t>(nb, kArgWeights);
+      for (int64_t d = 0; d < na; ++d)
+        wk.w[d] = std::exp(-(dbeta * (double)(d << c->hshift)));
+      for (int64_t d = na; d < nb; ++d)
+        w[d] = std::exp(-(dbeta * (double)(d << c->hshift)));
+      h.wtab = c->d_w + (size_t)slot * nb;
+      h.progress = c->d_prog;
+      h.wseq = seq;
+    }
+    c->rseq_tag = k;
+    hipEvent_t e0 = t_begin(c, PA_K_HIST);
+    CK(launch_hist_sched(h, wk, c->stream));
+    t_end(c, PA_K_HIST, e0, 0, 0, 8, 0);
+    if (k == K) break;
+    // (b) copy counts with the device tables, the new size and the parent
+    // of every new slot; the counts clear the histogram for the next step
+    CountsArgs ca{};
+    ca.E = c->E[c->cur];
+    ca.f = c->tab;
+    ca.T = c->tab + nb;
+    ca.n = c->n;
+    ca.tile_sum = c->tile_sum;
+    ca.clear = c->rb;
+    ca.nclear = c->nb2 + 8;
+    ca.R = cap;
+    ca.Rdev = &d_rec[k].Rc;
+    ca.lvl_dev = &d_rec[k].lo;
+    ca.twoN = 2 * c->N;
+    ca.shift = c->hshift;
+    ca.k0 = (uint32_t)(c->seed & 0xFFFFFFFFu);
+    ca.k1 = (uint32_t)(c->seed >> 32);
+    ca.pop = c->pop;
+    ca.step_next = (uint32_t)(step0 + k + 1);
+    e0 = t_begin(c, PA_K_COUNTS);
+    CK(launch_counts(ca, c->stream));
+    if (!one_pass_scatter)
+      CK(launch_scan_dev(c->tile_sum, c->tile_off, c->ntiles_cap, c->scal + 4,
+                         cap, d_halt, (uint32_t)k, c->stream));
+    t_end(c, PA_K_COUNTS, e0, 8 * c->ntiles_cap, 0, 8, 0);
+    e0 = t_begin(c, PA_K_SCATTER);
+    if (one_pass_scatter)
+      CK(launch_scatter_scan_dev(c->n, c->tile_sum, cap, &d_rec[k].Rc, cap,
+                                 c->parent, c->fam[c->famcur],
+                                 c->fam[c->famcur ^ 1], c->scal + 4, d_halt,
+                                 (uint32_t)k, c->stream));
+    else
+      CK(launch_scatter_dev(c->n, c->tile_off, cap, &d_rec[k].Rc, cap,
+                            c->parent, c->fam[c->famcur],
+                            c->fam[c->famcur ^ 1], c->stream));
+    t_end(c, PA_K_SCATTER, e0, 0, 0, 4, 0);
+    c->famcur ^= 1;
+    // (c) theta sweeps at betas[k], each new slot loaded from its parent
+    c->beta = betas[k];
+    c->step = step0 + k + 1;
+    c->sweeps_at_step = 0;
+    LatticeArgs a = lattice_args(c);
+    metropolis_K(c->beta, &a.K4, &a.K8);
+    a.theta = theta;
+    a.src = c->spins[c->cur];
+    a.parent = c->parent;
+    a.spins = c->spins[c->cur ^ 1];
+    a.E = c->E[c->cur ^ 1];
+    a.M = c->M[c->cur ^ 1];
+    c->rseq_tag = k + 1;
+    rc = run_lattice(c, a, PA_K_SWEEP);
+    if (rc) return rc;
+    c->cur ^= 1;
+    c->sweeps_at_step = theta;
+  }
+  c->rseq_tag = -1;
+  const size_t rec_bytes = 64 + (size_t)(K + 1) * sizeof(AnnealRec);
+  CK(hipMemcpyAsync(c->h_arec, c->arec, rec_bytes, hipMemcpyDeviceToHost,
+                    c->stream));
+  CK(wait_stream(c->stream));
+  const AnnealHalt hh = *reinterpret_cast<const AnnealHalt*>(c->h_arec);
+  const AnnealRec* rec = reinterpret_cast<const AnnealRec*>(c->h_arec + 64);
+  const int kd = hh.code ? (int)hh.step : K;
+  // timed launches: their per-replica parts with the size they acted on
+  for (auto& t : c->pending) {
+    if (t.rseq < 0) continue;
+    const int64_t Rs = (int64_t)rec[t.rseq].R;
+    t.bytes += t.bytes_rep * Rs;
+    t.attempts += t.attempts_rep * Rs;
+    t.bytes_rep = t.attempts_rep = 0;
+    t.rseq = -1;
+  }
+  // ln Q of every completed step from its sum S, in the host tables' order
+  // of operations (Eq. part-Q), and the observables after its sweeps
+  double lnZ = lnZ0, lq = lnQ0, bprev = beta0;
+  for (int k = 0; k < kd; ++k) {
+    const double dbeta = betas[k] - bprev;
+    const int Emin = -2 * c->N + (rec[k].lo << c->hshift);
+    const double q = (-(dbeta * (double)Emin)) +
+                     std::log(rec[k].S / (double)(int64_t)rec[k].R);
+    lnZ = lnZ + q;  // Eq. Free-En, read with the logarithm
+    lq = q;
+    if (lnQ) lnQ[k] = q;
+    if (obs) {
+      const AnnealRec& r = rec[k + 1];
+      observables_from_sums((int64_t)r.R, betas[k], c->N, r.sumE, r.sumE2,
+                            (int64_t)r.sumAbsM, (int64_t)r.sumM2,
+                            -2 * c->N + (r.lo << c->hshift),
+                            -2 * c->N + ((r.lo + r.nl - 1) << c->hshift),
+                            &obs[k]);
+    }
+    bprev = betas[k];
+  }
+  c->lnZ = lnZ;
+  c->lnQ_last = lq;
+  c->R_pending = false;
+  c->gather_pending = false;
+  c->hist_valid = false;
+  c->rb_zero = false;
+  if (kd == K) {
+    c->R = (int64_t)rec[K].R;
+    c->n_len = (int64_t)rec[K - 1].R;
+    c->hist_lo = rec[K].lo;
+  } else {
+    // as after the failed pa_resample of step kd: the population after the
+    // sweeps of step kd - 1, in the buffers it was left in
+    c->cur = cur0 ^ (kd & 1);
+    c->famcur = fam0 ^ (kd & 1);
+    c->step = step0 + kd;
+    c->beta = kd ? betas[kd - 1] : beta0;
+    c->sweeps_at_step = kd ? theta : sw0;
+    c->R = (int64_t)rec[kd].R;
+    c->n_len = 0;
+    rc = hh.code == kHaltCapacity ? PA_ECAPACITY
+         : hh.code == kHaltEmpty  ? PA_EEMPTY
+                                  : PA_EDEVICE;
+    if (rc == PA_EDEVICE)
+      note_error("a replica's energy lies outside the histogram range");
+  }
+  t_harvest(c);
+  if (done) *done = kd;
+  return rc;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;
 } catch (const std::exception& e) {

@@ -42,6 +42,43 @@ struct LatticeArgs {
   uint64_t Tp[4];
 };
 
+// One record per temperature step of a schedule run on the device
+// (pa_anneal), written by the last workgroup of the step's histogram: the
+// population it counted, its exact sums and the reweighting sum of the
+// step's tables (64 bytes).
+struct AnnealRec {
+  unsigned long long R;   // replicas counted
+  unsigned long long Rc;  // replicas the copy counts read: R, or 0 once the
+                          // schedule has stopped
+  unsigned long long sumAbsM, sumM2;
+  long long sumE, sumE2;
+  double S;               // sum of h w over the occupied levels, in order
+  int32_t lo, nl;         // first occupied level, level count (0: none)
+};
+static_assert(sizeof(AnnealRec) == 64, "record layout");
+
+// The first step of such a schedule that failed, 0 while none has.
+enum { kHaltCapacity = 1, kHaltEmpty = 2, kHaltEnergy = 3 };
+struct AnnealHalt {
+  uint32_t code, step;      // step: index of the failed resampling
+  unsigned long long total; // the new size that failed (capacity, empty)
+};
+
+// Occupied range and exact energy sums of a step's histogram, added up by
+// every workgroup of it (zero between steps): lo_rev = max of nbins - bin,
+// hi1 = max of bin + 1.
+struct SchedAcc {
+  uint32_t lo_rev, hi1;
+  long long sE, sE2;
+};
+
+// The first kArgWeights weights exp(-dbeta d 2^shift) of a step, in the
+// histogram kernel's arguments (no read from host memory for them).
+constexpr int kArgWeights = 440;
+struct ArgWeights {
+  double w[kArgWeights];
+};
+
 struct HistArgs {
   const int32_t* E;
   const int32_t* M;
@@ -64,6 +101,27 @@ struct HistArgs {
   uint32_t* counter;
   uint32_t seq;
   int32_t rb_words;
+  // schedule on the device (rec set): the last workgroup writes *rec and,
+  // with wtab set, the nearest-integer tables of the step (f to tab_f, T to
+  // tab_T, levels from rec->lo) from the weights wtab[d] = exp(-dbeta d
+  // 2^shift) the host computed (d >= kArgWeights read there, the others
+  // from the arguments), through the scratch wscr (nbins doubles);
+  // a bad energy stops the schedule (*halt, and *Rw = 0 so that every later
+  // kernel of it finds no replicas)
+  AnnealRec* rec;
+  AnnealHalt* halt;
+  unsigned long long* Rw;
+  const double* wtab;
+  double* wscr;
+  uint32_t* tab_f;
+  uint32_t* tab_T;
+  int64_t R_t;
+  uint32_t step;
+  // with weights: their sequence number, written to *progress (host
+  // memory) once they are read
+  uint32_t* progress;
+  uint32_t wseq;
+  SchedAcc* acc;
 };
 
 struct CountsArgs {
@@ -83,6 +141,10 @@ struct CountsArgs {
   int64_t R;
   int32_t twoN, shift, lvl0, nlvl;
   uint32_t k0, k1, pop, step_next;
+  // schedule on the device: the replica count min(*Rdev, R) and the level
+  // range (lvl_dev[0], lvl_dev[1]) come from the step's record
+  const unsigned long long* Rdev;
+  const int32_t* lvl_dev;
 };
 
 // Nearest-integer tables of at most kArgLevels occupied levels, passed by
@@ -224,6 +286,9 @@ double overlap_from_hist(const uint32_t* h, int nbins, int shift, int N,
 void observables_from_hist(const uint32_t* h, int nbins, int shift, int N,
                            int64_t R, double beta, int64_t sumAbsM,
                            int64_t sumM2, pa_obs* o);
+void observables_from_sums(int64_t R, double beta, int N, int64_t sumE,
+                           int64_t sumE2, int64_t sumAbsM, int64_t sumM2,
+                           int32_t Emin, int32_t Emax, pa_obs* o);
 double bisect_from_hist(const uint32_t* h, int nbins, int shift, int N,
                         int64_t R, double target, double span,
                         int* evals = nullptr, double tol = 0.0);
@@ -247,6 +312,10 @@ void log_step(const StepLog& s);
 hipError_t launch_lattice(const LatticeArgs& a, int W, int RPL, bool int8,
                           bool glass, bool planes, hipStream_t st);
 hipError_t launch_hist(const HistArgs& a, hipStream_t st);
+// the histogram of a step of a schedule on the device (a.rec set), the
+// first weights in the arguments (a.wtab holds them all)
+hipError_t launch_hist_sched(const HistArgs& a, const ArgWeights& w,
+                             hipStream_t st);
 // parent map of at most 256 tiles with its own scan of the tile sums (the
 // new size to *total)
 hipError_t launch_scatter_scan(const uint32_t* n, const uint32_t* tile_sum,
@@ -271,6 +340,25 @@ hipError_t launch_scatter(const uint32_t* n, const uint32_t* tile_off,
                           const uint32_t* fam_src, uint32_t* fam_dst,
                           hipStream_t st);
 hipError_t launch_gather(const GatherArgs& a, hipStream_t st);
+// the same steps of a schedule on the device: the old size is read from
+// *Rdev (R and cap bound the grid), a new size of 0 or above cap stops the
+// schedule (*halt, and the size written is 0)
+hipError_t launch_scatter_scan_dev(const uint32_t* n, const uint32_t* tile_sum,
+                                   int64_t R, const unsigned long long* Rdev,
+                                   int64_t cap, uint32_t* parent,
+                                   const uint32_t* fam_src, uint32_t* fam_dst,
+                                   unsigned long long* total,
+                                   AnnealHalt* halt, uint32_t step,
+                                   hipStream_t st);
+hipError_t launch_scan_dev(const uint32_t* tile_sum, uint32_t* tile_off,
+                           int64_t ntiles, unsigned long long* total,
+                           int64_t cap, AnnealHalt* halt, uint32_t step,
+                           hipStream_t st);
+hipError_t launch_scatter_dev(const uint32_t* n, const uint32_t* tile_off,
+                              int64_t R, const unsigned long long* Rdev,
+                              int64_t cap, uint32_t* parent,
+                              const uint32_t* fam_src, uint32_t* fam_dst,
+                              hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
 hipError_t launch_iota_u32(uint32_t* p, int64_t n, hipStream_t st);
 

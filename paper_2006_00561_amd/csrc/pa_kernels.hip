@@ -28,6 +28,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "pa_device.h"
 #include "pa_internal.h"
 #include "pa_lattice.h"
@@ -53,13 +55,131 @@ __global__ __launch_bounds__(256) void k_lattice(const LatticeArgs a) {
 // histogram once per workgroup.
 constexpr int kHistU = 8;
 
-__global__ __launch_bounds__(256) void k_hist(HistArgs a) {
-  extern __shared__ uint32_t sh[];
+// Lane q's value of v, the same in every lane (q uniform).
+__device__ __forceinline__ double readlane_f64(double v, int q) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, q);
+  const uint32_t hi =
+      (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), q);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Levels per piece of the term array of the table tail in LDS.
+constexpr int kTermPiece = 4096;
+
+// The end of a step's histogram in a schedule run on the device, in its last
+// workgroup (the histogram, moments and sums are final): the occupied range
+// and exact energy sums the workgroups added up, then, with weights given,
+// the nearest-integer tables of Eqs. part-Q/tau in the operation order of
+// the host's: terms h w per level, their sum S in ascending level order, and
+// per level rho = R_target w / S, f = floor(rho), T = floor(frac(rho)
+// 2^32).  The terms of up to kTermPiece levels at a time go to LDS (every
+// load of a piece in flight at once); one wave then adds them in level order
+// (empty levels and the padding add +0, which leaves every partial sum as it
+// is, as the host's skipping them does).  The population counted is R.
+// Finally the weights' sequence number goes to *progress, in host memory:
+// the host may then reuse their slot.
+__device__ void anneal_tail(const HistArgs& a, const double* wk, int64_t R,
+                            double* tl) {
+  __shared__ double s_S;
+  const int tid = threadIdx.x, wid = tid >> 6;
+  const SchedAcc acc = *a.acc;
+  const int lo = a.nbins - (int)acc.lo_rev, hi = (int)acc.hi1 - 1;
+  // a bad energy stops the schedule here: no tables, no replicas from now on
+  const bool bad = a.moments[3] != 0ull;
+  const int nl = (hi >= lo && !bad) ? hi - lo + 1 : 0;
+  double S = 0.0;
+  if (a.wtab && nl > 0) {
+    constexpr int PT = kTermPiece / 256;  // levels per thread and piece
+    double sum = 0.0;
+    for (int p0 = 0; p0 < nl; p0 += kTermPiece) {
+      const int n = min(kTermPiece, nl - p0);
+      const int npad = (n + 31) & ~31;
+      uint32_t h[PT];
+      double w[PT];
+#pragma unroll
+      for (int c = 0; c < PT; ++c) {
+        const int l = p0 + c * 256 + tid;
+        const bool in = c * 256 + tid < n;
+        h[c] = in ? a.hist[lo + l] : 0u;
+        w[c] = in ? (l < kArgWeights ? wk[l] : a.wtab[l]) : 0.0;
+      }
+#pragma unroll
+      for (int c = 0; c < PT; ++c) {
+        const int i = c * 256 + tid;
+        if (i < npad) tl[i] = (double)h[c] * w[c];
+        if (i < n) a.wscr[p0 + i] = w[c];
+      }
+      __syncthreads();
+      if (wid == 0) {
+        for (int i0 = 0; i0 < npad; i0 += 32) {
+          double v[32];
+#pragma unroll
+          for (int u = 0; u < 32; ++u) v[u] = tl[i0 + u];
+#pragma unroll
+          for (int u = 0; u < 32; ++u) sum = sum + v[u];
+        }
+      }
+      __syncthreads();
+    }
+    if (tid == 0) s_S = sum;
+    __syncthreads();
+    S = s_S;
+    const double Rt = (double)a.R_t;
+    for (int l = tid; l < nl; l += blockDim.x) {
+      uint32_t f = 0u, T = 0u;
+      if (a.hist[lo + l]) {
+        const double rho = (Rt * a.wscr[l]) / S;
+        const double fl = floor(rho);
+        f = (uint32_t)fl;
+        T = (uint32_t)(uint64_t)floor(ldexp(rho - fl, 32));
+      }
+      a.tab_f[l] = f;
+      a.tab_T[l] = T;
+    }
+  }
+  if (tid == 0) {
+    AnnealRec r;
+    r.R = (unsigned long long)R;
+    r.Rc = bad ? 0ull : (unsigned long long)R;
+    r.sumAbsM = a.moments[0];
+    r.sumM2 = a.moments[1];
+    r.sumE = acc.sE;
+    r.sumE2 = acc.sE2;
+    r.S = S;
+    r.lo = lo;
+    r.nl = nl;
+    *a.rec = r;
+    *a.acc = SchedAcc{0u, 0u, 0ll, 0ll};
+    if (bad) {
+      if (a.halt->code == 0u) {
+        a.halt->code = kHaltEnergy;
+        a.halt->step = a.step;
+        a.halt->total = 0ull;
+      }
+      *a.Rw = 0ull;
+    }
+    if (a.progress)
+      __hip_atomic_store(a.progress, a.wseq, __ATOMIC_RELEASE,
+                         __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
+// The histogram pass; SCHED: a step of a schedule on the device, which also
+// adds up the occupied range and the exact energy sums and ends in
+// anneal_tail (weights wk in the arguments).
+template <bool SCHED>
+__device__ __forceinline__ void hist_body(const HistArgs& a, const double* wk) {
+  extern __shared__ __attribute__((aligned(16))) uint32_t sh[];
   __shared__ unsigned long long red[2][4];
+  __shared__ long long red_e[2][4];
+  __shared__ uint32_t red_r[2][4];
   for (int i = threadIdx.x; i < a.win_n; i += blockDim.x) sh[i] = 0u;
   __syncthreads();
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   unsigned long long sam = 0ull, sm2 = 0ull;
+  long long se = 0, se2 = 0;
+  uint32_t lo_rev = 0u, hi1 = 0u;
   const int64_t R = a.Rdev ? min((int64_t)*a.Rdev, a.R) : a.R;
   // kHistU replicas per lane and pass, their loads all issued before any is
   // counted; the loop bound is uniform over the workgroup, so every wave
@@ -87,6 +207,13 @@ __global__ __launch_bounds__(256) void k_hist(HistArgs a) {
             atomicAdd(&a.hist[idx], 1u);
             w = -1;
           }
+          if (SCHED) {
+            const long long ee = e[u];
+            se += ee;
+            se2 += ee * ee;
+            lo_rev = max(lo_rev, (uint32_t)(a.nbins - idx));
+            hi1 = max(hi1, (uint32_t)(idx + 1));
+          }
         }
         const int mm = m[u];
         sam += (unsigned long long)(mm < 0 ? -mm : mm);
@@ -105,28 +232,74 @@ __global__ __launch_bounds__(256) void k_hist(HistArgs a) {
   for (int off = 32; off > 0; off >>= 1) {
     sam += __shfl_down(sam, off, 64);
     sm2 += __shfl_down(sm2, off, 64);
+    if (SCHED) {
+      se += __shfl_down(se, off, 64);
+      se2 += __shfl_down(se2, off, 64);
+      lo_rev = max(lo_rev, (uint32_t)__shfl_down((int)lo_rev, off, 64));
+      hi1 = max(hi1, (uint32_t)__shfl_down((int)hi1, off, 64));
+    }
   }
   if (lane == 0) {
     red[0][wid] = sam;
     red[1][wid] = sm2;
+    if (SCHED) {
+      red_e[0][wid] = se;
+      red_e[1][wid] = se2;
+      red_r[0][wid] = lo_rev;
+      red_r[1][wid] = hi1;
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     unsigned long long s0 = 0ull, s1 = 0ull;
+    long long t0 = 0, t1 = 0;
+    uint32_t r0 = 0u, r1 = 0u;
     for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
       s0 += red[0][i];
       s1 += red[1][i];
+      if (SCHED) {
+        t0 += red_e[0][i];
+        t1 += red_e[1][i];
+        r0 = max(r0, red_r[0][i]);
+        r1 = max(r1, red_r[1][i]);
+      }
     }
     atomicAdd(&a.moments[0], s0);
     atomicAdd(&a.moments[1], s1);
+    if (SCHED && r1) {
+      atomicAdd(reinterpret_cast<unsigned long long*>(&a.acc->sE),
+                (unsigned long long)t0);
+      atomicAdd(reinterpret_cast<unsigned long long*>(&a.acc->sE2),
+                (unsigned long long)t1);
+      atomicMax(&a.acc->lo_rev, r0);
+      atomicMax(&a.acc->hi1, r1);
+    }
   }
-  for (int i = threadIdx.x; i < a.win_n; i += blockDim.x)
+  // the window's nonzero bins to the global histogram (a step of a schedule
+  // knows its workgroup's occupied range: only that part)
+  int m0 = 0, m1 = a.win_n;
+  if (SCHED) {
+    __shared__ int s_m[2];
+    if (threadIdx.x == 0) {
+      uint32_t r0 = 0u, r1 = 0u;
+      for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+        r0 = max(r0, red_r[0][i]);
+        r1 = max(r1, red_r[1][i]);
+      }
+      s_m[0] = max(0, (a.nbins - (int)r0) - a.win_lo);
+      s_m[1] = min(a.win_n, (int)r1 - a.win_lo);
+    }
+    __syncthreads();
+    m0 = s_m[0];
+    m1 = s_m[1];
+  }
+  for (int i = m0 + threadIdx.x; i < m1; i += blockDim.x)
     if (sh[i]) atomicAdd(&a.hist[a.win_lo + i], sh[i]);
-  if (!a.host_rb) return;
-  // the last workgroup to finish sends the read-back block to the host:
-  // every workgroup's additions are made before its count (release), the
-  // last one reads them after (acquire) with atomic reads, writes them to
-  // host memory, and raises the flag after a system-scope fence
+  if (!SCHED && !a.host_rb) return;
+  // the last workgroup to finish sends the read-back block to the host, or
+  // ends the step of a schedule on the device: every workgroup's additions
+  // are made before its count (release), the last one reads them after
+  // (acquire)
   __shared__ bool last;
   __threadfence();
   __syncthreads();
@@ -134,6 +307,13 @@ __global__ __launch_bounds__(256) void k_hist(HistArgs a) {
   __syncthreads();
   if (!last) return;
   __threadfence();
+  if (SCHED) {
+    __syncthreads();  // every wave is past the window before it is reused
+    anneal_tail(a, wk, R, reinterpret_cast<double*>(sh));
+    if (threadIdx.x == 0) *a.counter = 0u;
+    return;
+  }
+  // to host memory, then the flag after a system-scope fence
   // 16-byte units (rb_words is a multiple of 4; both blocks 16-byte aligned)
   const uint4* src = reinterpret_cast<const uint4*>(a.rb);
   uint4* dst = reinterpret_cast<uint4*>(a.host_rb);
@@ -147,6 +327,18 @@ __global__ __launch_bounds__(256) void k_hist(HistArgs a) {
     __hip_atomic_store(a.host_flag, a.seq, __ATOMIC_RELEASE,
                        __HIP_MEMORY_SCOPE_SYSTEM);
   }
+}
+
+__global__ __launch_bounds__(256) void k_hist(HistArgs a) {
+  hist_body<false>(a, nullptr);
+}
+
+static_assert(sizeof(HistArgs) + sizeof(ArgWeights) <= 4096,
+              "kernel arguments of one launch stay within 4 KB");
+
+__global__ __launch_bounds__(256) void k_hist_sched(HistArgs a,
+                                                    ArgWeights w) {
+  hist_body<true>(a, w.w);
 }
 
 // ------------------------------------------------------------ copy counts
@@ -202,10 +394,16 @@ __device__ __forceinline__ uint32_t count_of(const CountsArgs& a, int64_t j,
   return nj;
 }
 
-__device__ __forceinline__ void counts_body(const CountsArgs& a,
+__device__ __forceinline__ void counts_body(const CountsArgs& a0,
                                             const uint32_t* f,
                                             const uint32_t* T,
                                             uint32_t* lds) {
+  CountsArgs a = a0;
+  if (a0.Rdev) a.R = min((int64_t)*a0.Rdev, a0.R);
+  if (a0.lvl_dev) {
+    a.lvl0 = a0.lvl_dev[0];
+    a.nlvl = a0.lvl_dev[1];
+  }
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t i = j; i < a.nclear; i += (int64_t)gridDim.x * blockDim.x)
     a.clear[i] = 0u;
@@ -385,10 +583,27 @@ __global__ __launch_bounds__(256) void k_count_tiles(CountsArgs a) {
 }
 
 // Single workgroup of 1024 threads: exclusive scan of ntiles tile sums.
+// New size of a resampling in a schedule on the device: 0 and sizes above
+// the capacity stop the schedule (the first such step is recorded) and
+// leave no replicas for the kernels after it.
+__device__ __forceinline__ unsigned long long checked_total(
+    unsigned long long t, int64_t cap, AnnealHalt* halt, uint32_t step) {
+  if (!halt || (t != 0ull && t <= (unsigned long long)cap)) return t;
+  if (halt->code == 0u) {
+    halt->code = t ? kHaltCapacity : kHaltEmpty;
+    halt->step = step;
+    halt->total = t;
+  }
+  return 0ull;
+}
+
 __global__ __launch_bounds__(1024) void k_scan(const uint32_t* tile_sum,
                                                uint32_t* tile_off,
                                                int64_t ntiles,
-                                               unsigned long long* total) {
+                                               unsigned long long* total,
+                                               int64_t cap,
+                                               AnnealHalt* halt,
+                                               uint32_t step) {
   __shared__ unsigned long long part[1024];
   const int tid = threadIdx.x;
   const int64_t per = (ntiles + 1023) / 1024;
@@ -410,16 +625,15 @@ __global__ __launch_bounds__(1024) void k_scan(const uint32_t* tile_sum,
     tile_off[i] = (uint32_t)run;
     run += tile_sum[i];
   }
-  if (tid == 1023) *total = part[1023];
+  if (tid == 1023) *total = checked_total(part[1023], cap, halt, step);
 }
 
-__global__ __launch_bounds__(256) void k_scatter(const uint32_t* n,
-                                                 const uint32_t* tile_off,
-                                                 int64_t R, int64_t cap,
-                                                 uint32_t* parent,
-                                                 const uint32_t* fam_src,
-                                                 uint32_t* fam_dst) {
+__global__ __launch_bounds__(256) void k_scatter(
+    const uint32_t* n, const uint32_t* tile_off, int64_t R, int64_t cap,
+    uint32_t* parent, const uint32_t* fam_src, uint32_t* fam_dst,
+    const unsigned long long* Rdev) {
   __shared__ uint32_t lds[8];
+  if (Rdev) R = min((int64_t)*Rdev, R);
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t nj = (j < R) ? n[j] : 0u;
   uint32_t total;
@@ -441,9 +655,11 @@ constexpr int kScatterTiles = 256;
 __global__ __launch_bounds__(256) void k_scatter_scan(
     const uint32_t* n, const uint32_t* tile_sum, int64_t ntiles, int64_t R,
     int64_t cap, uint32_t* parent, const uint32_t* fam_src, uint32_t* fam_dst,
-    unsigned long long* total_out) {
+    unsigned long long* total_out, const unsigned long long* Rdev,
+    AnnealHalt* halt, uint32_t step) {
   __shared__ uint32_t lds[8];
   __shared__ uint32_t base_sh;
+  if (Rdev) R = min((int64_t)*Rdev, R);
   // the tile sums before this tile, one per lane, then summed
   const uint32_t v = (threadIdx.x < blockIdx.x) ? tile_sum[threadIdx.x] : 0u;
   uint32_t before;
@@ -454,7 +670,7 @@ __global__ __launch_bounds__(256) void k_scatter_scan(
     const uint32_t w = (threadIdx.x < ntiles) ? tile_sum[threadIdx.x] : 0u;
     uint32_t all;
     (void)block_excl_scan(w, lds, &all);
-    if (threadIdx.x == 0) *total_out = all;
+    if (threadIdx.x == 0) *total_out = checked_total(all, cap, halt, step);
   }
   __syncthreads();  // every wave has read lds before its next use
   const uint32_t base = base_sh;
@@ -609,6 +825,22 @@ hipError_t launch_hist(const HistArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+hipError_t launch_hist_sched(const HistArgs& a, const ArgWeights& w,
+                             hipStream_t st) {
+  int64_t blocks = (a.R + 256 * kHistU - 1) / (256 * kHistU);
+  if (blocks < 1) blocks = 1;
+  if (blocks > 256) blocks = 256;
+  if (a.win_n < 0 || a.win_n > 16384 || a.win_lo < 0 ||
+      a.win_lo + a.win_n > a.nbins || !a.rec || !a.acc || !a.halt || !a.Rw)
+    return hipErrorInvalidValue;
+  // LDS: the window, then the table tail's terms (kTermPiece doubles)
+  const size_t shm = std::max((size_t)a.win_n * sizeof(uint32_t),
+                              (size_t)kTermPiece * sizeof(double));
+  hipLaunchKernelGGL(k_hist_sched, dim3((unsigned)blocks), dim3(256), shm, st,
+                     a, w);
+  return hipGetLastError();
+}
+
 hipError_t launch_counts_args(const CountsArgs& a, const ArgTables& t,
                               hipStream_t st) {
   if (a.nlvl > kArgLevels || a.poisson) return hipErrorInvalidValue;
@@ -626,7 +858,47 @@ hipError_t launch_scatter_scan(const uint32_t* n, const uint32_t* tile_sum,
   if (blocks > kScatterTiles) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_scatter_scan, dim3((unsigned)(blocks ? blocks : 1)),
                      dim3(256), 0, st, n, tile_sum, blocks, R, cap, parent,
-                     fam_src, fam_dst, total);
+                     fam_src, fam_dst, total,
+                     (const unsigned long long*)nullptr, (AnnealHalt*)nullptr,
+                     0u);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_scan_dev(const uint32_t* n, const uint32_t* tile_sum,
+                                   int64_t R, const unsigned long long* Rdev,
+                                   int64_t cap, uint32_t* parent,
+                                   const uint32_t* fam_src, uint32_t* fam_dst,
+                                   unsigned long long* total,
+                                   AnnealHalt* halt, uint32_t step,
+                                   hipStream_t st) {
+  const int64_t blocks = (R + 255) / 256;
+  if (blocks > kScatterTiles || !Rdev || !halt) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_scatter_scan, dim3((unsigned)(blocks ? blocks : 1)),
+                     dim3(256), 0, st, n, tile_sum, blocks, R, cap, parent,
+                     fam_src, fam_dst, total, Rdev, halt, step);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_dev(const uint32_t* tile_sum, uint32_t* tile_off,
+                           int64_t ntiles, unsigned long long* total,
+                           int64_t cap, AnnealHalt* halt, uint32_t step,
+                           hipStream_t st) {
+  if (!halt) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, tile_sum, tile_off,
+                     ntiles, total, cap, halt, step);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_dev(const uint32_t* n, const uint32_t* tile_off,
+                              int64_t R, const unsigned long long* Rdev,
+                              int64_t cap, uint32_t* parent,
+                              const uint32_t* fam_src, uint32_t* fam_dst,
+                              hipStream_t st) {
+  const int64_t blocks = (R + 255) / 256;
+  if (!Rdev) return hipErrorInvalidValue;
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter, dim3((unsigned)blocks), dim3(256), 0, st, n,
+                     tile_off, R, cap, parent, fam_src, fam_dst, Rdev);
   return hipGetLastError();
 }
 
@@ -670,7 +942,7 @@ hipError_t launch_scan(const uint32_t* tile_sum, uint32_t* tile_off,
                        int64_t ntiles, unsigned long long* total,
                        hipStream_t st) {
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, tile_sum, tile_off,
-                     ntiles, total);
+                     ntiles, total, (int64_t)0, (AnnealHalt*)nullptr, 0u);
   return hipGetLastError();
 }
 
@@ -680,7 +952,8 @@ hipError_t launch_scatter(const uint32_t* n, const uint32_t* tile_off,
                           hipStream_t st) {
   const int64_t blocks = (R + 255) / 256;
   hipLaunchKernelGGL(k_scatter, dim3((unsigned)blocks), dim3(256), 0, st, n,
-                     tile_off, R, cap, parent, fam_src, fam_dst);
+                     tile_off, R, cap, parent, fam_src, fam_dst,
+                     (const unsigned long long*)nullptr);
   return hipGetLastError();
 }
 

@@ -211,6 +211,16 @@ void observables_from_hist(const uint32_t* h, int nbins, int shift, int N,
     sE += c * e;
     sE2 += c * e * e;
   }
+  observables_from_sums(R, beta, N, sE, sE2, sumAbsM, sumM2,
+                        level_energy(N, shift, lo), level_energy(N, shift, hi),
+                        o);
+}
+
+// The same from the exact sums (a schedule run on the device sends only
+// these to the host).
+void observables_from_sums(int64_t R, double beta, int N, int64_t sE,
+                           int64_t sE2, int64_t sumAbsM, int64_t sumM2,
+                           int32_t Emin, int32_t Emax, pa_obs* o) {
   const double Rd = (double)R, Nd = (double)N;
   const __int128 var = (__int128)R * sE2 - (__int128)sE * sE;
   o->R = R;
@@ -223,8 +233,8 @@ void observables_from_hist(const uint32_t* h, int nbins, int shift, int N,
   o->sumE2 = sE2;
   o->sumAbsM = sumAbsM;
   o->sumM2 = sumM2;
-  o->Emin = level_energy(N, shift, lo);
-  o->Emax = level_energy(N, shift, hi);
+  o->Emin = Emin;
+  o->Emax = Emax;
 }
 
 // alpha(dbeta) = sum_E min(h/R, h w / S), w = exp(-dbeta (E - Emin))

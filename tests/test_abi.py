@@ -84,6 +84,7 @@ def test_strerror_and_validation_without_device():
                                  C.byref(bh)) == b.PA_EINVAL, (L, q, layout)
         assert not bh.value
     assert lib.pa_sweep(None, 0.1, 1) == b.PA_EINVAL
+    assert lib.pa_anneal(None, None, 0, 1, None, None, None) == b.PA_EINVAL
     assert lib.pa_resample(None, 0.1, None) == b.PA_EINVAL
 
 
