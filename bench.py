@@ -150,13 +150,14 @@ def gather_copy(binding, cfg, stream, reps=5):
 
 
 def run_anneal(binding, cfg, stream, timing=None, rows_per_lane=0,
-               families=None, step_calls=False):
+               families=None, step_calls=False, timing_every=1):
     """One full anneal: the whole schedule in one pa_anneal call (the
     device runs it with no host stop between steps), or with step_calls the
     pa_resample / pa_sweep / pa_observables calls of every step (at the
     capacity where no resampling waits for its size).  timing: None, or the
     kernel classes to time; families: a dict that receives the final family
-    statistics."""
+    statistics; timing_every: time the first launch of a class and then
+    one in timing_every."""
     layout = binding.PA_BITS if cfg["layout"] == "bits" else binding.PA_INT8
     L, R, theta = cfg["L"], cfg["R"], cfg["theta"]
     g = binding.Population(L, R, seed=cfg["seed"], layout=layout,
@@ -166,7 +167,7 @@ def run_anneal(binding, cfg, stream, timing=None, rows_per_lane=0,
                            resampling=cfg.get("law", 0),
                            rng_mode=cfg.get("rng_mode", 0))
     if timing:
-        g.set_timing(True, classes=timing)
+        g.set_timing(True, classes=timing, every=timing_every)
     sched = W.linear_schedule(cfg["beta_f"], cfg["K"])
     attempts = 0
     if step_calls:
@@ -270,7 +271,8 @@ def bench_batched(binding, stream, use_graph=True, rng_mode=0,
                   tune_sweep=True):
     """C4: 64 +-J populations (L in {8..32}, R in [2^10, 2^16]), beta 0 -> 3
     in 300 linear steps, theta = 10; each population alone through the
-    single-population path, then all of them in one batch.  Both runs give
+    single-population path (one pa_anneal call each, the whole schedule on
+    the device), then all of them in one batch.  Both runs give
     bit-identical ln Z, so accuracy is equal by construction."""
     import torch
     inst = W.batched_glass_instances()
@@ -285,10 +287,8 @@ def bench_batched(binding, stream, use_graph=True, rng_mode=0,
         g = binding.Population(c["L"], c["R"], seed=c["seed"],
                                population_id=c["population_id"], J=c["J"],
                                stream=stream, rng_mode=rng_mode)
-        for b in betas:
-            g.resample(b, wait=False)
-            g.sweep(b, theta)
-            attempts += g.observables()["R"] * c["L"] ** 2 * theta
+        obs, _ = g.anneal(betas, theta, as_dicts=False)
+        attempts += int(obs["R"].sum()) * c["L"] ** 2 * theta
         lnz_plain.append(g.free_energy()[0])
         g.close()
     torch.cuda.synchronize()
@@ -990,6 +990,13 @@ def describe(name, cfg):
                "site"))
 
 
+# In the timed anneals the sweep launches are timed with HIP events on a
+# systematic sample, the first and then every tenth: each timed launch adds
+# two event markers to the stream, which at theta = 1 would lengthen a step
+# of about 65 us by several microseconds.
+SWEEP_TIMING_EVERY = 10
+
+
 def time_workload(binding, cfg, stream, steps, warmup, rows_per_lane,
                   verbose=False, step_calls=False):
     """`warmup` untimed anneals, then `steps` timed ones between device
@@ -1011,7 +1018,8 @@ def time_workload(binding, cfg, stream, steps, warmup, rows_per_lane,
         # events on the sweep launches only (two markers per timed launch)
         a, lnZ, t = run_anneal(binding, cfg, stream, timing=("sweep",),
                                rows_per_lane=rows_per_lane,
-                               step_calls=step_calls)
+                               step_calls=step_calls,
+                               timing_every=SWEEP_TIMING_EVERY)
         total_attempts += a
         if tsum is None:
             tsum = t
@@ -1050,6 +1058,7 @@ def time_workload(binding, cfg, stream, steps, warmup, rows_per_lane,
             "sweep_attempts_per_ns": sweep_rate,
             "sweep_avg_ms": sweep_avg_ms,
             "sweep_launches": sw["launches"],
+            "sweep_timing_sample_every": SWEEP_TIMING_EVERY,
             "ops_per_attempt": ops,
             "algorithmic_multiplies_and_plain_ops_per_attempt": list(work),
             "rng": ["word", "planes"][cfg.get("rng_mode", 0)],

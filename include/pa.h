@@ -373,6 +373,12 @@ int pa_weighted_observables(int32_t M, const double* lnZ, const pa_obs* obs,
    since timing was started. */
 #define PA_TIMING_ALL (-1)
 int pa_set_timing(pa_ctx* c, int32_t classes);
+
+/* Time only the first launch and then every `every`-th (>= 1, default 1) of
+   each timed class, counted per class from the last pa_set_timing: a run of
+   many short launches is then disturbed by few events, and the averages
+   stand for a systematic sample of the launches.  PA_EINVAL for every < 1. */
+int pa_set_timing_sample(pa_ctx* c, int32_t every);
 int pa_get_timing(pa_ctx* c, pa_timing* out);
 
 void pa_destroy(pa_ctx* c);

@@ -123,6 +123,7 @@ def lib():
             "pa_overlap": ([P, d, C.POINTER(d)], C.c_int),
             "pa_bisect_dbeta": ([P, d, d, C.POINTER(d)], C.c_int),
             "pa_set_timing": ([P, i32], C.c_int),
+            "pa_set_timing_sample": ([P, i32], C.c_int),
             "pa_save": ([P, C.c_char_p], C.c_int),
             "pa_load": ([C.c_char_p, P, C.POINTER(P)], C.c_int),
             "pa_get_config": ([P, C.POINTER(pa_config)], C.c_int),
@@ -411,9 +412,10 @@ class Population:
             "pa_bisect_dbeta")
         return d.value
 
-    def set_timing(self, enable=True, classes=None):
+    def set_timing(self, enable=True, classes=None, every=1):
         """Start (zeroed) or stop the per-class kernel timing; classes is an
-        iterable of KERNEL_CLASSES names to time (default: all)."""
+        iterable of KERNEL_CLASSES names to time (default: all); every: time
+        the first launch of a class and then one in `every`."""
         if not enable:
             mask = 0
         elif classes is None:
@@ -423,6 +425,8 @@ class Population:
             for k in classes:
                 mask |= 1 << KERNEL_CLASSES.index(k)
         _ck(lib().pa_set_timing(self._h, mask), "pa_set_timing")
+        _ck(lib().pa_set_timing_sample(self._h, every),
+            "pa_set_timing_sample")
 
     def timing(self):
         t = pa_timing()

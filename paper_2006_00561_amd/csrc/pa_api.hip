@@ -39,10 +39,11 @@ struct TimedLaunch {
   int rseq;
 };
 
-// Weight tables of a schedule run on the device: one slot of pinned host
-// memory per queued step, reused kWSlots tables later, once the histogram
-// that read it has reported its sequence number.
-constexpr int kWSlots = 8;
+// Weight tables of a schedule run on the device: slots of pinned host
+// memory, each holding the table of one dbeta (a linear schedule has only a
+// few distinct differences); a slot is refilled, least recently used first,
+// once the last histogram that read it has reported its sequence number.
+constexpr int kWSlots = 16;
 
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
@@ -113,6 +114,8 @@ struct pa_ctx {
   bool R_pending = false;
   int64_t n_len = 0;
   uint32_t timing = 0;  // bit k set: launches of class k are timed
+  int32_t timing_every = 1;      // time one launch in this many per class
+  int64_t timing_count[6] = {};  // launches of each class since the start
   std::vector<TimedLaunch> pending;
   std::vector<hipEvent_t> pool;
   pa_timing acc{};
@@ -130,7 +133,11 @@ struct pa_ctx {
   double* d_w = nullptr;
   uint32_t* h_prog = nullptr;
   uint32_t* d_prog = nullptr;
-  uint32_t wseq = 0;  // weight tables queued so far
+  uint32_t wseq = 0;  // histograms with weights queued so far
+  uint64_t wkey[kWSlots] = {};   // the dbeta of each slot, as bits
+  uint32_t wlast[kWSlots] = {};  // the last histogram that reads it
+  bool wvalid[kWSlots] = {};
+  uint32_t lb_gen = 0;  // launches of the single-pass counts and scatter
 };
 
 #define CK(x) PA_HIP(x)
@@ -152,6 +159,7 @@ hipEvent_t take_event(pa_ctx* c) {
 
 hipEvent_t t_begin(pa_ctx* c, int cls) {
   if (!(c->timing >> cls & 1u)) return nullptr;
+  if (c->timing_count[cls]++ % c->timing_every != 0) return nullptr;
   hipEvent_t e = take_event(c);
   if (e) (void)hipEventRecord(e, c->stream);
   return e;
@@ -1037,12 +1045,19 @@ int pa_anneal(pa_ctx* c, const double* betas, int32_t K, int32_t theta,
   AnnealRec* d_rec = reinterpret_cast<AnnealRec*>(c->arec + 64);
   CK(launch_fill_u32(reinterpret_cast<uint32_t*>(c->arec), 16, 0u,
                      c->stream));
+  // the single-pass scan's status words: no generation in them may match a
+  // launch of this call (the memory may hold anything from earlier use)
+  CK(launch_fill_u32(reinterpret_cast<uint32_t*>(c->tile64),
+                     2 * c->ntiles_cap, 0u, c->stream));
   if (!c->rb_zero) CK(launch_fill_u32(c->rb, c->nb2 + 8, 0u, c->stream));
   const int cur0 = c->cur, fam0 = c->famcur, step0 = c->step;
   const int sw0 = c->sweeps_at_step;
   const double beta0 = c->beta, lnZ0 = c->lnZ, lnQ0 = c->lnQ_last;
   const int64_t R0 = c->R, cap = c->cap, nb = c->nbins;
-  const bool one_pass_scatter = c->ntiles_cap <= 256;
+  // the single-pass counts and parent map: its two counters after the halt
+  // record and the range sums
+  uint32_t* lb_ctr = reinterpret_cast<uint32_t*>(
+      c->arec + sizeof(AnnealHalt) + sizeof(SchedAcc));
   HistArgs h{};
   h.hist = c->hist;
   h.moments = c->scal;
@@ -1080,25 +1095,42 @@ int pa_anneal(pa_ctx* c, const double* betas, int32_t K, int32_t theta,
     h.tab_T = c->tab + nb;
     h.progress = nullptr;
     if (k < K) {
-      // table number wseq + 1 takes the slot of number wseq + 1 - kWSlots
-      const uint32_t seq = c->wseq + 1u;
-      if (seq > (uint32_t)kWSlots && !wait_progress(c, seq - kWSlots)) {
-        CK(wait_stream(c->stream));
-        note_error("a histogram of the schedule did not report its weights");
-        return PA_EDEVICE;
-      }
-      c->wseq = seq;
-      const int slot = (int)(seq % kWSlots);
       // w = exp(-dbeta (E - E0)) for E - E0 = d 2^shift, every level the
-      // histogram may start at: the first ones in the kernel's arguments,
-      // the rest in the slot
+      // histogram may start at: the slot holding this dbeta's table, else
+      // the least recently used one, refilled once its last reader is done
       const double dbeta = betas[k] - c->beta;
-      double* w = c->h_w + (size_t)slot * nb;
-      const int64_t na = std::min<int64_t>(nb, kArgWeights);
-      for (int64_t d = 0; d < na; ++d)
-        wk.w[d] = std::exp(-(dbeta * (double)(d << c->hshift)));
-      for (int64_t d = na; d < nb; ++d)
-        w[d] = std::exp(-(dbeta * (double)(d << c->hshift)));
+      uint64_t key;
+      std::memcpy(&key, &dbeta, sizeof key);
+      int slot = -1;
+      for (int i = 0; i < kWSlots && slot < 0; ++i)
+        if (c->wvalid[i] && c->wkey[i] == key) slot = i;
+      double* w;
+      if (slot >= 0) {
+        w = c->h_w + (size_t)slot * nb;
+      } else {
+        slot = 0;
+        for (int i = 0; i < kWSlots; ++i) {
+          if (!c->wvalid[i]) {
+            slot = i;
+            break;
+          }
+          if ((int32_t)(c->wlast[i] - c->wlast[slot]) < 0) slot = i;
+        }
+        if (c->wvalid[slot] && !wait_progress(c, c->wlast[slot])) {
+          CK(wait_stream(c->stream));
+          note_error("a histogram of the schedule did not report its weights");
+          return PA_EDEVICE;
+        }
+        w = c->h_w + (size_t)slot * nb;
+        for (int64_t d = 0; d < nb; ++d)
+          w[d] = std::exp(-(dbeta * (double)(d << c->hshift)));
+        c->wkey[slot] = key;
+        c->wvalid[slot] = true;
+      }
+      // the first levels also in the kernel's arguments
+      std::memcpy(wk.w, w, (size_t)std::min<int64_t>(nb, kArgWeights) * 8);
+      const uint32_t seq = ++c->wseq;
+      c->wlast[slot] = seq;
       h.wtab = c->d_w + (size_t)slot * nb;
       h.progress = c->d_prog;
       h.wseq = seq;
@@ -1127,23 +1159,35 @@ int pa_anneal(pa_ctx* c, const double* betas, int32_t K, int32_t theta,
     ca.k1 = (uint32_t)(c->seed >> 32);
     ca.pop = c->pop;
     ca.step_next = (uint32_t)(step0 + k + 1);
-    e0 = t_begin(c, PA_K_COUNTS);
-    CK(launch_counts(ca, c->stream));
-    if (!one_pass_scatter)
+    if (c->ntiles_cap > kLookbackTiles) {
+      e0 = t_begin(c, PA_K_COUNTS);
+      CK(launch_counts(ca, c->stream));
       CK(launch_scan_dev(c->tile_sum, c->tile_off, c->ntiles_cap, c->scal + 4,
                          cap, d_halt, (uint32_t)k, c->stream));
-    t_end(c, PA_K_COUNTS, e0, 8 * c->ntiles_cap, 0, 8, 0);
-    e0 = t_begin(c, PA_K_SCATTER);
-    if (one_pass_scatter)
-      CK(launch_scatter_scan_dev(c->n, c->tile_sum, cap, &d_rec[k].Rc, cap,
-                                 c->parent, c->fam[c->famcur],
-                                 c->fam[c->famcur ^ 1], c->scal + 4, d_halt,
-                                 (uint32_t)k, c->stream));
-    else
+      t_end(c, PA_K_COUNTS, e0, 8 * c->ntiles_cap, 0, 8, 0);
+      e0 = t_begin(c, PA_K_SCATTER);
       CK(launch_scatter_dev(c->n, c->tile_off, cap, &d_rec[k].Rc, cap,
                             c->parent, c->fam[c->famcur],
                             c->fam[c->famcur ^ 1], c->stream));
-    t_end(c, PA_K_SCATTER, e0, 0, 0, 4, 0);
+      t_end(c, PA_K_SCATTER, e0, 0, 0, 4, 0);
+    } else {
+    LookbackArgs lb{};
+    lb.status = reinterpret_cast<unsigned long long*>(c->tile64);
+    lb.ticket = lb_ctr;
+    lb.done = lb_ctr + 1;
+    lb.gen = ++c->lb_gen;
+    lb.ntiles = c->ntiles_cap;
+    lb.cap = cap;
+    lb.parent = c->parent;
+    lb.fam_src = c->fam[c->famcur];
+    lb.fam_dst = c->fam[c->famcur ^ 1];
+    lb.total = c->scal + 4;
+    lb.halt = d_halt;
+    lb.step = (uint32_t)k;
+    e0 = t_begin(c, PA_K_COUNTS);
+    CK(launch_counts_scatter(ca, lb, c->stream));
+    t_end(c, PA_K_COUNTS, e0, 8 * c->ntiles_cap, 0, 12, 0);
+    }
     c->famcur ^= 1;
     // (c) theta sweeps at betas[k], each new slot loaded from its parent
     c->beta = betas[k];
@@ -1211,6 +1255,9 @@ int pa_anneal(pa_ctx* c, const double* betas, int32_t K, int32_t theta,
     c->R = (int64_t)rec[K].R;
     c->n_len = (int64_t)rec[K - 1].R;
     c->hist_lo = rec[K].lo;
+  } else if (hh.code == kHaltWait) {
+    note_error("a wait of the single-pass scan for an earlier tile gave up");
+    rc = PA_EDEVICE;
   } else {
     // as after the failed pa_resample of step kd: the population after the
     // sweeps of step kd - 1, in the buffers it was left in
@@ -1550,6 +1597,22 @@ int pa_set_timing(pa_ctx* c, int32_t classes) try {
   if (rc) return rc;
   c->timing = (classes == PA_TIMING_ALL) ? 0x3Fu : ((uint32_t)classes & 0x3Fu);
   if (c->timing) c->acc = pa_timing{};
+  for (auto& n : c->timing_count) n = 0;
+  return PA_OK;
+} catch (const std::bad_alloc&) {
+  return PA_ENOMEM;
+} catch (const std::exception& e) {
+  ::pa::note_exception(e.what());
+  return PA_EDEVICE;
+} catch (...) {
+  ::pa::note_exception("unknown exception");
+  return PA_EDEVICE;
+}
+
+int pa_set_timing_sample(pa_ctx* c, int32_t every) try {
+  if (!c || every < 1) return PA_EINVAL;
+  c->timing_every = every;
+  for (auto& n : c->timing_count) n = 0;
   return PA_OK;
 } catch (const std::bad_alloc&) {
   return PA_ENOMEM;

@@ -953,13 +953,26 @@ int check_flags(pa_batch* b) {
   return PA_OK;
 }
 
+// Waits for the stream by polling it for up to 50 ms, then blocks (a
+// blocking wait wakes up tens of microseconds late, which every step of a
+// batch would pay).
+hipError_t poll_stream(hipStream_t st) {
+  const auto t0 = std::chrono::steady_clock::now();
+  for (;;) {
+    const hipError_t e = hipStreamQuery(st);
+    if (e != hipErrorNotReady) return e;
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(50))
+      return hipStreamSynchronize(st);
+  }
+}
+
 // The host part of a step between the two kernel sequences: all
 // histograms down, synchronise, the host function, all tables up.  The
 // copies and the host function stay outside the graphs.
 int host_between(pa_batch* b) {
   BK(hipMemcpyAsync(b->h_rb, b->d_rb, b->rb_bytes, hipMemcpyDeviceToHost,
                     b->stream));
-  BK(hipStreamSynchronize(b->stream));
+  BK(poll_stream(b->stream));
   const int rc = check_flags(b);
   if (rc) return rc;
   host_step(b);

@@ -57,8 +57,9 @@ struct AnnealRec {
 };
 static_assert(sizeof(AnnealRec) == 64, "record layout");
 
-// The first step of such a schedule that failed, 0 while none has.
-enum { kHaltCapacity = 1, kHaltEmpty = 2, kHaltEnergy = 3 };
+// The first step of such a schedule that failed, 0 while none has
+// (kHaltWait: a wait of the single-pass scan for an earlier tile gave up).
+enum { kHaltCapacity = 1, kHaltEmpty = 2, kHaltEnergy = 3, kHaltWait = 4 };
 struct AnnealHalt {
   uint32_t code, step;      // step: index of the failed resampling
   unsigned long long total; // the new size that failed (capacity, empty)
@@ -145,6 +146,27 @@ struct CountsArgs {
   // range (lvl_dev[0], lvl_dev[1]) come from the step's record
   const unsigned long long* Rdev;
   const int32_t* lvl_dev;
+};
+
+// Single-pass counts, scan and parent map of a schedule on the device: each
+// workgroup takes the next tile from *ticket, publishes its tile's sum in
+// status[tile] and looks back over the earlier tiles for its prefix
+// (decoupled look-back); *done finds the last workgroup, which resets both
+// counters.  Status words carry the launch's generation, so the array
+// needs no clearing.
+struct LookbackArgs {
+  unsigned long long* status;  // [ntiles]
+  uint32_t* ticket;
+  uint32_t* done;
+  uint32_t gen;                // 28 bits used
+  int64_t ntiles;
+  int64_t cap;
+  uint32_t* parent;
+  const uint32_t* fam_src;
+  uint32_t* fam_dst;
+  unsigned long long* total;   // the new size (0 once the schedule stops)
+  AnnealHalt* halt;
+  uint32_t step;
 };
 
 // Nearest-integer tables of at most kArgLevels occupied levels, passed by
@@ -340,16 +362,14 @@ hipError_t launch_scatter(const uint32_t* n, const uint32_t* tile_off,
                           const uint32_t* fam_src, uint32_t* fam_dst,
                           hipStream_t st);
 hipError_t launch_gather(const GatherArgs& a, hipStream_t st);
-// the same steps of a schedule on the device: the old size is read from
-// *Rdev (R and cap bound the grid), a new size of 0 or above cap stops the
-// schedule (*halt, and the size written is 0)
-hipError_t launch_scatter_scan_dev(const uint32_t* n, const uint32_t* tile_sum,
-                                   int64_t R, const unsigned long long* Rdev,
-                                   int64_t cap, uint32_t* parent,
-                                   const uint32_t* fam_src, uint32_t* fam_dst,
-                                   unsigned long long* total,
-                                   AnnealHalt* halt, uint32_t step,
-                                   hipStream_t st);
+// (at most kLookbackTiles tiles: with more, the waits for earlier tiles
+// cost more than the two launches they save)
+constexpr int64_t kLookbackTiles = 256;
+hipError_t launch_counts_scatter(const CountsArgs& a, const LookbackArgs& s,
+                                 hipStream_t st);
+// counts, scan and parent map in three launches for more tiles: the old
+// size is read from *Rdev (R and cap bound the grid); a new size of 0 or
+// above cap stops the schedule (*halt, and the size written is 0)
 hipError_t launch_scan_dev(const uint32_t* tile_sum, uint32_t* tile_off,
                            int64_t ntiles, unsigned long long* total,
                            int64_t cap, AnnealHalt* halt, uint32_t step,

@@ -585,15 +585,16 @@ __global__ __launch_bounds__(256) void k_count_tiles(CountsArgs a) {
 // Single workgroup of 1024 threads: exclusive scan of ntiles tile sums.
 // New size of a resampling in a schedule on the device: 0 and sizes above
 // the capacity stop the schedule (the first such step is recorded) and
-// leave no replicas for the kernels after it.
+// leave no replicas for the kernels after it; once it has stopped, every
+// size is 0.
 __device__ __forceinline__ unsigned long long checked_total(
     unsigned long long t, int64_t cap, AnnealHalt* halt, uint32_t step) {
-  if (!halt || (t != 0ull && t <= (unsigned long long)cap)) return t;
-  if (halt->code == 0u) {
-    halt->code = t ? kHaltCapacity : kHaltEmpty;
-    halt->step = step;
-    halt->total = t;
-  }
+  if (!halt) return t;
+  if (halt->code != 0u) return 0ull;
+  if (t != 0ull && t <= (unsigned long long)cap) return t;
+  halt->code = t ? kHaltCapacity : kHaltEmpty;
+  halt->step = step;
+  halt->total = t;
   return 0ull;
 }
 
@@ -655,11 +656,9 @@ constexpr int kScatterTiles = 256;
 __global__ __launch_bounds__(256) void k_scatter_scan(
     const uint32_t* n, const uint32_t* tile_sum, int64_t ntiles, int64_t R,
     int64_t cap, uint32_t* parent, const uint32_t* fam_src, uint32_t* fam_dst,
-    unsigned long long* total_out, const unsigned long long* Rdev,
-    AnnealHalt* halt, uint32_t step) {
+    unsigned long long* total_out) {
   __shared__ uint32_t lds[8];
   __shared__ uint32_t base_sh;
-  if (Rdev) R = min((int64_t)*Rdev, R);
   // the tile sums before this tile, one per lane, then summed
   const uint32_t v = (threadIdx.x < blockIdx.x) ? tile_sum[threadIdx.x] : 0u;
   uint32_t before;
@@ -670,7 +669,7 @@ __global__ __launch_bounds__(256) void k_scatter_scan(
     const uint32_t w = (threadIdx.x < ntiles) ? tile_sum[threadIdx.x] : 0u;
     uint32_t all;
     (void)block_excl_scan(w, lds, &all);
-    if (threadIdx.x == 0) *total_out = checked_total(all, cap, halt, step);
+    if (threadIdx.x == 0) *total_out = all;
   }
   __syncthreads();  // every wave has read lds before its next use
   const uint32_t base = base_sh;
@@ -685,6 +684,124 @@ __global__ __launch_bounds__(256) void k_scatter_scan(
       parent[o + t] = (uint32_t)j;
       if (fam_dst) fam_dst[o + t] = fj;
     }
+}
+
+// ------------------------------------------ single-pass counts and scatter
+
+// Polls of an earlier tile's status before the wait gives up (each poll
+// sleeps about 64 cycles first: some tens of milliseconds in all).
+constexpr int kLookbackPolls = 1 << 20;
+
+// Status word of a tile: the launch's generation (28 bits), the kind (1:
+// the tile's own sum, 2: the inclusive prefix through it) and the value (34
+// bits: sizes stay below 2^33, the capacity being below 2^32).
+constexpr unsigned long long kLbValue = (1ull << 34) - 1ull;
+__device__ __forceinline__ unsigned long long lb_word(uint32_t gen,
+                                                      uint32_t kind,
+                                                      unsigned long long v) {
+  return ((unsigned long long)gen << 36) | ((unsigned long long)kind << 34) |
+         (v & kLbValue);
+}
+
+// Copy counts of a tile of 256 replicas, the exclusive prefix of the tile
+// sums before it and the parent of every new slot of the tile, in one pass.
+// The tile is the workgroup's ticket, so every earlier tile belongs to a
+// workgroup that has already started; a workgroup publishes its tile's sum
+// before it waits for anything, and waits only for earlier tiles.
+__global__ __launch_bounds__(256) void k_counts_scatter(CountsArgs a0,
+                                                        LookbackArgs s) {
+  __shared__ uint32_t lds[8];
+  __shared__ uint32_t s_tile;
+  __shared__ unsigned long long s_prefix;
+  if (threadIdx.x == 0) s_tile = atomicAdd(s.ticket, 1u);
+  __syncthreads();
+  const uint32_t tile = s_tile;
+  CountsArgs a = a0;
+  if (a0.Rdev) a.R = min((int64_t)*a0.Rdev, a0.R);
+  if (a0.lvl_dev) {
+    a.lvl0 = a0.lvl_dev[0];
+    a.nlvl = a0.lvl_dev[1];
+  }
+  const int64_t j = (int64_t)tile * blockDim.x + threadIdx.x;
+  for (int64_t i = j; i < a.nclear; i += s.ntiles * blockDim.x)
+    a.clear[i] = 0u;
+  const uint32_t fj = (j < a.R && s.fam_src) ? s.fam_src[j] : 0u;
+  uint32_t nj = 0u;
+  if (j < a.R) {
+    nj = count_of(a, j, a.f, a.T);
+    a.n[j] = nj;
+  }
+  uint32_t agg;
+  const uint32_t ex = block_excl_scan(nj, lds, &agg);
+  const uint32_t gen = s.gen & 0x0FFFFFFFu;
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    if (tile == 0) {
+      if (lane == 0) {
+        __hip_atomic_store(&s.status[0], lb_word(gen, 2u, agg),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_prefix = 0ull;
+      }
+    } else {
+      if (lane == 0)
+        __hip_atomic_store(&s.status[tile], lb_word(gen, 1u, agg),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      unsigned long long prefix = 0ull;
+      bool failed = false;
+      // windows of 64 earlier tiles, lane 0 the nearest, until one of them
+      // holds an inclusive prefix (tile 0 always does)
+      for (int64_t end = tile; end > 0; end -= 64) {
+        const int64_t p = end - 1 - lane;
+        unsigned long long w = 0ull;
+        bool ready = p < 0;
+        for (int k = 0; !ready && k < kLookbackPolls; ++k) {
+          w = __hip_atomic_load(&s.status[p], __ATOMIC_RELAXED,
+                                __HIP_MEMORY_SCOPE_AGENT);
+          ready = (uint32_t)(w >> 36) == gen && ((w >> 34) & 3ull) != 0ull;
+          if (!ready) __builtin_amdgcn_s_sleep(1);
+        }
+        if (!__all(ready)) {
+          failed = true;
+          break;
+        }
+        const bool incl = p >= 0 && ((w >> 34) & 3ull) == 2ull;
+        const unsigned long long im = __ballot(incl);
+        // the lanes up to the nearest inclusive prefix, or the whole window
+        const int upto = im ? __builtin_ctzll(im) : 63;
+        unsigned long long v =
+            (p >= 0 && lane <= upto) ? (w & kLbValue) : 0ull;
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        prefix += v;
+        if (im) break;
+      }
+      if (lane == 0) {
+        if (failed) {
+          if (atomicCAS(&s.halt->code, 0u, (uint32_t)kHaltWait) == 0u)
+            s.halt->step = s.step;
+          prefix = 0ull;
+        }
+        __hip_atomic_store(&s.status[tile], lb_word(gen, 2u, prefix + agg),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_prefix = prefix;
+      }
+    }
+  }
+  __syncthreads();
+  const unsigned long long base = s_prefix;
+  const int64_t o = (int64_t)(base + ex);
+  for (uint32_t t = 0; t < nj; ++t)
+    if (o + t < s.cap) {
+      s.parent[o + t] = (uint32_t)j;
+      if (s.fam_dst) s.fam_dst[o + t] = fj;
+    }
+  if (threadIdx.x == 0) {
+    if (tile == (uint32_t)(s.ntiles - 1))
+      *s.total = checked_total(base + agg, s.cap, s.halt, s.step);
+    if (atomicAdd(s.done, 1u) == (uint32_t)(s.ntiles - 1)) {
+      *s.ticket = 0u;
+      *s.done = 0u;
+    }
+  }
 }
 
 // ---------------------------------------------------------------- gather
@@ -858,24 +975,19 @@ hipError_t launch_scatter_scan(const uint32_t* n, const uint32_t* tile_sum,
   if (blocks > kScatterTiles) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_scatter_scan, dim3((unsigned)(blocks ? blocks : 1)),
                      dim3(256), 0, st, n, tile_sum, blocks, R, cap, parent,
-                     fam_src, fam_dst, total,
-                     (const unsigned long long*)nullptr, (AnnealHalt*)nullptr,
-                     0u);
+                     fam_src, fam_dst, total);
   return hipGetLastError();
 }
 
-hipError_t launch_scatter_scan_dev(const uint32_t* n, const uint32_t* tile_sum,
-                                   int64_t R, const unsigned long long* Rdev,
-                                   int64_t cap, uint32_t* parent,
-                                   const uint32_t* fam_src, uint32_t* fam_dst,
-                                   unsigned long long* total,
-                                   AnnealHalt* halt, uint32_t step,
-                                   hipStream_t st) {
-  const int64_t blocks = (R + 255) / 256;
-  if (blocks > kScatterTiles || !Rdev || !halt) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_scatter_scan, dim3((unsigned)(blocks ? blocks : 1)),
-                     dim3(256), 0, st, n, tile_sum, blocks, R, cap, parent,
-                     fam_src, fam_dst, total, Rdev, halt, step);
+hipError_t launch_counts_scatter(const CountsArgs& a, const LookbackArgs& s,
+                                 hipStream_t st) {
+  const int64_t blocks = (a.R + 255) / 256;
+  if (blocks != s.ntiles || blocks <= 0 || blocks > kLookbackTiles ||
+      s.cap >= (1ll << 32) || a.poisson || !s.halt || !s.total ||
+      !s.status || !s.ticket || !s.done)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_counts_scatter, dim3((unsigned)blocks), dim3(256), 0,
+                     st, a, s);
   return hipGetLastError();
 }
 

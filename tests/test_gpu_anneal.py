@@ -46,7 +46,7 @@ SCHEDULES = [
     (64, 129, 0, 0, False, 1, 2, 10, 0.6, 0, 0),
     (64, 70, 1, 2, True, 1, 2, 8, 0.8, 0, 0),
     (128, 40, 1, 0, False, 0, 1, 6, 0.5, 0, 0),          # histogram window
-    (8, 70000, 0, 0, False, 0, 1, 4, 0.4, 0, 0),         # multi-pass scan
+    (8, 70000, 0, 0, False, 0, 1, 4, 0.4, 0, 0),         # 294 tiles
     (16, 2000, 0, 0, False, 1, 2, 12, 1.0, 0, 8192),     # roomy capacity
     (16, 400, 0, 0, False, 0, 2, 10, 1.2, 3, 0),         # Potts q = 3
     (10, 300, 0, 0, False, 0, 3, 8, 1.5, 5, 0),
@@ -111,10 +111,41 @@ def test_anneal_in_pieces_and_timing(pa):
     assert g.free_energy() == h.free_energy()
     t = g.timing()
     assert t["sweep"]["launches"] == 12 and t["hist"]["launches"] == 13
-    assert t["counts"]["launches"] == 12 and t["scatter"]["launches"] == 12
+    # counts, scan and parent map are one single-pass launch per step
+    assert t["counts"]["launches"] == 12 and t["scatter"]["launches"] == 0
     assert t["attempts"] == sum(o["R"] for o in obs_g) * L * L * theta
+    # a systematic sample of the launches: the first, then every fifth
+    s = pa.Population(L, R, seed=4)
+    s.set_timing(True, classes=("sweep",), every=5)
+    obs_s, _ = s.anneal(sched, theta)
+    ts = s.timing()
+    assert ts["sweep"]["launches"] == 3
+    assert ts["attempts"] == sum(obs_s[i]["R"] for i in (0, 5, 10)) * \
+        L * L * theta
+    with pytest.raises(pa.PAError):
+        s.set_timing(True, classes=("sweep",), every=0)
     g.close()
     h.close()
+    s.close()
+
+
+def test_anneal_on_reused_memory(pa):
+    """A context made after another was freed may get its memory back, with
+    the single-pass scan's status words of that context's launches in it;
+    the new schedule must not read them (it equals the first one)."""
+    L, R, theta = 32, 30000, 1
+    sched = W.linear_schedule(1.0, 40)
+    runs = []
+    for _ in range(3):
+        g = pa.Population(L, R, seed=21)
+        obs, q = g.anneal(sched, theta)
+        runs.append(([o["R"] for o in obs], q, g.free_energy(),
+                     g.energies()))
+        g.close()
+    for r in runs[1:]:
+        assert r[0] == runs[0][0] and r[1] == runs[0][1]
+        assert r[2] == runs[0][2]
+        assert np.array_equal(r[3][0], runs[0][3][0])
 
 
 def test_anneal_capacity_stop_matches_step_calls(pa):
