@@ -129,6 +129,7 @@ struct pa_ctx {
   unsigned char* h_arec = nullptr;
   int64_t arec_steps = 0;
   double* wscr = nullptr;
+  BlockSums* hpart = nullptr;  // the histogram workgroups' parts (256)
   double* h_w = nullptr;
   double* d_w = nullptr;
   uint32_t* h_prog = nullptr;
@@ -459,7 +460,8 @@ void free_all(pa_ctx* c) {
     if (c->fam[b]) (void)hipFree(c->fam[b]);
   }
   void* dev[] = {c->n,  c->parent, c->tile_sum, c->tile_off, c->tile64,
-                 c->off64, c->cum, c->rb, c->tab, c->jbits, c->arec, c->wscr};
+                 c->off64, c->cum, c->rb, c->tab, c->jbits, c->arec, c->wscr,
+                 c->hpart};
   for (void* p : dev)
     if (p) (void)hipFree(p);
   if (c->h_rb) (void)hipHostFree(c->h_rb);
@@ -497,6 +499,8 @@ bool dmalloc(T** p, size_t bytes) {
 int ensure_anneal(pa_ctx* c, int64_t K) {
   const size_t nb = (size_t)c->nbins;
   if (!c->wscr && !dmalloc(&c->wscr, 2 * nb * sizeof(double)))
+    return PA_ENOMEM;
+  if (!c->hpart && !dmalloc(&c->hpart, 256 * sizeof(BlockSums)))
     return PA_ENOMEM;
   if (!c->h_w) {
     void* h = nullptr;
@@ -1056,8 +1060,7 @@ int pa_anneal(pa_ctx* c, const double* betas, int32_t K, int32_t theta,
   const int64_t R0 = c->R, cap = c->cap, nb = c->nbins;
   // the single-pass counts and parent map: its two counters after the halt
   // record and the range sums
-  uint32_t* lb_ctr = reinterpret_cast<uint32_t*>(
-      c->arec + sizeof(AnnealHalt) + sizeof(SchedAcc));
+  uint32_t* lb_ctr = reinterpret_cast<uint32_t*>(c->arec + 32);
   HistArgs h{};
   h.hist = c->hist;
   h.moments = c->scal;
@@ -1073,7 +1076,7 @@ int pa_anneal(pa_ctx* c, const double* betas, int32_t K, int32_t theta,
     h.win_lo = (c->nbins - h.win_n) / 2;
   h.counter = c->rb + c->nb2 + 12;
   h.halt = d_halt;
-  h.acc = reinterpret_cast<SchedAcc*>(c->arec + sizeof(AnnealHalt));
+  h.part = c->hpart;
   h.Rw = c->scal + 4;
   h.wscr = c->wscr;
   h.R_t = c->R_t;

@@ -65,13 +65,16 @@ struct AnnealHalt {
   unsigned long long total; // the new size that failed (capacity, empty)
 };
 
-// Occupied range and exact energy sums of a step's histogram, added up by
-// every workgroup of it (zero between steps): lo_rev = max of nbins - bin,
-// hi1 = max of bin + 1.
-struct SchedAcc {
-  uint32_t lo_rev, hi1;
+// One workgroup's part of a step's histogram: its moment sums, exact energy
+// sums and occupied range (lo_rev = max of nbins - bin, hi1 = max of bin +
+// 1; both 0 when it counted nothing); the last workgroup adds them up.
+struct BlockSums {
+  unsigned long long sAbsM, sM2;
   long long sE, sE2;
+  uint32_t lo_rev, hi1;
+  uint32_t pad[2];
 };
+static_assert(sizeof(BlockSums) == 48, "block sums layout");
 
 // The first kArgWeights weights exp(-dbeta d 2^shift) of a step, in the
 // histogram kernel's arguments (no read from host memory for them).
@@ -122,7 +125,7 @@ struct HistArgs {
   // memory) once they are read
   uint32_t* progress;
   uint32_t wseq;
-  SchedAcc* acc;
+  BlockSums* part;  // one per workgroup (at most 256)
 };
 
 struct CountsArgs {

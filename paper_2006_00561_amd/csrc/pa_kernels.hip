@@ -82,8 +82,30 @@ constexpr int kTermPiece = 4096;
 __device__ void anneal_tail(const HistArgs& a, const double* wk, int64_t R,
                             double* tl) {
   __shared__ double s_S;
-  const int tid = threadIdx.x, wid = tid >> 6;
-  const SchedAcc acc = *a.acc;
+  __shared__ BlockSums s_red[4];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  // the workgroups' parts, one per thread, summed over the workgroup
+  BlockSums acc{};
+  if (tid < (int)gridDim.x) acc = a.part[tid];
+  for (int off = 32; off > 0; off >>= 1) {
+    acc.sAbsM += __shfl_down(acc.sAbsM, off, 64);
+    acc.sM2 += __shfl_down(acc.sM2, off, 64);
+    acc.sE += __shfl_down(acc.sE, off, 64);
+    acc.sE2 += __shfl_down(acc.sE2, off, 64);
+    acc.lo_rev = max(acc.lo_rev, (uint32_t)__shfl_down((int)acc.lo_rev, off, 64));
+    acc.hi1 = max(acc.hi1, (uint32_t)__shfl_down((int)acc.hi1, off, 64));
+  }
+  if (lane == 0) s_red[wid] = acc;
+  __syncthreads();
+  acc = s_red[0];
+  for (int i = 1; i < (int)(blockDim.x >> 6); ++i) {
+    acc.sAbsM += s_red[i].sAbsM;
+    acc.sM2 += s_red[i].sM2;
+    acc.sE += s_red[i].sE;
+    acc.sE2 += s_red[i].sE2;
+    acc.lo_rev = max(acc.lo_rev, s_red[i].lo_rev);
+    acc.hi1 = max(acc.hi1, s_red[i].hi1);
+  }
   const int lo = a.nbins - (int)acc.lo_rev, hi = (int)acc.hi1 - 1;
   // a bad energy stops the schedule here: no tables, no replicas from now on
   const bool bad = a.moments[3] != 0ull;
@@ -142,15 +164,14 @@ __device__ void anneal_tail(const HistArgs& a, const double* wk, int64_t R,
     AnnealRec r;
     r.R = (unsigned long long)R;
     r.Rc = bad ? 0ull : (unsigned long long)R;
-    r.sumAbsM = a.moments[0];
-    r.sumM2 = a.moments[1];
+    r.sumAbsM = acc.sAbsM;
+    r.sumM2 = acc.sM2;
     r.sumE = acc.sE;
     r.sumE2 = acc.sE2;
     r.S = S;
     r.lo = lo;
     r.nl = nl;
     *a.rec = r;
-    *a.acc = SchedAcc{0u, 0u, 0ll, 0ll};
     if (bad) {
       if (a.halt->code == 0u) {
         a.halt->code = kHaltEnergy;
@@ -264,15 +285,20 @@ __device__ __forceinline__ void hist_body(const HistArgs& a, const double* wk) {
         r1 = max(r1, red_r[1][i]);
       }
     }
-    atomicAdd(&a.moments[0], s0);
-    atomicAdd(&a.moments[1], s1);
-    if (SCHED && r1) {
-      atomicAdd(reinterpret_cast<unsigned long long*>(&a.acc->sE),
-                (unsigned long long)t0);
-      atomicAdd(reinterpret_cast<unsigned long long*>(&a.acc->sE2),
-                (unsigned long long)t1);
-      atomicMax(&a.acc->lo_rev, r0);
-      atomicMax(&a.acc->hi1, r1);
+    if (SCHED) {
+      // the workgroup's part, added up by the last workgroup (no device
+      // atomics on shared words)
+      BlockSums b{};
+      b.sAbsM = s0;
+      b.sM2 = s1;
+      b.sE = t0;
+      b.sE2 = t1;
+      b.lo_rev = r0;
+      b.hi1 = r1;
+      a.part[blockIdx.x] = b;
+    } else {
+      atomicAdd(&a.moments[0], s0);
+      atomicAdd(&a.moments[1], s1);
     }
   }
   // the window's nonzero bins to the global histogram (a step of a schedule
@@ -948,7 +974,7 @@ hipError_t launch_hist_sched(const HistArgs& a, const ArgWeights& w,
   if (blocks < 1) blocks = 1;
   if (blocks > 256) blocks = 256;
   if (a.win_n < 0 || a.win_n > 16384 || a.win_lo < 0 ||
-      a.win_lo + a.win_n > a.nbins || !a.rec || !a.acc || !a.halt || !a.Rw)
+      a.win_lo + a.win_n > a.nbins || !a.rec || !a.part || !a.halt || !a.Rw)
     return hipErrorInvalidValue;
   // LDS: the window, then the table tail's terms (kTermPiece doubles)
   const size_t shm = std::max((size_t)a.win_n * sizeof(uint32_t),
