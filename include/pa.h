@@ -212,7 +212,9 @@ int pa_resample(pa_ctx* c, double beta_next, int64_t* R_new);
    step with the context as the failed pa_resample leaves it: the
    population after the sweeps of the step before.  PA_EINVAL for K < 0,
    theta outside 0..32767, a non-finite or negative beta, or more than
-   65535 steps in all.  Synchronises once, at the end. */
+   65535 steps in all (nothing changes then); after PA_EDEVICE the context
+   is left as the device left it and is only fit for pa_destroy.
+   Synchronises once, at the end. */
 int pa_anneal(pa_ctx* c, const double* betas, int32_t K, int32_t theta,
               pa_obs* obs, double* lnQ, int32_t* done);
 

@@ -1081,6 +1081,12 @@ int pa_anneal(pa_ctx* c, const double* betas, int32_t K, int32_t theta,
   h.wscr = c->wscr;
   h.R_t = c->R_t;
   ArgWeights wk{};
+  // timed launches are tagged with their record while the loop runs, on
+  // every way out of it too
+  struct TagReset {
+    pa_ctx* c;
+    ~TagReset() { c->rseq_tag = -1; }
+  } tag_reset{c};
   // the sizes stay on the device until the end: grids cover the capacity
   c->R = cap;
   c->R_pending = true;
