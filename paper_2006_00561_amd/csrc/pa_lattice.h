@@ -205,6 +205,60 @@ __device__ __forceinline__ void plane_decide2(const uint4 oA, const uint4 oB,
   e8[1] = to_parity(q8, p);
 }
 
+// An L = 64 int8 replica (4 KB, one row of 64 bytes per lane) moved as
+// four contiguous kilobytes per wave: in load q, lane l reads bytes
+// [1024 q + 16 l, +16), which hold columns 16 (l % 4) .. + 15 of row
+// 16 q + l / 4; the 16 sites of each such piece are packed to 16 bits and
+// sent to the lane of their row through ds_bpermute (lane y takes the
+// pieces of lanes 4 (y % 16) + c of load y / 16).  Every load and store of
+// the wave covers 1 KB of consecutive bytes instead of 16 bytes of 64 rows.
+__device__ __forceinline__ void load_replica64_int8(const uint8_t* rp,
+                                                    uint32_t row[2]) {
+  const int lane = threadIdx.x & 63;
+  uint32_t p[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint4 v =
+        *reinterpret_cast<const uint4*>(rp + 1024 * q + 16 * lane);
+    p[q] = pack4(v.x) | (pack4(v.y) << 4) | (pack4(v.z) << 8) |
+           (pack4(v.w) << 12);
+  }
+  const uint32_t r01 = p[0] | (p[1] << 16), r23 = p[2] | (p[3] << 16);
+  const int qy = lane >> 4;  // the load that holds this lane's row
+  uint32_t piece[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int src = 4 * (lane & 15) + c;
+    const uint32_t a = shfl(r01, src), b = shfl(r23, src);
+    const uint32_t v = (qy & 2) ? b : a;
+    piece[c] = (qy & 1) ? (v >> 16) : (v & 0xFFFFu);
+  }
+  row[0] = piece[0] | (piece[1] << 16);
+  row[1] = piece[2] | (piece[3] << 16);
+}
+
+// The inverse: lane l writes bytes [1024 q + 16 l, +16) from the row
+// 16 q + l / 4 of lane 16 q + l / 4.  Every lane takes part in the
+// exchange; only `store` lanes write.
+__device__ __forceinline__ void store_replica64_int8(uint8_t* rp,
+                                                     const uint32_t row[2],
+                                                     bool store) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int src = 16 * q + (lane >> 2);
+    const uint32_t w0 = shfl(row[0], src), w1 = shfl(row[1], src);
+    const uint32_t v = (lane & 2) ? w1 : w0;
+    const uint32_t b = (lane & 1) ? (v >> 16) : (v & 0xFFFFu);
+    uint4 out;
+    out.x = unpack4(b & 0xFu);
+    out.y = unpack4((b >> 4) & 0xFu);
+    out.z = unpack4((b >> 8) & 0xFu);
+    out.w = unpack4((b >> 12) & 0xFu);
+    if (store) *reinterpret_cast<uint4*>(rp + 1024 * q + 16 * lane) = out;
+  }
+}
+
 // One wave's share of a lattice pass: replicas wave*rpw .. wave*rpw+rpw-1.
 // No workgroup barrier, so persistent kernels can call it per work item.
 // PLANES selects the bit-plane random numbers, else one Philox word per
@@ -233,6 +287,9 @@ __device__ __forceinline__ void lattice_pass(const LatticeArgs& a,
       a.parent ? a.src + (size_t)a.parent[slot] * (size_t)a.stride : rp;
 
   uint32_t s[RPL][W];
+  // an int8 replica of L = 64 in one wave, one row per lane: loaded and
+  // stored as whole kilobytes
+  const bool T64 = INT8 && W == 2 && RPL == 1 && L == 64 && a.rpw == 1;
   // couplings: jr = bond to the right, jl = bond to the left (jr of x-1),
   // jd = bond below, ju = bond above (jd of row y-1); bit set = J < 0
   uint32_t jr[RPL][W], jl[RPL][W], jd[RPL][W], ju[RPL][W];
@@ -280,6 +337,14 @@ __device__ __forceinline__ void lattice_pass(const LatticeArgs& a,
         }
         s[r][w] = v & valid_mask(L, w);
       }
+    } else if (T64) {
+      // the wave's one replica as four coalesced kilobytes (the branch is
+      // uniform: the wave holds one replica, and a wave past the
+      // population has left)
+      uint32_t row2[2];
+      load_replica64_int8(lp, row2);
+#pragma unroll
+      for (int w = 0; w < W; ++w) s[r][w] = row2[w < 2 ? w : 0];
     } else if (active) {
       load_row<W, RPL, INT8>(lp, L, y, s[r]);
     } else {
@@ -471,9 +536,16 @@ __device__ __forceinline__ void lattice_pass(const LatticeArgs& a,
       ups += up;
     }
   }
+  if (T64) {
+    uint32_t row2[2] = {s[0][0], s[0][W > 1 ? 1 : 0]};
+    store_replica64_int8(rp, row2, active);
+  }
   if (active) {
+    if (!T64) {
 #pragma unroll
-    for (int r = 0; r < RPL; ++r) store_row<W, RPL, INT8>(rp, L, lr * RPL + r, s[r]);
+      for (int r = 0; r < RPL; ++r)
+        store_row<W, RPL, INT8>(rp, L, lr * RPL + r, s[r]);
+    }
     if (lr == a.lpr - 1) {
       const int N = L * L;
       a.E[rep] = 2 * unsat - 2 * N;
