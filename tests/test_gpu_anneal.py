@@ -334,3 +334,45 @@ def test_anneal_whole_schedule_equals_step_calls(pa, name):
     assert np.array_equal(g.families()[0], h.families()[0])
     g.close()
     h.close()
+
+
+def test_anneal_zero_steps_and_repeated_betas(pa):
+    """dbeta = 0 (weights all exp(-0) = 1): a step at the current beta keeps
+    every replica once when R = R_target, also in the middle of a schedule
+    that repeats a beta; the whole run equals the oracle's."""
+    L, R, theta = 12, 300, 2
+    g = pa.Population(L, R, seed=17)
+    o = oracle.OraclePA(L, R, seed=17)
+    obs, q = g.anneal([0.0], theta)
+    assert obs[0]["R"] == R and q[0] == 0.0
+    assert np.all(g.counts() == 1)
+    o.resample(0.0)
+    o.sweep(theta)
+    sched = [0.2, 0.2, 0.5, 0.5, 0.5, 0.9]
+    obs_g, q_g = g.anneal(sched, theta)
+    for i, (Rn, lnQ, oo) in enumerate(_run_oracle(o, sched, theta)):
+        assert obs_g[i]["R"] == Rn and q_g[i] == lnQ, i
+        _cmp_obs(obs_g[i], oo)
+    _cmp_state(g, o, "repeated betas")
+    g.close()
+    o.close()
+
+
+@pytest.mark.parametrize("L,R", [(4, 1), (4, 255), (6, 256), (8, 257),
+                                 (4, 3000)])
+def test_anneal_tile_edges_and_smallest_lattice(pa, L, R):
+    """Populations of one replica, one tile less one, one tile, one tile plus
+    one, and the smallest lattice with many tiles, each for a one-step and a
+    longer schedule."""
+    print("anneal edges L=%d R=%d" % (L, R), flush=True)
+    for K in (1, 9):
+        sched = W.linear_schedule(1.5, K)
+        g = pa.Population(L, R, seed=5 + K)
+        o = oracle.OraclePA(L, R, seed=5 + K)
+        obs_g, q_g = g.anneal(sched, 3)
+        for i, (Rn, lnQ, oo) in enumerate(_run_oracle(o, sched, 3)):
+            assert obs_g[i]["R"] == Rn and q_g[i] == lnQ, (K, i)
+            _cmp_obs(obs_g[i], oo)
+        _cmp_state(g, o, "L=%d R=%d K=%d" % (L, R, K))
+        g.close()
+        o.close()
