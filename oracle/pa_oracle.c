@@ -849,9 +849,18 @@ int orc_get_counts(const orc_pa* p, uint32_t* n, int64_t cap) {
 /* The heating protocol (Sec. 2, with the Potts reference): the population
    starts close to zero temperature, at beta0 > 0, in the ground states of
    the ferromagnet, all spins +1 or all -1 with probability 1/2 each (the top
-   bit of the INIT word of site (0,0) of the replica decides), and
-   ln Z(beta0) = ln 2 + 2 N beta0 (two states of energy -2N; the excited
-   states add about N exp(-8 beta0) relative to this, which is left out). */
+   bit of the INIT word of site (0,0) of the replica decides), and ln Z(beta0)
+   is that of the ground states, ln g + 2 N beta0 (g = 2 states, or q for
+   Potts, of energy -2N), plus the smallest excitations of each: on a torus
+   of side L >= 4 one changed site (N of them, 4 bonds broken) and two
+   changed neighbours (2N pairs, 6 bonds broken, or 7 when the two Potts
+   states differ).  Taking the logarithm of 1 + these terms, the products of
+   two distant excitations cancel the square of the first term, so up to
+   terms of order N exp(-16 beta0) (Ising) or N exp(-8 beta0) (Potts):
+     Ising: ln Z = ln 2 + 2 N beta0 + N (exp(-8 beta0) + 2 exp(-12 beta0));
+     Potts: ln Z = ln q + 2 N beta0
+                   + N (q - 1) (exp(-4 beta0) + 2 exp(-6 beta0)
+                                + 2 (q - 2) exp(-7 beta0)). */
 int orc_start_heating(orc_pa* p, double beta0) {
   if (!p || p->J || p->step != 0 || !isfinite(beta0) || !(beta0 > 0.0))
     return ORC_EINVAL;
@@ -871,9 +880,17 @@ int orc_start_heating(orc_pa* p, double beta0) {
   }
   reset_families(p);
   p->beta = beta0;
-  /* ln(#ground states) - beta0 E_0 with E_0 = -2N */
-  p->lnZ = log(p->q ? (double)p->q : 2.0) +
-           ((ORC_MUTANT == 9) ? 0.0 : 2.0 * (double)p->N * beta0);
+  /* ln(#ground states) - beta0 E_0 with E_0 = -2N, then the excitations */
+  double ex;
+  if (p->q)
+    ex = (double)p->N * (double)(p->q - 1) *
+         (exp(-4.0 * beta0) + 2.0 * exp(-6.0 * beta0) +
+          2.0 * (double)(p->q - 2) * exp(-7.0 * beta0));
+  else
+    ex = (double)p->N * (exp(-8.0 * beta0) + 2.0 * exp(-12.0 * beta0));
+  p->lnZ = (log(p->q ? (double)p->q : 2.0) +
+            ((ORC_MUTANT == 9) ? 0.0 : 2.0 * (double)p->N * beta0)) +
+           ((ORC_MUTANT == 19) ? 0.0 : ex);
   p->lnQ_last = 0.0;
   p->n_len = 0;
   return ORC_OK;

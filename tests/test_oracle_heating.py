@@ -3,8 +3,10 @@ zero temperature in the ground states and beta decreases): the start state
 and its free energy, and ln Z along a heating run against enumeration and
 Kaufman's exact solution."""
 import numpy as np
+import pytest
 
 import exact_ising as X
+import exact_potts as XP
 import oracle
 
 
@@ -18,7 +20,10 @@ def test_ground_state_start():
     assert np.all(s.reshape(R, -1) == np.sign(M)[:, None])
     up = (M > 0).mean()
     assert abs(up - 0.5) < 5 * np.sqrt(0.25 / R)
-    assert p.free_energy()[0] == np.log(2.0) + 2.0 * N * beta0
+    # Kaufman's finite-torus ln Z; what the start leaves out is of order
+    # N exp(-16 beta0) = 1e-19 here, far below the rounding of ln Z
+    exact = float(X.kaufman_lnZ(L, beta0))
+    assert abs(p.free_energy()[0] - exact) <= 4e-16 * exact
     assert p.beta == beta0
     # ground states are a fresh ferromagnet's only
     q = oracle.OraclePA(L, 10, seed=5, J=np.ones((2, L, L), np.int8))
@@ -27,6 +32,39 @@ def test_ground_state_start():
         raise AssertionError("heating start accepted couplings")
     except RuntimeError:
         pass
+
+
+@pytest.mark.parametrize("beta0", [1.0, 1.5, 2.0, 2.5, 3.0, 4.0])
+def test_start_lnZ_ising_L4_within_the_expansion_bound(beta0):
+    """The start's ln Z against enumeration of all 2^16 states.  With
+    y = exp(-2 beta0) per broken bond, the first neglected term of ln Z is
+    of order N y^8 (two distant flipped spins, straight and bent triples,
+    2x2 squares), so the difference must stay below a few N exp(-16 beta0);
+    that bound is 14 times smaller than the dimer term 2 N exp(-12 beta0)
+    at beta0 = 1 and shrinks faster with beta0."""
+    L = 4
+    N = L * L
+    p = oracle.OraclePA(L, 10, seed=3)
+    p.start_heating(beta0)
+    exact = X.brute_thermo(L, beta0)["lnZ"]
+    bound = 8.0 * N * np.exp(-16.0 * beta0) + 4e-16 * exact
+    assert abs(p.free_energy()[0] - exact) <= bound
+
+
+@pytest.mark.parametrize("beta0", [2.0, 3.0, 4.0, 5.0, 6.0])
+def test_start_lnZ_potts_q3_L4_within_the_expansion_bound(beta0):
+    """The q = 3 Potts start against the transfer-matrix density of states.
+    One broken bond costs exp(-beta0); the first neglected terms have eight
+    broken bonds, so the difference stays below a few N exp(-8 beta0), which
+    is below the two-different-neighbours term 2 N (q-1)(q-2) exp(-7 beta0)
+    from beta0 = 2 on."""
+    L, q = 4, 3
+    N = L * L
+    p = oracle.OraclePA(L, 10, seed=3, q=q)
+    p.start_heating(beta0)
+    exact = XP.thermo(L, q, beta0)["lnZ"]
+    bound = 12.0 * N * np.exp(-8.0 * beta0) + 4e-16 * exact
+    assert abs(p.free_energy()[0] - exact) <= bound
 
 
 def _heat(L, R, beta0, beta_f, K, theta, seed):

@@ -52,6 +52,9 @@ CASES = {
     18: ("every colour site of a plane group reads the same plane bits",
          ["test_oracle_rng_planes.py::test_plane_draws_are_fair_and_independent",
           "test_oracle_rng_planes.py::test_planes_metropolis_samples_boltzmann_L4"]),
+    19: ("the excited states dropped from the heating start's ln Z",
+         ["test_oracle_heating.py::test_start_lnZ_ising_L4_within_the_expansion_bound",
+          "test_oracle_heating.py::test_start_lnZ_potts_q3_L4_within_the_expansion_bound"]),
 }
 
 
