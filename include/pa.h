@@ -223,9 +223,13 @@ int pa_anneal(pa_ctx* c, const double* betas, int32_t K, int32_t theta,
    context (step 0) by ground states at beta0 > 0 -- every spin of replica j
    equals the top bit of its INIT word of site (0,0) (+1 when set), or for
    Potts the state floor(w q / 2^32) of that word -- and sets beta = beta0,
-   ln Z = ln(#ground states) + 2 N beta0 (2 or q states of energy -2N; the
-   excited states' share, about N exp(-8 beta0) for Ising and
-   2qN exp(-4 beta0) for Potts, is left out).  Resampling
+   ln Z = ln(#ground states) + 2 N beta0 (2 or q states of energy -2N)
+   plus the lightest excitations of the low-temperature expansion, one
+   changed site and two changed neighbours:
+   N (exp(-8 beta0) + 2 exp(-12 beta0)) for Ising,
+   N (q-1) (exp(-4 beta0) + 2 exp(-6 beta0) + 2 (q-2) exp(-7 beta0)) for
+   Potts; what is left out is of order N exp(-16 beta0) (Ising) or
+   N exp(-8 beta0) (Potts).  Resampling
    then steps beta down; weights are shifted by the largest energy when
    beta decreases.  PA_EINVAL for +-J couplings or beta0 <= 0, PA_ESTATE
    after a resampling.  Synchronises. */

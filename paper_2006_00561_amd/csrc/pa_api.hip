@@ -1314,8 +1314,22 @@ int pa_start_heating(pa_ctx* c, double beta0) try {
   rc = sync(c);
   if (rc) return rc;
   c->beta = beta0;
-  // the ground states (2 Ising, q Potts) have energy -2N
-  c->lnZ = std::log(c->q ? (double)c->q : 2.0) + 2.0 * (double)c->N * beta0;
+  // ln Z(beta0): the ground states (2 Ising, q Potts) of energy -2N, and to
+  // first order their lightest excitations on a torus of side >= 4: one
+  // changed site (4 broken bonds) and two changed neighbours (6 broken
+  // bonds, or 7 for two different new Potts states)
+  const double n = (double)c->N;
+  double excited;
+  if (c->q) {
+    const double e4 = std::exp(-4.0 * beta0), e6 = std::exp(-6.0 * beta0),
+                 e7 = std::exp(-7.0 * beta0);
+    excited = n * (double)(c->q - 1) *
+              (e4 + 2.0 * e6 + 2.0 * (double)(c->q - 2) * e7);
+  } else {
+    const double e8 = std::exp(-8.0 * beta0), e12 = std::exp(-12.0 * beta0);
+    excited = n * (e8 + 2.0 * e12);
+  }
+  c->lnZ = (std::log(c->q ? (double)c->q : 2.0) + 2.0 * n * beta0) + excited;
   c->lnQ_last = 0.0;
   c->sweeps_at_step = 0;
   c->n_len = 0;
