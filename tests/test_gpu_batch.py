@@ -307,4 +307,16 @@ def test_sweep_shape_tuner_keeps_results(pa):
         for a, b in zip(t.population(p), d.population(p)):
             assert np.array_equal(a, b)
     t.close()
+    # every candidate shape, and a ragged one, gives the same populations
+    for blocks, chunk in [(512, 4), (2048, 4), (1024, 8), (2048, 8),
+                          (1024, 2), (37, 3)]:
+        c = pa.Batch(pops, autotune=True)
+        c.set_sweep_blocks(blocks, chunk)
+        assert c.sweep_blocks() == (blocks, chunk)
+        c.run(betas, 3)
+        for p in range(len(pops)):
+            assert c.state(p) == d.state(p), (blocks, chunk, p)
+            for a, b in zip(c.population(p), d.population(p)):
+                assert np.array_equal(a, b), (blocks, chunk, p)
+        c.close()
     d.close()
