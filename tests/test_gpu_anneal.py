@@ -264,7 +264,10 @@ def test_anneal_argument_checks(pa):
 
 
 @pytest.mark.parametrize("name,start,rng", [
-    ("CP1", 1, 1), ("CP1", 88, 1), ("C2", 88, 1), ("C2", 2, 0)])
+    ("CP1", 1, 1), ("CP1", 88, 1), ("C2", 88, 1), ("C2", 2, 0),
+    # the paper's total population on one device, bit-packed: 8192 tiles,
+    # so the counts, scan and parent map are three kernels
+    ("C3a", 1, 1), ("C3a", 88, 1)])
 def test_anneal_full_size_sampled(pa, name, start, rng):
     """At the benchmark sizes, in the benchmark's configuration: the
     schedule runs on the device up to step start - 1; then one more step of
@@ -273,9 +276,10 @@ def test_anneal_full_size_sampled(pa, name, start, rng):
     sample of new replicas through their sweeps)."""
     c = W.CONFIGS[name]
     L, R, theta = c["L"], c["R"], c["theta"]
+    layout = 1 if c["layout"] == "bits" else 0
     print("anneal full size %s start=%d rng=%d" % (name, start, rng),
           flush=True)
-    g = pa.Population(L, R, seed=c["seed"], rng_mode=rng)
+    g = pa.Population(L, R, seed=c["seed"], layout=layout, rng_mode=rng)
     sched = W.linear_schedule(c["beta_f"], c["K"])
     if start > 1:
         g.anneal(sched[:start - 1], theta)
@@ -306,7 +310,7 @@ def test_anneal_full_size_sampled(pa, name, start, rng):
     g.close()
 
 
-@pytest.mark.parametrize("name", ["CP1", "C2"])
+@pytest.mark.parametrize("name", ["CP1", "C2", "C3a"])
 def test_anneal_whole_schedule_equals_step_calls(pa, name):
     """The whole benchmark schedule: pa_anneal and the step-by-step calls
     (whose full-size steps are checked against the oracle elsewhere) end in
@@ -314,11 +318,12 @@ def test_anneal_whole_schedule_equals_step_calls(pa, name):
     sizes and ln Q at every step."""
     c = W.CONFIGS[name]
     L, R, theta = c["L"], c["R"], c["theta"]
+    layout = 1 if c["layout"] == "bits" else 0
     sched = W.linear_schedule(c["beta_f"], c["K"])
     print("anneal whole schedule %s" % name, flush=True)
-    g = pa.Population(L, R, seed=c["seed"], rng_mode=1)
+    g = pa.Population(L, R, seed=c["seed"], layout=layout, rng_mode=1)
     obs, q = g.anneal(sched, theta)
-    h = pa.Population(L, R, seed=c["seed"], rng_mode=1,
+    h = pa.Population(L, R, seed=c["seed"], layout=layout, rng_mode=1,
                       capacity=W.deferral_capacity(R))
     for i, b in enumerate(sched):
         h.resample(b, wait=False)
