@@ -460,55 +460,64 @@ __device__ __forceinline__ void lattice_pass(const LatticeArgs& a,
         // has one, draws that site's default-stream word and decides it on
         // the low part of T.  The wave leaves when no lane has a tie left.
         // Every tie is decided by its own site's word, so the order of the
-        // passes does not change the result.  With two words per row and
-        // two rows or more per lane a row's ties are merged into one word
-        // first (3.4 % faster at two rows of two words than one-hot picks
-        // over the four words); otherwise, with four words or more per lane
-        // the pick is kept as a one-hot mask per word (pk), so that the
-        // site's row, class and bookkeeping are plain mask operations, and
-        // with fewer an index of the picked word is cheaper (at one row of
-        // two words the merged form was 0.5 % slower).
+        // passes does not change the result.  With four words or more per
+        // lane and an even number per row, a row's ties are merged two words
+        // into one first (3.4 % faster at two rows of two words than one-hot
+        // picks over the four words); with an odd number per row the pick is
+        // a one-hot mask per word (pk), so that the site's row, class and
+        // bookkeeping are plain mask operations, and with fewer than four
+        // words an index of the picked word is cheaper (at one row of two
+        // words the merged form was 0.5 % slower).
         constexpr int NW = RPL * W;
-        if constexpr (W == 2 && RPL >= 2) {
-          // Two words per row: the colour sites of word 0 sit at positions
-          // of parity p and those of word 1, moved by one place, at parity
-          // 1 - p, so a row's ties and dE = +4 flags fit in one word.  A
-          // site at merged position x belongs to word (x ^ p) & 1, and in
-          // either word its default-stream word is number (x >> 1) & 3 of
-          // group y G8 + 4 word + (x >> 3).  Each pass takes the lowest
-          // pending tie of every lane that has one (first by row, then by
-          // position); the accepted ties go back to their words at the end.
-          uint32_t tM[RPL], cM[RPL], aM[RPL], pr[RPL], gb[RPL];
+        if constexpr (W % 2 == 0 && NW >= 4) {
+          // Words 2j and 2j + 1 of a row as one merged word j: the colour
+          // sites of word 2j sit at positions of parity p and those of word
+          // 2j + 1, moved by one place, at parity 1 - p, so the row's ties
+          // and dE = +4 flags take W / 2 words.  A site at merged position
+          // x of merged word j belongs to word 2j + ((x ^ p) & 1), and its
+          // default-stream word is number (x >> 1) & 3 of group
+          // y G8 + 4 word + (x >> 3).  Each pass takes the lowest pending
+          // tie of every lane that has one (first by row and merged word,
+          // then by position); the accepted ties go back to their words at
+          // the end.
+          constexpr int MW = W / 2, NM = RPL * MW;
+          uint32_t tM[NM], cM[NM], aM[NM], pr[RPL], gb[RPL];
 #pragma unroll
           for (int r = 0; r < RPL; ++r) {
             const int y = lr * RPL + r;
             pr[r] = (uint32_t)((c + y) & 1);
             gb[r] = (uint32_t)(y * G8);
             const uint32_t cm = pr[r] ? 0xAAAAAAAAu : 0x55555555u;
-            tM[r] = (tie[r][0] & cm) | (to_parity(tie[r][1], pr[r] ^ 1u) & ~cm);
-            cM[r] = (cls4[r][0] & cm) | (to_parity(cls4[r][1], pr[r] ^ 1u) & ~cm);
-            aM[r] = 0u;
+#pragma unroll
+            for (int j = 0; j < MW; ++j) {
+              tM[r * MW + j] = (tie[r][2 * j] & cm) |
+                               (to_parity(tie[r][2 * j + 1], pr[r] ^ 1u) & ~cm);
+              cM[r * MW + j] = (cls4[r][2 * j] & cm) |
+                               (to_parity(cls4[r][2 * j + 1], pr[r] ^ 1u) & ~cm);
+              aM[r * MW + j] = 0u;
+            }
           }
           for (;;) {
-            uint32_t pk[RPL];
+            uint32_t pk[NM];
             uint32_t any = 0u;
 #pragma unroll
-            for (int r = 0; r < RPL; ++r) {
-              const uint32_t lowest = tM[r] & (0u - tM[r]);
-              pk[r] = any ? 0u : lowest;
+            for (int i = 0; i < NM; ++i) {
+              const uint32_t lowest = tM[i] & (0u - tM[i]);
+              pk[i] = any ? 0u : lowest;
               any |= lowest;
             }
             if (!__any(any != 0u)) break;
             if (any) {
-              // the picked site's row (the one nonzero pk) and position
+              // the picked site's merged word (the one nonzero pk): its row
+              // parity and group base, its dE = +4 flag, and its position
               uint32_t par = pr[0], gbase = gb[0], c4 = cM[0] & pk[0];
               uint32_t bm = pk[0];
 #pragma unroll
-              for (int r = 1; r < RPL; ++r) {
-                par = pk[r] ? pr[r] : par;
-                gbase = pk[r] ? gb[r] : gbase;
-                c4 |= cM[r] & pk[r];
-                bm |= pk[r];
+              for (int i = 1; i < NM; ++i) {
+                par = pk[i] ? pr[i / MW] : par;
+                gbase = pk[i] ? gb[i / MW] + 8u * (uint32_t)(i % MW) : gbase;
+                c4 |= cM[i] & pk[i];
+                bm |= pk[i];
               }
               const uint32_t x = (uint32_t)__builtin_ctz(bm);
               const uint32_t wd = (x ^ par) & 1u;
@@ -522,17 +531,20 @@ __device__ __forceinline__ void lattice_pass(const LatticeArgs& a,
               const uint32_t acc =
                   ((wv >> 8) < (c4 ? pt.lo4 : pt.lo8)) ? ~0u : 0u;
 #pragma unroll
-              for (int r = 0; r < RPL; ++r) {
-                tM[r] &= ~pk[r];
-                aM[r] |= pk[r] & acc;
+              for (int i = 0; i < NM; ++i) {
+                tM[i] &= ~pk[i];
+                aM[i] |= pk[i] & acc;
               }
             }
           }
 #pragma unroll
           for (int r = 0; r < RPL; ++r) {
             const uint32_t cm = pr[r] ? 0xAAAAAAAAu : 0x55555555u;
-            flip[r][0] |= aM[r] & cm;
-            flip[r][1] |= to_parity(aM[r], pr[r]) & cm;
+#pragma unroll
+            for (int j = 0; j < MW; ++j) {
+              flip[r][2 * j] |= aM[r * MW + j] & cm;
+              flip[r][2 * j + 1] |= to_parity(aM[r * MW + j], pr[r]) & cm;
+            }
           }
         } else if constexpr (NW >= 4) {
           for (;;) {
