@@ -427,8 +427,12 @@ int pa_tune_rows_per_lane(int32_t L, int32_t layout, int32_t model,
 
 /* Creates n populations at beta_0 = 0 (Eq. part-F, as pa_init).  stream NULL
    = a private non-blocking stream (graph capture needs one).  flags:
-   PA_BATCH_AUTOTUNE picks rows_per_lane per distinct (L, layout, model) with
-   pa_tune_rows_per_lane where a config leaves it 0 (cached per process).
+   PA_BATCH_AUTOTUNE picks rows_per_lane where a config leaves it 0, with
+   the batch's own persistent sweep on scratch batches of the same
+   configurations: each distinct (L, layout, model, rng_mode) starts at its
+   smallest valid value, and each other valid value, one class at a time,
+   is kept when three timed steps take under 98 % of the best time so far
+   (cached per process by the configurations).
    Models: the ferromagnet and +-J glasses in either layout, and q-state
    Potts populations (PA_POTTS, PA_INT8, L = 8, 16, 32, 64 or 128: the
    four-sites-per-word pass, one replica per wave, rows_per_lane ignored);

@@ -248,6 +248,11 @@ int tune_rows_per_lane(int32_t L, int32_t layout, int32_t model,
                        int32_t rng_mode, int64_t R, int32_t theta,
                        void* stream, int32_t* best, float* ms);
 
+// Rows per lane of each population of a batch (0 where not tuned), timed
+// with the batch's own persistent sweep on scratch batches (pa_batch.hip).
+int tune_batch_rows(const pa_config* cfgs, int n, void* stream,
+                    std::vector<int>* out);
+
 // Fastest persistent-sweep launch shape of a batch of these populations,
 // timed on a scratch batch (pa_batch.hip).
 int tune_sweep_shape(const pa_config* cfgs, int n, void* stream,

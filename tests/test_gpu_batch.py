@@ -289,6 +289,26 @@ def test_batch_refuses_theta_beyond_the_counter(pa):
     b.close()
 
 
+def test_rows_per_lane_tuner_keeps_results(pa):
+    """PA_BATCH_AUTOTUNE times rows per lane with the batch's own sweep on
+    scratch batches; the tuned batch equals the untuned one (default rows
+    per lane) bit for bit, and a population that sets its rows per lane
+    keeps it."""
+    pops = _mixed_pops()
+    pops[0] = dict(pops[0], rows_per_lane=2)  # L = 4: two lanes per replica
+    betas = np.array(W.linear_schedule(1.0, 4))
+    t = pa.Batch(pops, autotune=True)
+    d = pa.Batch(pops)
+    t.run(betas, 3)
+    d.run(betas, 3)
+    for p in range(len(pops)):
+        assert t.state(p) == d.state(p), p
+        for a, b in zip(t.population(p), d.population(p)):
+            assert np.array_equal(a, b), p
+    t.close()
+    d.close()
+
+
 def test_sweep_shape_tuner_keeps_results(pa):
     """PA_BATCH_TUNE_SWEEP times the persistent sweep's launch shapes on a
     scratch batch; the tuned batch's results equal the default batch's bit
