@@ -231,14 +231,15 @@ struct BatchStep {         // per population, rewritten by the host each step
 // tuned: three rows per lane fill whole waves at L = 48 and 96 (16 and 32
 // lanes per replica), where the tuner measured them fastest; two rows above
 // L = 64 keep the registers in bounds; one row otherwise.  The plane stream
-// takes two rows at L = 64 for large populations: a lane then resolves the
-// ties of 64 draws per half sweep in one pass more often than of 32 (4977
-// against 4844 attempts/ns at R = 2^21); for R = 20480 the half-filled
-// last round of waves of the wider shape costs more (4296 against 3768
-// with one row).
+// takes two rows at L = 64 from 2^15 replicas: a lane then resolves the
+// ties of 64 draws per half sweep, merged two words into one, in fewer
+// passes per draw than of 32.  Whole anneals at theta = 10: int8 +2 % at
+// R = 32768, +5 % at 65536, +8 % at 131072, bit-packed +8 % at 65536; at
+// R = 20480 one row is 1.5 % faster (fewer waves to spread), and at
+// theta = 1 it keeps the coalesced int8 load of one replica per wave.
 inline int default_rows_per_lane(int L, bool planes = false,
                                  int64_t R = 0) {
-  if (planes && L == 64 && R >= (1 << 18)) return 2;
+  if (planes && L == 64 && R >= (1 << 15)) return 2;
   return (L == 48 || L == 96) ? 3 : (L > 64 ? 2 : 1);
 }
 
