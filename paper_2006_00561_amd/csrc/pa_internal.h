@@ -231,15 +231,16 @@ struct BatchStep {         // per population, rewritten by the host each step
 // tuned: three rows per lane fill whole waves at L = 48 and 96 (16 and 32
 // lanes per replica), where the tuner measured them fastest; two rows above
 // L = 64 keep the registers in bounds; one row otherwise.  The plane stream
-// takes two rows at L = 64 from 2^15 replicas: a lane then resolves the
+// takes two rows at L = 64 from 2^14 replicas: a lane then resolves the
 // ties of 64 draws per half sweep, merged two words into one, in fewer
-// passes per draw than of 32.  Whole anneals at theta = 10: int8 +2 % at
-// R = 32768, +5 % at 65536, +8 % at 131072, bit-packed +8 % at 65536; at
-// R = 20480 one row is 1.5 % faster (fewer waves to spread), and at
-// theta = 1 it keeps the coalesced int8 load of one replica per wave.
+// passes per draw than of 32, and int8 replicas still move as whole
+// kilobytes, two per wave.  Whole int8 anneals against one row: +4.5 % at
+// R = 20480 and +7.5 % at 65536 with theta = 10, +4.7 % at 65536 with
+// theta = 3, equal at 32768 and 65536 with theta = 1, -1.5 % at 20480
+// with theta = 1; bit-packed +8 % at 65536 with theta = 10.
 inline int default_rows_per_lane(int L, bool planes = false,
                                  int64_t R = 0) {
-  if (planes && L == 64 && R >= (1 << 15)) return 2;
+  if (planes && L == 64 && R >= (1 << 14)) return 2;
   return (L == 48 || L == 96) ? 3 : (L > 64 ? 2 : 1);
 }
 

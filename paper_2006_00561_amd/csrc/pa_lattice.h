@@ -290,6 +290,13 @@ __device__ __forceinline__ void lattice_pass(const LatticeArgs& a,
   // an int8 replica of L = 64 in one wave, one row per lane: loaded and
   // stored as whole kilobytes
   const bool T64 = INT8 && W == 2 && RPL == 1 && L == 64 && a.rpw == 1;
+  // two such replicas per wave, two rows per lane: each replica moves as
+  // four kilobytes through the same exchange (lane l taking its row l),
+  // then lane 32 g + i takes rows 2i and 2i + 1 of replica g; a second
+  // replica past the population is neither loaded nor stored
+  const bool T64x2 = INT8 && W == 2 && RPL == 2 && L == 64 && a.rpw == 2;
+  const int64_t rep0 = wave * a.rpw;
+  const bool act1 = rep0 + 1 < R;
   // couplings: jr = bond to the right, jl = bond to the left (jr of x-1),
   // jd = bond below, ju = bond above (jd of row y-1); bit set = J < 0
   uint32_t jr[RPL][W], jl[RPL][W], jd[RPL][W], ju[RPL][W];
@@ -345,6 +352,29 @@ __device__ __forceinline__ void lattice_pass(const LatticeArgs& a,
       load_replica64_int8(lp, row2);
 #pragma unroll
       for (int w = 0; w < W; ++w) s[r][w] = row2[w < 2 ? w : 0];
+    } else if (T64x2) {
+      if (r == 0) {
+        // both replicas of the wave (uniform branches: the first is in the
+        // population, the second when act1)
+        const uint32_t sl0 = (uint32_t)rep0, sl1 = act1 ? sl0 + 1u : sl0;
+        const uint8_t* lp0 =
+            a.parent ? a.src + (size_t)a.parent[sl0] * (size_t)a.stride
+                     : a.spins + (size_t)sl0 * (size_t)a.stride;
+        const uint8_t* lp1 =
+            a.parent ? a.src + (size_t)a.parent[sl1] * (size_t)a.stride
+                     : a.spins + (size_t)sl1 * (size_t)a.stride;
+        uint32_t ra[2], rb[2] = {0u, 0u};
+        load_replica64_int8(lp0, ra);
+        if (act1) load_replica64_int8(lp1, rb);
+        const int i2 = 2 * (lane & 31);
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+          const uint32_t a0 = shfl(ra[w], i2), a1 = shfl(ra[w], i2 + 1);
+          const uint32_t b0 = shfl(rb[w], i2), b1 = shfl(rb[w], i2 + 1);
+          s[0][w < W ? w : 0] = (lane >> 5) ? b0 : a0;
+          s[RPL > 1 ? 1 : 0][w < W ? w : 0] = (lane >> 5) ? b1 : a1;
+        }
+      }
     } else if (active) {
       load_row<W, RPL, INT8>(lp, L, y, s[r]);
     } else {
@@ -669,8 +699,26 @@ __device__ __forceinline__ void lattice_pass(const LatticeArgs& a,
     uint32_t row2[2] = {s[0][0], s[0][W > 1 ? 1 : 0]};
     store_replica64_int8(rp, row2, active);
   }
+  if (T64x2) {
+    // lane l gathers row l of replica g (rows 2i, 2i + 1 sit in lane
+    // 32 g + i), then the wave writes the replica as four kilobytes
+    const int hl = lane >> 1;
+#pragma unroll
+    for (int g2 = 0; g2 < 2; ++g2) {
+      uint32_t row2[2];
+#pragma unroll
+      for (int w = 0; w < 2; ++w) {
+        const uint32_t v0 = shfl(s[0][w < W ? w : 0], 32 * g2 + hl);
+        const uint32_t v1 = shfl(s[RPL > 1 ? 1 : 0][w < W ? w : 0], 32 * g2 + hl);
+        row2[w] = (lane & 1) ? v1 : v0;
+      }
+      if (g2 == 0 || act1)
+        store_replica64_int8(a.spins + (size_t)(rep0 + g2) * (size_t)a.stride,
+                             row2, true);
+    }
+  }
   if (active) {
-    if (!T64) {
+    if (!T64 && !T64x2) {
 #pragma unroll
       for (int r = 0; r < RPL; ++r)
         store_row<W, RPL, INT8>(rp, L, lr * RPL + r, s[r]);

@@ -103,6 +103,9 @@ SHAPES = [
     (128, 24, 1, 0, False), (128, 20, 0, 4, True),
     (12, 250, 1, 3, False), (24, 300, 0, 3, True), (48, 90, 0, 3, False),
     (96, 30, 1, 3, True),
+    # int8 L = 64 at two rows per lane: two replicas per wave moved as
+    # whole kilobytes; an odd R leaves the last wave one replica
+    (64, 129, 0, 2, False), (64, 67, 0, 2, True),
 ]
 
 

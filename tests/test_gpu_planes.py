@@ -77,6 +77,7 @@ SHAPES = [
     (64, 129, 1, 1, False), (64, 70, 1, 2, True), (64, 70, 0, 4, False),
     (66, 20, 0, 0, False), (96, 30, 1, 3, True), (100, 12, 0, 4, False),
     (128, 24, 1, 0, False), (128, 20, 0, 4, True), (12, 250, 1, 3, False),
+    (64, 129, 0, 2, False), (64, 67, 0, 2, True),
 ]
 
 
