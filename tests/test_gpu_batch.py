@@ -106,6 +106,27 @@ def test_plane_stream_batch_matches_oracle(pa, use_graph):
     b.close()
 
 
+def test_two_replicas_per_wave_int8_batch_matches_oracle(pa):
+    """int8 L = 64 populations at two rows per lane in the persistent sweep
+    (two replicas per wave moved as whole kilobytes), an odd R leaving the
+    last wave one replica, in both random-number streams and with +-J
+    bonds: every population equals the oracle's run."""
+    pops = []
+    for k, (R, glass, rng) in enumerate([(129, False, 1), (67, True, 1),
+                                         (131, True, 0), (64, False, 0)]):
+        pops.append(dict(L=64, R=R, J=W.pmj_couplings(64, 70 + k) if glass
+                         else None, seed=9, population_id=k, layout=0,
+                         rows_per_lane=2, rng_mode=rng))
+    betas = W.linear_schedule(1.0, 5)
+    theta = 2
+    b = pa.Batch(pops)
+    b.run(np.array(betas), theta, use_graph=True)
+    for p, pop in enumerate(pops):
+        o, traj = _oracle_run(pop, betas, theta)
+        _check_pop(b, p, o, traj)
+    b.close()
+
+
 def test_graph_replays_match_eager_across_runs(pa):
     """Two graph runs of 4 steps each, with host reads in between, against
     one eager run of 8 steps: identical populations and ln Z."""
