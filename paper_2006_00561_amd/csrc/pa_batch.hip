@@ -30,6 +30,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <exception>
 #include <new>
 #include <numeric>
@@ -1149,6 +1150,8 @@ int tune_rows_per_lane(int32_t L, int32_t layout, int32_t model,
 // configuration is not tuned.  Cached per process by the configurations.
 int tune_batch_rows(const pa_config* cfgs, int n, void* stream,
                     std::vector<int>* out) {
+  // the cache is shared by threads; the tuning itself runs unlocked
+  static std::mutex mu;
   static std::map<std::vector<int64_t>, std::vector<int>> cache;
   std::vector<int64_t> key;
   for (int p = 0; p < n; ++p) {
@@ -1156,10 +1159,13 @@ int tune_batch_rows(const pa_config* cfgs, int n, void* stream,
     key.insert(key.end(), {c.L, c.R_target, c.layout, c.model, c.q,
                            c.rng_mode, c.rows_per_lane});
   }
-  auto it = cache.find(key);
-  if (it != cache.end()) {
-    *out = it->second;
-    return PA_OK;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+      *out = it->second;
+      return PA_OK;
+    }
   }
   auto valid = [](int L, int r) {
     return L % r == 0 && L / r <= 64 && !((L + 31) / 32 >= 3 && r < 2);
@@ -1216,7 +1222,10 @@ int tune_batch_rows(const pa_config* cfgs, int n, void* stream,
     for (const auto& kv : members)
       for (int p : kv.second) res[p] = cur[kv.first];
   }
-  cache[key] = res;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    cache[key] = res;
+  }
   *out = res;
   return PA_OK;
 }
@@ -1229,6 +1238,7 @@ int tune_batch_rows(const pa_config* cfgs, int n, void* stream,
 // (L, R, layout, model, q, stream) of the populations.
 int tune_sweep_shape(const pa_config* cfgs, int n, void* stream,
                      int* blocks, int* chunk) {
+  static std::mutex mu;
   static std::map<std::vector<int64_t>, std::pair<int, int>> cache;
   std::vector<int64_t> key;
   for (int p = 0; p < n; ++p) {
@@ -1236,11 +1246,14 @@ int tune_sweep_shape(const pa_config* cfgs, int n, void* stream,
     key.insert(key.end(), {c.L, c.R_target, c.layout, c.model, c.q,
                            c.rng_mode, c.rows_per_lane});
   }
-  auto it = cache.find(key);
-  if (it != cache.end()) {
-    *blocks = it->second.first;
-    *chunk = it->second.second;
-    return PA_OK;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+      *blocks = it->second.first;
+      *chunk = it->second.second;
+      return PA_OK;
+    }
   }
   static const int cand[][2] = {{1024, 4}, {512, 4}, {2048, 4},
                                 {1024, 8}, {2048, 8}, {1024, 2}};
@@ -1267,7 +1280,10 @@ int tune_sweep_shape(const pa_config* cfgs, int n, void* stream,
   }
   pa_batch_destroy(t);
   if (rc) return rc;
-  cache[key] = {bb, bc};
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    cache[key] = {bb, bc};
+  }
   *blocks = bb;
   *chunk = bc;
   return PA_OK;
