@@ -81,7 +81,8 @@ typedef struct {
                          per lane (must divide L; L/rows <= 64; at least 2
                          for L > 64), or 0: 3 at L = 48 and 96, 2 above
                          L = 64 (and at L = 64 with PA_RNG_PLANES and
-                         R_target >= 2^14), else 1
+                         R_target >= 2^14, except that an int8 launch of
+                         one sweep then takes 1), else 1
                          (a batch created with
                          PA_BATCH_AUTOTUNE times the valid shapes instead).
                          Results do not depend on it.                       */
